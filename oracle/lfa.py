@@ -1,0 +1,169 @@
+"""Local Fourier analysis of the omega-Jacobi gamma-cycle -- TEST INFRASTRUCTURE ONLY.
+
+Everything here is built from the Fourier symbols the paper prints, not from stencils:
+
+* fine operator symbol, fourth order: (4/h^2) sum_a (s_a + s_a^2/3), s_a = sin^2(theta_a/2)
+  (appendix A.4, eq. L_hat_2d_4o, written per axis); second order: (4/h^2) sum_a s_a
+  (section 5.3, the symbol behind xi_theta);
+* full weighting: prod_a (1 - s_a) (appendix A.2, below eq. transfer_hat_2d);
+* cubic transfer: prod_a (1 - s_a^2 (3 - 2 s_a)) (appendix A.4);
+* linear interpolation: the transpose of full weighting (appendix A.2), same values;
+* omega-Jacobi: S = 1 - omega * L/a_0 with a_0 the centre coefficient (section 5.3);
+* two-grid operator on the 2^d aliases of theta in [-pi/2, pi/2)^d:
+  M = S^nu2 (I - p L_H^{-1} r^T diag(L)) S^nu1 (section 2.2 eqs. K, M_2level; appendix
+  A.2 eqs. K_hat_2, M_2); Galerkin coarse symbol L_H(2 theta) = sum_alpha r_alpha L_alpha p_alpha
+  (eq. L_2h_G and the line after it);
+* smoothing factor: sup over high frequencies (section 2.2 eq. mu; section 5.3).
+
+Convention: an interpolated coarse mode phi_H(2 theta) is sum_alpha p(theta_alpha) phi_h(theta_alpha)
+and restriction maps phi_h(theta_alpha) to r(theta_alpha) phi_H(2 theta).
+
+On the finite Dirichlet grid with the odd-reflection closure, sine modes are exact
+eigenfunctions of every operator above, so ``finite_two_grid_spectrum`` is the exact
+spectrum of the computed two-grid operator (not an approximation).
+"""
+import itertools
+
+import numpy as np
+
+FW, CUBIC = 1, 3
+LINEAR = 1
+NG, GALERKIN = 0, 1
+
+
+def sin2(theta):
+    return np.sin(np.asarray(theta, dtype=float) / 2.0) ** 2
+
+
+def symbol_fine(theta, h, order=4):
+    """Symbol of -Delta_h; theta has shape (..., dim)."""
+    s = sin2(theta)
+    if order == 4:
+        return (4.0 / h ** 2) * np.sum(s + s * s / 3.0, axis=-1)
+    if order == 2:
+        return (4.0 / h ** 2) * np.sum(s, axis=-1)
+    raise ValueError(order)
+
+
+def symbol_transfer(theta, op):
+    """Restriction / interpolation symbol (full weighting or linear: op=1; cubic: op=3)."""
+    s = sin2(theta)
+    if op == 1:
+        return np.prod(1.0 - s, axis=-1)
+    if op == 3:
+        return np.prod(1.0 - s * s * (3.0 - 2.0 * s), axis=-1)
+    raise ValueError(op)
+
+
+def aliases(theta):
+    """The 2^d frequencies theta + pi*alpha, alpha in {0,1}^d (alpha = 0 first)."""
+    theta = np.asarray(theta, dtype=float)
+    dim = theta.shape[-1]
+    out = []
+    for alpha in itertools.product((0, 1), repeat=dim):
+        out.append(theta + np.pi * np.array(alpha, dtype=float))
+    return np.stack(out, axis=-2)  # (..., 2^d, dim)
+
+
+class Scheme:
+    """Parameters of the cycle being analysed."""
+
+    def __init__(self, dim, order=4, coarse=NG, restrict_op=FW, prolong=CUBIC, nu1=2, nu2=1,
+                 omega=None):
+        self.dim, self.order, self.coarse = dim, order, coarse
+        self.restrict_op, self.prolong = restrict_op, prolong
+        self.nu1, self.nu2 = nu1, nu2
+        self.omega = jacobi_optimum(dim, order)[0] if omega is None else omega
+
+    def level_symbol(self, level, theta, h0=1.0):
+        """Symbol of the level-l operator at level-l frequency theta (spacing h0 * 2^l)."""
+        h = h0 * 2 ** level
+        if level == 0 or self.coarse == NG:
+            return symbol_fine(theta, h, self.order)
+        half = aliases(np.asarray(theta, dtype=float) / 2.0)
+        fine = self.level_symbol(level - 1, half, h0)
+        return np.sum(symbol_transfer(half, self.restrict_op) * fine
+                      * symbol_transfer(half, self.prolong), axis=-1)
+
+    def level_diagonal(self, level, h0=1.0, m=32):
+        """Centre stencil coefficient = mean of the symbol over the frequency torus."""
+        grid = -np.pi + 2 * np.pi * np.arange(m) / m
+        pts = np.stack(np.meshgrid(*([grid] * self.dim), indexing="ij"), axis=-1)
+        return float(np.mean(self.level_symbol(level, pts, h0)))
+
+    def smoother_symbol(self, theta, level=0, h0=1.0):
+        return 1.0 - self.omega * self.level_symbol(level, theta, h0) / self.level_diagonal(level, h0)
+
+    def two_grid_matrix(self, theta, h0=1.0):
+        """2^d x 2^d symbol of S^nu2 K S^nu1 at one low frequency theta."""
+        th = aliases(theta)
+        L = self.level_symbol(0, th, h0)
+        S = np.diag(1.0 - self.omega * L / self.level_diagonal(0, h0))
+        r = symbol_transfer(th, self.restrict_op)
+        p = symbol_transfer(th, self.prolong)
+        LH = self.level_symbol(1, 2.0 * np.asarray(theta, dtype=float), h0)
+        K = np.eye(len(L)) - np.outer(p, r * L) / LH
+        return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
+
+
+def jacobi_optimum(dim, order=4):
+    """Optimal omega-Jacobi parameter and smoothing factor for standard coarsening.
+
+    The smoother symbol is 1 - omega*q(theta) with q = L/a_0.  Over the high
+    frequencies q ranges over [q_lo, q_hi]; equioscillation |1 - omega q_lo| =
+    |1 - omega q_hi| gives omega* = 2/(q_lo + q_hi), mu* = (q_hi - q_lo)/(q_hi + q_lo)
+    (the argument of section 5.3 that yields eq. mu_w_J_r).  For order 4,
+    a_0 = 30 d/(12 h^2), q_lo is reached with one s_a = 1/2 and the rest 0, q_hi with
+    every s_a = 1."""
+    if order == 4:
+        a0 = 30.0 * dim / 12.0
+        g = lambda s: 4.0 * (s + s * s / 3.0)
+    else:
+        a0 = 2.0 * dim
+        g = lambda s: 4.0 * s
+    q_lo = g(0.5) / a0
+    q_hi = dim * g(1.0) / a0
+    return 2.0 / (q_lo + q_hi), (q_hi - q_lo) / (q_hi + q_lo)
+
+
+def smoothing_factor(scheme, m=64):
+    """mu = sup over high frequencies of |S(theta)| (omega-Jacobi, section 2.2 eq. mu)."""
+    grid = -np.pi + 2 * np.pi * (np.arange(m) + 0.0) / m
+    pts = np.stack(np.meshgrid(*([grid] * scheme.dim), indexing="ij"), axis=-1).reshape(-1, scheme.dim)
+    high = np.any(np.abs(pts) >= np.pi / 2 - 1e-12, axis=-1)
+    return float(np.max(np.abs(scheme.smoother_symbol(pts[high]))))
+
+
+def two_grid_rho(scheme, m=32):
+    """sup over a uniform grid of low frequencies (theta = 0 excluded) of rho(M(theta))."""
+    grid = -np.pi / 2 + np.pi * np.arange(m + 1) / m
+    best = 0.0
+    for theta in itertools.product(grid, repeat=scheme.dim):
+        theta = np.array(theta)
+        if np.allclose(theta, 0.0):
+            continue
+        best = max(best, float(np.max(np.abs(np.linalg.eigvals(scheme.two_grid_matrix(theta))))))
+    return best
+
+
+def finite_two_grid_spectrum(scheme, n):
+    """Exact eigenvalues of the two-grid operator on the Dirichlet grid of n points/axis
+    (interior (n-2)^dim unknowns), from the symbols at theta_a = k_a*pi/(n-1).
+
+    Fine sine modes k and N-k (N = n-1) alias on the coarse grid; mode N/2 on an axis
+    restricts to zero and is never interpolated, so on such blocks the coarse-level
+    correction is the identity and the eigenvalues are S^(nu1+nu2)."""
+    N = n - 1
+    h0 = 1.0 / N
+    eig = []
+    for k in itertools.product(range(1, N // 2 + 1), repeat=scheme.dim):
+        k = np.array(k, dtype=float)
+        theta = k * np.pi / N
+        if np.all(k < N // 2):
+            eig.extend(np.linalg.eigvals(scheme.two_grid_matrix(theta, h0)))
+        else:
+            th = aliases(theta)
+            keep = np.all((k[None, :] < N // 2) | (th - theta[None, :] == 0), axis=-1)
+            S = scheme.smoother_symbol(th[keep], 0, h0)
+            eig.extend(S ** (scheme.nu1 + scheme.nu2))
+    return np.array(eig)
