@@ -1,0 +1,174 @@
+/*
+ * mg.h -- C ABI of the MI355X multigrid library for fourth-order finite-difference
+ * Poisson problems.
+ *
+ * Method: K. Liu, W. D. Henshaw, "Multigrid with Nonstandard Coarsening".  The library
+ * solves L_h u = f for L_h = -Delta_h on [0,1]^dim (section 2.1 problem statement;
+ * section 2.3 eq. L_h_2d_4o for the fourth-order operator, its 3D analogue the sum of
+ * the three axis operators) with homogeneous Dirichlet boundary values, by the
+ * (lmax+1)-level gamma-cycle of section 2.2: omega-Jacobi smoothing, full-weighting
+ * restriction of the defect (section 3.1 eq. transfer_2d), exact solve on the coarsest
+ * level, cubic (appendix A.4) or linear interpolation of the correction, and either
+ * rediscretized coarse operators (eq. L_H_4n_2d) or Galerkin coarse operators
+ * R * L * P (eqs. L_H_G, L_H_4G).  Coarse grids come from standard coarsening
+ * (eq. G_H_d).
+ *
+ * Grids.  A level of side n holds n points per axis including both boundary points,
+ * x_i = i h, h = 1/(n-1), n = 2^k + 1.  Arrays are dense, x fastest:
+ * index (k*n + j)*n + i (2D: j*n + i).  Boundary entries are the (zero) Dirichlet data.
+ * The width-5 stencils reach one point past the boundary; the library reads that
+ * value as the odd reflection u(-i) = -u(i) (the paper's analysis is on periodic or
+ * infinite grids and gives no closure for wide stencils at a Dirichlet boundary).
+ *
+ * Memory.  Every pointer named "device" is GPU memory of the device current when the
+ * handle was set up (for instance a torch tensor's data_ptr()).  The caller owns f and
+ * u; the handle owns every hierarchy buffer.  All work is ordered on the HIP stream
+ * given to mg_setup.  No entry point allocates memory except mg_setup.
+ *
+ * Errors.  Every entry point returns an mg_status; on failure mg_last_error() gives a
+ * message (per calling thread).  A handle is used by one thread at a time.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx *mg_handle;
+
+typedef enum {
+  MG_OK = 0,
+  MG_EINVAL = 1,    /* bad configuration or argument */
+  MG_ENOMEM = 2,    /* device allocation failed or the footprint exceeds the budget */
+  MG_EDEVICE = 3,   /* a HIP runtime call failed */
+  MG_ENOCONV = 4,   /* max_cycles reached, or the residual grew: result still filled */
+  MG_ENUMERIC = 5,  /* the residual norm is NaN or Inf */
+  MG_EBUSY = 6      /* an asynchronous solve on the handle has not finished */
+} mg_status;
+
+typedef enum {
+  MG_COARSE_NG = 0,       /* rediscretized: the fine stencil at the coarse spacing (eq. L_H_4n_2d) */
+  MG_COARSE_GALERKIN = 1  /* R * L_l * P built at setup, level by level (eq. L_H_4G) */
+} mg_coarse;
+
+typedef enum { MG_SMOOTH_JACOBI = 0 } mg_smoother;
+
+typedef enum {
+  MG_PREC_FP64 = 0,   /* every step in FP64 */
+  MG_PREC_MIXED = 1   /* FP32 cycles inside FP64 iterative refinement (FP64 outer residual,
+                         correction and coarsest solve) */
+} mg_precision;
+
+typedef struct {
+  int dim;             /* 2 or 3 */
+  int n;               /* points per axis incl. boundary, 2^k + 1, reaching n_coarsest */
+  int order;           /* 4 (fourth order, width-5 stencil) or 2 (5-/7-point) */
+  int coarse;          /* mg_coarse */
+  int smoother;        /* mg_smoother */
+  double omega;        /* Jacobi relaxation; <= 0 selects the Fourier-analysis optimum
+                          (10/13 in 2D, 9/11 in 3D for order 4; 4/5, 6/7 for order 2) */
+  int nu1, nu2;        /* pre- and post-smoothing sweeps per cycle (nu1 + nu2 >= 1) */
+  int gamma;           /* 1 = V cycle, 2 = W cycle */
+  int prolong;         /* 3 = cubic interpolation, 1 = (bi/tri)linear */
+  int restrict_op;     /* 1 = full weighting */
+  int n_coarsest;      /* side of the coarsest level (exact dense solve), e.g. 9 */
+  int precision;       /* mg_precision */
+  double rtol;         /* stop when ||f - L u||_h <= rtol ||f||_h */
+  int max_cycles;      /* FP64: cycle cap; MIXED: cap on refinement steps */
+  int inner_cycles;    /* MIXED: FP32 cycles per refinement step */
+} mg_config;
+
+#define MG_MAX_HISTORY 512
+
+typedef struct {
+  int cycles;          /* multigrid cycles run (MIXED: FP32 inner cycles) */
+  int outer_steps;     /* MIXED: refinement steps run; FP64: 0 */
+  int status;          /* 1 converged, 2 cycle cap, 3 rounding floor, 4 non-finite, 5 growth */
+  int floor_hit;       /* 1 when the residual stopped decreasing above rtol */
+  double rel_residual; /* final ||f - L u||_h / ||f||_h (FP64, difference form) */
+  double conv_factor;  /* last residual ratio between successive checks */
+  int history_len;     /* entries in history */
+  double history[MG_MAX_HISTORY]; /* relative residual before each cycle (FP64) or each
+                                     refinement step (MIXED), and after the last */
+} mg_result;
+
+/* Validates cfg, builds the level hierarchy (coarse operators, the coarsest-level
+ * inverse) and allocates every device buffer.  hip_stream: a hipStream_t (NULL = the
+ * default stream).  On failure *out is NULL and nothing is leaked. */
+mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out);
+
+/* Device bytes a handle for cfg allocates (0 for an invalid cfg). */
+size_t mg_footprint_bytes(const mg_config *cfg);
+
+/* Solves L u = f.  f, u: device FP64 arrays of n^dim values; u holds the initial
+ * guess on entry and the solution on exit; f is read only.  Stops at rtol, at the
+ * rounding floor (floor_hit), or at max_cycles.  res may be NULL.  Returns after the
+ * solve finished.  MG_ENOCONV if rtol was not reached (res still filled). */
+mg_status mg_solve(mg_handle h, const double *f, double *u, mg_result *res);
+
+/* Runs exactly ncycles cycles (MIXED: ncycles refinement steps) with no stopping
+ * test, recording the residual before each and after the last.  For measurement and
+ * parity checks at a fixed cycle count. */
+mg_status mg_run_cycles(mg_handle h, const double *f, double *u, int ncycles, mg_result *res);
+
+/* Stream-ordered solve: enqueues the whole solve (device-side stopping test, the
+ * cycle cap as the launch bound) and returns without waiting.  f and u must stay
+ * valid until mg_query reports completion. */
+mg_status mg_solve_async(mg_handle h, const double *f, double *u);
+
+/* After mg_solve_async: MG_EBUSY while running, else the solve's status and res. */
+mg_status mg_query(mg_handle h, mg_result *res);
+
+/* rel = ||f - L u||_h / ||f||_h in FP64 on the device (difference form). */
+mg_status mg_residual_norm(mg_handle h, const double *f, const double *u, double *rel);
+
+/* Releases every buffer of the handle (waits for its stream first). */
+mg_status mg_destroy(mg_handle h);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *mg_last_error(void);
+
+/* ---- component entry points: one hot-path step on level `level` of a handle ----
+ * Arrays are the level's dense n_l^dim layout; fp32 = 1 selects float arrays (the FP32
+ * kernels of MIXED precision), else double.  They launch on the handle's stream and
+ * return without waiting. */
+
+/* Side n_l of level l (0 = finest), or -1. */
+int mg_level_size(mg_handle h, int level);
+
+/* One omega-Jacobi sweep u_out = u_in + omega/a_0 (f - L_l u_in) (section 5.3 smoother
+ * with a_0 the centre coefficient of L_l).  u_in == NULL means u_in = 0.
+ * u_out != u_in. */
+mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, const void *u_in,
+                           void *u_out);
+
+/* r = f - L_l u (the defect of section 2.2), zero on the boundary. */
+mg_status mg_kernel_residual(mg_handle h, int level, int fp32, const void *f, const void *u,
+                             void *r);
+
+/* fc = I_h^H (f - L_l u) on level l+1 (defect and full weighting in one pass). */
+mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const void *f,
+                                      const void *u, void *fc);
+
+/* u_out = u_in + I_H^h v, v on level l+1 (interpolation and correction in one pass);
+ * u_out may equal u_in. */
+mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void *v,
+                                    const void *u_in, void *u_out);
+
+/* v = L_c^{-1} g on the coarsest level (FP64 arithmetic for either storage type). */
+mg_status mg_kernel_coarsest_solve(mg_handle h, int fp32, const void *g, void *v);
+
+/* Level-l operator as 1D factors: L_l = sum over axes of a (along the axis) times b
+ * (along every other axis).  Writes 7 coefficients each (offsets -3..3). */
+mg_status mg_level_operator(mg_handle h, int level, double a[7], double b[7]);
+
+/* Blocks until the handle's stream is idle. */
+mg_status mg_synchronize(mg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -222,11 +222,33 @@ static void free_entries(entries *e) {
   free(e->ox); free(e->oy); free(e->oz); free(e->c);
 }
 
+/* (L u)(x) = sum_k c_k u(x+k).  Every operator of the method annihilates constants (its
+ * coefficients sum to zero: -Delta_h of either order, and R L P with transfers that
+ * preserve constants), so the sum equals sum_{k != 0} c_k (u(x+k) - u(x)).  That form is
+ * used here: with the plain form, the rounding of coefficients such as -16/12 leaves a
+ * non-zero row sum of order eps/h^2, i.e. a spurious term (eps/h^2) u that shifts the
+ * discrete solution by about eps/(h^2 lambda_min) relative, 1e-10 at h = 1/4096. */
 static double apply_at(const entries *e, int dim, int n, const double *u, int i, int j, int k) {
+  const double u0 = ext(u, dim, n, i, j, k);
   double sum = 0.0;
-  for (int q = 0; q < e->count; ++q)
-    sum += e->c[q] * ext(u, dim, n, i + e->ox[q], j + e->oy[q], k + e->oz[q]);
+  for (int q = 0; q < e->count; ++q) {
+    if (e->ox[q] == 0 && e->oy[q] == 0 && e->oz[q] == 0) continue;
+    sum += e->c[q] * (ext(u, dim, n, i + e->ox[q], j + e->oy[q], k + e->oz[q]) - u0);
+  }
   return sum;
+}
+
+/* True when the stencil annihilates constants up to rounding (the relative row sum of a
+ * computed Galerkin stencil grows like 4^l * eps over l levels: 2e-12 at l = 9). */
+static int annihilates_constants(int dim, int R, const double *s) {
+  int w = swidth(R);
+  long total = dim == 2 ? (long)w * w : (long)w * w * w;
+  double sum = 0.0, mag = 0.0;
+  for (long q = 0; q < total; ++q) {
+    sum += s[q];
+    mag += fabs(s[q]);
+  }
+  return fabs(sum) <= 1e-9 * mag;
 }
 
 /* -------------------------------------------------------- grid operators -- */
@@ -353,9 +375,13 @@ double or_residual_norm_ld(int dim, int n, int R, const double *s, const double 
     long double acc = 0.0L;
     for (int j = 1; j < n - 1; ++j)
       for (int i = 1; i < n - 1; ++i) {
+        const long double u0 = ext(u, dim, n, i, j, k);
         long double lu = 0.0L;
-        for (int q = 0; q < e.count; ++q)
-          lu += (long double)e.c[q] * (long double)ext(u, dim, n, i + e.ox[q], j + e.oy[q], k + e.oz[q]);
+        for (int q = 0; q < e.count; ++q) {
+          if (e.ox[q] == 0 && e.oy[q] == 0 && e.oz[q] == 0) continue;
+          lu += (long double)e.c[q] *
+                ((long double)ext(u, dim, n, i + e.ox[q], j + e.oy[q], k + e.oz[q]) - u0);
+        }
         long double r = (long double)f[at(n, i, j, k)] - lu;
         acc += r * r;
       }
@@ -480,6 +506,10 @@ or_mg *or_mg_create(const or_config *cfg) {
     } else {
       or_level *fl = &mg->lev[l - 1];
       lv->R = or_galerkin_stencil(dim, fl->R, fl->s, cfg->restrict_op, cfg->prolong, lv->s);
+    }
+    if (!annihilates_constants(dim, lv->R, lv->s)) {
+      or_mg_destroy(mg);
+      return NULL;
     }
     if (l > 0) {
       lv->u = alloc_grid(dim, n);

@@ -67,7 +67,9 @@ int or_fine_stencil(int dim, int order, double h, double *s);
 int or_galerkin_stencil(int dim, int Rf, const double *sf, int restrict_op, int prolong,
                         double *sc);
 
-/* out = L u on interior points, 0 on the boundary. */
+/* The operator functions below require a stencil whose coefficients sum to zero (true
+ * for every operator of the method) and evaluate L u = sum_{k != 0} c_k (u(x+k) - u(x)).
+ * out = L u on interior points, 0 on the boundary. */
 void or_apply(int dim, int n, int R, const double *s, const double *u, double *out);
 /* d = f - L u on interior points (the defect of section 2.2), 0 on the boundary. */
 void or_residual(int dim, int n, int R, const double *s, const double *f, const double *u,

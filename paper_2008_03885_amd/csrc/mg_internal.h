@@ -1,0 +1,100 @@
+// mg_internal.h -- declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mg.h"
+
+namespace mgk {
+
+constexpr int kBlock = 256;      // threads per block of the streaming kernels
+constexpr int kMaxRadius = 3;    // widest 1D operator factor (Galerkin coarse levels)
+constexpr int kMaxHistory = MG_MAX_HISTORY;
+
+// Level operator L = sum over axes of a (along that axis) times b (along the others),
+// a and b symmetric 1D stencils of radius <= 3 stored at offsets -3..3.
+// cross: b is the unit stencil, so L is the (2D 9-point / 3D 13-point) cross and the
+// kernels use the difference form sum_{k != 0} w_k (u_0 - u_k) with w_k = -a_k.
+struct LevelOp {
+  double a[7];
+  double b[7];
+  bool cross;
+  double diag;  // centre coefficient of L
+};
+
+// Coefficients as seen by a kernel, in its arithmetic type.
+template <typename T>
+struct KOp {
+  T a[7];
+  T b[7];
+  T w1, w2;   // cross: weights of (u_0 - u_{+-1}) and (u_0 - u_{+-2})
+  T om_d;     // omega / diag
+};
+
+// Device-resident stopping state of a solve; every step kernel returns at once when
+// done != 0, so a captured step can be replayed past convergence at no cost.
+struct DevState {
+  int done;
+  int checks;      // number of residual checks recorded
+  int status;      // 0 running, 1 converged, 2 cap, 3 floor, 4 non-finite, 5 growth
+  int stall;
+  int max_checks;  // stop after this many checks
+  int floor_detect;
+  double rtol;
+  double fnorm2;   // sum of f^2 over interior points
+  double best;
+  double last_ratio;
+  double hist[kMaxHistory];
+};
+
+enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2 };
+
+// ---- launchers (kernels.hip) ----------------------------------------------------
+// All take the level side n, dense arrays, and an optional `done` flag.
+
+template <typename T, typename TO>
+hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, const T *f,
+                        const T *u, TO *out, int n, double *partials, int *nparts,
+                        const int *done, hipStream_t s);
+
+template <typename T>
+hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T *u, T *fc,
+                                 int n, const int *done, hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong_correct(int dim, int prolong, const T *v, const T *uin, T *uout,
+                                  int n, const int *done, hipStream_t s);
+
+template <typename T>
+hipError_t launch_coarsest(int dim, const double *ainv_t, const T *g, T *v, int nc,
+                           const int *done, hipStream_t s);
+
+hipError_t launch_check(DevState *st, const double *partials, int nparts, int record,
+                        hipStream_t s);
+
+hipError_t launch_ir_correct(int dim, double *u, const float *e, int n, const int *done,
+                             hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t s);
+
+// Largest number of partial sums a level-0 sweep of side n produces.
+int sweep_partials(int dim, int n);
+
+// 3D variants (kernels3d.hip), called by the launchers above for dim == 3.
+int sweep_partials_3d(int n);
+template <typename T, typename TO>
+hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
+                           TO *out, int n, double *partials, int *nparts, const int *done,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
+                                    const int *done, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
+                                     const int *done, hipStream_t s);
+
+}  // namespace mgk

@@ -1,0 +1,767 @@
+// runtime.hip -- host runtime and C ABI of the multigrid library.
+//
+// Hierarchy: standard coarsening n_{l+1} = (n_l - 1)/2 + 1 down to n_coarsest (eq. G_H_d).
+// Level operators are kept as 1D factors (a along an axis, b along the others):
+//   rediscretized: a = the 1D fourth- (or second-) order second difference at h_l, b = unit
+//   (eq. L_H_4n_2d);
+//   Galerkin: a_{l+1} = R a_l P and b_{l+1} = R b_l P in 1D, which is exactly R L_l P for the
+//   tensor-product transfers (eqs. L_H_G, L_H_4G).
+// A solve step is one gamma-cycle (FP64) or one refinement step (MIXED); it is captured
+// once into a HIP graph and replayed.  The residual check runs on the device and sets a
+// flag that makes every later kernel of the step return at once, so the host can launch
+// replays in chunks and read the flag one chunk behind without stalling the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+
+using mgk::DevState;
+using mgk::LevelOp;
+
+namespace {
+
+thread_local std::string g_error;
+
+mg_status fail(mg_status st, const std::string &msg) {
+  g_error = msg;
+  return st;
+}
+
+#define MG_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct Buffers {
+  void *u = nullptr, *f = nullptr, *t = nullptr;
+};
+
+__global__ void k_state_init(DevState *st, double rtol, int max_checks, int floor_detect) {
+  if (threadIdx.x == 0) {
+    st->done = 0;
+    st->checks = 0;
+    st->status = 0;
+    st->stall = 0;
+    st->max_checks = max_checks;
+    st->floor_detect = floor_detect;
+    st->rtol = rtol;
+    st->fnorm2 = 0.0;
+    st->best = 0.0;
+    st->last_ratio = 0.0;
+  }
+}
+
+int num_levels(int n, int nc) {
+  if (nc < 5 || n < nc) return 0;
+  int L = 1;
+  while (n > nc) {
+    if ((n - 1) % 2) return 0;
+    n = (n - 1) / 2 + 1;
+    ++L;
+  }
+  return n == nc ? L : 0;
+}
+
+// 1D restriction weight (full weighting) and interpolation weight at fine offset o.
+double fw1(int o) { return o == 0 ? 0.5 : (o == 1 || o == -1 ? 0.25 : 0.0); }
+double p1(int prolong, int o) {
+  o = o < 0 ? -o : o;
+  if (prolong == 3) return o == 0 ? 1.0 : (o == 1 ? 9.0 / 16.0 : (o == 3 ? -1.0 / 16.0 : 0.0));
+  return o == 0 ? 1.0 : (o == 1 ? 0.5 : 0.0);
+}
+
+// c' = R c P in 1D (coarse offsets -3..3): c'_J = sum_o r(o) sum_k c_k p(o + k - 2J).
+void galerkin_1d(const double c[7], int prolong, double out[7]) {
+  for (int J = -3; J <= 3; ++J) {
+    double s = 0.0;
+    for (int o = -1; o <= 1; ++o)
+      for (int k = -3; k <= 3; ++k) s += fw1(o) * c[k + 3] * p1(prolong, o + k - 2 * J);
+    out[J + 3] = s;
+  }
+}
+
+LevelOp rediscretized(int order, int dim, double h) {
+  LevelOp op{};
+  const double s = 1.0 / (h * h);
+  if (order == 4) {
+    const double c[7] = {0.0, 1.0 / 12, -16.0 / 12, 30.0 / 12, -16.0 / 12, 1.0 / 12, 0.0};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  } else {
+    const double c[7] = {0.0, 0.0, -1.0, 2.0, -1.0, 0.0, 0.0};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  }
+  op.b[3] = 1.0;
+  op.cross = true;
+  op.diag = dim * op.a[3];
+  return op;
+}
+
+LevelOp galerkin(const LevelOp &fine, int dim, int prolong) {
+  LevelOp op{};
+  galerkin_1d(fine.a, prolong, op.a);
+  galerkin_1d(fine.b, prolong, op.b);
+  op.cross = false;
+  op.diag = dim * op.a[3] * std::pow(op.b[3], dim - 1);
+  return op;
+}
+
+// Dense matrix of the level operator over interior points (odd reflection folded in),
+// inverted by Gauss-Jordan elimination with partial pivoting; returned transposed.
+bool coarsest_inverse(const LevelOp &op, int dim, int n, std::vector<double> &inv_t) {
+  const int q = n - 2;
+  const int m = dim == 2 ? q * q : q * q * q;
+  std::vector<double> A((size_t)m * m, 0.0), B((size_t)m * m, 0.0);
+  auto coef = [&](int ox, int oy, int oz) {
+    // sum over axes of a along the axis times b along the others
+    double c = op.a[ox + 3] * op.b[oy + 3];
+    double d = op.b[ox + 3] * op.a[oy + 3];
+    if (dim == 3) {
+      c *= op.b[oz + 3];
+      d *= op.b[oz + 3];
+      return c + d + op.b[ox + 3] * op.b[oy + 3] * op.a[oz + 3];
+    }
+    return c + d;
+  };
+  auto fold = [&](int i, double &sign) {
+    if (i < 0) { i = -i; sign = -sign; }
+    if (i > n - 1) { i = 2 * (n - 1) - i; sign = -sign; }
+    return i;
+  };
+  const int zr = dim == 3 ? 3 : 0;
+  for (int row = 0; row < m; ++row) {
+    const int i = 1 + row % q, j = 1 + (row / q) % q, k = dim == 3 ? 1 + row / (q * q) : 0;
+    for (int oz = -zr; oz <= zr; ++oz)
+      for (int oy = -3; oy <= 3; ++oy)
+        for (int ox = -3; ox <= 3; ++ox) {
+          const double c = coef(ox, oy, oz);
+          if (c == 0.0) continue;
+          double sign = 1.0;
+          const int ti = fold(i + ox, sign), tj = fold(j + oy, sign);
+          const int tk = dim == 3 ? fold(k + oz, sign) : 0;
+          if (ti == 0 || ti == n - 1 || tj == 0 || tj == n - 1) continue;
+          if (dim == 3 && (tk == 0 || tk == n - 1)) continue;
+          const int col = (ti - 1) + q * ((tj - 1) + (dim == 3 ? q * (tk - 1) : 0));
+          A[(size_t)row * m + col] += sign * c;
+        }
+  }
+  for (int r = 0; r < m; ++r) B[(size_t)r * m + r] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int p = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)p * m + c])) p = r;
+    if (A[(size_t)p * m + c] == 0.0) return false;
+    if (p != c)
+      for (int k = 0; k < m; ++k) {
+        std::swap(A[(size_t)p * m + k], A[(size_t)c * m + k]);
+        std::swap(B[(size_t)p * m + k], B[(size_t)c * m + k]);
+      }
+    const double piv = 1.0 / A[(size_t)c * m + c];
+    for (int k = 0; k < m; ++k) {
+      A[(size_t)c * m + k] *= piv;
+      B[(size_t)c * m + k] *= piv;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double l = A[(size_t)r * m + c];
+      if (l == 0.0) continue;
+      for (int k = 0; k < m; ++k) {
+        A[(size_t)r * m + k] -= l * A[(size_t)c * m + k];
+        B[(size_t)r * m + k] -= l * B[(size_t)c * m + k];
+      }
+    }
+  }
+  inv_t.assign((size_t)m * m, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) inv_t[(size_t)c * m + r] = B[(size_t)r * m + c];
+  return true;
+}
+
+size_t points(int dim, int n) { return dim == 2 ? (size_t)n * n : (size_t)n * n * n; }
+
+mg_status validate(const mg_config *c, int *levels) {
+  if (!c) return fail(MG_EINVAL, "null config");
+  if (c->dim != 2 && c->dim != 3) return fail(MG_EINVAL, "dim must be 2 or 3");
+  if (c->order != 2 && c->order != 4) return fail(MG_EINVAL, "order must be 2 or 4");
+  if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN)
+    return fail(MG_EINVAL, "unknown coarse operator");
+  if (c->smoother != MG_SMOOTH_JACOBI) return fail(MG_EINVAL, "unknown smoother");
+  if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
+    return fail(MG_EINVAL, "need 0 <= nu1, nu2 <= 16 and nu1 + nu2 >= 1");
+  if (c->gamma != 1 && c->gamma != 2) return fail(MG_EINVAL, "gamma must be 1 (V) or 2 (W)");
+  if (c->prolong != 1 && c->prolong != 3) return fail(MG_EINVAL, "prolong must be 1 or 3");
+  if (c->restrict_op != 1) return fail(MG_EINVAL, "restrict_op must be 1 (full weighting)");
+  if (c->precision != MG_PREC_FP64 && c->precision != MG_PREC_MIXED)
+    return fail(MG_EINVAL, "unknown precision");
+  if (c->omega > 0.0 && c->omega >= 2.0) return fail(MG_EINVAL, "omega must be in (0, 2)");
+  if (c->max_cycles < 1 || c->max_cycles > MG_MAX_HISTORY - 2)
+    return fail(MG_EINVAL, "max_cycles out of range");
+  if (c->precision == MG_PREC_MIXED && (c->inner_cycles < 1 || c->inner_cycles > 64))
+    return fail(MG_EINVAL, "inner_cycles must be in 1..64 for mixed precision");
+  if (!(c->rtol >= 0.0)) return fail(MG_EINVAL, "rtol must be >= 0");
+  const int maxn = c->dim == 2 ? 32769 : 2049;
+  if (c->n > maxn) return fail(MG_EINVAL, "n too large");
+  if (c->n_coarsest > (c->dim == 2 ? 33 : 9)) return fail(MG_EINVAL, "n_coarsest too large");
+  const int L = num_levels(c->n, c->n_coarsest);
+  if (L <= 0) return fail(MG_EINVAL, "n must be 2^k+1 coarsening to n_coarsest >= 5");
+  *levels = L;
+  return MG_OK;
+}
+
+double default_omega(int dim, int order) {
+  // Equioscillation of the omega-Jacobi symbol over the high frequencies.
+  if (order == 4) return dim == 2 ? 10.0 / 13.0 : 9.0 / 11.0;
+  return dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0;
+}
+
+}  // namespace
+
+struct mg_ctx {
+  mg_config cfg{};
+  double omega = 0.0;
+  int dim = 2, L = 0;
+  std::vector<int> ns;
+  std::vector<LevelOp> ops;
+  std::vector<Buffers> b64, b32;
+  int device = 0;
+  hipStream_t stream = nullptr, cap = nullptr;
+  double *ainv_t = nullptr;
+  double *partials = nullptr;
+  int np_max = 0;
+  DevState *st = nullptr;
+  int *poll = nullptr;  // pinned host: 2 x {done, checks}
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev_async = nullptr;
+  bool async_pending = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double *gf = nullptr;
+  double *gu = nullptr;
+  bool use_graph = true;
+  int chunk = 4;
+  std::vector<void *> allocs;
+  size_t footprint = 0;
+};
+
+namespace {
+
+mg_status dev_alloc(mg_ctx *c, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return MG_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(MG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  c->allocs.push_back(*p);
+  c->footprint += bytes;
+  return MG_OK;
+}
+
+size_t footprint_of(const mg_config *cfg, int L) {
+  size_t total = 0;
+  int n = cfg->n;
+  const size_t es = cfg->precision == MG_PREC_MIXED ? 4 : 8;
+  const bool mixed = cfg->precision == MG_PREC_MIXED;
+  for (int l = 0; l < L; ++l) {
+    const size_t np = points(cfg->dim, n);
+    int arrays = (l > 0 || mixed) ? 2 : 0;  // u and f (level 0 FP64 uses the caller's)
+    if (L > 1 && l < L - 1) arrays += 1;    // Jacobi target
+    total += arrays * np * es;
+    n = (n - 1) / 2 + 1;
+  }
+  const int q = cfg->n_coarsest - 2;
+  const size_t m = cfg->dim == 2 ? (size_t)q * q : (size_t)q * q * q;
+  total += m * m * 8;
+  total += (size_t)mgk::sweep_partials(cfg->dim, cfg->n) * 8;
+  total += sizeof(DevState);
+  return total;
+}
+
+template <typename T>
+hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
+                 bool check, hipStream_t s) {
+  const int *done = &c->st->done;
+  const int dim = c->dim;
+  const int n = c->ns[l];
+  const LevelOp &op = c->ops[l];
+  hipError_t e;
+  if (c->L == 1) {  // a single level: the exact solve is the whole cycle
+    if (check) {
+      int np = 0;
+      e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero_u ? nullptr : u,
+                                  (T *)nullptr, n, c->partials, &np, done, s);
+      if (e != hipSuccess) return e;
+      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return mgk::launch_coarsest<T>(dim, c->ainv_t, f, u, n, done, s);
+  }
+  T *t = (T *)B[l].t;
+  T *cur = u, *other = t;
+  bool zero = zero_u;
+  if (check && c->cfg.nu1 == 0) {
+    int np = 0;
+    e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero ? nullptr : u,
+                                (T *)nullptr, n, c->partials, &np, done, s);
+    if (e != hipSuccess) return e;
+    e = mgk::launch_check(c->st, c->partials, np, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  if (zero && c->cfg.nu1 == 0) {
+    e = mgk::launch_fill<T>(u, points(dim, n), T(0), done, s);
+    if (e != hipSuccess) return e;
+    zero = false;
+  }
+  for (int k = 0; k < c->cfg.nu1; ++k) {
+    const bool first_check = check && k == 0;
+    int np = 0;
+    e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
+                                first_check ? c->partials : nullptr, &np, done, s);
+    if (e != hipSuccess) return e;
+    if (first_check) {
+      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    zero = false;
+    std::swap(cur, other);
+  }
+  T *uc = (T *)B[l + 1].u;
+  T *fc = (T *)B[l + 1].f;
+  e = mgk::launch_resid_restrict<T>(dim, op, f, cur, fc, n, done, s);
+  if (e != hipSuccess) return e;
+  if (l + 1 == c->L - 1) {
+    e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s);
+    if (e != hipSuccess) return e;
+  } else {
+    for (int g = 0; g < c->cfg.gamma; ++g) {
+      e = cycle<T>(c, B, l + 1, uc, fc, g == 0, false, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  T *dst = (c->cfg.nu2 % 2 == 0) ? u : t;
+  e = mgk::launch_prolong_correct<T>(dim, c->cfg.prolong, uc, cur, dst, n, done, s);
+  if (e != hipSuccess) return e;
+  cur = dst;
+  other = (dst == u) ? t : u;
+  for (int k = 0; k < c->cfg.nu2; ++k) {
+    e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
+                                done, s);
+    if (e != hipSuccess) return e;
+    std::swap(cur, other);
+  }
+  return hipSuccess;
+}
+
+// One solve step on stream s: an FP64 cycle, or a mixed-precision refinement step.
+hipError_t record_step(mg_ctx *c, const double *f, double *u, hipStream_t s) {
+  if (c->cfg.precision == MG_PREC_FP64) return cycle<double>(c, c->b64, 0, u, f, false, true, s);
+  const int *done = &c->st->done;
+  int np = 0;
+  float *r32 = (float *)c->b32[0].f;
+  float *e32 = (float *)c->b32[0].u;
+  hipError_t e = mgk::launch_sweep<double, float>(c->dim, mgk::kResidual, c->ops[0], c->omega, f, u,
+                                                  r32, c->ns[0], c->partials, &np, done, s);
+  if (e != hipSuccess) return e;
+  e = mgk::launch_check(c->st, c->partials, np, 1, s);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < c->cfg.inner_cycles; ++i) {
+    e = cycle<float>(c, c->b32, 0, e32, r32, i == 0, false, s);
+    if (e != hipSuccess) return e;
+  }
+  return mgk::launch_ir_correct(c->dim, u, e32, c->ns[0], done, s);
+}
+
+mg_status ensure_graph(mg_ctx *c, const double *f, double *u) {
+  if (!c->use_graph) return MG_OK;
+  if (c->gexec && c->gf == f && c->gu == u) return MG_OK;
+  if (c->gexec) {
+    MG_HIP(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    MG_HIP(hipGraphDestroy(c->graph));
+    c->graph = nullptr;
+  }
+  MG_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = record_step(c, f, u, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(MG_EDEVICE, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+  }
+  if (e2 != hipSuccess) return fail(MG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+  c->graph = g;
+  MG_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->gf = f;
+  c->gu = u;
+  return MG_OK;
+}
+
+mg_status launch_step(mg_ctx *c, const double *f, double *u) {
+  if (c->use_graph) {
+    MG_HIP(hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    MG_HIP(record_step(c, f, u, c->stream));
+  }
+  return MG_OK;
+}
+
+mg_status begin_solve(mg_ctx *c, const double *f, double *u, double rtol, int max_steps,
+                      int floor_detect) {
+  if (!f || !u) return fail(MG_EINVAL, "null f or u");
+  if (c->async_pending) return fail(MG_EBUSY, "an asynchronous solve is still pending");
+  MG_HIP(hipSetDevice(c->device));
+  mg_status st = ensure_graph(c, f, u);
+  if (st != MG_OK) return st;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, c->stream, c->st, rtol, max_steps + 1,
+                     floor_detect);
+  MG_HIP(hipGetLastError());
+  int np = 0;
+  MG_HIP((mgk::launch_sweep<double, double>(c->dim, mgk::kNormOnly, c->ops[0], c->omega, f,
+                                            nullptr, (double *)nullptr, c->ns[0], c->partials,
+                                            &np, nullptr, c->stream)));
+  MG_HIP(mgk::launch_check(c->st, c->partials, np, 0, c->stream));
+  return MG_OK;
+}
+
+mg_status fill_result(mg_ctx *c, mg_result *res, mg_status *outcome) {
+  DevState hs;
+  MG_HIP(hipMemcpyAsync(&hs, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  const int checks = std::min(hs.checks, mgk::kMaxHistory);
+  const double final_rel = checks > 0 ? hs.hist[checks - 1] : 0.0;
+  if (res) {
+    std::memset(res, 0, sizeof(*res));
+    const int steps = std::max(0, hs.checks - 1);
+    if (c->cfg.precision == MG_PREC_MIXED) {
+      res->outer_steps = steps;
+      res->cycles = steps * c->cfg.inner_cycles;
+    } else {
+      res->cycles = steps;
+    }
+    res->status = hs.status;
+    res->floor_hit = hs.status == 3;
+    res->rel_residual = final_rel;
+    res->conv_factor = hs.last_ratio;
+    res->history_len = checks;
+    for (int i = 0; i < checks; ++i) res->history[i] = hs.hist[i];
+  }
+  switch (hs.status) {
+    case 1: *outcome = MG_OK; break;
+    case 3: *outcome = MG_OK; break;  // rounding floor: the best FP64 can certify
+    case 4: *outcome = MG_ENUMERIC; break;
+    default: *outcome = MG_ENOCONV; break;
+  }
+  return MG_OK;
+}
+
+mg_status run(mg_ctx *c, const double *f, double *u, double rtol, int max_steps, int floor_detect,
+              mg_result *res) {
+  mg_status st = begin_solve(c, f, u, rtol, max_steps, floor_detect);
+  if (st != MG_OK) return st;
+  const int total = max_steps + 1;
+  int launched = 0, k = 0;
+  while (launched < total) {
+    const int cnt = std::min(c->chunk, total - launched);
+    for (int i = 0; i < cnt; ++i) {
+      st = launch_step(c, f, u);
+      if (st != MG_OK) return st;
+    }
+    launched += cnt;
+    MG_HIP(hipMemcpyAsync(&c->poll[2 * (k & 1)], &c->st->done, 2 * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    MG_HIP(hipEventRecord(c->ev[k & 1], c->stream));
+    if (k > 0) {
+      MG_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
+      if (c->poll[2 * ((k - 1) & 1)] != 0) break;
+    }
+    ++k;
+  }
+  mg_status outcome = MG_OK;
+  st = fill_result(c, res, &outcome);
+  if (st != MG_OK) return st;
+  if (outcome == MG_ENOCONV && rtol < 0.0) outcome = MG_OK;  // fixed cycle count requested
+  if (outcome != MG_OK) g_error = "solve did not reach rtol";
+  return outcome;
+}
+
+template <typename T>
+mg_status check_level(mg_ctx *c, int level, bool needs_coarse) {
+  if (!c) return fail(MG_EINVAL, "null handle");
+  if (level < 0 || level >= c->L || (needs_coarse && level >= c->L - 1))
+    return fail(MG_EINVAL, "level out of range");
+  MG_HIP(hipSetDevice(c->device));
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mg_last_error(void) { return g_error.c_str(); }
+
+size_t mg_footprint_bytes(const mg_config *cfg) {
+  int L = 0;
+  if (validate(cfg, &L) != MG_OK) return 0;
+  return footprint_of(cfg, L);
+}
+
+mg_status mg_destroy(mg_handle h) {
+  if (!h) return MG_OK;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (void *p : h->allocs) (void)hipFree(p);
+  if (h->poll) (void)hipHostFree(h->poll);
+  for (auto &e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->ev_async) (void)hipEventDestroy(h->ev_async);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  delete h;
+  return MG_OK;
+}
+
+mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
+  if (!out) return fail(MG_EINVAL, "null output handle");
+  *out = nullptr;
+  int L = 0;
+  mg_status st = validate(cfg, &L);
+  if (st != MG_OK) return st;
+  mg_ctx *c = new mg_ctx();
+  c->cfg = *cfg;
+  c->dim = cfg->dim;
+  c->L = L;
+  c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order);
+  c->stream = (hipStream_t)hip_stream;
+  if (const char *g = std::getenv("MG_GRAPH")) c->use_graph = std::atoi(g) != 0;
+  if (const char *k = std::getenv("MG_CHUNK")) c->chunk = std::max(1, std::atoi(k));
+  auto bail = [&](mg_status s) {
+    std::string msg = g_error;
+    mg_destroy(c);
+    g_error = msg;
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(MG_EDEVICE, "no HIP device"));
+  int n = cfg->n;
+  for (int l = 0; l < L; ++l) {
+    c->ns.push_back(n);
+    const double h = 1.0 / (n - 1);
+    if (l == 0 || cfg->coarse == MG_COARSE_NG)
+      c->ops.push_back(rediscretized(cfg->order, cfg->dim, h));
+    else
+      c->ops.push_back(galerkin(c->ops[l - 1], cfg->dim, cfg->prolong));
+    n = (n - 1) / 2 + 1;
+  }
+  std::vector<double> inv;
+  if (!coarsest_inverse(c->ops[L - 1], c->dim, c->ns[L - 1], inv))
+    return bail(fail(MG_EINVAL, "coarsest operator is singular"));
+  if ((st = dev_alloc(c, (void **)&c->ainv_t, inv.size() * sizeof(double))) != MG_OK) return bail(st);
+  const bool mixed = cfg->precision == MG_PREC_MIXED;
+  c->b64.resize(L);
+  c->b32.resize(L);
+  for (int l = 0; l < L; ++l) {
+    const size_t np = points(c->dim, c->ns[l]);
+    if (!mixed) {
+      Buffers &b = c->b64[l];
+      if (l > 0) {
+        if ((st = dev_alloc(c, &b.u, np * 8)) != MG_OK) return bail(st);
+        if ((st = dev_alloc(c, &b.f, np * 8)) != MG_OK) return bail(st);
+      }
+      if (L > 1 && l < L - 1)
+        if ((st = dev_alloc(c, &b.t, np * 8)) != MG_OK) return bail(st);
+    } else {
+      Buffers &b = c->b32[l];
+      if ((st = dev_alloc(c, &b.u, np * 4)) != MG_OK) return bail(st);
+      if ((st = dev_alloc(c, &b.f, np * 4)) != MG_OK) return bail(st);
+      if (L > 1 && l < L - 1)
+        if ((st = dev_alloc(c, &b.t, np * 4)) != MG_OK) return bail(st);
+    }
+  }
+  c->np_max = mgk::sweep_partials(c->dim, cfg->n);
+  if ((st = dev_alloc(c, (void **)&c->partials, (size_t)c->np_max * 8)) != MG_OK) return bail(st);
+  if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState))) != MG_OK) return bail(st);
+  if (hipMemcpy(c->ainv_t, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(MG_EDEVICE, "upload of the coarsest inverse failed"));
+  if (hipMemset(c->st, 0, sizeof(DevState)) != hipSuccess)
+    return bail(fail(MG_EDEVICE, "hipMemset failed"));
+  if (hipHostMalloc((void **)&c->poll, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(MG_ENOMEM, "pinned host allocation failed"));
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(MG_EDEVICE, "stream creation failed"));
+  for (auto &e : c->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(MG_EDEVICE, "event creation failed"));
+  if (hipEventCreateWithFlags(&c->ev_async, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(MG_EDEVICE, "event creation failed"));
+  *out = c;
+  return MG_OK;
+}
+
+mg_status mg_solve(mg_handle h, const double *f, double *u, mg_result *res) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  return run(h, f, u, h->cfg.rtol, h->cfg.max_cycles, 1, res);
+}
+
+mg_status mg_run_cycles(mg_handle h, const double *f, double *u, int ncycles, mg_result *res) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  if (ncycles < 0 || ncycles > MG_MAX_HISTORY - 2) return fail(MG_EINVAL, "ncycles out of range");
+  return run(h, f, u, -1.0, ncycles, 0, res);
+}
+
+mg_status mg_solve_async(mg_handle h, const double *f, double *u) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  mg_status st = begin_solve(h, f, u, h->cfg.rtol, h->cfg.max_cycles, 1);
+  if (st != MG_OK) return st;
+  for (int i = 0; i < h->cfg.max_cycles + 1; ++i) {
+    st = launch_step(h, f, u);
+    if (st != MG_OK) return st;
+  }
+  MG_HIP(hipEventRecord(h->ev_async, h->stream));
+  h->async_pending = true;
+  return MG_OK;
+}
+
+mg_status mg_query(mg_handle h, mg_result *res) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  if (!h->async_pending) return fail(MG_EINVAL, "no asynchronous solve pending");
+  hipError_t e = hipEventQuery(h->ev_async);
+  if (e == hipErrorNotReady) return MG_EBUSY;
+  if (e != hipSuccess) return fail(MG_EDEVICE, hipGetErrorString(e));
+  h->async_pending = false;
+  mg_status outcome = MG_OK;
+  mg_status st = fill_result(h, res, &outcome);
+  return st != MG_OK ? st : outcome;
+}
+
+mg_status mg_residual_norm(mg_handle h, const double *f, const double *u, double *rel) {
+  if (!h || !f || !u || !rel) return fail(MG_EINVAL, "null argument");
+  MG_HIP(hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, h->stream, h->st, -1.0, 2, 0);
+  int np = 0;
+  MG_HIP((mgk::launch_sweep<double, double>(h->dim, mgk::kNormOnly, h->ops[0], h->omega, f, nullptr,
+                                            (double *)nullptr, h->ns[0], h->partials, &np, nullptr,
+                                            h->stream)));
+  MG_HIP(mgk::launch_check(h->st, h->partials, np, 0, h->stream));
+  MG_HIP((mgk::launch_sweep<double, double>(h->dim, mgk::kNormOnly, h->ops[0], h->omega, f, u,
+                                            (double *)nullptr, h->ns[0], h->partials, &np, nullptr,
+                                            h->stream)));
+  MG_HIP(mgk::launch_check(h->st, h->partials, np, 1, h->stream));
+  DevState hs;
+  MG_HIP(hipMemcpyAsync(&hs, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  MG_HIP(hipStreamSynchronize(h->stream));
+  *rel = hs.hist[0];
+  return MG_OK;
+}
+
+int mg_level_size(mg_handle h, int level) {
+  if (!h || level < 0 || level >= h->L) return -1;
+  return h->ns[level];
+}
+
+mg_status mg_level_operator(mg_handle h, int level, double a[7], double b[7]) {
+  if (!h || level < 0 || level >= h->L || !a || !b) return fail(MG_EINVAL, "bad argument");
+  for (int i = 0; i < 7; ++i) {
+    a[i] = h->ops[level].a[i];
+    b[i] = h->ops[level].b[i];
+  }
+  return MG_OK;
+}
+
+mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, const void *u_in,
+                           void *u_out) {
+  mg_status st = fp32 ? check_level<float>(h, level, false) : check_level<double>(h, level, false);
+  if (st != MG_OK) return st;
+  if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  if (fp32)
+    MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kSweep, h->ops[level], h->omega,
+                                            (const float *)f, (const float *)u_in, (float *)u_out,
+                                            h->ns[level], nullptr, nullptr, nullptr, h->stream)));
+  else
+    MG_HIP((mgk::launch_sweep<double, double>(h->dim, mgk::kSweep, h->ops[level], h->omega,
+                                              (const double *)f, (const double *)u_in,
+                                              (double *)u_out, h->ns[level], nullptr, nullptr,
+                                              nullptr, h->stream)));
+  return MG_OK;
+}
+
+mg_status mg_kernel_residual(mg_handle h, int level, int fp32, const void *f, const void *u,
+                             void *r) {
+  mg_status st = check_level<double>(h, level, false);
+  if (st != MG_OK) return st;
+  if (!f || !u || !r) return fail(MG_EINVAL, "bad buffers");
+  if (fp32)
+    MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kResidual, h->ops[level], h->omega,
+                                            (const float *)f, (const float *)u, (float *)r,
+                                            h->ns[level], nullptr, nullptr, nullptr, h->stream)));
+  else
+    MG_HIP((mgk::launch_sweep<double, double>(h->dim, mgk::kResidual, h->ops[level], h->omega,
+                                              (const double *)f, (const double *)u, (double *)r,
+                                              h->ns[level], nullptr, nullptr, nullptr, h->stream)));
+  return MG_OK;
+}
+
+mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const void *f,
+                                      const void *u, void *fc) {
+  mg_status st = check_level<double>(h, level, true);
+  if (st != MG_OK) return st;
+  if (!f || !fc) return fail(MG_EINVAL, "bad buffers");
+  if (fp32)
+    MG_HIP(mgk::launch_resid_restrict<float>(h->dim, h->ops[level], (const float *)f,
+                                             (const float *)u, (float *)fc, h->ns[level], nullptr,
+                                             h->stream));
+  else
+    MG_HIP(mgk::launch_resid_restrict<double>(h->dim, h->ops[level], (const double *)f,
+                                              (const double *)u, (double *)fc, h->ns[level],
+                                              nullptr, h->stream));
+  return MG_OK;
+}
+
+mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void *v,
+                                    const void *u_in, void *u_out) {
+  mg_status st = check_level<double>(h, level, true);
+  if (st != MG_OK) return st;
+  if (!v || !u_in || !u_out) return fail(MG_EINVAL, "bad buffers");
+  if (fp32)
+    MG_HIP(mgk::launch_prolong_correct<float>(h->dim, h->cfg.prolong, (const float *)v,
+                                              (const float *)u_in, (float *)u_out, h->ns[level],
+                                              nullptr, h->stream));
+  else
+    MG_HIP(mgk::launch_prolong_correct<double>(h->dim, h->cfg.prolong, (const double *)v,
+                                               (const double *)u_in, (double *)u_out,
+                                               h->ns[level], nullptr, h->stream));
+  return MG_OK;
+}
+
+mg_status mg_kernel_coarsest_solve(mg_handle h, int fp32, const void *g, void *v) {
+  if (!h || !g || !v) return fail(MG_EINVAL, "bad argument");
+  MG_HIP(hipSetDevice(h->device));
+  const int nc = h->ns[h->L - 1];
+  if (fp32)
+    MG_HIP(mgk::launch_coarsest<float>(h->dim, h->ainv_t, (const float *)g, (float *)v, nc, nullptr,
+                                       h->stream));
+  else
+    MG_HIP(mgk::launch_coarsest<double>(h->dim, h->ainv_t, (const double *)g, (double *)v, nc,
+                                        nullptr, h->stream));
+  return MG_OK;
+}
+
+mg_status mg_synchronize(mg_handle h) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  MG_HIP(hipStreamSynchronize(h->stream));
+  return MG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad
+configurations before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_2008_03885_amd import mg
+
+
+def _declared_functions():
+    names = []
+    with open(os.path.join(ROOT, "include", "mg.h")) as fh:
+        text = fh.read()
+    for m in re.finditer(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(mg_[a-z0-9_]+)\s*\(", text, re.M):
+        names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("mg_setup", "mg_solve", "mg_destroy", "mg_footprint_bytes", "mg_solve_async",
+                     "mg_query", "mg_last_error", "mg_run_cycles"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(mg.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding covers the same names
+    assert set(_declared_functions()) <= set(mg._SIGS)
+
+
+@pytest.mark.parametrize("kwargs", [
+    dict(dim=4), dict(order=6), dict(n=100), dict(n=129, n_coarsest=7), dict(gamma=3),
+    dict(prolong=2), dict(restrict_op=3), dict(nu1=0, nu2=0), dict(omega=2.5),
+    dict(max_cycles=0), dict(precision=1, inner_cycles=0), dict(coarse=5),
+])
+def test_invalid_configs_rejected(kwargs):
+    cfg = mg.make_config(**kwargs)
+    assert mg.mg_footprint_bytes(cfg) == 0
+    h = ctypes.c_void_p()
+    st = mg.lib().mg_setup(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == mg.MG_EINVAL
+    assert h.value is None
+    assert mg.last_error() != ""
+
+
+def test_footprint_counts_hierarchy():
+    cfg = mg.make_config(dim=2, n=4097)
+    fp = mg.mg_footprint_bytes(cfg)
+    # level-0 Jacobi target, three arrays per intermediate level, u and f on the coarsest
+    n, total = 4097, 4097 ** 2 * 8
+    n = (n - 1) // 2 + 1
+    while n > 9:
+        total += 3 * n * n * 8
+        n = (n - 1) // 2 + 1
+    total += 2 * 9 * 9 * 8
+    assert total <= fp <= total + 2 * 1024 * 1024
+    mixed = mg.mg_footprint_bytes(mg.make_config(dim=2, n=4097, precision=mg.MG_PREC_MIXED))
+    assert mixed > 0
+
+
+def test_null_arguments_rejected():
+    lib = mg.lib()
+    assert lib.mg_solve(None, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_destroy(None) == mg.MG_OK
+    assert lib.mg_level_size(None, 0) == -1

@@ -1,0 +1,202 @@
+"""Each hot-path kernel against the oracle's same step, element by element (GPU).
+
+FP64 tolerances: the kernels evaluate the same sums in another order (difference form,
+fused multiply-adds), so results differ by a few units in the last place of the
+largest term; the bounds below are 1e-13 of that scale.  FP32 kernels are compared with
+the FP64 oracle applied to the same FP32-rounded inputs, to 2e-5 of the scale.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import Handle, assert_close, dev, host, rand_grid
+from paper_2008_03885_amd import mg
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-13, 2e-5
+
+# (dim, finest n, coarse, prolong, level): level sides cover single-block grids,
+# ragged last blocks (257, 1025 vs 252/250-column blocks) and the Galerkin kernels.
+CASES_2D = [
+    (2, 9, 0, 3, 0), (2, 17, 0, 3, 0), (2, 65, 0, 3, 0), (2, 257, 0, 3, 0), (2, 1025, 0, 3, 0),
+    (2, 1025, 0, 3, 2), (2, 257, 1, 3, 1), (2, 257, 1, 3, 2), (2, 1025, 1, 3, 1),
+    (2, 513, 1, 1, 1), (2, 513, 1, 1, 2),
+]
+
+
+def _scale_u(u, f, s):
+    R = (s.shape[0] - 1) // 2
+    return np.abs(u).max() + np.abs(f).max() / s[(R,) * s.ndim]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", CASES_2D)
+def test_smooth(dim, n, coarse, prolong, level, fp32):
+    H = Handle(dim, n, coarse=coarse, prolong=prolong)
+    try:
+        n_l, s = H.level(level)
+        u = rand_grid(n_l, dim, 1)
+        f = rand_grid(n_l, dim, 2) * s[(s.shape[0] // 2,) * dim]
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        out = dev(np.full_like(u, np.nan), fp32)
+        mg.mg_kernel_smooth(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.jacobi(s, H.omega, f, u)
+        assert_close(host(out), ref, (TOL32 if fp32 else TOL64) * _scale_u(u, f, s), "smooth")
+        # zero initial guess (u_in = NULL)
+        mg.mg_kernel_smooth(H.h, level, fp32, fd.data_ptr(), None, out.data_ptr())
+        ref0 = oracle.jacobi(s, H.omega, f, np.zeros_like(u))
+        assert_close(host(out), ref0, (TOL32 if fp32 else TOL64) * _scale_u(u, f, s), "smooth0")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", CASES_2D)
+def test_residual(dim, n, coarse, prolong, level, fp32):
+    H = Handle(dim, n, coarse=coarse, prolong=prolong)
+    try:
+        n_l, s = H.level(level)
+        d = s[(s.shape[0] // 2,) * dim]
+        u = rand_grid(n_l, dim, 3)
+        f = rand_grid(n_l, dim, 4) * d
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        out = dev(np.full_like(u, np.nan), fp32)
+        fd, ud = dev(f, fp32), dev(u, fp32)  # keep the tensors alive across the launch
+        mg.mg_kernel_residual(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.residual(s, f, u)
+        scale = np.abs(f).max() + d * np.abs(u).max()
+        assert_close(host(out), ref, (TOL32 if fp32 else TOL64) * scale * 4, "residual")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", [c for c in CASES_2D if c[1] > 9])
+def test_residual_restrict(dim, n, coarse, prolong, level, fp32):
+    H = Handle(dim, n, coarse=coarse, prolong=prolong)
+    try:
+        n_l, s = H.level(level)
+        if level >= H.oracle.levels - 1:
+            pytest.skip("coarsest level has no coarser level")
+        d = s[(s.shape[0] // 2,) * dim]
+        u = rand_grid(n_l, dim, 5)
+        f = rand_grid(n_l, dim, 6) * d
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        nc = (n_l - 1) // 2 + 1
+        out = dev(np.full((nc,) * dim, np.nan), fp32)
+        fd, ud = dev(f, fp32), dev(u, fp32)
+        mg.mg_kernel_residual_restrict(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.restrict(oracle.residual(s, f, u))
+        scale = np.abs(f).max() + d * np.abs(u).max()
+        assert_close(host(out), ref, (TOL32 if fp32 else TOL64) * scale * 4, "resid_restrict")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", [c for c in CASES_2D if c[1] > 9])
+def test_prolong_correct(dim, n, coarse, prolong, level, fp32):
+    H = Handle(dim, n, coarse=coarse, prolong=prolong)
+    try:
+        n_l, s = H.level(level)
+        if level >= H.oracle.levels - 1:
+            pytest.skip("coarsest level has no coarser level")
+        nc = (n_l - 1) // 2 + 1
+        u = rand_grid(n_l, dim, 7)
+        v = rand_grid(nc, dim, 8)
+        if fp32:
+            u, v = u.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64)
+        ud, vd = dev(u, fp32), dev(v, fp32)
+        out = dev(np.full_like(u, np.nan), fp32)
+        mg.mg_kernel_prolong_correct(H.h, level, fp32, vd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.prolong_add(v, u.copy(), prolong)
+        scale = np.abs(u).max() + 2 * np.abs(v).max()
+        assert_close(host(out), ref, (TOL32 if fp32 else TOL64) * scale, "prolong")
+        # in place
+        mg.mg_kernel_prolong_correct(H.h, level, fp32, vd.data_ptr(), ud.data_ptr(), ud.data_ptr())
+        assert_close(host(ud), ref, (TOL32 if fp32 else TOL64) * scale, "prolong in place")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,coarse,prolong", [(2, 0, 3), (2, 1, 3), (2, 1, 1)])
+def test_coarsest_solve(dim, coarse, prolong, fp32):
+    H = Handle(dim, 65, coarse=coarse, prolong=prolong)
+    try:
+        L = H.oracle.levels
+        n_c, s = H.level(L - 1)
+        g = rand_grid(n_c, dim, 9)
+        if fp32:
+            g = g.astype(np.float32).astype(np.float64)
+        out = dev(np.full_like(g, np.nan), fp32)
+        gd = dev(g, fp32)
+        mg.mg_kernel_coarsest_solve(H.h, fp32, gd.data_ptr(), out.data_ptr())
+        ref = H.oracle.coarsest_solve(g)
+        tol = (1e-6 if fp32 else 1e-12) * np.abs(ref).max()
+        assert_close(host(out), ref, tol, "coarsest")
+    finally:
+        H.close()
+
+
+def test_level_operators_match_oracle_stencils():
+    """The library's 1D-factor Galerkin recursion reproduces the oracle's coarse stencils
+    (built by the definition R*L*P on the infinite grid)."""
+    for coarse, prolong in ((0, 3), (1, 3), (1, 1)):
+        H = Handle(2, 257, coarse=coarse, prolong=prolong)
+        try:
+            for l in range(H.oracle.levels):
+                _, s = H.level(l)
+                a, b = mg.mg_level_operator(H.h, l)
+                a, b = np.array(a), np.array(b)
+                dense = np.outer(b, a) + np.outer(a, b)  # [y][x]
+                R = (s.shape[0] - 1) // 2
+                full = np.zeros((7, 7))
+                full[3 - R:4 + R, 3 - R:4 + R] = s
+                assert np.abs(dense - full).max() <= 1e-12 * np.abs(full).max()
+        finally:
+            H.close()
+
+
+def test_full_size_sweep_4097():
+    """Level-0 sweep and residual at the benchmark size, every element."""
+    n = 4097
+    H = Handle(2, n)
+    try:
+        _, s = H.level(0)
+        u = rand_grid(n, 2, 11)
+        f = rand_grid(n, 2, 12) * s[2, 2]
+        out = dev(np.full_like(u, np.nan))
+        ud, fd = dev(u), dev(f)
+        mg.mg_kernel_smooth(H.h, 0, 0, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        assert_close(host(out), oracle.jacobi(s, H.omega, f, u), TOL64 * _scale_u(u, f, s), "sweep")
+        nc = (n - 1) // 2 + 1
+        fc = dev(np.full((nc, nc), np.nan))
+        mg.mg_kernel_residual_restrict(H.h, 0, 0, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
+        ref = oracle.restrict(oracle.residual(s, f, u))
+        assert_close(host(fc), ref, TOL64 * 4 * (np.abs(f).max() + s[2, 2] * np.abs(u).max()), "rr")
+        v = rand_grid(nc, 2, 13)
+        vd = dev(v)
+        mg.mg_kernel_prolong_correct(H.h, 0, 0, vd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.prolong_add(v, u.copy(), 3)
+        assert_close(host(out), ref, TOL64 * (np.abs(u).max() + 2 * np.abs(v).max()), "prolong")
+    finally:
+        H.close()
+
+
+def test_kernels_are_deterministic():
+    n = 1025
+    H = Handle(2, n, coarse=1)
+    try:
+        u, f = dev(rand_grid(n, 2, 14)), dev(rand_grid(n, 2, 15))
+        a, b = dev(np.zeros((n, n))), dev(np.zeros((n, n)))
+        for out in (a, b):
+            mg.mg_kernel_smooth(H.h, 0, 0, f.data_ptr(), u.data_ptr(), out.data_ptr())
+        assert np.array_equal(host(a), host(b))
+    finally:
+        H.close()

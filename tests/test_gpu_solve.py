@@ -1,0 +1,203 @@
+"""Whole-cycle and whole-solve parity of the HIP path with the oracle (GPU).
+
+Bar (FP64): after the same fixed number of cycles, ||u_gpu - u_oracle|| <= 1e-12 ||u_oracle||;
+the recorded relative residuals agree to 1e-9 relative plus 5e-14 absolute (near the
+rounding floor, about 6e-13 at n = 1025, both are dominated by rounding noise that the
+two implementations produce in different orders).  Converged solves are checked against the exact discrete solution
+(sine transform) within the bound ||L^{-1}|| ||r|| that the final residual implies.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import Handle, dev, host, rand_grid, torch
+from oracle import dst
+from paper_2008_03885_amd import inputs, mg
+
+pytestmark = pytest.mark.gpu
+
+
+def _fixed_cycles(H, f, cycles):
+    fd = dev(f)
+    ud = dev(np.zeros_like(f))
+    st, res = mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), cycles)
+    u_ref = np.zeros_like(f)
+    _, hist = H.oracle.solve(u_ref, f, rtol=0.0, max_cycles=cycles)
+    return host(ud), res, u_ref, hist
+
+
+CYCLE_CASES = [
+    # dim, n, coarse, prolong, nu1, nu2, gamma
+    (2, 129, 0, 3, 2, 1, 1), (2, 129, 1, 3, 2, 1, 1), (2, 129, 0, 3, 2, 1, 2),
+    (2, 129, 1, 3, 2, 1, 2), (2, 129, 0, 1, 2, 1, 1), (2, 129, 1, 1, 2, 2, 1),
+    (2, 257, 0, 3, 1, 1, 1), (2, 65, 0, 3, 0, 2, 1), (2, 65, 0, 3, 3, 0, 2), (2, 9, 0, 3, 2, 1, 1),
+    (2, 1025, 1, 3, 2, 1, 2),
+]
+
+
+@pytest.mark.parametrize("dim,n,coarse,prolong,nu1,nu2,gamma", CYCLE_CASES)
+def test_fixed_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, gamma=gamma)
+    try:
+        _, f, _ = inputs.manufactured_2d(n)
+        cycles = 8
+        u, res, u_ref, hist = _fixed_cycles(H, f, cycles)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        assert res.cycles == cycles and res.history_len == cycles + 1
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+def test_c1_solve_to_tolerance():
+    """2D 129^2, manufactured solution, V(2,1), nG, FW + cubic, omega = 10/13, to 1e-10."""
+    n = 129
+    H = Handle(2, n, rtol=1e-10, max_cycles=60)
+    try:
+        ustar, f, c = inputs.manufactured_2d(n)
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_OK and res.status == 1
+        assert res.rel_residual <= 1e-10
+        u = host(ud)
+        u_ref = np.zeros_like(f)
+        cyc, hist = H.oracle.solve(u_ref, f, rtol=1e-10, max_cycles=60)
+        assert res.cycles == cyc
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        exact = dst.discrete_solution_of_sine_series(n, c)
+        bound = res.rel_residual * oracle.norm(f) / dst.eigenvalues(n, 2).min()
+        assert oracle.norm(u - exact) <= 1.01 * bound
+        # the device residual check agrees with the oracle's long-double residual
+        s = H.oracle.level_stencil(0)[1]
+        rel_ld = oracle.residual_norm_ld(s, f, u) / oracle.norm(f)
+        assert abs(res.rel_residual - rel_ld) <= 1e-3 * rel_ld
+        assert abs(mg.mg_residual_norm(H.h, fd.data_ptr(), ud.data_ptr()) - rel_ld) <= 1e-3 * rel_ld
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_c2_full_size(coarse, gamma):
+    """2D 4097^2, Fourier right-hand side k <= 64, V(2,1)/W(2,1), nG/Galerkin, FP64: the
+    solve reaches 1e-10 or the rounding floor, and matches the exact discrete solution."""
+    n = 4097
+    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
+    H = Handle(2, n, coarse=coarse, gamma=gamma, rtol=1e-10, max_cycles=40)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_OK, res.status
+        assert res.rel_residual <= 1e-10 or (res.floor_hit and res.rel_residual <= 3e-10)
+        assert res.cycles <= 30
+        u = host(ud)
+        exact = dst.solve(f)
+        err = np.linalg.norm(u - exact) / np.linalg.norm(exact)
+        assert err <= 1e-9, err
+        # the device residual equals an independent long-double evaluation
+        s = oracle.fine_stencil(2, 4, 1.0 / (n - 1))
+        rel_ld = oracle.residual_norm_ld(s, f, u) / oracle.norm(f)
+        assert abs(res.rel_residual - rel_ld) <= 0.05 * rel_ld
+    finally:
+        H.close()
+
+
+def test_c2_two_cycles_match_oracle_elementwise():
+    n = 4097
+    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
+    H = Handle(2, n)
+    try:
+        u, res, u_ref, hist = _fixed_cycles(H, f, 2)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        assert np.abs(u - u_ref).max() <= 1e-12 * np.abs(u_ref).max()
+    finally:
+        H.close()
+
+
+def test_mixed_precision_2d():
+    """FP32 cycles inside FP64 refinement reach the FP64 tolerance; final error vs FP64."""
+    n = 1025
+    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
+    H64 = Handle(2, n, rtol=1e-10)
+    Hmx = Handle(2, n, precision=1, rtol=1e-10, max_cycles=20, inner_cycles=4)
+    try:
+        fd = dev(f)
+        u64, umx = dev(np.zeros_like(f)), dev(np.zeros_like(f))
+        st, r64 = mg.mg_solve(H64.h, fd.data_ptr(), u64.data_ptr())
+        st2, rmx = mg.mg_solve(Hmx.h, fd.data_ptr(), umx.data_ptr())
+        assert st == mg.MG_OK and st2 == mg.MG_OK
+        assert rmx.rel_residual <= 1e-10 and rmx.outer_steps >= 2
+        a, b = host(u64), host(umx)
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        assert rel <= 1e-9, rel
+        exact = dst.solve(f)
+        assert np.linalg.norm(b - exact) / np.linalg.norm(exact) <= 1e-9
+    finally:
+        H64.close()
+        Hmx.close()
+
+
+def test_async_solve_matches_sync_and_is_deterministic():
+    n = 513
+    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
+    H = Handle(2, n, rtol=1e-10, max_cycles=40)
+    try:
+        fd = dev(f)
+        u1, u2, u3 = (dev(np.zeros_like(f)) for _ in range(3))
+        _, r1 = mg.mg_solve(H.h, fd.data_ptr(), u1.data_ptr())
+        _, r2 = mg.mg_solve(H.h, fd.data_ptr(), u2.data_ptr())   # new pointers: new graph
+        mg.mg_solve_async(H.h, fd.data_ptr(), u3.data_ptr())
+        import time
+        while True:
+            st, r3 = mg.mg_query(H.h)
+            if st != mg.MG_EBUSY:
+                break
+            time.sleep(0.001)
+        a, b, c = host(u1), host(u2), host(u3)
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+        assert r1.cycles == r2.cycles == r3.cycles
+        assert r1.hist() == r3.hist()
+    finally:
+        H.close()
+
+
+def test_warm_start_continues_the_iteration():
+    """u is the whole state: k cycles then m cycles equals k+m cycles."""
+    n = 257
+    _, f, _ = inputs.manufactured_2d(n)
+    H = Handle(2, n)
+    try:
+        fd = dev(f)
+        a, b = dev(np.zeros_like(f)), dev(np.zeros_like(f))
+        mg.mg_run_cycles(H.h, fd.data_ptr(), a.data_ptr(), 5)
+        mg.mg_run_cycles(H.h, fd.data_ptr(), b.data_ptr(), 3)
+        mg.mg_run_cycles(H.h, fd.data_ptr(), b.data_ptr(), 2)
+        assert np.array_equal(host(a), host(b))
+    finally:
+        H.close()
+
+
+def test_cycle_cap_reports_enoconv():
+    n = 129
+    _, f, _ = inputs.manufactured_2d(n)
+    H = Handle(2, n, rtol=1e-14, max_cycles=3)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_ENOCONV and res.status == 2 and res.cycles == 3
+    finally:
+        H.close()
+
+
+def test_nonfinite_rhs_reports_enumeric():
+    n = 65
+    f = np.zeros((n, n))
+    f[10, 10] = np.nan
+    H = Handle(2, n)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_ENUMERIC and res.status == 4
+    finally:
+        H.close()
