@@ -158,6 +158,17 @@ mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const vo
 mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void *v,
                                     const void *u_in, void *u_out);
 
+/* The pre-coarse half of a cycle on level l in one pass (2D): u_out = nu1 omega-Jacobi
+ * sweeps of u_in (NULL = zero guess), fc = I_h^H (f - L_l u_out) on level l+1.
+ * u_out != u_in. */
+mg_status mg_kernel_presmooth_restrict(mg_handle h, int level, int fp32, const void *f,
+                                       const void *u_in, void *u_out, void *fc);
+
+/* The post-coarse half of a cycle on level l in one pass (2D): u_out = nu2 omega-Jacobi
+ * sweeps of (u_in + I_H^h v).  u_out != u_in. */
+mg_status mg_kernel_prolong_postsmooth(mg_handle h, int level, int fp32, const void *v,
+                                       const void *u_in, const void *f, void *u_out);
+
 /* v = L_c^{-1} g on the coarsest level (FP64 arithmetic for either storage type). */
 mg_status mg_kernel_coarsest_solve(mg_handle h, int fp32, const void *g, void *v);
 

@@ -1,0 +1,578 @@
+// fused2d.hip -- temporally blocked 2D cycle kernels for gfx950.
+//
+// Every wave (64 lanes) owns one strip of grid columns and marches down a chunk of rows
+// on its own: no block-wide barrier inside the row loop, so the u/f loads of the next
+// rows stay in flight while the current rows are computed.  y neighbours live in
+// per-lane register windows; x neighbours are exchanged through a wave-private LDS row
+// (one write and two paired reads per stencil stage; waves of a block never wait for
+// each other).  Each stencil stage shrinks the valid lanes by the stencil radius R, so
+// a strip carries a halo of H columns on each side that are computed but not written.
+//
+// Pre kernel (k_pre2d):  NU omega-Jacobi sweeps, then the defect f - L u, then full
+//   weighting, in one pass: reads u and f once, writes the smoothed u and the coarse
+//   right-hand side.  Stage s of the pipeline lags stage s-1 by R rows.
+// Post kernel (k_post2d): interpolation of the coarse correction (cubic or linear),
+//   correction, then NU2 sweeps, in one pass: reads u, f and the coarse v once, writes u.
+//
+// Dirichlet closure: all inputs are extended oddly across the boundary (u(-i) = -u(i),
+// boundary values read as zero), and every stage is evaluated with the same formula on
+// the extended rows and columns, which reproduces the odd extension of its output.
+// Blocks whose rows all lie inside the grid take a path without row reflection.
+//
+// Loads are issued unconditionally from a valid address and the reflection sign / zero
+// is applied when the value is consumed: a branch around a load would make the compiler
+// wait for it at once and serialise the row loop on memory latency.
+#include <cmath>
+#include <type_traits>
+
+#include "mg_internal.h"
+
+namespace mgk {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kPad = 4;              // LDS row padding on each side (>= R + 1)
+constexpr int kRowLen = kWave + 2 * kPad;
+constexpr int kPF = 4;               // rows of u and f loaded ahead
+
+__device__ __forceinline__ bool stopped(const int *done) { return done != nullptr && *done != 0; }
+
+__device__ __forceinline__ int floordiv2(int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); }
+
+// Odd extension: fold index i into 0..n-1 (at most two reflections), sign flips per
+// reflection; returns -1 when i lies further out.
+__device__ __forceinline__ int fold(int i, int n, int &sign) {
+  if (i < 0) { i = -i; sign = -sign; }
+  if (i > n - 1) { i = 2 * (n - 1) - i; sign = -sign; }
+  if (i < 0) { i = -i; sign = -sign; }
+  return (i >= 0 && i <= n - 1) ? i : -1;
+}
+
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// L u at the centre of window w (rows c-R..c+R of this lane's column); x neighbours
+// through the wave's LDS rows (ra, rb point at this lane's slot).  Cross operator
+// (R = 2): difference form with weights w1, w2.  Separable operator (R = 3):
+// L = a_x b_y + b_x a_y with the a factors in difference form.
+template <typename T, int R>
+__device__ __forceinline__ T apply_op(const T (&w)[2 * R + 1], const KOp<T> &op, T *ra, T *rb) {
+  const T c = w[R];
+  if constexpr (R == 2) {
+    ra[0] = c;
+    wave_sync();
+    const T xm1 = ra[-1], xp1 = ra[1], xm2 = ra[-2], xp2 = ra[2];
+    wave_sync();
+    return op.w1 * (((c - xm1) + (c - xp1)) + ((c - w[R - 1]) + (c - w[R + 1]))) +
+           op.w2 * (((c - xm2) + (c - xp2)) + ((c - w[R - 2]) + (c - w[R + 2])));
+  } else {
+    T A = T(0), B = T(0);
+#pragma unroll
+    for (int k = 0; k < 2 * R + 1; ++k) {
+      if (k != R) A += op.a[k] * (w[k] - c);
+      B += op.b[k] * w[k];
+    }
+    ra[0] = A;
+    rb[0] = B;
+    wave_sync();
+    T lu = T(0);
+#pragma unroll
+    for (int i = 0; i < 2 * R + 1; ++i) {
+      if (i != R) lu += op.a[i] * (rb[i - R] - B);
+      lu += op.b[i] * ra[i - R];
+    }
+    wave_sync();
+    return lu;
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void push(T (&w)[N], T v) {
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k) w[k] = w[k + 1];
+  w[N - 1] = v;
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double ws[kWavesPerBlock];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double tot = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kWavesPerBlock; ++i) tot += ws[i];
+  return tot;
+}
+
+// Row access for one lane's column: raw loads from a valid address and the factor that
+// turns them into the odd extension (sign, or zero on and beyond the boundary).
+template <typename T>
+struct Column {
+  int n;
+  int xs;       // address column (valid even when the lane lies outside)
+  bool xin;     // the lane's column is an interior column
+  T xsign;      // reflection sign of the column
+  T xmul;       // xin ? xsign : 0
+  __device__ void init(int x, int n_) {
+    n = n_;
+    int sx = 1;
+    const int xf = fold(x, n, sx);
+    xin = xf > 0 && xf < n - 1;
+    xs = xin ? xf : 1;
+    xsign = T(sx);
+    xmul = xin ? xsign : T(0);
+  }
+  template <bool FAST>
+  __device__ __forceinline__ size_t addr(int y) const {
+    if (FAST) return (size_t)y * n + xs;
+    int s = 1;
+    int ys = fold(y, n, s);
+    ys = (ys > 0 && ys < n - 1) ? ys : 1;
+    return (size_t)ys * n + xs;
+  }
+  template <bool FAST>
+  __device__ __forceinline__ T fix(T v, int y) const {
+    if (FAST) return v * xmul;
+    int s = 1;
+    const int ys = fold(y, n, s);
+    const bool ok = xin && ys > 0 && ys < n - 1;
+    return ok ? v * (xsign * T(s)) : T(0);
+  }
+};
+
+// Pre-kernel modes.
+constexpr int kWriteU = 1;    // write the smoothed iterate
+constexpr int kRestrict = 2;  // full-weight the defect onto the coarse grid
+constexpr int kWriteR = 4;    // write the defect itself
+
+template <typename T>
+struct PreArgs {
+  const T *f;
+  const T *u;  // nullptr: zero initial guess
+  T *uout;
+  T *rout;
+  T *fc;
+  int n;
+  int chunk;  // coarse rows (kRestrict) or fine rows per block
+  KOp<T> op;
+  double *partials;  // sum of squares of the first defect (f - L u), per block
+  const int *done;
+};
+
+template <typename T, int R, int NU, int MODE, bool HAS_U>
+__global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
+  constexpr bool RESTRICT = (MODE & kRestrict) != 0;
+  constexpr bool WRITE_R = (MODE & kWriteR) != 0;
+  constexpr bool WRITE_U = (MODE & kWriteU) != 0;
+  constexpr bool RES = RESTRICT || WRITE_R;
+  constexpr int K = NU + (RES ? 1 : 0);
+  constexpr int H = K * R + (RESTRICT ? 1 : 0);
+  constexpr int S = kWave - 2 * H;
+  constexpr int W = 2 * R + 1;
+  constexpr int FQ = NU * R + 1;
+  __shared__ T lrow[kWavesPerBlock][2][kRowLen];
+  if (stopped(a.done)) return;
+  const int n = a.n;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  const int strip = blockIdx.x * kWavesPerBlock + wv;
+  const int x = strip * S - H + lane;
+  const bool active = strip * S < n;  // wave-uniform
+  const bool useful = lane >= H && lane < H + S && x <= n - 1;
+  T *ra = &lrow[wv][0][kPad + lane];
+  T *rb = &lrow[wv][1][kPad + lane];
+  Column<T> col;
+  col.init(x, n);
+
+  // Rows: the pipeline emits stage-NU values and defects at rows ya..yb; rows [own_a,
+  // own_b) belong to this block for writes and for the defect norm.
+  int ya, yb, own_a, own_b, Jlo = 0, Jhi = 0;
+  const int nc = (n - 1) / 2 + 1;
+  if (RESTRICT) {
+    const int J0 = blockIdx.y * a.chunk, J1 = min(J0 + a.chunk, nc);
+    ya = 2 * J0 - 1;
+    yb = 2 * J1 - 1;
+    own_a = 2 * J0;
+    own_b = min(2 * J1, n);
+    Jlo = max(J0, 1);
+    Jhi = min(J1, nc - 1);
+    if (active && useful && (x & 1) == 0) {
+      const int I = x >> 1;
+      if (J0 == 0) a.fc[I] = T(0);
+      if (J1 == nc) a.fc[(size_t)(nc - 1) * nc + I] = T(0);
+    }
+  } else {
+    const int y0 = blockIdx.y * a.chunk;
+    ya = y0;
+    yb = min(y0 + a.chunk, n) - 1;
+    own_a = y0;
+    own_b = yb + 1;
+  }
+  const int ts = ya - NU * R, te = yb + NU * R;
+  const bool fast = ts - R > 0 && te + R + kPF < n - 1;
+  const T *up = HAS_U ? a.u : a.f;
+
+  double acc = 0.0;
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    T w[NU + 1][W];
+    T fw[FQ];
+    T uq[kPF], fq[kPF];
+    T r0 = T(0), r1 = T(0);  // defects of the two rows before the current one
+#pragma unroll
+    for (int s = 0; s <= NU; ++s)
+#pragma unroll
+      for (int k = 0; k < W; ++k) w[s][k] = T(0);
+#pragma unroll
+    for (int k = 0; k < FQ; ++k) fw[k] = T(0);
+    if (HAS_U) {
+#pragma unroll
+      for (int k = 0; k < 2 * R; ++k) w[0][k + 1] = col.template fix<FAST>(up[col.template addr<FAST>(ts - R + k)], ts - R + k);
+    }
+#pragma unroll
+    for (int p = 0; p < kPF; ++p) {
+      if (HAS_U) uq[p] = up[col.template addr<FAST>(ts + R + p)];
+      fq[p] = a.f[col.template addr<FAST>(ts + p)];
+    }
+    const KOp<T> op = a.op;
+
+    for (int t = ts; t <= te; ++t) {
+      const T unew = HAS_U ? col.template fix<FAST>(uq[0], t + R) : T(0);
+      const T fnew = col.template fix<FAST>(fq[0], t);
+      if (HAS_U) push(uq, up[col.template addr<FAST>(t + R + kPF)]);
+      push(fq, a.f[col.template addr<FAST>(t + kPF)]);
+      push(w[0], unew);
+      push(fw, fnew);  // fw[FQ-1-j] = f at row t - j
+#pragma unroll
+      for (int s = 1; s <= NU; ++s) {
+        // stage s: sweep at row t - (s-1) R, the centre of w[s-1]
+        const T fv = fw[FQ - 1 - (s - 1) * R];
+        const T r = fv - apply_op<T, R>(w[s - 1], op, ra, rb);
+        if (s == 1 && a.partials != nullptr && useful && col.xin && t >= own_a && t < own_b &&
+            t > 0 && t < n - 1)
+          acc += (double)r * (double)r;
+        push(w[s], w[s - 1][R] + op.om_d * r);
+      }
+      const int c = t - NU * R;  // row of the centre of w[NU]
+      T r = T(0);
+      if (RES || (NU == 0 && a.partials != nullptr)) {
+        r = fw[0] - apply_op<T, R>(w[NU], op, ra, rb);
+        if (NU == 0 && a.partials != nullptr && useful && col.xin && c >= own_a && c < own_b &&
+            c > 0 && c < n - 1)
+          acc += (double)r * (double)r;
+      }
+      if (useful && c >= own_a && c < own_b && c >= 0 && c <= n - 1) {
+        const bool inside = col.xin && c > 0 && c < n - 1;
+        const size_t id = (size_t)c * n + x;
+        if (WRITE_U) a.uout[id] = inside ? w[NU][R] : T(0);
+        if (WRITE_R) a.rout[id] = inside ? r : T(0);
+      }
+      if (RESTRICT) {
+        if ((c & 1) != 0) {
+          const int J = (c - 1) >> 1;
+          if (J >= Jlo && J < Jhi) {
+            const T ry = T(0.25) * r0 + T(0.5) * r1 + T(0.25) * r;
+            ra[0] = ry;
+            wave_sync();
+            const T left = ra[-1], right = ra[1];
+            wave_sync();
+            if (useful && (x & 1) == 0) {
+              const int I = x >> 1;
+              const bool inside = I > 0 && I < nc - 1;
+              a.fc[(size_t)J * nc + I] = inside ? T(0.25) * left + T(0.5) * ry + T(0.25) * right : T(0);
+            }
+          }
+        }
+        r0 = r1;
+        r1 = r;
+      }
+    }
+  };
+  if (active) {
+    if (fast)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+  }
+  if (a.partials != nullptr) {
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+template <typename T>
+struct PostArgs {
+  const T *v;    // coarse correction, side nc
+  const T *uin;  // iterate before the correction
+  const T *f;
+  T *uout;
+  int n;
+  int chunk;  // fine rows per block
+  KOp<T> op;
+  const int *done;
+};
+
+template <typename T, int R, int NU2, int P>
+__global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
+  constexpr int H = NU2 * R;
+  constexpr int S = kWave - 2 * H;
+  constexpr int W = 2 * R + 1;
+  constexpr int FQ = NU2 > 0 ? (NU2 - 1) * R + 1 : 1;
+  __shared__ T lrow[kWavesPerBlock][2][kRowLen];
+  if (stopped(a.done)) return;
+  const int n = a.n, nc = (n - 1) / 2 + 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  const int strip = blockIdx.x * kWavesPerBlock + wv;
+  const int x0 = strip * S - H;
+  const int x = x0 + lane;
+  if (strip * S >= n) return;  // whole wave idle; no block barrier follows
+  const bool useful = lane >= H && lane < H + S && x <= n - 1;
+  T *ra = &lrow[wv][0][kPad + lane];
+  T *rb = &lrow[wv][1][kPad + lane];
+  Column<T> col;
+  col.init(x, n);
+  // coarse column loaded by this lane (lanes 0..35 cover the strip and its stencil)
+  const int Ib = floordiv2(x0) - 1;
+  Column<T> ccol;
+  ccol.init(Ib + lane, nc);
+  // LDS slots of this fine column's coarse neighbours (relative to the lane's own slot)
+  const int src0 = floordiv2(x) - Ib - lane;
+  T *crow = &lrow[wv][1][kPad + lane];
+
+  const int y0 = blockIdx.y * a.chunk;
+  const int y1 = min(y0 + a.chunk, n);
+  const int ts = y0 - NU2 * R, te = y1 - 1 + NU2 * R;
+  const int jb0 = floordiv2(ts) - 1;
+  const bool fast = ts - R > 0 && te + kPF < n - 1 && jb0 - 1 > 0 && floordiv2(te) + 4 < nc - 1;
+  const T *fp = NU2 > 0 ? a.f : a.uin;  // f is not read without post-smoothing
+
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    // x-interpolation of a coarse row at this lane's fine column
+    auto interp = [&](T cv) -> T {
+      crow[0] = cv;
+      wave_sync();
+      const T c0 = crow[src0], c1 = crow[src0 + 1];
+      T out;
+      if (P == 3) {
+        const T cm = crow[src0 - 1], c2 = crow[src0 + 2];
+        out = (x & 1) == 0 ? c0 : (T(9) * (c0 + c1) - (cm + c2)) * T(0.0625);
+      } else {
+        out = (x & 1) == 0 ? c0 : T(0.5) * (c0 + c1);
+      }
+      wave_sync();
+      return out;
+    };
+    T pw[4];
+    int jb = jb0;
+    // coarse rows jb..jb+3 now, and the next one ahead
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pw[k] = interp(ccol.template fix<FAST>(a.v[ccol.template addr<FAST>(jb + k)], jb + k));
+    T cnext = a.v[ccol.template addr<FAST>(jb + 4)];
+    T w[NU2 + 1][W];
+#pragma unroll
+    for (int s = 0; s <= NU2; ++s)
+#pragma unroll
+      for (int k = 0; k < W; ++k) w[s][k] = T(0);
+    T fw[FQ];
+#pragma unroll
+    for (int k = 0; k < FQ; ++k) fw[k] = T(0);
+    T uq[kPF], fq[kPF];
+#pragma unroll
+    for (int p = 0; p < kPF; ++p) {
+      uq[p] = a.uin[col.template addr<FAST>(ts + p)];
+      if (NU2 > 0) fq[p] = fp[col.template addr<FAST>(ts - R + p)];
+    }
+    const KOp<T> op = a.op;
+
+    for (int t = ts; t <= te; ++t) {
+      const int Jc = floordiv2(t);
+      if (jb < Jc - 1) {  // the stencil moved down one coarse row (every other fine row)
+        const T nv = interp(ccol.template fix<FAST>(cnext, jb + 4));
+        cnext = a.v[ccol.template addr<FAST>(jb + 5)];
+        push(pw, nv);
+        ++jb;
+      }
+      const T pv = ((t & 1) == 0) ? pw[1]
+                   : (P == 3 ? (T(9) * (pw[1] + pw[2]) - (pw[0] + pw[3])) * T(0.0625)
+                             : T(0.5) * (pw[1] + pw[2]));
+      const T unew = col.template fix<FAST>(uq[0], t);
+      push(uq, a.uin[col.template addr<FAST>(t + kPF)]);
+      const T ut = unew + pv;  // corrected iterate at row t
+      T out = ut;
+      int c = t;
+      if (NU2 > 0) {
+        const T fnew = col.template fix<FAST>(fq[0], t - R);
+        push(fq, fp[col.template addr<FAST>(t - R + kPF)]);
+        push(fw, fnew);
+        push(w[0], ut);
+#pragma unroll
+        for (int s = 1; s <= NU2; ++s) {
+          // stage s: sweep at row t - s R, the centre of w[s-1]
+          const T fv = fw[FQ - 1 - (s - 1) * R];
+          const T r = fv - apply_op<T, R>(w[s - 1], op, ra, rb);
+          push(w[s], w[s - 1][R] + op.om_d * r);
+        }
+        out = w[NU2][W - 1];
+        c = t - NU2 * R;
+      }
+      if (useful && c >= y0 && c < y1) {
+        const bool inside = col.xin && c > 0 && c < n - 1;
+        a.uout[(size_t)c * n + x] = inside ? out : T(0);
+      }
+    }
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+}
+
+int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+int clampi(long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
+
+template <typename T>
+KOp<T> to_kop(const LevelOp &op, double omega) {
+  KOp<T> k;
+  for (int i = 0; i < 7; ++i) {
+    k.a[i] = (T)op.a[i];
+    k.b[i] = (T)op.b[i];
+  }
+  k.w1 = (T)(-op.a[2]);
+  k.w2 = (T)(-op.a[1]);
+  k.om_d = (T)(omega / op.diag);
+  return k;
+}
+
+// Rows per block: about 1024 blocks per launch, within [lo, hi] rows.
+int pre_geometry(int n, int S, bool restrict_mode, int *chunk, dim3 *grid) {
+  const int strips = cdiv(n, S);
+  const int bx = cdiv(strips, kWavesPerBlock);
+  const int rows_total = restrict_mode ? (n - 1) / 2 + 1 : n;
+  const int target_blocks = 1024;
+  const int c = clampi((long)rows_total * bx / target_blocks, restrict_mode ? 8 : 16,
+                       restrict_mode ? 64 : 128);
+  *chunk = c;
+  *grid = dim3(bx, cdiv(rows_total, c));
+  return bx * grid->y;
+}
+
+template <typename T, int R, int NU, int MODE>
+hipError_t pre_dispatch(const PreArgs<T> &args, dim3 grid, hipStream_t s) {
+  if (args.u != nullptr)
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true>), grid, dim3(kBlock), 0, s, args);
+  else
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, false>), grid, dim3(kBlock), 0, s, args);
+  return hipGetLastError();
+}
+
+template <typename T, int R, int MODE>
+hipError_t pre_nu(int nu, const PreArgs<T> &args, dim3 grid, hipStream_t s) {
+  switch (nu) {
+    case 0: return pre_dispatch<T, R, 0, MODE>(args, grid, s);
+    case 1: return pre_dispatch<T, R, 1, MODE>(args, grid, s);
+    case 2: return pre_dispatch<T, R, 2, MODE>(args, grid, s);
+    case 3: return pre_dispatch<T, R, 3, MODE>(args, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int R, int NU2>
+hipError_t post_dispatch(int prolong, const PostArgs<T> &args, dim3 grid, hipStream_t s) {
+  if (prolong == 3)
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 3>), grid, dim3(kBlock), 0, s, args);
+  else
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 1>), grid, dim3(kBlock), 0, s, args);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t post_nu(int nu2, int prolong, const PostArgs<T> &args, dim3 grid, hipStream_t s) {
+  switch (nu2) {
+    case 0: return post_dispatch<T, R, 0>(prolong, args, grid, s);
+    case 1: return post_dispatch<T, R, 1>(prolong, args, grid, s);
+    case 2: return post_dispatch<T, R, 2>(prolong, args, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int pre2d_partials(int n) {
+  // the largest grid any pre launch uses at side n (smallest strip width S = 64 - 2H)
+  int best = 0;
+  for (int R = 2; R <= 3; ++R)
+    for (int nu = 0; nu <= 3; ++nu)
+      for (int restrict_mode = 0; restrict_mode <= 1; ++restrict_mode) {
+        const int H = (nu + 1) * R + restrict_mode;
+        const int S = kWave - 2 * H;
+        if (S <= 0) continue;
+        int chunk;
+        dim3 grid;
+        const int nb = pre_geometry(n, S, restrict_mode != 0, &chunk, &grid);
+        best = nb > best ? nb : best;
+      }
+  return best;
+}
+
+template <typename T>
+hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
+                        T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
+                        const int *done, hipStream_t s) {
+  const int R = op.cross ? 2 : 3;
+  const bool restrict_mode = (mode & kRestrict) != 0;
+  const bool res = restrict_mode || (mode & kWriteR) != 0;
+  const int K = nu + (res ? 1 : 0);
+  const int H = K * R + (restrict_mode ? 1 : 0);
+  const int S = kWave - 2 * H;
+  if (S <= 0 || nu < 0 || nu > 3) return hipErrorInvalidValue;
+  PreArgs<T> args{f, u, uout, rout, fc, n, 0, to_kop<T>(op, omega), partials, done};
+  dim3 grid;
+  const int nb = pre_geometry(n, S, restrict_mode, &args.chunk, &grid);
+  if (nparts) *nparts = nb;
+#define MG_PRE(RR)                                                                        \
+  switch (mode) {                                                                         \
+    case kWriteU | kRestrict: return pre_nu<T, RR, kWriteU | kRestrict>(nu, args, grid, s); \
+    case kRestrict: return pre_nu<T, RR, kRestrict>(nu, args, grid, s);                   \
+    case kWriteU: return pre_nu<T, RR, kWriteU>(nu, args, grid, s);                       \
+    case kWriteR: return pre_nu<T, RR, kWriteR>(nu, args, grid, s);                       \
+    case 0: return pre_nu<T, RR, 0>(nu, args, grid, s);                                   \
+    default: return hipErrorInvalidValue;                                                 \
+  }
+  if (R == 2) { MG_PRE(2) } else { MG_PRE(3) }
+#undef MG_PRE
+}
+
+template <typename T>
+hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
+                         const T *uin, const T *f, T *uout, int n, const int *done,
+                         hipStream_t s) {
+  const int R = op.cross ? 2 : 3;
+  if (nu2 < 0 || nu2 > 2) return hipErrorInvalidValue;
+  const int H = nu2 * R;
+  const int S = kWave - 2 * H;
+  PostArgs<T> args{v, uin, f, uout, n, 0, to_kop<T>(op, omega), done};
+  const int strips = cdiv(n, S);
+  const int bx = cdiv(strips, kWavesPerBlock);
+  args.chunk = clampi((long)n * bx / 1024, 16, 128);
+  const dim3 grid(bx, cdiv(n, args.chunk));
+  if (R == 2) return post_nu<T, 2>(nu2, prolong, args, grid, s);
+  return post_nu<T, 3>(nu2, prolong, args, grid, s);
+}
+
+template hipError_t launch_pre2d<double>(const LevelOp &, double, int, int, const double *,
+                                         const double *, double *, double *, double *, int,
+                                         double *, int *, const int *, hipStream_t);
+template hipError_t launch_pre2d<float>(const LevelOp &, double, int, int, const float *,
+                                        const float *, float *, float *, float *, int, double *,
+                                        int *, const int *, hipStream_t);
+template hipError_t launch_post2d<double>(const LevelOp &, double, int, int, const double *,
+                                          const double *, const double *, double *, int,
+                                          const int *, hipStream_t);
+template hipError_t launch_post2d<float>(const LevelOp &, double, int, int, const float *,
+                                         const float *, const float *, float *, int, const int *,
+                                         hipStream_t);
+
+}  // namespace mgk

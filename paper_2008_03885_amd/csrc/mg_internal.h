@@ -97,4 +97,48 @@ template <typename T>
 hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
                                      const int *done, hipStream_t s);
 
+// ---- fused 2D cycle kernels (fused2d.hip) ----------------------------------------
+// Pre kernel modes (bit set): 1 write the smoothed iterate, 2 full-weight the defect,
+// 4 write the defect.
+constexpr int kPreWriteU = 1, kPreRestrict = 2, kPreWriteR = 4;
+int pre2d_partials(int n);
+template <typename T>
+hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
+                        T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
+                        const int *done, hipStream_t s);
+template <typename T>
+hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
+                         const T *uin, const T *f, T *uout, int n, const int *done,
+                         hipStream_t s);
+
+// ---- LDS-resident tail (tail.hip) -------------------------------------------------
+constexpr int kMaxTailLevels = 8;
+struct TailLevel {
+  int n;
+  int ent_begin, ent_count;  // non-centre stencil entries of this level
+  int cross;                 // rediscretized cross stencil (weights w1, w2)
+  double om_d;               // omega / centre coefficient
+  double w1, w2;
+};
+struct TailArgs {
+  int levels, gamma, nu1, nu2, prolong, zero_init, m, lds_r;
+  int ent_first, ent_total;  // entries of the tail's levels in eoff/ecoef
+  int lds_ent;               // byte offset of the entry table in LDS
+  TailLevel lv[kMaxTailLevels];
+  const int *eoff;       // (dx, dy, dz) per entry
+  const double *ecoef;   // coefficient per entry
+  const double *ainv_t;  // coarsest inverse, transposed, m x m
+  const void *f_top;
+  void *u_top;
+  const int *done;
+};
+int tail_max_side(int dim);
+size_t tail_scratch_offset(int dim, int G, const int *ns, int levels);
+size_t tail_entry_offset(int dim, int G, const int *ns, int levels, size_t es);
+size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, size_t es);
+template <typename T>
+hipError_t tail_prepare(int dim, int G, size_t lds_bytes);
+template <typename T>
+hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s);
+
 }  // namespace mgk

@@ -247,6 +247,12 @@ struct mg_ctx {
   const double *gf = nullptr;
   double *gu = nullptr;
   bool use_graph = true;
+  bool fused = true;       // temporally blocked 2D kernels
+  int tail_top = 0;        // first level handled by the LDS-resident tail (L: none)
+  size_t tail_lds = 0;     // dynamic LDS bytes of the tail
+  int *eoff = nullptr;     // stencil entry lists of every level (tail kernel)
+  double *ecoef = nullptr;
+  std::vector<int> ent_begin, ent_count;
   int chunk = 4;
   std::vector<void *> allocs;
   size_t footprint = 0;
@@ -268,6 +274,19 @@ mg_status dev_alloc(mg_ctx *c, void **p, size_t bytes) {
   return MG_OK;
 }
 
+int partials_needed(int dim, int n) {
+  int np = mgk::sweep_partials(dim, n);
+  if (dim == 2) np = std::max(np, mgk::pre2d_partials(n));
+  return np;
+}
+
+// Upper bound of the stencil entry lists (non-centre entries of every level).
+size_t entries_bytes(const mg_config *cfg, int L) {
+  const int w = 7;
+  const size_t per = cfg->dim == 2 ? (size_t)w * w : (size_t)w * w * w;
+  return (size_t)L * per * (3 * sizeof(int) + sizeof(double));
+}
+
 size_t footprint_of(const mg_config *cfg, int L) {
   size_t total = 0;
   int n = cfg->n;
@@ -283,9 +302,62 @@ size_t footprint_of(const mg_config *cfg, int L) {
   const int q = cfg->n_coarsest - 2;
   const size_t m = cfg->dim == 2 ? (size_t)q * q : (size_t)q * q * q;
   total += m * m * 8;
-  total += (size_t)mgk::sweep_partials(cfg->dim, cfg->n) * 8;
+  total += (size_t)partials_needed(cfg->dim, cfg->n) * 8;
+  total += entries_bytes(cfg, L);
   total += sizeof(DevState);
   return total;
+}
+
+// Ghost width of a tail starting at level l: 1 if every tail level is the cross.
+int tail_ghost(const mg_ctx *c, int l) {
+  for (int k = l; k < c->L; ++k)
+    if (!c->ops[k].cross) return 2;
+  return 1;
+}
+
+int tail_entries(const mg_ctx *c, int l) {
+  return c->ent_begin[c->L - 1] + c->ent_count[c->L - 1] - c->ent_begin[l];
+}
+
+// Dynamic LDS of a tail starting at level l.
+size_t tail_bytes(const mg_ctx *c, int l, size_t es) {
+  return mgk::tail_lds_bytes(c->dim, tail_ghost(c, l), &c->ns[l], c->L - l, tail_entries(c, l), es);
+}
+
+template <typename T>
+hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const int *done,
+                          hipStream_t s) {
+  mgk::TailArgs a{};
+  a.levels = c->L - l;
+  a.gamma = c->cfg.gamma;
+  a.nu1 = c->cfg.nu1;
+  a.nu2 = c->cfg.nu2;
+  a.prolong = c->cfg.prolong;
+  a.zero_init = zero_u ? 1 : 0;
+  const int q = c->ns[c->L - 1] - 2;
+  a.m = c->dim == 2 ? q * q : q * q * q;
+  for (int k = l; k < c->L; ++k) {
+    mgk::TailLevel &tl = a.lv[k - l];
+    tl.n = c->ns[k];
+    tl.ent_begin = c->ent_begin[k];
+    tl.ent_count = c->ent_count[k];
+    tl.cross = c->ops[k].cross ? 1 : 0;
+    tl.om_d = c->omega / c->ops[k].diag;
+    tl.w1 = -c->ops[k].a[2];
+    tl.w2 = -c->ops[k].a[1];
+  }
+  const int G = tail_ghost(c, l);
+  a.lds_r = (int)mgk::tail_scratch_offset(c->dim, G, &c->ns[l], c->L - l);
+  a.lds_ent = (int)mgk::tail_entry_offset(c->dim, G, &c->ns[l], c->L - l, sizeof(T));
+  a.eoff = c->eoff;
+  a.ecoef = c->ecoef;
+  a.ainv_t = c->ainv_t;
+  a.f_top = f;
+  a.u_top = u;
+  a.done = done;
+  a.ent_first = c->ent_begin[l];
+  a.ent_total = tail_entries(c, l);
+  return mgk::launch_tail<T>(c->dim, G, a, tail_bytes(c, l, sizeof(T)), s);
 }
 
 template <typename T>
@@ -296,6 +368,46 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   const int n = c->ns[l];
   const LevelOp &op = c->ops[l];
   hipError_t e;
+  if (l >= c->tail_top) {
+    if (check) {
+      int np = 0;
+      e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero_u ? nullptr : u,
+                                  (T *)nullptr, n, c->partials, &np, done, s);
+      if (e != hipSuccess) return e;
+      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return launch_tail_at<T>(c, l, u, f, zero_u, done, s);
+  }
+  if (c->fused && dim == 2 && c->L > 1) {
+    T *t = (T *)B[l].t;
+    T *uc = (T *)B[l + 1].u;
+    T *fc = (T *)B[l + 1].f;
+    int np = 0;
+    e = mgk::launch_pre2d<T>(op, c->omega, c->cfg.nu1, mgk::kPreWriteU | mgk::kPreRestrict, f,
+                             zero_u ? nullptr : u, t, nullptr, fc, n,
+                             check ? c->partials : nullptr, &np, done, s);
+    if (e != hipSuccess) return e;
+    if (check) {
+      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    if (l + 1 >= c->tail_top) {
+      for (int g = 0; g < c->cfg.gamma; ++g) {
+        e = launch_tail_at<T>(c, l + 1, uc, fc, g == 0, done, s);
+        if (e != hipSuccess) return e;
+      }
+    } else if (l + 1 == c->L - 1) {
+      e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s);
+      if (e != hipSuccess) return e;
+    } else {
+      for (int g = 0; g < c->cfg.gamma; ++g) {
+        e = cycle<T>(c, B, l + 1, uc, fc, g == 0, false, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return mgk::launch_post2d<T>(op, c->omega, c->cfg.nu2, c->cfg.prolong, uc, t, f, u, n, done, s);
+  }
   if (c->L == 1) {  // a single level: the exact solve is the whole cycle
     if (check) {
       int np = 0;
@@ -340,7 +452,7 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   T *fc = (T *)B[l + 1].f;
   e = mgk::launch_resid_restrict<T>(dim, op, f, cur, fc, n, done, s);
   if (e != hipSuccess) return e;
-  if (l + 1 == c->L - 1) {
+  if (l + 1 == c->L - 1 && l + 1 < c->tail_top) {
     e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s);
     if (e != hipSuccess) return e;
   } else {
@@ -548,6 +660,8 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
   c->stream = (hipStream_t)hip_stream;
   if (const char *g = std::getenv("MG_GRAPH")) c->use_graph = std::atoi(g) != 0;
   if (const char *k = std::getenv("MG_CHUNK")) c->chunk = std::max(1, std::atoi(k));
+  if (const char *fz = std::getenv("MG_FUSED")) c->fused = std::atoi(fz) != 0;
+  if (cfg->nu1 > 3 || cfg->nu2 > 2) c->fused = false;
   auto bail = [&](mg_status s) {
     std::string msg = g_error;
     mg_destroy(c);
@@ -590,7 +704,61 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
         if ((st = dev_alloc(c, &b.t, np * 4)) != MG_OK) return bail(st);
     }
   }
-  c->np_max = mgk::sweep_partials(c->dim, cfg->n);
+  // Stencil entry lists (non-centre, non-zero) of every level, for the tail kernel.
+  {
+    std::vector<int> off;
+    std::vector<double> coef;
+    for (int l = 0; l < L; ++l) {
+      const LevelOp &op = c->ops[l];
+      c->ent_begin.push_back((int)coef.size());
+      const int zr = c->dim == 3 ? 3 : 0;
+      for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -3; oy <= 3; ++oy)
+          for (int ox = -3; ox <= 3; ++ox) {
+            if (ox == 0 && oy == 0 && oz == 0) continue;
+            double v = op.a[ox + 3] * op.b[oy + 3] + op.b[ox + 3] * op.a[oy + 3];
+            if (c->dim == 3)
+              v = (op.a[ox + 3] * op.b[oy + 3] + op.b[ox + 3] * op.a[oy + 3]) * op.b[oz + 3] +
+                  op.b[ox + 3] * op.b[oy + 3] * op.a[oz + 3];
+            if (v == 0.0) continue;
+            off.push_back(ox);
+            off.push_back(oy);
+            off.push_back(oz);
+            coef.push_back(v);
+          }
+      c->ent_count.push_back((int)coef.size() - c->ent_begin[l]);
+    }
+    if ((st = dev_alloc(c, (void **)&c->eoff, off.size() * sizeof(int))) != MG_OK) return bail(st);
+    if ((st = dev_alloc(c, (void **)&c->ecoef, coef.size() * sizeof(double))) != MG_OK) return bail(st);
+    if (hipMemcpy(c->eoff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->ecoef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(MG_EDEVICE, "upload of the stencil entries failed"));
+  }
+  // The coarse end of the hierarchy runs in one LDS-resident workgroup when it fits.
+  {
+    int lds_limit = 0;
+    if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+      lds_limit = 65536;
+    int cap = c->dim == 2 ? 65 : 17;
+    if (const char *tn = std::getenv("MG_TAIL_N")) cap = std::atoi(tn);
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    c->tail_top = L;
+    for (int l = L - 1; l >= 0 && L - l <= mgk::kMaxTailLevels; --l) {
+      const size_t np = points(c->dim, c->ns[l]);
+      const size_t need = tail_bytes(c, l, es);
+      if (c->ns[l] > cap || c->ns[l] > mgk::tail_max_side(c->dim) || need > (size_t)lds_limit) break;
+      (void)np;
+      c->tail_top = l;
+      c->tail_lds = need;
+    }
+    if (c->tail_top < L) {
+      const int G = tail_ghost(c, c->tail_top);
+      hipError_t e = mixed ? mgk::tail_prepare<float>(c->dim, G, c->tail_lds)
+                           : mgk::tail_prepare<double>(c->dim, G, c->tail_lds);
+      if (e != hipSuccess) return bail(fail(MG_EDEVICE, std::string("tail setup: ") + hipGetErrorString(e)));
+    }
+  }
+  c->np_max = partials_needed(c->dim, cfg->n);
   if ((st = dev_alloc(c, (void **)&c->partials, (size_t)c->np_max * 8)) != MG_OK) return bail(st);
   if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState))) != MG_OK) return bail(st);
   if (hipMemcpy(c->ainv_t, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -685,6 +853,17 @@ mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, cons
   mg_status st = fp32 ? check_level<float>(h, level, false) : check_level<double>(h, level, false);
   if (st != MG_OK) return st;
   if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  if (h->dim == 2) {
+    if (fp32)
+      MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, 1, mgk::kPreWriteU, (const float *)f,
+                                      (const float *)u_in, (float *)u_out, nullptr, nullptr,
+                                      h->ns[level], nullptr, nullptr, nullptr, h->stream));
+    else
+      MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, 1, mgk::kPreWriteU, (const double *)f,
+                                       (const double *)u_in, (double *)u_out, nullptr, nullptr,
+                                       h->ns[level], nullptr, nullptr, nullptr, h->stream));
+    return MG_OK;
+  }
   if (fp32)
     MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kSweep, h->ops[level], h->omega,
                                             (const float *)f, (const float *)u_in, (float *)u_out,
@@ -702,6 +881,17 @@ mg_status mg_kernel_residual(mg_handle h, int level, int fp32, const void *f, co
   mg_status st = check_level<double>(h, level, false);
   if (st != MG_OK) return st;
   if (!f || !u || !r) return fail(MG_EINVAL, "bad buffers");
+  if (h->dim == 2) {
+    if (fp32)
+      MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, 0, mgk::kPreWriteR, (const float *)f,
+                                      (const float *)u, nullptr, (float *)r, nullptr, h->ns[level],
+                                      nullptr, nullptr, nullptr, h->stream));
+    else
+      MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, 0, mgk::kPreWriteR, (const double *)f,
+                                       (const double *)u, nullptr, (double *)r, nullptr,
+                                       h->ns[level], nullptr, nullptr, nullptr, h->stream));
+    return MG_OK;
+  }
   if (fp32)
     MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kResidual, h->ops[level], h->omega,
                                             (const float *)f, (const float *)u, (float *)r,
@@ -718,6 +908,18 @@ mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const vo
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
   if (!f || !fc) return fail(MG_EINVAL, "bad buffers");
+  if (h->dim == 2) {
+    if (fp32)
+      MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, 0, mgk::kPreRestrict, (const float *)f,
+                                      (const float *)u, nullptr, nullptr, (float *)fc, h->ns[level],
+                                      nullptr, nullptr, nullptr, h->stream));
+    else
+      MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, 0, mgk::kPreRestrict,
+                                       (const double *)f, (const double *)u, nullptr, nullptr,
+                                       (double *)fc, h->ns[level], nullptr, nullptr, nullptr,
+                                       h->stream));
+    return MG_OK;
+  }
   if (fp32)
     MG_HIP(mgk::launch_resid_restrict<float>(h->dim, h->ops[level], (const float *)f,
                                              (const float *)u, (float *)fc, h->ns[level], nullptr,
@@ -734,6 +936,17 @@ mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
   if (!v || !u_in || !u_out) return fail(MG_EINVAL, "bad buffers");
+  if (h->dim == 2) {
+    if (fp32)
+      MG_HIP(mgk::launch_post2d<float>(h->ops[level], h->omega, 0, h->cfg.prolong, (const float *)v,
+                                       (const float *)u_in, nullptr, (float *)u_out, h->ns[level],
+                                       nullptr, h->stream));
+    else
+      MG_HIP(mgk::launch_post2d<double>(h->ops[level], h->omega, 0, h->cfg.prolong,
+                                        (const double *)v, (const double *)u_in, nullptr,
+                                        (double *)u_out, h->ns[level], nullptr, h->stream));
+    return MG_OK;
+  }
   if (fp32)
     MG_HIP(mgk::launch_prolong_correct<float>(h->dim, h->cfg.prolong, (const float *)v,
                                               (const float *)u_in, (float *)u_out, h->ns[level],
@@ -742,6 +955,41 @@ mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void
     MG_HIP(mgk::launch_prolong_correct<double>(h->dim, h->cfg.prolong, (const double *)v,
                                                (const double *)u_in, (double *)u_out,
                                                h->ns[level], nullptr, h->stream));
+  return MG_OK;
+}
+
+mg_status mg_kernel_presmooth_restrict(mg_handle h, int level, int fp32, const void *f,
+                                       const void *u_in, void *u_out, void *fc) {
+  mg_status st = check_level<double>(h, level, true);
+  if (st != MG_OK) return st;
+  if (h->dim != 2 || h->cfg.nu1 > 3) return fail(MG_EINVAL, "fused pre-smoothing needs dim 2, nu1 <= 3");
+  if (!f || !u_out || !fc || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  const int mode = mgk::kPreWriteU | mgk::kPreRestrict;
+  if (fp32)
+    MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, h->cfg.nu1, mode, (const float *)f,
+                                    (const float *)u_in, (float *)u_out, nullptr, (float *)fc,
+                                    h->ns[level], nullptr, nullptr, nullptr, h->stream));
+  else
+    MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, h->cfg.nu1, mode, (const double *)f,
+                                     (const double *)u_in, (double *)u_out, nullptr, (double *)fc,
+                                     h->ns[level], nullptr, nullptr, nullptr, h->stream));
+  return MG_OK;
+}
+
+mg_status mg_kernel_prolong_postsmooth(mg_handle h, int level, int fp32, const void *v,
+                                       const void *u_in, const void *f, void *u_out) {
+  mg_status st = check_level<double>(h, level, true);
+  if (st != MG_OK) return st;
+  if (h->dim != 2 || h->cfg.nu2 > 2) return fail(MG_EINVAL, "fused post-smoothing needs dim 2, nu2 <= 2");
+  if (!v || !u_in || !f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  if (fp32)
+    MG_HIP(mgk::launch_post2d<float>(h->ops[level], h->omega, h->cfg.nu2, h->cfg.prolong,
+                                     (const float *)v, (const float *)u_in, (const float *)f,
+                                     (float *)u_out, h->ns[level], nullptr, h->stream));
+  else
+    MG_HIP(mgk::launch_post2d<double>(h->ops[level], h->omega, h->cfg.nu2, h->cfg.prolong,
+                                      (const double *)v, (const double *)u_in, (const double *)f,
+                                      (double *)u_out, h->ns[level], nullptr, h->stream));
   return MG_OK;
 }
 

@@ -1,0 +1,409 @@
+// tail.hip -- the coarse end of a cycle in one workgroup, resident in LDS.
+//
+// Below a few thousand points per level, a multigrid level costs a few microseconds of
+// launch latency per kernel and almost no memory traffic.  This kernel runs the whole
+// gamma-cycle from a given level down to the coarsest one (pre-smoothing, defect and
+// full weighting, the exact coarsest solve, interpolation and correction,
+// post-smoothing; gamma recursive visits per level) inside one workgroup of 1024
+// threads, with barriers between the steps.
+//
+// LDS layout per level: the iterate u with a ghost frame of G points on every side
+// that holds the odd reflection across the Dirichlet boundary (refreshed after every
+// update, so stencil reads need no index folding), and the right-hand side f without a
+// frame.  One defect scratch array of the top level's size is shared by all levels.
+// Rediscretized levels use the cross stencil directly; Galerkin levels walk a list of
+// non-centre stencil entries in the difference form sum_e c_e (u(x + o_e) - u(x)).
+#include <cmath>
+
+#include "mg_internal.h"
+
+namespace mgk {
+namespace {
+
+constexpr int kTailThreads = 1024;
+// Ghost frame G: a stencil of radius R reaches R-1 points past the boundary, cubic
+// interpolation one coarse point; G = 1 when every tail level is the radius-2 cross,
+// G = 2 otherwise.
+
+// Thread tiling of a level and the number of points each thread visits at the largest
+// tail side (65 in 2D, 17 in 3D).
+template <int DIM>
+struct Tiling;
+template <>
+struct Tiling<2> {
+  static constexpr int TX = 64, TY = 16, TZ = 1, NI = 2, NJ = 5, NK = 1;
+};
+template <>
+struct Tiling<3> {
+  static constexpr int TX = 16, TY = 8, TZ = 8, NI = 2, NJ = 3, NK = 3;
+};
+
+struct LevelInfo {
+  int n, pp;       // side and padded pitch (n + 2G)
+  int u, f;        // element offsets in LDS
+  int e0, ne;      // entries of this level in the LDS entry table
+  double om_d;
+  double w1, w2;   // cross weights (rediscretized levels)
+  int cross;
+};
+
+template <typename T, int DIM, int G>
+struct Tail {
+  const LevelInfo *lv;
+  T *lds;
+  const int *edelta;  // entry offsets as index deltas in the padded layout of their level
+  const T *ecoef;
+  const double *ainv_t;
+  int m, levels, gamma, nu1, nu2, prolong, scratch;
+  int tx, ty, tz;
+
+  __device__ __forceinline__ int pidx(int l, int i, int j, int k) const {
+    const int pp = lv[l].pp;
+    return lv[l].u + (DIM == 3 ? ((k + G) * pp + (j + G)) * pp : (j + G) * pp) + (i + G);
+  }
+  __device__ __forceinline__ int didx(int l, int i, int j, int k) const {
+    const int n = lv[l].n;
+    return (DIM == 3 ? (k * n + j) * n : j * n) + i;
+  }
+  template <typename F>
+  __device__ __forceinline__ void each(int n, F fn) const {
+    using TL = Tiling<DIM>;
+    for (int k = (DIM == 3 ? tz : 0); k < (DIM == 3 ? n : 1); k += TL::TZ)
+      for (int j = ty; j < n; j += TL::TY)
+        for (int i = tx; i < n; i += TL::TX) fn(i, j, k);
+  }
+  __device__ __forceinline__ bool interior(int n, int i, int j, int k) const {
+    return i > 0 && i < n - 1 && j > 0 && j < n - 1 && (DIM == 2 || (k > 0 && k < n - 1));
+  }
+  __device__ __forceinline__ T lu(int l, int p, T c) const {
+    const LevelInfo &L = lv[l];
+    if (L.cross) {
+      const int sy = L.pp, sz = L.pp * L.pp;
+      T d1 = (c - lds[p - 1]) + (c - lds[p + 1]);
+      T d2 = (c - lds[p - 2]) + (c - lds[p + 2]);
+      d1 += (c - lds[p - sy]) + (c - lds[p + sy]);
+      d2 += (c - lds[p - 2 * sy]) + (c - lds[p + 2 * sy]);
+      if (DIM == 3) {
+        d1 += (c - lds[p - sz]) + (c - lds[p + sz]);
+        d2 += (c - lds[p - 2 * sz]) + (c - lds[p + 2 * sz]);
+      }
+      return T(L.w1) * d1 + T(L.w2) * d2;
+    }
+    T s = T(0);
+    for (int e = L.e0; e < L.e0 + L.ne; ++e) s += ecoef[e] * (lds[p + edelta[e]] - c);
+    return s;
+  }
+  // refresh the ghost frame of u on level l with the odd reflection
+  __device__ __forceinline__ void ghosts(int l) const {
+    const int n = lv[l].n;
+    using TL = Tiling<DIM>;
+    for (int k = (DIM == 3 ? tz - G : 0); k < (DIM == 3 ? n + G : 1); k += TL::TZ)
+      for (int j = ty - G; j < n + G; j += TL::TY)
+        for (int i = tx - G; i < n + G; i += TL::TX) {
+          const bool in = i >= 0 && i < n && j >= 0 && j < n && (DIM == 2 || (k >= 0 && k < n));
+          if (in) continue;
+          T sgn = T(1);
+          int si = i, sj = j, sk = k;
+          if (si < 0) { si = -si; sgn = -sgn; }
+          if (si > n - 1) { si = 2 * (n - 1) - si; sgn = -sgn; }
+          if (sj < 0) { sj = -sj; sgn = -sgn; }
+          if (sj > n - 1) { sj = 2 * (n - 1) - sj; sgn = -sgn; }
+          if (DIM == 3) {
+            if (sk < 0) { sk = -sk; sgn = -sgn; }
+            if (sk > n - 1) { sk = 2 * (n - 1) - sk; sgn = -sgn; }
+          }
+          lds[pidx(l, i, j, k)] = sgn * lds[pidx(l, si, sj, sk)];
+        }
+    __syncthreads();
+  }
+  __device__ __forceinline__ void smooth(int l, bool zero) const {
+    using TL = Tiling<DIM>;
+    const int n = lv[l].n;
+    const T om = T(lv[l].om_d);
+    T vals[TL::NK][TL::NJ][TL::NI];
+#pragma unroll
+    for (int c = 0; c < TL::NK; ++c)
+#pragma unroll
+      for (int b = 0; b < TL::NJ; ++b)
+#pragma unroll
+        for (int a = 0; a < TL::NI; ++a) {
+          const int i = tx + a * TL::TX, j = ty + b * TL::TY, k = DIM == 3 ? tz + c * TL::TZ : 0;
+          T v = T(0);
+          if (interior(n, i, j, k)) {
+            const int p = pidx(l, i, j, k);
+            const T u0 = zero ? T(0) : lds[p];
+            const T r = lds[lv[l].f + didx(l, i, j, k)] - (zero ? T(0) : lu(l, p, u0));
+            v = u0 + om * r;
+          }
+          vals[c][b][a] = v;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < TL::NK; ++c)
+#pragma unroll
+      for (int b = 0; b < TL::NJ; ++b)
+#pragma unroll
+        for (int a = 0; a < TL::NI; ++a) {
+          const int i = tx + a * TL::TX, j = ty + b * TL::TY, k = DIM == 3 ? tz + c * TL::TZ : 0;
+          if (i < n && j < n && (DIM == 2 || k < n)) lds[pidx(l, i, j, k)] = vals[c][b][a];
+        }
+    __syncthreads();
+    ghosts(l);
+  }
+  __device__ __forceinline__ void zero_level(int l) const {
+    const int n = lv[l].n;
+    each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
+    __syncthreads();
+    ghosts(l);
+  }
+  // defect of level l into the scratch array, then full weighting into f of level l+1
+  __device__ __forceinline__ void resid_restrict(int l) const {
+    const int n = lv[l].n;
+    T *r = lds + scratch;
+    each(n, [&](int i, int j, int k) {
+      T v = T(0);
+      if (interior(n, i, j, k)) {
+        const int p = pidx(l, i, j, k);
+        v = lds[lv[l].f + didx(l, i, j, k)] - lu(l, p, lds[p]);
+      }
+      r[didx(l, i, j, k)] = v;
+    });
+    __syncthreads();
+    const int nc = lv[l + 1].n;
+    T *fc = lds + lv[l + 1].f;
+    each(nc, [&](int I, int J, int K) {
+      T s = T(0);
+      if (interior(nc, I, J, K)) {
+        for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+          for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+              T w = (ox == 0 ? T(0.5) : T(0.25)) * (oy == 0 ? T(0.5) : T(0.25));
+              if (DIM == 3) w *= (oz == 0 ? T(0.5) : T(0.25));
+              s += w * r[didx(l, 2 * I + ox, 2 * J + oy, DIM == 3 ? 2 * K + oz : 0)];
+            }
+      }
+      fc[didx(l + 1, I, J, K)] = s;
+    });
+    __syncthreads();
+  }
+  // 1D interpolation weight of the coarse point at fine distance o
+  __device__ __forceinline__ T pw1(int o) const {
+    o = o < 0 ? -o : o;
+    if (prolong == 3) return o == 0 ? T(1) : (o == 1 ? T(0.5625) : (o == 3 ? T(-0.0625) : T(0)));
+    return o == 0 ? T(1) : (o == 1 ? T(0.5) : T(0));
+  }
+  // u(l) += I_H^h u(l+1), coarse values read from the ghost-framed array
+  __device__ __forceinline__ void prolong_correct(int l) const {
+    const int n = lv[l].n;
+    const int rP = prolong == 3 ? 3 : 1;
+    each(n, [&](int i, int j, int k) {
+      if (!interior(n, i, j, k)) return;
+      T s = T(0);
+      const int klo = DIM == 3 ? ((k - rP + 1) >> 1) : 0, khi = DIM == 3 ? ((k + rP) >> 1) : 0;
+      for (int Kc = klo; Kc <= khi; ++Kc) {
+        const T wz = DIM == 3 ? pw1(k - 2 * Kc) : T(1);
+        if (wz == T(0)) continue;
+        for (int Jc = (j - rP + 1) >> 1; Jc <= (j + rP) >> 1; ++Jc) {
+          const T wy = pw1(j - 2 * Jc);
+          if (wy == T(0)) continue;
+          for (int Ic = (i - rP + 1) >> 1; Ic <= (i + rP) >> 1; ++Ic) {
+            const T wx = pw1(i - 2 * Ic);
+            if (wx == T(0)) continue;
+            s += wx * wy * wz * lds[pidx(l + 1, Ic, Jc, Kc)];
+          }
+        }
+      }
+      lds[pidx(l, i, j, k)] += s;
+    });
+    __syncthreads();
+    ghosts(l);
+  }
+  __device__ __forceinline__ void coarsest(int l) const {
+    const int n = lv[l].n, q = n - 2;
+    const int r = threadIdx.x;
+    double val = 0.0;
+    if (r < m) {
+      for (int c = 0; c < m; ++c) {
+        const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
+        val += ainv_t[(size_t)c * m + r] * (double)lds[lv[l].f + didx(l, ci, cj, ck)];
+      }
+    }
+    __syncthreads();
+    each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
+    __syncthreads();
+    if (r < m) {
+      const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
+      lds[pidx(l, ri, rj, rk)] = (T)val;
+    }
+    __syncthreads();
+    ghosts(l);
+  }
+};
+
+// The gamma-cycle from level 0 of the tail, without recursion: a visit of level l
+// pre-smooths, restricts and descends; the way back up interpolates, post-smooths and
+// either repeats level l (gamma > 1, second visit from the same parent, non-zero guess)
+// or returns to the parent.  Bit l of `visited` records a finished visit of level l.
+template <typename T, int DIM, int G>
+__device__ __forceinline__ void run_cycle(const Tail<T, DIM, G> &c, bool zero0) {
+  const int last = c.levels - 1;
+  if (last == 0) {
+    c.coarsest(0);
+    return;
+  }
+  int l = 0;
+  bool zero = zero0;
+  unsigned visited = 0u;
+  for (;;) {
+    // down: pre-smoothing and restriction of level l
+    if (zero && c.nu1 == 0) c.zero_level(l);
+    for (int s = 0; s < c.nu1; ++s) c.smooth(l, zero && s == 0);
+    c.resid_restrict(l);
+    if (l + 1 < last) {
+      visited &= ~(1u << (l + 1));
+      ++l;
+      zero = true;
+      continue;
+    }
+    c.coarsest(l + 1);
+    // up: interpolation, correction and post-smoothing, as far as the visits allow
+    for (;;) {
+      c.prolong_correct(l);
+      for (int s = 0; s < c.nu2; ++s) c.smooth(l, false);
+      if (l == 0) return;
+      if (c.gamma > 1 && !(visited & (1u << l))) {
+        visited |= 1u << l;  // the parent's second visit of level l follows
+        zero = false;
+        break;
+      }
+      --l;
+    }
+  }
+}
+
+template <typename T, int DIM, int G>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ LevelInfo lvt[kMaxTailLevels];
+  if (a.done != nullptr && *a.done != 0) return;
+  using TL = Tiling<DIM>;
+  // level table: padded pitches and LDS offsets (u framed, f dense)
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int l = 0; l < a.levels; ++l) {
+      LevelInfo &L = lvt[l];
+      L.n = a.lv[l].n;
+      L.pp = L.n + 2 * G;
+      L.u = off;
+      off += DIM == 3 ? L.pp * L.pp * L.pp : L.pp * L.pp;
+      L.f = off;
+      off += DIM == 3 ? L.n * L.n * L.n : L.n * L.n;
+      L.e0 = a.lv[l].ent_begin - a.ent_first;
+      L.ne = a.lv[l].ent_count;
+      L.om_d = a.lv[l].om_d;
+      L.cross = a.lv[l].cross;
+      L.w1 = a.lv[l].w1;
+      L.w2 = a.lv[l].w2;
+    }
+  }
+  __syncthreads();
+  T *lds = reinterpret_cast<T *>(tail_lds);
+  int *edelta = reinterpret_cast<int *>(tail_lds + a.lds_ent);
+  T *ecoef = reinterpret_cast<T *>(tail_lds + a.lds_ent + sizeof(int) * a.ent_total +
+                                   (sizeof(T) - (sizeof(int) * a.ent_total) % sizeof(T)) % sizeof(T));
+  for (int e = threadIdx.x; e < a.ent_total; e += kTailThreads) {
+    const int g = a.ent_first + e;
+    int l = 0;
+    while (l + 1 < a.levels && e >= lvt[l + 1].e0) ++l;
+    const int pp = lvt[l].pp;
+    edelta[e] = (a.eoff[3 * g + 2] * pp + a.eoff[3 * g + 1]) * pp + a.eoff[3 * g];
+    ecoef[e] = (T)a.ecoef[g];
+  }
+  Tail<T, DIM, G> c;
+  c.lv = lvt;
+  c.lds = lds;
+  c.edelta = edelta;
+  c.ecoef = ecoef;
+  c.ainv_t = a.ainv_t;
+  c.m = a.m;
+  c.levels = a.levels;
+  c.gamma = a.gamma;
+  c.nu1 = a.nu1;
+  c.nu2 = a.nu2;
+  c.prolong = a.prolong;
+  c.scratch = a.lds_r;
+  c.tx = threadIdx.x % TL::TX;
+  c.ty = (threadIdx.x / TL::TX) % TL::TY;
+  c.tz = threadIdx.x / (TL::TX * TL::TY);
+  const T *fg = static_cast<const T *>(a.f_top);
+  T *ug = static_cast<T *>(a.u_top);
+  const int n = lvt[0].n;
+  c.each(n, [&](int i, int j, int k) {
+    const int d = c.didx(0, i, j, k);
+    lds[lvt[0].f + d] = fg[d];
+    const bool bd = !c.interior(n, i, j, k);
+    lds[c.pidx(0, i, j, k)] = (a.zero_init || bd) ? T(0) : ug[d];
+  });
+  __syncthreads();
+  c.ghosts(0);
+  run_cycle<T, DIM, G>(c, a.zero_init != 0);
+  c.each(n, [&](int i, int j, int k) { ug[c.didx(0, i, j, k)] = lds[c.pidx(0, i, j, k)]; });
+}
+
+}  // namespace
+
+int tail_max_side(int dim) { return dim == 2 ? 65 : 17; }
+
+// Element offset of the defect scratch (after every level's framed u and dense f).
+size_t tail_scratch_offset(int dim, int G, const int *ns, int levels) {
+  size_t pts = 0;
+  for (int l = 0; l < levels; ++l) {
+    const size_t n = ns[l], pp = n + 2 * G;
+    pts += dim == 3 ? pp * pp * pp + n * n * n : pp * pp + n * n;
+  }
+  return pts;
+}
+
+// Byte offset of the entry table.
+size_t tail_entry_offset(int dim, int G, const int *ns, int levels, size_t es) {
+  const size_t n0 = ns[0];
+  return (tail_scratch_offset(dim, G, ns, levels) + (dim == 3 ? n0 * n0 * n0 : n0 * n0)) * es;
+}
+
+size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, size_t es) {
+  size_t bytes = tail_entry_offset(dim, G, ns, levels, es) + sizeof(int) * (size_t)entries;
+  bytes = (bytes + es - 1) / es * es;
+  return bytes + (size_t)entries * es;
+}
+
+template <typename T>
+const void *tail_fn(int dim, int G) {
+  if (dim == 2) return G == 1 ? (const void *)k_tail<T, 2, 1> : (const void *)k_tail<T, 2, 2>;
+  return G == 1 ? (const void *)k_tail<T, 3, 1> : (const void *)k_tail<T, 3, 2>;
+}
+
+template <typename T>
+hipError_t tail_prepare(int dim, int G, size_t lds_bytes) {
+  return hipFuncSetAttribute(tail_fn<T>(dim, G), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_bytes);
+}
+
+template <typename T>
+hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s) {
+  if (dim == 2 && G == 1)
+    hipLaunchKernelGGL((k_tail<T, 2, 1>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+  else if (dim == 2)
+    hipLaunchKernelGGL((k_tail<T, 2, 2>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+  else if (G == 1)
+    hipLaunchKernelGGL((k_tail<T, 3, 1>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+  else
+    hipLaunchKernelGGL((k_tail<T, 3, 2>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+  return hipGetLastError();
+}
+
+template hipError_t tail_prepare<double>(int, int, size_t);
+template hipError_t tail_prepare<float>(int, int, size_t);
+template hipError_t launch_tail<double>(int, int, const TailArgs &, size_t, hipStream_t);
+template hipError_t launch_tail<float>(int, int, const TailArgs &, size_t, hipStream_t);
+
+}  // namespace mgk

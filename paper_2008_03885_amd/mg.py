@@ -67,6 +67,8 @@ _SIGS = {
     "mg_kernel_residual": (_I, [_V, _I, _I, _V, _V, _V]),
     "mg_kernel_residual_restrict": (_I, [_V, _I, _I, _V, _V, _V]),
     "mg_kernel_prolong_correct": (_I, [_V, _I, _I, _V, _V, _V]),
+    "mg_kernel_presmooth_restrict": (_I, [_V, _I, _I, _V, _V, _V, _V]),
+    "mg_kernel_prolong_postsmooth": (_I, [_V, _I, _I, _V, _V, _V, _V]),
     "mg_kernel_coarsest_solve": (_I, [_V, _I, _V, _V]),
     "mg_level_operator": (_I, [_V, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "mg_synchronize": (_I, [_V]),
@@ -178,6 +180,16 @@ def mg_kernel_residual_restrict(h, level, fp32, f_ptr, u_ptr, fc_ptr):
 def mg_kernel_prolong_correct(h, level, fp32, v_ptr, uin_ptr, uout_ptr):
     _check(lib().mg_kernel_prolong_correct(_V(h), int(level), int(fp32), _V(v_ptr), _V(uin_ptr),
                                            _V(uout_ptr)))
+
+
+def mg_kernel_presmooth_restrict(h, level, fp32, f_ptr, uin_ptr, uout_ptr, fc_ptr):
+    _check(lib().mg_kernel_presmooth_restrict(_V(h), int(level), int(fp32), _V(f_ptr), _V(uin_ptr),
+                                              _V(uout_ptr), _V(fc_ptr)))
+
+
+def mg_kernel_prolong_postsmooth(h, level, fp32, v_ptr, uin_ptr, f_ptr, uout_ptr):
+    _check(lib().mg_kernel_prolong_postsmooth(_V(h), int(level), int(fp32), _V(v_ptr), _V(uin_ptr),
+                                              _V(f_ptr), _V(uout_ptr)))
 
 
 def mg_kernel_coarsest_solve(h, fp32, g_ptr, v_ptr):

@@ -200,3 +200,78 @@ def test_kernels_are_deterministic():
         assert np.array_equal(host(a), host(b))
     finally:
         H.close()
+
+
+FUSED_CASES = [
+    # dim, n, coarse, prolong, level, nu1, nu2
+    (2, 17, 0, 3, 0, 2, 1), (2, 65, 0, 3, 0, 2, 1), (2, 257, 0, 3, 0, 2, 1), (2, 1025, 0, 3, 0, 2, 1),
+    (2, 257, 0, 3, 1, 0, 1), (2, 257, 0, 3, 0, 1, 2), (2, 257, 0, 1, 0, 3, 2), (2, 129, 0, 3, 0, 3, 0),
+    (2, 257, 1, 3, 1, 2, 1), (2, 513, 1, 3, 2, 2, 2), (2, 513, 1, 1, 1, 1, 1), (2, 1025, 1, 3, 1, 3, 0),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level,nu1,nu2", FUSED_CASES)
+def test_presmooth_restrict(dim, n, coarse, prolong, level, nu1, nu2, fp32):
+    """nu1 sweeps, defect and full weighting in one kernel = the oracle's steps in turn."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2)
+    try:
+        n_l, s = H.level(level)
+        d = s[(s.shape[0] // 2,) * dim]
+        u = rand_grid(n_l, dim, 21)
+        f = rand_grid(n_l, dim, 22) * d
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        nc = (n_l - 1) // 2 + 1
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        uo = dev(np.full_like(u, np.nan), fp32)
+        fc = dev(np.full((nc,) * dim, np.nan), fp32)
+        mg.mg_kernel_presmooth_restrict(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(),
+                                        uo.data_ptr(), fc.data_ptr())
+        ref = u.copy()
+        for _ in range(nu1):
+            ref = oracle.jacobi(s, H.omega, f, ref)
+        ref_fc = oracle.restrict(oracle.residual(s, f, ref))
+        tol = TOL32 if fp32 else TOL64
+        scale_u = _scale_u(u, f, s) * (1 + nu1)
+        assert_close(host(uo), ref, tol * scale_u * 4, "smoothed u")
+        assert_close(host(fc), ref_fc, tol * 8 * (np.abs(f).max() + d * scale_u), "coarse rhs")
+        # zero initial guess
+        mg.mg_kernel_presmooth_restrict(H.h, level, fp32, fd.data_ptr(), None, uo.data_ptr(),
+                                        fc.data_ptr())
+        ref = np.zeros_like(u)
+        for _ in range(nu1):
+            ref = oracle.jacobi(s, H.omega, f, ref)
+        assert_close(host(uo), ref, tol * scale_u * 4, "smoothed u (zero guess)")
+        assert_close(host(fc), oracle.restrict(oracle.residual(s, f, ref)),
+                     tol * 8 * (np.abs(f).max() + d * scale_u), "coarse rhs (zero guess)")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level,nu1,nu2", FUSED_CASES)
+def test_prolong_postsmooth(dim, n, coarse, prolong, level, nu1, nu2, fp32):
+    """Interpolation, correction and nu2 sweeps in one kernel = the oracle's steps in turn."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2)
+    try:
+        n_l, s = H.level(level)
+        d = s[(s.shape[0] // 2,) * dim]
+        nc = (n_l - 1) // 2 + 1
+        u = rand_grid(n_l, dim, 23)
+        v = rand_grid(nc, dim, 24)
+        f = rand_grid(n_l, dim, 25) * d
+        if fp32:
+            u, v, f = (a.astype(np.float32).astype(np.float64) for a in (u, v, f))
+        ud, vd, fd = dev(u, fp32), dev(v, fp32), dev(f, fp32)
+        uo = dev(np.full_like(u, np.nan), fp32)
+        mg.mg_kernel_prolong_postsmooth(H.h, level, fp32, vd.data_ptr(), ud.data_ptr(), fd.data_ptr(),
+                                        uo.data_ptr())
+        ref = oracle.prolong_add(v, u.copy(), prolong)
+        for _ in range(nu2):
+            ref = oracle.jacobi(s, H.omega, f, ref)
+        tol = TOL32 if fp32 else TOL64
+        scale = (np.abs(u).max() + 2 * np.abs(v).max() + np.abs(f).max() / d) * (1 + nu2)
+        assert_close(host(uo), ref, tol * scale * 4, "post")
+    finally:
+        H.close()

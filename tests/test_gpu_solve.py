@@ -51,6 +51,25 @@ def test_fixed_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
         H.close()
 
 
+@pytest.mark.parametrize("fused,tail", [("1", None), ("0", "0"), ("1", "0"), ("1", "17"), ("0", "65")])
+@pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 2)])
+def test_runtime_variants_agree(fused, tail, coarse, gamma, monkeypatch):
+    """Fused or separate kernels, with or without the LDS-resident tail: same cycles."""
+    monkeypatch.setenv("MG_FUSED", fused)
+    if tail is None:
+        monkeypatch.delenv("MG_TAIL_N", raising=False)
+    else:
+        monkeypatch.setenv("MG_TAIL_N", tail)
+    n = 257
+    H = Handle(2, n, coarse=coarse, gamma=gamma)
+    try:
+        _, f, _ = inputs.manufactured_2d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 6)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+    finally:
+        H.close()
+
+
 def test_c1_solve_to_tolerance():
     """2D 129^2, manufactured solution, V(2,1), nG, FW + cubic, omega = 10/13, to 1e-10."""
     n = 129
