@@ -1,24 +1,571 @@
-// kernels3d.hip -- 3D hot-path kernels for gfx950 (not yet implemented).
+// kernels3d.hip -- 3D hot-path kernels for gfx950.
+//
+// A block of 256 threads owns a 32 x 8 tile of (x, y) columns and marches along z over a
+// chunk of planes.  LDS holds a ring of the last 2R+1 planes of the tile extended by
+// its halo; each step loads one new plane cooperatively (the next plane's loads are
+// issued one step ahead, branch-free, with the reflection sign applied at use), waits
+// at one barrier and computes the outputs of one plane from LDS.  The odd extension
+// across the Dirichlet boundary is applied to every load (u(-i) = -u(i), boundary
+// values zero).
+//
+// Cross operator (rediscretized levels, R = 2): difference form with weights w1, w2 on
+// the 12 neighbours.  Separable operator (Galerkin levels, R = 3):
+// L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as a z pass, a y pass and an x
+// pass through LDS with every a factor in difference form, so constants are annihilated
+// exactly.
+#include <cmath>
+
 #include "mg_internal.h"
 
 namespace mgk {
+namespace {
 
-int sweep_partials_3d(int n) { return 1; }
+constexpr int TX = 32, TY = 8;  // output tile per block (one column per thread)
+
+__device__ __forceinline__ bool stopped(const int *done) { return done != nullptr && *done != 0; }
+
+__device__ __forceinline__ int fold(int i, int n, int &sign) {
+  if (i < 0) { i = -i; sign = -sign; }
+  if (i > n - 1) { i = 2 * (n - 1) - i; sign = -sign; }
+  if (i < 0) { i = -i; sign = -sign; }
+  return (i >= 0 && i <= n - 1) ? i : -1;
+}
+
+__device__ double block_sum256(double v) {
+  __shared__ double ws[4];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = ws[0] + ws[1] + ws[2] + ws[3];
+  return t;
+}
+
+// Cooperative loader of one z-plane of a PX x PY region with origin (gx0, gy0): each
+// thread owns up to Q positions; their (x, y) reflection is fixed, the z part is
+// applied per plane.
+template <typename T, int PX, int PY>
+struct PlaneLoader {
+  static constexpr int NP = PX * PY;
+  static constexpr int Q = (NP + 255) / 256;
+  int off[Q];   // y*n + x of the folded position (valid address)
+  T mul[Q];     // sign of the xy reflection, 0 for boundary / far positions
+  int n;
+  __device__ void init(int gx0, int gy0, int n_) {
+    n = n_;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int px = e % PX, py = e / PX;
+      int s = 1;
+      const int xf = fold(gx0 + px, n, s), yf = fold(gy0 + py, n, s);
+      const bool ok = e < NP && xf > 0 && xf < n - 1 && yf > 0 && yf < n - 1;
+      off[q] = ok ? yf * n + xf : n + 1;
+      mul[q] = ok ? T(s) : T(0);
+    }
+  }
+  // raw loads of plane z (valid addresses always)
+  __device__ void load(const T *p, int z, T (&raw)[Q]) const {
+    int s = 1;
+    int zf = fold(z, n, s);
+    zf = (zf > 0 && zf < n - 1) ? zf : 1;
+    const T *base = p + (size_t)zf * n * n;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) raw[q] = base[off[q]];
+  }
+  // store the odd-extended values of plane z into dst (PX*PY, row-major)
+  __device__ void store(T *dst, int z, const T (&raw)[Q]) const {
+    int s = 1;
+    const int zf = fold(z, n, s);
+    const T zm = (zf > 0 && zf < n - 1) ? T(s) : T(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < NP) dst[e] = (mul[q] * zm != T(0)) ? raw[q] * (mul[q] * zm) : T(0);
+    }
+  }
+};
+
+// L u at point (px, py) of the middle plane of the ring (planes c-R..c+R at ring slots
+// (head + k) % W), region pitch PX.  Cross only.
+template <typename T, int PX>
+__device__ __forceinline__ T cross_lu(const T *ring, int plane_sz, const int (&slot)[5], int px,
+                                      int py, T w1, T w2) {
+  const T *mid = ring + slot[2] * plane_sz;
+  const int p = py * PX + px;
+  const T c = mid[p];
+  T d1 = (c - mid[p - 1]) + (c - mid[p + 1]);
+  T d2 = (c - mid[p - 2]) + (c - mid[p + 2]);
+  d1 += (c - mid[p - PX]) + (c - mid[p + PX]);
+  d2 += (c - mid[p - 2 * PX]) + (c - mid[p + 2 * PX]);
+  d1 += (c - ring[slot[1] * plane_sz + p]) + (c - ring[slot[3] * plane_sz + p]);
+  d2 += (c - ring[slot[0] * plane_sz + p]) + (c - ring[slot[4] * plane_sz + p]);
+  return w1 * d1 + w2 * d2;
+}
+
+// Separable operator on the region's inner part: given the ring of 7 planes, compute
+// L u for every (px, py) with E <= px < PX-E, E <= py < PY-E (E = 3) into out (same
+// pitch).  Uses scratch arrays zb, za (PX*PY) and yb, ys (PX*PY).  Barriers inside.
+template <typename T, int PX, int PY>
+__device__ void sep_lu_plane(const T *ring, int plane_sz, const int (&slot)[7], const KOp<T> &op,
+                             T *zb, T *za, T *t1, T *t2, T *out) {
+  constexpr int NP = PX * PY;
+  // z pass over the whole region
+  for (int e = threadIdx.x; e < NP; e += 256) {
+    const T c = ring[slot[3] * plane_sz + e];
+    T A = T(0), B = T(0);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      const T v = ring[slot[k] * plane_sz + e];
+      if (k != 3) A += op.a[k] * (v - c);
+      B += op.b[k] * v;
+    }
+    zb[e] = B;
+    za[e] = A;
+  }
+  __syncthreads();
+  // y pass over rows 3..PY-4 (all columns)
+  for (int e = threadIdx.x; e < NP; e += 256) {
+    const int py = e / PX;
+    if (py < 3 || py >= PY - 3) continue;
+    const T bc = zb[e];
+    T s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const T bz = zb[e + (j - 3) * PX];
+      s1 += op.b[j] * bz;                               // b_y b_z u
+      if (j != 3) s2 += op.a[j] * (bz - bc);             // a_y b_z u
+      s3 += op.b[j] * za[e + (j - 3) * PX];              // b_y a_z u
+    }
+    t1[e] = s1;
+    t2[e] = s2 + s3;
+  }
+  __syncthreads();
+  // x pass for the inner points
+  for (int e = threadIdx.x; e < NP; e += 256) {
+    const int px = e % PX, py = e / PX;
+    if (py < 3 || py >= PY - 3 || px < 3 || px >= PX - 3) continue;
+    const T c1 = t1[e];
+    T lu = T(0);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      if (i != 3) lu += op.a[i] * (t1[e + i - 3] - c1);
+      lu += op.b[i] * t2[e + i - 3];
+    }
+    out[e] = lu;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ sweep ----
+template <typename T, typename TO, int MODE, int R>
+__global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const T *__restrict__ u,
+                                                 TO *__restrict__ out, int n, int zchunk, KOp<T> op,
+                                                 double *__restrict__ partials,
+                                                 const int *__restrict__ done) {
+  constexpr int W = 2 * R + 1;
+  constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  extern __shared__ __align__(16) unsigned char smem3[];
+  T *ring = reinterpret_cast<T *>(smem3);
+  T *zb = ring + W * PS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
+  if (stopped(done)) return;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int z0 = blockIdx.z * zchunk, z1 = min(z0 + zchunk, n);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x <= n - 1 && y <= n - 1;
+  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
+  const bool zero_u = u == nullptr;
+  PlaneLoader<T, PX, PY> ld;
+  ld.init(x0 - R, y0 - R, n);
+  using Raw = T[PlaneLoader<T, PX, PY>::Q];
+  Raw nxt;
+  const T *up = zero_u ? f : u;
+  // fill the ring with planes z0-R .. z0+R-1 (zeros for a zero initial guess)
+  if (zero_u) {
+    for (int e = threadIdx.x; e < W * PS; e += 256) ring[e] = T(0);
+  } else {
+    for (int k = 0; k < 2 * R; ++k) {
+      Raw r;
+      ld.load(up, z0 - R + k, r);
+      ld.store(ring + k * PS, z0 - R + k, r);
+    }
+  }
+  ld.load(up, z0 + R, nxt);
+  // f at this thread's column, address always valid
+  const size_t fcol = (size_t)(own && xin ? y : 1) * n + (own && xin ? x : 1);
+  double acc = 0.0;
+  int head = 0;  // ring slot of plane z - R
+  for (int z = z0; z < z1; ++z) {
+    // plane z + R into the slot after the newest
+    const int ns = (head + 2 * R) % W;
+    if (!zero_u) ld.store(ring + ns * PS, z + R, nxt);
+    if (!zero_u) ld.load(up, z + R + 1, nxt);
+    const T fraw = f[(size_t)(z > 0 && z < n - 1 ? z : 1) * n * n + fcol];
+    __syncthreads();
+    const T fv = (own && xin && z > 0 && z < n - 1) ? fraw : T(0);
+    T lu;
+    const int p = (ty + R) * PX + (tx + R);
+    if constexpr (R == 2) {
+      int slot[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) slot[k] = (head + k) % W;
+      lu = zero_u ? T(0) : cross_lu<T, PX>(ring, PS, slot, tx + R, ty + R, op.w1, op.w2);
+    } else {
+      int slot[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) slot[k] = (head + k) % W;
+      sep_lu_plane<T, PX, PY>(ring, PS, slot, op, zb, za, t1, t2, lo);
+      lu = zero_u ? T(0) : lo[p];
+    }
+    const T uc = ring[((head + R) % W) * PS + p];
+    const bool inside = own && xin && z > 0 && z < n - 1;
+    const T r = inside ? fv - lu : T(0);
+    if (inside) acc += (double)r * (double)r;
+    if (own) {
+      const size_t id = ((size_t)z * n + y) * n + x;
+      if (MODE == kSweep) out[id] = (TO)(inside ? uc + op.om_d * r : T(0));
+      if (MODE == kResidual) out[id] = (TO)r;
+    }
+    head = (head + 1) % W;
+    __syncthreads();
+  }
+  if (partials != nullptr) {
+    const double tot = block_sum256(acc);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// ------------------------------------------------- defect + full weighting ----
+// Block: coarse tile (TX/2) x (TY/2) at coarse planes [K0, K1).  The defect is computed on
+// the fine tile extended by one point (the full-weighting support), kept for three
+// fine planes in LDS, and restricted in z, y and x.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ f,
+                                                          const T *__restrict__ u,
+                                                          T *__restrict__ fc, int n, int kchunk,
+                                                          KOp<T> op, const int *__restrict__ done) {
+  constexpr int W = 2 * R + 1;
+  constexpr int E = R + 1;  // halo of the u region: stencil plus the restriction support
+  constexpr int PX = TX + 2 * E, PY = TY + 2 * E, PS = PX * PY;
+  constexpr int RX = TX + 2, RY = TY + 2, RS = RX * RY;  // defect region
+  extern __shared__ __align__(16) unsigned char smem3[];
+  T *ring = reinterpret_cast<T *>(smem3);
+  T *rr = ring + W * PS;  // three defect planes
+  T *zb = rr + 3 * RS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
+  if (stopped(done)) return;
+  const int nc = (n - 1) / 2 + 1;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;  // fine origin (even)
+  const int K0 = blockIdx.z * kchunk, K1 = min(K0 + kchunk, nc);
+  const bool zero_u = u == nullptr;
+  PlaneLoader<T, PX, PY> ld;
+  ld.init(x0 - E, y0 - E, n);
+  using Raw = T[PlaneLoader<T, PX, PY>::Q];
+  Raw nxt;
+  const T *up = zero_u ? f : u;
+  // coarse points of this thread: (I, J) = (x0/2 + ci, y0/2 + cj), ci < TX/2, cj < TY/2
+  const int ci = threadIdx.x % (TX / 2), cj = threadIdx.x / (TX / 2);
+  const int I = x0 / 2 + ci, J = y0 / 2 + cj;
+  const bool cown = threadIdx.x < (TX / 2) * (TY / 2) && I <= nc - 1 && J <= nc - 1;
+  const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
+  // boundary coarse planes
+  if (cown) {
+    if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
+    if (K1 == nc) fc[((size_t)(nc - 1) * nc + J) * nc + I] = T(0);
+  }
+  const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
+  if (Klo >= Khi) return;
+  const int zs = 2 * Klo - 1, ze = 2 * (Khi - 1) + 1;
+  if (zero_u) {
+    for (int e = threadIdx.x; e < W * PS; e += 256) ring[e] = T(0);
+  } else {
+    for (int k = 0; k < 2 * R; ++k) {
+      Raw r;
+      ld.load(up, zs - R + k, r);
+      ld.store(ring + k * PS, zs - R + k, r);
+    }
+  }
+  ld.load(up, zs + R, nxt);
+  int head = 0;
+  int rhead = 0;  // slot of the oldest defect plane
+  for (int z = zs; z <= ze; ++z) {
+    const int ns = (head + 2 * R) % W;
+    if (!zero_u) ld.store(ring + ns * PS, z + R, nxt);
+    if (!zero_u) ld.load(up, z + R + 1, nxt);
+    __syncthreads();
+    // defect on the RX x RY region (fine x0-1 .. x0+TX, y0-1 .. y0+TY) into the newest slot
+    T *rnew = rr + ((rhead + 2) % 3) * RS;
+    int slot7[7];
+    if constexpr (R == 3) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) slot7[k] = (head + k) % W;
+      sep_lu_plane<T, PX, PY>(ring, PS, slot7, op, zb, za, t1, t2, lo);
+    }
+    for (int e = threadIdx.x; e < RS; e += 256) {
+      const int rx = e % RX, ry = e / RX;
+      const int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
+      const bool inside = gx > 0 && gx < n - 1 && gy > 0 && gy < n - 1 && z > 0 && z < n - 1;
+      T v = T(0);
+      if (inside) {
+        const int px = rx + (E - 1), py = ry + (E - 1);
+        T lu;
+        if constexpr (R == 2) {
+          int slot[5];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) slot[k] = (head + k) % W;
+          lu = cross_lu<T, PX>(ring, PS, slot, px, py, op.w1, op.w2);
+        } else {
+          lu = lo[py * PX + px];
+        }
+        if (zero_u) lu = T(0);
+        v = f[((size_t)z * n + gy) * n + gx] - lu;
+      }
+      rnew[e] = v;
+    }
+    __syncthreads();
+    // z = 2K+1 completes coarse plane K = (z-1)/2 (planes 2K-1, 2K, 2K+1 in the ring)
+    if (((z - zs) & 1) == 0 && z > zs) {
+      const int K = (z - 1) / 2;
+      if (cown) {
+        T s = T(0);
+        if (cin) {
+          const T *p0 = rr + (rhead % 3) * RS, *p1 = rr + ((rhead + 1) % 3) * RS,
+                  *p2 = rr + ((rhead + 2) % 3) * RS;
+          for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+              const int e = (2 * cj + 1 + oy) * RX + (2 * ci + 1 + ox);
+              const T wxy = (ox == 0 ? T(0.5) : T(0.25)) * (oy == 0 ? T(0.5) : T(0.25));
+              s += wxy * (T(0.25) * p0[e] + T(0.5) * p1[e] + T(0.25) * p2[e]);
+            }
+        }
+        fc[((size_t)K * nc + J) * nc + I] = s;
+      }
+    }
+    head = (head + 1) % W;
+    rhead = (rhead + 1) % 3;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------- interpolation + correction ----
+// Fine tile TX x TY at planes [z0, z1).  For each coarse plane the coarse region around
+// the tile is staged in LDS, interpolated in x and y at this thread's fine column, and
+// kept in a window of four coarse planes; the z interpolation completes the value.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_prolong3d(const T *__restrict__ v, const T *uin, T *uout,
+                                                   int n, int zchunk, const int *__restrict__ done) {
+  constexpr int CX = TX / 2 + 4, CY = TY / 2 + 4, CS = CX * CY;
+  __shared__ T cpl[2][CS];
+  if (stopped(done)) return;
+  const int nc = (n - 1) / 2 + 1;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int z0 = blockIdx.z * zchunk, z1 = min(z0 + zchunk, n);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const int Ib = x0 / 2 - 1, Jb = y0 / 2 - 1;  // coarse region origin
+  // coarse loader for the CX x CY region
+  int coff = 0;
+  T cmul = T(0);
+  {
+    const int e = threadIdx.x;
+    if (e < CS) {
+      int s = 1;
+      const int xf = fold(Ib + e % CX, nc, s), yf = fold(Jb + e / CX, nc, s);
+      const bool ok = xf > 0 && xf < nc - 1 && yf > 0 && yf < nc - 1;
+      coff = ok ? yf * nc + xf : nc + 1;
+      cmul = ok ? T(s) : T(0);
+    }
+  }
+  auto cload = [&](int K) -> T {
+    int s = 1;
+    int kf = fold(K, nc, s);
+    kf = (kf > 0 && kf < nc - 1) ? kf : 1;
+    return v[(size_t)kf * nc * nc + coff];
+  };
+  auto cmulz = [&](int K) -> T {
+    int s = 1;
+    const int kf = fold(K, nc, s);
+    return (kf > 0 && kf < nc - 1) ? T(s) : T(0);
+  };
+  auto w1d = [&](int fine, T (&w)[4]) {  // weights of coarse fine/2-1 .. fine/2+2 (floor)
+    if ((fine & 1) == 0) {
+      w[0] = T(0); w[1] = T(1); w[2] = T(0); w[3] = T(0);
+    } else if (P == 3) {
+      w[0] = T(-0.0625); w[1] = T(0.5625); w[2] = T(0.5625); w[3] = T(-0.0625);
+    } else {
+      w[0] = T(0); w[1] = T(0.5); w[2] = T(0.5); w[3] = T(0);
+    }
+  };
+  T wx[4], wy[4];
+  w1d(x, wx);
+  w1d(y, wy);
+  const int lx = (x >> 1) - 1 - Ib, ly = (y >> 1) - 1 - Jb;  // local coarse index of window start
+  auto interp_xy = [&](const T *pl) -> T {
+    T s = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      T row = T(0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) row += wx[a] * pl[(ly + b) * CX + lx + a];
+      s += wy[b] * row;
+    }
+    return s;
+  };
+  T pw[4];
+  int kb = (z0 >> 1) - 1;  // coarse plane of pw[0]
+  int buf = 0;
+  T cnext = threadIdx.x < CS ? cload(kb) : T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (threadIdx.x < CS) {
+      const T m = cmul * cmulz(kb + k);
+      cpl[buf][threadIdx.x] = m != T(0) ? cnext * m : T(0);
+    }
+    if (threadIdx.x < CS) cnext = cload(kb + k + 1);
+    __syncthreads();
+    pw[k] = interp_xy(cpl[buf]);
+    buf ^= 1;
+  }
+  T wz[4];
+  const bool own = x <= n - 1 && y <= n - 1;
+  for (int z = z0; z < z1; ++z) {
+    const int Kc = z >> 1;
+    while (kb < Kc - 1) {
+      if (threadIdx.x < CS) {
+        const T m = cmul * cmulz(kb + 4);
+        cpl[buf][threadIdx.x] = m != T(0) ? cnext * m : T(0);
+        cnext = cload(kb + 5);
+      }
+      __syncthreads();
+      const T nv = interp_xy(cpl[buf]);
+      buf ^= 1;
+      pw[0] = pw[1];
+      pw[1] = pw[2];
+      pw[2] = pw[3];
+      pw[3] = nv;
+      ++kb;
+    }
+    w1d(z, wz);
+    const T val = wz[0] * pw[0] + wz[1] * pw[1] + wz[2] * pw[2] + wz[3] * pw[3];
+    if (own) {
+      const size_t id = ((size_t)z * n + y) * n + x;
+      const bool inside = x > 0 && x < n - 1 && y > 0 && y < n - 1 && z > 0 && z < n - 1;
+      uout[id] = inside ? uin[id] + val : T(0);
+    }
+  }
+}
+
+int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+int clampi(long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
+
+template <typename T>
+KOp<T> to_kop3(const LevelOp &op, double omega) {
+  KOp<T> k;
+  for (int i = 0; i < 7; ++i) {
+    k.a[i] = (T)op.a[i];
+    k.b[i] = (T)op.b[i];
+  }
+  k.w1 = (T)(-op.a[2]);
+  k.w2 = (T)(-op.a[1]);
+  k.om_d = (T)(omega / op.diag);
+  return k;
+}
+
+// planes per block: about 4096 blocks in total, 8..64 planes
+int zchunk_for(int n, long tiles, int lo, int hi) {
+  return clampi((long)n * tiles / 4096, lo, hi);
+}
+
+template <typename T, int R>
+size_t sweep_smem() {
+  constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  return sizeof(T) * (size_t)((2 * R + 1) * PS + (R == 3 ? 5 * PS : 0));
+}
+
+template <typename T, int R>
+size_t rr_smem() {
+  constexpr int E = R + 1;
+  constexpr int PX = TX + 2 * E, PY = TY + 2 * E, PS = PX * PY;
+  constexpr int RS = (TX + 2) * (TY + 2);
+  return sizeof(T) * (size_t)((2 * R + 1) * PS + 3 * RS + (R == 3 ? 5 * PS : 0));
+}
+
+}  // namespace
+
+int sweep_partials_3d(int n) {
+  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
+  const int zc = zchunk_for(n, tiles, 8, 64);
+  return (int)(tiles * cdiv(n, zc));
+}
 
 template <typename T, typename TO>
-hipError_t launch_sweep_3d(int, const LevelOp &, double, const T *, const T *, TO *, int,
-                           double *, int *, const int *, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
+                           TO *out, int n, double *partials, int *nparts, const int *done,
+                           hipStream_t s) {
+  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
+  const int zc = zchunk_for(n, tiles, 8, 64);
+  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
+  if (nparts) *nparts = grid.x * grid.y * grid.z;
+  const KOp<T> k = to_kop3<T>(op, omega);
+#define MG_S3(MODE, R) \
+  hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, R>), grid, dim3(256), (sweep_smem<T, R>()), s, f, u, out, n, zc, k, partials, done)
+  if (op.cross) {
+    if (mode == kSweep) MG_S3(kSweep, 2);
+    else if (mode == kResidual) MG_S3(kResidual, 2);
+    else MG_S3(kNormOnly, 2);
+  } else {
+    if (mode == kSweep) MG_S3(kSweep, 3);
+    else if (mode == kResidual) MG_S3(kResidual, 3);
+    else MG_S3(kNormOnly, 3);
+  }
+#undef MG_S3
+  return hipGetLastError();
 }
+
 template <typename T>
-hipError_t launch_resid_restrict_3d(const LevelOp &, const T *, const T *, T *, int, const int *,
-                                    hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
+                                    const int *done, hipStream_t s) {
+  const int nc = (n - 1) / 2 + 1;
+  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
+  const int kc = zchunk_for(nc, tiles, 4, 32);
+  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(nc, kc));
+  const KOp<T> k = to_kop3<T>(op, 1.0);
+  if (op.cross)
+    hipLaunchKernelGGL((k_resid_restrict3d<T, 2>), grid, dim3(256), (rr_smem<T, 2>()), s, f, u, fc, n, kc, k, done);
+  else
+    hipLaunchKernelGGL((k_resid_restrict3d<T, 3>), grid, dim3(256), (rr_smem<T, 3>()), s, f, u, fc, n, kc, k, done);
+  return hipGetLastError();
 }
+
 template <typename T>
-hipError_t launch_prolong_correct_3d(int, const T *, const T *, T *, int, const int *,
-                                     hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
+                                     const int *done, hipStream_t s) {
+  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
+  const int zc = zchunk_for(n, tiles, 8, 64);
+  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
+  if (prolong == 3)
+    hipLaunchKernelGGL((k_prolong3d<T, 3>), grid, dim3(256), 0, s, v, uin, uout, n, zc, done);
+  else
+    hipLaunchKernelGGL((k_prolong3d<T, 1>), grid, dim3(256), 0, s, v, uin, uout, n, zc, done);
+  return hipGetLastError();
+}
+
+// Dynamic LDS above 64 KB must be enabled per kernel before the first launch.
+hipError_t prepare_3d() {
+  hipError_t e = hipSuccess;
+#define MG_P(K, B)                                                                         \
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void *)K, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B));
+  MG_P((k_sweep3d<double, double, kSweep, 3>), (sweep_smem<double, 3>()));
+  MG_P((k_sweep3d<double, double, kResidual, 3>), (sweep_smem<double, 3>()));
+  MG_P((k_sweep3d<double, double, kNormOnly, 3>), (sweep_smem<double, 3>()));
+  MG_P((k_sweep3d<float, float, kSweep, 3>), (sweep_smem<float, 3>()));
+  MG_P((k_sweep3d<float, float, kResidual, 3>), (sweep_smem<float, 3>()));
+  MG_P((k_sweep3d<float, float, kNormOnly, 3>), (sweep_smem<float, 3>()));
+  MG_P((k_resid_restrict3d<double, 3>), (rr_smem<double, 3>()));
+  MG_P((k_resid_restrict3d<float, 3>), (rr_smem<float, 3>()));
+#undef MG_P
+  return e;
 }
 
 template hipError_t launch_sweep_3d<double, double>(int, const LevelOp &, double, const double *,

@@ -86,6 +86,7 @@ int sweep_partials(int dim, int n);
 
 // 3D variants (kernels3d.hip), called by the launchers above for dim == 3.
 int sweep_partials_3d(int n);
+hipError_t prepare_3d();  // enables the large dynamic LDS of the separable 3D kernels
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,

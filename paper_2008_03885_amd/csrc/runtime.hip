@@ -758,6 +758,10 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
       if (e != hipSuccess) return bail(fail(MG_EDEVICE, std::string("tail setup: ") + hipGetErrorString(e)));
     }
   }
+  if (c->dim == 3) {
+    hipError_t e = mgk::prepare_3d();
+    if (e != hipSuccess) return bail(fail(MG_EDEVICE, std::string("3D kernel setup: ") + hipGetErrorString(e)));
+  }
   c->np_max = partials_needed(c->dim, cfg->n);
   if ((st = dev_alloc(c, (void **)&c->partials, (size_t)c->np_max * 8)) != MG_OK) return bail(st);
   if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState))) != MG_OK) return bail(st);

@@ -127,7 +127,7 @@ def test_prolong_correct(dim, n, coarse, prolong, level, fp32):
 @pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("dim,coarse,prolong", [(2, 0, 3), (2, 1, 3), (2, 1, 1)])
 def test_coarsest_solve(dim, coarse, prolong, fp32):
-    H = Handle(dim, 65, coarse=coarse, prolong=prolong)
+    H = Handle(dim, 65 if dim == 2 else 33, coarse=coarse, prolong=prolong)
     try:
         L = H.oracle.levels
         n_c, s = H.level(L - 1)
@@ -273,5 +273,64 @@ def test_prolong_postsmooth(dim, n, coarse, prolong, level, nu1, nu2, fp32):
         tol = TOL32 if fp32 else TOL64
         scale = (np.abs(u).max() + 2 * np.abs(v).max() + np.abs(f).max() / d) * (1 + nu2)
         assert_close(host(uo), ref, tol * scale * 4, "post")
+    finally:
+        H.close()
+
+
+CASES_3D = [
+    # dim, finest n, coarse, prolong, level
+    (3, 9, 0, 3, 0), (3, 17, 0, 3, 0), (3, 33, 0, 3, 0), (3, 65, 0, 3, 0), (3, 65, 0, 3, 1),
+    (3, 33, 1, 3, 1), (3, 65, 1, 3, 1), (3, 65, 1, 3, 2), (3, 33, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", CASES_3D)
+def test_smooth_3d(dim, n, coarse, prolong, level, fp32):
+    test_smooth(dim, n, coarse, prolong, level, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", CASES_3D)
+def test_residual_3d(dim, n, coarse, prolong, level, fp32):
+    test_residual(dim, n, coarse, prolong, level, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", [c for c in CASES_3D if c[1] > 9])
+def test_residual_restrict_3d(dim, n, coarse, prolong, level, fp32):
+    test_residual_restrict(dim, n, coarse, prolong, level, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", [c for c in CASES_3D if c[1] > 9])
+def test_prolong_correct_3d(dim, n, coarse, prolong, level, fp32):
+    test_prolong_correct(dim, n, coarse, prolong, level, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("coarse,prolong", [(0, 3), (1, 3)])
+def test_coarsest_solve_3d(coarse, prolong, fp32):
+    test_coarsest_solve(3, coarse, prolong, fp32)
+
+
+def test_full_size_sweep_513_3d():
+    """Level-0 sweep and defect + full weighting at 513^3, every element."""
+    n = 513
+    H = Handle(3, n)
+    try:
+        _, s = H.level(0)
+        u = rand_grid(n, 3, 31)
+        f = rand_grid(n, 3, 32) * s[2, 2, 2]
+        ud, fd = dev(u), dev(f)
+        out = dev(np.full_like(u, np.nan))
+        mg.mg_kernel_smooth(H.h, 0, 0, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        assert_close(host(out), oracle.jacobi(s, H.omega, f, u), TOL64 * _scale_u(u, f, s), "sweep")
+        del out
+        nc = (n - 1) // 2 + 1
+        fc = dev(np.full((nc,) * 3, np.nan))
+        mg.mg_kernel_residual_restrict(H.h, 0, 0, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
+        ref = oracle.restrict(oracle.residual(s, f, u))
+        assert_close(host(fc), ref, TOL64 * 4 * (np.abs(f).max() + s[2, 2, 2] * np.abs(u).max()), "rr")
     finally:
         H.close()

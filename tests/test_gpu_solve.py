@@ -220,3 +220,82 @@ def test_nonfinite_rhs_reports_enumeric():
         assert st == mg.MG_ENUMERIC and res.status == 4
     finally:
         H.close()
+
+
+CYCLE_CASES_3D = [
+    # n, coarse, prolong, nu1, nu2, gamma
+    (17, 0, 3, 2, 1, 1), (33, 0, 3, 2, 1, 1), (33, 1, 3, 2, 1, 1), (33, 0, 3, 2, 2, 2),
+    (33, 1, 3, 2, 2, 2), (33, 0, 1, 1, 1, 1), (65, 0, 3, 2, 1, 1), (65, 1, 3, 2, 2, 2),
+]
+
+
+@pytest.mark.parametrize("n,coarse,prolong,nu1,nu2,gamma", CYCLE_CASES_3D)
+def test_fixed_cycles_match_oracle_3d(n, coarse, prolong, nu1, nu2, gamma):
+    H = Handle(3, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, gamma=gamma)
+    try:
+        f = inputs.smooth_sine_3d(n)
+        cycles = 6
+        u, res, u_ref, hist = _fixed_cycles(H, f, cycles)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("tail", [None, "0"])
+def test_3d_tail_variants_agree(tail, monkeypatch):
+    if tail is None:
+        monkeypatch.delenv("MG_TAIL_N", raising=False)
+    else:
+        monkeypatch.setenv("MG_TAIL_N", tail)
+    n = 33
+    H = Handle(3, n, gamma=2)
+    try:
+        f = inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 4)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+    finally:
+        H.close()
+
+
+def test_mixed_precision_3d():
+    """3D noise right-hand side: FP32 cycles in FP64 refinement reach 1e-10 like FP64."""
+    n = 129
+    f = inputs.smoothed_noise_3d(n)
+    H64 = Handle(3, n, rtol=1e-10, max_cycles=60)
+    Hmx = Handle(3, n, precision=1, rtol=1e-10, max_cycles=20, inner_cycles=4)
+    try:
+        fd = dev(f)
+        u64, umx = dev(np.zeros_like(f)), dev(np.zeros_like(f))
+        st, r64 = mg.mg_solve(H64.h, fd.data_ptr(), u64.data_ptr())
+        st2, rmx = mg.mg_solve(Hmx.h, fd.data_ptr(), umx.data_ptr())
+        assert st == mg.MG_OK and st2 == mg.MG_OK
+        assert r64.rel_residual <= 1e-10 and rmx.rel_residual <= 1e-10
+        a, b = host(u64), host(umx)
+        assert np.linalg.norm(a - b) / np.linalg.norm(a) <= 1e-9
+        exact = dst.solve(f)
+        assert np.linalg.norm(a - exact) / np.linalg.norm(exact) <= 1e-9
+    finally:
+        H64.close()
+        Hmx.close()
+
+
+def test_c3_513_fp64_solve():
+    """3D 513^3, smoothed-noise right-hand side, V(2,1), FP64, to 1e-10: the device residual
+    agrees with a long-double evaluation of the returned iterate."""
+    n = 513
+    f = inputs.smoothed_noise_3d(n)
+    H = Handle(3, n, rtol=1e-10, max_cycles=60)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_OK and res.rel_residual <= 1e-10
+        assert res.cycles <= 40
+        u = host(ud)
+        s = oracle.fine_stencil(3, 4, 1.0 / (n - 1))
+        rel_ld = oracle.residual_norm_ld(s, f, u) / oracle.norm(f)
+        assert abs(res.rel_residual - rel_ld) <= 0.05 * rel_ld
+    finally:
+        H.close()
