@@ -1,16 +1,24 @@
-"""Benchmark: 2D fourth-order Poisson multigrid solve on one MI355X.
+"""Benchmark: fourth-order Poisson multigrid solves on one MI355X.
 
-Workload (one step = one whole solve from a zero initial guess to a 1e-10 relative
-residual, or the FP64 rounding floor): n = 4097 points per side (16,769,025 unknowns),
-right-hand side sum_{kx,ky<=64} g_k/|k| sin(kx pi x) sin(ky pi y), g_k ~ N(0,1) (seeded),
-fourth-order width-5 operator, homogeneous Dirichlet boundary, V(2,1) cycles with
-omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized coarse
-operators down to 9x9 with an exact coarsest solve, all in FP64.
+One step is one whole solve from a zero initial guess to a 1e-10 relative residual (or
+the FP64 rounding floor), with f and u resident in HBM.  Workloads (--workload):
 
-Prints one JSON line: throughput in unknowns/s, the roofline of the level-0 Jacobi sweep
-(HIP-event timed here), and the CPU oracle timed on a bounded sample.
+  poisson2d-4097 (default)  2D, n = 4097 (16,769,025 unknowns), right-hand side
+      sum_{kx,ky<=64} g_k/|k| sin(kx pi x) sin(ky pi y), g_k ~ N(0,1) (seeded), V(2,1)
+      omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized
+      coarse operators to 9x9 with an exact coarsest solve, FP64.
+  poisson3d-513             3D, n = 513, uniform[-1,1] noise smoothed by three
+      neighbour-average passes, V(2,1) (omega = 9/11), mixed precision against FP64.
+  poisson3d-1025-galerkin-w22  3D, n = 1025, smooth sine series (k <= 8), Galerkin
+      coarse operators, W(2,2), mixed against FP64, plus the error of the solution
+      against the oracle's 129^3 solve of the same continuous problem.
+
+Prints one JSON line: throughput in unknowns/s, the roofline of the dominant kernel
+(HIP-event timed on the handle's stream), per-level kernel rates, and the CPU oracle
+timed on a bounded sample.  --gpus N with N > 1 exits: this library runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,105 +29,405 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+WORKLOADS = {
+    "poisson2d-4097": dict(dim=2, n=4097, rhs="fourier", coarse=0, gamma=1, nu1=2, nu2=1,
+                           precision=0, compare=False, inner=4),
+    "poisson3d-513": dict(dim=3, n=513, rhs="noise", coarse=0, gamma=1, nu1=2, nu2=1,
+                          precision=1, compare=True, inner=4),
+    "poisson3d-1025-galerkin-w22": dict(dim=3, n=1025, rhs="sine", coarse=1, gamma=2, nu1=2,
+                                        nu2=2, precision=1, compare=True, inner=3, check129=True),
+}
+
+# HBM traffic of the dominant kernels from rocprofv3 --pmc (FETCH_SIZE and WRITE_SIZE per
+# dispatch, scaled by the counters of a plain copy of known size), valid only for the
+# kernel source they were taken on.
+MEASURED_TRAFFIC = {}
+
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--n", type=int, default=4097)
-    p.add_argument("--coarse", type=int, default=0)
-    p.add_argument("--gamma", type=int, default=1)
-    p.add_argument("--precision", type=int, default=0)
+    p.add_argument("--workload", default="poisson2d-4097", choices=sorted(WORKLOADS))
+    p.add_argument("--n", type=int, default=None)
+    p.add_argument("--coarse", type=int, default=None)
+    p.add_argument("--gamma", type=int, default=None)
+    p.add_argument("--precision", type=int, default=None)
+    p.add_argument("--compare", type=int, default=None, help="also run the other precision")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--no-levels", action="store_true", help="skip the per-level kernel table")
+    p.add_argument("--kernel-reps", type=int, default=30)
+    p.add_argument("--pmc-probe", action="store_true",
+                   help="run a plain copy of known size, then the dominant kernel (for counters)")
+    p.add_argument("--serve-requests", type=int, default=120,
+                   help="requests per serving run (0: skip the serving measurement)")
+    p.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     return p.parse_args()
 
 
-def cpu_baseline(n, cycles_needed, budget_s=20.0):
-    """The oracle (plain C, FP64, OpenMP over rows) on a bounded sample: whole cycles of
-    the same problem, timed, scaled to the cycles the GPU solve needed."""
+def source_hash(*names):
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2008_03885_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_rhs(w):
+    from paper_2008_03885_amd import inputs
+    n = w["n"]
+    if w["rhs"] == "fourier":
+        return inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2), None
+    if w["rhs"] == "noise":
+        return inputs.smoothed_noise_3d(n), None
+    return inputs.smooth_sine_3d(n, return_coeffs=True)
+
+
+def describe(w):
+    kind = "Galerkin" if w["coarse"] else "rediscretized"
+    cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
+    rhs = {"fourier": "Fourier RHS k<=64 amplitudes N(0,1)/|k|",
+           "noise": "uniform[-1,1] noise smoothed by 3 neighbour-average passes",
+           "sine": "smooth sine-series RHS k<=8"}[w["rhs"]]
+    prec = "FP64" if w["precision"] == 0 else "FP32 cycles in FP64 refinement"
+    d = w["dim"]
+    return "%dD 4th-order Poisson %s, %s, %s omega-Jacobi, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
+        d, "x".join([str(w["n"])] * d), rhs, cyc, kind, d, prec)
+
+
+class Run:
+    """One handle of the workload at a given precision, solving from zero."""
+
+    def __init__(self, w, precision, fd, stream):
+        import torch
+        from paper_2008_03885_amd import mg
+        self.mg = mg
+        self.cfg = mg.make_config(dim=w["dim"], n=w["n"], coarse=w["coarse"], gamma=w["gamma"],
+                                  nu1=w["nu1"], nu2=w["nu2"], precision=precision, rtol=1e-10,
+                                  max_cycles=60 if precision == 0 else 30,
+                                  inner_cycles=w["inner"])
+        self.h = mg.mg_setup(self.cfg, stream.cuda_stream)
+        self.fd = fd
+        self.ud = torch.zeros_like(fd)
+        self.precision = precision
+
+    def step(self):
+        self.ud.zero_()
+        return self.mg.mg_solve(self.h, self.fd.data_ptr(), self.ud.data_ptr())
+
+    def timed(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = [self.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, results[-1]
+
+    def close(self):
+        self.mg.mg_destroy(self.h)
+
+
+def event_time(stream, fn, reps):
+    """Average duration of fn() over reps launches, HIP events on the handle's stream."""
+    import torch
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def level_kernels(run, w, stream, reps, only_level0=False):
+    """Per-level launches of the kernels the cycle runs on that level, each timed with HIP
+    events, with their algorithmic bytes.  2D: the fused pre-smoothing + defect + full
+    weighting and the fused interpolation + correction + post-smoothing; 3D: the sweep, the
+    fused defect + full weighting and the interpolation + correction."""
+    import torch
+    mg = run.mg
+    fp32 = 1 if run.precision == 1 else 0
+    dt = torch.float32 if fp32 else torch.float64
+    b = 4 if fp32 else 8
+    d = w["dim"]
+    rows = []
+    L = 0
+    while mg.mg_level_size(run.h, L) > 0:
+        L += 1
+    tail_cap = 65 if d == 2 else 17
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    for l in range(L - 1):
+        n, nc = mg.mg_level_size(run.h, l), mg.mg_level_size(run.h, l + 1)
+        if n <= tail_cap or (only_level0 and l > 0):
+            break
+        shp, cshp = (n,) * d, (nc,) * d
+        f = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
+        u = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
+        t = torch.empty_like(u)
+        fc = torch.empty(cshp, device="cuda", dtype=dt)
+        v = torch.randn(cshp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
+        P, Pc = n ** d, nc ** d
+        if d == 2:
+            ks = [
+                ("k_pre2d", "presmooth(%d)+defect+FW" % w["nu1"], (3 * P + Pc) * b,
+                 lambda: mg.mg_kernel_presmooth_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
+                                                         t.data_ptr(), fc.data_ptr())),
+                ("k_post2d", "interp+correct+postsmooth(%d)" % w["nu2"], (3 * P + Pc) * b,
+                 lambda: mg.mg_kernel_prolong_postsmooth(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
+                                                         f.data_ptr(), t.data_ptr())),
+            ]
+        else:
+            ks = [
+                ("k_sweep3d", "omega-Jacobi sweep", 3 * P * b,
+                 lambda: mg.mg_kernel_smooth(run.h, l, fp32, f.data_ptr(), u.data_ptr(), t.data_ptr())),
+                ("k_resid_restrict3d", "defect+FW", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
+                                                        fc.data_ptr())),
+                ("k_prolong3d", "interp+correct", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_prolong_correct(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
+                                                      t.data_ptr())),
+            ]
+        for name, what, nbytes, fn in ks:
+            s = event_time(stream, fn, reps)
+            rows.append({"level": l, "n": n, "kernel": name, "op": what, "us": s * 1e6,
+                         "bytes": nbytes, "GB/s": nbytes / s / 1e9})
+        del f, u, t, fc, v
+    return rows
+
+
+def cpu_baseline(w, cycles_needed, budget_s=20.0):
+    """The oracle (plain C, FP64, OpenMP over the outer loop) on a bounded sample: whole
+    cycles of the same configuration, timed, scaled to the cycles the GPU solve needed.
+    3D problems above 513^3 (257^3 with Galerkin operators) are sampled at that size and
+    scaled per unknown."""
     import numpy as np
 
     import oracle
-    from paper_2008_03885_amd import inputs
-
-    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
-    m = oracle.Multigrid(2, n)
+    d = w["dim"]
+    cap = 257 if w["coarse"] else 513
+    n = w["n"] if (d == 2 or w["n"] <= cap) else cap
+    ws = dict(w, n=n)
+    f, _ = make_rhs(ws)
+    m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"])
     u = np.zeros_like(f)
     t0 = time.perf_counter()
     m.cycle(u, f)
     t_cycle = time.perf_counter() - t0
     done = 1
-    while done * t_cycle < budget_s and done < 4:
+    while (done + 1) * t_cycle < budget_s and done < 4:
         t0 = time.perf_counter()
         m.cycle(u, f)
         t_cycle = min(t_cycle, time.perf_counter() - t0)
         done += 1
-    unknowns = (n - 2) ** 2
+    m.close()
+    unknowns = (n - 2) ** d
+    cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
     return {
         "value": unknowns / (t_cycle * cycles_needed),
         "unit": "unknowns/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "%d V(2,1) cycles of the %dx%d problem (best cycle %.2f s), scaled to the %d "
-                  "cycles the solve needs" % (done, n, n, t_cycle, cycles_needed),
+        "sample": "%d FP64 %s cycles of the %s problem (best cycle %.2f s), scaled to the %d "
+                  "cycles the GPU FP64 solve needs" % (done, cyc, "x".join([str(n)] * d), t_cycle,
+                                                      cycles_needed),
     }
+
+
+def error_vs_129(ud_host, w, coeffs):
+    """The 1025^3 solution injected onto the 129^3 grid against the oracle's 129^3 solve of
+    the same continuous right-hand side, and both against the continuous solution."""
+    import numpy as np
+
+    import oracle
+    from paper_2008_03885_amd import inputs
+    n, nco = w["n"], 129
+    stride = (n - 1) // (nco - 1)
+    f129 = inputs.smooth_sine_3d(nco)
+    m = oracle.Multigrid(3, nco, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"])
+    u129 = np.zeros_like(f129)
+    cycles, hist = m.solve(u129, f129, rtol=1e-10, max_cycles=60)
+    m.close()
+    k2 = inputs.wavenumber_sq(coeffs.shape[0], 3)
+    exact = inputs.sine_series(nco, coeffs / (np.pi ** 2 * k2))
+    inj = ud_host[::stride, ::stride, ::stride]
+    nrm = np.linalg.norm(u129)
+    return {
+        "oracle_129_cycles": int(cycles), "oracle_129_rel_residual": float(hist[-1]),
+        "rel_diff_gpu1025_vs_oracle129": float(np.linalg.norm(inj - u129) / nrm),
+        "rel_err_oracle129_vs_continuous": float(np.linalg.norm(u129 - exact) / nrm),
+        "rel_err_gpu1025_vs_continuous": float(np.linalg.norm(inj - exact) / nrm),
+    }
+
+
+def pmc_probe(w, run, stream):
+    """A plain copy of known size, then the dominant kernel, for hardware counters."""
+    import torch
+    a = torch.ones(256 * 1024 * 1024, device="cuda", dtype=torch.float64)  # 2 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    rows = level_kernels(run, w, stream, 5, only_level0=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8,
+                      "kernels": rows}), flush=True)
+
+
+SERVE_BUDGET = 32 << 30
+
+
+def serve_bench(count, loads=(0.5, 0.8)):
+    """Continuous-batching server on a Poisson stream of 2D solves, n = 2^k + 1 with k
+    uniform on 6..11, Fourier right-hand sides (k <= min(64, (n-1)/4)), mixed precision
+    V(2,1) to 1e-10.  First all requests at once (saturated throughput), then open-loop
+    Poisson arrivals at fractions of that rate; latency = completion - scheduled arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03885_amd import inputs, mg, serve
+    base = dict(dim=2, coarse=0, gamma=1, nu1=2, nu2=1, precision=mg.MG_PREC_MIXED, rtol=1e-10,
+                max_cycles=30, inner_cycles=4)
+    stream = inputs.request_stream(count, 1.0)
+    fs = {}
+    reqs = []
+    for i, (t, n, seed) in enumerate(stream):
+        f = torch.from_numpy(inputs.fourier_rhs(n, 2, min(64, (n - 1) // 4), seed=seed)).cuda()
+        reqs.append((i, n, f, torch.empty_like(f), t))
+        fs.setdefault(n, f)
+    torch.cuda.synchronize()
+    unknowns = sum((n - 2) ** 2 for _, n, _, _, _ in reqs)
+    S = serve.Server(SERVE_BUDGET, 16, 2, n=65, **base)
+    try:
+        # warm-up: one request per size creates every batch and captures its graph
+        warm = [(10 ** 6 + n, f, torch.empty_like(f)) for n, f in sorted(fs.items())]
+        for tag, f, u in warm:
+            S.submit(tag, f, u)
+        S.wait_all(len(warm), 120.0)
+
+        def run(arrivals):
+            t0 = time.monotonic()
+            got, i = [], 0
+            while len(got) < len(reqs):
+                now = time.monotonic() - t0
+                while i < len(reqs) and arrivals[i] <= now:
+                    tag, n, f, u, _ = reqs[i]
+                    if S.submit(tag, f, u) != mg.MG_OK:
+                        raise RuntimeError("submit failed")
+                    i += 1
+                wait = (arrivals[i] - now) if i < len(reqs) else 0.01
+                got += S.poll(256, max(0.0, min(wait, 0.002)))
+            end = max(c.t_done for c in got)
+            lat = np.array([c.t_done - (t0 + arrivals[c.tag]) for c in got])
+            bad = [c.tag for c in got if c.status != mg.MG_OK or c.result.rel_residual > 1e-10]
+            return end - t0, lat, bad
+
+        span, lat_sat, bad = run([0.0] * len(reqs))
+        rate_sat = len(reqs) / span
+        out = {
+            "requests": len(reqs), "sizes": "2^k+1, k~U{6..11}", "precision": "mixed",
+            "saturated": {"requests_per_s": rate_sat, "unknowns_per_s": unknowns / span,
+                          "makespan_s": span, "p50_ms": float(np.percentile(lat_sat, 50) * 1e3),
+                          "p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
+            "not_converged": bad,
+        }
+        gaps = np.array([t for *_, t in reqs])
+        for load in loads:
+            arrivals = list(gaps / (load * rate_sat))
+            span, lat, bad2 = run(arrivals)
+            out["load_%.2f" % load] = {
+                "offered_requests_per_s": load * rate_sat, "requests_per_s": len(reqs) / span,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+            out["not_converged"] += bad2
+        st = S.stats()
+        out["peak_active"] = st["peak_active"]
+        out["batches"] = st["batches_created"]
+        out["peak_hbm_bytes"] = st["peak_bytes_held"]
+        out["hbm_budget"] = SERVE_BUDGET
+        return out
+    finally:
+        S.close()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
 
-    from paper_2008_03885_amd import inputs, mg
-
+    w = dict(WORKLOADS[args.workload])
+    for k in ("n", "coarse", "gamma", "precision", "compare"):
+        if getattr(args, k) is not None:
+            w[k] = getattr(args, k)
     torch.cuda.set_device(0)
-    n = args.n
-    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
-    fd = torch.from_numpy(f).cuda()
-    ud = torch.zeros_like(fd)
     stream = torch.cuda.current_stream()
-    cfg = mg.make_config(dim=2, n=n, coarse=args.coarse, gamma=args.gamma, nu1=2, nu2=1,
-                         precision=args.precision, rtol=1e-10, max_cycles=60, inner_cycles=4)
-    h = mg.mg_setup(cfg, stream.cuda_stream)
+    if args.serve_only:
+        print(json.dumps({"serving": serve_bench(max(args.serve_requests, 1))}), flush=True)
+        return
+    f, coeffs = make_rhs(w)
+    fd = torch.from_numpy(f).cuda()
+    del f
+    d, n = w["dim"], w["n"]
+    unknowns = (n - 2) ** d
 
-    def step():
-        ud.zero_()
-        return mg.mg_solve(h, fd.data_ptr(), ud.data_ptr())
+    main_run = Run(w, w["precision"], fd, stream)
+    if args.pmc_probe:
+        pmc_probe(w, main_run, stream)
+        main_run.close()
+        return
+    sec, (status, res) = main_run.timed(args.steps, args.warmup)
+    ms = 1e3 * sec
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    status, res = results[-1]
-    ms = 1e3 * elapsed / args.steps
-    unknowns = (n - 2) ** 2
+    compare = None
+    fp64_cycles = res.cycles if w["precision"] == 0 else None
+    if w["compare"]:
+        other = Run(w, 1 - w["precision"], fd, stream)
+        osec, (ostatus, ores) = other.timed(max(1, args.steps // 2), 1)
+        u64, umx = (main_run.ud, other.ud) if w["precision"] == 0 else (other.ud, main_run.ud)
+        rel = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+        r64, rmx = (res, ores) if w["precision"] == 0 else (ores, res)
+        s64, smx = (sec, osec) if w["precision"] == 0 else (osec, sec)
+        fp64_cycles = r64.cycles
+        compare = {
+            "fp64": {"ms": s64 * 1e3, "unknowns_per_s": unknowns / s64, "cycles": r64.cycles,
+                     "rel_residual": r64.rel_residual, "floor_hit": bool(r64.floor_hit)},
+            "mixed": {"ms": smx * 1e3, "unknowns_per_s": unknowns / smx, "outer_steps": rmx.outer_steps,
+                      "fp32_cycles": rmx.cycles, "inner_cycles": w["inner"],
+                      "rel_residual": rmx.rel_residual, "floor_hit": bool(rmx.floor_hit)},
+            "mixed_speedup": s64 / smx,
+            "rel_diff_mixed_vs_fp64": rel,
+        }
+        other.close()
 
-    # Dominant kernel: the level-0 omega-Jacobi sweep, same launch as inside the cycle.
-    tmp = torch.empty_like(fd)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(5):
-        mg.mg_kernel_smooth(h, 0, 0, fd.data_ptr(), ud.data_ptr(), tmp.data_ptr())
-    ev0.record(stream)
-    for _ in range(args.kernel_reps):
-        mg.mg_kernel_smooth(h, 0, 0, fd.data_ptr(), ud.data_ptr(), tmp.data_ptr())
-    ev1.record(stream)
-    ev1.synchronize()
-    sweep_s = ev0.elapsed_time(ev1) / 1e3 / args.kernel_reps
-    sweep_bytes = 3 * n * n * 8  # read u, f; write u' (FP64)
-    achieved = sweep_bytes / sweep_s / 1e9
+    extra = None
+    if w.get("check129"):
+        extra = error_vs_129(main_run.ud.cpu().numpy(), w, coeffs)
 
+    rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
+    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
+    dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
+    if not dom:
+        dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
+               if r["kernel"] == dom_name]
+    dom = dom[0]
+    src = "fused2d.hip" if d == 2 else "kernels3d.hip"
+    key = "%s/%s/%s/%d" % (dom_name, "f32" if w["precision"] else "f64", src, n)
+    tr = MEASURED_TRAFFIC.get(key)
+    traffic = tr["bytes"] if tr and tr["source"] == source_hash(src) else None
+
+    cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual (mixed vs FP64) + smoother HBM GB/s; p99 lat",
-        "value": unknowns / (ms / 1e3),
+        "value": unknowns / sec,
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -128,33 +436,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32-in-f64",
+        "dtype": "f64" if w["precision"] == 0 else "f32-in-f64",
         "data": "synthetic",
         "config": {
-            "workload": "2D 4th-order Poisson %dx%d, Fourier RHS k<=64, V(2,1) omega-Jacobi, FW + cubic, "
-                        "%s coarse ops to 9x9, FP64, to 1e-10" % (n, n, "Galerkin" if args.coarse else "rediscretized"),
-            "n": n, "unknowns": unknowns, "cycle": "W(2,1)" if args.gamma == 2 else "V(2,1)",
-            "coarse": "galerkin" if args.coarse else "rediscretized",
-            "precision": "fp64" if args.precision == 0 else "mixed",
+            "workload": describe(w), "name": args.workload, "dim": d, "n": n, "unknowns": unknowns,
+            "cycle": cyc, "coarse": "galerkin" if w["coarse"] else "rediscretized",
+            "precision": "fp64" if w["precision"] == 0 else "mixed",
             "cycles": res.cycles, "outer_steps": res.outer_steps,
             "final_rel_residual": res.rel_residual, "floor_hit": bool(res.floor_hit),
             "status": status,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep2d (level-0 omega-Jacobi, FP64)",
-            "achieved": achieved,
+            "kernel": "%s level 0 (%s, %s)" % (dom_name, dom["op"], "FP32" if w["precision"] else "FP64"),
+            "achieved": dom["GB/s"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_launch_us": sweep_s * 1e6,
-            "algorithmic_bytes_per_launch": sweep_bytes,
+            "frac": dom["GB/s"] / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_launch_us": dom["us"],
+            "algorithmic_bytes_per_launch": dom["bytes"],
         },
     }
-    mg.mg_destroy(h)
+    if compare:
+        out["precision_compare"] = compare
+    if extra:
+        out["error_vs_oracle_129"] = extra
+    if rows:
+        out["levels"] = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
+                         for r in rows]
+    main_run.close()
+    if args.serve_requests > 0 and args.workload == "poisson2d-4097":
+        del fd
+        out["serving"] = serve_bench(args.serve_requests)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, max(res.cycles, 1))
+        out["cpu_baseline"] = cpu_baseline(w, max(fp64_cycles or res.cycles, 1))
     print(json.dumps(out), flush=True)
 
 

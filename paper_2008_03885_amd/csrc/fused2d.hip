@@ -172,7 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   constexpr int W = 2 * R + 1;
   constexpr int FQ = NU * R + 1;
   __shared__ T lrow[kWavesPerBlock][2][kRowLen];
+  a.done = slot_done(a.done);
   if (stopped(a.done)) return;
+  {
+    const size_t ps = (size_t)a.n * a.n, ncs = (size_t)((a.n - 1) / 2 + 1);
+    a.f = slot_ptr(a.f, ps);
+    a.u = slot_ptr(a.u, ps);
+    a.uout = slot_ptr(a.uout, ps);
+    a.rout = slot_ptr(a.rout, ps);
+    a.fc = slot_ptr(a.fc, ncs * ncs);
+    a.partials = slot_ptr(a.partials, (size_t)gridDim.x * gridDim.y);
+  }
   const int n = a.n;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
@@ -320,8 +330,13 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
   constexpr int W = 2 * R + 1;
   constexpr int FQ = NU2 > 0 ? (NU2 - 1) * R + 1 : 1;
   __shared__ T lrow[kWavesPerBlock][2][kRowLen];
+  a.done = slot_done(a.done);
   if (stopped(a.done)) return;
   const int n = a.n, nc = (n - 1) / 2 + 1;
+  a.v = slot_ptr(a.v, (size_t)nc * nc);
+  a.uin = slot_ptr(a.uin, (size_t)n * n);
+  a.f = slot_ptr(a.f, (size_t)n * n);
+  a.uout = slot_ptr(a.uout, (size_t)n * n);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   const int strip = blockIdx.x * kWavesPerBlock + wv;
@@ -455,7 +470,7 @@ int pre_geometry(int n, int S, bool restrict_mode, int *chunk, dim3 *grid) {
   const int c = clampi((long)rows_total * bx / target_blocks, restrict_mode ? 8 : 16,
                        restrict_mode ? 64 : 128);
   *chunk = c;
-  *grid = dim3(bx, cdiv(rows_total, c));
+  *grid = dim3(bx, cdiv(rows_total, c), grid->z);
   return bx * grid->y;
 }
 
@@ -520,7 +535,7 @@ int pre2d_partials(int n) {
 template <typename T>
 hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                         T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s) {
+                        const int *done, hipStream_t s, int slots) {
   const int R = op.cross ? 2 : 3;
   const bool restrict_mode = (mode & kRestrict) != 0;
   const bool res = restrict_mode || (mode & kWriteR) != 0;
@@ -529,7 +544,7 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
   const int S = kWave - 2 * H;
   if (S <= 0 || nu < 0 || nu > 3) return hipErrorInvalidValue;
   PreArgs<T> args{f, u, uout, rout, fc, n, 0, to_kop<T>(op, omega), partials, done};
-  dim3 grid;
+  dim3 grid(1, 1, slots);
   const int nb = pre_geometry(n, S, restrict_mode, &args.chunk, &grid);
   if (nparts) *nparts = nb;
 #define MG_PRE(RR)                                                                        \
@@ -548,7 +563,7 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
 template <typename T>
 hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                          const T *uin, const T *f, T *uout, int n, const int *done,
-                         hipStream_t s) {
+                         hipStream_t s, int slots) {
   const int R = op.cross ? 2 : 3;
   if (nu2 < 0 || nu2 > 2) return hipErrorInvalidValue;
   const int H = nu2 * R;
@@ -557,22 +572,22 @@ hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, 
   const int strips = cdiv(n, S);
   const int bx = cdiv(strips, kWavesPerBlock);
   args.chunk = clampi((long)n * bx / 1024, 16, 128);
-  const dim3 grid(bx, cdiv(n, args.chunk));
+  const dim3 grid(bx, cdiv(n, args.chunk), slots);
   if (R == 2) return post_nu<T, 2>(nu2, prolong, args, grid, s);
   return post_nu<T, 3>(nu2, prolong, args, grid, s);
 }
 
 template hipError_t launch_pre2d<double>(const LevelOp &, double, int, int, const double *,
                                          const double *, double *, double *, double *, int,
-                                         double *, int *, const int *, hipStream_t);
+                                         double *, int *, const int *, hipStream_t, int);
 template hipError_t launch_pre2d<float>(const LevelOp &, double, int, int, const float *,
                                         const float *, float *, float *, float *, int, double *,
-                                        int *, const int *, hipStream_t);
+                                        int *, const int *, hipStream_t, int);
 template hipError_t launch_post2d<double>(const LevelOp &, double, int, int, const double *,
                                           const double *, const double *, double *, int,
-                                          const int *, hipStream_t);
+                                          const int *, hipStream_t, int);
 template hipError_t launch_post2d<float>(const LevelOp &, double, int, int, const float *,
                                          const float *, const float *, float *, int, const int *,
-                                         hipStream_t);
+                                         hipStream_t, int);
 
 }  // namespace mgk

@@ -51,7 +51,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(const T *__restrict__ f,
   constexpr int W = 2 * R + 1;
   constexpr int NP = CROSS ? 1 : 2;
   __shared__ T pub[2][NP][kBlock];
+  done = slot_done(done);
   if (stopped(done)) return;
+  f = slot_ptr(f, (size_t)n * n);
+  u = slot_ptr(u, (size_t)n * n);
+  out = slot_ptr(out, (size_t)n * n);
+  partials = slot_ptr(partials, (size_t)gridDim.x * gridDim.y);
   const int t = threadIdx.x;
   const int x = blockIdx.x * (kBlock - 2 * R) - R + t;
   const int y0 = blockIdx.y * rows;
@@ -148,8 +153,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict2d(const T *__restrict
   constexpr int CB = (kBlock - 2 * R - 2) / 2;
   __shared__ T pub[2][NP][kBlock];
   __shared__ T rrow[kBlock];
+  done = slot_done(done);
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
+  f = slot_ptr(f, (size_t)n * n);
+  u = slot_ptr(u, (size_t)n * n);
+  fc = slot_ptr(fc, (size_t)nc * nc);
   const int t = threadIdx.x;
   const int x = 2 * blockIdx.x * CB - (R + 1) + t;
   int sx = 1;
@@ -251,8 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong2d(const T *__restrict__ v,
                                                       const int *__restrict__ done) {
   constexpr int NCOL = kBlock / 2 + 4;
   __shared__ T crow[2][NCOL];
+  done = slot_done(done);
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
+  v = slot_ptr(v, (size_t)nc * nc);
+  uin = slot_ptr(uin, (size_t)n * n);
+  uout = slot_ptr(uout, (size_t)n * n);
   const int t = threadIdx.x;
   const int xb = blockIdx.x * kBlock;
   const int x = xb + t;
@@ -328,7 +341,11 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double *__restrict__ 
                                                      T *__restrict__ v, int nc, int dim,
                                                      const int *__restrict__ done) {
   extern __shared__ double gs[];
+  done = slot_done(done);
   if (stopped(done)) return;
+  const size_t per = dim == 2 ? (size_t)nc * nc : (size_t)nc * nc * nc;
+  g = slot_ptr(g, per);
+  v = slot_ptr(v, per);
   const int q = nc - 2;
   const int m = dim == 2 ? q * q : q * q * q;
   for (int p = threadIdx.x; p < m; p += kBlock) {
@@ -356,6 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double *__restrict__ 
 // relative residual of the latest pass into the history and the stopping decision.
 __global__ __launch_bounds__(kBlock) void k_check(DevState *st, const double *__restrict__ partials,
                                                   int np, int record) {
+  st += blockIdx.z;
+  partials += (size_t)blockIdx.z * np;
   if (record && st->done) return;
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += kBlock) s += partials[i];
@@ -397,7 +416,10 @@ __global__ __launch_bounds__(kBlock) void k_check(DevState *st, const double *__
 __global__ __launch_bounds__(kBlock) void k_ir_correct(double *__restrict__ u,
                                                        const float *__restrict__ e, size_t total,
                                                        const int *__restrict__ done) {
+  done = slot_done(done);
   if (stopped(done)) return;
+  u = slot_ptr(u, total);
+  e = slot_ptr(e, total);
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
        i += (size_t)gridDim.x * kBlock)
     u[i] += (double)e[i];
@@ -406,7 +428,9 @@ __global__ __launch_bounds__(kBlock) void k_ir_correct(double *__restrict__ u,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ p, size_t count, T value,
                                                  const int *__restrict__ done) {
+  done = slot_done(done);
   if (stopped(done)) return;
+  p = slot_ptr(p, count);
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count;
        i += (size_t)gridDim.x * kBlock)
     p[i] = value;
@@ -452,12 +476,15 @@ int sweep_partials(int dim, int n) {
 template <typename T, typename TO>
 hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, const T *f,
                         const T *u, TO *out, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s) {
-  if (dim == 3) return launch_sweep_3d<T, TO>(mode, op, omega, f, u, out, n, partials, nparts, done, s);
+                        const int *done, hipStream_t s, int slots) {
+  if (dim == 3) {
+    if (slots != 1) return hipErrorInvalidValue;
+    return launch_sweep_3d<T, TO>(mode, op, omega, f, u, out, n, partials, nparts, done, s);
+  }
   const int R = op.cross ? 2 : 3;
   const int nbx = cdiv(n, kBlock - 2 * R);
   const int rows = strip_rows(n, nbx, 4, 32);
-  const dim3 grid(nbx, cdiv(n, rows));
+  const dim3 grid(nbx, cdiv(n, rows), slots);
   if (nparts) *nparts = grid.x * grid.y;
   const KOp<T> k = to_kop<T>(op, omega);
 #define MG_SWEEP2D(MODE, CROSS) \
@@ -477,14 +504,17 @@ hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, cons
 
 template <typename T>
 hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T *u, T *fc,
-                                 int n, const int *done, hipStream_t s) {
-  if (dim == 3) return launch_resid_restrict_3d<T>(op, f, u, fc, n, done, s);
+                                 int n, const int *done, hipStream_t s, int slots) {
+  if (dim == 3) {
+    if (slots != 1) return hipErrorInvalidValue;
+    return launch_resid_restrict_3d<T>(op, f, u, fc, n, done, s);
+  }
   const int nc = (n - 1) / 2 + 1;
   const int R = op.cross ? 2 : 3;
   const int CB = (kBlock - 2 * R - 2) / 2;
   const int nbx = cdiv(nc, CB);
   const int crows = strip_rows(nc, nbx, 2, 16);
-  const dim3 grid(nbx, cdiv(nc, crows));
+  const dim3 grid(nbx, cdiv(nc, crows), slots);
   const KOp<T> k = to_kop<T>(op, 1.0);
   if (op.cross)
     hipLaunchKernelGGL((k_resid_restrict2d<T, true>), grid, dim3(kBlock), 0, s, f, u, fc, n, crows, k, done);
@@ -495,11 +525,14 @@ hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T
 
 template <typename T>
 hipError_t launch_prolong_correct(int dim, int prolong, const T *v, const T *uin, T *uout,
-                                  int n, const int *done, hipStream_t s) {
-  if (dim == 3) return launch_prolong_correct_3d<T>(prolong, v, uin, uout, n, done, s);
+                                  int n, const int *done, hipStream_t s, int slots) {
+  if (dim == 3) {
+    if (slots != 1) return hipErrorInvalidValue;
+    return launch_prolong_correct_3d<T>(prolong, v, uin, uout, n, done, s);
+  }
   const int nbx = cdiv(n, kBlock);
   const int rows = strip_rows(n, nbx, 4, 32);
-  const dim3 grid(nbx, cdiv(n, rows));
+  const dim3 grid(nbx, cdiv(n, rows), slots);
   if (prolong == 3)
     hipLaunchKernelGGL((k_prolong2d<T, 3>), grid, dim3(kBlock), 0, s, v, uin, uout, n, rows, done);
   else
@@ -509,59 +542,59 @@ hipError_t launch_prolong_correct(int dim, int prolong, const T *v, const T *uin
 
 template <typename T>
 hipError_t launch_coarsest(int dim, const double *ainv_t, const T *g, T *v, int nc,
-                           const int *done, hipStream_t s) {
+                           const int *done, hipStream_t s, int slots) {
   const int q = nc - 2;
   const int m = dim == 2 ? q * q : q * q * q;
-  hipLaunchKernelGGL((k_coarsest<T>), dim3(1), dim3(kBlock), sizeof(double) * m, s, ainv_t, g, v,
+  hipLaunchKernelGGL((k_coarsest<T>), dim3(1, 1, slots), dim3(kBlock), sizeof(double) * m, s, ainv_t, g, v,
                      nc, dim, done);
   return hipGetLastError();
 }
 
 hipError_t launch_check(DevState *st, const double *partials, int nparts, int record,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, st, partials, nparts, record);
+                        hipStream_t s, int slots) {
+  hipLaunchKernelGGL(k_check, dim3(1, 1, slots), dim3(kBlock), 0, s, st, partials, nparts, record);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_correct(int dim, double *u, const float *e, int n, const int *done,
-                             hipStream_t s) {
+                             hipStream_t s, int slots) {
   const size_t total = dim == 2 ? (size_t)n * n : (size_t)n * n * n;
   const int blocks = clampi(cdiv((long)total, kBlock), 1, 8192);
-  hipLaunchKernelGGL(k_ir_correct, dim3(blocks), dim3(kBlock), 0, s, u, e, total, done);
+  hipLaunchKernelGGL(k_ir_correct, dim3(blocks, 1, slots), dim3(kBlock), 0, s, u, e, total, done);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t s) {
+hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t s, int slots) {
   const int blocks = clampi(cdiv((long)count, kBlock), 1, 8192);
-  hipLaunchKernelGGL((k_fill<T>), dim3(blocks), dim3(kBlock), 0, s, p, count, value, done);
+  hipLaunchKernelGGL((k_fill<T>), dim3(blocks, 1, slots), dim3(kBlock), 0, s, p, count, value, done);
   return hipGetLastError();
 }
 
 // explicit instantiations
 template hipError_t launch_sweep<double, double>(int, int, const LevelOp &, double, const double *,
                                                  const double *, double *, int, double *, int *,
-                                                 const int *, hipStream_t);
+                                                 const int *, hipStream_t, int);
 template hipError_t launch_sweep<float, float>(int, int, const LevelOp &, double, const float *,
                                                const float *, float *, int, double *, int *,
-                                               const int *, hipStream_t);
+                                               const int *, hipStream_t, int);
 template hipError_t launch_sweep<double, float>(int, int, const LevelOp &, double, const double *,
                                                 const double *, float *, int, double *, int *,
-                                                const int *, hipStream_t);
+                                                const int *, hipStream_t, int);
 template hipError_t launch_resid_restrict<double>(int, const LevelOp &, const double *,
                                                   const double *, double *, int, const int *,
-                                                  hipStream_t);
+                                                  hipStream_t, int);
 template hipError_t launch_resid_restrict<float>(int, const LevelOp &, const float *, const float *,
-                                                 float *, int, const int *, hipStream_t);
+                                                 float *, int, const int *, hipStream_t, int);
 template hipError_t launch_prolong_correct<double>(int, int, const double *, const double *,
-                                                   double *, int, const int *, hipStream_t);
+                                                   double *, int, const int *, hipStream_t, int);
 template hipError_t launch_prolong_correct<float>(int, int, const float *, const float *, float *,
-                                                  int, const int *, hipStream_t);
+                                                  int, const int *, hipStream_t, int);
 template hipError_t launch_coarsest<double>(int, const double *, const double *, double *, int,
-                                            const int *, hipStream_t);
+                                            const int *, hipStream_t, int);
 template hipError_t launch_coarsest<float>(int, const double *, const float *, float *, int,
-                                           const int *, hipStream_t);
-template hipError_t launch_fill<double>(double *, size_t, double, const int *, hipStream_t);
-template hipError_t launch_fill<float>(float *, size_t, float, const int *, hipStream_t);
+                                           const int *, hipStream_t, int);
+template hipError_t launch_fill<double>(double *, size_t, double, const int *, hipStream_t, int);
+template hipError_t launch_fill<float>(float *, size_t, float, const int *, hipStream_t, int);
 
 }  // namespace mgk

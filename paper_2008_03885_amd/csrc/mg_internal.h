@@ -52,34 +52,51 @@ struct DevState {
 
 enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2 };
 
+// Batched launches.  grid.z indexes independent problems of one size ("slots"): every
+// per-problem array is dense [slot][points], partial sums are [slot][blocks of one slot]
+// and each slot has its own DevState, so slot k of a batched launch computes exactly
+// what an unbatched launch on slot k's arrays computes.  The 3D streaming kernels use
+// grid.z for plane chunks and are never batched.
+constexpr size_t kStateInts = sizeof(DevState) / sizeof(int);
+static_assert(sizeof(DevState) % sizeof(int) == 0, "DevState packs whole ints");
+__device__ __forceinline__ const int *slot_done(const int *done) {
+  return done == nullptr ? nullptr : done + (size_t)blockIdx.z * kStateInts;
+}
+template <typename P>
+__device__ __forceinline__ P *slot_ptr(P *p, size_t per_slot) {
+  return p == nullptr ? p : p + (size_t)blockIdx.z * per_slot;
+}
+
 // ---- launchers (kernels.hip) ----------------------------------------------------
 // All take the level side n, dense arrays, and an optional `done` flag.
 
 template <typename T, typename TO>
 hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, const T *f,
                         const T *u, TO *out, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s);
+                        const int *done, hipStream_t s, int slots = 1);
 
 template <typename T>
 hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T *u, T *fc,
-                                 int n, const int *done, hipStream_t s);
+                                 int n, const int *done, hipStream_t s, int slots = 1);
 
 template <typename T>
 hipError_t launch_prolong_correct(int dim, int prolong, const T *v, const T *uin, T *uout,
-                                  int n, const int *done, hipStream_t s);
+                                  int n, const int *done, hipStream_t s, int slots = 1);
 
 template <typename T>
 hipError_t launch_coarsest(int dim, const double *ainv_t, const T *g, T *v, int nc,
-                           const int *done, hipStream_t s);
+                           const int *done, hipStream_t s, int slots = 1);
 
+// nparts: partial sums per slot (slot k reads partials[k * nparts ...]).
 hipError_t launch_check(DevState *st, const double *partials, int nparts, int record,
-                        hipStream_t s);
+                        hipStream_t s, int slots = 1);
 
 hipError_t launch_ir_correct(int dim, double *u, const float *e, int n, const int *done,
-                             hipStream_t s);
+                             hipStream_t s, int slots = 1);
 
 template <typename T>
-hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t s);
+hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t s,
+                       int slots = 1);
 
 // Largest number of partial sums a level-0 sweep of side n produces.
 int sweep_partials(int dim, int n);
@@ -106,11 +123,11 @@ int pre2d_partials(int n);
 template <typename T>
 hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                         T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s);
+                        const int *done, hipStream_t s, int slots = 1);
 template <typename T>
 hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                          const T *uin, const T *f, T *uout, int n, const int *done,
-                         hipStream_t s);
+                         hipStream_t s, int slots = 1);
 
 // ---- LDS-resident tail (tail.hip) -------------------------------------------------
 constexpr int kMaxTailLevels = 8;
@@ -140,6 +157,7 @@ size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, si
 template <typename T>
 hipError_t tail_prepare(int dim, int G, size_t lds_bytes);
 template <typename T>
-hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s);
+hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s,
+                       int slots = 1);
 
 }  // namespace mgk

@@ -14,12 +14,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "mg.h"
 #include "mg_internal.h"
 
@@ -254,6 +256,8 @@ struct mg_ctx {
   double *ecoef = nullptr;
   std::vector<int> ent_begin, ent_count;
   int chunk = 4;
+  int slots = 1;         // independent problems of this size (batched launches, grid.z)
+  bool own_top = false;  // level-0 FP64 f and u are the handle's (batches), not the caller's
   std::vector<void *> allocs;
   size_t footprint = 0;
 };
@@ -287,8 +291,10 @@ size_t entries_bytes(const mg_config *cfg, int L) {
   return (size_t)L * per * (3 * sizeof(int) + sizeof(double));
 }
 
-size_t footprint_of(const mg_config *cfg, int L) {
-  size_t total = 0;
+// Device bytes of a handle: per-problem arrays times `slots`, plus the shared tables.
+// own_top: the handle also holds level-0 FP64 f and u (batches copy requests in).
+size_t footprint_of(const mg_config *cfg, int L, int slots = 1, bool own_top = false) {
+  size_t per = 0;
   int n = cfg->n;
   const size_t es = cfg->precision == MG_PREC_MIXED ? 4 : 8;
   const bool mixed = cfg->precision == MG_PREC_MIXED;
@@ -296,16 +302,15 @@ size_t footprint_of(const mg_config *cfg, int L) {
     const size_t np = points(cfg->dim, n);
     int arrays = (l > 0 || mixed) ? 2 : 0;  // u and f (level 0 FP64 uses the caller's)
     if (L > 1 && l < L - 1) arrays += 1;    // Jacobi target
-    total += arrays * np * es;
+    per += arrays * np * es;
+    if (l == 0 && own_top) per += 2 * np * 8;
     n = (n - 1) / 2 + 1;
   }
+  per += (size_t)partials_needed(cfg->dim, cfg->n) * 8;
+  per += sizeof(DevState);
   const int q = cfg->n_coarsest - 2;
   const size_t m = cfg->dim == 2 ? (size_t)q * q : (size_t)q * q * q;
-  total += m * m * 8;
-  total += (size_t)partials_needed(cfg->dim, cfg->n) * 8;
-  total += entries_bytes(cfg, L);
-  total += sizeof(DevState);
-  return total;
+  return per * (size_t)slots + m * m * 8 + entries_bytes(cfg, L);
 }
 
 // Ghost width of a tail starting at level l: 1 if every tail level is the cross.
@@ -357,7 +362,7 @@ hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const
   a.done = done;
   a.ent_first = c->ent_begin[l];
   a.ent_total = tail_entries(c, l);
-  return mgk::launch_tail<T>(c->dim, G, a, tail_bytes(c, l, sizeof(T)), s);
+  return mgk::launch_tail<T>(c->dim, G, a, tail_bytes(c, l, sizeof(T)), s, c->slots);
 }
 
 template <typename T>
@@ -372,9 +377,9 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     if (check) {
       int np = 0;
       e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero_u ? nullptr : u,
-                                  (T *)nullptr, n, c->partials, &np, done, s);
+                                  (T *)nullptr, n, c->partials, &np, done, s, c->slots);
       if (e != hipSuccess) return e;
-      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
       if (e != hipSuccess) return e;
     }
     return launch_tail_at<T>(c, l, u, f, zero_u, done, s);
@@ -386,10 +391,10 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     int np = 0;
     e = mgk::launch_pre2d<T>(op, c->omega, c->cfg.nu1, mgk::kPreWriteU | mgk::kPreRestrict, f,
                              zero_u ? nullptr : u, t, nullptr, fc, n,
-                             check ? c->partials : nullptr, &np, done, s);
+                             check ? c->partials : nullptr, &np, done, s, c->slots);
     if (e != hipSuccess) return e;
     if (check) {
-      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
       if (e != hipSuccess) return e;
     }
     if (l + 1 >= c->tail_top) {
@@ -398,7 +403,7 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
         if (e != hipSuccess) return e;
       }
     } else if (l + 1 == c->L - 1) {
-      e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s);
+      e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
       if (e != hipSuccess) return e;
     } else {
       for (int g = 0; g < c->cfg.gamma; ++g) {
@@ -406,18 +411,18 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
         if (e != hipSuccess) return e;
       }
     }
-    return mgk::launch_post2d<T>(op, c->omega, c->cfg.nu2, c->cfg.prolong, uc, t, f, u, n, done, s);
+    return mgk::launch_post2d<T>(op, c->omega, c->cfg.nu2, c->cfg.prolong, uc, t, f, u, n, done, s, c->slots);
   }
   if (c->L == 1) {  // a single level: the exact solve is the whole cycle
     if (check) {
       int np = 0;
       e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero_u ? nullptr : u,
-                                  (T *)nullptr, n, c->partials, &np, done, s);
+                                  (T *)nullptr, n, c->partials, &np, done, s, c->slots);
       if (e != hipSuccess) return e;
-      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
       if (e != hipSuccess) return e;
     }
-    return mgk::launch_coarsest<T>(dim, c->ainv_t, f, u, n, done, s);
+    return mgk::launch_coarsest<T>(dim, c->ainv_t, f, u, n, done, s, c->slots);
   }
   T *t = (T *)B[l].t;
   T *cur = u, *other = t;
@@ -425,13 +430,13 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   if (check && c->cfg.nu1 == 0) {
     int np = 0;
     e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero ? nullptr : u,
-                                (T *)nullptr, n, c->partials, &np, done, s);
+                                (T *)nullptr, n, c->partials, &np, done, s, c->slots);
     if (e != hipSuccess) return e;
-    e = mgk::launch_check(c->st, c->partials, np, 1, s);
+    e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
     if (e != hipSuccess) return e;
   }
   if (zero && c->cfg.nu1 == 0) {
-    e = mgk::launch_fill<T>(u, points(dim, n), T(0), done, s);
+    e = mgk::launch_fill<T>(u, points(dim, n), T(0), done, s, c->slots);
     if (e != hipSuccess) return e;
     zero = false;
   }
@@ -439,10 +444,10 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     const bool first_check = check && k == 0;
     int np = 0;
     e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
-                                first_check ? c->partials : nullptr, &np, done, s);
+                                first_check ? c->partials : nullptr, &np, done, s, c->slots);
     if (e != hipSuccess) return e;
     if (first_check) {
-      e = mgk::launch_check(c->st, c->partials, np, 1, s);
+      e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
       if (e != hipSuccess) return e;
     }
     zero = false;
@@ -450,10 +455,10 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   }
   T *uc = (T *)B[l + 1].u;
   T *fc = (T *)B[l + 1].f;
-  e = mgk::launch_resid_restrict<T>(dim, op, f, cur, fc, n, done, s);
+  e = mgk::launch_resid_restrict<T>(dim, op, f, cur, fc, n, done, s, c->slots);
   if (e != hipSuccess) return e;
   if (l + 1 == c->L - 1 && l + 1 < c->tail_top) {
-    e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s);
+    e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
     if (e != hipSuccess) return e;
   } else {
     for (int g = 0; g < c->cfg.gamma; ++g) {
@@ -462,13 +467,13 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     }
   }
   T *dst = (c->cfg.nu2 % 2 == 0) ? u : t;
-  e = mgk::launch_prolong_correct<T>(dim, c->cfg.prolong, uc, cur, dst, n, done, s);
+  e = mgk::launch_prolong_correct<T>(dim, c->cfg.prolong, uc, cur, dst, n, done, s, c->slots);
   if (e != hipSuccess) return e;
   cur = dst;
   other = (dst == u) ? t : u;
   for (int k = 0; k < c->cfg.nu2; ++k) {
     e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
-                                done, s);
+                                done, s, c->slots);
     if (e != hipSuccess) return e;
     std::swap(cur, other);
   }
@@ -483,15 +488,15 @@ hipError_t record_step(mg_ctx *c, const double *f, double *u, hipStream_t s) {
   float *r32 = (float *)c->b32[0].f;
   float *e32 = (float *)c->b32[0].u;
   hipError_t e = mgk::launch_sweep<double, float>(c->dim, mgk::kResidual, c->ops[0], c->omega, f, u,
-                                                  r32, c->ns[0], c->partials, &np, done, s);
+                                                  r32, c->ns[0], c->partials, &np, done, s, c->slots);
   if (e != hipSuccess) return e;
-  e = mgk::launch_check(c->st, c->partials, np, 1, s);
+  e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
   if (e != hipSuccess) return e;
   for (int i = 0; i < c->cfg.inner_cycles; ++i) {
     e = cycle<float>(c, c->b32, 0, e32, r32, i == 0, false, s);
     if (e != hipSuccess) return e;
   }
-  return mgk::launch_ir_correct(c->dim, u, e32, c->ns[0], done, s);
+  return mgk::launch_ir_correct(c->dim, u, e32, c->ns[0], done, s, c->slots);
 }
 
 mg_status ensure_graph(mg_ctx *c, const double *f, double *u) {
@@ -548,10 +553,7 @@ mg_status begin_solve(mg_ctx *c, const double *f, double *u, double rtol, int ma
   return MG_OK;
 }
 
-mg_status fill_result(mg_ctx *c, mg_result *res, mg_status *outcome) {
-  DevState hs;
-  MG_HIP(hipMemcpyAsync(&hs, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-  MG_HIP(hipStreamSynchronize(c->stream));
+void result_from_state(const mg_ctx *c, const DevState &hs, mg_result *res, mg_status *outcome) {
   const int checks = std::min(hs.checks, mgk::kMaxHistory);
   const double final_rel = checks > 0 ? hs.hist[checks - 1] : 0.0;
   if (res) {
@@ -576,6 +578,13 @@ mg_status fill_result(mg_ctx *c, mg_result *res, mg_status *outcome) {
     case 4: *outcome = MG_ENUMERIC; break;
     default: *outcome = MG_ENOCONV; break;
   }
+}
+
+mg_status fill_result(mg_ctx *c, mg_result *res, mg_status *outcome) {
+  DevState hs;
+  MG_HIP(hipMemcpyAsync(&hs, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  result_from_state(c, hs, res, outcome);
   return MG_OK;
 }
 
@@ -646,14 +655,19 @@ mg_status mg_destroy(mg_handle h) {
   return MG_OK;
 }
 
-mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
-  if (!out) return fail(MG_EINVAL, "null output handle");
+namespace {
+
+// Builds a handle for `slots` independent problems of the configured size.
+mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_top, mg_ctx **out) {
   *out = nullptr;
   int L = 0;
   mg_status st = validate(cfg, &L);
   if (st != MG_OK) return st;
+  if (slots < 1 || (slots > 1 && cfg->dim != 2)) return fail(MG_EINVAL, "batches are 2D only");
   mg_ctx *c = new mg_ctx();
   c->cfg = *cfg;
+  c->slots = slots;
+  c->own_top = own_top;
   c->dim = cfg->dim;
   c->L = L;
   c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order);
@@ -687,7 +701,12 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
   c->b64.resize(L);
   c->b32.resize(L);
   for (int l = 0; l < L; ++l) {
-    const size_t np = points(c->dim, c->ns[l]);
+    const size_t np = points(c->dim, c->ns[l]) * (size_t)slots;
+    if (l == 0 && own_top) {
+      Buffers &b = c->b64[0];
+      if ((st = dev_alloc(c, &b.u, np * 8)) != MG_OK) return bail(st);
+      if ((st = dev_alloc(c, &b.f, np * 8)) != MG_OK) return bail(st);
+    }
     if (!mixed) {
       Buffers &b = c->b64[l];
       if (l > 0) {
@@ -763,12 +782,19 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
     if (e != hipSuccess) return bail(fail(MG_EDEVICE, std::string("3D kernel setup: ") + hipGetErrorString(e)));
   }
   c->np_max = partials_needed(c->dim, cfg->n);
-  if ((st = dev_alloc(c, (void **)&c->partials, (size_t)c->np_max * 8)) != MG_OK) return bail(st);
-  if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState))) != MG_OK) return bail(st);
+  if ((st = dev_alloc(c, (void **)&c->partials, (size_t)c->np_max * 8 * slots)) != MG_OK) return bail(st);
+  if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState) * slots)) != MG_OK) return bail(st);
   if (hipMemcpy(c->ainv_t, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(MG_EDEVICE, "upload of the coarsest inverse failed"));
-  if (hipMemset(c->st, 0, sizeof(DevState)) != hipSuccess)
-    return bail(fail(MG_EDEVICE, "hipMemset failed"));
+  {
+    // slots of a batch start parked (done = 1) until a problem is admitted
+    std::vector<DevState> init(slots);
+    std::memset(init.data(), 0, sizeof(DevState) * slots);
+    if (slots > 1)
+      for (auto &d : init) d.done = 1;
+    if (hipMemcpy(c->st, init.data(), sizeof(DevState) * slots, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(MG_EDEVICE, "upload of the solve state failed"));
+  }
   if (hipHostMalloc((void **)&c->poll, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return bail(fail(MG_ENOMEM, "pinned host allocation failed"));
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
@@ -780,6 +806,13 @@ mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
     return bail(fail(MG_EDEVICE, "event creation failed"));
   *out = c;
   return MG_OK;
+}
+
+}  // namespace
+
+mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out) {
+  if (!out) return fail(MG_EINVAL, "null output handle");
+  return setup_ctx(cfg, hip_stream, 1, false, out);
 }
 
 mg_status mg_solve(mg_handle h, const double *f, double *u, mg_result *res) {
@@ -1017,3 +1050,81 @@ mg_status mg_synchronize(mg_handle h) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches ----
+namespace mgb {
+
+static_assert(offsetof(DevState, done) == 0 && offsetof(DevState, checks) == 4 &&
+                  offsetof(DevState, status) == 8 && offsetof(DevState, stall) == 12,
+              "SlotFlags mirrors the leading fields of DevState");
+
+size_t footprint(const mg_config *cfg, int slots) {
+  int L = 0;
+  if (validate(cfg, &L) != MG_OK) return 0;
+  return footprint_of(cfg, L, slots, true);
+}
+
+mg_status create(const mg_config *cfg, int slots, hipStream_t stream, mg_ctx **out) {
+  mg_status st = setup_ctx(cfg, stream, slots, true, out);
+  if (st != MG_OK) return st;
+  mg_ctx *c = *out;
+  st = ensure_graph(c, (const double *)c->b64[0].f, (double *)c->b64[0].u);
+  if (st != MG_OK) {
+    mg_destroy(c);
+    *out = nullptr;
+  }
+  return st;
+}
+
+void destroy(mg_ctx *c) { mg_destroy(c); }
+
+mg_status admit(mg_ctx *c, int k, const double *f) {
+  if (k < 0 || k >= c->slots || !f) return fail(MG_EINVAL, "bad slot or buffer");
+  const size_t np = points(c->dim, c->ns[0]);
+  double *fk = (double *)c->b64[0].f + (size_t)k * np;
+  double *uk = (double *)c->b64[0].u + (size_t)k * np;
+  DevState *sk = c->st + k;
+  double *pk = c->partials + (size_t)k * c->np_max;
+  MG_HIP(hipMemcpyAsync(fk, f, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  MG_HIP(mgk::launch_fill<double>(uk, np, 0.0, nullptr, c->stream));
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, c->stream, sk, c->cfg.rtol,
+                     c->cfg.max_cycles + 1, 1);
+  MG_HIP(hipGetLastError());
+  int nparts = 0;
+  MG_HIP((mgk::launch_sweep<double, double>(c->dim, mgk::kNormOnly, c->ops[0], c->omega, fk,
+                                            nullptr, (double *)nullptr, c->ns[0], pk, &nparts,
+                                            nullptr, c->stream)));
+  MG_HIP(mgk::launch_check(sk, pk, nparts, 0, c->stream));
+  return MG_OK;
+}
+
+mg_status step(mg_ctx *c, int count) {
+  for (int i = 0; i < count; ++i) {
+    mg_status st = launch_step(c, (const double *)c->b64[0].f, (double *)c->b64[0].u);
+    if (st != MG_OK) return st;
+  }
+  return MG_OK;
+}
+
+mg_status read_flags(mg_ctx *c, SlotFlags *host) {
+  MG_HIP(hipMemcpy2DAsync(host, sizeof(SlotFlags), c->st, sizeof(DevState), sizeof(SlotFlags),
+                          c->slots, hipMemcpyDeviceToHost, c->stream));
+  return MG_OK;
+}
+
+mg_status retire(mg_ctx *c, int k, double *u_dst, DevState *host_state) {
+  if (k < 0 || k >= c->slots || !u_dst) return fail(MG_EINVAL, "bad slot or buffer");
+  const size_t np = points(c->dim, c->ns[0]);
+  const double *uk = (const double *)c->b64[0].u + (size_t)k * np;
+  MG_HIP(hipMemcpyAsync(u_dst, uk, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  MG_HIP(hipMemcpyAsync(host_state, c->st + k, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  return MG_OK;
+}
+
+void result(const mg_ctx *c, const DevState &hs, mg_result *res, mg_status *outcome) {
+  result_from_state(c, hs, res, outcome);
+}
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+}  // namespace mgb

@@ -285,7 +285,8 @@ template <typename T, int DIM, int G>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   extern __shared__ __align__(16) unsigned char tail_lds[];
   __shared__ LevelInfo lvt[kMaxTailLevels];
-  if (a.done != nullptr && *a.done != 0) return;
+  const int *done = slot_done(a.done);
+  if (done != nullptr && *done != 0) return;
   using TL = Tiling<DIM>;
   // level table: padded pitches and LDS offsets (u framed, f dense)
   if (threadIdx.x == 0) {
@@ -335,9 +336,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   c.tx = threadIdx.x % TL::TX;
   c.ty = (threadIdx.x / TL::TX) % TL::TY;
   c.tz = threadIdx.x / (TL::TX * TL::TY);
-  const T *fg = static_cast<const T *>(a.f_top);
-  T *ug = static_cast<T *>(a.u_top);
   const int n = lvt[0].n;
+  const size_t per = DIM == 3 ? (size_t)n * n * n : (size_t)n * n;
+  const T *fg = slot_ptr(static_cast<const T *>(a.f_top), per);
+  T *ug = slot_ptr(static_cast<T *>(a.u_top), per);
   c.each(n, [&](int i, int j, int k) {
     const int d = c.didx(0, i, j, k);
     lds[lvt[0].f + d] = fg[d];
@@ -389,21 +391,23 @@ hipError_t tail_prepare(int dim, int G, size_t lds_bytes) {
 }
 
 template <typename T>
-hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s,
+                       int slots) {
+  const dim3 grid(1, 1, slots);
   if (dim == 2 && G == 1)
-    hipLaunchKernelGGL((k_tail<T, 2, 1>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 2, 1>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else if (dim == 2)
-    hipLaunchKernelGGL((k_tail<T, 2, 2>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 2, 2>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else if (G == 1)
-    hipLaunchKernelGGL((k_tail<T, 3, 1>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 3, 1>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else
-    hipLaunchKernelGGL((k_tail<T, 3, 2>), dim3(1), dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 3, 2>), grid, dim3(kTailThreads), lds_bytes, s, args);
   return hipGetLastError();
 }
 
 template hipError_t tail_prepare<double>(int, int, size_t);
 template hipError_t tail_prepare<float>(int, int, size_t);
-template hipError_t launch_tail<double>(int, int, const TailArgs &, size_t, hipStream_t);
-template hipError_t launch_tail<float>(int, int, const TailArgs &, size_t, hipStream_t);
+template hipError_t launch_tail<double>(int, int, const TailArgs &, size_t, hipStream_t, int);
+template hipError_t launch_tail<float>(int, int, const TailArgs &, size_t, hipStream_t, int);
 
 }  // namespace mgk

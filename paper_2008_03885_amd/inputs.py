@@ -75,11 +75,17 @@ def smoothed_noise_3d(n, seed=SEED_BASE + 3, passes=3):
     return f
 
 
-def smooth_sine_3d(n, seed=SEED_BASE + 5, kmax=8):
+def smooth_sine_3d(n, seed=SEED_BASE + 5, kmax=8, return_coeffs=False):
     """Continuous smooth right-hand side sum_{k_a <= kmax} g_k prod sin(k_a pi x_a), g_k ~ N(0,1):
-    the same function at every resolution."""
+    the same function at every resolution.  With return_coeffs, also g (indexed [kz][ky][kx])."""
     g = generator(seed).standard_normal((kmax,) * 3)
-    return sine_series(n, g)
+    f = sine_series(n, g)
+    return (f, g) if return_coeffs else f
+
+
+def wavenumber_sq(kmax, dim):
+    """|k|^2 = sum_a k_a^2 on the grid of modes 1..kmax per axis (indexed like the coefficients)."""
+    return _wavenumber_sq(kmax, dim)
 
 
 def request_stream(count, rate, seed=SEED_BASE + 104, kmin=6, kmax=11):

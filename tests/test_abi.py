@@ -7,15 +7,19 @@ import re
 import pytest
 
 from conftest import ROOT
-from paper_2008_03885_amd import mg
+from paper_2008_03885_amd import mg, serve
 
 
 def _declared_functions():
     names = []
-    with open(os.path.join(ROOT, "include", "mg.h")) as fh:
-        text = fh.read()
-    for m in re.finditer(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(mg_[a-z0-9_]+)\s*\(", text, re.M):
-        names.append(m.group(1))
+    inc = os.path.join(ROOT, "include")
+    for hdr in sorted(os.listdir(inc)):
+        if not hdr.endswith(".h"):
+            continue
+        with open(os.path.join(inc, hdr)) as fh:
+            text = fh.read()
+        for m in re.finditer(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(mg_[a-z0-9_]+)\s*\(", text, re.M):
+            names.append(m.group(1))
     return sorted(set(names))
 
 
@@ -30,8 +34,8 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(mg.LIB_PATH)
     missing = [n for n in _declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    # the binding covers the same names
-    assert set(_declared_functions()) <= set(mg._SIGS)
+    # the bindings cover the same names
+    assert set(_declared_functions()) <= set(mg._SIGS) | set(serve._SIGS)
 
 
 @pytest.mark.parametrize("kwargs", [
@@ -69,3 +73,37 @@ def test_null_arguments_rejected():
     assert lib.mg_solve(None, None, None, None) == mg.MG_EINVAL
     assert lib.mg_destroy(None) == mg.MG_OK
     assert lib.mg_level_size(None, 0) == -1
+
+
+def test_batch_footprint_is_linear_in_slots():
+    """A batch holds per-problem arrays (level-0 f and u included) once per slot and the
+    shared tables once."""
+    base = mg.make_config(dim=2, n=65, precision=mg.MG_PREC_MIXED)
+    for n in (65, 129, 1025):
+        one, two, five = (serve.mg_serve_batch_bytes(base, n, k) for k in (1, 2, 5))
+        per = two - one
+        assert five == one + 4 * per
+        # at least the FP64 f, u and the FP32 u, f, r of the top level per slot
+        assert per >= n * n * (2 * 8 + 3 * 4)
+        assert per < n * n * (2 * 8 + 3 * 4) * 4 / 3 + 64 * 1024
+    assert serve.mg_serve_batch_bytes(base, 100, 1) == 0   # not 2^k + 1
+    assert serve.mg_serve_batch_bytes(base, 65, 0) == 0
+
+
+@pytest.mark.parametrize("change", [
+    dict(max_slots=0), dict(max_slots=2000), dict(chunk_steps=0), dict(hbm_budget=0),
+    dict(dim=3), dict(gamma=5),
+])
+def test_server_rejects_bad_configs(change):
+    """Configuration errors are found before any device call."""
+    kw = dict(hbm_budget=1 << 30, max_slots=8, chunk_steps=2)
+    base = dict(dim=2, n=65)
+    for k, v in change.items():
+        (kw if k in kw else base)[k] = v
+    cfg = serve.make_server_config(kw["hbm_budget"], kw["max_slots"], kw["chunk_steps"], **base)
+    h = ctypes.c_void_p()
+    assert serve.lib().mg_server_create(ctypes.byref(cfg), ctypes.byref(h)) == mg.MG_EINVAL
+    assert h.value is None
+    assert serve.lib().mg_server_submit(None, 0, 65, None, None) == mg.MG_EINVAL
+    assert serve.lib().mg_server_poll(None, None, 0, 0.0) == -1
+    assert serve.lib().mg_server_destroy(None) == mg.MG_OK

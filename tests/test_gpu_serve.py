@@ -1,0 +1,147 @@
+"""The solve server on the GPU: continuous batching of mixed-size 2D solves.
+
+Each request must come out exactly as a standalone handle solves it (same kernels, same
+per-slot reduction order), whatever else shares its batch or the device, and must
+reach the 1e-10 relative residual in FP64.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, torch
+from paper_2008_03885_amd import inputs, mg, serve
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(dim=2, coarse=0, gamma=1, nu1=2, nu2=1, precision=mg.MG_PREC_MIXED, rtol=1e-10,
+            max_cycles=30, inner_cycles=4)
+
+
+def _rhs(n, seed):
+    return inputs.fourier_rhs(n, 2, min(64, (n - 1) // 4), seed=seed)
+
+
+def _solo(n, f, **over):
+    """u and result of a standalone handle (mg_solve) for the same configuration."""
+    cfg = dict(BASE, **over)
+    h = mg.mg_setup(mg.make_config(n=n, **cfg), torch().cuda.current_stream().cuda_stream)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(h, fd.data_ptr(), ud.data_ptr())
+        return host(ud), st, res.hist()
+    finally:
+        mg.mg_destroy(h)
+
+
+def _serve(reqs, budget=8 << 30, max_slots=8, chunk_steps=2, stagger=None, **over):
+    """Runs (tag, n, f) requests through one server; returns {tag: (u, completion)}."""
+    import time
+    cfg = dict(BASE, **over)
+    S = serve.Server(budget, max_slots, chunk_steps, n=65, **cfg)
+    try:
+        bufs = {tag: (dev(f), dev(np.full_like(f, np.nan))) for tag, n, f in reqs}
+        torch().cuda.synchronize()  # the server reads f on its own streams
+        for i, (tag, n, f) in enumerate(reqs):
+            assert S.submit(tag, *bufs[tag]) == mg.MG_OK
+            if stagger:
+                time.sleep(stagger[i])
+        done = S.wait_all(len(reqs), 300.0)
+        stats = S.stats()
+        out = {c.tag: (host(bufs[c.tag][1]), c) for c in done}
+        return out, stats
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("precision", [mg.MG_PREC_MIXED, mg.MG_PREC_FP64])
+def test_single_request_equals_standalone_solve(precision):
+    n = 129
+    f = _rhs(n, inputs.SEED_BASE + 1000)
+    out, stats = _serve([(7, n, f)], precision=precision,
+                        max_cycles=30 if precision else 60)
+    u, c = out[7]
+    ref, st, hist = _solo(n, f, precision=precision, max_cycles=30 if precision else 60)
+    assert c.status == st == mg.MG_OK
+    assert np.array_equal(u, ref)
+    assert c.result.hist() == hist
+    assert c.result.rel_residual <= 1e-10
+    assert stats["completed"] == 1 and stats["batches_created"] == 1
+
+
+def test_results_identical_alone_and_in_the_mix():
+    """A stream of mixed sizes arriving while others run; the probe request (same n and
+    f) appears three times at different points of the stream.  Every request equals its
+    standalone solve bit for bit and reaches 1e-10."""
+    rng = np.random.default_rng(5)
+    sizes = [65, 129, 257, 513, 1025]
+    probe_n, probe_f = 257, _rhs(257, inputs.SEED_BASE + 1001)
+    reqs = []
+    for i in range(24):
+        if i in (0, 9, 20):
+            reqs.append((i, probe_n, probe_f))
+        else:
+            n = int(rng.choice(sizes))
+            reqs.append((i, n, _rhs(n, inputs.SEED_BASE + 1100 + i)))
+    stagger = list(rng.exponential(0.002, len(reqs)))
+    out, stats = _serve(reqs, stagger=stagger)
+    assert stats["completed"] == len(reqs)
+    assert stats["peak_active"] > 1          # requests overlapped on the device
+    solo = {}
+    for tag, n, f in reqs:
+        key = (n, tag) if tag not in (0, 9, 20) else (n, "probe")
+        if key not in solo:
+            solo[key] = _solo(n, f)
+        ref, st, hist = solo[key]
+        u, c = out[tag]
+        assert c.status == mg.MG_OK and st == mg.MG_OK, tag
+        assert np.array_equal(u, ref), tag
+        assert c.result.hist() == hist, tag
+        assert c.result.rel_residual <= 1e-10
+        assert c.t_submit <= c.t_admit <= c.t_done
+    a, b, d = out[0][0], out[9][0], out[20][0]
+    assert np.array_equal(a, b) and np.array_equal(a, d)
+
+
+def test_admission_by_footprint():
+    """A budget that holds one slot of 513^2: three such requests run one after another,
+    and a later 257^2 request gets memory by releasing the idle 513 batch."""
+    base = mg.make_config(n=65, **BASE)
+    one513 = serve.mg_serve_batch_bytes(base, 513, 1)
+    one257 = serve.mg_serve_batch_bytes(base, 257, 1)
+    budget = one513 + one257 // 2   # not a second 513 slot, nor a 257 batch beside it
+    assert budget < serve.mg_serve_batch_bytes(base, 513, 2)
+    reqs = [(i, 513, _rhs(513, inputs.SEED_BASE + 1200 + i)) for i in range(3)]
+    out, stats = _serve(reqs, budget=budget)
+    assert stats["peak_active"] == 1 and stats["completed"] == 3
+    assert stats["peak_bytes_held"] <= budget
+    for tag, n, f in reqs:
+        ref, _, _ = _solo(n, f)
+        assert np.array_equal(out[tag][0], ref)
+    # second server: a 513 request, then a 257 request that needs the 513 batch released
+    reqs2 = [(0, 513, reqs[0][2]), (1, 257, _rhs(257, inputs.SEED_BASE + 1300))]
+    out2, stats2 = _serve(reqs2, budget=budget, stagger=[0.05, 0.0])
+    assert stats2["completed"] == 2
+    assert stats2["batches_created"] == 2 and stats2["batches_released"] >= 1
+    assert np.array_equal(out2[0][0], out[0][0])
+
+
+def test_many_small_requests_fill_the_slots():
+    reqs = [(i, 65, _rhs(65, inputs.SEED_BASE + 1400 + i)) for i in range(40)]
+    out, stats = _serve(reqs, max_slots=16)
+    assert stats["completed"] == 40 and stats["peak_active"] == 16
+    for tag, n, f in reqs[:6]:
+        ref, _, hist = _solo(n, f)
+        assert np.array_equal(out[tag][0], ref)
+        assert out[tag][1].result.hist() == hist
+
+
+def test_oversized_request_is_rejected():
+    base = mg.make_config(n=65, **BASE)
+    budget = serve.mg_serve_batch_bytes(base, 257, 1)
+    S = serve.Server(budget, 4, 2, n=65, **BASE)
+    try:
+        f, u = dev(np.zeros((513, 513))), dev(np.zeros((513, 513)))
+        assert S.submit(1, f, u) == mg.MG_ENOMEM
+        assert S.submit(2, dev(np.zeros((100, 100))), dev(np.zeros((100, 100)))) == mg.MG_EINVAL
+        assert S.stats()["rejected"] == 1
+    finally:
+        S.close()
