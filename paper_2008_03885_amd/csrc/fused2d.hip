@@ -24,6 +24,7 @@
 // wait for it at once and serialise the row loop on memory latency.
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "mg_internal.h"
 
@@ -37,6 +38,24 @@ constexpr int kRowLen = kWave + 2 * kPad;
 constexpr int kPF = 4;               // rows of u and f loaded ahead
 
 __device__ __forceinline__ bool stopped(const int *done) { return done != nullptr && *done != 0; }
+
+__device__ __forceinline__ int round_up(int a, int m) { return (a + m - 1) / m * m; }
+
+// Slot of an offset in a ring of length L (compile time).
+template <int L>
+__host__ __device__ constexpr int ring(int a) {
+  return ((a % L) + L) % L;
+}
+
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled.
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ __forceinline__ int floordiv2(int a) { return a >= 0 ? a / 2 : -((1 - a) / 2); }
 
@@ -160,18 +179,29 @@ struct PreArgs {
   const int *done;
 };
 
+// Stage s (1 <= s <= K) of the pipeline works on row t - (s-1)(R+1) at row step t: one
+// row more than the stencil radius behind stage s-1, so every stage reads only values
+// that earlier row steps produced.  All stages of a row step are then independent: their
+// x neighbours go through LDS in one batched exchange and their arithmetic overlaps.
+// The full weighting of the defect lags one more row for the same reason.
 template <typename T, int R, int NU, int MODE, bool HAS_U>
 __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   constexpr bool RESTRICT = (MODE & kRestrict) != 0;
   constexpr bool WRITE_R = (MODE & kWriteR) != 0;
   constexpr bool WRITE_U = (MODE & kWriteU) != 0;
   constexpr bool RES = RESTRICT || WRITE_R;
-  constexpr int K = NU + (RES ? 1 : 0);
-  constexpr int H = K * R + (RESTRICT ? 1 : 0);
+  constexpr int K = NU + (RES ? 1 : 0);            // stencil stages (sweeps, then the defect)
+  constexpr int H = K * R + (RESTRICT ? 1 : 0);    // halo columns of a strip
   constexpr int S = kWave - 2 * H;
   constexpr int W = 2 * R + 1;
-  constexpr int FQ = NU * R + 1;
-  __shared__ T lrow[kWavesPerBlock][2][kRowLen];
+  constexpr int LAG = R + 1;                       // rows between consecutive stages
+  constexpr int FQ = (K - 1) * LAG + 1;            // f rows kept (stage s reads row t-(s-1)LAG)
+  constexpr int XV = R == 2 ? 1 : 2;               // values one stage exchanges across lanes
+  constexpr int NX = K * XV + (RESTRICT ? 1 : 0);  // LDS rows per wave
+  constexpr int LR = FQ <= 8 ? 8 : 16;            // ring length = row steps per loop turn
+  static_assert(K >= 1, "the pre kernel runs at least one stencil stage");
+  static_assert(2 * R + 1 < LR && LR % kPF == 0, "rings hold a stencil window; queue divides");
+  __shared__ T lrow[kWavesPerBlock][NX][kRowLen];
   a.done = slot_done(a.done);
   if (stopped(a.done)) return;
   {
@@ -186,21 +216,21 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   const int n = a.n;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
-  const int strip = blockIdx.x * kWavesPerBlock + wv;
+  const Block2 blk = block2();
+  const int strip = blk.x * kWavesPerBlock + wv;
   const int x = strip * S - H + lane;
   const bool active = strip * S < n;  // wave-uniform
   const bool useful = lane >= H && lane < H + S && x <= n - 1;
-  T *ra = &lrow[wv][0][kPad + lane];
-  T *rb = &lrow[wv][1][kPad + lane];
+  T *const lds0 = &lrow[wv][0][kPad + lane];  // LDS row k of this wave at lds0 + k * kRowLen
   Column<T> col;
   col.init(x, n);
 
-  // Rows: the pipeline emits stage-NU values and defects at rows ya..yb; rows [own_a,
-  // own_b) belong to this block for writes and for the defect norm.
+  // Rows: the last stage emits rows ya..yb; rows [own_a, own_b) belong to this block for
+  // writes and for the defect norm.
   int ya, yb, own_a, own_b, Jlo = 0, Jhi = 0;
   const int nc = (n - 1) / 2 + 1;
   if (RESTRICT) {
-    const int J0 = blockIdx.y * a.chunk, J1 = min(J0 + a.chunk, nc);
+    const int J0 = blk.y * a.chunk, J1 = min(J0 + a.chunk, nc);
     ya = 2 * J0 - 1;
     yb = 2 * J1 - 1;
     own_a = 2 * J0;
@@ -213,32 +243,42 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
       if (J1 == nc) a.fc[(size_t)(nc - 1) * nc + I] = T(0);
     }
   } else {
-    const int y0 = blockIdx.y * a.chunk;
+    const int y0 = blk.y * a.chunk;
     ya = y0;
     yb = min(y0 + a.chunk, n) - 1;
     own_a = y0;
     own_b = yb + 1;
   }
-  const int ts = ya - NU * R, te = yb + NU * R;
+  // stage 1 starts (K-1)R rows early so that stage K is exact from row ya on; the row
+  // loop runs whole groups of kPF steps (extra steps emit nothing: their rows are past yb)
+  const int ts = ya - (K - 1) * R;
+  const int te = ts + round_up(yb + (K - 1) * LAG + (RESTRICT ? 1 : 0) - ts + 1, LR) - 1;
   const bool fast = ts - R > 0 && te + R + kPF < n - 1;
   const T *up = HAS_U ? a.u : a.f;
 
   double acc = 0.0;
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
-    T w[NU + 1][W];
-    T fw[FQ];
-    T uq[kPF], fq[kPF];
-    T r0 = T(0), r1 = T(0);  // defects of the two rows before the current one
+    // Every array carried from one row step to the next is a ring whose slot for row r is
+    // (r - ts) mod its length, known at compile time once the loop is unrolled by LR row
+    // steps; no value ever moves between registers, so loads in flight across the loop
+    // back edge stay in flight.
+    T w[K][LR];  // w[s][ring(r - ts)]: stage-s value of row r (s = 0: the input u)
+    T fr[LR];    // f of row r
+    T uq[kPF], fq[kPF];  // loads in flight: u of row t + R, f of row t, slot (t - ts) mod kPF
+    T dr[4];     // defect of row r, slot (r - ts) mod 4
 #pragma unroll
-    for (int s = 0; s <= NU; ++s)
+    for (int s = 0; s < K; ++s)
 #pragma unroll
-      for (int k = 0; k < W; ++k) w[s][k] = T(0);
+      for (int k = 0; k < LR; ++k) w[s][k] = T(0);
 #pragma unroll
-    for (int k = 0; k < FQ; ++k) fw[k] = T(0);
+    for (int k = 0; k < LR; ++k) fr[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dr[k] = T(0);
     if (HAS_U) {
 #pragma unroll
-      for (int k = 0; k < 2 * R; ++k) w[0][k + 1] = col.template fix<FAST>(up[col.template addr<FAST>(ts - R + k)], ts - R + k);
+      for (int k = 0; k < 2 * R; ++k)
+        w[0][ring<LR>(k - R)] = col.template fix<FAST>(up[col.template addr<FAST>(ts - R + k)], ts - R + k);
     }
 #pragma unroll
     for (int p = 0; p < kPF; ++p) {
@@ -247,57 +287,126 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
     }
     const KOp<T> op = a.op;
 
-    for (int t = ts; t <= te; ++t) {
-      const T unew = HAS_U ? col.template fix<FAST>(uq[0], t + R) : T(0);
-      const T fnew = col.template fix<FAST>(fq[0], t);
-      if (HAS_U) push(uq, up[col.template addr<FAST>(t + R + kPF)]);
-      push(fq, a.f[col.template addr<FAST>(t + kPF)]);
-      push(w[0], unew);
-      push(fw, fnew);  // fw[FQ-1-j] = f at row t - j
+    // Row step t = ts + (multiple of LR) + P.
+    auto step = [&](const int t, auto pc) {
+      constexpr int P = decltype(pc)::value;
+      constexpr int Q = P % kPF;
+      const T unew = HAS_U ? col.template fix<FAST>(uq[Q], t + R) : T(0);
+      const T fnew = col.template fix<FAST>(fq[Q], t);
+      // keep the refill below the read of the slot, so it lands in the slot's own register
+      __builtin_amdgcn_sched_barrier(0);
+      if (HAS_U) uq[Q] = up[col.template addr<FAST>(t + R + kPF)];
+      fq[Q] = a.f[col.template addr<FAST>(t + kPF)];
+      w[0][ring<LR>(P + R)] = unew;  // row t + R
+      fr[ring<LR>(P)] = fnew;        // row t
+      const int cK = t - (K - 1) * LAG;  // row of stage K
+
+      // one exchange for every stage: the centre (cross) or the y sums (separable) of
+      // stage s+1's input, stage s around row t - s LAG
+      T ya_[K], yb_[K];
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        if constexpr (R == 2) {
+          ya_[s] = w[s][ring<LR>(P - s * LAG)];
+          lds0[s * kRowLen] = ya_[s];
+        } else {
+          const T c = w[s][ring<LR>(P - s * LAG)];
+          T A = T(0), B = T(0);
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            const T v = w[s][ring<LR>(P - s * LAG + k - R)];
+            if (k != R) A += op.a[k] * (v - c);
+            B += op.b[k] * v;
+          }
+          ya_[s] = A;
+          yb_[s] = B;
+          lds0[(2 * s) * kRowLen] = A;
+          lds0[(2 * s + 1) * kRowLen] = B;
+        }
+      }
+      T ry = T(0);
+      if (RESTRICT) {
+        constexpr int D = ring<4>(P - (K - 1) * LAG);  // slot of row cK
+        ry = T(0.25) * dr[(D + 1) % 4] + T(0.5) * dr[(D + 2) % 4] + T(0.25) * dr[(D + 3) % 4];
+        lds0[(NX - 1) * kRowLen] = ry;
+      }
+      wave_sync();
+      T lu[K];
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        if constexpr (R == 2) {
+          const T *row = lds0 + s * kRowLen;
+          const T c = ya_[s];
+          const T ym1 = w[s][ring<LR>(P - s * LAG - 1)], yp1 = w[s][ring<LR>(P - s * LAG + 1)];
+          const T ym2 = w[s][ring<LR>(P - s * LAG - 2)], yp2 = w[s][ring<LR>(P - s * LAG + 2)];
+          const T xm1 = row[-1], xp1 = row[1], xm2 = row[-2], xp2 = row[2];
+          lu[s] = op.w1 * (((c - xm1) + (c - xp1)) + ((c - ym1) + (c - yp1))) +
+                  op.w2 * (((c - xm2) + (c - xp2)) + ((c - ym2) + (c - yp2)));
+        } else {
+          const T *ra = lds0 + (2 * s) * kRowLen;
+          const T *rb = lds0 + (2 * s + 1) * kRowLen;
+          const T B = yb_[s];
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < W; ++i) {
+            if (i != R) v += op.a[i] * (rb[i - R] - B);
+            v += op.b[i] * ra[i - R];
+          }
+          lu[s] = v;
+        }
+      }
+      T left = T(0), right = T(0);
+      if (RESTRICT) {
+        left = lds0[(NX - 1) * kRowLen - 1];
+        right = lds0[(NX - 1) * kRowLen + 1];
+      }
+      wave_sync();
+
+      // sweeps: stage s at row t - (s-1)LAG
+      T nv[NU > 0 ? NU : 1];
 #pragma unroll
       for (int s = 1; s <= NU; ++s) {
-        // stage s: sweep at row t - (s-1) R, the centre of w[s-1]
-        const T fv = fw[FQ - 1 - (s - 1) * R];
-        const T r = fv - apply_op<T, R>(w[s - 1], op, ra, rb);
-        if (s == 1 && a.partials != nullptr && useful && col.xin && t >= own_a && t < own_b &&
-            t > 0 && t < n - 1)
+        const int row = t - (s - 1) * LAG;
+        const T r = fr[ring<LR>(P - (s - 1) * LAG)] - lu[s - 1];
+        if (s == 1 && a.partials != nullptr && useful && col.xin && row >= own_a && row < own_b &&
+            row > 0 && row < n - 1)
           acc += (double)r * (double)r;
-        push(w[s], w[s - 1][R] + op.om_d * r);
+        nv[s - 1] = w[s - 1][ring<LR>(P - (s - 1) * LAG)] + op.om_d * r;
       }
-      const int c = t - NU * R;  // row of the centre of w[NU]
-      T r = T(0);
-      if (RES || (NU == 0 && a.partials != nullptr)) {
-        r = fw[0] - apply_op<T, R>(w[NU], op, ra, rb);
-        if (NU == 0 && a.partials != nullptr && useful && col.xin && c >= own_a && c < own_b &&
-            c > 0 && c < n - 1)
-          acc += (double)r * (double)r;
+      // defect of the smoothed iterate at row cK
+      T rd = T(0);
+      if (RES) {
+        rd = fr[ring<LR>(P - (K - 1) * LAG)] - lu[K - 1];
+        if (NU == 0 && a.partials != nullptr && useful && col.xin && cK >= own_a && cK < own_b &&
+            cK > 0 && cK < n - 1)
+          acc += (double)rd * (double)rd;
       }
-      if (useful && c >= own_a && c < own_b && c >= 0 && c <= n - 1) {
-        const bool inside = col.xin && c > 0 && c < n - 1;
-        const size_t id = (size_t)c * n + x;
-        if (WRITE_U) a.uout[id] = inside ? w[NU][R] : T(0);
-        if (WRITE_R) a.rout[id] = inside ? r : T(0);
+      if (useful && cK >= own_a && cK < own_b && cK >= 0 && cK <= n - 1) {
+        const bool inside = col.xin && cK > 0 && cK < n - 1;
+        const size_t id = (size_t)cK * n + x;
+        T uval;
+        if constexpr (RES)
+          uval = w[NU][ring<LR>(P - NU * LAG)];
+        else
+          uval = nv[NU > 0 ? NU - 1 : 0];
+        if (WRITE_U) a.uout[id] = inside ? uval : T(0);
+        if (WRITE_R) a.rout[id] = inside ? rd : T(0);
       }
-      if (RESTRICT) {
-        if ((c & 1) != 0) {
-          const int J = (c - 1) >> 1;
-          if (J >= Jlo && J < Jhi) {
-            const T ry = T(0.25) * r0 + T(0.5) * r1 + T(0.25) * r;
-            ra[0] = ry;
-            wave_sync();
-            const T left = ra[-1], right = ra[1];
-            wave_sync();
-            if (useful && (x & 1) == 0) {
-              const int I = x >> 1;
-              const bool inside = I > 0 && I < nc - 1;
-              a.fc[(size_t)J * nc + I] = inside ? T(0.25) * left + T(0.5) * ry + T(0.25) * right : T(0);
-            }
-          }
+      // full weighting of the defect rows cK-3 .. cK-1 onto coarse row J
+      if (RESTRICT && (cK & 1) == 0) {
+        const int J = (cK >> 1) - 1;
+        if (J >= Jlo && J < Jhi && useful && (x & 1) == 0) {
+          const int I = x >> 1;
+          const bool inside = I > 0 && I < nc - 1;
+          a.fc[(size_t)J * nc + I] = inside ? T(0.25) * left + T(0.5) * ry + T(0.25) * right : T(0);
         }
-        r0 = r1;
-        r1 = r;
       }
-    }
+#pragma unroll
+      for (int s = 1; s < K; ++s) w[s][ring<LR>(P - (s - 1) * LAG)] = nv[s - 1];
+      if (RES) dr[ring<4>(P - (K - 1) * LAG)] = rd;
+    };
+    for (int t = ts; t <= te; t += LR)
+      static_for<LR>([&](auto pc) { step(t + decltype(pc)::value, pc); });
   };
   if (active) {
     if (fast)
@@ -339,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
   a.uout = slot_ptr(a.uout, (size_t)n * n);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
-  const int strip = blockIdx.x * kWavesPerBlock + wv;
+  const Block2 blk = block2();
+  const int strip = blk.x * kWavesPerBlock + wv;
   const int x0 = strip * S - H;
   const int x = x0 + lane;
   if (strip * S >= n) return;  // whole wave idle; no block barrier follows
@@ -356,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
   const int src0 = floordiv2(x) - Ib - lane;
   T *crow = &lrow[wv][1][kPad + lane];
 
-  const int y0 = blockIdx.y * a.chunk;
+  const int y0 = blk.y * a.chunk;
   const int y1 = min(y0 + a.chunk, n);
   const int ts = y0 - NU2 * R, te = y1 - 1 + NU2 * R;
   const int jb0 = floordiv2(ts) - 1;
@@ -446,7 +556,6 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
 }
 
 int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
-int clampi(long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
 
 template <typename T>
 KOp<T> to_kop(const LevelOp &op, double omega) {
@@ -461,21 +570,25 @@ KOp<T> to_kop(const LevelOp &op, double omega) {
   return k;
 }
 
-// Rows per block: about 1024 blocks per launch, within [lo, hi] rows.
-int pre_geometry(int n, int S, bool restrict_mode, int *chunk, dim3 *grid) {
-  const int strips = cdiv(n, S);
-  const int bx = cdiv(strips, kWavesPerBlock);
+// Shortest band of a fused launch: coarse rows (pre kernel with restriction) or fine rows.
+constexpr int kMinCoarseRows = 4, kMinFineRows = 8;
+
+// Rows of a pre launch and its bands.  grid.x (blocks across) is set by the caller; the
+// band height fills at most one round of resident blocks of the kernel fn.
+int pre_bands(const void *fn, int n, bool restrict_mode, dim3 *grid) {
   const int rows_total = restrict_mode ? (n - 1) / 2 + 1 : n;
-  const int target_blocks = 1024;
-  const int c = clampi((long)rows_total * bx / target_blocks, restrict_mode ? 8 : 16,
-                       restrict_mode ? 64 : 128);
-  *chunk = c;
-  *grid = dim3(bx, cdiv(rows_total, c), grid->z);
-  return bx * grid->y;
+  const int c = band_rows(rows_total, grid->x, resident_blocks(fn, kBlock, 0),
+                          restrict_mode ? kMinCoarseRows : kMinFineRows);
+  grid->y = cdiv(rows_total, c);
+  return c;
 }
 
 template <typename T, int R, int NU, int MODE>
-hipError_t pre_dispatch(const PreArgs<T> &args, dim3 grid, hipStream_t s) {
+hipError_t pre_dispatch(PreArgs<T> args, dim3 grid, bool restrict_mode, int *nparts, hipStream_t s) {
+  const void *fn = args.u != nullptr ? (const void *)k_pre2d<T, R, NU, MODE, true>
+                                     : (const void *)k_pre2d<T, R, NU, MODE, false>;
+  args.chunk = pre_bands(fn, args.n, restrict_mode, &grid);
+  if (nparts) *nparts = grid.x * grid.y;
   if (args.u != nullptr)
     hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true>), grid, dim3(kBlock), 0, s, args);
   else
@@ -484,18 +597,26 @@ hipError_t pre_dispatch(const PreArgs<T> &args, dim3 grid, hipStream_t s) {
 }
 
 template <typename T, int R, int MODE>
-hipError_t pre_nu(int nu, const PreArgs<T> &args, dim3 grid, hipStream_t s) {
+hipError_t pre_nu(int nu, const PreArgs<T> &args, dim3 grid, int *nparts, hipStream_t s) {
+  constexpr bool RM = (MODE & kRestrict) != 0;
+  constexpr bool RES = (MODE & (kRestrict | kWriteR)) != 0;
   switch (nu) {
-    case 0: return pre_dispatch<T, R, 0, MODE>(args, grid, s);
-    case 1: return pre_dispatch<T, R, 1, MODE>(args, grid, s);
-    case 2: return pre_dispatch<T, R, 2, MODE>(args, grid, s);
-    case 3: return pre_dispatch<T, R, 3, MODE>(args, grid, s);
+    case 0:
+      if constexpr (RES) return pre_dispatch<T, R, 0, MODE>(args, grid, RM, nparts, s);
+      return hipErrorInvalidValue;  // nothing to compute
+    case 1: return pre_dispatch<T, R, 1, MODE>(args, grid, RM, nparts, s);
+    case 2: return pre_dispatch<T, R, 2, MODE>(args, grid, RM, nparts, s);
+    case 3: return pre_dispatch<T, R, 3, MODE>(args, grid, RM, nparts, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int R, int NU2>
-hipError_t post_dispatch(int prolong, const PostArgs<T> &args, dim3 grid, hipStream_t s) {
+hipError_t post_dispatch(int prolong, PostArgs<T> args, dim3 grid, hipStream_t s) {
+  const void *fn = prolong == 3 ? (const void *)k_post2d<T, R, NU2, 3>
+                                : (const void *)k_post2d<T, R, NU2, 1>;
+  args.chunk = band_rows(args.n, grid.x, resident_blocks(fn, kBlock, 0), kMinFineRows);
+  grid.y = cdiv(args.n, args.chunk);
   if (prolong == 3)
     hipLaunchKernelGGL((k_post2d<T, R, NU2, 3>), grid, dim3(kBlock), 0, s, args);
   else
@@ -524,9 +645,9 @@ int pre2d_partials(int n) {
         const int H = (nu + 1) * R + restrict_mode;
         const int S = kWave - 2 * H;
         if (S <= 0) continue;
-        int chunk;
-        dim3 grid;
-        const int nb = pre_geometry(n, S, restrict_mode != 0, &chunk, &grid);
+        const int bx = cdiv(cdiv(n, S), kWavesPerBlock);
+        const int rows_total = restrict_mode ? (n - 1) / 2 + 1 : n;
+        const int nb = bx * cdiv(rows_total, restrict_mode ? kMinCoarseRows : kMinFineRows);
         best = nb > best ? nb : best;
       }
   return best;
@@ -544,18 +665,13 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
   const int S = kWave - 2 * H;
   if (S <= 0 || nu < 0 || nu > 3) return hipErrorInvalidValue;
   PreArgs<T> args{f, u, uout, rout, fc, n, 0, to_kop<T>(op, omega), partials, done};
-  dim3 grid(1, 1, slots);
-  const int nb = pre_geometry(n, S, restrict_mode, &args.chunk, &grid);
-  if (nparts) *nparts = nb;
-#define MG_PRE(RR)                                                                        \
-  switch (mode) {                                                                         \
-    case kWriteU | kRestrict: return pre_nu<T, RR, kWriteU | kRestrict>(nu, args, grid, s); \
-    case kRestrict: return pre_nu<T, RR, kRestrict>(nu, args, grid, s);                   \
-    case kWriteU: return pre_nu<T, RR, kWriteU>(nu, args, grid, s);                       \
-    case kWriteR: return pre_nu<T, RR, kWriteR>(nu, args, grid, s);                       \
-    case 0: return pre_nu<T, RR, 0>(nu, args, grid, s);                                   \
-    default: return hipErrorInvalidValue;                                                 \
-  }
+  const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
+#define MG_PRE(RR)                                                                         \
+  if (mode == (kWriteU | kRestrict)) return pre_nu<T, RR, kWriteU | kRestrict>(nu, args, grid, nparts, s); \
+  if (mode == kWriteU && nu == 1) return pre_dispatch<T, RR, 1, kWriteU>(args, grid, false, nparts, s); \
+  if (mode == kWriteR && nu == 0) return pre_dispatch<T, RR, 0, kWriteR>(args, grid, false, nparts, s); \
+  if (mode == kRestrict && nu == 0) return pre_dispatch<T, RR, 0, kRestrict>(args, grid, true, nparts, s); \
+  return hipErrorInvalidValue;
   if (R == 2) { MG_PRE(2) } else { MG_PRE(3) }
 #undef MG_PRE
 }
@@ -569,10 +685,7 @@ hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, 
   const int H = nu2 * R;
   const int S = kWave - 2 * H;
   PostArgs<T> args{v, uin, f, uout, n, 0, to_kop<T>(op, omega), done};
-  const int strips = cdiv(n, S);
-  const int bx = cdiv(strips, kWavesPerBlock);
-  args.chunk = clampi((long)n * bx / 1024, 16, 128);
-  const dim3 grid(bx, cdiv(n, args.chunk), slots);
+  const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
   if (R == 2) return post_nu<T, 2>(nu2, prolong, args, grid, s);
   return post_nu<T, 3>(nu2, prolong, args, grid, s);
 }

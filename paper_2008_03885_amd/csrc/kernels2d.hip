@@ -8,7 +8,11 @@
 // the x neighbours are read: one barrier per row, every u value read from HBM once
 // per strip, and the x halo (R columns on each side) costs 2R/256 extra loads.  Grid
 // functions are extended across the Dirichlet boundary by odd reflection.
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "mg_internal.h"
 
@@ -58,8 +62,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(const T *__restrict__ f,
   out = slot_ptr(out, (size_t)n * n);
   partials = slot_ptr(partials, (size_t)gridDim.x * gridDim.y);
   const int t = threadIdx.x;
-  const int x = blockIdx.x * (kBlock - 2 * R) - R + t;
-  const int y0 = blockIdx.y * rows;
+  const Block2 blk = block2();
+  const int x = blk.x * (kBlock - 2 * R) - R + t;
+  const int y0 = blk.y * rows;
   const int y1 = min(y0 + rows, n);
   int sx = 1;
   const int xs = fold(x, n, sx);
@@ -160,17 +165,18 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict2d(const T *__restrict
   u = slot_ptr(u, (size_t)n * n);
   fc = slot_ptr(fc, (size_t)nc * nc);
   const int t = threadIdx.x;
-  const int x = 2 * blockIdx.x * CB - (R + 1) + t;
+  const Block2 blk = block2();
+  const int x = 2 * blk.x * CB - (R + 1) + t;
   int sx = 1;
   const int xs = fold(x, n, sx);
   const bool col_ok = xs >= 0 && xs <= n - 1;
   const bool own = t >= R && t < kBlock - R;
   const bool emits = t >= R + 1 && ((t - R - 1) & 1) == 0 && t <= 2 * CB + R - 1;
-  const int I = blockIdx.x * CB + (t - R - 1) / 2;
+  const int I = blk.x * CB + (t - R - 1) / 2;
   const bool I_ok = emits && I <= nc - 1;
   const bool I_int = I_ok && I >= 1 && I <= nc - 2;
   const bool zero_u = (u == nullptr);
-  const int J0 = blockIdx.y * crows;
+  const int J0 = blk.y * crows;
   const int J1 = min(J0 + crows, nc);
   if (I_ok) {
     if (J0 == 0) fc[I] = T(0);
@@ -267,13 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong2d(const T *__restrict__ v,
   uin = slot_ptr(uin, (size_t)n * n);
   uout = slot_ptr(uout, (size_t)n * n);
   const int t = threadIdx.x;
-  const int xb = blockIdx.x * kBlock;
+  const Block2 blk = block2();
+  const int xb = blk.x * kBlock;
   const int x = xb + t;
   const int Ib = xb / 2 - 1;
   int sc = 1;
   const int Ic = fold(Ib + t, nc, sc);
   const bool cok = t < NCOL && Ic >= 0 && Ic <= nc - 1;
-  const int y0 = blockIdx.y * rows;
+  const int y0 = blk.y * rows;
   const int y1 = min(y0 + rows, n);
 
   auto load_row = [&](int J, int b) {
@@ -440,8 +447,19 @@ int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 int clampi(long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
 
-// Rows per block of a 2D strip kernel: about 2048 blocks in total, 4..32 rows each.
-int strip_rows(int n, int nbx, int lo, int hi) { return clampi((long)n * nbx / 2048, lo, hi); }
+template <typename T, typename TO>
+const void *sweep2d_fn(int mode, bool cross) {
+  if (cross) {
+    if (mode == kSweep) return (const void *)k_sweep2d<T, TO, kSweep, true>;
+    if (mode == kResidual) return (const void *)k_sweep2d<T, TO, kResidual, true>;
+    return (const void *)k_sweep2d<T, TO, kNormOnly, true>;
+  }
+  if (mode == kSweep) return (const void *)k_sweep2d<T, TO, kSweep, false>;
+  if (mode == kResidual) return (const void *)k_sweep2d<T, TO, kResidual, false>;
+  return (const void *)k_sweep2d<T, TO, kNormOnly, false>;
+}
+
+constexpr int kMinRows = 4;  // rows per band of the unfused 2D kernels, at least
 
 template <typename T>
 KOp<T> to_kop(const LevelOp &op, double omega) {
@@ -459,13 +477,39 @@ KOp<T> to_kop(const LevelOp &op, double omega) {
 // For R = 3 kernels the a/b arrays are used at offsets -3..3 directly.
 }  // namespace
 
+int resident_blocks(const void *fn, int threads, size_t smem) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void *, int, size_t>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(dev, fn, threads, smem);
+  std::lock_guard<std::mutex> g(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, smem) != hipSuccess ||
+      per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  return cache[key] = per_cu * cus;
+}
+
+int band_rows(int total, int across, int capacity, int cmin) {
+  const int per = std::max(1, capacity / std::max(1, across));
+  return std::max(cmin, cdiv(total, per));
+}
+
 int sweep_partials(int dim, int n) {
   if (dim == 2) {
     int best = 0;
     for (int R = 2; R <= 3; ++R) {
-      const int nbx = cdiv(n, kBlock - 2 * R);
-      const int rows = strip_rows(n, nbx, 4, 32);
-      const int np = nbx * cdiv(n, rows);
+      const int np = cdiv(n, kBlock - 2 * R) * cdiv(n, kMinRows);
       best = np > best ? np : best;
     }
     return best;
@@ -483,7 +527,8 @@ hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, cons
   }
   const int R = op.cross ? 2 : 3;
   const int nbx = cdiv(n, kBlock - 2 * R);
-  const int rows = strip_rows(n, nbx, 4, 32);
+  const int rows =
+      band_rows(n, nbx, resident_blocks(sweep2d_fn<T, TO>(mode, op.cross), kBlock, 0), kMinRows);
   const dim3 grid(nbx, cdiv(n, rows), slots);
   if (nparts) *nparts = grid.x * grid.y;
   const KOp<T> k = to_kop<T>(op, omega);
@@ -513,7 +558,9 @@ hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T
   const int R = op.cross ? 2 : 3;
   const int CB = (kBlock - 2 * R - 2) / 2;
   const int nbx = cdiv(nc, CB);
-  const int crows = strip_rows(nc, nbx, 2, 16);
+  const void *fn = op.cross ? (const void *)k_resid_restrict2d<T, true>
+                            : (const void *)k_resid_restrict2d<T, false>;
+  const int crows = band_rows(nc, nbx, resident_blocks(fn, kBlock, 0), 2);
   const dim3 grid(nbx, cdiv(nc, crows), slots);
   const KOp<T> k = to_kop<T>(op, 1.0);
   if (op.cross)
@@ -531,7 +578,8 @@ hipError_t launch_prolong_correct(int dim, int prolong, const T *v, const T *uin
     return launch_prolong_correct_3d<T>(prolong, v, uin, uout, n, done, s);
   }
   const int nbx = cdiv(n, kBlock);
-  const int rows = strip_rows(n, nbx, 4, 32);
+  const void *fn = prolong == 3 ? (const void *)k_prolong2d<T, 3> : (const void *)k_prolong2d<T, 1>;
+  const int rows = band_rows(n, nbx, resident_blocks(fn, kBlock, 0), kMinRows);
   const dim3 grid(nbx, cdiv(n, rows), slots);
   if (prolong == 3)
     hipLaunchKernelGGL((k_prolong2d<T, 3>), grid, dim3(kBlock), 0, s, v, uin, uout, n, rows, done);

@@ -13,6 +13,7 @@
 // L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as a z pass, a y pass and an x
 // pass through LDS with every a factor in difference form, so constants are annihilated
 // exactly.
+#include <algorithm>
 #include <cmath>
 
 #include "mg_internal.h"
@@ -169,8 +170,9 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const 
   T *ring = reinterpret_cast<T *>(smem3);
   T *zb = ring + W * PS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
   if (stopped(done)) return;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int z0 = blockIdx.z * zchunk, z1 = min(z0 + zchunk, n);
+  const Block3 blk = block3();
+  const int x0 = blk.x * TX, y0 = blk.y * TY;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x <= n - 1 && y <= n - 1;
@@ -256,8 +258,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
   T *zb = rr + 3 * RS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;  // fine origin (even)
-  const int K0 = blockIdx.z * kchunk, K1 = min(K0 + kchunk, nc);
+  const Block3 blk = block3();
+  const int x0 = blk.x * TX, y0 = blk.y * TY;  // fine origin (even)
+  const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
   const bool zero_u = u == nullptr;
   PlaneLoader<T, PX, PY> ld;
   ld.init(x0 - E, y0 - E, n);
@@ -359,8 +362,9 @@ __global__ __launch_bounds__(256) void k_prolong3d(const T *__restrict__ v, cons
   __shared__ T cpl[2][CS];
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int z0 = blockIdx.z * zchunk, z1 = min(z0 + zchunk, n);
+  const Block3 blk = block3();
+  const int x0 = blk.x * TX, y0 = blk.y * TY;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int x = x0 + tx, y = y0 + ty;
   const int Ib = x0 / 2 - 1, Jb = y0 / 2 - 1;  // coarse region origin
@@ -457,7 +461,6 @@ __global__ __launch_bounds__(256) void k_prolong3d(const T *__restrict__ v, cons
 }
 
 int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
-int clampi(long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
 
 template <typename T>
 KOp<T> to_kop3(const LevelOp &op, double omega) {
@@ -472,9 +475,21 @@ KOp<T> to_kop3(const LevelOp &op, double omega) {
   return k;
 }
 
-// planes per block: about 4096 blocks in total, 8..64 planes
-int zchunk_for(int n, long tiles, int lo, int hi) {
-  return clampi((long)n * tiles / 4096, lo, hi);
+// Plane bands of the 3D kernels: 8..64 fine planes (4..32 coarse), about four rounds of
+// resident blocks per launch (the plane loop of a block is latency-bound, so several
+// blocks per CU in flight beat one long march each).
+constexpr int kMinPlanes = 8, kMaxPlanes = 64, kRounds3d = 4;
+
+template <typename T, typename TO>
+const void *sweep3d_fn(int mode, bool cross) {
+  if (cross) {
+    if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 2>;
+    if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 2>;
+    return (const void *)k_sweep3d<T, TO, kNormOnly, 2>;
+  }
+  if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
+  if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
+  return (const void *)k_sweep3d<T, TO, kNormOnly, 3>;
 }
 
 template <typename T, int R>
@@ -495,16 +510,17 @@ size_t rr_smem() {
 
 int sweep_partials_3d(int n) {
   const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
-  const int zc = zchunk_for(n, tiles, 8, 64);
-  return (int)(tiles * cdiv(n, zc));
+  return (int)(tiles * cdiv(n, kMinPlanes));
 }
 
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s) {
-  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
-  const int zc = zchunk_for(n, tiles, 8, 64);
+  const int tiles = cdiv(n, TX) * cdiv(n, TY);
+  const size_t smem = op.cross ? sweep_smem<T, 2>() : sweep_smem<T, 3>();
+  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross), 256, smem),
+                                                kMinPlanes));
   const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   const KOp<T> k = to_kop3<T>(op, omega);
@@ -527,8 +543,10 @@ template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s) {
   const int nc = (n - 1) / 2 + 1;
-  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
-  const int kc = zchunk_for(nc, tiles, 4, 32);
+  const int tiles = cdiv(n, TX) * cdiv(n, TY);
+  const void *fn = op.cross ? (const void *)k_resid_restrict3d<T, 2> : (const void *)k_resid_restrict3d<T, 3>;
+  const size_t smem = op.cross ? rr_smem<T, 2>() : rr_smem<T, 3>();
+  const int kc = std::min(kMaxPlanes / 2, band_rows(nc, tiles, kRounds3d * resident_blocks(fn, 256, smem), kMinPlanes / 2));
   const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(nc, kc));
   const KOp<T> k = to_kop3<T>(op, 1.0);
   if (op.cross)
@@ -541,8 +559,9 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
 template <typename T>
 hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
                                      const int *done, hipStream_t s) {
-  const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
-  const int zc = zchunk_for(n, tiles, 8, 64);
+  const int tiles = cdiv(n, TX) * cdiv(n, TY);
+  const void *fn = prolong == 3 ? (const void *)k_prolong3d<T, 3> : (const void *)k_prolong3d<T, 1>;
+  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, 256, 0), kMinPlanes));
   const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
   if (prolong == 3)
     hipLaunchKernelGGL((k_prolong3d<T, 3>), grid, dim3(256), 0, s, v, uin, uout, n, zc, done);

@@ -52,6 +52,37 @@ struct DevState {
 
 enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2 };
 
+// Workgroups are dealt to the XCDs (8 on MI355X, each with its own L2) round-robin in
+// linear dispatch order.  xcd_logical maps a linear id to a logical block id such that
+// each XCD receives one contiguous range of logical ids; neighbouring tiles then run on
+// the same XCD and share their halo lines in its L2.  A bijection on [0, nb).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_logical(unsigned lid, unsigned nb) {
+  const unsigned q = nb / kXcds, r = nb % kXcds;
+  const unsigned x = lid % kXcds, local = lid / kXcds;
+  return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+// Logical (x, y) block of a 2D grid (the third grid dimension is left alone).
+struct Block2 {
+  int x, y;
+};
+__device__ __forceinline__ Block2 block2() {
+  const unsigned nb = gridDim.x * gridDim.y;
+  const unsigned l = xcd_logical(blockIdx.y * gridDim.x + blockIdx.x, nb);
+  return {(int)(l % gridDim.x), (int)(l / gridDim.x)};
+}
+// Logical (x, y, z) block of a 3D grid.
+struct Block3 {
+  int x, y, z;
+};
+__device__ __forceinline__ Block3 block3() {
+  const unsigned nxy = gridDim.x * gridDim.y;
+  const unsigned l = xcd_logical((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                                 nxy * gridDim.z);
+  const unsigned rxy = l % nxy;
+  return {(int)(rxy % gridDim.x), (int)(rxy / gridDim.x), (int)(l / nxy)};
+}
+
 // Batched launches.  grid.z indexes independent problems of one size ("slots"): every
 // per-problem array is dense [slot][points], partial sums are [slot][blocks of one slot]
 // and each slot has its own DevState, so slot k of a batched launch computes exactly
@@ -101,6 +132,15 @@ hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t
 // Largest number of partial sums a level-0 sweep of side n produces.
 int sweep_partials(int dim, int n);
 
+// ---- launch geometry ----------------------------------------------------------------
+// Blocks of kernel fn (`threads` per block, `smem` dynamic LDS bytes) the current device
+// keeps resident at once: the occupancy calculator's blocks per CU times the CU count.
+int resident_blocks(const void *fn, int threads, size_t smem);
+// Rows (or planes) per band when a launch covers `total` rows in bands of `across`
+// blocks each: as many bands as one round of `capacity` resident blocks holds, none
+// shorter than cmin.  A launch of one round has no straggler blocks.
+int band_rows(int total, int across, int capacity, int cmin);
+
 // 3D variants (kernels3d.hip), called by the launchers above for dim == 3.
 int sweep_partials_3d(int n);
 hipError_t prepare_3d();  // enables the large dynamic LDS of the separable 3D kernels
@@ -117,7 +157,9 @@ hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *u
 
 // ---- fused 2D cycle kernels (fused2d.hip) ----------------------------------------
 // Pre kernel modes (bit set): 1 write the smoothed iterate, 2 full-weight the defect,
-// 4 write the defect.
+// 4 write the defect.  Supported: WriteU|Restrict with nu <= 3 (the pre half of a cycle),
+// WriteU with nu = 1 (one sweep), WriteR with nu = 0 (the defect), Restrict with nu = 0
+// (defect and full weighting).
 constexpr int kPreWriteU = 1, kPreRestrict = 2, kPreWriteR = 4;
 int pre2d_partials(int n);
 template <typename T>
