@@ -41,7 +41,13 @@ WORKLOADS = {
 # HBM traffic of the dominant kernels from rocprofv3 --pmc (FETCH_SIZE and WRITE_SIZE per
 # dispatch, scaled by the counters of a plain copy of known size), valid only for the
 # kernel source they were taken on.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # 4097^2 level 0, two sweeps + defect + full weighting: 172,281.7 KiB fetched x 2.0000
+    # + 169,180.3 KiB written x 1.0000 (a 2 GiB copy reads 1,048,595 KiB / writes 2,097,152)
+    "k_pre2d/f64/fused2d.hip/4097": {"bytes": 526067037, "source": "29a9c7046e24eaad"},
+    # 513^3 level 0 FP32 sweep: 620,912.0 KiB x 2.0000 + 561,025.6 KiB x 1.0000
+    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 1846094590, "source": "6f97bc5ea822d368"},
+}
 
 
 def parse():
@@ -55,6 +61,7 @@ def parse():
     p.add_argument("--gamma", type=int, default=None)
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
+    p.add_argument("--inner", type=int, default=None, help="FP32 cycles per refinement step")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-levels", action="store_true", help="skip the per-level kernel table")
     p.add_argument("--kernel-reps", type=int, default=30)
@@ -365,7 +372,7 @@ def main():
     import torch
 
     w = dict(WORKLOADS[args.workload])
-    for k in ("n", "coarse", "gamma", "precision", "compare"):
+    for k in ("n", "coarse", "gamma", "precision", "compare", "inner"):
         if getattr(args, k) is not None:
             w[k] = getattr(args, k)
     torch.cuda.set_device(0)

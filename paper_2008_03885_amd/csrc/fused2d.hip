@@ -291,9 +291,11 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
     auto step = [&](const int t, auto pc) {
       constexpr int P = decltype(pc)::value;
       constexpr int Q = P % kPF;
-      const T unew = HAS_U ? col.template fix<FAST>(uq[Q], t + R) : T(0);
-      const T fnew = col.template fix<FAST>(fq[Q], t);
-      // keep the refill below the read of the slot, so it lands in the slot's own register
+      T unew = HAS_U ? col.template fix<FAST>(uq[Q], t + R) : T(0);
+      T fnew = col.template fix<FAST>(fq[Q], t);
+      // Materialise both values here (an empty asm that only pins them in registers) and
+      // keep the refill below: the slot's raw value dies before its register is reloaded.
+      asm volatile("" : "+v"(unew), "+v"(fnew));
       __builtin_amdgcn_sched_barrier(0);
       if (HAS_U) uq[Q] = up[col.template addr<FAST>(t + R + kPF)];
       fq[Q] = a.f[col.template addr<FAST>(t + kPF)];

@@ -758,7 +758,7 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
     int lds_limit = 0;
     if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
       lds_limit = 65536;
-    int cap = c->dim == 2 ? 65 : 17;
+    int cap = c->dim == 2 ? 33 : 17;
     if (const char *tn = std::getenv("MG_TAIL_N")) cap = std::atoi(tn);
     const size_t es = mixed ? sizeof(float) : sizeof(double);
     c->tail_top = L;
