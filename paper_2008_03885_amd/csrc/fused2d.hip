@@ -640,7 +640,7 @@ hipError_t post_nu(int nu2, int prolong, const PostArgs<T> &args, dim3 grid, hip
 
 int pre2d_partials(int n) {
   // the largest grid any pre launch uses at side n (smallest strip width S = 64 - 2H)
-  int best = 0;
+  int best = pre2d_tile_partials(n);
   for (int R = 2; R <= 3; ++R)
     for (int nu = 0; nu <= 3; ++nu)
       for (int restrict_mode = 0; restrict_mode <= 1; ++restrict_mode) {
@@ -659,6 +659,9 @@ template <typename T>
 hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                         T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
                         const int *done, hipStream_t s, int slots) {
+  if (n <= tile2d_max_side())
+    return launch_pre2d_tile<T>(op, omega, nu, mode, f, u, uout, rout, fc, n, partials, nparts, done,
+                                s, slots);
   const int R = op.cross ? 2 : 3;
   const bool restrict_mode = (mode & kRestrict) != 0;
   const bool res = restrict_mode || (mode & kWriteR) != 0;
@@ -682,8 +685,10 @@ template <typename T>
 hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                          const T *uin, const T *f, T *uout, int n, const int *done,
                          hipStream_t s, int slots) {
-  const int R = op.cross ? 2 : 3;
   if (nu2 < 0 || nu2 > 2) return hipErrorInvalidValue;
+  if (n <= tile2d_max_side())
+    return launch_post2d_tile<T>(op, omega, nu2, prolong, v, uin, f, uout, n, done, s, slots);
+  const int R = op.cross ? 2 : 3;
   const int H = nu2 * R;
   const int S = kWave - 2 * H;
   PostArgs<T> args{v, uin, f, uout, n, 0, to_kop<T>(op, omega), done};

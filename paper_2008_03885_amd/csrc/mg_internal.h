@@ -171,6 +171,20 @@ hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, 
                          const T *uin, const T *f, T *uout, int n, const int *done,
                          hipStream_t s, int slots = 1);
 
+// ---- tile kernels for small levels (tile2d.hip) -------------------------------------
+// launch_pre2d / launch_post2d use them for sides up to tile2d_max_side() (the
+// MG_TILE_N environment variable, default 513).
+int tile2d_max_side();
+int pre2d_tile_partials(int n);
+template <typename T>
+hipError_t launch_pre2d_tile(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
+                             T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
+                             const int *done, hipStream_t s, int slots);
+template <typename T>
+hipError_t launch_post2d_tile(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
+                              const T *uin, const T *f, T *uout, int n, const int *done,
+                              hipStream_t s, int slots);
+
 // ---- LDS-resident tail (tail.hip) -------------------------------------------------
 constexpr int kMaxTailLevels = 8;
 struct TailLevel {

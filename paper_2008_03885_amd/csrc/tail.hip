@@ -25,16 +25,16 @@ constexpr int kTailThreads = 1024;
 // interpolation one coarse point; G = 1 when every tail level is the radius-2 cross,
 // G = 2 otherwise.
 
-// Thread tiling of a level and the number of points each thread visits at the largest
-// tail side (65 in 2D, 17 in 3D).
-template <int DIM>
+// Thread tiling of a level (NT threads) and the number of points each thread visits at
+// the largest tail side (65 in 2D, 17 in 3D).
+template <int DIM, int NT>
 struct Tiling;
 template <>
-struct Tiling<2> {
+struct Tiling<2, 1024> {
   static constexpr int TX = 64, TY = 16, TZ = 1, NI = 2, NJ = 5, NK = 1;
 };
 template <>
-struct Tiling<3> {
+struct Tiling<3, 1024> {
   static constexpr int TX = 16, TY = 8, TZ = 8, NI = 2, NJ = 3, NK = 3;
 };
 
@@ -47,8 +47,9 @@ struct LevelInfo {
   int cross;
 };
 
-template <typename T, int DIM, int G>
+template <typename T, int DIM, int G, int NT>
 struct Tail {
+  using TL = Tiling<DIM, NT>;
   const LevelInfo *lv;
   T *lds;
   const int *edelta;  // entry offsets as index deltas in the padded layout of their level
@@ -67,7 +68,6 @@ struct Tail {
   }
   template <typename F>
   __device__ __forceinline__ void each(int n, F fn) const {
-    using TL = Tiling<DIM>;
     for (int k = (DIM == 3 ? tz : 0); k < (DIM == 3 ? n : 1); k += TL::TZ)
       for (int j = ty; j < n; j += TL::TY)
         for (int i = tx; i < n; i += TL::TX) fn(i, j, k);
@@ -96,7 +96,6 @@ struct Tail {
   // refresh the ghost frame of u on level l with the odd reflection
   __device__ __forceinline__ void ghosts(int l) const {
     const int n = lv[l].n;
-    using TL = Tiling<DIM>;
     for (int k = (DIM == 3 ? tz - G : 0); k < (DIM == 3 ? n + G : 1); k += TL::TZ)
       for (int j = ty - G; j < n + G; j += TL::TY)
         for (int i = tx - G; i < n + G; i += TL::TX) {
@@ -117,7 +116,6 @@ struct Tail {
     __syncthreads();
   }
   __device__ __forceinline__ void smooth(int l, bool zero) const {
-    using TL = Tiling<DIM>;
     const int n = lv[l].n;
     const T om = T(lv[l].om_d);
     T vals[TL::NK][TL::NJ][TL::NI];
@@ -218,22 +216,23 @@ struct Tail {
     __syncthreads();
     ghosts(l);
   }
+  // v = A^{-1} f on the coarsest level (FP64 sums), staged in the defect scratch (free here)
   __device__ __forceinline__ void coarsest(int l) const {
     const int n = lv[l].n, q = n - 2;
-    const int r = threadIdx.x;
-    double val = 0.0;
-    if (r < m) {
+    T *v = lds + scratch;
+    for (int r = threadIdx.x; r < m; r += NT) {
+      double val = 0.0;
       for (int c = 0; c < m; ++c) {
         const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
         val += ainv_t[(size_t)c * m + r] * (double)lds[lv[l].f + didx(l, ci, cj, ck)];
       }
+      v[r] = (T)val;
     }
-    __syncthreads();
     each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
     __syncthreads();
-    if (r < m) {
+    for (int r = threadIdx.x; r < m; r += NT) {
       const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
-      lds[pidx(l, ri, rj, rk)] = (T)val;
+      lds[pidx(l, ri, rj, rk)] = v[r];
     }
     __syncthreads();
     ghosts(l);
@@ -244,8 +243,8 @@ struct Tail {
 // pre-smooths, restricts and descends; the way back up interpolates, post-smooths and
 // either repeats level l (gamma > 1, second visit from the same parent, non-zero guess)
 // or returns to the parent.  Bit l of `visited` records a finished visit of level l.
-template <typename T, int DIM, int G>
-__device__ __forceinline__ void run_cycle(const Tail<T, DIM, G> &c, bool zero0) {
+template <typename T, int DIM, int G, int NT>
+__device__ __forceinline__ void run_cycle(const Tail<T, DIM, G, NT> &c, bool zero0) {
   const int last = c.levels - 1;
   if (last == 0) {
     c.coarsest(0);
@@ -281,13 +280,12 @@ __device__ __forceinline__ void run_cycle(const Tail<T, DIM, G> &c, bool zero0) 
   }
 }
 
-template <typename T, int DIM, int G>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
+template <typename T, int DIM, int G, int NT>
+__global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   extern __shared__ __align__(16) unsigned char tail_lds[];
   __shared__ LevelInfo lvt[kMaxTailLevels];
   const int *done = slot_done(a.done);
   if (done != nullptr && *done != 0) return;
-  using TL = Tiling<DIM>;
   // level table: padded pitches and LDS offsets (u framed, f dense)
   if (threadIdx.x == 0) {
     int off = 0;
@@ -312,7 +310,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   int *edelta = reinterpret_cast<int *>(tail_lds + a.lds_ent);
   T *ecoef = reinterpret_cast<T *>(tail_lds + a.lds_ent + sizeof(int) * a.ent_total +
                                    (sizeof(T) - (sizeof(int) * a.ent_total) % sizeof(T)) % sizeof(T));
-  for (int e = threadIdx.x; e < a.ent_total; e += kTailThreads) {
+  for (int e = threadIdx.x; e < a.ent_total; e += NT) {
     const int g = a.ent_first + e;
     int l = 0;
     while (l + 1 < a.levels && e >= lvt[l + 1].e0) ++l;
@@ -320,7 +318,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
     edelta[e] = (a.eoff[3 * g + 2] * pp + a.eoff[3 * g + 1]) * pp + a.eoff[3 * g];
     ecoef[e] = (T)a.ecoef[g];
   }
-  Tail<T, DIM, G> c;
+  using TL = Tiling<DIM, NT>;
+  Tail<T, DIM, G, NT> c;
   c.lv = lvt;
   c.lds = lds;
   c.edelta = edelta;
@@ -348,7 +347,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs a) {
   });
   __syncthreads();
   c.ghosts(0);
-  run_cycle<T, DIM, G>(c, a.zero_init != 0);
+  run_cycle<T, DIM, G, NT>(c, a.zero_init != 0);
   c.each(n, [&](int i, int j, int k) { ug[c.didx(0, i, j, k)] = lds[c.pidx(0, i, j, k)]; });
 }
 
@@ -380,8 +379,8 @@ size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, si
 
 template <typename T>
 const void *tail_fn(int dim, int G) {
-  if (dim == 2) return G == 1 ? (const void *)k_tail<T, 2, 1> : (const void *)k_tail<T, 2, 2>;
-  return G == 1 ? (const void *)k_tail<T, 3, 1> : (const void *)k_tail<T, 3, 2>;
+  if (dim == 2) return G == 1 ? (const void *)k_tail<T, 2, 1, kTailThreads> : (const void *)k_tail<T, 2, 2, kTailThreads>;
+  return G == 1 ? (const void *)k_tail<T, 3, 1, kTailThreads> : (const void *)k_tail<T, 3, 2, kTailThreads>;
 }
 
 template <typename T>
@@ -395,13 +394,13 @@ hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, h
                        int slots) {
   const dim3 grid(1, 1, slots);
   if (dim == 2 && G == 1)
-    hipLaunchKernelGGL((k_tail<T, 2, 1>), grid, dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 2, 1, kTailThreads>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else if (dim == 2)
-    hipLaunchKernelGGL((k_tail<T, 2, 2>), grid, dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 2, 2, kTailThreads>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else if (G == 1)
-    hipLaunchKernelGGL((k_tail<T, 3, 1>), grid, dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 3, 1, kTailThreads>), grid, dim3(kTailThreads), lds_bytes, s, args);
   else
-    hipLaunchKernelGGL((k_tail<T, 3, 2>), grid, dim3(kTailThreads), lds_bytes, s, args);
+    hipLaunchKernelGGL((k_tail<T, 3, 2, kTailThreads>), grid, dim3(kTailThreads), lds_bytes, s, args);
   return hipGetLastError();
 }
 
