@@ -15,6 +15,8 @@
 // exactly.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "mg_internal.h"
 
@@ -31,6 +33,8 @@ __device__ __forceinline__ int fold(int i, int n, int &sign) {
   if (i < 0) { i = -i; sign = -sign; }
   return (i >= 0 && i <= n - 1) ? i : -1;
 }
+
+__device__ __forceinline__ int round_up8(int a) { return (a + 7) / 8 * 8; }
 
 __device__ double block_sum256(double v) {
   __shared__ double ws[4];
@@ -239,6 +243,166 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const 
   }
 }
 
+// ----------------------------------------------- cross sweep, z windows in registers ----
+// The radius-2 cross operator (rediscretized levels).  Each thread keeps the u values of
+// its own column at planes z-2 .. z+5 in a ring of registers; only plane z of the tile and
+// its halo goes through LDS (double-buffered, one barrier per plane).  The plane loop is
+// unrolled by the ring length, so ring slots are fixed registers and loads issued four to
+// six planes ahead stay in flight.
+
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int kZR = 8;  // planes per loop turn (the u ring); f and halo rings hold 4
+
+// A grid column (x, y): folded address and the sign of the odd extension (0 on and
+// beyond the boundary).
+template <typename T>
+struct Col3 {
+  int off;
+  T mul;
+  __device__ void init(int x, int y, int n) {
+    int s = 1;
+    const int xf = fold(x, n, s), yf = fold(y, n, s);
+    const bool ok = xf > 0 && xf < n - 1 && yf > 0 && yf < n - 1;
+    off = ok ? yf * n + xf : n + 1;
+    mul = ok ? T(s) : T(0);
+  }
+};
+
+// Address of plane z (folded into the grid) and the factor of its odd extension.
+__device__ __forceinline__ size_t plane_base(int z, int n) {
+  int s = 1;
+  int zf = fold(z, n, s);
+  zf = (zf > 0 && zf < n - 1) ? zf : 1;
+  return (size_t)zf * n * n;
+}
+template <typename T>
+__device__ __forceinline__ T plane_mul(int z, int n) {
+  int s = 1;
+  const int zf = fold(z, n, s);
+  return (zf > 0 && zf < n - 1) ? T(s) : T(0);
+}
+
+template <typename T, typename TO, int MODE, bool HAS_U>
+__global__ __launch_bounds__(256) void k_xsweep3d(const T *__restrict__ f, const T *__restrict__ u,
+                                                  TO *__restrict__ out, int n, int zchunk, KOp<T> op,
+                                                  double *__restrict__ partials,
+                                                  const int *__restrict__ done) {
+  constexpr int R = 2, PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int NH = PS - TX * TY;  // halo cells of a plane
+  static_assert(NH <= 256, "one halo cell per thread");
+  __shared__ T plane[2][PS];
+  if (stopped(done)) return;
+  const Block3 blk = block3();
+  const int x0 = blk.x * TX, y0 = blk.y * TY;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x <= n - 1 && y <= n - 1;
+  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
+  Col3<T> cu, ch;
+  cu.init(x, y, n);
+  // this thread's halo cell (threads 0 .. NH-1): two rows above, two below, two columns
+  // on each side of the middle rows
+  int hx = 0, hy = 0;
+  const bool has_halo = threadIdx.x < NH;
+  {
+    const int h = threadIdx.x;
+    if (h < 2 * PX) {
+      hy = h / PX;
+      hx = h % PX;
+    } else if (h < 4 * PX) {
+      hy = PY - R + (h - 2 * PX) / PX;
+      hx = (h - 2 * PX) % PX;
+    } else {
+      const int hh = h - 4 * PX;
+      hy = R + hh / (2 * R);
+      const int c = hh % (2 * R);
+      hx = c < R ? c : PX - 2 * R + c;
+    }
+  }
+  // threads without a halo cell load their own column again (a line already in cache)
+  if (has_halo)
+    ch.init(x0 - R + hx, y0 - R + hy, n);
+  else
+    ch = cu;
+  const int pown = (ty + R) * PX + tx + R, phal = hy * PX + hx;
+  const size_t fcol = (size_t)(xin ? y : 1) * n + (xin ? x : 1);
+  const T *up = HAS_U ? u : f;  // a valid address when there is no u
+  const int zlast = z0 + round_up8(z1 - z0) - 1;
+  const bool fast = z0 - R > 0 && zlast + 6 < n - 1;
+
+  double acc = 0.0;
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
+    T ur[kZR], fr[4], hr[4];  // raw loads: u of this column at z-2+k, f and the halo at z+k
+#pragma unroll
+    for (int k = 0; k < kZR; ++k) ur[k] = HAS_U ? up[base(z0 - 2 + k) + cu.off] : T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fr[k] = f[(FAST ? (size_t)(z0 + k) * n * n : base(z0 + k)) + fcol];
+      hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
+    }
+    // Drain the prologue once: the loop header then sees only the back edge's loads and
+    // waits for exactly the slot it reads (s_waitcnt vmcnt(0), other counters untouched).
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    const KOp<T> kop = op;
+    auto step = [&](const int z, auto pc) {
+      constexpr int P = decltype(pc)::value;
+      const T m = cu.mul;
+      T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
+      T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
+      T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
+      T fz = fr[P % 4], hz = hr[P % 4] * (ch.mul * zm(z));
+      asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
+      __builtin_amdgcn_sched_barrier(0);
+      if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];  // the slot of plane z-2
+      fr[P % 4] = f[base(z + 4) + fcol];
+      if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
+      T *pl = plane[P & 1];
+      pl[pown] = uc;
+      if (has_halo) pl[phal] = hz;
+      __syncthreads();
+      const T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
+                                     ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
+                               kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
+                                         ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
+                                         ((uc - um2) + (uc - up2)))
+                         : T(0);
+      const bool inside = own && xin && z > 0 && z < n - 1;
+      const T r = inside ? fz - lu : T(0);
+      if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
+      // Every lane stores, so no store sits under a branch.  A lane past the grid, or a
+      // step past the last plane, lands on the boundary (clamped address) and stores its
+      // value there, 0; a step past this block's planes stores the value the owning
+      // block stores too (same inputs, same arithmetic).
+      const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
+      if (MODE == kSweep) out[id] = (TO)(inside ? uc + kop.om_d * r : T(0));
+      if (MODE == kResidual) out[id] = (TO)r;
+    };
+    for (int z = z0; z < z1; z += kZR)
+      static_for<kZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+  if (partials != nullptr) {
+    const double tot = block_sum256(acc);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
 // ------------------------------------------------- defect + full weighting ----
 // Block: coarse tile (TX/2) x (TY/2) at coarse planes [K0, K1).  The defect is computed on
 // the fine tile extended by one point (the full-weighting support), kept for three
@@ -349,6 +513,143 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
     rhead = (rhead + 1) % 3;
     __syncthreads();
   }
+}
+
+// ------------------------------------- cross defect + full weighting, z rings ----
+// The radius-2 cross operator.  A block owns a 16 x 3 tile of coarse columns and coarse
+// planes [K0, K1).  The full-weighting support of the tile is 33 x 7 fine columns, one per
+// thread; each keeps its u values at planes z-2 .. z+5 in a ring of registers and its last
+// four defects in another, while plane z of the support plus a two-point halo goes
+// through LDS.  After every odd fine plane 2K+1 the z-weighted defects of planes
+// 2K-1 .. 2K+1 are weighted in x and y through LDS.
+constexpr int kRCX = 16, kRCY = 3;
+constexpr int kRDX = 2 * kRCX + 1, kRDY = 2 * kRCY + 1;  // defect support: 33 x 7
+
+template <typename T, bool HAS_U>
+__global__ __launch_bounds__(256) void k_xrr3d(const T *__restrict__ f, const T *__restrict__ u,
+                                               T *__restrict__ fc, int n, int kchunk, KOp<T> op,
+                                               const int *__restrict__ done) {
+  constexpr int R = 2, PX = kRDX + 2 * R, PY = kRDY + 2 * R, PS = PX * PY;
+  constexpr int ND = kRDX * kRDY, NH = PS - ND;  // defect columns, halo cells
+  static_assert(ND <= 256 && NH <= 256, "one column and one halo cell per thread");
+  __shared__ T plane[2][PS];
+  __shared__ T dz[ND];
+  if (stopped(done)) return;
+  const int nc = (n - 1) / 2 + 1;
+  const Block3 blk = block3();
+  const int I0 = blk.x * kRCX, J0 = blk.y * kRCY;
+  const int X0 = 2 * I0 - 1, Y0 = 2 * J0 - 1;  // defect support origin
+  const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
+  const int t = threadIdx.x;
+  const bool has_col = t < ND;
+  const int dx = has_col ? t % kRDX : 0, dy = has_col ? t / kRDX : 0;
+  Col3<T> cu, ch;
+  cu.init(X0 + dx, Y0 + dy, n);
+  int hx = 0, hy = 0;
+  const bool has_halo = t < NH;
+  if (t < 2 * PX) {
+    hy = t / PX;
+    hx = t % PX;
+  } else if (t < 4 * PX) {
+    hy = PY - R + (t - 2 * PX) / PX;
+    hx = (t - 2 * PX) % PX;
+  } else {
+    const int hh = t - 4 * PX;
+    hy = R + hh / (2 * R);
+    const int c = hh % (2 * R);
+    hx = c < R ? c : PX - 2 * R + c;
+  }
+  if (has_halo)
+    ch.init(X0 - R + hx, Y0 - R + hy, n);
+  else
+    ch = cu;
+  const int pown = (dy + R) * PX + dx + R, phal = hy * PX + hx;
+  const int fx = X0 + dx, fy = Y0 + dy;
+  const bool fin = has_col && fx > 0 && fx < n - 1 && fy > 0 && fy < n - 1;
+  const size_t fcol = (size_t)(fin ? fy : 1) * n + (fin ? fx : 1);
+  // boundary coarse planes of this block
+  const int ci = t % kRCX, cj = t / kRCX;
+  const int I = I0 + ci, J = J0 + cj;
+  const bool cown = t < kRCX * kRCY && I <= nc - 1 && J <= nc - 1;
+  const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
+  if (cown) {
+    if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
+    if (K1 == nc) fc[((size_t)(nc - 1) * nc + J) * nc + I] = T(0);
+  }
+  const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
+  if (Klo >= Khi) return;
+  const int zs = 2 * Klo - 1;                                // odd
+  const int ze = zs + round_up8(2 * (Khi - Klo) + 1) - 1;    // whole turns of the ring
+  const T *up = HAS_U ? u : f;
+  const bool fast = zs - R > 0 && ze + 6 < n - 1;
+
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
+    T ur[kZR], fr[4], hr[4], dr[4];
+#pragma unroll
+    for (int k = 0; k < kZR; ++k) ur[k] = HAS_U ? up[base(zs - 2 + k) + cu.off] : T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fr[k] = f[base(zs + k) + fcol];
+      hr[k] = HAS_U ? up[base(zs + k) + ch.off] : T(0);
+      dr[k] = T(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // drain the prologue once (see the sweep)
+    const KOp<T> kop = op;
+    auto step = [&](const int z, auto pc) {
+      constexpr int P = decltype(pc)::value;  // z - zs mod 8; z odd exactly when P is even
+      const T m = cu.mul;
+      T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
+      T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
+      T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
+      T fz = fr[P % 4], hz = hr[P % 4] * (ch.mul * zm(z));
+      asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
+      __builtin_amdgcn_sched_barrier(0);
+      if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];
+      fr[P % 4] = f[base(z + 4) + fcol];
+      if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
+      T *pl = plane[P & 1];
+      if (has_col) pl[pown] = uc;
+      if (has_halo) pl[phal] = hz;
+      __syncthreads();
+      const T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
+                                     ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
+                               kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
+                                         ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
+                                         ((uc - um2) + (uc - up2)))
+                         : T(0);
+      dr[P % 4] = fz - lu;  // defect of plane z at this column (used on interior supports only)
+      if constexpr ((P & 1) == 0) {
+        if (z >= zs + 2) {  // z = 2K+1 completes coarse plane K
+          const int K = (z - 1) >> 1;
+          if (has_col)
+            dz[t] = T(0.25) * dr[(P + 2) % 4] + T(0.5) * dr[(P + 3) % 4] + T(0.25) * dr[P % 4];
+          __syncthreads();
+          if (cown && K < Khi) {
+            T sum = T(0);
+            if (cin) {
+#pragma unroll
+              for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) {
+                  const T w = (ox == 0 ? T(0.5) : T(0.25)) * (oy == 0 ? T(0.5) : T(0.25));
+                  sum += w * dz[(2 * cj + 1 + oy) * kRDX + 2 * ci + 1 + ox];
+                }
+            }
+            fc[((size_t)K * nc + J) * nc + I] = sum;
+          }
+        }
+      }
+    };
+    for (int z = zs; z <= ze; z += kZR)
+      static_for<kZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 }
 
 // ---------------------------------------------- interpolation + correction ----
@@ -481,11 +782,11 @@ KOp<T> to_kop3(const LevelOp &op, double omega) {
 constexpr int kMinPlanes = 8, kMaxPlanes = 64, kRounds3d = 4;
 
 template <typename T, typename TO>
-const void *sweep3d_fn(int mode, bool cross) {
+const void *sweep3d_fn(int mode, bool cross, bool has_u) {
   if (cross) {
-    if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 2>;
-    if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 2>;
-    return (const void *)k_sweep3d<T, TO, kNormOnly, 2>;
+    if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true> : (const void *)k_xsweep3d<T, TO, kSweep, false>;
+    if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true> : (const void *)k_xsweep3d<T, TO, kResidual, false>;
+    return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true> : (const void *)k_xsweep3d<T, TO, kNormOnly, false>;
   }
   if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
   if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
@@ -518,23 +819,29 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s) {
   const int tiles = cdiv(n, TX) * cdiv(n, TY);
-  const size_t smem = op.cross ? sweep_smem<T, 2>() : sweep_smem<T, 3>();
-  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross), 256, smem),
-                                                kMinPlanes));
+  const size_t smem = op.cross ? 0 : sweep_smem<T, 3>();
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross, u != nullptr), 256, smem),
+                                                 kMinPlanes)) + kZR - 1) / kZR * kZR;
   const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   const KOp<T> k = to_kop3<T>(op, omega);
-#define MG_S3(MODE, R) \
-  hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, R>), grid, dim3(256), (sweep_smem<T, R>()), s, f, u, out, n, zc, k, partials, done)
   if (op.cross) {
-    if (mode == kSweep) MG_S3(kSweep, 2);
-    else if (mode == kResidual) MG_S3(kResidual, 2);
-    else MG_S3(kNormOnly, 2);
-  } else {
-    if (mode == kSweep) MG_S3(kSweep, 3);
-    else if (mode == kResidual) MG_S3(kResidual, 3);
-    else MG_S3(kNormOnly, 3);
+#define MG_X3(MODE)                                                                          \
+  if (u != nullptr)                                                                          \
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true>), grid, dim3(256), 0, s, f, u, out, n, zc, k, partials, done); \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false>), grid, dim3(256), 0, s, f, u, out, n, zc, k, partials, done);
+    if (mode == kSweep) { MG_X3(kSweep) }
+    else if (mode == kResidual) { MG_X3(kResidual) }
+    else { MG_X3(kNormOnly) }
+#undef MG_X3
+    return hipGetLastError();
   }
+#define MG_S3(MODE) \
+  hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, 3>), grid, dim3(256), (sweep_smem<T, 3>()), s, f, u, out, n, zc, k, partials, done)
+  if (mode == kSweep) MG_S3(kSweep);
+  else if (mode == kResidual) MG_S3(kResidual);
+  else MG_S3(kNormOnly);
 #undef MG_S3
   return hipGetLastError();
 }
@@ -543,16 +850,28 @@ template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s) {
   const int nc = (n - 1) / 2 + 1;
+  if (op.cross) {
+    const int ctiles = cdiv(nc, kRCX) * cdiv(nc, kRCY);
+    const void *fx = u != nullptr ? (const void *)k_xrr3d<T, true> : (const void *)k_xrr3d<T, false>;
+    // coarse planes per band: 4m-1, so that the 8m-1 fine planes of a band fill m turns
+    // of the plane ring but one plane
+    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 256, 0), kMinPlanes / 2));
+    const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
+    const dim3 grid(cdiv(nc, kRCX), cdiv(nc, kRCY), cdiv(nc, kc));
+    const KOp<T> k = to_kop3<T>(op, 1.0);
+    if (u != nullptr)
+      hipLaunchKernelGGL((k_xrr3d<T, true>), grid, dim3(256), 0, s, f, u, fc, n, kc, k, done);
+    else
+      hipLaunchKernelGGL((k_xrr3d<T, false>), grid, dim3(256), 0, s, f, u, fc, n, kc, k, done);
+    return hipGetLastError();
+  }
   const int tiles = cdiv(n, TX) * cdiv(n, TY);
-  const void *fn = op.cross ? (const void *)k_resid_restrict3d<T, 2> : (const void *)k_resid_restrict3d<T, 3>;
-  const size_t smem = op.cross ? rr_smem<T, 2>() : rr_smem<T, 3>();
+  const void *fn = (const void *)k_resid_restrict3d<T, 3>;
+  const size_t smem = rr_smem<T, 3>();
   const int kc = std::min(kMaxPlanes / 2, band_rows(nc, tiles, kRounds3d * resident_blocks(fn, 256, smem), kMinPlanes / 2));
   const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(nc, kc));
   const KOp<T> k = to_kop3<T>(op, 1.0);
-  if (op.cross)
-    hipLaunchKernelGGL((k_resid_restrict3d<T, 2>), grid, dim3(256), (rr_smem<T, 2>()), s, f, u, fc, n, kc, k, done);
-  else
-    hipLaunchKernelGGL((k_resid_restrict3d<T, 3>), grid, dim3(256), (rr_smem<T, 3>()), s, f, u, fc, n, kc, k, done);
+  hipLaunchKernelGGL((k_resid_restrict3d<T, 3>), grid, dim3(256), (rr_smem<T, 3>()), s, f, u, fc, n, kc, k, done);
   return hipGetLastError();
 }
 
