@@ -8,7 +8,8 @@ the FP64 rounding floor), with f and u resident in HBM.  Workloads (--workload):
       omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized
       coarse operators to 9x9 with an exact coarsest solve, FP64.
   poisson3d-513             3D, n = 513, uniform[-1,1] noise smoothed by three
-      neighbour-average passes, V(2,1) (omega = 9/11), mixed precision against FP64.
+      neighbour-average passes, V(2,1) (omega = 9/11), mixed precision (eight FP32
+      cycles per FP64 refinement step) against FP64.
   poisson3d-1025-galerkin-w22  3D, n = 1025, smooth sine series (k <= 8), Galerkin
       coarse operators, W(2,2), mixed against FP64, plus the error of the solution
       against the oracle's 129^3 solve of the same continuous problem.
@@ -33,7 +34,7 @@ WORKLOADS = {
     "poisson2d-4097": dict(dim=2, n=4097, rhs="fourier", coarse=0, gamma=1, nu1=2, nu2=1,
                            precision=0, compare=False, inner=4),
     "poisson3d-513": dict(dim=3, n=513, rhs="noise", coarse=0, gamma=1, nu1=2, nu2=1,
-                          precision=1, compare=True, inner=4),
+                          precision=1, compare=True, inner=8),
     "poisson3d-1025-galerkin-w22": dict(dim=3, n=1025, rhs="sine", coarse=1, gamma=2, nu1=2,
                                         nu2=2, precision=1, compare=True, inner=3, check129=True),
 }

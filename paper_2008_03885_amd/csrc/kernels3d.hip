@@ -15,6 +15,7 @@
 // exactly.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -36,15 +37,19 @@ __device__ __forceinline__ int fold(int i, int n, int &sign) {
 
 __device__ __forceinline__ int round_up8(int a) { return (a + 7) / 8 * 8; }
 
-__device__ double block_sum256(double v) {
-  __shared__ double ws[4];
+// Sum over a block of NT threads (valid in thread 0).
+template <int NT>
+__device__ double block_sum(double v) {
+  __shared__ double ws[NT / 64];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
   __syncthreads();
   double t = 0.0;
-  if (threadIdx.x == 0) t = ws[0] + ws[1] + ws[2] + ws[3];
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) t += ws[w];
   return t;
 }
+__device__ double block_sum256(double v) { return block_sum<256>(v); }
 
 // Cooperative loader of one z-plane of a PX x PY region with origin (gx0, gy0): each
 // thread owns up to Q positions; their (x, y) reflection is fixed, the z part is
@@ -261,6 +266,20 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 constexpr int kZR = 8;  // planes per loop turn (the u ring); f and halo rings hold 4
 
+// Register rings: the loop of a kernel refills a ring slot right after consuming it, in an
+// unrolled turn that addresses the slots at compile-time positions.  Two rules keep the
+// refills in flight across the loop's back edge:
+//  - a slot is consumed by arithmetic (a product, even by 1), never by a plain copy, so
+//    that the old value is dead when the refill is issued and the refill can land in the
+//    slot's own register (a copy would be tied up in a register move and a wait);
+//  - the prologue's loads are pinned before the loop (hold_regs), so that the loop header
+//    does not wait for loads the compiler would otherwise sink to the loop entry.
+template <typename T, int N>
+__device__ __forceinline__ void hold_regs(T (&r)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) asm volatile("" : "+v"(r[k]));
+}
+
 // A grid column (x, y): folded address and the sign of the odd extension (0 on and
 // beyond the boundary).
 template <typename T>
@@ -290,20 +309,20 @@ __device__ __forceinline__ T plane_mul(int z, int n) {
   return (zf > 0 && zf < n - 1) ? T(s) : T(0);
 }
 
-template <typename T, typename TO, int MODE, bool HAS_U>
-__global__ __launch_bounds__(256) void k_xsweep3d(const T *__restrict__ f, const T *__restrict__ u,
+template <typename T, typename TO, int MODE, bool HAS_U, int XW>
+__global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, const T *__restrict__ u,
                                                   TO *__restrict__ out, int n, int zchunk, KOp<T> op,
                                                   double *__restrict__ partials,
                                                   const int *__restrict__ done) {
-  constexpr int R = 2, PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
-  constexpr int NH = PS - TX * TY;  // halo cells of a plane
-  static_assert(NH <= 256, "one halo cell per thread");
+  constexpr int NT = XW * TY, R = 2, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int NH = PS - NT;  // halo cells of a plane
+  static_assert(NH <= NT, "one halo cell per thread");
   __shared__ T plane[2][PS];
   if (stopped(done)) return;
   const Block3 blk = block3();
-  const int x0 = blk.x * TX, y0 = blk.y * TY;
+  const int x0 = blk.x * XW, y0 = blk.y * TY;
   const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int tx = threadIdx.x % XW, ty = threadIdx.x / XW;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x <= n - 1 && y <= n - 1;
   const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
@@ -352,17 +371,18 @@ __global__ __launch_bounds__(256) void k_xsweep3d(const T *__restrict__ f, const
       fr[k] = f[(FAST ? (size_t)(z0 + k) * n * n : base(z0 + k)) + fcol];
       hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
     }
-    // Drain the prologue once: the loop header then sees only the back edge's loads and
-    // waits for exactly the slot it reads (s_waitcnt vmcnt(0), other counters untouched).
-    __builtin_amdgcn_s_waitcnt(0x0f70);
+    hold_regs(ur);
+    hold_regs(fr);
+    hold_regs(hr);
     const KOp<T> kop = op;
+    const T fmask = xin ? T(1) : T(0);
     auto step = [&](const int z, auto pc) {
       constexpr int P = decltype(pc)::value;
       const T m = cu.mul;
       T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
       T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
       T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
-      T fz = fr[P % 4], hz = hr[P % 4] * (ch.mul * zm(z));
+      T fz = fr[P % 4] * fmask, hz = hr[P % 4] * (ch.mul * zm(z));
       asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
       if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];  // the slot of plane z-2
@@ -397,7 +417,7 @@ __global__ __launch_bounds__(256) void k_xsweep3d(const T *__restrict__ f, const
   else
     run(std::false_type{});
   if (partials != nullptr) {
-    const double tot = block_sum256(acc);
+    const double tot = block_sum<NT>(acc);
     if (threadIdx.x == 0)
       partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
   }
@@ -516,28 +536,26 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
 }
 
 // ------------------------------------- cross defect + full weighting, z rings ----
-// The radius-2 cross operator.  A block owns a 16 x 3 tile of coarse columns and coarse
-// planes [K0, K1).  The full-weighting support of the tile is 33 x 7 fine columns, one per
-// thread; each keeps its u values at planes z-2 .. z+5 in a ring of registers and its last
-// four defects in another, while plane z of the support plus a two-point halo goes
-// through LDS.  After every odd fine plane 2K+1 the z-weighted defects of planes
-// 2K-1 .. 2K+1 are weighted in x and y through LDS.
-constexpr int kRCX = 16, kRCY = 3;
-constexpr int kRDX = 2 * kRCX + 1, kRDY = 2 * kRCY + 1;  // defect support: 33 x 7
-
-template <typename T, bool HAS_U>
-__global__ __launch_bounds__(256) void k_xrr3d(const T *__restrict__ f, const T *__restrict__ u,
-                                               T *__restrict__ fc, int n, int kchunk, KOp<T> op,
-                                               const int *__restrict__ done) {
+// The radius-2 cross operator.  A block owns a CX x CY tile of coarse columns and coarse
+// planes [K0, K1).  The full-weighting support of the tile is (2CX+1) x (2CY+1) fine
+// columns, one per thread; each keeps its u values at planes z-2 .. z+5 in a ring of
+// registers and its last four defects in another, while plane z of the support plus a
+// two-point halo goes through LDS.  After every odd fine plane 2K+1 the z-weighted
+// defects of planes 2K-1 .. 2K+1 are weighted in x and y through LDS.
+template <typename T, bool HAS_U, int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *__restrict__ u,
+                                              T *__restrict__ fc, int n, int kchunk, KOp<T> op,
+                                              const int *__restrict__ done) {
+  constexpr int kRDX = 2 * CX + 1, kRDY = 2 * CY + 1;
   constexpr int R = 2, PX = kRDX + 2 * R, PY = kRDY + 2 * R, PS = PX * PY;
   constexpr int ND = kRDX * kRDY, NH = PS - ND;  // defect columns, halo cells
-  static_assert(ND <= 256 && NH <= 256, "one column and one halo cell per thread");
+  static_assert(ND <= NT && NH <= NT, "one column and one halo cell per thread");
   __shared__ T plane[2][PS];
   __shared__ T dz[ND];
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
   const Block3 blk = block3();
-  const int I0 = blk.x * kRCX, J0 = blk.y * kRCY;
+  const int I0 = blk.x * CX, J0 = blk.y * CY;
   const int X0 = 2 * I0 - 1, Y0 = 2 * J0 - 1;  // defect support origin
   const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
   const int t = threadIdx.x;
@@ -568,9 +586,9 @@ __global__ __launch_bounds__(256) void k_xrr3d(const T *__restrict__ f, const T 
   const bool fin = has_col && fx > 0 && fx < n - 1 && fy > 0 && fy < n - 1;
   const size_t fcol = (size_t)(fin ? fy : 1) * n + (fin ? fx : 1);
   // boundary coarse planes of this block
-  const int ci = t % kRCX, cj = t / kRCX;
+  const int ci = t % CX, cj = t / CX;
   const int I = I0 + ci, J = J0 + cj;
-  const bool cown = t < kRCX * kRCY && I <= nc - 1 && J <= nc - 1;
+  const bool cown = t < CX * CY && I <= nc - 1 && J <= nc - 1;
   const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
   if (cown) {
     if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
@@ -596,15 +614,18 @@ __global__ __launch_bounds__(256) void k_xrr3d(const T *__restrict__ f, const T 
       hr[k] = HAS_U ? up[base(zs + k) + ch.off] : T(0);
       dr[k] = T(0);
     }
-    __builtin_amdgcn_s_waitcnt(0x0f70);  // drain the prologue once (see the sweep)
+    hold_regs(ur);
+    hold_regs(fr);
+    hold_regs(hr);
     const KOp<T> kop = op;
+    const T fmask = fin ? T(1) : T(0);
     auto step = [&](const int z, auto pc) {
       constexpr int P = decltype(pc)::value;  // z - zs mod 8; z odd exactly when P is even
       const T m = cu.mul;
       T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
       T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
       T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
-      T fz = fr[P % 4], hz = hr[P % 4] * (ch.mul * zm(z));
+      T fz = fr[P % 4] * fmask, hz = hr[P % 4] * (ch.mul * zm(z));
       asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
       if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];
@@ -653,59 +674,65 @@ __global__ __launch_bounds__(256) void k_xrr3d(const T *__restrict__ f, const T 
 }
 
 // ---------------------------------------------- interpolation + correction ----
-// Fine tile TX x TY at planes [z0, z1).  For each coarse plane the coarse region around
-// the tile is staged in LDS, interpolated in x and y at this thread's fine column, and
-// kept in a window of four coarse planes; the z interpolation completes the value.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_prolong3d(const T *__restrict__ v, const T *uin, T *uout,
-                                                   int n, int zchunk, const int *__restrict__ done) {
-  constexpr int CX = TX / 2 + 4, CY = TY / 2 + 4, CS = CX * CY;
-  __shared__ T cpl[2][CS];
+// Fine tile XW x TY at planes [z0, z1), one column per thread.  Each coarse plane of the
+// region around the tile goes through LDS once and is interpolated in x and y at every
+// fine column; the four coarse planes around the current fine plane stay in registers
+// for the z interpolation.  Coarse planes are loaded four planes (eight fine steps) and
+// the fine u eight planes ahead, into register rings that a fully unrolled turn of eight
+// fine planes addresses at compile-time positions.
+//
+// Every lane stores every step, so that no store sits under a branch: lanes past the grid
+// and steps past the last plane land on the boundary (clamped address) and store 0 there.
+// Bands other than the last are whole turns (the host rounds the band to 8 planes), so no
+// block stores outside its own planes and uout may be uin.
+template <typename T, int P, int XW>
+__global__ __launch_bounds__(XW * TY) void k_prolong3d(const T *__restrict__ v, const T *uin, T *uout,
+                                                      int n, int zchunk, const int *__restrict__ done) {
+  constexpr int NT = XW * TY, CX = XW / 2 + 4, CY = TY / 2 + 4, CS = CX * CY;
+  static_assert(CS <= NT, "one coarse point per thread");
+  __shared__ T cpl[2][CS + 1];  // the last slot takes the stores of threads past CS
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
   const Block3 blk = block3();
-  const int x0 = blk.x * TX, y0 = blk.y * TY;
-  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int x0 = blk.x * XW, y0 = blk.y * TY;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);  // z0 even (zchunk is)
+  const int tx = threadIdx.x % XW, ty = threadIdx.x / XW;
   const int x = x0 + tx, y = y0 + ty;
   const int Ib = x0 / 2 - 1, Jb = y0 / 2 - 1;  // coarse region origin
-  // coarse loader for the CX x CY region
-  int coff = 0;
+  const bool xyin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
+  const size_t col = (size_t)min(y, n - 1) * n + min(x, n - 1);
+  // this thread's coarse point of the region (threads below CS)
+  const bool has_c = threadIdx.x < CS;
+  const int cslot = has_c ? (int)threadIdx.x : CS;
+  int coff = nc + 1;
   T cmul = T(0);
-  {
-    const int e = threadIdx.x;
-    if (e < CS) {
-      int s = 1;
-      const int xf = fold(Ib + e % CX, nc, s), yf = fold(Jb + e / CX, nc, s);
-      const bool ok = xf > 0 && xf < nc - 1 && yf > 0 && yf < nc - 1;
-      coff = ok ? yf * nc + xf : nc + 1;
-      cmul = ok ? T(s) : T(0);
-    }
+  if (has_c) {
+    int s = 1;
+    const int xf = fold(Ib + (int)threadIdx.x % CX, nc, s), yf = fold(Jb + (int)threadIdx.x / CX, nc, s);
+    const bool ok = xf > 0 && xf < nc - 1 && yf > 0 && yf < nc - 1;
+    coff = ok ? yf * nc + xf : nc + 1;
+    cmul = ok ? T(s) : T(0);
   }
-  auto cload = [&](int K) -> T {
+  auto cbase = [&](int K) -> size_t {
     int s = 1;
     int kf = fold(K, nc, s);
     kf = (kf > 0 && kf < nc - 1) ? kf : 1;
-    return v[(size_t)kf * nc * nc + coff];
+    return (size_t)kf * nc * nc;
   };
   auto cmulz = [&](int K) -> T {
     int s = 1;
     const int kf = fold(K, nc, s);
     return (kf > 0 && kf < nc - 1) ? T(s) : T(0);
   };
-  auto w1d = [&](int fine, T (&w)[4]) {  // weights of coarse fine/2-1 .. fine/2+2 (floor)
-    if ((fine & 1) == 0) {
-      w[0] = T(0); w[1] = T(1); w[2] = T(0); w[3] = T(0);
-    } else if (P == 3) {
-      w[0] = T(-0.0625); w[1] = T(0.5625); w[2] = T(0.5625); w[3] = T(-0.0625);
-    } else {
-      w[0] = T(0); w[1] = T(0.5); w[2] = T(0.5); w[3] = T(0);
-    }
-  };
+  // 1D weights of coarse points fine/2-1 .. fine/2+2 for an odd fine index
+  constexpr T c0 = P == 3 ? T(-0.0625) : T(0), c1 = P == 3 ? T(0.5625) : T(0.5);
   T wx[4], wy[4];
-  w1d(x, wx);
-  w1d(y, wy);
-  const int lx = (x >> 1) - 1 - Ib, ly = (y >> 1) - 1 - Jb;  // local coarse index of window start
+  {
+    const bool ox = x & 1, oy = y & 1;
+    wx[0] = ox ? c0 : T(0); wx[1] = ox ? c1 : T(1); wx[2] = ox ? c1 : T(0); wx[3] = ox ? c0 : T(0);
+    wy[0] = oy ? c0 : T(0); wy[1] = oy ? c1 : T(1); wy[2] = oy ? c1 : T(0); wy[3] = oy ? c0 : T(0);
+  }
+  const int lx = (x >> 1) - 1 - Ib, ly = (y >> 1) - 1 - Jb;  // local start of the 4 x 4 window
   auto interp_xy = [&](const T *pl) -> T {
     T s = T(0);
 #pragma unroll
@@ -717,48 +744,57 @@ __global__ __launch_bounds__(256) void k_prolong3d(const T *__restrict__ v, cons
     }
     return s;
   };
-  T pw[4];
-  int kb = (z0 >> 1) - 1;  // coarse plane of pw[0]
-  int buf = 0;
-  T cnext = threadIdx.x < CS ? cload(kb) : T(0);
+  const int kb0 = z0 / 2 - 1;  // first coarse plane of the window
+  const int zlast = z0 + round_up8(z1 - z0) - 1;
+  T pw[4], cr[4], ur[8];
+  // prologue: coarse planes kb0 .. kb0+2 into the window (the first advance brings
+  // kb0+3), kb0+3 .. kb0+6 into the coarse ring, fine planes z0 .. z0+7 into the u ring
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (threadIdx.x < CS) {
-      const T m = cmul * cmulz(kb + k);
-      cpl[buf][threadIdx.x] = m != T(0) ? cnext * m : T(0);
-    }
-    if (threadIdx.x < CS) cnext = cload(kb + k + 1);
+  for (int k = 0; k < 4; ++k) cr[k] = v[cbase(kb0 + 3 + k) + coff];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ur[k] = uin[(size_t)min(z0 + k, n - 1) * n * n + col];
+  pw[0] = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T c = v[cbase(kb0 + k) + coff];
+    const T m = cmul * cmulz(kb0 + k);
+    cpl[k & 1][cslot] = m != T(0) ? c * m : T(0);
     __syncthreads();
-    pw[k] = interp_xy(cpl[buf]);
-    buf ^= 1;
+    pw[k + 1] = interp_xy(cpl[k & 1]);
   }
-  T wz[4];
-  const bool own = x <= n - 1 && y <= n - 1;
-  for (int z = z0; z < z1; ++z) {
-    const int Kc = z >> 1;
-    while (kb < Kc - 1) {
-      if (threadIdx.x < CS) {
-        const T m = cmul * cmulz(kb + 4);
-        cpl[buf][threadIdx.x] = m != T(0) ? cnext * m : T(0);
-        cnext = cload(kb + 5);
-      }
+  __syncthreads();  // the first advance writes cpl[0] again
+  hold_regs(cr);
+  hold_regs(ur);
+  auto step = [&](const int z, auto pc) {
+    constexpr int Q = decltype(pc)::value;  // z - z0 mod 8; z even exactly when Q is
+    // A ring slot is consumed by arithmetic before its refill is issued, so that the
+    // refill can land in the same register (a plain copy would keep the old value alive
+    // across the load and cost a register move, and a wait, at the loop's back edge).
+    if constexpr ((Q & 1) == 0) {
+      // advance the window to coarse planes z/2-1 .. z/2+2
+      const int K = z / 2 + 2;
+      constexpr int S = Q / 2;  // ring slot of plane K
+      const T m = cmul * cmulz(K);
+      const T cv = m != T(0) ? cr[S] * m : T(0);
+      __builtin_amdgcn_sched_barrier(0);
+      cr[S] = v[cbase(K + 4) + coff];
+      cpl[S & 1][cslot] = cv;
       __syncthreads();
-      const T nv = interp_xy(cpl[buf]);
-      buf ^= 1;
+      const T nv = interp_xy(cpl[S & 1]);
       pw[0] = pw[1];
       pw[1] = pw[2];
       pw[2] = pw[3];
       pw[3] = nv;
-      ++kb;
     }
-    w1d(z, wz);
-    const T val = wz[0] * pw[0] + wz[1] * pw[1] + wz[2] * pw[2] + wz[3] * pw[3];
-    if (own) {
-      const size_t id = ((size_t)z * n + y) * n + x;
-      const bool inside = x > 0 && x < n - 1 && y > 0 && y < n - 1 && z > 0 && z < n - 1;
-      uout[id] = inside ? uin[id] + val : T(0);
-    }
-  }
+    const T val = (Q & 1) == 0 ? pw[1] : c0 * pw[0] + c1 * pw[1] + c1 * pw[2] + c0 * pw[3];
+    const bool inside = xyin && z > 0 && z < n - 1;
+    const T res = inside ? ur[Q] + val : T(0);
+    __builtin_amdgcn_sched_barrier(0);
+    ur[Q] = uin[(size_t)min(z + 8, n - 1) * n * n + col];
+    uout[(size_t)min(z, n - 1) * n * n + col] = res;
+  };
+  for (int z = z0; z <= zlast; z += 8)
+    static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
 }
 
 int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
@@ -781,13 +817,27 @@ KOp<T> to_kop3(const LevelOp &op, double omega) {
 // blocks per CU in flight beat one long march each).
 constexpr int kMinPlanes = 8, kMaxPlanes = 64, kRounds3d = 4;
 
+// Whether a level takes the wide tiles (64 fine columns) in the cross kernels: rows of
+// 256 bytes and more keep the HBM pages of a plane busy on the large levels, while the
+// narrow tiles give more blocks on the small ones.  Environment variable `var` = 0 or 1
+// forces the choice.
+template <typename T>
+bool wide_tiles(int n, const char *var) {
+  const char *e = getenv(var);
+  if (e != nullptr && *e != 0) return atoi(e) != 0;
+  return (size_t)n * n * n * sizeof(T) >= ((size_t)96 << 20);
+}
+
+template <typename T, typename TO, int XW>
+const void *xsweep3d_fn(int mode, bool has_u) {
+  if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW>;
+  if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW>;
+  return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW>;
+}
+
 template <typename T, typename TO>
-const void *sweep3d_fn(int mode, bool cross, bool has_u) {
-  if (cross) {
-    if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true> : (const void *)k_xsweep3d<T, TO, kSweep, false>;
-    if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true> : (const void *)k_xsweep3d<T, TO, kResidual, false>;
-    return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true> : (const void *)k_xsweep3d<T, TO, kNormOnly, false>;
-  }
+const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw) {
+  if (cross) return xw == 64 ? xsweep3d_fn<T, TO, 64>(mode, has_u) : xsweep3d_fn<T, TO, 32>(mode, has_u);
   if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
   if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
   return (const void *)k_sweep3d<T, TO, kNormOnly, 3>;
@@ -818,22 +868,29 @@ template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s) {
-  const int tiles = cdiv(n, TX) * cdiv(n, TY);
+  const int xw = op.cross && wide_tiles<T>(n, "MG_X3_W") ? 64 : TX, nt = xw * TY;
+  const int tiles = cdiv(n, xw) * cdiv(n, TY);
   const size_t smem = op.cross ? 0 : sweep_smem<T, 3>();
-  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross, u != nullptr), 256, smem),
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross, u != nullptr, xw), nt, smem),
                                                  kMinPlanes)) + kZR - 1) / kZR * kZR;
-  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
+  const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   const KOp<T> k = to_kop3<T>(op, omega);
   if (op.cross) {
-#define MG_X3(MODE)                                                                          \
+#define MG_X3(MODE, XW)                                                                      \
   if (u != nullptr)                                                                          \
-    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true>), grid, dim3(256), 0, s, f, u, out, n, zc, k, partials, done); \
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
   else                                                                                       \
-    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false>), grid, dim3(256), 0, s, f, u, out, n, zc, k, partials, done);
-    if (mode == kSweep) { MG_X3(kSweep) }
-    else if (mode == kResidual) { MG_X3(kResidual) }
-    else { MG_X3(kNormOnly) }
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
+    if (xw == 64) {
+      if (mode == kSweep) { MG_X3(kSweep, 64) }
+      else if (mode == kResidual) { MG_X3(kResidual, 64) }
+      else { MG_X3(kNormOnly, 64) }
+    } else {
+      if (mode == kSweep) { MG_X3(kSweep, 32) }
+      else if (mode == kResidual) { MG_X3(kResidual, 32) }
+      else { MG_X3(kNormOnly, 32) }
+    }
 #undef MG_X3
     return hipGetLastError();
   }
@@ -851,18 +908,34 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
                                     const int *done, hipStream_t s) {
   const int nc = (n - 1) / 2 + 1;
   if (op.cross) {
-    const int ctiles = cdiv(nc, kRCX) * cdiv(nc, kRCY);
-    const void *fx = u != nullptr ? (const void *)k_xrr3d<T, true> : (const void *)k_xrr3d<T, false>;
+    // 16 x 3 coarse columns per 256-thread block on the small levels, 16 x 7 per 512
+    // threads from 257^3 up (support 33 x 15, 90% of it owned; wider or larger tiles
+    // measured slower).  MG_XRR_TALL = 0 or 1 forces the choice.
+    bool tall = n >= 257;
+    if (const char *e = getenv("MG_XRR_TALL")) {
+      if (*e != 0) tall = atoi(e) != 0;
+    }
+    const int cx = 16, cy = tall ? 7 : 3, nt = tall ? 512 : 256;
+    const int ctiles = cdiv(nc, cx) * cdiv(nc, cy);
+    const void *fx = tall ? (u != nullptr ? (const void *)k_xrr3d<T, true, 16, 7, 512> : (const void *)k_xrr3d<T, false, 16, 7, 512>)
+                          : (u != nullptr ? (const void *)k_xrr3d<T, true, 16, 3, 256> : (const void *)k_xrr3d<T, false, 16, 3, 256>);
     // coarse planes per band: 4m-1, so that the 8m-1 fine planes of a band fill m turns
     // of the plane ring but one plane
-    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 256, 0), kMinPlanes / 2));
+    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, nt, 0), kMinPlanes / 2));
     const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
-    const dim3 grid(cdiv(nc, kRCX), cdiv(nc, kRCY), cdiv(nc, kc));
+    const dim3 grid(cdiv(nc, cx), cdiv(nc, cy), cdiv(nc, kc));
     const KOp<T> k = to_kop3<T>(op, 1.0);
-    if (u != nullptr)
-      hipLaunchKernelGGL((k_xrr3d<T, true>), grid, dim3(256), 0, s, f, u, fc, n, kc, k, done);
-    else
-      hipLaunchKernelGGL((k_xrr3d<T, false>), grid, dim3(256), 0, s, f, u, fc, n, kc, k, done);
+#define MG_XRR(CX, CY, NT)                                                                  \
+  if (u != nullptr)                                                                         \
+    hipLaunchKernelGGL((k_xrr3d<T, true, CX, CY, NT>), grid, dim3(nt), 0, s, f, u, fc, n, kc, k, done); \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_xrr3d<T, false, CX, CY, NT>), grid, dim3(nt), 0, s, f, u, fc, n, kc, k, done);
+    if (tall) {
+      MG_XRR(16, 7, 512)
+    } else {
+      MG_XRR(16, 3, 256)
+    }
+#undef MG_XRR
     return hipGetLastError();
   }
   const int tiles = cdiv(n, TX) * cdiv(n, TY);
@@ -878,14 +951,22 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
 template <typename T>
 hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
                                      const int *done, hipStream_t s) {
-  const int tiles = cdiv(n, TX) * cdiv(n, TY);
-  const void *fn = prolong == 3 ? (const void *)k_prolong3d<T, 3> : (const void *)k_prolong3d<T, 1>;
-  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, 256, 0), kMinPlanes));
-  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(n, zc));
-  if (prolong == 3)
-    hipLaunchKernelGGL((k_prolong3d<T, 3>), grid, dim3(256), 0, s, v, uin, uout, n, zc, done);
-  else
-    hipLaunchKernelGGL((k_prolong3d<T, 1>), grid, dim3(256), 0, s, v, uin, uout, n, zc, done);
+  const int xw = wide_tiles<T>(n, "MG_P3_W") ? 64 : TX, nt = xw * TY;
+  const int tiles = cdiv(n, xw) * cdiv(n, TY);
+  const void *fn = xw == 64 ? (prolong == 3 ? (const void *)k_prolong3d<T, 3, 64> : (const void *)k_prolong3d<T, 1, 64>)
+                            : (prolong == 3 ? (const void *)k_prolong3d<T, 3, TX> : (const void *)k_prolong3d<T, 1, TX>);
+  // bands of whole turns (8 planes): no block stores outside its planes
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, nt, 0), kMinPlanes)) + 7) / 8 * 8;
+  const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
+#define MG_P3(PP, XW) hipLaunchKernelGGL((k_prolong3d<T, PP, XW>), grid, dim3(nt), 0, s, v, uin, uout, n, zc, done)
+  if (xw == 64) {
+    if (prolong == 3) MG_P3(3, 64);
+    else MG_P3(1, 64);
+  } else {
+    if (prolong == 3) MG_P3(3, TX);
+    else MG_P3(1, TX);
+  }
+#undef MG_P3
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 // frame.  One defect scratch array of the top level's size is shared by all levels.
 // Rediscretized levels use the cross stencil directly; Galerkin levels walk a list of
 // non-centre stencil entries in the difference form sum_e c_e (u(x + o_e) - u(x)).
+#include <algorithm>
 #include <cmath>
 
 #include "mg_internal.h"
@@ -216,17 +217,30 @@ struct Tail {
     __syncthreads();
     ghosts(l);
   }
-  // v = A^{-1} f on the coarsest level (FP64 sums), staged in the defect scratch (free here)
+  // v = A^{-1} f on the coarsest level (FP64 sums).  The interior right-hand side is
+  // packed into the defect scratch first (row-major interior order, the order of A's
+  // unknowns); two adjacent lanes share a row of A^{-1}, each summing one half of the
+  // columns, and add their halves with a lane shuffle.  The result goes to the second
+  // half of the scratch before u is rewritten.
   __device__ __forceinline__ void coarsest(int l) const {
     const int n = lv[l].n, q = n - 2;
-    T *v = lds + scratch;
-    for (int r = threadIdx.x; r < m; r += NT) {
+    T *fv = lds + scratch, *v = fv + m;
+    for (int c = threadIdx.x; c < m; c += NT) {
+      const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
+      fv[c] = lds[lv[l].f + didx(l, ci, cj, ck)];
+    }
+    __syncthreads();
+    const int half = (m + 1) / 2, h = threadIdx.x & 1;
+    const int c0 = h * half, c1 = h ? m : half;
+    for (int r0 = 0; r0 < m; r0 += NT / 2) {
+      const int r = r0 + (threadIdx.x >> 1);
+      const int rr = r < m ? r : m - 1;  // lanes past the last row repeat it (result unused)
+      const double *col = ainv_t + rr;
       double val = 0.0;
-      for (int c = 0; c < m; ++c) {
-        const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
-        val += ainv_t[(size_t)c * m + r] * (double)lds[lv[l].f + didx(l, ci, cj, ck)];
-      }
-      v[r] = (T)val;
+#pragma unroll 8
+      for (int c = c0; c < c1; ++c) val += col[(size_t)c * m] * (double)fv[c];
+      val += __shfl_xor(val, 1);
+      if (h == 0 && r < m) v[r] = (T)val;
     }
     each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
     __syncthreads();
@@ -365,10 +379,12 @@ size_t tail_scratch_offset(int dim, int G, const int *ns, int levels) {
   return pts;
 }
 
-// Byte offset of the entry table.
+// Byte offset of the entry table.  The scratch holds the top level's defect, and on the
+// coarsest level the packed right-hand side and the solution (two interior vectors).
 size_t tail_entry_offset(int dim, int G, const int *ns, int levels, size_t es) {
-  const size_t n0 = ns[0];
-  return (tail_scratch_offset(dim, G, ns, levels) + (dim == 3 ? n0 * n0 * n0 : n0 * n0)) * es;
+  const size_t n0 = ns[0], q = ns[levels - 1] - 2;
+  const size_t top = dim == 3 ? n0 * n0 * n0 : n0 * n0, m = dim == 3 ? q * q * q : q * q;
+  return (tail_scratch_offset(dim, G, ns, levels) + std::max(top, 2 * m)) * es;
 }
 
 size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, size_t es) {

@@ -309,6 +309,21 @@ def test_prolong_correct_3d(dim, n, coarse, prolong, level, fp32):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("wide", ["0", "1"])
+@pytest.mark.parametrize("n,prolong", [(33, 3), (65, 3), (65, 1)])
+def test_3d_tile_shapes(n, prolong, wide, fp32, monkeypatch):
+    """The cross kernels' other tile shapes (64-wide sweep and interpolation tiles,
+    16 x 7 coarse defect tiles), which the large levels take, against the oracle on
+    small and ragged grids; and the small-level shapes forced."""
+    for var in ("MG_X3_W", "MG_P3_W", "MG_XRR_TALL"):
+        monkeypatch.setenv(var, wide)
+    test_smooth(3, n, 0, prolong, 0, fp32)
+    test_residual(3, n, 0, prolong, 0, fp32)
+    test_residual_restrict(3, n, 0, prolong, 0, fp32)
+    test_prolong_correct(3, n, 0, prolong, 0, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("coarse,prolong", [(0, 3), (1, 3)])
 def test_coarsest_solve_3d(coarse, prolong, fp32):
     test_coarsest_solve(3, coarse, prolong, fp32)
