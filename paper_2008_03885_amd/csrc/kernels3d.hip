@@ -423,6 +423,186 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   }
 }
 
+// ------------------------------------------- separable (Galerkin) sweep, z rings ----
+// Coarse Galerkin operators are sums of three tensor products of 1D stencils of radius 3,
+// L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as
+//   L u(z) = sum_k b_k P1(z+k) + sum_{k != 0} a_k (P2(z+k) - P2(z)),
+//   P1 = a_x (b_y u) + b_x (a_y u),  P2 = b_x (b_y u)   (in-plane, per plane),
+// each a-stencil in difference form (its coefficients sum to zero).  A block owns an
+// XW x TY tile of columns, one per thread.  Plane q = z+3 of the tile plus a three-point
+// halo goes through LDS; the y pass (b_y u and a_y u over the tile rows and all halo
+// columns) and the x pass give P1(q) and P2(q) at this thread's column, which enter
+// register rings of eight planes; the z pass over the rings completes L u(z).  The u of
+// the own column, the halo cell and f are loaded ahead into register rings as in the
+// cross sweep (same register-ring rules).
+template <typename T, typename TO, int MODE, int XW>
+__global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_gsweep3d(const T *__restrict__ f, const T *__restrict__ u,
+                                                     TO *__restrict__ out, int n, int zchunk, KOp<T> op,
+                                                     double *__restrict__ partials,
+                                                     const int *__restrict__ done) {
+  constexpr int NT = XW * TY, R = 3, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int NH = PS - NT;   // halo cells of a plane
+  constexpr int NYO = PX * TY;  // y-pass outputs: all region columns, the tile's rows
+  static_assert(NH <= NT && NYO <= 2 * NT, "one halo cell and at most two y outputs per thread");
+  __shared__ T upl[PS];
+  __shared__ T yb[NYO], ya[NYO];
+  if (stopped(done)) return;
+  const Block3 blk = block3();
+  const int x0 = blk.x * XW, y0 = blk.y * TY;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
+  const int t = threadIdx.x;
+  const int tx = t % XW, ty = t / XW;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x <= n - 1 && y <= n - 1;
+  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
+  Col3<T> cu, ch;
+  cu.init(x, y, n);
+  int hx = 0, hy = 0;
+  const bool has_halo = t < NH;
+  if (t < R * PX) {
+    hy = t / PX;
+    hx = t % PX;
+  } else if (t < 2 * R * PX) {
+    hy = PY - R + (t - R * PX) / PX;
+    hx = (t - R * PX) % PX;
+  } else {
+    const int hh = t - 2 * R * PX;
+    hy = R + hh / (2 * R);
+    const int c = hh % (2 * R);
+    hx = c < R ? c : PX - 2 * R + c;
+  }
+  if (has_halo)
+    ch.init(x0 - R + hx, y0 - R + hy, n);
+  else
+    ch = cu;
+  const int pown = (ty + R) * PX + tx + R, phal = hy * PX + hx;
+  const size_t fcol = (size_t)(xin ? y : 1) * n + (xin ? x : 1);
+  // y-pass items of this thread: e = t and t + NT (region column e % PX, tile row e / PX)
+  const bool y2 = t + NT < NYO;
+  const int ye0 = (t / PX + R) * PX + t % PX, ye1 = y2 ? ((t + NT) / PX + R) * PX + (t + NT) % PX : ye0;
+  const int xo = ty * PX + tx + R;  // this column in the y-pass outputs
+  const int zlast = z0 + round_up8(z1 - z0) - 1;
+  const bool fast = z0 - R > 0 && zlast + 8 < n - 1;
+
+  double acc = 0.0;
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
+    const KOp<T> kop = op;
+    // ring slots: u and P rings by (plane - (z0-3)) mod 8, halo by the same mod 4, f by
+    // (plane - z0) mod 4
+    T ur[8], hr[4], fr[4], p1r[8], p2r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ur[k] = u[base(z0 - R + k) + cu.off];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hr[k] = u[base(z0 - R + k) + ch.off];
+      fr[k] = f[base(z0 + k) + fcol];
+    }
+    hold_regs(ur);
+    hold_regs(hr);
+    hold_regs(fr);
+    // P1(q), P2(q) at this column from plane q (own value uq, halo value hq)
+    auto inplane = [&](T uq, T hq, T &p1, T &p2) {
+      upl[pown] = uq;
+      if (has_halo) upl[phal] = hq;
+      __syncthreads();
+      {
+        const T c = upl[ye0];
+        T sb = T(0), sa = T(0);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const T v = upl[ye0 + (j - 3) * PX];
+          sb += kop.b[j] * v;
+          if (j != 3) sa += kop.a[j] * (v - c);
+        }
+        yb[t] = sb;
+        ya[t] = sa;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (y2) {
+        const T c = upl[ye1];
+        T sb = T(0), sa = T(0);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const T v = upl[ye1 + (j - 3) * PX];
+          sb += kop.b[j] * v;
+          if (j != 3) sa += kop.a[j] * (v - c);
+        }
+        yb[t + NT] = sb;
+        ya[t + NT] = sa;
+      }
+      __syncthreads();
+      const T c1 = yb[xo];
+      T s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const T vb = yb[xo + i - 3];
+        if (i != 3) s1 += kop.a[i] * (vb - c1);
+        s1 += kop.b[i] * ya[xo + i - 3];
+        s2 += kop.b[i] * vb;
+      }
+      p1 = s1;
+      p2 = s2;
+    };
+    // prologue: P of planes z0-3 .. z0+2 (slots 0..5); the u slots of planes z0-3 .. z0-1
+    // are refilled with planes z0+5 .. z0+7, the halo ring runs ahead by four planes
+    static_for<6>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      const int q = z0 - R + K;
+      T uq = ur[K] * (cu.mul * zm(q)), hq = hr[K % 4] * (ch.mul * zm(q));
+      asm volatile("" : "+v"(uq), "+v"(hq));
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (K < 3) ur[K] = u[base(q + 8) + cu.off];
+      hr[K % 4] = u[base(q + 4) + ch.off];
+      inplane(uq, hq, p1r[K], p2r[K]);
+    });
+    hold_regs(ur);
+    hold_regs(hr);
+    const T fmask = xin ? T(1) : T(0);
+    auto step = [&](const int z, auto pc) {
+      constexpr int P = decltype(pc)::value;  // z - z0 mod 8
+      constexpr int SQ = (P + 6) % 8, SZ = (P + 3) % 8, SH = (P + 2) % 4, SF = P % 4;
+      const T m = cu.mul;
+      T uq = ur[SQ] * (m * zm(z + R)), hq = hr[SH] * (ch.mul * zm(z + R));
+      T uz = ur[SZ] * (m * zm(z)), fz = fr[SF] * fmask;
+      asm volatile("" : "+v"(uq), "+v"(hq), "+v"(uz), "+v"(fz));
+      __builtin_amdgcn_sched_barrier(0);
+      ur[SZ] = u[base(z + 8) + cu.off];
+      hr[SH] = u[base(z + R + 4) + ch.off];
+      fr[SF] = f[base(z + 4) + fcol];
+      inplane(uq, hq, p1r[SQ], p2r[SQ]);
+      // z pass: planes z-3 .. z+3 sit in slots P .. P+6
+      const T c2 = p2r[SZ];
+      T lu = T(0);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        lu += kop.b[k] * p1r[(P + k) % 8];
+        if (k != 3) lu += kop.a[k] * (p2r[(P + k) % 8] - c2);
+      }
+      const bool inside = own && xin && z > 0 && z < n - 1;
+      const T r = inside ? fz - lu : T(0);
+      if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
+      // every lane stores (clamped address; see the cross sweep)
+      const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
+      if (MODE == kSweep) out[id] = (TO)(inside ? uz + kop.om_d * r : T(0));
+      if (MODE == kResidual) out[id] = (TO)r;
+    };
+    for (int z = z0; z < z1; z += 8)
+      static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+  if (partials != nullptr) {
+    const double tot = block_sum<NT>(acc);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
 // ------------------------------------------------- defect + full weighting ----
 // Block: coarse tile (TX/2) x (TY/2) at coarse planes [K0, K1).  The defect is computed on
 // the fine tile extended by one point (the full-weighting support), kept for three
@@ -673,6 +853,198 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
     run(std::false_type{});
 }
 
+// ----------------------- separable (Galerkin) defect + full weighting, z rings ----
+// The defect of the separable operator (applied as in the separable sweep) on the
+// full-weighting support of a CX x CY coarse tile, restricted as in the cross kernel:
+// support columns one per thread, P1/P2 and defect rings in registers, z weighting per
+// column, x and y weighting through LDS after every odd fine plane.
+template <typename T, int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+void k_grr3d(const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc, int n,
+             int kchunk, KOp<T> op, const int *__restrict__ done) {
+  constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, ND = SX * SY;  // support
+  constexpr int R = 3, PX = SX + 2 * R, PY = SY + 2 * R, PS = PX * PY, NH = PS - ND;
+  constexpr int NYO = PX * SY;
+  static_assert(ND <= NT && NH <= NT && NYO <= 2 * NT, "thread mapping");
+  __shared__ T upl[PS];
+  __shared__ T yb[NYO], ya[NYO];
+  __shared__ T dz[ND];
+  if (stopped(done)) return;
+  const int nc = (n - 1) / 2 + 1;
+  const Block3 blk = block3();
+  const int I0 = blk.x * CX, J0 = blk.y * CY;
+  const int X0 = 2 * I0 - 1, Y0 = 2 * J0 - 1;  // support origin
+  const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
+  const int t = threadIdx.x;
+  const bool has_col = t < ND;
+  const int dx = has_col ? t % SX : 0, dy = has_col ? t / SX : 0;
+  Col3<T> cu, ch;
+  cu.init(X0 + dx, Y0 + dy, n);
+  int hx = 0, hy = 0;
+  const bool has_halo = t < NH;
+  if (t < R * PX) {
+    hy = t / PX;
+    hx = t % PX;
+  } else if (t < 2 * R * PX) {
+    hy = PY - R + (t - R * PX) / PX;
+    hx = (t - R * PX) % PX;
+  } else {
+    const int hh = t - 2 * R * PX;
+    hy = R + hh / (2 * R);
+    const int c = hh % (2 * R);
+    hx = c < R ? c : PX - 2 * R + c;
+  }
+  if (has_halo)
+    ch.init(X0 - R + hx, Y0 - R + hy, n);
+  else
+    ch = cu;
+  const int pown = (dy + R) * PX + dx + R, phal = hy * PX + hx;
+  const int fx = X0 + dx, fy = Y0 + dy;
+  const bool fin = has_col && fx > 0 && fx < n - 1 && fy > 0 && fy < n - 1;
+  const size_t fcol = (size_t)(fin ? fy : 1) * n + (fin ? fx : 1);
+  const bool y2 = t + NT < NYO;
+  const int ye0 = t < NYO ? (t / PX + R) * PX + t % PX : R * PX;
+  const int ye1 = y2 ? ((t + NT) / PX + R) * PX + (t + NT) % PX : ye0;
+  const int xo = dy * PX + dx + R;
+  // coarse points of this block
+  const int ci = t % CX, cj = t / CX;
+  const int I = I0 + ci, J = J0 + cj;
+  const bool cown = t < CX * CY && I <= nc - 1 && J <= nc - 1;
+  const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
+  if (cown) {
+    if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
+    if (K1 == nc) fc[((size_t)(nc - 1) * nc + J) * nc + I] = T(0);
+  }
+  const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
+  if (Klo >= Khi) return;
+  const int zs = 2 * Klo - 1;                              // odd
+  const int ze = zs + round_up8(2 * (Khi - Klo) + 1) - 1;  // whole turns of the rings
+  const bool fast = zs - R > 0 && ze + 8 < n - 1;
+
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
+    const KOp<T> kop = op;
+    // ring slots: u and P by (plane - (zs-3)) mod 8, halo by the same mod 4, f and the
+    // defects by (plane - zs) mod 4
+    T ur[8], hr[4], fr[4], dr[4], p1r[8], p2r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ur[k] = u[base(zs - R + k) + cu.off];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hr[k] = u[base(zs - R + k) + ch.off];
+      fr[k] = f[base(zs + k) + fcol];
+      dr[k] = T(0);
+    }
+    hold_regs(ur);
+    hold_regs(hr);
+    hold_regs(fr);
+    auto inplane = [&](T uq, T hq, T &p1, T &p2) {
+      if (has_col) upl[pown] = uq;
+      if (has_halo) upl[phal] = hq;
+      __syncthreads();
+      if (t < NYO) {
+        const T c = upl[ye0];
+        T sb = T(0), sa = T(0);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const T v = upl[ye0 + (j - 3) * PX];
+          sb += kop.b[j] * v;
+          if (j != 3) sa += kop.a[j] * (v - c);
+        }
+        yb[t] = sb;
+        ya[t] = sa;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (y2) {
+        const T c = upl[ye1];
+        T sb = T(0), sa = T(0);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const T v = upl[ye1 + (j - 3) * PX];
+          sb += kop.b[j] * v;
+          if (j != 3) sa += kop.a[j] * (v - c);
+        }
+        yb[t + NT] = sb;
+        ya[t + NT] = sa;
+      }
+      __syncthreads();
+      const T c1 = yb[xo];
+      T s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const T vb = yb[xo + i - 3];
+        if (i != 3) s1 += kop.a[i] * (vb - c1);
+        s1 += kop.b[i] * ya[xo + i - 3];
+        s2 += kop.b[i] * vb;
+      }
+      p1 = s1;
+      p2 = s2;
+    };
+    static_for<6>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      const int q = zs - R + K;
+      T uq = ur[K] * (cu.mul * zm(q)), hq = hr[K % 4] * (ch.mul * zm(q));
+      asm volatile("" : "+v"(uq), "+v"(hq));
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (K < 3) ur[K] = u[base(q + 8) + cu.off];
+      hr[K % 4] = u[base(q + 4) + ch.off];
+      inplane(uq, hq, p1r[K], p2r[K]);
+    });
+    hold_regs(ur);
+    hold_regs(hr);
+    const T fmask = fin ? T(1) : T(0);
+    auto step = [&](const int z, auto pc) {
+      constexpr int P = decltype(pc)::value;  // z - zs mod 8; z odd exactly when P is even
+      constexpr int SQ = (P + 6) % 8, SZ = (P + 3) % 8, SH = (P + 2) % 4, SF = P % 4;
+      T uq = ur[SQ] * (cu.mul * zm(z + R)), hq = hr[SH] * (ch.mul * zm(z + R));
+      T fz = fr[SF] * fmask;
+      asm volatile("" : "+v"(uq), "+v"(hq), "+v"(fz));
+      __builtin_amdgcn_sched_barrier(0);
+      ur[SZ] = u[base(z + 8) + cu.off];  // plane z: used by no later step
+      hr[SH] = u[base(z + R + 4) + ch.off];
+      fr[SF] = f[base(z + 4) + fcol];
+      inplane(uq, hq, p1r[SQ], p2r[SQ]);
+      const T c2 = p2r[SZ];
+      T lu = T(0);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        lu += kop.b[k] * p1r[(P + k) % 8];
+        if (k != 3) lu += kop.a[k] * (p2r[(P + k) % 8] - c2);
+      }
+      dr[SF] = fz - lu;  // defect of plane z (used on interior supports only)
+      if constexpr ((P & 1) == 0) {
+        if (z >= zs + 2) {  // z = 2K+1 completes coarse plane K
+          const int K = (z - 1) >> 1;
+          if (has_col)
+            dz[t] = T(0.25) * dr[(P + 2) % 4] + T(0.5) * dr[(P + 3) % 4] + T(0.25) * dr[P % 4];
+          __syncthreads();
+          if (cown && K < Khi) {
+            T sum = T(0);
+            if (cin) {
+#pragma unroll
+              for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) {
+                  const T w = (ox == 0 ? T(0.5) : T(0.25)) * (oy == 0 ? T(0.5) : T(0.25));
+                  sum += w * dz[(2 * cj + 1 + oy) * SX + 2 * ci + 1 + ox];
+                }
+            }
+            fc[((size_t)K * nc + J) * nc + I] = sum;
+          }
+        }
+      }
+    };
+    for (int z = zs; z <= ze; z += 8)
+      static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+}
+
 // ---------------------------------------------- interpolation + correction ----
 // Fine tile XW x TY at planes [z0, z1), one column per thread.  Each coarse plane of the
 // region around the tile goes through LDS once and is interpolated in x and y at every
@@ -836,8 +1208,23 @@ const void *xsweep3d_fn(int mode, bool has_u) {
 }
 
 template <typename T, typename TO>
+const void *gsweep3d_fn(int mode) {
+  if (mode == kSweep) return (const void *)k_gsweep3d<T, TO, kSweep, 64>;
+  if (mode == kResidual) return (const void *)k_gsweep3d<T, TO, kResidual, 64>;
+  return (const void *)k_gsweep3d<T, TO, kNormOnly, 64>;
+}
+
+// The separable kernel serves the radius-3 operators unless MG_G3_OLD = 1 (the LDS-ring
+// kernel that applies them plane by plane, kept as a second implementation).
+inline bool gsweep_rings() {
+  const char *e = getenv("MG_G3_OLD");
+  return !(e != nullptr && atoi(e) == 1);
+}
+
+template <typename T, typename TO>
 const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw) {
   if (cross) return xw == 64 ? xsweep3d_fn<T, TO, 64>(mode, has_u) : xsweep3d_fn<T, TO, 32>(mode, has_u);
+  if (gsweep_rings()) return gsweep3d_fn<T, TO>(mode);
   if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
   if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
   return (const void *)k_sweep3d<T, TO, kNormOnly, 3>;
@@ -868,15 +1255,26 @@ template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s) {
-  const int xw = op.cross && wide_tiles<T>(n, "MG_X3_W") ? 64 : TX, nt = xw * TY;
+  // a zero initial guess needs no operator: the cross kernel's u-free path serves every
+  // operator (it uses om_d only)
+  const bool xpath = op.cross || u == nullptr, gpath = !xpath && gsweep_rings();
+  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath ? 64 : TX, nt = xpath || gpath ? xw * TY : 256;
   const int tiles = cdiv(n, xw) * cdiv(n, TY);
-  const size_t smem = op.cross ? 0 : sweep_smem<T, 3>();
-  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, op.cross, u != nullptr, xw), nt, smem),
+  const size_t smem = xpath || gpath ? 0 : sweep_smem<T, 3>();
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw), nt, smem),
                                                  kMinPlanes)) + kZR - 1) / kZR * kZR;
   const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   const KOp<T> k = to_kop3<T>(op, omega);
-  if (op.cross) {
+  if (gpath) {
+#define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+    if (mode == kSweep) MG_G3(kSweep);
+    else if (mode == kResidual) MG_G3(kResidual);
+    else MG_G3(kNormOnly);
+#undef MG_G3
+    return hipGetLastError();
+  }
+  if (xpath) {
 #define MG_X3(MODE, XW)                                                                      \
   if (u != nullptr)                                                                          \
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
@@ -907,7 +1305,8 @@ template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s) {
   const int nc = (n - 1) / 2 + 1;
-  if (op.cross) {
+  // the cross kernel also serves every operator on a zero u (the defect is f)
+  if (op.cross || u == nullptr) {
     // 16 x 3 coarse columns per 256-thread block on the small levels, 16 x 7 per 512
     // threads from 257^3 up (support 33 x 15, 90% of it owned; wider or larger tiles
     // measured slower).  MG_XRR_TALL = 0 or 1 forces the choice.
@@ -936,6 +1335,15 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
       MG_XRR(16, 3, 256)
     }
 #undef MG_XRR
+    return hipGetLastError();
+  }
+  if (gsweep_rings()) {
+    const int ctiles = cdiv(nc, 16) * cdiv(nc, 7);
+    const void *fx = (const void *)k_grr3d<T, 16, 7, 512>;
+    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 512, 0), kMinPlanes / 2));
+    const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
+    const dim3 grid(cdiv(nc, 16), cdiv(nc, 7), cdiv(nc, kc));
+    hipLaunchKernelGGL((k_grr3d<T, 16, 7, 512>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
     return hipGetLastError();
   }
   const int tiles = cdiv(n, TX) * cdiv(n, TY);

@@ -324,6 +324,18 @@ def test_3d_tile_shapes(n, prolong, wide, fp32, monkeypatch):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("old", ["0", "1"])
+@pytest.mark.parametrize("n,level", [(33, 1), (65, 1), (65, 2), (129, 1)])
+def test_3d_galerkin_sweep_kernels(n, level, old, fp32, monkeypatch):
+    """Galerkin levels: the separable register-ring kernels (default) and the plane-ring
+    LDS kernels (MG_G3_OLD=1) against the oracle's assembled Galerkin stencils."""
+    monkeypatch.setenv("MG_G3_OLD", old)
+    test_smooth(3, n, 1, 3, level, fp32)
+    test_residual(3, n, 1, 3, level, fp32)
+    test_residual_restrict(3, n, 1, 3, level, fp32)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("coarse,prolong", [(0, 3), (1, 3)])
 def test_coarsest_solve_3d(coarse, prolong, fp32):
     test_coarsest_solve(3, coarse, prolong, fp32)

@@ -226,6 +226,7 @@ CYCLE_CASES_3D = [
     # n, coarse, prolong, nu1, nu2, gamma
     (17, 0, 3, 2, 1, 1), (33, 0, 3, 2, 1, 1), (33, 1, 3, 2, 1, 1), (33, 0, 3, 2, 2, 2),
     (33, 1, 3, 2, 2, 2), (33, 0, 1, 1, 1, 1), (65, 0, 3, 2, 1, 1), (65, 1, 3, 2, 2, 2),
+    (33, 1, 3, 0, 2, 1), (129, 1, 3, 2, 2, 2),
 ]
 
 
