@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -255,7 +256,7 @@ struct mg_ctx {
   int *eoff = nullptr;     // stencil entry lists of every level (tail kernel)
   double *ecoef = nullptr;
   std::vector<int> ent_begin, ent_count;
-  int chunk = 4;
+  int chunk = 0;          // steps per replay chunk; 0: chosen from the measured step time
   int slots = 1;         // independent problems of this size (batched launches, grid.z)
   bool own_top = false;  // level-0 FP64 f and u are the handle's (batches), not the caller's
   std::vector<void *> allocs;
@@ -588,14 +589,29 @@ mg_status fill_result(mg_ctx *c, mg_result *res, mg_status *outcome) {
   return MG_OK;
 }
 
+// Replay policy.  Steps are replayed in chunks, and the host reads the stopping flag of
+// chunk k-1 while chunk k runs, so the device never waits for the host.  Every step
+// replayed after convergence still launches its kernels, which return at once (a few
+// microseconds each: a W-cycle on eight levels is some two thousand launches).  So the
+// chunk is sized from the measured step time to about kChunkSeconds, and steps longer
+// than kSyncStepSeconds are run one at a time with no lookahead: the host turnaround
+// (tens of microseconds) then costs less than one replay past convergence.
+constexpr double kChunkSeconds = 3e-4, kSyncStepSeconds = 2e-3;
+
+double wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 mg_status run(mg_ctx *c, const double *f, double *u, double rtol, int max_steps, int floor_detect,
               mg_result *res) {
   mg_status st = begin_solve(c, f, u, rtol, max_steps, floor_detect);
   if (st != MG_OK) return st;
   const int total = max_steps + 1;
-  int launched = 0, k = 0;
+  int launched = 0, k = 0, chunk = c->chunk > 0 ? c->chunk : 1, prev_cnt = 0;
+  bool lookahead = true;
+  double t_prev = wall_seconds();
   while (launched < total) {
-    const int cnt = std::min(c->chunk, total - launched);
+    const int cnt = std::min(chunk, total - launched);
     for (int i = 0; i < cnt; ++i) {
       st = launch_step(c, f, u);
       if (st != MG_OK) return st;
@@ -604,10 +620,25 @@ mg_status run(mg_ctx *c, const double *f, double *u, double rtol, int max_steps,
     MG_HIP(hipMemcpyAsync(&c->poll[2 * (k & 1)], &c->st->done, 2 * sizeof(int),
                           hipMemcpyDeviceToHost, c->stream));
     MG_HIP(hipEventRecord(c->ev[k & 1], c->stream));
-    if (k > 0) {
+    if (!lookahead) {  // wait for this chunk (one step) at once
+      MG_HIP(hipEventSynchronize(c->ev[k & 1]));
+      if (c->poll[2 * (k & 1)] != 0) break;
+    } else if (k > 0) {
       MG_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
       if (c->poll[2 * ((k - 1) & 1)] != 0) break;
+      // chunk k-1 ran from the end of chunk k-2 (or the start) to now
+      const double t = wall_seconds(), step_s = (t - t_prev) / std::max(prev_cnt, 1);
+      t_prev = t;
+      if (c->chunk == 0) {
+        if (step_s > kSyncStepSeconds) {
+          lookahead = false;
+          chunk = 1;
+        } else {
+          chunk = std::min(8, std::max(1, (int)std::ceil(kChunkSeconds / step_s)));
+        }
+      }
     }
+    prev_cnt = cnt;
     ++k;
   }
   mg_status outcome = MG_OK;
