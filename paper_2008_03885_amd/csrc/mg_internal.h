@@ -202,6 +202,7 @@ struct TailArgs {
   const int *eoff;       // (dx, dy, dz) per entry
   const double *ecoef;   // coefficient per entry
   const double *ainv_t;  // coarsest inverse, transposed, m x m
+  const double *dst;     // coarsest sine table (S, then scaled inverse eigenvalues), or null
   const void *f_top;
   void *u_top;
   const int *done;

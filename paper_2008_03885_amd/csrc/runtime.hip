@@ -120,10 +120,12 @@ LevelOp galerkin(const LevelOp &fine, int dim, int prolong) {
 
 // Dense matrix of the level operator over interior points (odd reflection folded in),
 // inverted by Gauss-Jordan elimination with partial pivoting; returned transposed.
-bool coarsest_inverse(const LevelOp &op, int dim, int n, std::vector<double> &inv_t) {
+// The coarsest operator as a dense m x m matrix over the interior points (x fastest),
+// with the odd reflection of the Dirichlet closure folded in.
+std::vector<double> coarsest_matrix(const LevelOp &op, int dim, int n) {
   const int q = n - 2;
   const int m = dim == 2 ? q * q : q * q * q;
-  std::vector<double> A((size_t)m * m, 0.0), B((size_t)m * m, 0.0);
+  std::vector<double> A((size_t)m * m, 0.0);
   auto coef = [&](int ox, int oy, int oz) {
     // sum over axes of a along the axis times b along the others
     double c = op.a[ox + 3] * op.b[oy + 3];
@@ -157,6 +159,13 @@ bool coarsest_inverse(const LevelOp &op, int dim, int n, std::vector<double> &in
           A[(size_t)row * m + col] += sign * c;
         }
   }
+  return A;
+}
+
+bool coarsest_inverse(const LevelOp &op, int dim, int n, std::vector<double> &inv_t) {
+  const int q = n - 2;
+  const int m = dim == 2 ? q * q : q * q * q;
+  std::vector<double> A = coarsest_matrix(op, dim, n), B((size_t)m * m, 0.0);
   for (int r = 0; r < m; ++r) B[(size_t)r * m + r] = 1.0;
   for (int c = 0; c < m; ++c) {
     int p = c;
@@ -186,6 +195,60 @@ bool coarsest_inverse(const LevelOp &op, int dim, int n, std::vector<double> &in
   inv_t.assign((size_t)m * m, 0.0);
   for (int r = 0; r < m; ++r)
     for (int c = 0; c < m; ++c) inv_t[(size_t)c * m + r] = B[(size_t)r * m + c];
+  return true;
+}
+
+// Sine-transform form of the coarsest solve.  Under the odd-reflection closure every
+// level operator is a symmetric stencil applied alike at every interior point, so the
+// sine modes sin(pi i k / N) (N = n - 1) are its eigenvectors, and with the 1D factors
+// a, b of radius <= 3 the eigenvalue of mode (kx, ky, kz) is
+//   lambda = a^(kx) b^(ky) b^(kz) + b^(kx) a^(ky) b^(kz) + b^(kx) b^(ky) a^(kz),
+//   c^(k) = c_0 + 2 sum_j c_j cos(pi j k / N).
+// Then L^{-1} = (2/N)^d S diag(1/lambda) S with S_ik = sin(pi i k / N) per axis.  The
+// table holds S (q x q) followed by (2/N)^d / lambda for every mode (x fastest).  Each
+// eigenpair is checked against the assembled matrix; false if any fails.
+bool coarsest_dst(const LevelOp &op, int dim, int n, std::vector<double> &tab) {
+  const int q = n - 2, N = n - 1;
+  const int m = dim == 2 ? q * q : q * q * q;
+  const double pi = 3.14159265358979323846;
+  std::vector<double> S((size_t)q * q), ah(q), bh(q);
+  for (int i = 0; i < q; ++i)
+    for (int k = 0; k < q; ++k) S[(size_t)i * q + k] = std::sin(pi * (i + 1) * (k + 1) / N);
+  for (int k = 0; k < q; ++k) {
+    double sa = op.a[3], sb = op.b[3];
+    for (int j = 1; j <= 3; ++j) {
+      if (op.a[3 + j] != op.a[3 - j] || op.b[3 + j] != op.b[3 - j]) return false;  // not symmetric
+      sa += 2.0 * op.a[3 + j] * std::cos(pi * j * (k + 1) / N);
+      sb += 2.0 * op.b[3 + j] * std::cos(pi * j * (k + 1) / N);
+    }
+    ah[k] = sa;
+    bh[k] = sb;
+  }
+  const std::vector<double> A = coarsest_matrix(op, dim, n);
+  const double norm = std::pow(2.0 / N, dim);
+  tab.assign((size_t)q * q + m, 0.0);
+  std::copy(S.begin(), S.end(), tab.begin());
+  std::vector<double> v(m), Av(m);
+  for (int mode = 0; mode < m; ++mode) {
+    const int kx = mode % q, ky = (mode / q) % q, kz = dim == 3 ? mode / (q * q) : 0;
+    double lam = ah[kx] * bh[ky] + bh[kx] * ah[ky];
+    if (dim == 3) lam = ah[kx] * bh[ky] * bh[kz] + bh[kx] * ah[ky] * bh[kz] + bh[kx] * bh[ky] * ah[kz];
+    if (!(std::fabs(lam) > 0.0)) return false;
+    double vmax = 0.0;
+    for (int p = 0; p < m; ++p) {
+      const int i = p % q, j = (p / q) % q, k = dim == 3 ? p / (q * q) : 0;
+      v[p] = S[(size_t)i * q + kx] * S[(size_t)j * q + ky] * (dim == 3 ? S[(size_t)k * q + kz] : 1.0);
+      vmax = std::max(vmax, std::fabs(v[p]));
+    }
+    double err = 0.0;
+    for (int r = 0; r < m; ++r) {
+      double acc = 0.0;
+      for (int c2 = 0; c2 < m; ++c2) acc += A[(size_t)r * m + c2] * v[c2];
+      err = std::max(err, std::fabs(acc - lam * v[r]));
+    }
+    if (err > 1e-10 * std::fabs(lam) * vmax) return false;
+    tab[(size_t)q * q + mode] = norm / lam;
+  }
   return true;
 }
 
@@ -238,6 +301,7 @@ struct mg_ctx {
   int device = 0;
   hipStream_t stream = nullptr, cap = nullptr;
   double *ainv_t = nullptr;
+  double *dst = nullptr;    // sine-transform table of the coarsest solve (tail), or null
   double *partials = nullptr;
   int np_max = 0;
   DevState *st = nullptr;
@@ -311,7 +375,7 @@ size_t footprint_of(const mg_config *cfg, int L, int slots = 1, bool own_top = f
   per += sizeof(DevState);
   const int q = cfg->n_coarsest - 2;
   const size_t m = cfg->dim == 2 ? (size_t)q * q : (size_t)q * q * q;
-  return per * (size_t)slots + m * m * 8 + entries_bytes(cfg, L);
+  return per * (size_t)slots + m * m * 8 + ((size_t)q * q + m) * 8 + entries_bytes(cfg, L);
 }
 
 // Ghost width of a tail starting at level l: 1 if every tail level is the cross.
@@ -358,6 +422,7 @@ hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const
   a.eoff = c->eoff;
   a.ecoef = c->ecoef;
   a.ainv_t = c->ainv_t;
+  a.dst = c->dst;
   a.f_top = f;
   a.u_top = u;
   a.done = done;
@@ -817,6 +882,21 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
   if ((st = dev_alloc(c, (void **)&c->st, sizeof(DevState) * slots)) != MG_OK) return bail(st);
   if (hipMemcpy(c->ainv_t, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(MG_EDEVICE, "upload of the coarsest inverse failed"));
+  {
+    // the tail solves the coarsest level by sine transforms unless MG_COARSE_DST=0 (or
+    // the operator fails the eigenpair check): no matrix to stream per visit
+    const char *e = std::getenv("MG_COARSE_DST");
+    const int q = c->ns[L - 1] - 2;
+    const size_t tab_len = (size_t)q * q + (c->dim == 2 ? (size_t)q * q : (size_t)q * q * q);
+    double *table = nullptr;  // allocated in any case, so that the footprint is exact
+    if ((st = dev_alloc(c, (void **)&table, tab_len * sizeof(double))) != MG_OK) return bail(st);
+    std::vector<double> tab;
+    if (!(e != nullptr && std::atoi(e) == 0) && coarsest_dst(c->ops[L - 1], c->dim, c->ns[L - 1], tab)) {
+      if (hipMemcpy(table, tab.data(), tab_len * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(MG_EDEVICE, "upload of the coarsest sine table failed"));
+      c->dst = table;
+    }
+  }
   {
     // slots of a batch start parked (done = 1) until a problem is admitted
     std::vector<DevState> init(slots);

@@ -15,6 +15,7 @@
 // non-centre stencil entries in the difference form sum_e c_e (u(x + o_e) - u(x)).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "mg_internal.h"
 
@@ -56,6 +57,7 @@ struct Tail {
   const int *edelta;  // entry offsets as index deltas in the padded layout of their level
   const T *ecoef;
   const double *ainv_t;
+  const double *dst;  // sine table of the coarsest solve, or null (dense inverse)
   int m, levels, gamma, nu1, nu2, prolong, scratch;
   int tx, ty, tz;
 
@@ -222,7 +224,66 @@ struct Tail {
   // unknowns); two adjacent lanes share a row of A^{-1}, each summing one half of the
   // columns, and add their halves with a lane shuffle.  The result goes to the second
   // half of the scratch before u is rewritten.
+  // v = A^{-1} f on the coarsest level by sine transforms (FP64): the interior right-hand
+  // side goes to a double array in the defect scratch, is transformed along each axis
+  // (w(.., a, ..) = sum_i S(a, i) w(.., i, ..), one pass per axis), scaled per mode by
+  // (2/N)^d / lambda, and transformed back.  A few KB of LDS, no matrix to stream.
+  __device__ __forceinline__ void coarsest_dst(int l) const {
+    const int n = lv[l].n, q = n - 2;
+    double *w0 = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(lds + scratch) + 7) & ~uintptr_t(7));
+    double *w1 = w0 + m, *S = w0 + 2 * m;
+    for (int c = threadIdx.x; c < m; c += NT) {
+      const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
+      w0[c] = (double)lds[lv[l].f + didx(l, ci, cj, ck)];
+    }
+    for (int e = threadIdx.x; e < q * q; e += NT) S[e] = dst[e];
+    __syncthreads();
+    const double *scale = dst + q * q;
+    auto pass = [&](const double *in, double *out, int stride, bool scaled) {
+      for (int c = threadIdx.x; c < m; c += NT) {
+        const int a = (c / stride) % q, b0 = c - a * stride;
+        double acc = 0.0;
+        for (int i = 0; i < q; ++i) acc += S[a * q + i] * in[b0 + i * stride];
+        out[c] = scaled ? acc * scale[c] : acc;
+      }
+      __syncthreads();
+    };
+    // forward along x, y (, z), the last pass scaled; then back.  Each pass reads one
+    // array and writes the other; the result ends in w1.
+    auto flip = [&] {
+      double *t = w0;
+      w0 = w1;
+      w1 = t;
+    };
+    pass(w0, w1, 1, false);
+    if (DIM == 3) {
+      pass(w1, w0, q, false);
+      pass(w0, w1, q * q, true);
+    } else {
+      pass(w1, w0, q, true);
+      flip();
+    }
+    pass(w1, w0, 1, false);
+    pass(w0, w1, q, false);
+    if (DIM == 3) {
+      pass(w1, w0, q * q, false);
+      flip();
+    }
+    const double *res = w1;
+    each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += NT) {
+      const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
+      lds[pidx(l, ri, rj, rk)] = (T)res[r];
+    }
+    __syncthreads();
+    ghosts(l);
+  }
   __device__ __forceinline__ void coarsest(int l) const {
+    if (dst != nullptr) {
+      coarsest_dst(l);
+      return;
+    }
     const int n = lv[l].n, q = n - 2;
     T *fv = lds + scratch, *v = fv + m;
     for (int c = threadIdx.x; c < m; c += NT) {
@@ -339,6 +400,7 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   c.edelta = edelta;
   c.ecoef = ecoef;
   c.ainv_t = a.ainv_t;
+  c.dst = a.dst;
   c.m = a.m;
   c.levels = a.levels;
   c.gamma = a.gamma;
@@ -380,11 +442,13 @@ size_t tail_scratch_offset(int dim, int G, const int *ns, int levels) {
 }
 
 // Byte offset of the entry table.  The scratch holds the top level's defect, and on the
-// coarsest level the packed right-hand side and the solution (two interior vectors).
+// coarsest level the packed right-hand side and the solution (two interior vectors), or
+// the sine-transform work arrays (two FP64 interior vectors and the q x q table).
 size_t tail_entry_offset(int dim, int G, const int *ns, int levels, size_t es) {
   const size_t n0 = ns[0], q = ns[levels - 1] - 2;
   const size_t top = dim == 3 ? n0 * n0 * n0 : n0 * n0, m = dim == 3 ? q * q * q : q * q;
-  return (tail_scratch_offset(dim, G, ns, levels) + std::max(top, 2 * m)) * es;
+  const size_t dst = ((2 * m + q * q) * 8 + 8 + es - 1) / es;  // sine-transform work arrays
+  return (tail_scratch_offset(dim, G, ns, levels) + std::max(std::max(top, 2 * m), dst)) * es;
 }
 
 size_t tail_lds_bytes(int dim, int G, const int *ns, int levels, int entries, size_t es) {

@@ -51,10 +51,13 @@ def test_fixed_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
         H.close()
 
 
-@pytest.mark.parametrize("fused,tail", [("1", None), ("0", "0"), ("1", "0"), ("1", "17"), ("0", "65")])
+@pytest.mark.parametrize("fused,tail,dst", [("1", None, "1"), ("0", "0", "1"), ("1", "0", "1"),
+                                            ("1", "17", "1"), ("0", "65", "1"), ("1", None, "0")])
 @pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 2)])
-def test_runtime_variants_agree(fused, tail, coarse, gamma, monkeypatch):
-    """Fused or separate kernels, with or without the LDS-resident tail: same cycles."""
+def test_runtime_variants_agree(fused, tail, dst, coarse, gamma, monkeypatch):
+    """Fused or separate kernels, with or without the LDS-resident tail, the tail's
+    coarsest solve by sine transforms or the dense inverse: same cycles."""
+    monkeypatch.setenv("MG_COARSE_DST", dst)
     monkeypatch.setenv("MG_FUSED", fused)
     if tail is None:
         monkeypatch.delenv("MG_TAIL_N", raising=False)
@@ -245,14 +248,18 @@ def test_fixed_cycles_match_oracle_3d(n, coarse, prolong, nu1, nu2, gamma):
         H.close()
 
 
-@pytest.mark.parametrize("tail", [None, "0"])
-def test_3d_tail_variants_agree(tail, monkeypatch):
+@pytest.mark.parametrize("tail,dst,coarse", [(None, "1", 0), (None, "0", 0), ("0", "1", 0),
+                                              (None, "1", 1), (None, "0", 1)])
+def test_3d_tail_variants_agree(tail, dst, coarse, monkeypatch):
+    """With or without the LDS-resident tail, its coarsest solve by sine transforms or by
+    the dense inverse: same cycles as the oracle."""
     if tail is None:
         monkeypatch.delenv("MG_TAIL_N", raising=False)
     else:
         monkeypatch.setenv("MG_TAIL_N", tail)
+    monkeypatch.setenv("MG_COARSE_DST", dst)
     n = 33
-    H = Handle(3, n, gamma=2)
+    H = Handle(3, n, gamma=2, coarse=coarse)
     try:
         f = inputs.smooth_sine_3d(n)
         u, res, u_ref, hist = _fixed_cycles(H, f, 4)
