@@ -854,7 +854,10 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
     int lds_limit = 0;
     if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
       lds_limit = 65536;
-    int cap = c->dim == 2 ? 33 : 17;
+    // Largest level side in the tail, by measurement: in 3D one workgroup's pass over a
+    // 17^3 level costs more than the streaming kernels' launches, so only the coarsest
+    // solve runs there; in 2D the tail takes the levels up to 33^2.
+    int cap = c->dim == 2 ? 33 : 9;
     if (const char *tn = std::getenv("MG_TAIL_N")) cap = std::atoi(tn);
     const size_t es = mixed ? sizeof(float) : sizeof(double);
     c->tail_top = L;

@@ -249,7 +249,8 @@ def test_fixed_cycles_match_oracle_3d(n, coarse, prolong, nu1, nu2, gamma):
 
 
 @pytest.mark.parametrize("tail,dst,coarse", [(None, "1", 0), (None, "0", 0), ("0", "1", 0),
-                                              (None, "1", 1), (None, "0", 1)])
+                                              (None, "1", 1), ("17", "1", 0), ("17", "0", 1),
+                                              ("33", "1", 1)])
 def test_3d_tail_variants_agree(tail, dst, coarse, monkeypatch):
     """With or without the LDS-resident tail, its coarsest solve by sine transforms or by
     the dense inverse: same cycles as the oracle."""
