@@ -43,11 +43,11 @@ WORKLOADS = {
 # dispatch, scaled by the counters of a plain copy of known size), valid only for the
 # kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    # 4097^2 level 0, two sweeps + defect + full weighting: 172,281.7 KiB fetched x 2.0000
-    # + 169,180.3 KiB written x 1.0000 (a 2 GiB copy reads 1,048,595 KiB / writes 2,097,152)
-    "k_pre2d/f64/fused2d.hip/4097": {"bytes": 526067037, "source": "29a9c7046e24eaad"},
-    # 513^3 level 0 FP32 sweep: 620,912.0 KiB x 2.0000 + 561,025.6 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 1846094590, "source": "6f97bc5ea822d368"},
+    # 4097^2 level 0, two sweeps + defect + full weighting: 172,318.0 KiB fetched x 2.0000
+    # + 169,062.0 KiB written x 1.0000 (a 2 GiB copy reads 1,048,595 KiB / writes 2,097,152)
+    "k_pre2d/f64/fused2d.hip/4097": {"bytes": 526020368, "source": "847dc90aeecebc30"},
+    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 717,385.4 KiB x 2.0000 + 591,388.4 KiB x 1.0000
+    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2074757094, "source": "855fb34db4670c4c"},
 }
 
 
