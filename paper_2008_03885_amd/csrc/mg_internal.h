@@ -196,6 +196,7 @@ struct TailLevel {
 };
 struct TailArgs {
   int levels, gamma, nu1, nu2, prolong, zero_init, m, lds_r;
+  int repeats;               // cycles from the top level (the parent's gamma visits)
   int ent_first, ent_total;  // entries of the tail's levels in eoff/ecoef
   int lds_ent;               // byte offset of the entry table in LDS
   TailLevel lv[kMaxTailLevels];

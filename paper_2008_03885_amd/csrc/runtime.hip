@@ -396,8 +396,9 @@ size_t tail_bytes(const mg_ctx *c, int l, size_t es) {
 
 template <typename T>
 hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const int *done,
-                          hipStream_t s) {
+                          hipStream_t s, int repeats = 1) {
   mgk::TailArgs a{};
+  a.repeats = repeats;
   a.levels = c->L - l;
   a.gamma = c->cfg.gamma;
   a.nu1 = c->cfg.nu1;
@@ -464,10 +465,9 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
       if (e != hipSuccess) return e;
     }
     if (l + 1 >= c->tail_top) {
-      for (int g = 0; g < c->cfg.gamma; ++g) {
-        e = launch_tail_at<T>(c, l + 1, uc, fc, g == 0, done, s);
-        if (e != hipSuccess) return e;
-      }
+      // the gamma visits of the tail's top level in one launch
+      e = launch_tail_at<T>(c, l + 1, uc, fc, true, done, s, c->cfg.gamma);
+      if (e != hipSuccess) return e;
     } else if (l + 1 == c->L - 1) {
       e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
       if (e != hipSuccess) return e;
@@ -525,6 +525,10 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   if (e != hipSuccess) return e;
   if (l + 1 == c->L - 1 && l + 1 < c->tail_top) {
     e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
+    if (e != hipSuccess) return e;
+  } else if (l + 1 >= c->tail_top) {
+    // the gamma visits of the tail's top level in one launch
+    e = launch_tail_at<T>(c, l + 1, uc, fc, true, done, s, c->cfg.gamma);
     if (e != hipSuccess) return e;
   } else {
     for (int g = 0; g < c->cfg.gamma; ++g) {

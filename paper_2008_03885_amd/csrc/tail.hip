@@ -423,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   });
   __syncthreads();
   c.ghosts(0);
-  run_cycle<T, DIM, G, NT>(c, a.zero_init != 0);
+  for (int r = 0; r < a.repeats; ++r) run_cycle<T, DIM, G, NT>(c, r == 0 && a.zero_init != 0);
   c.each(n, [&](int i, int j, int k) { ug[c.didx(0, i, j, k)] = lds[c.pidx(0, i, j, k)]; });
 }
 
