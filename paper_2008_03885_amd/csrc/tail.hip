@@ -23,6 +23,10 @@ namespace mgk {
 namespace {
 
 constexpr int kTailThreads = 1024;
+// Points per thread of a sweep at the largest tail side (65^2 = 4225, 17^3 = 4913).
+constexpr int kSlots = 5;
+static_assert(65 * 65 <= kSlots * kTailThreads && 17 * 17 * 17 <= kSlots * kTailThreads,
+              "tail sides must fit kSlots points per thread");
 // Ghost frame G: a stencil of radius R reaches R-1 points past the boundary, cubic
 // interpolation one coarse point; G = 1 when every tail level is the radius-2 cross,
 // G = 2 otherwise.
@@ -78,6 +82,38 @@ struct Tail {
   __device__ __forceinline__ bool interior(int n, int i, int j, int k) const {
     return i > 0 && i < n - 1 && j > 0 && j < n - 1 && (DIM == 2 || (k > 0 && k < n - 1));
   }
+  // Point p of an n^DIM level in x-fastest order.
+  __device__ __forceinline__ void decode(int p, int n, int &i, int &j, int &k) const {
+    i = p % n;
+    const int t = p / n;
+    if (DIM == 3) {
+      j = t % n;
+      k = t / n;
+    } else {
+      j = t;
+      k = 0;
+    }
+  }
+  // Stores the value v of interior point (i, j, k) of level l together with its odd
+  // images in the ghost frame (points within G of the boundary have one image per such
+  // axis, and the products of those for corners).  Frame cells whose source is a
+  // boundary point hold 0 from the start and are never written.
+  __device__ __forceinline__ void put(int l, int i, int j, int k, T v) const {
+    const int n = lv[l].n;
+    int xs[2] = {i, i}, ys[2] = {j, j}, zs[2] = {k, k};
+    int nx = 1, ny = 1, nz = 1;
+    if (i <= G) { xs[1] = -i; nx = 2; } else if (i >= n - 1 - G) { xs[1] = 2 * (n - 1) - i; nx = 2; }
+    if (j <= G) { ys[1] = -j; ny = 2; } else if (j >= n - 1 - G) { ys[1] = 2 * (n - 1) - j; ny = 2; }
+    if (DIM == 3) {
+      if (k <= G) { zs[1] = -k; nz = 2; } else if (k >= n - 1 - G) { zs[1] = 2 * (n - 1) - k; nz = 2; }
+    }
+    for (int c = 0; c < nz; ++c)
+      for (int b = 0; b < ny; ++b)
+        for (int a = 0; a < nx; ++a) {
+          const bool odd = (a + b + c) & 1;
+          lds[pidx(l, xs[a], ys[b], zs[c])] = odd ? -v : v;
+        }
+  }
   __device__ __forceinline__ T lu(int l, int p, T c) const {
     const LevelInfo &L = lv[l];
     if (L.cross) {
@@ -118,38 +154,40 @@ struct Tail {
         }
     __syncthreads();
   }
+  // One omega-Jacobi sweep on level l: every thread computes its points (at most kSlots,
+  // x-fastest order) into registers, then all store them with their ghost images.
   __device__ __forceinline__ void smooth(int l, bool zero) const {
     const int n = lv[l].n;
+    const int total = DIM == 3 ? n * n * n : n * n;
     const T om = T(lv[l].om_d);
-    T vals[TL::NK][TL::NJ][TL::NI];
+    T vals[kSlots];
 #pragma unroll
-    for (int c = 0; c < TL::NK; ++c)
-#pragma unroll
-      for (int b = 0; b < TL::NJ; ++b)
-#pragma unroll
-        for (int a = 0; a < TL::NI; ++a) {
-          const int i = tx + a * TL::TX, j = ty + b * TL::TY, k = DIM == 3 ? tz + c * TL::TZ : 0;
-          T v = T(0);
-          if (interior(n, i, j, k)) {
-            const int p = pidx(l, i, j, k);
-            const T u0 = zero ? T(0) : lds[p];
-            const T r = lds[lv[l].f + didx(l, i, j, k)] - (zero ? T(0) : lu(l, p, u0));
-            v = u0 + om * r;
-          }
-          vals[c][b][a] = v;
+    for (int r = 0; r < kSlots; ++r) {
+      const int p = (int)threadIdx.x + r * NT;
+      T v = T(0);
+      if (p < total) {
+        int i, j, k;
+        decode(p, n, i, j, k);
+        if (interior(n, i, j, k)) {
+          const int q = pidx(l, i, j, k);
+          const T u0 = zero ? T(0) : lds[q];
+          const T rr = lds[lv[l].f + p] - (zero ? T(0) : lu(l, q, u0));
+          v = u0 + om * rr;
         }
+      }
+      vals[r] = v;
+    }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < TL::NK; ++c)
-#pragma unroll
-      for (int b = 0; b < TL::NJ; ++b)
-#pragma unroll
-        for (int a = 0; a < TL::NI; ++a) {
-          const int i = tx + a * TL::TX, j = ty + b * TL::TY, k = DIM == 3 ? tz + c * TL::TZ : 0;
-          if (i < n && j < n && (DIM == 2 || k < n)) lds[pidx(l, i, j, k)] = vals[c][b][a];
-        }
+    for (int r = 0; r < kSlots; ++r) {
+      const int p = (int)threadIdx.x + r * NT;
+      if (p < total) {
+        int i, j, k;
+        decode(p, n, i, j, k);
+        if (interior(n, i, j, k)) put(l, i, j, k, vals[r]);
+      }
+    }
     __syncthreads();
-    ghosts(l);
   }
   __device__ __forceinline__ void zero_level(int l) const {
     const int n = lv[l].n;
@@ -214,16 +252,10 @@ struct Tail {
           }
         }
       }
-      lds[pidx(l, i, j, k)] += s;
+      put(l, i, j, k, lds[pidx(l, i, j, k)] + s);
     });
     __syncthreads();
-    ghosts(l);
   }
-  // v = A^{-1} f on the coarsest level (FP64 sums).  The interior right-hand side is
-  // packed into the defect scratch first (row-major interior order, the order of A's
-  // unknowns); two adjacent lanes share a row of A^{-1}, each summing one half of the
-  // columns, and add their halves with a lane shuffle.  The result goes to the second
-  // half of the scratch before u is rewritten.
   // v = A^{-1} f on the coarsest level by sine transforms (FP64): the interior right-hand
   // side goes to a double array in the defect scratch, is transformed along each axis
   // (w(.., a, ..) = sum_i S(a, i) w(.., i, ..), one pass per axis), scaled per mode by
@@ -270,15 +302,17 @@ struct Tail {
       flip();
     }
     const double *res = w1;
-    each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
-    __syncthreads();
     for (int r = threadIdx.x; r < m; r += NT) {
       const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
-      lds[pidx(l, ri, rj, rk)] = (T)res[r];
+      put(l, ri, rj, rk, (T)res[r]);
     }
     __syncthreads();
-    ghosts(l);
   }
+  // v = A^{-1} f on the coarsest level, by sine transforms when the table is there, else
+  // by the dense inverse (FP64 sums): the interior right-hand side is packed into the
+  // defect scratch (row-major interior order, the order of A's unknowns); two adjacent
+  // lanes share a row of A^{-1}, each summing one half of the columns, and add their
+  // halves with a lane shuffle.  The result goes to the second half of the scratch.
   __device__ __forceinline__ void coarsest(int l) const {
     if (dst != nullptr) {
       coarsest_dst(l);
@@ -303,14 +337,12 @@ struct Tail {
       val += __shfl_xor(val, 1);
       if (h == 0 && r < m) v[r] = (T)val;
     }
-    each(n, [&](int i, int j, int k) { lds[pidx(l, i, j, k)] = T(0); });
-    __syncthreads();
+    __syncthreads();  // v complete
     for (int r = threadIdx.x; r < m; r += NT) {
       const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
-      lds[pidx(l, ri, rj, rk)] = v[r];
+      put(l, ri, rj, rk, v[r]);
     }
     __syncthreads();
-    ghosts(l);
   }
 };
 
@@ -415,6 +447,12 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   const size_t per = DIM == 3 ? (size_t)n * n * n : (size_t)n * n;
   const T *fg = slot_ptr(static_cast<const T *>(a.f_top), per);
   T *ug = slot_ptr(static_cast<T *>(a.u_top), per);
+  // coarser levels' framed u start at zero: boundary points and the frame cells that
+  // mirror them are never written afterwards
+  for (int l = 1; l < a.levels; ++l) {
+    const int pp = lvt[l].pp, tot = DIM == 3 ? pp * pp * pp : pp * pp;
+    for (int e = threadIdx.x; e < tot; e += NT) lds[lvt[l].u + e] = T(0);
+  }
   c.each(n, [&](int i, int j, int k) {
     const int d = c.didx(0, i, j, k);
     lds[lvt[0].f + d] = fg[d];
