@@ -6,7 +6,9 @@ the FP64 rounding floor), with f and u resident in HBM.  Workloads (--workload):
   poisson2d-4097 (default)  2D, n = 4097 (16,769,025 unknowns), right-hand side
       sum_{kx,ky<=64} g_k/|k| sin(kx pi x) sin(ky pi y), g_k ~ N(0,1) (seeded), V(2,1)
       omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized
-      coarse operators to 9x9 with an exact coarsest solve, FP64.
+      coarse operators to 9x9 with an exact coarsest solve, FP64.  The JSON line also
+      carries the Galerkin and W(2,1) combinations of the same problem
+      (`config_variants`; --no-variants skips them).
   poisson3d-513             3D, n = 513, uniform[-1,1] noise smoothed by three
       neighbour-average passes, V(2,1) (omega = 9/11), mixed precision (eight FP32
       cycles per FP64 refinement step) against FP64.
@@ -65,6 +67,8 @@ def parse():
     p.add_argument("--inner", type=int, default=None, help="FP32 cycles per refinement step")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-levels", action="store_true", help="skip the per-level kernel table")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the Galerkin and W-cycle runs of the 2D workload")
     p.add_argument("--kernel-reps", type=int, default=30)
     p.add_argument("--pmc-probe", action="store_true",
                    help="run a plain copy of known size, then the dominant kernel (for counters)")
@@ -438,6 +442,22 @@ def main():
     sec, (status, res) = main_run.timed(args.steps, args.warmup)
     ms = 1e3 * sec
 
+    # the other coarse-operator / cycle combinations of the 2D 4097^2 configuration
+    variants = None
+    if args.workload == "poisson2d-4097" and not args.no_variants:
+        variants = {}
+        for coarse, gamma in ((0, 1), (1, 1), (0, 2), (1, 2)):
+            name = "%s-%s(%d,%d)" % ("galerkin" if coarse else "rediscretized", "W" if gamma == 2 else "V",
+                                     w["nu1"], w["nu2"])
+            if coarse == w["coarse"] and gamma == w["gamma"]:
+                vs, vres = sec, res
+            else:
+                vr = Run(dict(w, coarse=coarse, gamma=gamma), w["precision"], fd, stream)
+                vs, (vst, vres) = vr.timed(2, 1)
+                vr.close()
+            variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
+                              "rel_residual": vres.rel_residual}
+
     compare = None
     fp64_cycles = res.cycles if w["precision"] == 0 else None
     if w["compare"]:
@@ -515,6 +535,8 @@ def main():
     }
     if compare:
         out["precision_compare"] = compare
+    if variants:
+        out["config_variants"] = variants
     if extra:
         out["error_vs_oracle_129"] = extra
     if rows:
