@@ -379,10 +379,27 @@ def serve_bench(count, loads=(0.5, 0.8)):
                 got += S.poll(256, max(0.0, min(wait, 0.002)))
             end = max(c.t_done for c in got)
             lat = np.array([c.t_done - (t0 + arrivals[c.tag]) for c in got])
+            sizes = np.array([c.n for c in got])
             bad = [c.tag for c in got if c.status != mg.MG_OK or c.result.rel_residual > 1e-10]
-            return end - t0, lat, bad
+            return end - t0, lat, bad, sizes
 
-        span, lat_sat, bad = run([0.0] * len(reqs))
+        def per_size(lat, sizes):
+            return {str(int(n)): {"count": int((sizes == n).sum()),
+                                  "p50_ms": float(np.percentile(lat[sizes == n], 50) * 1e3),
+                                  "p99_ms": float(np.percentile(lat[sizes == n], 99) * 1e3)}
+                    for n in sorted(set(sizes.tolist()))}
+
+        # one request at a time: the latency of each size on an idle device
+        alone = {}
+        for n, f in sorted(fs.items()):
+            u = torch.empty_like(f)
+            t1 = time.monotonic()
+            S.submit(2 * 10 ** 6 + n, f, u)
+            c = S.wait_all(1, 60.0)[0]
+            alone[str(n)] = {"ms": (time.monotonic() - t1) * 1e3,
+                             "solve_ms": (c.t_done - c.t_admit) * 1e3, "cycles": c.result.cycles}
+
+        span, lat_sat, bad, _ = run([0.0] * len(reqs))
         rate_sat = len(reqs) / span
         out = {
             "requests": len(reqs), "sizes": "2^k+1, k~U{6..11}", "precision": "mixed",
@@ -390,15 +407,17 @@ def serve_bench(count, loads=(0.5, 0.8)):
                           "makespan_s": span, "p50_ms": float(np.percentile(lat_sat, 50) * 1e3),
                           "p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
             "not_converged": bad,
+            "alone": alone,
         }
         gaps = np.array([t for *_, t in reqs])
         for load in loads:
             arrivals = list(gaps / (load * rate_sat))
-            span, lat, bad2 = run(arrivals)
+            span, lat, bad2, sizes = run(arrivals)
             out["load_%.2f" % load] = {
                 "offered_requests_per_s": load * rate_sat, "requests_per_s": len(reqs) / span,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "per_size": per_size(lat, sizes)}
             out["not_converged"] += bad2
         st = S.stats()
         out["peak_active"] = st["peak_active"]
