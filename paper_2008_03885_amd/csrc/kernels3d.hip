@@ -96,23 +96,6 @@ struct PlaneLoader {
   }
 };
 
-// L u at point (px, py) of the middle plane of the ring (planes c-R..c+R at ring slots
-// (head + k) % W), region pitch PX.  Cross only.
-template <typename T, int PX>
-__device__ __forceinline__ T cross_lu(const T *ring, int plane_sz, const int (&slot)[5], int px,
-                                      int py, T w1, T w2) {
-  const T *mid = ring + slot[2] * plane_sz;
-  const int p = py * PX + px;
-  const T c = mid[p];
-  T d1 = (c - mid[p - 1]) + (c - mid[p + 1]);
-  T d2 = (c - mid[p - 2]) + (c - mid[p + 2]);
-  d1 += (c - mid[p - PX]) + (c - mid[p + PX]);
-  d2 += (c - mid[p - 2 * PX]) + (c - mid[p + 2 * PX]);
-  d1 += (c - ring[slot[1] * plane_sz + p]) + (c - ring[slot[3] * plane_sz + p]);
-  d2 += (c - ring[slot[0] * plane_sz + p]) + (c - ring[slot[4] * plane_sz + p]);
-  return w1 * d1 + w2 * d2;
-}
-
 // Separable operator on the region's inner part: given the ring of 7 planes, compute
 // L u for every (px, py) with E <= px < PX-E, E <= py < PY-E (E = 3) into out (same
 // pitch).  Uses scratch arrays zb, za (PX*PY) and yb, ys (PX*PY).  Barriers inside.
@@ -167,12 +150,15 @@ __device__ void sep_lu_plane(const T *ring, int plane_sz, const int (&slot)[7], 
   __syncthreads();
 }
 
-// ------------------------------------------------------------------ sweep ----
+// ------------------------------------------- plane-ring sweep (Galerkin levels) ----
+// The second implementation of the radius-3 separable operator (MG_G3_OLD=1): an LDS
+// ring of 2R+1 haloed planes, the operator applied plane by plane with sep_lu_plane.
 template <typename T, typename TO, int MODE, int R>
 __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const T *__restrict__ u,
                                                  TO *__restrict__ out, int n, int zchunk, KOp<T> op,
                                                  double *__restrict__ partials,
                                                  const int *__restrict__ done) {
+  static_assert(R == 3, "separable radius-3 operators only");
   constexpr int W = 2 * R + 1;
   constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
   extern __shared__ __align__(16) unsigned char smem3[];
@@ -217,12 +203,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const 
     const T fv = (own && xin && z > 0 && z < n - 1) ? fraw : T(0);
     T lu;
     const int p = (ty + R) * PX + (tx + R);
-    if constexpr (R == 2) {
-      int slot[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) slot[k] = (head + k) % W;
-      lu = zero_u ? T(0) : cross_lu<T, PX>(ring, PS, slot, tx + R, ty + R, op.w1, op.w2);
-    } else {
+    {
       int slot[7];
 #pragma unroll
       for (int k = 0; k < 7; ++k) slot[k] = (head + k) % W;
@@ -603,15 +584,16 @@ __global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
   }
 }
 
-// ------------------------------------------------- defect + full weighting ----
-// Block: coarse tile (TX/2) x (TY/2) at coarse planes [K0, K1).  The defect is computed on
-// the fine tile extended by one point (the full-weighting support), kept for three
-// fine planes in LDS, and restricted in z, y and x.
+// ------------------------ plane-ring defect + full weighting (Galerkin levels) ----
+// The second implementation (MG_G3_OLD=1).  Block: coarse tile (TX/2) x (TY/2) at coarse
+// planes [K0, K1).  The defect is computed on the fine tile extended by one point (the
+// full-weighting support), kept for three fine planes in LDS, and restricted in z, y and x.
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ f,
                                                           const T *__restrict__ u,
                                                           T *__restrict__ fc, int n, int kchunk,
                                                           KOp<T> op, const int *__restrict__ done) {
+  static_assert(R == 3, "separable radius-3 operators only");
   constexpr int W = 2 * R + 1;
   constexpr int E = R + 1;  // halo of the u region: stencil plus the restriction support
   constexpr int PX = TX + 2 * E, PY = TY + 2 * E, PS = PX * PY;
@@ -664,11 +646,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
     // defect on the RX x RY region (fine x0-1 .. x0+TX, y0-1 .. y0+TY) into the newest slot
     T *rnew = rr + ((rhead + 2) % 3) * RS;
     int slot7[7];
-    if constexpr (R == 3) {
 #pragma unroll
-      for (int k = 0; k < 7; ++k) slot7[k] = (head + k) % W;
-      sep_lu_plane<T, PX, PY>(ring, PS, slot7, op, zb, za, t1, t2, lo);
-    }
+    for (int k = 0; k < 7; ++k) slot7[k] = (head + k) % W;
+    sep_lu_plane<T, PX, PY>(ring, PS, slot7, op, zb, za, t1, t2, lo);
     for (int e = threadIdx.x; e < RS; e += 256) {
       const int rx = e % RX, ry = e / RX;
       const int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
@@ -676,16 +656,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
       T v = T(0);
       if (inside) {
         const int px = rx + (E - 1), py = ry + (E - 1);
-        T lu;
-        if constexpr (R == 2) {
-          int slot[5];
-#pragma unroll
-          for (int k = 0; k < 5; ++k) slot[k] = (head + k) % W;
-          lu = cross_lu<T, PX>(ring, PS, slot, px, py, op.w1, op.w2);
-        } else {
-          lu = lo[py * PX + px];
-        }
-        if (zero_u) lu = T(0);
+        const T lu = zero_u ? T(0) : lo[py * PX + px];
         v = f[((size_t)z * n + gy) * n + gx] - lu;
       }
       rnew[e] = v;
