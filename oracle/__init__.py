@@ -31,6 +31,9 @@ _LIB = os.path.join(_HERE, "libmgoracle.so")
 RESTRICT_FW, RESTRICT_CUBIC = 1, 3
 PROLONG_LINEAR, PROLONG_CUBIC = 1, 3
 COARSE_NG, COARSE_GALERKIN = 0, 1
+# second-order coarse operators for a fourth-order fine operator (section 3.1):
+# rediscretized (eq. L_H_2d) and "Galerkin" from the second-order operator (eq. L_H_2G_2d)
+COARSE_NG2, COARSE_G2 = 2, 3
 MAX_RADIUS = 6
 
 

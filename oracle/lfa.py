@@ -12,7 +12,9 @@ Everything here is built from the Fourier symbols the paper prints, not from ste
 * two-grid operator on the 2^d aliases of theta in [-pi/2, pi/2)^d:
   M = S^nu2 (I - p L_H^{-1} r^T diag(L)) S^nu1 (section 2.2 eqs. K, M_2level; appendix
   A.2 eqs. K_hat_2, M_2); Galerkin coarse symbol L_H(2 theta) = sum_alpha r_alpha L_alpha p_alpha
-  (eq. L_2h_G and the line after it);
+  (eq. L_2h_G and the line after it); second-order coarse operators (section 3.1): the
+  second-order symbol at H (eq. L_H_2d), or the Galerkin symbol of the second-order
+  fine symbol (eq. L_H_2G_2d);
 * smoothing factor: sup over high frequencies (section 2.2 eq. mu; section 5.3).
 
 Convention: an interpolated coarse mode phi_H(2 theta) is sum_alpha p(theta_alpha) phi_h(theta_alpha)
@@ -29,6 +31,7 @@ import numpy as np
 FW, CUBIC = 1, 3
 LINEAR = 1
 NG, GALERKIN = 0, 1
+NG2, G2 = 2, 3  # second-order coarse operators (section 3.1 eqs. L_H_2d, L_H_2G_2d)
 
 
 def sin2(theta):
@@ -80,8 +83,13 @@ class Scheme:
         h = h0 * 2 ** level
         if level == 0 or self.coarse == NG:
             return symbol_fine(theta, h, self.order)
+        if self.coarse == NG2:
+            return symbol_fine(theta, h, 2)
         half = aliases(np.asarray(theta, dtype=float) / 2.0)
-        fine = self.level_symbol(level - 1, half, h0)
+        if self.coarse == G2 and level == 1:
+            fine = symbol_fine(half, h0, 2)  # the second-order operator at the finest spacing
+        else:
+            fine = self.level_symbol(level - 1, half, h0)
         return np.sum(symbol_transfer(half, self.restrict_op) * fine
                       * symbol_transfer(half, self.prolong), axis=-1)
 

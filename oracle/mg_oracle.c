@@ -489,6 +489,7 @@ or_mg *or_mg_create(const or_config *cfg) {
   int L = or_num_levels(cfg->n, cfg->n_coarsest);
   if (L <= 0 || L > OR_MAX_LEVELS || (cfg->dim != 2 && cfg->dim != 3)) return NULL;
   if (cfg->order != 2 && cfg->order != 4) return NULL;
+  if (cfg->coarse < OR_COARSE_NG || cfg->coarse > OR_COARSE_G2) return NULL;
   or_mg *mg = (or_mg *)calloc(1, sizeof(or_mg));
   int dim = cfg->dim;
   int w = swidth(OR_MAX_RADIUS);
@@ -503,6 +504,14 @@ or_mg *or_mg_create(const or_config *cfg) {
     double h = 1.0 / (n - 1);
     if (l == 0 || cfg->coarse == OR_COARSE_NG) {
       lv->R = or_fine_stencil(dim, cfg->order, h, lv->s);
+    } else if (cfg->coarse == OR_COARSE_NG2) {
+      lv->R = or_fine_stencil(dim, 2, h, lv->s);
+    } else if (cfg->coarse == OR_COARSE_G2 && l == 1) {
+      /* R L_h^(2) P with the second-order operator at the finest spacing */
+      double *s2 = (double *)calloc(smax, sizeof(double));
+      const int R2 = or_fine_stencil(dim, 2, 1.0 / (cfg->n - 1), s2);
+      lv->R = or_galerkin_stencil(dim, R2, s2, cfg->restrict_op, cfg->prolong, lv->s);
+      free(s2);
     } else {
       or_level *fl = &mg->lev[l - 1];
       lv->R = or_galerkin_stencil(dim, fl->R, fl->s, cfg->restrict_op, cfg->prolong, lv->s);

@@ -38,12 +38,15 @@ extern "C" {
 
 #define OR_COARSE_NG 0       /* rediscretized: same stencil at the coarse spacing (eq. L_H_4n_2d) */
 #define OR_COARSE_GALERKIN 1 /* L_{l+1} = R L_l P, built recursively (eq. L_H_4G, section 2.4) */
+#define OR_COARSE_NG2 2      /* second-order operator at every coarse spacing (section 3.1, eq. L_H_2d) */
+#define OR_COARSE_G2 3       /* L_1 = R L_h^(2) P from the second-order operator at the finest
+                              * spacing (section 3.1, eq. L_H_2G_2d), then L_{l+1} = R L_l P */
 
 typedef struct {
   int dim;          /* 2 or 3 */
   int n;            /* finest points per axis incl. boundary, 2^k+1 */
   int order;        /* 2 or 4: order of the finest-level operator */
-  int coarse;       /* OR_COARSE_NG or OR_COARSE_GALERKIN */
+  int coarse;       /* OR_COARSE_NG, OR_COARSE_GALERKIN, OR_COARSE_NG2 or OR_COARSE_G2 */
   int restrict_op;  /* OR_RESTRICT_FW or OR_RESTRICT_CUBIC */
   int prolong;      /* OR_PROLONG_LINEAR or OR_PROLONG_CUBIC */
   int nu1, nu2;     /* pre- and post-smoothing sweeps */

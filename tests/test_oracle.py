@@ -87,6 +87,31 @@ def test_galerkin_of_five_point_operator_matches_printed():
     assert np.abs(outer).max() < 1e-12
 
 
+def test_second_order_coarse_operators_of_the_hierarchy():
+    """Section 3.1: with a fourth-order fine operator, the "Galerkin" second-order coarse
+    operator of the hierarchy (full weighting, bilinear interpolation) is the printed
+    appendix A.2 operator at level 1, and the rediscretized one is the 5-point operator
+    at H on every coarse level (eq. L_H_2d), in the printed units."""
+    printed, factor = read_golden("galerkin_order2_fw_bilinear_2d.txt")
+    n = 33
+    mg = oracle.Multigrid(2, n, coarse=oracle.COARSE_G2, prolong=oracle.PROLONG_LINEAR, n_coarsest=9)
+    n1, s1 = mg.level_stencil(1)
+    H = 1.0 / (n1 - 1)
+    R = (s1.shape[0] - 1) // 2
+    np.testing.assert_allclose(s1[R - 1:R + 2, R - 1:R + 2] * H * H, printed * factor, atol=1e-12)
+    # level 0 stays the fourth-order operator
+    n0, s0 = mg.level_stencil(0)
+    np.testing.assert_allclose(s0, oracle.fine_stencil(2, 4, 1.0 / (n - 1)), atol=0)
+    mg2 = oracle.Multigrid(2, n, coarse=oracle.COARSE_NG2, n_coarsest=9)
+    five = printed * 0
+    five[1, :] = [-1, 4, -1]
+    five[:, 1] += [-1, 0, -1]
+    for l in (1, 2):
+        nl, sl = mg2.level_stencil(l)
+        Hl = 1.0 / (nl - 1)
+        np.testing.assert_allclose(sl * Hl * Hl, five, atol=1e-12)
+
+
 # ------------------------------------------------------------------ Fourier symbols --
 
 @pytest.mark.parametrize("dim,order", [(2, 4), (3, 4), (2, 2), (3, 2)])
@@ -193,8 +218,8 @@ def _cycle_matrix(mg, n, dim):
     return M
 
 
-CASES_2G = [(2, 17, 9, c, p, nu) for c in (0, 1) for p in (1, 3) for nu in ((2, 1), (1, 1))] + \
-           [(3, 9, 5, c, 3, (2, 1)) for c in (0, 1)]
+CASES_2G = [(2, 17, 9, c, p, nu) for c in (0, 1, 2, 3) for p in (1, 3) for nu in ((2, 1), (1, 1))] + \
+           [(3, 9, 5, c, 3, (2, 1)) for c in (0, 1, 2, 3)]
 
 
 @pytest.mark.parametrize("dim,n,nc,coarse,prolong,nu", CASES_2G)
@@ -224,7 +249,7 @@ def test_two_grid_rho_values():
 
 
 @pytest.mark.parametrize("gamma", [1, 2])
-@pytest.mark.parametrize("coarse", [0, 1])
+@pytest.mark.parametrize("coarse", [0, 1, 2, 3])
 def test_multilevel_cycle_matches_explicit_matrices(gamma, coarse):
     """Three-level V and W cycles equal the composition of explicit matrices by the
     recursion of section 2.2 (eqs. K_l, M) with appendix A.3.1 eq. L_H_approx."""
@@ -261,6 +286,22 @@ def test_galerkin_equals_brute_force_rap(dim, n, prolong):
         G2 = explicit.galerkin(explicit.restriction(dim, nc, 1), Ac, explicit.prolongation(dim, nc, prolong))
         Ac2 = explicit.operator(sc2, (nc - 1) // 2 + 1)
         assert np.abs(G2 - Ac2).max() <= 1e-13 * np.abs(G2).max()
+
+
+@pytest.mark.parametrize("dim,n,prolong", [(2, 17, 3), (2, 33, 1), (3, 17, 3)])
+def test_second_order_galerkin_equals_brute_force_rap(dim, n, prolong):
+    """The hierarchy's "Galerkin" second-order coarse operators (section 3.1 eq.
+    L_H_2G_2d): level 1 equals R A2 P with A2 the explicit second-order operator at the
+    finest spacing, level 2 equals R A1 P, from explicit matrices."""
+    mg = oracle.Multigrid(dim, n, coarse=oracle.COARSE_G2, prolong=prolong, n_coarsest=5)
+    A2 = explicit.operator(oracle.fine_stencil(dim, 2, 1.0 / (n - 1)), n)
+    G1 = explicit.galerkin(explicit.restriction(dim, n, 1), A2, explicit.prolongation(dim, n, prolong))
+    n1, s1 = mg.level_stencil(1)
+    A1 = explicit.operator(s1, n1)
+    assert np.abs(G1 - A1).max() <= 1e-13 * np.abs(G1).max()
+    G2 = explicit.galerkin(explicit.restriction(dim, n1, 1), A1, explicit.prolongation(dim, n1, prolong))
+    n2, s2 = mg.level_stencil(2)
+    assert np.abs(G2 - explicit.operator(s2, n2)).max() <= 1e-13 * np.abs(G2).max()
 
 
 def test_galerkin_radius_with_cubic_interpolation():
@@ -345,10 +386,13 @@ def test_measured_two_grid_rate_matches_lfa():
     assert rho - 0.01 * rho < cr <= rho * (1 + 1e-9)
 
 
-@pytest.mark.parametrize("gamma", [1, 2])
-def test_multilevel_rate_is_near_two_grid_rate(gamma):
+@pytest.mark.parametrize("gamma,coarse", [(1, 0), (2, 0), (1, 2), (1, 3), (2, 3)])
+def test_multilevel_rate_is_near_two_grid_rate(gamma, coarse):
+    """Measured multilevel rate against the LFA two-grid factor of the same coarse
+    operator (for the second-order ones, section 3.1's claim that the lower-order coarse
+    operator does not slow the cycle is what the LFA quantifies)."""
     n = 129
-    mg = oracle.Multigrid(2, n, gamma=gamma)
+    mg = oracle.Multigrid(2, n, gamma=gamma, coarse=coarse)
     s = mg.level_stencil(0)[1]
     rng = np.random.default_rng(4)
     f = np.zeros((n, n))
@@ -359,7 +403,7 @@ def test_multilevel_rate_is_near_two_grid_rate(gamma):
         mg.cycle(u, f)
         r.append(oracle.norm(oracle.residual(s, f, u)))
     cr = r[-1] / r[-2]
-    rho2 = lfa.two_grid_rho(lfa.Scheme(2), m=16)
+    rho2 = lfa.two_grid_rho(lfa.Scheme(2, coarse=coarse), m=16)
     assert rho2 - 0.01 <= cr <= rho2 + 0.05
 
 
