@@ -7,8 +7,9 @@ the FP64 rounding floor), with f and u resident in HBM.  Workloads (--workload):
       sum_{kx,ky<=64} g_k/|k| sin(kx pi x) sin(ky pi y), g_k ~ N(0,1) (seeded), V(2,1)
       omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized
       coarse operators to 9x9 with an exact coarsest solve, FP64.  The JSON line also
-      carries the Galerkin and W(2,1) combinations of the same problem
-      (`config_variants`; --no-variants skips them).
+      carries the Galerkin and W(2,1) combinations of the same problem, and V(2,1) with
+      the second-order coarse operators of section 3.1 (`config_variants`;
+      --no-variants skips them).
   poisson3d-513             3D, n = 513, uniform[-1,1] noise smoothed by three
       neighbour-average passes, V(2,1) (omega = 9/11), mixed precision (eight FP32
       cycles per FP64 refinement step) against FP64.
@@ -60,7 +61,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="poisson2d-4097", choices=sorted(WORKLOADS))
     p.add_argument("--n", type=int, default=None)
-    p.add_argument("--coarse", type=int, default=None)
+    p.add_argument("--coarse", type=int, default=None,
+                   help="0 rediscretized, 1 Galerkin, 2 second-order rediscretized, 3 second-order Galerkin")
     p.add_argument("--gamma", type=int, default=None)
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
@@ -97,7 +99,8 @@ def make_rhs(w):
 
 
 def describe(w):
-    kind = "Galerkin" if w["coarse"] else "rediscretized"
+    kind = {0: "rediscretized", 1: "Galerkin", 2: "second-order rediscretized",
+            3: "second-order Galerkin"}[w["coarse"]]
     cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
     rhs = {"fourier": "Fourier RHS k<=64 amplitudes N(0,1)/|k|",
            "noise": "uniform[-1,1] noise smoothed by 3 neighbour-average passes",
@@ -465,9 +468,9 @@ def main():
     variants = None
     if args.workload == "poisson2d-4097" and not args.no_variants:
         variants = {}
-        for coarse, gamma in ((0, 1), (1, 1), (0, 2), (1, 2)):
-            name = "%s-%s(%d,%d)" % ("galerkin" if coarse else "rediscretized", "W" if gamma == 2 else "V",
-                                     w["nu1"], w["nu2"])
+        kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
+        for coarse, gamma in ((0, 1), (1, 1), (0, 2), (1, 2), (2, 1), (3, 1)):
+            name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
             if coarse == w["coarse"] and gamma == w["gamma"]:
                 vs, vres = sec, res
             else:
@@ -531,7 +534,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": describe(w), "name": args.workload, "dim": d, "n": n, "unknowns": unknowns,
-            "cycle": cyc, "coarse": "galerkin" if w["coarse"] else "rediscretized",
+            "cycle": cyc, "coarse": ["rediscretized", "galerkin", "rediscretized-order2",
+                                     "galerkin-order2"][w["coarse"]],
             "precision": "fp64" if w["precision"] == 0 else "mixed",
             "cycles": res.cycles, "outer_steps": res.outer_steps,
             "final_rel_residual": res.rel_residual, "floor_hit": bool(res.floor_hit),

@@ -50,8 +50,12 @@ typedef enum {
 } mg_status;
 
 typedef enum {
-  MG_COARSE_NG = 0,       /* rediscretized: the fine stencil at the coarse spacing (eq. L_H_4n_2d) */
-  MG_COARSE_GALERKIN = 1  /* R * L_l * P built at setup, level by level (eq. L_H_4G) */
+  MG_COARSE_NG = 0,        /* rediscretized: the fine stencil at the coarse spacing (eq. L_H_4n_2d) */
+  MG_COARSE_GALERKIN = 1,  /* R * L_l * P built at setup, level by level (eq. L_H_4G) */
+  /* Second-order coarse operators for a fourth-order fine operator (section 3.1): */
+  MG_COARSE_NG2 = 2,       /* the second-order operator at every coarse spacing (eq. L_H_2d) */
+  MG_COARSE_G2 = 3         /* level 1: R * L_h^(2) * P with the second-order operator at the finest
+                            * spacing (eq. L_H_2G_2d); below it R * L_l * P, level by level */
 } mg_coarse;
 
 typedef enum { MG_SMOOTH_JACOBI = 0 } mg_smoother;

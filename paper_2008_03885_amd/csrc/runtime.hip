@@ -258,7 +258,8 @@ mg_status validate(const mg_config *c, int *levels) {
   if (!c) return fail(MG_EINVAL, "null config");
   if (c->dim != 2 && c->dim != 3) return fail(MG_EINVAL, "dim must be 2 or 3");
   if (c->order != 2 && c->order != 4) return fail(MG_EINVAL, "order must be 2 or 4");
-  if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN)
+  if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN && c->coarse != MG_COARSE_NG2 &&
+      c->coarse != MG_COARSE_G2)
     return fail(MG_EINVAL, "unknown coarse operator");
   if (c->smoother != MG_SMOOTH_JACOBI) return fail(MG_EINVAL, "unknown smoother");
   if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
@@ -789,6 +790,10 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
     const double h = 1.0 / (n - 1);
     if (l == 0 || cfg->coarse == MG_COARSE_NG)
       c->ops.push_back(rediscretized(cfg->order, cfg->dim, h));
+    else if (cfg->coarse == MG_COARSE_NG2)
+      c->ops.push_back(rediscretized(2, cfg->dim, h));
+    else if (cfg->coarse == MG_COARSE_G2 && l == 1)  // R L_h^(2) P, second order at the finest spacing
+      c->ops.push_back(galerkin(rediscretized(2, cfg->dim, 1.0 / (cfg->n - 1)), cfg->dim, cfg->prolong));
     else
       c->ops.push_back(galerkin(c->ops[l - 1], cfg->dim, cfg->prolong));
     n = (n - 1) / 2 + 1;

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgmi.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOCONV, MG_ENUMERIC, MG_EBUSY = range(7)
-MG_COARSE_NG, MG_COARSE_GALERKIN = 0, 1
+MG_COARSE_NG, MG_COARSE_GALERKIN, MG_COARSE_NG2, MG_COARSE_G2 = 0, 1, 2, 3
 MG_SMOOTH_JACOBI = 0
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_MAX_HISTORY = 512

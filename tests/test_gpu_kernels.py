@@ -22,6 +22,8 @@ CASES_2D = [
     (2, 9, 0, 3, 0), (2, 17, 0, 3, 0), (2, 65, 0, 3, 0), (2, 257, 0, 3, 0), (2, 1025, 0, 3, 0),
     (2, 1025, 0, 3, 2), (2, 257, 1, 3, 1), (2, 257, 1, 3, 2), (2, 1025, 1, 3, 1),
     (2, 513, 1, 1, 1), (2, 513, 1, 1, 2),
+    # second-order coarse operators (section 3.1): rediscretized and "Galerkin"
+    (2, 257, 2, 3, 1), (2, 257, 3, 3, 1), (2, 257, 3, 3, 2), (2, 513, 3, 1, 1),
 ]
 
 
@@ -147,7 +149,7 @@ def test_coarsest_solve(dim, coarse, prolong, fp32):
 def test_level_operators_match_oracle_stencils():
     """The library's 1D-factor Galerkin recursion reproduces the oracle's coarse stencils
     (built by the definition R*L*P on the infinite grid)."""
-    for coarse, prolong in ((0, 3), (1, 3), (1, 1)):
+    for coarse, prolong in ((0, 3), (1, 3), (1, 1), (2, 3), (3, 3), (3, 1)):
         H = Handle(2, 257, coarse=coarse, prolong=prolong)
         try:
             for l in range(H.oracle.levels):
@@ -281,6 +283,7 @@ CASES_3D = [
     # dim, finest n, coarse, prolong, level
     (3, 9, 0, 3, 0), (3, 17, 0, 3, 0), (3, 33, 0, 3, 0), (3, 65, 0, 3, 0), (3, 65, 0, 3, 1),
     (3, 33, 1, 3, 1), (3, 65, 1, 3, 1), (3, 65, 1, 3, 2), (3, 33, 1, 1, 1),
+    (3, 65, 2, 3, 1), (3, 65, 3, 3, 1), (3, 65, 3, 3, 2),
 ]
 
 

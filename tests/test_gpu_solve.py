@@ -32,6 +32,8 @@ CYCLE_CASES = [
     (2, 129, 1, 3, 2, 1, 2), (2, 129, 0, 1, 2, 1, 1), (2, 129, 1, 1, 2, 2, 1),
     (2, 257, 0, 3, 1, 1, 1), (2, 65, 0, 3, 0, 2, 1), (2, 65, 0, 3, 3, 0, 2), (2, 9, 0, 3, 2, 1, 1),
     (2, 1025, 1, 3, 2, 1, 2),
+    # second-order coarse operators (section 3.1)
+    (2, 257, 2, 3, 2, 1, 1), (2, 257, 3, 3, 2, 1, 1), (2, 129, 3, 1, 2, 1, 2), (2, 129, 2, 3, 2, 2, 2),
 ]
 
 
@@ -100,7 +102,7 @@ def test_c1_solve_to_tolerance():
         H.close()
 
 
-@pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 1), (0, 2), (1, 2)])
+@pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 1), (0, 2), (1, 2), (2, 1), (3, 1)])
 def test_c2_full_size(coarse, gamma):
     """2D 4097^2, Fourier right-hand side k <= 64, V(2,1)/W(2,1), nG/Galerkin, FP64: the
     solve reaches 1e-10 or the rounding floor, and matches the exact discrete solution."""
@@ -230,6 +232,7 @@ CYCLE_CASES_3D = [
     (17, 0, 3, 2, 1, 1), (33, 0, 3, 2, 1, 1), (33, 1, 3, 2, 1, 1), (33, 0, 3, 2, 2, 2),
     (33, 1, 3, 2, 2, 2), (33, 0, 1, 1, 1, 1), (65, 0, 3, 2, 1, 1), (65, 1, 3, 2, 2, 2),
     (33, 1, 3, 0, 2, 1), (129, 1, 3, 2, 2, 2),
+    (65, 2, 3, 2, 1, 1), (65, 3, 3, 2, 2, 2), (33, 3, 1, 2, 1, 1),
 ]
 
 
