@@ -34,6 +34,9 @@ COARSE_NG, COARSE_GALERKIN = 0, 1
 # second-order coarse operators for a fourth-order fine operator (section 3.1):
 # rediscretized (eq. L_H_2d) and "Galerkin" from the second-order operator (eq. L_H_2G_2d)
 COARSE_NG2, COARSE_G2 = 2, 3
+# smoothers: omega-Jacobi (section 5.3) and omega red-black Jacobi (section 3.1 eq. S_rb with
+# the Jacobi partial step; red = odd index sum)
+SMOOTH_JACOBI, SMOOTH_RBJ = 0, 1
 MAX_RADIUS = 6
 
 
@@ -53,7 +56,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("order", ctypes.c_int),
                 ("coarse", ctypes.c_int), ("restrict_op", ctypes.c_int), ("prolong", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int),
-                ("n_coarsest", ctypes.c_int), ("omega", ctypes.c_double)]
+                ("n_coarsest", ctypes.c_int), ("omega", ctypes.c_double), ("smoother", ctypes.c_int)]
 
 
 _lib = None
@@ -73,6 +76,7 @@ def _load():
             "or_apply": (None, [_I, _I, _I, _D, _D, _D]),
             "or_residual": (None, [_I, _I, _I, _D, _D, _D, _D]),
             "or_jacobi": (None, [_I, _I, _I, _D, ctypes.c_double, _D, _D, _D]),
+            "or_jacobi_colour": (None, [_I, _I, _I, _D, ctypes.c_double, _I, _D, _D, _D]),
             "or_restrict": (None, [_I, _I, _I, _D, _D]),
             "or_prolong_add": (None, [_I, _I, _I, _D, _D]),
             "or_norm": (ctypes.c_double, [_I, _I, _D]),
@@ -156,6 +160,16 @@ def jacobi(s, omega, f, u):
     return out
 
 
+def jacobi_colour(s, omega, colour, f, u):
+    """One partial step on colour 1 (odd index sum), 2 (even) or 0 (every point)."""
+    dim, n = _grid_dim(u)
+    out = np.empty_like(u)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    _load().or_jacobi_colour(dim, n, _stencil_radius(s), _p(s), float(omega), int(colour), _p(f),
+                             _p(u), _p(out))
+    return out
+
+
 def restrict(d, restrict_op=RESTRICT_FW):
     dim, nf = _grid_dim(d)
     nc = (nf - 1) // 2 + 1
@@ -189,15 +203,22 @@ def jacobi_omega_star(dim):
     return {2: 10.0 / 13.0, 3: 9.0 / 11.0}[dim]
 
 
+def rbj_omega(dim, order=4):
+    """Default omega of red-black Jacobi: the minimiser of the LFA two-grid factor of the
+    V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
+    return {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13}[(dim, order)]
+
+
 class Multigrid:
     """The (lmax+1)-level gamma-cycle of section 2.2 on the CPU, in FP64."""
 
     def __init__(self, dim, n, order=4, coarse=COARSE_NG, restrict_op=RESTRICT_FW,
-                 prolong=PROLONG_CUBIC, nu1=2, nu2=1, gamma=1, n_coarsest=9, omega=None):
+                 prolong=PROLONG_CUBIC, nu1=2, nu2=1, gamma=1, n_coarsest=9, omega=None,
+                 smoother=SMOOTH_JACOBI):
         if omega is None:
-            omega = jacobi_omega_star(dim)
+            omega = jacobi_omega_star(dim) if smoother == SMOOTH_JACOBI else rbj_omega(dim, order)
         self.cfg = _Config(dim, n, order, coarse, restrict_op, prolong, nu1, nu2, gamma,
-                           n_coarsest, float(omega))
+                           n_coarsest, float(omega), smoother)
         self.dim, self.n = dim, n
         self._h = _load().or_mg_create(ctypes.byref(self.cfg))
         if not self._h:

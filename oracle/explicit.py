@@ -9,7 +9,9 @@ give brute-force checks of the C oracle:
 * ``cycle_matrix`` composes the gamma-cycle error propagator from section 2.2:
   M_l = S^nu2 (I - P Ltilde_{l+1}^{-1} R A_l) S^nu1 with the exact inverse on the
   coarsest level and Ltilde^{-1} = (I - M_{l+1}^gamma) A_{l+1}^{-1} elsewhere
-  (appendix A.3.1, eq. L_H_approx).
+  (appendix A.3.1, eq. L_H_approx).  With rb=True the smoother is the red-black product
+  S = S^B S^R of section 3.1 eq. S_rb, S^c = I - (omega/a_0) X_c A with X_c the diagonal
+  0/1 mask of colour c (red: odd index sum).
 
 Unknown p enumerates interior points x fastest: p = ((k-1)*q + (j-1))*q + (i-1), q = n-2.
 """
@@ -135,14 +137,28 @@ def jacobi(A, omega, a0):
     return (sp.identity(m) - (omega / a0) * A).tocsr()
 
 
-def cycle_matrix(As, a0s, omega, nu1, nu2, gamma, dim, ns, restrict_op=1, prolong=3):
+def colour_mask(n, dim, odd):
+    """Diagonal of X_c over the interior unknowns: 1 where (i+j+k) % 2 == odd."""
+    x = np.zeros((n - 2) ** dim)
+    for pt_zyx in _interior(n, dim):
+        pt = _as_xyz(pt_zyx)
+        x[_unknown(pt, n)] = 1.0 if sum(pt) % 2 == odd else 0.0
+    return x
+
+
+def cycle_matrix(As, a0s, omega, nu1, nu2, gamma, dim, ns, restrict_op=1, prolong=3, rb=False):
     """Dense error propagator of the gamma-cycle over levels 0..L-1 (level L-1 exact)."""
     L = len(As)
 
     def M(l):
         A = As[l].toarray()
         m = A.shape[0]
-        S = np.eye(m) - (omega / a0s[l]) * A
+        if rb:
+            red = np.eye(m) - (omega / a0s[l]) * colour_mask(ns[l], dim, 1)[:, None] * A
+            black = np.eye(m) - (omega / a0s[l]) * colour_mask(ns[l], dim, 0)[:, None] * A
+            S = black @ red
+        else:
+            S = np.eye(m) - (omega / a0s[l]) * A
         Rm = restriction(dim, ns[l], restrict_op).toarray()
         Pm = prolongation(dim, ns[l], prolong).toarray()
         Ac_inv = np.linalg.inv(As[l + 1].toarray())

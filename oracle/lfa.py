@@ -9,6 +9,11 @@ Everything here is built from the Fourier symbols the paper prints, not from ste
 * cubic transfer: prod_a (1 - s_a^2 (3 - 2 s_a)) (appendix A.4);
 * linear interpolation: the transpose of full weighting (appendix A.2), same values;
 * omega-Jacobi: S = 1 - omega * L/a_0 with a_0 the centre coefficient (section 5.3);
+* omega red-black Jacobi (section 3.1 eq. S_rb with the Jacobi partial step, the smoother of
+  appendix A.4.1): the red (odd index sum) then the black points take an omega-Jacobi
+  step.  Multiplying a grid function by (-1)^(index sum) moves theta to theta + (pi,..,pi),
+  so a partial step is I + (1/2)(I -+ P) (S_J - I) on the 2^d aliases, P the alias
+  permutation alpha -> 1 - alpha (section 5.3 eq. S_hat_RB_2d is the 2D five-point case);
 * two-grid operator on the 2^d aliases of theta in [-pi/2, pi/2)^d:
   M = S^nu2 (I - p L_H^{-1} r^T diag(L)) S^nu1 (section 2.2 eqs. K, M_2level; appendix
   A.2 eqs. K_hat_2, M_2); Galerkin coarse symbol L_H(2 theta) = sum_alpha r_alpha L_alpha p_alpha
@@ -32,6 +37,7 @@ FW, CUBIC = 1, 3
 LINEAR = 1
 NG, GALERKIN = 0, 1
 NG2, G2 = 2, 3  # second-order coarse operators (section 3.1 eqs. L_H_2d, L_H_2G_2d)
+JACOBI, RBJ = 0, 1  # smoothers: omega-Jacobi, omega red-black Jacobi
 
 
 def sin2(theta):
@@ -72,11 +78,14 @@ class Scheme:
     """Parameters of the cycle being analysed."""
 
     def __init__(self, dim, order=4, coarse=NG, restrict_op=FW, prolong=CUBIC, nu1=2, nu2=1,
-                 omega=None):
+                 omega=None, smoother=JACOBI):
         self.dim, self.order, self.coarse = dim, order, coarse
         self.restrict_op, self.prolong = restrict_op, prolong
         self.nu1, self.nu2 = nu1, nu2
-        self.omega = jacobi_optimum(dim, order)[0] if omega is None else omega
+        self.smoother = smoother
+        if omega is None:
+            omega = jacobi_optimum(dim, order)[0] if smoother == JACOBI else RBJ_OMEGA[(dim, order)]
+        self.omega = omega
 
     def level_symbol(self, level, theta, h0=1.0):
         """Symbol of the level-l operator at level-l frequency theta (spacing h0 * 2^l)."""
@@ -95,23 +104,54 @@ class Scheme:
 
     def level_diagonal(self, level, h0=1.0, m=32):
         """Centre stencil coefficient = mean of the symbol over the frequency torus."""
-        grid = -np.pi + 2 * np.pi * np.arange(m) / m
-        pts = np.stack(np.meshgrid(*([grid] * self.dim), indexing="ij"), axis=-1)
-        return float(np.mean(self.level_symbol(level, pts, h0)))
+        key = (level, h0, m)
+        memo = self.__dict__.setdefault("_diag", {})
+        if key not in memo:
+            grid = -np.pi + 2 * np.pi * np.arange(m) / m
+            pts = np.stack(np.meshgrid(*([grid] * self.dim), indexing="ij"), axis=-1)
+            memo[key] = float(np.mean(self.level_symbol(level, pts, h0)))
+        return memo[key]
 
     def smoother_symbol(self, theta, level=0, h0=1.0):
         return 1.0 - self.omega * self.level_symbol(level, theta, h0) / self.level_diagonal(level, h0)
+
+    def smoother_matrix(self, theta, h0=1.0):
+        """2^d x 2^d symbol of one smoothing sweep on the aliases of theta."""
+        th = aliases(theta)
+        D = np.diag(-self.omega * self.level_symbol(0, th, h0) / self.level_diagonal(0, h0))
+        eye = np.eye(len(D))
+        if self.smoother == JACOBI:
+            return eye + D
+        P = eye[::-1]  # alias index alpha (binary, axis 0 first) -> its complement
+        red = eye + 0.5 * (eye - P) @ D
+        black = eye + 0.5 * (eye + P) @ D
+        return black @ red
 
     def two_grid_matrix(self, theta, h0=1.0):
         """2^d x 2^d symbol of S^nu2 K S^nu1 at one low frequency theta."""
         th = aliases(theta)
         L = self.level_symbol(0, th, h0)
-        S = np.diag(1.0 - self.omega * L / self.level_diagonal(0, h0))
+        S = self.smoother_matrix(theta, h0)
         r = symbol_transfer(th, self.restrict_op)
         p = symbol_transfer(th, self.prolong)
         LH = self.level_symbol(1, 2.0 * np.asarray(theta, dtype=float), h0)
         K = np.eye(len(L)) - np.outer(p, r * L) / LH
         return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
+
+
+# Default omega of the red-black Jacobi smoother: the value minimising the two-grid factor
+# of the V(2,1) cycle with cubic interpolation and the rediscretized operator, rounded to two
+# decimals (rbj_optimum recomputes it).
+RBJ_OMEGA = {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13}
+
+
+def rbj_optimum(dim, order=4, m=None):
+    """omega minimising two_grid_rho for red-black Jacobi, V(2,1), cubic, rediscretized."""
+    from scipy.optimize import minimize_scalar
+    m = m or (24 if dim == 2 else 10)
+    rho = lambda w: two_grid_rho(Scheme(dim, order, nu1=2, nu2=1, omega=w, smoother=RBJ), m)
+    r = minimize_scalar(rho, bounds=(0.9, 1.3), method="bounded", options={"xatol": 1e-4})
+    return float(r.x), float(r.fun)
 
 
 def jacobi_optimum(dim, order=4):
@@ -134,8 +174,22 @@ def jacobi_optimum(dim, order=4):
     return 2.0 / (q_lo + q_hi), (q_hi - q_lo) / (q_hi + q_lo)
 
 
+def rb_smoothing_factor(scheme, nu=1, m=32):
+    """mu = sup over low theta of rho(Q S^nu)^(1/nu), Q the ideal coarse-level correction
+    (zero on alias 0, identity on the others): section 5.3 eq. mu_2_2, any smoother."""
+    grid = -np.pi / 2 + np.pi * np.arange(m + 1) / m
+    Q = np.eye(2 ** scheme.dim)
+    Q[0, 0] = 0.0
+    best = 0.0
+    for theta in itertools.product(grid, repeat=scheme.dim):
+        S = np.linalg.matrix_power(scheme.smoother_matrix(np.array(theta)), nu)
+        best = max(best, float(np.max(np.abs(np.linalg.eigvals(Q @ S)))) ** (1.0 / nu))
+    return best
+
+
 def smoothing_factor(scheme, m=64):
     """mu = sup over high frequencies of |S(theta)| (omega-Jacobi, section 2.2 eq. mu)."""
+    assert scheme.smoother == JACOBI
     grid = -np.pi + 2 * np.pi * (np.arange(m) + 0.0) / m
     pts = np.stack(np.meshgrid(*([grid] * scheme.dim), indexing="ij"), axis=-1).reshape(-1, scheme.dim)
     high = np.any(np.abs(pts) >= np.pi / 2 - 1e-12, axis=-1)
@@ -170,8 +224,16 @@ def finite_two_grid_spectrum(scheme, n):
         if np.all(k < N // 2):
             eig.extend(np.linalg.eigvals(scheme.two_grid_matrix(theta, h0)))
         else:
-            th = aliases(theta)
-            keep = np.all((k[None, :] < N // 2) | (th - theta[None, :] == 0), axis=-1)
-            S = scheme.smoother_symbol(th[keep], 0, h0)
-            eig.extend(S ** (scheme.nu1 + scheme.nu2))
+            # On an axis with k = N/2 the alias theta + pi is the same sine mode with the
+            # sign flipped; fold the 2^d alias coefficients onto the distinct modes.
+            half = k == N // 2
+            idx = list(itertools.product((0, 1), repeat=scheme.dim))
+            keep = [i for i, a in enumerate(idx) if not any(half & (np.array(a) == 1))]
+            fold = np.zeros((len(keep), len(idx)))
+            for j, a in enumerate(idx):
+                a = np.array(a)
+                base = tuple(np.where(half, 0, a))
+                fold[keep.index(idx.index(base)), j] = (-1.0) ** int(np.sum(a[half]))
+            S = fold @ scheme.smoother_matrix(theta, h0)[:, keep]
+            eig.extend(np.linalg.eigvals(np.linalg.matrix_power(S, scheme.nu1 + scheme.nu2)))
     return np.array(eig)

@@ -279,8 +279,8 @@ void or_residual(int dim, int n, int R, const double *s, const double *f, const 
   free_entries(&e);
 }
 
-void or_jacobi(int dim, int n, int R, const double *s, double omega, const double *f,
-               const double *u, double *u_out) {
+void or_jacobi_colour(int dim, int n, int R, const double *s, double omega, int colour,
+                      const double *f, const double *u, double *u_out) {
   entries e = list_entries(dim, R, s);
   double a0 = s[sidx(dim, R, 0, 0, 0)];
   memcpy(u_out, u, sizeof(double) * npts(dim, n));
@@ -288,11 +288,19 @@ void or_jacobi(int dim, int n, int R, const double *s, double omega, const doubl
   for (int k = k_first(dim); k < k_end(dim, n); ++k) {
     for (int j = 1; j < n - 1; ++j)
       for (int i = 1; i < n - 1; ++i) {
+        int odd = (i + j + k) % 2;  /* k = 0 in 2D */
+        if (colour == 1 && !odd) continue;
+        if (colour == 2 && odd) continue;
         long p = at(n, i, j, k);
         u_out[p] = u[p] + omega / a0 * (f[p] - apply_at(&e, dim, n, u, i, j, k));
       }
   }
   free_entries(&e);
+}
+
+void or_jacobi(int dim, int n, int R, const double *s, double omega, const double *f,
+               const double *u, double *u_out) {
+  or_jacobi_colour(dim, n, R, s, omega, 0, f, u, u_out);
 }
 
 void or_restrict(int dim, int nf, int restrict_op, const double *d, double *fc) {
@@ -490,6 +498,7 @@ or_mg *or_mg_create(const or_config *cfg) {
   if (L <= 0 || L > OR_MAX_LEVELS || (cfg->dim != 2 && cfg->dim != 3)) return NULL;
   if (cfg->order != 2 && cfg->order != 4) return NULL;
   if (cfg->coarse < OR_COARSE_NG || cfg->coarse > OR_COARSE_G2) return NULL;
+  if (cfg->smoother != OR_SMOOTH_JACOBI && cfg->smoother != OR_SMOOTH_RBJ) return NULL;
   or_mg *mg = (or_mg *)calloc(1, sizeof(or_mg));
   int dim = cfg->dim;
   int w = swidth(OR_MAX_RADIUS);
@@ -557,9 +566,14 @@ int or_mg_level_stencil(const or_mg *mg, int l, int *n_out, double *s) {
 static void smooth(or_mg *mg, int l, double *u, const double *f, int sweeps) {
   or_level *lv = &mg->lev[l];
   int dim = mg->cfg.dim;
+  /* omega-Jacobi: one partial step on every point; red-black: red points, then black
+   * points from the updated red values (S = S^B S^R, section 3.1 eq. S_rb) */
+  const int rb = mg->cfg.smoother == OR_SMOOTH_RBJ;
   for (int s = 0; s < sweeps; ++s) {
-    or_jacobi(dim, lv->n, lv->R, lv->s, mg->cfg.omega, f, u, lv->t);
-    memcpy(u, lv->t, sizeof(double) * npts(dim, lv->n));
+    for (int c = rb ? 1 : 0; c <= (rb ? 2 : 0); ++c) {
+      or_jacobi_colour(dim, lv->n, lv->R, lv->s, mg->cfg.omega, c, f, u, lv->t);
+      memcpy(u, lv->t, sizeof(double) * npts(dim, lv->n));
+    }
   }
 }
 

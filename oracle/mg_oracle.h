@@ -42,6 +42,12 @@ extern "C" {
 #define OR_COARSE_G2 3       /* L_1 = R L_h^(2) P from the second-order operator at the finest
                               * spacing (section 3.1, eq. L_H_2G_2d), then L_{l+1} = R L_l P */
 
+/* Smoother identifiers. */
+#define OR_SMOOTH_JACOBI 0 /* omega-Jacobi (section 5.3) */
+#define OR_SMOOTH_RBJ 1    /* omega red-black Jacobi: section 3.1 eq. S_rb, S = S^B S^R, with the
+                            * Jacobi partial step on each colour (the smoother appendix A.4.1
+                            * uses); red = odd index sum i+j(+k), black = even */
+
 typedef struct {
   int dim;          /* 2 or 3 */
   int n;            /* finest points per axis incl. boundary, 2^k+1 */
@@ -53,6 +59,7 @@ typedef struct {
   int gamma;        /* 1 = V cycle, 2 = W cycle */
   int n_coarsest;   /* points per axis of the coarsest level, e.g. 9 */
   double omega;     /* omega-Jacobi relaxation parameter, same on every level */
+  int smoother;     /* OR_SMOOTH_JACOBI or OR_SMOOTH_RBJ; a sweep of either counts once in nu */
 } or_config;
 
 /* Number of levels n, (n-1)/2+1, ... down to n_coarsest; 0 if n does not reach it. */
@@ -81,6 +88,11 @@ void or_residual(int dim, int n, int R, const double *s, const double *f, const 
  * (section 5.3 smoother with the diagonal of the operator in use). */
 void or_jacobi(int dim, int n, int R, const double *s, double omega, const double *f,
                const double *u, double *u_out);
+/* One omega-Jacobi partial step on one colour: at interior points whose index sum
+ * i+j(+k) is odd (colour 1, red) or even (colour 2, black) u_out = u + omega/a_0 (f - L u);
+ * every other point keeps u.  Colour 0 updates every interior point (or_jacobi). */
+void or_jacobi_colour(int dim, int n, int R, const double *s, double omega, int colour,
+                      const double *f, const double *u, double *u_out);
 /* fc = I_h^H d on the coarse grid of nc = (nf-1)/2+1 points (standard coarsening). */
 void or_restrict(int dim, int nf, int restrict_op, const double *d, double *fc);
 /* u += I_H^h v, v on the coarse grid of nc = (nf-1)/2+1 points. */

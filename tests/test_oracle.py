@@ -218,19 +218,23 @@ def _cycle_matrix(mg, n, dim):
     return M
 
 
-CASES_2G = [(2, 17, 9, c, p, nu) for c in (0, 1, 2, 3) for p in (1, 3) for nu in ((2, 1), (1, 1))] + \
-           [(3, 9, 5, c, 3, (2, 1)) for c in (0, 1, 2, 3)]
+CASES_2G = [(2, 17, 9, c, p, nu, 0) for c in (0, 1, 2, 3) for p in (1, 3) for nu in ((2, 1), (1, 1))] + \
+           [(3, 9, 5, c, 3, (2, 1), 0) for c in (0, 1, 2, 3)] + \
+           [(2, 17, 9, c, p, nu, 1) for c in (0, 1, 2, 3) for p in (1, 3) for nu in ((2, 1), (1, 1))] + \
+           [(2, 13, 7, 0, 3, (1, 1), 1), (3, 9, 5, 0, 3, (2, 1), 1), (3, 9, 5, 1, 3, (1, 1), 1),
+            (3, 9, 5, 3, 1, (2, 1), 1)]
 
 
-@pytest.mark.parametrize("dim,n,nc,coarse,prolong,nu", CASES_2G)
-def test_two_grid_spectrum_equals_lfa(dim, n, nc, coarse, prolong, nu):
+@pytest.mark.parametrize("dim,n,nc,coarse,prolong,nu,smoother", CASES_2G)
+def test_two_grid_spectrum_equals_lfa(dim, n, nc, coarse, prolong, nu, smoother):
     """The computed two-grid operator has exactly the eigenvalues the LFA symbols give
-    on the finite grid (section 2.2 eqs. K, M_2level; appendix A.2 eq. M_2)."""
+    on the finite grid (section 2.2 eqs. K, M_2level; appendix A.2 eq. M_2), for
+    omega-Jacobi and for red-black Jacobi (section 5.3 eqs. S_hat_F, M_2)."""
     mg = oracle.Multigrid(dim, n, coarse=coarse, prolong=prolong, nu1=nu[0], nu2=nu[1],
-                          n_coarsest=nc)
+                          n_coarsest=nc, smoother=smoother)
     assert mg.levels == 2
     ev = np.linalg.eigvals(_cycle_matrix(mg, n, dim))
-    sch = lfa.Scheme(dim, coarse=coarse, prolong=prolong, nu1=nu[0], nu2=nu[1])
+    sch = lfa.Scheme(dim, coarse=coarse, prolong=prolong, nu1=nu[0], nu2=nu[1], smoother=smoother)
     ref = lfa.finite_two_grid_spectrum(sch, n)
     assert len(ev) == len(ref)
     key = lambda z: (round(z.real, 9), round(z.imag, 9))
@@ -250,19 +254,102 @@ def test_two_grid_rho_values():
 
 @pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("coarse", [0, 1, 2, 3])
-def test_multilevel_cycle_matches_explicit_matrices(gamma, coarse):
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_multilevel_cycle_matches_explicit_matrices(gamma, coarse, smoother):
     """Three-level V and W cycles equal the composition of explicit matrices by the
-    recursion of section 2.2 (eqs. K_l, M) with appendix A.3.1 eq. L_H_approx."""
+    recursion of section 2.2 (eqs. K_l, M) with appendix A.3.1 eq. L_H_approx; the
+    red-black smoother as the product of masked Jacobi matrices (section 3.1 eq. S_rb)."""
     dim, n = 2, 17
-    mg = oracle.Multigrid(dim, n, coarse=coarse, gamma=gamma, n_coarsest=5)
+    mg = oracle.Multigrid(dim, n, coarse=coarse, gamma=gamma, n_coarsest=5, smoother=smoother)
     assert mg.levels == 3
     M = _cycle_matrix(mg, n, dim)
     ns = [17, 9, 5]
     stencils = [mg.level_stencil(l)[1] for l in range(3)]
     As = [explicit.operator(s, ns[l]) for l, s in enumerate(stencils)]
     a0 = [s[((s.shape[0] - 1) // 2,) * dim] for s in stencils]
-    Me = explicit.cycle_matrix(As, a0, oracle.jacobi_omega_star(dim), 2, 1, gamma, dim, ns)
+    Me = explicit.cycle_matrix(As, a0, mg.cfg.omega, 2, 1, gamma, dim, ns, rb=smoother == 1)
     np.testing.assert_allclose(M, Me, atol=1e-13)
+
+
+# ------------------------------------------------------------ red-black smoothing --
+
+def test_rb_symbol_matches_printed_five_point():
+    """For the five-point operator the alias-mask construction of the red-black sweep
+    reduces to the printed 2 x 2 symbols (section 5.3 eq. S_hat_RB_2d, with xi of eq. xi_r2)
+    on span{theta, theta + (pi, pi)}, and leaves the other pair of aliases to itself."""
+    rng = np.random.default_rng(11)
+    for w in (1.0, 0.8, 1.2):
+        sch = lfa.Scheme(2, order=2, omega=w, smoother=lfa.RBJ)
+        for _ in range(5):
+            th = rng.uniform(-np.pi / 2, np.pi / 2, 2)
+            xi = 0.5 * (np.sin(th[0] / 2) ** 2 + np.sin(th[1] / 2) ** 2)
+            D = np.diag([xi, 1 - xi])
+            SR = np.eye(2) - w * np.array([[1.0, -1.0], [-1.0, 1.0]]) @ D
+            SB = np.eye(2) - w * np.array([[1.0, 1.0], [1.0, 1.0]]) @ D
+            S = sch.smoother_matrix(th)  # aliases (0,0), (0,1), (1,0), (1,1)
+            np.testing.assert_allclose(S[np.ix_([0, 3], [0, 3])], SB @ SR, atol=1e-14)
+            assert np.abs(S[np.ix_([0, 3], [1, 2])]).max() < 1e-15
+            assert np.abs(S[np.ix_([1, 2], [0, 3])]).max() < 1e-15
+
+
+@pytest.mark.parametrize("nu,rho", [(1, 0.250), (2, 0.074), (3, 0.053), (4, 0.041)])
+def test_rb_five_point_two_grid_factors_textbook(nu, rho):
+    """For the five-point operator red-black Jacobi is red-black Gauss-Seidel (no
+    same-colour neighbours).  Its LFA two-grid factors with full weighting and bilinear
+    interpolation at omega = 1 are the classical 0.250, 0.074, 0.053, 0.041 for nu = 1..4
+    (U. Trottenberg, C. W. Oosterlee, A. Schueller, Multigrid, 2001, section 4.5), and its
+    smoothing factor (section 5.3 eq. mu_2_2) is 1/4."""
+    sch = lfa.Scheme(2, order=2, prolong=lfa.LINEAR, nu1=nu, nu2=0, omega=1.0, smoother=lfa.RBJ)
+    assert abs(lfa.two_grid_rho(sch, m=96) - rho) < 5e-4
+    assert abs(lfa.rb_smoothing_factor(sch, 1, m=32) - 0.25) < 1e-12
+
+
+def _rb_gauss_seidel_five_point(f, u, h, omega):
+    """In-place Gauss-Seidel over the red points (odd i+j), then the black points, for
+    the five-point operator (section 5.3): each point solves its own equation given its
+    neighbours' current values, over-relaxed by omega."""
+    n = u.shape[0]
+    u = u.copy()
+    for colour in (1, 0):
+        for j in range(1, n - 1):
+            for i in range(1, n - 1):
+                if (i + j) % 2 != colour:
+                    continue
+                nb = u[j, i - 1] + u[j, i + 1] + u[j - 1, i] + u[j + 1, i]
+                gs = (h * h * f[j, i] + nb) / 4.0
+                u[j, i] = (1 - omega) * u[j, i] + omega * gs
+    return u
+
+
+def test_rb_partial_steps_equal_gauss_seidel_five_point():
+    """The red then black partial steps of the oracle equal in-place red-black
+    Gauss-Seidel for the five-point operator, which pins the colour of every point."""
+    n = 11
+    h = 1.0 / (n - 1)
+    rng = np.random.default_rng(5)
+    f = np.zeros((n, n))
+    u = np.zeros((n, n))
+    f[1:-1, 1:-1] = rng.standard_normal((n - 2, n - 2))
+    u[1:-1, 1:-1] = rng.standard_normal((n - 2, n - 2))
+    s = oracle.fine_stencil(2, 2, h)
+    for w in (1.0, 1.15):
+        red = oracle.jacobi_colour(s, w, 1, f, u)
+        both = oracle.jacobi_colour(s, w, 2, f, red)
+        np.testing.assert_allclose(both, _rb_gauss_seidel_five_point(f, u, h, w), atol=1e-12)
+        odd = (np.add.outer(np.arange(n), np.arange(n)) % 2) == 1
+        assert np.array_equal(red[~odd], u[~odd])  # the red step leaves black points alone
+    np.testing.assert_array_equal(oracle.jacobi_colour(s, 0.9, 0, f, u), oracle.jacobi(s, 0.9, f, u))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rbj_default_omega_is_lfa_optimum(dim):
+    """The default red-black omega minimises the LFA two-grid factor of V(2,1) (the
+    reading that omega is chosen for rho rather than mu, section 2.2 after eq. mu)."""
+    w, rho = lfa.rbj_optimum(dim, 4)
+    assert abs(w - oracle.rbj_omega(dim, 4)) < 0.01
+    assert abs(lfa.RBJ_OMEGA[(dim, 4)] - oracle.rbj_omega(dim, 4)) == 0
+    jac = lfa.two_grid_rho(lfa.Scheme(dim), m=12 if dim == 3 else 24)
+    assert rho < 0.2 * jac  # red-black Jacobi beats omega-Jacobi per sweep by far here
 
 
 # ----------------------------------------------------------------- brute-force RAP --
@@ -386,13 +473,14 @@ def test_measured_two_grid_rate_matches_lfa():
     assert rho - 0.01 * rho < cr <= rho * (1 + 1e-9)
 
 
-@pytest.mark.parametrize("gamma,coarse", [(1, 0), (2, 0), (1, 2), (1, 3), (2, 3)])
-def test_multilevel_rate_is_near_two_grid_rate(gamma, coarse):
+@pytest.mark.parametrize("gamma,coarse,smoother", [(1, 0, 0), (2, 0, 0), (1, 2, 0), (1, 3, 0),
+                                                (2, 3, 0), (1, 0, 1), (2, 1, 1)])
+def test_multilevel_rate_is_near_two_grid_rate(gamma, coarse, smoother):
     """Measured multilevel rate against the LFA two-grid factor of the same coarse
     operator (for the second-order ones, section 3.1's claim that the lower-order coarse
     operator does not slow the cycle is what the LFA quantifies)."""
     n = 129
-    mg = oracle.Multigrid(2, n, gamma=gamma, coarse=coarse)
+    mg = oracle.Multigrid(2, n, gamma=gamma, coarse=coarse, smoother=smoother)
     s = mg.level_stencil(0)[1]
     rng = np.random.default_rng(4)
     f = np.zeros((n, n))
@@ -403,7 +491,7 @@ def test_multilevel_rate_is_near_two_grid_rate(gamma, coarse):
         mg.cycle(u, f)
         r.append(oracle.norm(oracle.residual(s, f, u)))
     cr = r[-1] / r[-2]
-    rho2 = lfa.two_grid_rho(lfa.Scheme(2, coarse=coarse), m=16)
+    rho2 = lfa.two_grid_rho(lfa.Scheme(2, coarse=coarse, smoother=smoother), m=16)
     assert rho2 - 0.01 <= cr <= rho2 + 0.05
 
 
