@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--coarse", type=int, default=None,
                    help="0 rediscretized, 1 Galerkin, 2 second-order rediscretized, 3 second-order Galerkin")
     p.add_argument("--gamma", type=int, default=None)
+    p.add_argument("--smoother", type=int, default=None,
+                   help="0 omega-Jacobi (default), 1 red-black Jacobi")
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
     p.add_argument("--inner", type=int, default=None, help="FP32 cycles per refinement step")
@@ -107,8 +109,9 @@ def describe(w):
            "sine": "smooth sine-series RHS k<=8"}[w["rhs"]]
     prec = "FP64" if w["precision"] == 0 else "FP32 cycles in FP64 refinement"
     d = w["dim"]
-    return "%dD 4th-order Poisson %s, %s, %s omega-Jacobi, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
-        d, "x".join([str(w["n"])] * d), rhs, cyc, kind, d, prec)
+    sm = "red-black Jacobi" if w.get("smoother", 0) else "omega-Jacobi"
+    return "%dD 4th-order Poisson %s, %s, %s %s, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
+        d, "x".join([str(w["n"])] * d), rhs, cyc, sm, kind, d, prec)
 
 
 class Run:
@@ -121,7 +124,7 @@ class Run:
         self.cfg = mg.make_config(dim=w["dim"], n=w["n"], coarse=w["coarse"], gamma=w["gamma"],
                                   nu1=w["nu1"], nu2=w["nu2"], precision=precision, rtol=1e-10,
                                   max_cycles=60 if precision == 0 else 30,
-                                  inner_cycles=w["inner"])
+                                  inner_cycles=w["inner"], smoother=w.get("smoother", 0))
         self.h = mg.mg_setup(self.cfg, stream.cuda_stream)
         self.fd = fd
         self.ud = torch.zeros_like(fd)
@@ -177,7 +180,18 @@ def in_cycle_time(run, w, stream, reps):
     t = torch.empty_like(u)
     fc = torch.empty((nc,) * d, device="cuda", dtype=dt)
     v = torch.randn((nc,) * d, generator=gen, device="cuda", dtype=torch.float64).to(dt)
-    if d == 2:
+    if w.get("smoother", 0):
+        # red then black partial steps in a ping-pong, as the cycle runs them
+        bufs = [u, t]
+        col = [1]
+        def one():
+            e0.record(stream)
+            mg.mg_kernel_smooth_colour(run.h, 0, fp32, col[0], f.data_ptr(), bufs[0].data_ptr(),
+                                       bufs[1].data_ptr())
+            e1.record(stream)
+            bufs.reverse()
+            col[0] = 3 - col[0]
+    elif d == 2:
         def one():
             mg.mg_kernel_prolong_postsmooth(run.h, 0, fp32, v.data_ptr(), t.data_ptr(), f.data_ptr(), u.data_ptr())
             e0.record(stream)
@@ -231,7 +245,20 @@ def level_kernels(run, w, stream, reps, only_level0=False):
         fc = torch.empty(cshp, device="cuda", dtype=dt)
         v = torch.randn(cshp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
         P, Pc = n ** d, nc ** d
-        if d == 2:
+        if w.get("smoother", 0):
+            # red-black smoothing runs the separate kernels: two partial steps per sweep
+            ks = [
+                ("k_sweep%dd" % d, "red-black partial step", 3 * P * b,
+                 lambda: mg.mg_kernel_smooth_colour(run.h, l, fp32, 1, f.data_ptr(), u.data_ptr(),
+                                                    t.data_ptr())),
+                ("k_resid_restrict%dd" % d, "defect+FW", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
+                                                        fc.data_ptr())),
+                ("k_prolong%dd" % d, "interp+correct", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_prolong_correct(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
+                                                      t.data_ptr())),
+            ]
+        elif d == 2:
             ks = [
                 ("k_pre2d", "presmooth(%d)+defect+FW" % w["nu1"], (3 * P + Pc) * b,
                  lambda: mg.mg_kernel_presmooth_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
@@ -272,7 +299,8 @@ def cpu_baseline(w, cycles_needed, budget_s=20.0):
     n = w["n"] if (d == 2 or w["n"] <= cap) else cap
     ws = dict(w, n=n)
     f, _ = make_rhs(ws)
-    m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"])
+    m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
+                         smoother=w.get("smoother", 0))
     u = np.zeros_like(f)
     t0 = time.perf_counter()
     m.cycle(u, f)
@@ -307,7 +335,8 @@ def error_vs_129(ud_host, w, coeffs):
     n, nco = w["n"], 129
     stride = (n - 1) // (nco - 1)
     f129 = inputs.smooth_sine_3d(nco)
-    m = oracle.Multigrid(3, nco, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"])
+    m = oracle.Multigrid(3, nco, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
+                         smoother=w.get("smoother", 0))
     u129 = np.zeros_like(f129)
     cycles, hist = m.solve(u129, f129, rtol=1e-10, max_cycles=60)
     m.close()
@@ -442,7 +471,7 @@ def main():
     import torch
 
     w = dict(WORKLOADS[args.workload])
-    for k in ("n", "coarse", "gamma", "precision", "compare", "inner"):
+    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother"):
         if getattr(args, k) is not None:
             w[k] = getattr(args, k)
     torch.cuda.set_device(0)
@@ -469,12 +498,15 @@ def main():
     if args.workload == "poisson2d-4097" and not args.no_variants:
         variants = {}
         kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
-        for coarse, gamma in ((0, 1), (1, 1), (0, 2), (1, 2), (2, 1), (3, 1)):
+        for coarse, gamma, sm in ((0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 0), (2, 1, 0), (3, 1, 0),
+                                  (0, 1, 1), (1, 1, 1), (3, 1, 1), (0, 2, 1)):
             name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
-            if coarse == w["coarse"] and gamma == w["gamma"]:
+            if sm:
+                name = "redblack-" + name
+            if coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0):
                 vs, vres = sec, res
             else:
-                vr = Run(dict(w, coarse=coarse, gamma=gamma), w["precision"], fd, stream)
+                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm), w["precision"], fd, stream)
                 vs, (vst, vres) = vr.timed(2, 1)
                 vr.close()
             variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
@@ -506,14 +538,15 @@ def main():
         extra = error_vs_129(main_run.ud.cpu().numpy(), w, coeffs)
 
     rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
-    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
+    rb = bool(w.get("smoother", 0))
+    dom_name = "k_sweep2d" if d == 2 and rb else "k_pre2d" if d == 2 else "k_sweep3d"
     dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
     if not dom:
         dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
                if r["kernel"] == dom_name]
     dom = dom[0]
     cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
-    src = "fused2d.hip" if d == 2 else "kernels3d.hip"
+    src = ("kernels2d.hip" if rb else "fused2d.hip") if d == 2 else "kernels3d.hip"
     key = "%s/%s/%s/%d" % (dom_name, "f32" if w["precision"] else "f64", src, n)
     tr = MEASURED_TRAFFIC.get(key)
     traffic = tr["bytes"] if tr and tr["source"] == source_hash(src) else None
@@ -537,6 +570,7 @@ def main():
             "cycle": cyc, "coarse": ["rediscretized", "galerkin", "rediscretized-order2",
                                      "galerkin-order2"][w["coarse"]],
             "precision": "fp64" if w["precision"] == 0 else "mixed",
+            "smoother": "red-black-jacobi" if w.get("smoother", 0) else "jacobi",
             "cycles": res.cycles, "outer_steps": res.outer_steps,
             "final_rel_residual": res.rel_residual, "floor_hit": bool(res.floor_hit),
             "status": status,

@@ -58,7 +58,13 @@ typedef enum {
                             * spacing (eq. L_H_2G_2d); below it R * L_l * P, level by level */
 } mg_coarse;
 
-typedef enum { MG_SMOOTH_JACOBI = 0 } mg_smoother;
+typedef enum {
+  MG_SMOOTH_JACOBI = 0,  /* omega-Jacobi: every interior point relaxed at once (section 5.3) */
+  MG_SMOOTH_RBJ = 1      /* omega red-black Jacobi (section 3.1 eq. S_rb with the Jacobi partial
+                          * step; the smoother of appendix A.4.1): the red points (odd index sum
+                          * i+j(+k)) take an omega-Jacobi step, then the black points from the
+                          * updated red values; one such pair counts once in nu1, nu2 */
+} mg_smoother;
 
 typedef enum {
   MG_PREC_FP64 = 0,   /* every step in FP64 */
@@ -72,8 +78,10 @@ typedef struct {
   int order;           /* 4 (fourth order, width-5 stencil) or 2 (5-/7-point) */
   int coarse;          /* mg_coarse */
   int smoother;        /* mg_smoother */
-  double omega;        /* Jacobi relaxation; <= 0 selects the Fourier-analysis optimum
-                          (10/13 in 2D, 9/11 in 3D for order 4; 4/5, 6/7 for order 2) */
+  double omega;        /* Jacobi relaxation; <= 0 selects the Fourier-analysis optimum:
+                          omega-Jacobi 10/13 in 2D, 9/11 in 3D for order 4 (4/5, 6/7 for
+                          order 2); red-black Jacobi 1.13 in 2D, 1.17 in 3D for order 4 (1.0,
+                          1.13 for order 2), the minimisers of the two-grid factor of V(2,1) */
   int nu1, nu2;        /* pre- and post-smoothing sweeps per cycle (nu1 + nu2 >= 1) */
   int gamma;           /* 1 = V cycle, 2 = W cycle */
   int prolong;         /* 3 = cubic interpolation, 1 = (bi/tri)linear */
@@ -148,6 +156,14 @@ int mg_level_size(mg_handle h, int level);
  * u_out != u_in. */
 mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, const void *u_in,
                            void *u_out);
+
+/* One partial step of red-black smoothing (section 3.1 eq. S_rb): the points of one colour
+ * take the omega-Jacobi step of mg_kernel_smooth, every other point copies u_in.
+ * colour 1 = red (odd index sum i+j(+k)), 2 = black (even), 0 = every point.  A red-black
+ * sweep is colour 1 into a second array, then colour 2 back.  u_in == NULL means
+ * u_in = 0.  u_out != u_in. */
+mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, const void *f,
+                                  const void *u_in, void *u_out);
 
 /* r = f - L_l u (the defect of section 2.2), zero on the boundary. */
 mg_status mg_kernel_residual(mg_handle h, int level, int fp32, const void *f, const void *u,

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(const T *__restrict__ f,
           }
         }
         r = fv - lu;
-        val = w[R] + op.om_d * r;
+        val = w[R] + colour_om(op, x + y) * r;
         acc += (double)r * (double)r;
       }
       if (MODE == kSweep) out[(size_t)y * n + x] = (TO)val;
@@ -471,6 +471,7 @@ KOp<T> to_kop(const LevelOp &op, double omega) {
   k.w1 = (T)(-op.a[2]);
   k.w2 = (T)(-op.a[1]);
   k.om_d = (T)(omega / op.diag);
+  k.colour = 0;
   return k;
 }
 
@@ -520,10 +521,11 @@ int sweep_partials(int dim, int n) {
 template <typename T, typename TO>
 hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, const T *f,
                         const T *u, TO *out, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s, int slots) {
+                        const int *done, hipStream_t s, int slots, int colour) {
+  if (colour < 0 || colour > 2) return hipErrorInvalidValue;
   if (dim == 3) {
     if (slots != 1) return hipErrorInvalidValue;
-    return launch_sweep_3d<T, TO>(mode, op, omega, f, u, out, n, partials, nparts, done, s);
+    return launch_sweep_3d<T, TO>(mode, op, omega, f, u, out, n, partials, nparts, done, s, colour);
   }
   const int R = op.cross ? 2 : 3;
   const int nbx = cdiv(n, kBlock - 2 * R);
@@ -531,7 +533,8 @@ hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, cons
       band_rows(n, nbx, resident_blocks(sweep2d_fn<T, TO>(mode, op.cross), kBlock, 0), kMinRows);
   const dim3 grid(nbx, cdiv(n, rows), slots);
   if (nparts) *nparts = grid.x * grid.y;
-  const KOp<T> k = to_kop<T>(op, omega);
+  KOp<T> k = to_kop<T>(op, omega);
+  k.colour = colour;
 #define MG_SWEEP2D(MODE, CROSS) \
   hipLaunchKernelGGL((k_sweep2d<T, TO, MODE, CROSS>), grid, dim3(kBlock), 0, s, f, u, out, n, rows, k, partials, done)
   if (op.cross) {
@@ -622,13 +625,13 @@ hipError_t launch_fill(T *p, size_t count, T value, const int *done, hipStream_t
 // explicit instantiations
 template hipError_t launch_sweep<double, double>(int, int, const LevelOp &, double, const double *,
                                                  const double *, double *, int, double *, int *,
-                                                 const int *, hipStream_t, int);
+                                                 const int *, hipStream_t, int, int);
 template hipError_t launch_sweep<float, float>(int, int, const LevelOp &, double, const float *,
                                                const float *, float *, int, double *, int *,
-                                               const int *, hipStream_t, int);
+                                               const int *, hipStream_t, int, int);
 template hipError_t launch_sweep<double, float>(int, int, const LevelOp &, double, const double *,
                                                 const double *, float *, int, double *, int *,
-                                                const int *, hipStream_t, int);
+                                                const int *, hipStream_t, int, int);
 template hipError_t launch_resid_restrict<double>(int, const LevelOp &, const double *,
                                                   const double *, double *, int, const int *,
                                                   hipStream_t, int);

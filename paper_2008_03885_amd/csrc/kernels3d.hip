@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const 
     if (inside) acc += (double)r * (double)r;
     if (own) {
       const size_t id = ((size_t)z * n + y) * n + x;
-      if (MODE == kSweep) out[id] = (TO)(inside ? uc + op.om_d * r : T(0));
+      if (MODE == kSweep) out[id] = (TO)(inside ? uc + colour_om(op, x + y + z) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     }
     head = (head + 1) % W;
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
       // value there, 0; a step past this block's planes stores the value the owning
       // block stores too (same inputs, same arithmetic).
       const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep) out[id] = (TO)(inside ? uc + kop.om_d * r : T(0));
+      if (MODE == kSweep) out[id] = (TO)(inside ? uc + colour_om(kop, x + y + z) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     };
     for (int z = z0; z < z1; z += kZR)
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
       if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
       // every lane stores (clamped address; see the cross sweep)
       const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep) out[id] = (TO)(inside ? uz + kop.om_d * r : T(0));
+      if (MODE == kSweep) out[id] = (TO)(inside ? uz + colour_om(kop, x + y + z) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     };
     for (int z = z0; z < z1; z += 8)
@@ -1152,6 +1152,7 @@ KOp<T> to_kop3(const LevelOp &op, double omega) {
   k.w1 = (T)(-op.a[2]);
   k.w2 = (T)(-op.a[1]);
   k.om_d = (T)(omega / op.diag);
+  k.colour = 0;
   return k;
 }
 
@@ -1225,7 +1226,7 @@ int sweep_partials_3d(int n) {
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
-                           hipStream_t s) {
+                           hipStream_t s, int colour) {
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
   // operator (it uses om_d only)
   const bool xpath = op.cross || u == nullptr, gpath = !xpath && gsweep_rings();
@@ -1236,7 +1237,8 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
                                                  kMinPlanes)) + kZR - 1) / kZR * kZR;
   const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
-  const KOp<T> k = to_kop3<T>(op, omega);
+  KOp<T> k = to_kop3<T>(op, omega);
+  k.colour = colour;
   if (gpath) {
 #define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
     if (mode == kSweep) MG_G3(kSweep);
@@ -1368,13 +1370,13 @@ hipError_t prepare_3d() {
 
 template hipError_t launch_sweep_3d<double, double>(int, const LevelOp &, double, const double *,
                                                     const double *, double *, int, double *, int *,
-                                                    const int *, hipStream_t);
+                                                    const int *, hipStream_t, int);
 template hipError_t launch_sweep_3d<float, float>(int, const LevelOp &, double, const float *,
                                                   const float *, float *, int, double *, int *,
-                                                  const int *, hipStream_t);
+                                                  const int *, hipStream_t, int);
 template hipError_t launch_sweep_3d<double, float>(int, const LevelOp &, double, const double *,
                                                    const double *, float *, int, double *, int *,
-                                                   const int *, hipStream_t);
+                                                   const int *, hipStream_t, int);
 template hipError_t launch_resid_restrict_3d<double>(const LevelOp &, const double *,
                                                      const double *, double *, int, const int *,
                                                      hipStream_t);

@@ -32,7 +32,15 @@ struct KOp {
   T b[7];
   T w1, w2;   // cross: weights of (u_0 - u_{+-1}) and (u_0 - u_{+-2})
   T om_d;     // omega / diag
+  int colour; // sweeps: 0 relax every interior point; 1 only odd x+y(+z), 2 only even
 };
+
+// Relaxation weight of a sweep at a point with coordinate sum xyz: omega/diag where the
+// point's colour is relaxed, 0 (the value is kept) elsewhere.
+template <typename T>
+__device__ __forceinline__ T colour_om(const KOp<T> &k, int xyz) {
+  return (k.colour == 0 || (xyz & 1) == (k.colour & 1)) ? k.om_d : T(0);
+}
 
 // Device-resident stopping state of a solve; every step kernel returns at once when
 // done != 0, so a captured step can be replayed past convergence at no cost.
@@ -101,10 +109,12 @@ __device__ __forceinline__ P *slot_ptr(P *p, size_t per_slot) {
 // ---- launchers (kernels.hip) ----------------------------------------------------
 // All take the level side n, dense arrays, and an optional `done` flag.
 
+// colour (kSweep): 0 relaxes every interior point, 1 the red points (odd x+y(+z)), 2 the
+// black ones; the other points are copied.  One red-black sweep is colour 1, then 2.
 template <typename T, typename TO>
 hipError_t launch_sweep(int dim, int mode, const LevelOp &op, double omega, const T *f,
                         const T *u, TO *out, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s, int slots = 1);
+                        const int *done, hipStream_t s, int slots = 1, int colour = 0);
 
 template <typename T>
 hipError_t launch_resid_restrict(int dim, const LevelOp &op, const T *f, const T *u, T *fc,
@@ -147,7 +157,7 @@ hipError_t prepare_3d();  // enables the large dynamic LDS of the separable 3D k
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
-                           hipStream_t s);
+                           hipStream_t s, int colour = 0);
 template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s);
@@ -197,6 +207,7 @@ struct TailLevel {
 struct TailArgs {
   int levels, gamma, nu1, nu2, prolong, zero_init, m, lds_r;
   int repeats;               // cycles from the top level (the parent's gamma visits)
+  int rb;                    // 1: red-black Jacobi sweeps, 0: omega-Jacobi
   int ent_first, ent_total;  // entries of the tail's levels in eoff/ecoef
   int lds_ent;               // byte offset of the entry table in LDS
   TailLevel lv[kMaxTailLevels];

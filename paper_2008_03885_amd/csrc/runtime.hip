@@ -261,7 +261,8 @@ mg_status validate(const mg_config *c, int *levels) {
   if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN && c->coarse != MG_COARSE_NG2 &&
       c->coarse != MG_COARSE_G2)
     return fail(MG_EINVAL, "unknown coarse operator");
-  if (c->smoother != MG_SMOOTH_JACOBI) return fail(MG_EINVAL, "unknown smoother");
+  if (c->smoother != MG_SMOOTH_JACOBI && c->smoother != MG_SMOOTH_RBJ)
+    return fail(MG_EINVAL, "unknown smoother");
   if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
     return fail(MG_EINVAL, "need 0 <= nu1, nu2 <= 16 and nu1 + nu2 >= 1");
   if (c->gamma != 1 && c->gamma != 2) return fail(MG_EINVAL, "gamma must be 1 (V) or 2 (W)");
@@ -284,8 +285,14 @@ mg_status validate(const mg_config *c, int *levels) {
   return MG_OK;
 }
 
-double default_omega(int dim, int order) {
-  // Equioscillation of the omega-Jacobi symbol over the high frequencies.
+double default_omega(int dim, int order, int smoother) {
+  // Red-black Jacobi: the minimiser of the Fourier-analysis two-grid factor of the V(2,1)
+  // cycle (cubic interpolation, rediscretized operator), to two decimals.
+  if (smoother == MG_SMOOTH_RBJ) {
+    if (order == 4) return dim == 2 ? 1.13 : 1.17;
+    return dim == 2 ? 1.0 : 1.13;
+  }
+  // omega-Jacobi: equioscillation of the symbol over the high frequencies.
   if (order == 4) return dim == 2 ? 10.0 / 13.0 : 9.0 / 11.0;
   return dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0;
 }
@@ -405,6 +412,7 @@ hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const
   a.nu1 = c->cfg.nu1;
   a.nu2 = c->cfg.nu2;
   a.prolong = c->cfg.prolong;
+  a.rb = c->cfg.smoother == MG_SMOOTH_RBJ ? 1 : 0;
   a.zero_init = zero_u ? 1 : 0;
   const int q = c->ns[c->L - 1] - 2;
   a.m = c->dim == 2 ? q * q : q * q * q;
@@ -507,11 +515,15 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     if (e != hipSuccess) return e;
     zero = false;
   }
-  for (int k = 0; k < c->cfg.nu1; ++k) {
+  // a red-black sweep is two steps: the red points (colour 1), then the black ones (2)
+  const bool rb = c->cfg.smoother == MG_SMOOTH_RBJ;
+  const int steps = rb ? 2 : 1;
+  for (int k = 0; k < c->cfg.nu1 * steps; ++k) {
     const bool first_check = check && k == 0;
     int np = 0;
     e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
-                                first_check ? c->partials : nullptr, &np, done, s, c->slots);
+                                first_check ? c->partials : nullptr, &np, done, s, c->slots,
+                                rb ? 1 + k % 2 : 0);
     if (e != hipSuccess) return e;
     if (first_check) {
       e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
@@ -537,14 +549,14 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
       if (e != hipSuccess) return e;
     }
   }
-  T *dst = (c->cfg.nu2 % 2 == 0) ? u : t;
+  T *dst = ((c->cfg.nu2 * steps) % 2 == 0) ? u : t;
   e = mgk::launch_prolong_correct<T>(dim, c->cfg.prolong, uc, cur, dst, n, done, s, c->slots);
   if (e != hipSuccess) return e;
   cur = dst;
   other = (dst == u) ? t : u;
-  for (int k = 0; k < c->cfg.nu2; ++k) {
+  for (int k = 0; k < c->cfg.nu2 * steps; ++k) {
     e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
-                                done, s, c->slots);
+                                done, s, c->slots, rb ? 1 + k % 2 : 0);
     if (e != hipSuccess) return e;
     std::swap(cur, other);
   }
@@ -771,12 +783,13 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
   c->own_top = own_top;
   c->dim = cfg->dim;
   c->L = L;
-  c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order);
+  c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order, cfg->smoother);
   c->stream = (hipStream_t)hip_stream;
   if (const char *g = std::getenv("MG_GRAPH")) c->use_graph = std::atoi(g) != 0;
   if (const char *k = std::getenv("MG_CHUNK")) c->chunk = std::max(1, std::atoi(k));
   if (const char *fz = std::getenv("MG_FUSED")) c->fused = std::atoi(fz) != 0;
   if (cfg->nu1 > 3 || cfg->nu2 > 2) c->fused = false;
+  if (cfg->smoother == MG_SMOOTH_RBJ) c->fused = false;  // the fused 2D kernels relax every point
   auto bail = [&](mg_status s) {
     std::string msg = g_error;
     mg_destroy(c);
@@ -1033,6 +1046,25 @@ mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, cons
                                               (const double *)f, (const double *)u_in,
                                               (double *)u_out, h->ns[level], nullptr, nullptr,
                                               nullptr, h->stream)));
+  return MG_OK;
+}
+
+mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, const void *f,
+                                  const void *u_in, void *u_out) {
+  mg_status st = fp32 ? check_level<float>(h, level, false) : check_level<double>(h, level, false);
+  if (st != MG_OK) return st;
+  if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  if (colour < 0 || colour > 2) return fail(MG_EINVAL, "colour must be 0, 1 or 2");
+  if (fp32)
+    MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kSweep, h->ops[level], h->omega,
+                                            (const float *)f, (const float *)u_in, (float *)u_out,
+                                            h->ns[level], nullptr, nullptr, nullptr, h->stream, 1,
+                                            colour)));
+  else
+    MG_HIP((mgk::launch_sweep<double, double>(h->dim, mgk::kSweep, h->ops[level], h->omega,
+                                              (const double *)f, (const double *)u_in,
+                                              (double *)u_out, h->ns[level], nullptr, nullptr,
+                                              nullptr, h->stream, 1, colour)));
   return MG_OK;
 }
 

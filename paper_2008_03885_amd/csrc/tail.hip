@@ -63,6 +63,7 @@ struct Tail {
   const double *ainv_t;
   const double *dst;  // sine table of the coarsest solve, or null (dense inverse)
   int m, levels, gamma, nu1, nu2, prolong, scratch;
+  int rb;  // red-black smoothing: a sweep is the red, then the black partial step
   int tx, ty, tz;
 
   __device__ __forceinline__ int pidx(int l, int i, int j, int k) const {
@@ -154,12 +155,14 @@ struct Tail {
         }
     __syncthreads();
   }
-  // One omega-Jacobi sweep on level l: every thread computes its points (at most kSlots,
+  // One omega-Jacobi step on level l: every thread computes its points (at most kSlots,
   // x-fastest order) into registers, then all store them with their ghost images.
-  __device__ __forceinline__ void smooth(int l, bool zero) const {
+  // colour 0 updates every interior point, 1 those with odd i+j(+k), 2 the even ones; the
+  // others keep their value (relaxation weight 0).
+  __device__ __forceinline__ void step(int l, bool zero, int colour) const {
     const int n = lv[l].n;
     const int total = DIM == 3 ? n * n * n : n * n;
-    const T om = T(lv[l].om_d);
+    const T om_all = T(lv[l].om_d);
     T vals[kSlots];
 #pragma unroll
     for (int r = 0; r < kSlots; ++r) {
@@ -172,6 +175,7 @@ struct Tail {
           const int q = pidx(l, i, j, k);
           const T u0 = zero ? T(0) : lds[q];
           const T rr = lds[lv[l].f + p] - (zero ? T(0) : lu(l, q, u0));
+          const T om = (colour == 0 || ((i + j + k) & 1) == (colour & 1)) ? om_all : T(0);
           v = u0 + om * rr;
         }
       }
@@ -188,6 +192,15 @@ struct Tail {
       }
     }
     __syncthreads();
+  }
+  // One smoothing sweep: omega-Jacobi, or red then black (section 3.1 eq. S_rb).
+  __device__ __forceinline__ void smooth(int l, bool zero) const {
+    if (rb) {
+      step(l, zero, 1);
+      step(l, false, 2);
+    } else {
+      step(l, zero, 0);
+    }
   }
   __device__ __forceinline__ void zero_level(int l) const {
     const int n = lv[l].n;
@@ -439,6 +452,7 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   c.nu1 = a.nu1;
   c.nu2 = a.nu2;
   c.prolong = a.prolong;
+  c.rb = a.rb;
   c.scratch = a.lds_r;
   c.tx = threadIdx.x % TL::TX;
   c.ty = (threadIdx.x / TL::TX) % TL::TY;

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libmgmi.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOCONV, MG_ENUMERIC, MG_EBUSY = range(7)
 MG_COARSE_NG, MG_COARSE_GALERKIN, MG_COARSE_NG2, MG_COARSE_G2 = 0, 1, 2, 3
-MG_SMOOTH_JACOBI = 0
+MG_SMOOTH_JACOBI, MG_SMOOTH_RBJ = 0, 1
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_MAX_HISTORY = 512
 STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EDEVICE", 4: "MG_ENOCONV",
@@ -64,6 +64,7 @@ _SIGS = {
     "mg_last_error": (ctypes.c_char_p, []),
     "mg_level_size": (_I, [_V, _I]),
     "mg_kernel_smooth": (_I, [_V, _I, _I, _V, _V, _V]),
+    "mg_kernel_smooth_colour": (_I, [_V, _I, _I, _I, _V, _V, _V]),
     "mg_kernel_residual": (_I, [_V, _I, _I, _V, _V, _V]),
     "mg_kernel_residual_restrict": (_I, [_V, _I, _I, _V, _V, _V]),
     "mg_kernel_prolong_correct": (_I, [_V, _I, _I, _V, _V, _V]),
@@ -166,6 +167,11 @@ def mg_level_operator(h, level):
 
 def mg_kernel_smooth(h, level, fp32, f_ptr, uin_ptr, uout_ptr):
     _check(lib().mg_kernel_smooth(_V(h), int(level), int(fp32), _V(f_ptr), _V(uin_ptr), _V(uout_ptr)))
+
+
+def mg_kernel_smooth_colour(h, level, fp32, colour, f_ptr, uin_ptr, uout_ptr):
+    _check(lib().mg_kernel_smooth_colour(_V(h), int(level), int(fp32), int(colour), _V(f_ptr),
+                                         _V(uin_ptr), _V(uout_ptr)))
 
 
 def mg_kernel_residual(h, level, fp32, f_ptr, u_ptr, r_ptr):

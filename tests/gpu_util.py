@@ -38,18 +38,24 @@ class Handle:
     """An mg handle and the oracle hierarchy built from the same configuration."""
 
     def __init__(self, dim, n, coarse=0, prolong=3, n_coarsest=9, nu1=2, nu2=1, gamma=1,
-                 precision=0, rtol=1e-10, max_cycles=100, inner_cycles=4, order=4, omega=0.0):
+                 precision=0, rtol=1e-10, max_cycles=100, inner_cycles=4, order=4, omega=0.0,
+                 smoother=0):
         self.cfg = mg.make_config(dim=dim, n=n, coarse=coarse, prolong=prolong,
                                   n_coarsest=n_coarsest, nu1=nu1, nu2=nu2, gamma=gamma,
                                   precision=precision, rtol=rtol, max_cycles=max_cycles,
-                                  inner_cycles=inner_cycles, order=order, omega=omega)
+                                  inner_cycles=inner_cycles, order=order, omega=omega,
+                                  smoother=smoother)
         self.h = mg.mg_setup(self.cfg, stream())
         self.dim, self.n = dim, n
-        self.omega = omega if omega > 0 else oracle.jacobi_omega_star(dim) if order == 4 else \
-            {2: 4 / 5, 3: 6 / 7}[dim]
+        if omega > 0:
+            self.omega = omega
+        elif smoother == oracle.SMOOTH_RBJ:
+            self.omega = oracle.rbj_omega(dim, order)
+        else:
+            self.omega = oracle.jacobi_omega_star(dim) if order == 4 else {2: 4 / 5, 3: 6 / 7}[dim]
         self.oracle = oracle.Multigrid(dim, n, order=order, coarse=coarse, prolong=prolong,
                                        nu1=nu1, nu2=nu2, gamma=gamma, n_coarsest=n_coarsest,
-                                       omega=self.omega)
+                                       omega=self.omega, smoother=smoother)
 
     def level(self, l):
         n_l, s = self.oracle.level_stencil(l)

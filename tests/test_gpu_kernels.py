@@ -338,6 +338,53 @@ def test_3d_galerkin_sweep_kernels(n, level, old, fp32, monkeypatch):
     test_residual_restrict(3, n, 1, 3, level, fp32)
 
 
+# Red-black partial steps (section 3.1 eq. S_rb): (dim, finest n, coarse, level, old 3D
+# Galerkin kernels).  Level sides cover single blocks, ragged blocks and 3D plane bands.
+CASES_RB = [
+    (2, 17, 0, 0, "0"), (2, 257, 0, 0, "0"), (2, 1025, 0, 1, "0"), (2, 257, 1, 1, "0"),
+    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"),
+    (3, 17, 0, 0, "0"), (3, 65, 0, 0, "0"), (3, 129, 0, 0, "0"), (3, 65, 1, 1, "0"),
+    (3, 129, 1, 1, "0"), (3, 65, 1, 1, "1"), (3, 65, 3, 2, "0"), (3, 33, 2, 1, "0"),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,level,old", CASES_RB)
+def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
+    """One partial step per colour against the oracle's; the other colour is copied
+    bit for bit."""
+    monkeypatch.setenv("MG_G3_OLD", old)
+    H = Handle(dim, n, coarse=coarse, smoother=1)
+    try:
+        n_l, s = H.level(level)
+        u = rand_grid(n_l, dim, 41)
+        f = rand_grid(n_l, dim, 42) * s[(s.shape[0] // 2,) * dim]
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        idx = np.indices(u.shape).sum(axis=0)
+        tol = (TOL32 if fp32 else TOL64) * _scale_u(u, f, s)
+        for colour in (1, 2, 0):
+            out = dev(np.full_like(u, np.nan), fp32)
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, colour, fd.data_ptr(), ud.data_ptr(),
+                                       out.data_ptr())
+            got = host(out)
+            ref = oracle.jacobi_colour(s, H.omega, colour, f, u)
+            assert_close(got, ref, tol, "colour %d" % colour)
+            if colour:
+                keep = (idx % 2) != (colour % 2)
+                assert np.array_equal(got[keep], u[keep])
+            out0 = dev(np.full_like(u, np.nan), fp32)
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, colour, fd.data_ptr(), None, out0.data_ptr())
+            ref0 = oracle.jacobi_colour(s, H.omega, colour, f, np.zeros_like(u))
+            assert_close(host(out0), ref0, tol, "colour %d, zero guess" % colour)
+        with pytest.raises(mg.MGError):
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), ud.data_ptr(),
+                                       out.data_ptr())
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("coarse,prolong", [(0, 3), (1, 3)])
 def test_coarsest_solve_3d(coarse, prolong, fp32):

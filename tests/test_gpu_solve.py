@@ -53,6 +53,59 @@ def test_fixed_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
         H.close()
 
 
+RB_CASES = [
+    # dim, n, coarse, prolong, nu1, nu2, gamma: red-black Jacobi smoothing
+    (2, 129, 0, 3, 2, 1, 1), (2, 129, 1, 3, 1, 1, 2), (2, 257, 3, 3, 2, 1, 1), (2, 65, 0, 1, 0, 2, 1),
+    (2, 1025, 0, 3, 2, 1, 1), (2, 257, 2, 3, 1, 0, 2),
+    (3, 33, 0, 3, 2, 1, 1), (3, 65, 1, 3, 2, 2, 2), (3, 65, 0, 3, 1, 1, 1), (3, 65, 3, 1, 2, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dim,n,coarse,prolong,nu1,nu2,gamma", RB_CASES)
+def test_red_black_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
+    """Cycles with red-black Jacobi smoothing (section 3.1 eq. S_rb) on every level,
+    the LDS-resident tail's included."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, gamma=gamma, smoother=1)
+    try:
+        f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+        cycles = 5
+        u, res, u_ref, hist = _fixed_cycles(H, f, cycles)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17")])
+def test_red_black_tail_variants_agree(dim, n, tail, monkeypatch):
+    """Red-black smoothing inside and outside the LDS-resident tail: same cycles."""
+    monkeypatch.setenv("MG_TAIL_N", tail)
+    H = Handle(dim, n, gamma=2, smoother=1)
+    try:
+        f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 4)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+    finally:
+        H.close()
+
+
+def test_red_black_mixed_precision_solves():
+    """FP32 red-black cycles inside FP64 refinement reach the FP64 tolerance."""
+    for dim, n in ((2, 513), (3, 65)):
+        H = Handle(dim, n, smoother=1, precision=1, rtol=1e-10, inner_cycles=2)
+        try:
+            f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+            assert st == mg.MG_OK and res.rel_residual <= 1e-10, (dim, res.rel_residual)
+            rel = mg.mg_residual_norm(H.h, fd.data_ptr(), ud.data_ptr())
+            assert rel <= 1e-10
+        finally:
+            H.close()
+
+
 @pytest.mark.parametrize("fused,tail,dst", [("1", None, "1"), ("0", "0", "1"), ("1", "0", "1"),
                                             ("1", "17", "1"), ("0", "65", "1"), ("1", None, "0")])
 @pytest.mark.parametrize("coarse,gamma", [(0, 1), (1, 2)])
