@@ -180,7 +180,7 @@ def in_cycle_time(run, w, stream, reps):
     t = torch.empty_like(u)
     fc = torch.empty((nc,) * d, device="cuda", dtype=dt)
     v = torch.randn((nc,) * d, generator=gen, device="cuda", dtype=torch.float64).to(dt)
-    if w.get("smoother", 0):
+    if w.get("smoother", 0) and d == 3:
         # red then black partial steps in a ping-pong, as the cycle runs them
         bufs = [u, t]
         col = [1]
@@ -245,8 +245,9 @@ def level_kernels(run, w, stream, reps, only_level0=False):
         fc = torch.empty(cshp, device="cuda", dtype=dt)
         v = torch.randn(cshp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
         P, Pc = n ** d, nc ** d
-        if w.get("smoother", 0):
-            # red-black smoothing runs the separate kernels: two partial steps per sweep
+        rb = w.get("smoother", 0)
+        if rb and d == 3:
+            # 3D red-black smoothing: two partial-step launches per sweep
             ks = [
                 ("k_sweep%dd" % d, "red-black partial step", 3 * P * b,
                  lambda: mg.mg_kernel_smooth_colour(run.h, l, fp32, 1, f.data_ptr(), u.data_ptr(),
@@ -259,11 +260,14 @@ def level_kernels(run, w, stream, reps, only_level0=False):
                                                       t.data_ptr())),
             ]
         elif d == 2:
+            # red-black: the passes hold one red-black sweep each (the cycle runs max(1, nu))
+            pre = "red-black sweep" if rb else "presmooth(%d)" % w["nu1"]
+            post = "red-black sweep" if rb else "postsmooth(%d)" % w["nu2"]
             ks = [
-                ("k_pre2d", "presmooth(%d)+defect+FW" % w["nu1"], (3 * P + Pc) * b,
+                ("k_pre2d", "%s+defect+FW" % pre, (3 * P + Pc) * b,
                  lambda: mg.mg_kernel_presmooth_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
                                                          t.data_ptr(), fc.data_ptr())),
-                ("k_post2d", "interp+correct+postsmooth(%d)" % w["nu2"], (3 * P + Pc) * b,
+                ("k_post2d", "interp+correct+%s" % post, (3 * P + Pc) * b,
                  lambda: mg.mg_kernel_prolong_postsmooth(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
                                                          f.data_ptr(), t.data_ptr())),
             ]
@@ -539,15 +543,15 @@ def main():
 
     rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
     rb = bool(w.get("smoother", 0))
-    dom_name = "k_sweep2d" if d == 2 and rb else "k_pre2d" if d == 2 else "k_sweep3d"
+    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
     dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
     if not dom:
         dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
                if r["kernel"] == dom_name]
     dom = dom[0]
     cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
-    src = ("kernels2d.hip" if rb else "fused2d.hip") if d == 2 else "kernels3d.hip"
-    key = "%s/%s/%s/%d" % (dom_name, "f32" if w["precision"] else "f64", src, n)
+    src = "fused2d.hip" if d == 2 else "kernels3d.hip"
+    key = "%s/%s/%s/%d%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "")
     tr = MEASURED_TRAFFIC.get(key)
     traffic = tr["bytes"] if tr and tr["source"] == source_hash(src) else None
 

@@ -180,12 +180,14 @@ mg_status mg_kernel_prolong_correct(mg_handle h, int level, int fp32, const void
 
 /* The pre-coarse half of a cycle on level l in one pass (2D): u_out = nu1 omega-Jacobi
  * sweeps of u_in (NULL = zero guess), fc = I_h^H (f - L_l u_out) on level l+1.
- * u_out != u_in. */
+ * u_out != u_in.  With red-black smoothing the pass holds min(1, nu1) red-black sweeps:
+ * the last pass of the cycle's pre-coarse half (the cycle runs max(1, nu1) passes). */
 mg_status mg_kernel_presmooth_restrict(mg_handle h, int level, int fp32, const void *f,
                                        const void *u_in, void *u_out, void *fc);
 
 /* The post-coarse half of a cycle on level l in one pass (2D): u_out = nu2 omega-Jacobi
- * sweeps of (u_in + I_H^h v).  u_out != u_in. */
+ * sweeps of (u_in + I_H^h v).  u_out != u_in.  With red-black smoothing the pass holds
+ * min(1, nu2) red-black sweeps: the first pass of the cycle's post-coarse half. */
 mg_status mg_kernel_prolong_postsmooth(mg_handle h, int level, int fp32, const void *v,
                                        const void *u_in, const void *f, void *u_out);
 

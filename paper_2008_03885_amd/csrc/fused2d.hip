@@ -10,7 +10,8 @@
 //
 // Pre kernel (k_pre2d):  NU omega-Jacobi sweeps, then the defect f - L u, then full
 //   weighting, in one pass: reads u and f once, writes the smoothed u and the coarse
-//   right-hand side.  Stage s of the pipeline lags stage s-1 by R rows.
+//   right-hand side.  Stage s of the pipeline lags stage s-1 by R rows.  With red-black
+//   smoothing the sweeps are partial steps, red and black in turn.
 // Post kernel (k_post2d): interpolation of the coarse correction (cubic or linear),
 //   correction, then NU2 sweeps, in one pass: reads u, f and the coarse v once, writes u.
 //
@@ -184,7 +185,8 @@ struct PreArgs {
 // that earlier row steps produced.  All stages of a row step are then independent: their
 // x neighbours go through LDS in one batched exchange and their arithmetic overlaps.
 // The full weighting of the defect lags one more row for the same reason.
-template <typename T, int R, int NU, int MODE, bool HAS_U>
+// RBS: the stages are red-black partial steps (stage_om), else omega-Jacobi sweeps.
+template <typename T, int R, int NU, int MODE, bool HAS_U, bool RBS = false>
 __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   constexpr bool RESTRICT = (MODE & kRestrict) != 0;
   constexpr bool WRITE_R = (MODE & kWriteR) != 0;
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
         if (s == 1 && a.partials != nullptr && useful && col.xin && row >= own_a && row < own_b &&
             row > 0 && row < n - 1)
           acc += (double)r * (double)r;
-        nv[s - 1] = w[s - 1][ring<LR>(P - (s - 1) * LAG)] + op.om_d * r;
+        nv[s - 1] = w[s - 1][ring<LR>(P - (s - 1) * LAG)] + (RBS ? stage_om(op, s, x + row) : op.om_d) * r;
       }
       // defect of the smoothed iterate at row cK
       T rd = T(0);
@@ -434,7 +436,7 @@ struct PostArgs {
   const int *done;
 };
 
-template <typename T, int R, int NU2, int P>
+template <typename T, int R, int NU2, int P, bool RBS = false>
 __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
   constexpr int H = NU2 * R;
   constexpr int S = kWave - 2 * H;
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
           // stage s: sweep at row t - s R, the centre of w[s-1]
           const T fv = fw[FQ - 1 - (s - 1) * R];
           const T r = fv - apply_op<T, R>(w[s - 1], op, ra, rb);
-          push(w[s], w[s - 1][R] + op.om_d * r);
+          push(w[s], w[s - 1][R] + (RBS ? stage_om(op, s, x + t - s * R) : op.om_d) * r);
         }
         out = w[NU2][W - 1];
         c = t - NU2 * R;
@@ -586,16 +588,16 @@ int pre_bands(const void *fn, int n, bool restrict_mode, dim3 *grid) {
   return c;
 }
 
-template <typename T, int R, int NU, int MODE>
+template <typename T, int R, int NU, int MODE, bool RBS = false>
 hipError_t pre_dispatch(PreArgs<T> args, dim3 grid, bool restrict_mode, int *nparts, hipStream_t s) {
-  const void *fn = args.u != nullptr ? (const void *)k_pre2d<T, R, NU, MODE, true>
-                                     : (const void *)k_pre2d<T, R, NU, MODE, false>;
+  const void *fn = args.u != nullptr ? (const void *)k_pre2d<T, R, NU, MODE, true, RBS>
+                                     : (const void *)k_pre2d<T, R, NU, MODE, false, RBS>;
   args.chunk = pre_bands(fn, args.n, restrict_mode, &grid);
   if (nparts) *nparts = grid.x * grid.y;
   if (args.u != nullptr)
-    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true, RBS>), grid, dim3(kBlock), 0, s, args);
   else
-    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, false>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, false, RBS>), grid, dim3(kBlock), 0, s, args);
   return hipGetLastError();
 }
 
@@ -614,16 +616,16 @@ hipError_t pre_nu(int nu, const PreArgs<T> &args, dim3 grid, int *nparts, hipStr
   }
 }
 
-template <typename T, int R, int NU2>
+template <typename T, int R, int NU2, bool RBS = false>
 hipError_t post_dispatch(int prolong, PostArgs<T> args, dim3 grid, hipStream_t s) {
-  const void *fn = prolong == 3 ? (const void *)k_post2d<T, R, NU2, 3>
-                                : (const void *)k_post2d<T, R, NU2, 1>;
+  const void *fn = prolong == 3 ? (const void *)k_post2d<T, R, NU2, 3, RBS>
+                                : (const void *)k_post2d<T, R, NU2, 1, RBS>;
   args.chunk = band_rows(args.n, grid.x, resident_blocks(fn, kBlock, 0), kMinFineRows);
   grid.y = cdiv(args.n, args.chunk);
   if (prolong == 3)
-    hipLaunchKernelGGL((k_post2d<T, R, NU2, 3>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 3, RBS>), grid, dim3(kBlock), 0, s, args);
   else
-    hipLaunchKernelGGL((k_post2d<T, R, NU2, 1>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 1, RBS>), grid, dim3(kBlock), 0, s, args);
   return hipGetLastError();
 }
 
@@ -659,10 +661,10 @@ int pre2d_partials(int n) {
 template <typename T>
 hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                         T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s, int slots) {
+                        const int *done, hipStream_t s, int slots, bool rb) {
   if (n <= tile2d_max_side())
     return launch_pre2d_tile<T>(op, omega, nu, mode, f, u, uout, rout, fc, n, partials, nparts, done,
-                                s, slots);
+                                s, slots, rb);
   const int R = op.cross ? 2 : 3;
   const bool restrict_mode = (mode & kRestrict) != 0;
   const bool res = restrict_mode || (mode & kWriteR) != 0;
@@ -672,6 +674,21 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
   if (S <= 0 || nu < 0 || nu > 3) return hipErrorInvalidValue;
   PreArgs<T> args{f, u, uout, rout, fc, n, 0, to_kop<T>(op, omega), partials, done};
   const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
+  if (rb) {
+    // red-black passes: two stages (one sweep), or none before the defect
+    constexpr int WR = kWriteU | kRestrict;
+    args.op.colour = kColourRB;
+    if (R == 2) {
+      if (mode == WR && nu == 0) return pre_dispatch<T, 2, 0, WR>(args, grid, true, nparts, s);
+      if (mode == WR && nu == 2) return pre_dispatch<T, 2, 2, WR, true>(args, grid, true, nparts, s);
+      if (mode == kWriteU && nu == 2) return pre_dispatch<T, 2, 2, kWriteU, true>(args, grid, false, nparts, s);
+    } else {
+      if (mode == WR && nu == 0) return pre_dispatch<T, 3, 0, WR>(args, grid, true, nparts, s);
+      if (mode == WR && nu == 2) return pre_dispatch<T, 3, 2, WR, true>(args, grid, true, nparts, s);
+      if (mode == kWriteU && nu == 2) return pre_dispatch<T, 3, 2, kWriteU, true>(args, grid, false, nparts, s);
+    }
+    return hipErrorInvalidValue;
+  }
 #define MG_PRE(RR)                                                                         \
   if (mode == (kWriteU | kRestrict)) return pre_nu<T, RR, kWriteU | kRestrict>(nu, args, grid, nparts, s); \
   if (mode == kWriteU && nu == 1) return pre_dispatch<T, RR, 1, kWriteU>(args, grid, false, nparts, s); \
@@ -685,30 +702,36 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
 template <typename T>
 hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                          const T *uin, const T *f, T *uout, int n, const int *done,
-                         hipStream_t s, int slots) {
+                         hipStream_t s, int slots, bool rb) {
   if (nu2 < 0 || nu2 > 2) return hipErrorInvalidValue;
   if (n <= tile2d_max_side())
-    return launch_post2d_tile<T>(op, omega, nu2, prolong, v, uin, f, uout, n, done, s, slots);
+    return launch_post2d_tile<T>(op, omega, nu2, prolong, v, uin, f, uout, n, done, s, slots, rb);
   const int R = op.cross ? 2 : 3;
   const int H = nu2 * R;
   const int S = kWave - 2 * H;
   PostArgs<T> args{v, uin, f, uout, n, 0, to_kop<T>(op, omega), done};
   const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
+  if (rb) {
+    args.op.colour = kColourRB;
+    if (nu2 == 0) return R == 2 ? post_dispatch<T, 2, 0>(prolong, args, grid, s) : post_dispatch<T, 3, 0>(prolong, args, grid, s);
+    if (nu2 == 2) return R == 2 ? post_dispatch<T, 2, 2, true>(prolong, args, grid, s) : post_dispatch<T, 3, 2, true>(prolong, args, grid, s);
+    return hipErrorInvalidValue;
+  }
   if (R == 2) return post_nu<T, 2>(nu2, prolong, args, grid, s);
   return post_nu<T, 3>(nu2, prolong, args, grid, s);
 }
 
 template hipError_t launch_pre2d<double>(const LevelOp &, double, int, int, const double *,
                                          const double *, double *, double *, double *, int,
-                                         double *, int *, const int *, hipStream_t, int);
+                                         double *, int *, const int *, hipStream_t, int, bool);
 template hipError_t launch_pre2d<float>(const LevelOp &, double, int, int, const float *,
                                         const float *, float *, float *, float *, int, double *,
-                                        int *, const int *, hipStream_t, int);
+                                        int *, const int *, hipStream_t, int, bool);
 template hipError_t launch_post2d<double>(const LevelOp &, double, int, int, const double *,
                                           const double *, const double *, double *, int,
-                                          const int *, hipStream_t, int);
+                                          const int *, hipStream_t, int, bool);
 template hipError_t launch_post2d<float>(const LevelOp &, double, int, int, const float *,
                                          const float *, const float *, float *, int, const int *,
-                                         hipStream_t, int);
+                                         hipStream_t, int, bool);
 
 }  // namespace mgk

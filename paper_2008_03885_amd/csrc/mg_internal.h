@@ -35,6 +35,14 @@ struct KOp {
   int colour; // sweeps: 0 relax every interior point; 1 only odd x+y(+z), 2 only even
 };
 
+// Fused 2D kernels with colour kColourRB run red-black stages: stage s (1-based) relaxes
+// the red points (odd x+y) when s is odd and the black ones when s is even.
+constexpr int kColourRB = 3;
+template <typename T>
+__device__ __forceinline__ T stage_om(const KOp<T> &k, int s, int xy) {
+  return (k.colour != kColourRB || ((xy + s) & 1) == 0) ? k.om_d : T(0);
+}
+
 // Relaxation weight of a sweep at a point with coordinate sum xyz: omega/diag where the
 // point's colour is relaxed, 0 (the value is kept) elsewhere.
 template <typename T>
@@ -169,17 +177,19 @@ hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *u
 // Pre kernel modes (bit set): 1 write the smoothed iterate, 2 full-weight the defect,
 // 4 write the defect.  Supported: WriteU|Restrict with nu <= 3 (the pre half of a cycle),
 // WriteU with nu = 1 (one sweep), WriteR with nu = 0 (the defect), Restrict with nu = 0
-// (defect and full weighting).
+// (defect and full weighting).  rb: the nu stages alternate red and black partial steps,
+// red first (a red-black sweep is two stages); supported: WriteU|Restrict with nu = 0 or
+// 2, WriteU with nu = 2.  launch_post2d with rb: nu2 = 0 or 2 stages.
 constexpr int kPreWriteU = 1, kPreRestrict = 2, kPreWriteR = 4;
 int pre2d_partials(int n);
 template <typename T>
 hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                         T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                        const int *done, hipStream_t s, int slots = 1);
+                        const int *done, hipStream_t s, int slots = 1, bool rb = false);
 template <typename T>
 hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                          const T *uin, const T *f, T *uout, int n, const int *done,
-                         hipStream_t s, int slots = 1);
+                         hipStream_t s, int slots = 1, bool rb = false);
 
 // ---- tile kernels for small levels (tile2d.hip) -------------------------------------
 // launch_pre2d / launch_post2d use them for sides up to tile2d_max_side() (the
@@ -189,11 +199,11 @@ int pre2d_tile_partials(int n);
 template <typename T>
 hipError_t launch_pre2d_tile(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                              T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                             const int *done, hipStream_t s, int slots);
+                             const int *done, hipStream_t s, int slots, bool rb);
 template <typename T>
 hipError_t launch_post2d_tile(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                               const T *uin, const T *f, T *uout, int n, const int *done,
-                              hipStream_t s, int slots);
+                              hipStream_t s, int slots, bool rb);
 
 // ---- LDS-resident tail (tail.hip) -------------------------------------------------
 constexpr int kMaxTailLevels = 8;

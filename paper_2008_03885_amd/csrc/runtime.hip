@@ -47,6 +47,7 @@ mg_status fail(mg_status st, const std::string &msg) {
 
 struct Buffers {
   void *u = nullptr, *f = nullptr, *t = nullptr;
+  void *t2 = nullptr;  // second sweep target (fused red-black passes, see rb_passes)
 };
 
 __global__ void k_state_init(DevState *st, double rtol, int max_checks, int floor_detect) {
@@ -364,6 +365,15 @@ size_t entries_bytes(const mg_config *cfg, int L) {
   return (size_t)L * per * (3 * sizeof(int) + sizeof(double));
 }
 
+// Fused 2D red-black cycles run one pass per red-black sweep: max(1, nu1) pre passes (the
+// last one also forms and restricts the defect) and max(1, nu2) post passes (the first one
+// also interpolates and corrects).  Passes alternate between u and t and must end in u;
+// with an odd number of passes the first one writes a third array t2.
+int rb_passes(const mg_config *cfg) { return std::max(1, cfg->nu1) + std::max(1, cfg->nu2); }
+bool needs_t2(const mg_config *cfg) {
+  return cfg->dim == 2 && cfg->smoother == MG_SMOOTH_RBJ && rb_passes(cfg) % 2 == 1;
+}
+
 // Device bytes of a handle: per-problem arrays times `slots`, plus the shared tables.
 // own_top: the handle also holds level-0 FP64 f and u (batches copy requests in).
 size_t footprint_of(const mg_config *cfg, int L, int slots = 1, bool own_top = false) {
@@ -374,7 +384,7 @@ size_t footprint_of(const mg_config *cfg, int L, int slots = 1, bool own_top = f
   for (int l = 0; l < L; ++l) {
     const size_t np = points(cfg->dim, n);
     int arrays = (l > 0 || mixed) ? 2 : 0;  // u and f (level 0 FP64 uses the caller's)
-    if (L > 1 && l < L - 1) arrays += 1;    // Jacobi target
+    if (L > 1 && l < L - 1) arrays += needs_t2(cfg) ? 2 : 1;  // sweep targets
     per += arrays * np * es;
     if (l == 0 && own_top) per += 2 * np * 8;
     n = (n - 1) / 2 + 1;
@@ -443,6 +453,72 @@ hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const
 
 template <typename T>
 hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
+                 bool check, hipStream_t s);
+
+// The fused 2D cycle on level l with red-black smoothing (rb_passes): every pass is one
+// pre or post kernel whose stages alternate red and black partial steps.
+template <typename T>
+hipError_t cycle_rb2d(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
+                      bool check, hipStream_t s) {
+  const int *done = &c->st->done;
+  const int n = c->ns[l];
+  const LevelOp &op = c->ops[l];
+  T *t = (T *)B[l].t, *t2 = (T *)B[l].t2;
+  T *uc = (T *)B[l + 1].u;
+  T *fc = (T *)B[l + 1].f;
+  const int pre = std::max(1, c->cfg.nu1), total = rb_passes(&c->cfg);
+  int k = 0;  // passes done
+  const T *in = zero_u ? nullptr : u;
+  // pass k writes u when total - 1 - k is even, else t; a first pass that would write its
+  // own input u writes t2 instead
+  auto target = [&](int kk) -> T * {
+    T *o = ((total - 1 - kk) % 2 == 0) ? u : t;
+    return (o == in) ? t2 : o;
+  };
+  hipError_t e;
+  for (; k < pre; ++k) {
+    const bool last = k == pre - 1;
+    const int stages = c->cfg.nu1 == 0 ? 0 : 2;
+    T *o = target(k);
+    if (o == nullptr) return hipErrorInvalidValue;
+    int np = 0;
+    e = mgk::launch_pre2d<T>(op, c->omega, stages, last ? (mgk::kPreWriteU | mgk::kPreRestrict) : mgk::kPreWriteU,
+                             f, in, o, nullptr, last ? fc : nullptr, n,
+                             check && k == 0 ? c->partials : nullptr, &np, done, s, c->slots, true);
+    if (e != hipSuccess) return e;
+    if (check && k == 0) {
+      e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
+      if (e != hipSuccess) return e;
+    }
+    in = o;
+  }
+  if (l + 1 >= c->tail_top) {
+    e = launch_tail_at<T>(c, l + 1, uc, fc, true, done, s, c->cfg.gamma);
+  } else if (l + 1 == c->L - 1) {
+    e = mgk::launch_coarsest<T>(c->dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
+  } else {
+    e = hipSuccess;
+    for (int g = 0; g < c->cfg.gamma && e == hipSuccess; ++g)
+      e = cycle<T>(c, B, l + 1, uc, fc, g == 0, false, s);
+  }
+  if (e != hipSuccess) return e;
+  for (int j = 0; k < total; ++k, ++j) {
+    T *o = target(k);
+    if (o == nullptr || o == in) return hipErrorInvalidValue;
+    if (j == 0)
+      e = mgk::launch_post2d<T>(op, c->omega, c->cfg.nu2 == 0 ? 0 : 2, c->cfg.prolong, uc, in, f, o, n,
+                                done, s, c->slots, true);
+    else
+      e = mgk::launch_pre2d<T>(op, c->omega, 2, mgk::kPreWriteU, f, in, o, nullptr, nullptr, n, nullptr,
+                               nullptr, done, s, c->slots, true);
+    if (e != hipSuccess) return e;
+    in = o;
+  }
+  return in == u ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
                  bool check, hipStream_t s) {
   const int *done = &c->st->done;
   const int dim = c->dim;
@@ -460,6 +536,8 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     }
     return launch_tail_at<T>(c, l, u, f, zero_u, done, s);
   }
+  if (c->fused && dim == 2 && c->L > 1 && c->cfg.smoother == MG_SMOOTH_RBJ)
+    return cycle_rb2d<T>(c, B, l, u, f, zero_u, check, s);
   if (c->fused && dim == 2 && c->L > 1) {
     T *t = (T *)B[l].t;
     T *uc = (T *)B[l + 1].u;
@@ -788,8 +866,7 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
   if (const char *g = std::getenv("MG_GRAPH")) c->use_graph = std::atoi(g) != 0;
   if (const char *k = std::getenv("MG_CHUNK")) c->chunk = std::max(1, std::atoi(k));
   if (const char *fz = std::getenv("MG_FUSED")) c->fused = std::atoi(fz) != 0;
-  if (cfg->nu1 > 3 || cfg->nu2 > 2) c->fused = false;
-  if (cfg->smoother == MG_SMOOTH_RBJ) c->fused = false;  // the fused 2D kernels relax every point
+  if (cfg->smoother == MG_SMOOTH_JACOBI && (cfg->nu1 > 3 || cfg->nu2 > 2)) c->fused = false;
   auto bail = [&](mg_status s) {
     std::string msg = g_error;
     mg_destroy(c);
@@ -831,14 +908,18 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
         if ((st = dev_alloc(c, &b.u, np * 8)) != MG_OK) return bail(st);
         if ((st = dev_alloc(c, &b.f, np * 8)) != MG_OK) return bail(st);
       }
-      if (L > 1 && l < L - 1)
+      if (L > 1 && l < L - 1) {
         if ((st = dev_alloc(c, &b.t, np * 8)) != MG_OK) return bail(st);
+        if (needs_t2(cfg) && (st = dev_alloc(c, &b.t2, np * 8)) != MG_OK) return bail(st);
+      }
     } else {
       Buffers &b = c->b32[l];
       if ((st = dev_alloc(c, &b.u, np * 4)) != MG_OK) return bail(st);
       if ((st = dev_alloc(c, &b.f, np * 4)) != MG_OK) return bail(st);
-      if (L > 1 && l < L - 1)
+      if (L > 1 && l < L - 1) {
         if ((st = dev_alloc(c, &b.t, np * 4)) != MG_OK) return bail(st);
+        if (needs_t2(cfg) && (st = dev_alloc(c, &b.t2, np * 4)) != MG_OK) return bail(st);
+      }
     }
   }
   // Stencil entry lists (non-centre, non-zero) of every level, for the tail kernel.
@@ -1154,17 +1235,20 @@ mg_status mg_kernel_presmooth_restrict(mg_handle h, int level, int fp32, const v
                                        const void *u_in, void *u_out, void *fc) {
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
-  if (h->dim != 2 || h->cfg.nu1 > 3) return fail(MG_EINVAL, "fused pre-smoothing needs dim 2, nu1 <= 3");
+  const bool rb = h->cfg.smoother == MG_SMOOTH_RBJ;
+  if (h->dim != 2 || (!rb && h->cfg.nu1 > 3))
+    return fail(MG_EINVAL, "fused pre-smoothing needs dim 2, nu1 <= 3");
   if (!f || !u_out || !fc || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
   const int mode = mgk::kPreWriteU | mgk::kPreRestrict;
+  const int stages = rb ? 2 * std::min(1, h->cfg.nu1) : h->cfg.nu1;
   if (fp32)
-    MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, h->cfg.nu1, mode, (const float *)f,
+    MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, stages, mode, (const float *)f,
                                     (const float *)u_in, (float *)u_out, nullptr, (float *)fc,
-                                    h->ns[level], nullptr, nullptr, nullptr, h->stream));
+                                    h->ns[level], nullptr, nullptr, nullptr, h->stream, 1, rb));
   else
-    MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, h->cfg.nu1, mode, (const double *)f,
+    MG_HIP(mgk::launch_pre2d<double>(h->ops[level], h->omega, stages, mode, (const double *)f,
                                      (const double *)u_in, (double *)u_out, nullptr, (double *)fc,
-                                     h->ns[level], nullptr, nullptr, nullptr, h->stream));
+                                     h->ns[level], nullptr, nullptr, nullptr, h->stream, 1, rb));
   return MG_OK;
 }
 
@@ -1172,16 +1256,19 @@ mg_status mg_kernel_prolong_postsmooth(mg_handle h, int level, int fp32, const v
                                        const void *u_in, const void *f, void *u_out) {
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
-  if (h->dim != 2 || h->cfg.nu2 > 2) return fail(MG_EINVAL, "fused post-smoothing needs dim 2, nu2 <= 2");
+  const bool rb = h->cfg.smoother == MG_SMOOTH_RBJ;
+  if (h->dim != 2 || (!rb && h->cfg.nu2 > 2))
+    return fail(MG_EINVAL, "fused post-smoothing needs dim 2, nu2 <= 2");
   if (!v || !u_in || !f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
+  const int stages = rb ? 2 * std::min(1, h->cfg.nu2) : h->cfg.nu2;
   if (fp32)
-    MG_HIP(mgk::launch_post2d<float>(h->ops[level], h->omega, h->cfg.nu2, h->cfg.prolong,
+    MG_HIP(mgk::launch_post2d<float>(h->ops[level], h->omega, stages, h->cfg.prolong,
                                      (const float *)v, (const float *)u_in, (const float *)f,
-                                     (float *)u_out, h->ns[level], nullptr, h->stream));
+                                     (float *)u_out, h->ns[level], nullptr, h->stream, 1, rb));
   else
-    MG_HIP(mgk::launch_post2d<double>(h->ops[level], h->omega, h->cfg.nu2, h->cfg.prolong,
+    MG_HIP(mgk::launch_post2d<double>(h->ops[level], h->omega, stages, h->cfg.prolong,
                                       (const double *)v, (const double *)u_in, (const double *)f,
-                                      (double *)u_out, h->ns[level], nullptr, h->stream));
+                                      (double *)u_out, h->ns[level], nullptr, h->stream, 1, rb));
   return MG_OK;
 }
 

@@ -7,6 +7,7 @@
 // of the previous one), with one barrier between stages:
 //   pre:  nu omega-Jacobi sweeps, the defect, its full weighting onto the coarse tile;
 //   post: interpolation of the coarse correction and correction, nu2 sweeps.
+// With red-black smoothing the sweeps are partial steps, red and black in turn.
 // Inputs are extended oddly across the Dirichlet boundary when loaded (u(-i) = -u(i),
 // boundary values zero), and every stage evaluated on the extended region reproduces the
 // odd extension of its output, exactly as in the row-marching kernels.
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_pre_tile(const T *__restrict__ f, co
           x < n - 1 && y > 0 && y < n - 1)
         acc += (double)r * (double)r;
       if (s <= NU)
-        su[s & 1][p] = ui[p] + op.om_d * r;
+        su[s & 1][p] = ui[p] + stage_om(op, s, x + y) * r;
       else
         su[s & 1][p] = r;  // the defect (stage K of a residual mode)
     }
@@ -273,9 +274,10 @@ __global__ __launch_bounds__(kBlock) void k_post_tile(const T *__restrict__ v, c
     }
     const int w = PW - 2 * m, h = PH - 2 * m;
     for (int e = threadIdx.x; e < w * h; e += kBlock) {
-      const int p = (m + e / w) * PW + m + e % w;
+      const int i = m + e % w, j = m + e / w;
+      const int p = j * PW + i;
       const T r = sf[NU2 > 0 ? p : 0] - lu_at<T, R, PW>(ui, sy[0], sy[SEP && NU2 > 0 ? 1 : 0], p, op);
-      su[s & 1][p] = ui[p] + op.om_d * r;
+      su[s & 1][p] = ui[p] + stage_om(op, s, X0 + i + Y0 + j) * r;
     }
     __syncthreads();
   }
@@ -300,6 +302,7 @@ KOp<T> to_kop(const LevelOp &op, double omega) {
   k.w1 = (T)(-op.a[2]);
   k.w2 = (T)(-op.a[1]);
   k.om_d = (T)(omega / op.diag);
+  k.colour = 0;
   return k;
 }
 
@@ -336,6 +339,8 @@ hipError_t pre_tile_r(int nu, int mode, const T *f, const T *u, T *uout, T *rout
   }
   if (mode == kPreWriteU && nu == 1)
     return pre_tile_dispatch<T, R, 1, kPreWriteU>(f, u, uout, rout, fc, n, k, partials, nparts, done, s, slots);
+  if (mode == kPreWriteU && nu == 2)
+    return pre_tile_dispatch<T, R, 2, kPreWriteU>(f, u, uout, rout, fc, n, k, partials, nparts, done, s, slots);
   if (mode == kPreWriteR && nu == 0)
     return pre_tile_dispatch<T, R, 0, kPreWriteR>(f, u, uout, rout, fc, n, k, partials, nparts, done, s, slots);
   if (mode == kPreRestrict && nu == 0)
@@ -372,8 +377,9 @@ int pre2d_tile_partials(int n) {
 template <typename T>
 hipError_t launch_pre2d_tile(const LevelOp &op, double omega, int nu, int mode, const T *f, const T *u,
                              T *uout, T *rout, T *fc, int n, double *partials, int *nparts,
-                             const int *done, hipStream_t s, int slots) {
-  const KOp<T> k = to_kop<T>(op, omega);
+                             const int *done, hipStream_t s, int slots, bool rb) {
+  KOp<T> k = to_kop<T>(op, omega);
+  if (rb) k.colour = kColourRB;
   if (op.cross) return pre_tile_r<T, 2>(nu, mode, f, u, uout, rout, fc, n, k, partials, nparts, done, s, slots);
   return pre_tile_r<T, 3>(nu, mode, f, u, uout, rout, fc, n, k, partials, nparts, done, s, slots);
 }
@@ -381,8 +387,9 @@ hipError_t launch_pre2d_tile(const LevelOp &op, double omega, int nu, int mode, 
 template <typename T>
 hipError_t launch_post2d_tile(const LevelOp &op, double omega, int nu2, int prolong, const T *v,
                               const T *uin, const T *f, T *uout, int n, const int *done,
-                              hipStream_t s, int slots) {
-  const KOp<T> k = to_kop<T>(op, omega);
+                              hipStream_t s, int slots, bool rb) {
+  KOp<T> k = to_kop<T>(op, omega);
+  if (rb) k.colour = kColourRB;
   if (op.cross) {
     switch (nu2) {
       case 0: return post_tile_dispatch<T, 2, 0>(prolong, v, uin, f, uout, n, k, done, s, slots);
@@ -401,15 +408,15 @@ hipError_t launch_post2d_tile(const LevelOp &op, double omega, int nu2, int prol
 
 template hipError_t launch_pre2d_tile<double>(const LevelOp &, double, int, int, const double *,
                                               const double *, double *, double *, double *, int,
-                                              double *, int *, const int *, hipStream_t, int);
+                                              double *, int *, const int *, hipStream_t, int, bool);
 template hipError_t launch_pre2d_tile<float>(const LevelOp &, double, int, int, const float *,
                                              const float *, float *, float *, float *, int, double *,
-                                             int *, const int *, hipStream_t, int);
+                                             int *, const int *, hipStream_t, int, bool);
 template hipError_t launch_post2d_tile<double>(const LevelOp &, double, int, int, const double *,
                                                const double *, const double *, double *, int,
-                                               const int *, hipStream_t, int);
+                                               const int *, hipStream_t, int, bool);
 template hipError_t launch_post2d_tile<float>(const LevelOp &, double, int, int, const float *,
                                               const float *, const float *, float *, int, const int *,
-                                              hipStream_t, int);
+                                              hipStream_t, int, bool);
 
 }  // namespace mgk

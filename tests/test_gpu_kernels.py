@@ -279,6 +279,59 @@ def test_prolong_postsmooth(dim, n, coarse, prolong, level, nu1, nu2, fp32):
         H.close()
 
 
+# Fused passes with red-black smoothing: min(1, nu) red-black sweeps per pass.  Sides up
+# to 513 take the LDS tile kernels, larger ones the row-marching kernels.
+RB_FUSED_CASES = [
+    # dim, n, coarse, prolong, level, nu1, nu2
+    (2, 65, 0, 3, 0, 2, 1), (2, 257, 0, 3, 0, 1, 1), (2, 257, 0, 1, 0, 0, 2), (2, 1025, 0, 3, 0, 2, 1),
+    (2, 1025, 0, 1, 0, 1, 0), (2, 1025, 1, 3, 1, 1, 2), (2, 2049, 1, 3, 1, 2, 1), (2, 1025, 3, 3, 0, 2, 2),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level,nu1,nu2", RB_FUSED_CASES)
+def test_red_black_fused_passes(dim, n, coarse, prolong, level, nu1, nu2, fp32):
+    """The fused pre pass (a red-black sweep, the defect, full weighting) and post pass
+    (interpolation, correction, a red-black sweep) = the oracle's partial steps in turn."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, smoother=1)
+    try:
+        n_l, s = H.level(level)
+        d = s[(s.shape[0] // 2,) * dim]
+        nc = (n_l - 1) // 2 + 1
+        u = rand_grid(n_l, dim, 51)
+        f = rand_grid(n_l, dim, 52) * d
+        v = rand_grid(nc, dim, 53)
+        if fp32:
+            u, f, v = (a.astype(np.float32).astype(np.float64) for a in (u, f, v))
+        ud, fd, vd = dev(u, fp32), dev(f, fp32), dev(v, fp32)
+        tol = TOL32 if fp32 else TOL64
+
+        def rb_sweeps(x, count):
+            for _ in range(count):
+                x = oracle.jacobi_colour(s, H.omega, 2, f, oracle.jacobi_colour(s, H.omega, 1, f, x))
+            return x
+
+        uo = dev(np.full_like(u, np.nan), fp32)
+        fc = dev(np.full((nc,) * dim, np.nan), fp32)
+        for start in (u, None):
+            u0 = u if start is not None else np.zeros_like(u)
+            mg.mg_kernel_presmooth_restrict(H.h, level, fp32, fd.data_ptr(),
+                                            ud.data_ptr() if start is not None else None,
+                                            uo.data_ptr(), fc.data_ptr())
+            ref = rb_sweeps(u0, min(1, nu1))
+            scale_u = _scale_u(u, f, s) * 3
+            assert_close(host(uo), ref, tol * scale_u * 4, "pre u")
+            assert_close(host(fc), oracle.restrict(oracle.residual(s, f, ref)),
+                         tol * 8 * (np.abs(f).max() + d * scale_u), "pre coarse rhs")
+        mg.mg_kernel_prolong_postsmooth(H.h, level, fp32, vd.data_ptr(), ud.data_ptr(), fd.data_ptr(),
+                                        uo.data_ptr())
+        ref = rb_sweeps(oracle.prolong_add(v, u.copy(), prolong), min(1, nu2))
+        scale = (np.abs(u).max() + 2 * np.abs(v).max() + np.abs(f).max() / d) * 3
+        assert_close(host(uo), ref, tol * scale * 4, "post")
+    finally:
+        H.close()
+
+
 CASES_3D = [
     # dim, finest n, coarse, prolong, level
     (3, 9, 0, 3, 0), (3, 17, 0, 3, 0), (3, 33, 0, 3, 0), (3, 65, 0, 3, 0), (3, 65, 0, 3, 1),

@@ -78,6 +78,27 @@ def test_red_black_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma)
         H.close()
 
 
+@pytest.mark.parametrize("fused", ["0", "1"])
+@pytest.mark.parametrize("nu1,nu2,gamma", [(2, 1, 1), (2, 1, 2), (1, 1, 1), (3, 2, 1), (0, 1, 1),
+                                           (1, 0, 2), (2, 2, 2)])
+def test_red_black_fused_cycles(fused, nu1, nu2, gamma, monkeypatch):
+    """2D red-black cycles through the fused passes (one pass per red-black sweep, with
+    the third sweep target when the pass count is odd) and through the separate kernels,
+    against the oracle, on a grid with row-marching (1025, 513 tiles) and tail levels."""
+    monkeypatch.setenv("MG_FUSED", fused)
+    n = 1025
+    H = Handle(2, n, nu1=nu1, nu2=nu2, gamma=gamma, smoother=1)
+    try:
+        _, f, _ = inputs.manufactured_2d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 3)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17")])
 def test_red_black_tail_variants_agree(dim, n, tail, monkeypatch):
     """Red-black smoothing inside and outside the LDS-resident tail: same cycles."""
