@@ -203,10 +203,18 @@ def jacobi_omega_star(dim):
     return {2: 10.0 / 13.0, 3: 9.0 / 11.0}[dim]
 
 
+def jacobi_omega(dim, order=4):
+    """omega* of omega-Jacobi for every order: second order 4/5, 6/7 (section 5.3);
+    fourth order 10/13, 9/11; sixth order 490/653, 147/185 (lfa.jacobi_optimum)."""
+    return {2: {2: 4.0 / 5.0, 3: 6.0 / 7.0}, 4: {2: 10.0 / 13.0, 3: 9.0 / 11.0},
+            6: {2: 490.0 / 653.0, 3: 147.0 / 185.0}}[order][dim]
+
+
 def rbj_omega(dim, order=4):
     """Default omega of red-black Jacobi: the minimiser of the LFA two-grid factor of the
     V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
-    return {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13}[(dim, order)]
+    return {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13, (2, 6): 1.13,
+            (3, 6): 1.15}[(dim, order)]
 
 
 class Multigrid:
@@ -216,7 +224,7 @@ class Multigrid:
                  prolong=PROLONG_CUBIC, nu1=2, nu2=1, gamma=1, n_coarsest=9, omega=None,
                  smoother=SMOOTH_JACOBI):
         if omega is None:
-            omega = jacobi_omega_star(dim) if smoother == SMOOTH_JACOBI else rbj_omega(dim, order)
+            omega = jacobi_omega(dim, order) if smoother == SMOOTH_JACOBI else rbj_omega(dim, order)
         self.cfg = _Config(dim, n, order, coarse, restrict_op, prolong, nu1, nu2, gamma,
                            n_coarsest, float(omega), smoother)
         self.dim, self.n = dim, n

@@ -11,12 +11,24 @@ import numpy as np
 import scipy.fft
 
 
+def _per_axis(s, h, order):
+    """1D symbol of the order-2/4/6 second difference at s = sin^2(theta/2) (appendix A.4;
+    sixth order: section 3.3 eq. LhOrder6, one more term of the same series)."""
+    if order == 2:
+        return 4.0 / h ** 2 * s
+    if order == 4:
+        return 4.0 / h ** 2 * (s + s * s / 3.0)
+    if order == 6:
+        return 4.0 / h ** 2 * (s + s * s / 3.0 + 8.0 * s ** 3 / 45.0)
+    raise ValueError(order)
+
+
 def eigenvalues(n, dim, order=4):
     """lambda_k on the (n-2)^dim grid of interior modes, index [kz][ky][kx]."""
     h = 1.0 / (n - 1)
     k = np.arange(1, n - 1)
     s = np.sin(k * np.pi * h / 2.0) ** 2
-    per_axis = 4.0 / h ** 2 * (s + s * s / 3.0) if order == 4 else 4.0 / h ** 2 * s
+    per_axis = _per_axis(s, h, order)
     lam = np.zeros((n - 2,) * dim)
     for a in range(dim):
         shape = [1] * dim
@@ -58,7 +70,7 @@ def discrete_solution_of_sine_series(n, coeffs, order=4):
     h = 1.0 / (n - 1)
     k = np.arange(1, K + 1)
     s = np.sin(k * np.pi * h / 2.0) ** 2
-    per_axis = 4.0 / h ** 2 * (s + s * s / 3.0) if order == 4 else 4.0 / h ** 2 * s
+    per_axis = _per_axis(s, h, order)
     lam = np.zeros((K,) * dim)
     ksq = np.zeros((K,) * dim)
     for a in range(dim):

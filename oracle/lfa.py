@@ -4,7 +4,9 @@ Everything here is built from the Fourier symbols the paper prints, not from ste
 
 * fine operator symbol, fourth order: (4/h^2) sum_a (s_a + s_a^2/3), s_a = sin^2(theta_a/2)
   (appendix A.4, eq. L_hat_2d_4o, written per axis); second order: (4/h^2) sum_a s_a
-  (section 5.3, the symbol behind xi_theta);
+  (section 5.3, the symbol behind xi_theta); sixth order (section 3.3 eq. LhOrder6):
+  (4/h^2) sum_a (s_a + s_a^2/3 + 8 s_a^3/45), the next term of the series
+  theta^2 = 4 arcsin^2(sqrt(s)) that the lower orders truncate;
 * full weighting: prod_a (1 - s_a) (appendix A.2, below eq. transfer_hat_2d);
 * cubic transfer: prod_a (1 - s_a^2 (3 - 2 s_a)) (appendix A.4);
 * linear interpolation: the transpose of full weighting (appendix A.2), same values;
@@ -51,6 +53,8 @@ def symbol_fine(theta, h, order=4):
         return (4.0 / h ** 2) * np.sum(s + s * s / 3.0, axis=-1)
     if order == 2:
         return (4.0 / h ** 2) * np.sum(s, axis=-1)
+    if order == 6:
+        return (4.0 / h ** 2) * np.sum(s + s * s / 3.0 + 8.0 * s ** 3 / 45.0, axis=-1)
     raise ValueError(order)
 
 
@@ -142,7 +146,7 @@ class Scheme:
 # Default omega of the red-black Jacobi smoother: the value minimising the two-grid factor
 # of the V(2,1) cycle with cubic interpolation and the rediscretized operator, rounded to two
 # decimals (rbj_optimum recomputes it).
-RBJ_OMEGA = {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13}
+RBJ_OMEGA = {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13, (2, 6): 1.13, (3, 6): 1.15}
 
 
 def rbj_optimum(dim, order=4, m=None):
@@ -166,6 +170,9 @@ def jacobi_optimum(dim, order=4):
     if order == 4:
         a0 = 30.0 * dim / 12.0
         g = lambda s: 4.0 * (s + s * s / 3.0)
+    elif order == 6:
+        a0 = 490.0 * dim / 180.0
+        g = lambda s: 4.0 * (s + s * s / 3.0 + 8.0 * s ** 3 / 45.0)
     else:
         a0 = 2.0 * dim
         g = lambda s: 4.0 * s

@@ -75,19 +75,23 @@ static long sidx(int dim, int R, int ox, int oy, int oz) {
   return dim == 2 ? (long)(oy + R) * w + (ox + R) : ((long)(oz + R) * w + (oy + R)) * w + (ox + R);
 }
 
-/* 1D second difference -u'' of order 2 (eq. L_h_2) or 4 (eq. L_h_2d_4o), times h^2. */
+/* 1D second difference -u'' of order 2 (eq. L_h_2), 4 (eq. L_h_2d_4o) or 6 (section 3.3
+ * eq. LhOrder6, one axis of the printed 2D stencil), times h^2. */
 static void second_difference_1d(int order, double *c /* 2R+1 */) {
   if (order == 2) {
     c[0] = -1.0; c[1] = 2.0; c[2] = -1.0;
-  } else {
+  } else if (order == 4) {
     c[0] = 1.0 / 12.0; c[1] = -16.0 / 12.0; c[2] = 30.0 / 12.0;
     c[3] = -16.0 / 12.0; c[4] = 1.0 / 12.0;
+  } else {
+    c[0] = -2.0 / 180.0; c[1] = 27.0 / 180.0; c[2] = -270.0 / 180.0; c[3] = 490.0 / 180.0;
+    c[4] = -270.0 / 180.0; c[5] = 27.0 / 180.0; c[6] = -2.0 / 180.0;
   }
 }
 
 int or_fine_stencil(int dim, int order, double h, double *s) {
   int R = order / 2, w = swidth(R);
-  double c[5];
+  double c[7];
   long total = dim == 2 ? (long)w * w : (long)w * w * w;
   second_difference_1d(order, c);
   memset(s, 0, sizeof(double) * total);
@@ -496,7 +500,7 @@ void or_mg_coarsest_solve(or_mg *mg, const double *g, double *v) {
 or_mg *or_mg_create(const or_config *cfg) {
   int L = or_num_levels(cfg->n, cfg->n_coarsest);
   if (L <= 0 || L > OR_MAX_LEVELS || (cfg->dim != 2 && cfg->dim != 3)) return NULL;
-  if (cfg->order != 2 && cfg->order != 4) return NULL;
+  if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6) return NULL;
   if (cfg->coarse < OR_COARSE_NG || cfg->coarse > OR_COARSE_G2) return NULL;
   if (cfg->smoother != OR_SMOOTH_JACOBI && cfg->smoother != OR_SMOOTH_RBJ) return NULL;
   or_mg *mg = (or_mg *)calloc(1, sizeof(or_mg));

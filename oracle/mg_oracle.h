@@ -51,7 +51,7 @@ extern "C" {
 typedef struct {
   int dim;          /* 2 or 3 */
   int n;            /* finest points per axis incl. boundary, 2^k+1 */
-  int order;        /* 2 or 4: order of the finest-level operator */
+  int order;        /* 2, 4 or 6: order of the finest-level operator */
   int coarse;       /* OR_COARSE_NG, OR_COARSE_GALERKIN, OR_COARSE_NG2 or OR_COARSE_G2 */
   int restrict_op;  /* OR_RESTRICT_FW or OR_RESTRICT_CUBIC */
   int prolong;      /* OR_PROLONG_LINEAR or OR_PROLONG_CUBIC */
@@ -65,9 +65,9 @@ typedef struct {
 /* Number of levels n, (n-1)/2+1, ... down to n_coarsest; 0 if n does not reach it. */
 int or_num_levels(int n, int n_coarsest);
 
-/* Finest-level operator -Delta_h of the given order (2: eq. L_h_2, 4: eq. L_h_2d_4o),
- * in dim dimensions as the sum of the 1D operators along each axis.  Writes
- * (2R+1)^dim coefficients with R = order/2 and returns R. */
+/* Finest-level operator -Delta_h of the given order (2: eq. L_h_2, 4: eq. L_h_2d_4o,
+ * 6: section 3.3 eq. LhOrder6), in dim dimensions as the sum of the 1D operators along
+ * each axis.  Writes (2R+1)^dim coefficients with R = order/2 and returns R. */
 int or_fine_stencil(int dim, int order, double h, double *s);
 
 /* Galerkin coarse stencil R * L * P on the infinite grid (eq. L_H_G), computed by its

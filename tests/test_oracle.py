@@ -31,6 +31,23 @@ def test_fourth_order_stencil_matches_printed():
     np.testing.assert_allclose(Lu[2:7, 2:7] * h * h, (printed * factor)[::-1, ::-1], atol=1e-15)
 
 
+def test_sixth_order_stencil_matches_printed():
+    printed, factor = read_golden("stencil_6th_order_2d.txt")
+    h = 0.125
+    s = oracle.fine_stencil(2, 6, h)
+    np.testing.assert_allclose(s * h * h, printed * factor, rtol=0, atol=1e-14)
+    # the 3D operator is the sum of the three axis operators (the 1D one is the printed
+    # middle row with half its centre)
+    s3 = oracle.fine_stencil(3, 6, 1.0)
+    axis = printed[3] * factor
+    axis[3] /= 2
+    off = [0, 1, 2, 4, 5, 6]
+    for line in (s3[3, 3, :], s3[3, :, 3], s3[:, 3, 3]):
+        np.testing.assert_allclose(line[off], axis[off], atol=1e-14)
+    assert abs(s3[3, 3, 3] - 3 * axis[3]) < 1e-13 and abs(s3.sum()) < 1e-12
+    assert np.count_nonzero(s3) == 19
+
+
 def test_3d_operator_is_sum_of_axis_operators():
     s = oracle.fine_stencil(3, 4, 1.0)
     c = np.array([1, -16, 30, -16, 1]) / 12.0
@@ -114,7 +131,7 @@ def test_second_order_coarse_operators_of_the_hierarchy():
 
 # ------------------------------------------------------------------ Fourier symbols --
 
-@pytest.mark.parametrize("dim,order", [(2, 4), (3, 4), (2, 2), (3, 2)])
+@pytest.mark.parametrize("dim,order", [(2, 4), (3, 4), (2, 2), (3, 2), (2, 6), (3, 6)])
 def test_operator_symbol_on_sine_modes(dim, order):
     """L_h sin-mode = symbol(theta) * sin-mode (appendix A.4 eq. L_hat_2d_4o)."""
     n = 17 if dim == 2 else 9
@@ -175,16 +192,19 @@ def test_jacobi_optimum_order2_matches_paper_formula():
         assert abs(mu - (1 - zeta) / (1 + zeta)) < 1e-15
 
 
-@pytest.mark.parametrize("dim,omega,mu", [(2, 10 / 13, 25 / 39), (3, 9 / 11, 41 / 55)])
-def test_jacobi_optimum_fourth_order(dim, omega, mu):
-    w, m = lfa.jacobi_optimum(dim, 4)
+@pytest.mark.parametrize("dim,order,omega,mu", [(2, 4, 10 / 13, 25 / 39), (3, 4, 9 / 11, 41 / 55),
+                                                (2, 6, 490 / 653, 435 / 653),
+                                                (3, 6, 147 / 185, 707 / 925)])
+def test_jacobi_optimum_fourth_order(dim, order, omega, mu):
+    w, m = lfa.jacobi_optimum(dim, order)
     assert abs(w - omega) < 1e-15 and abs(m - mu) < 1e-15
+    assert abs(oracle.jacobi_omega(dim, order) - omega) < 1e-15
     # The closed form is the supremum of |S| over the high frequencies ...
-    sch = lfa.Scheme(dim, omega=w)
+    sch = lfa.Scheme(dim, order=order, omega=w)
     assert abs(lfa.smoothing_factor(sch, m=32 if dim == 3 else 64) - mu) < 1e-12
     # ... and any other omega smooths worse.
     for dw in (-0.02, 0.02):
-        assert lfa.smoothing_factor(lfa.Scheme(dim, omega=w + dw), m=16) > mu
+        assert lfa.smoothing_factor(lfa.Scheme(dim, order=order, omega=w + dw), m=16) > mu
 
 
 def test_smoother_diagonal_from_symbol():
@@ -271,6 +291,46 @@ def test_multilevel_cycle_matches_explicit_matrices(gamma, coarse, smoother):
     np.testing.assert_allclose(M, Me, atol=1e-13)
 
 
+@pytest.mark.parametrize("coarse,prolong,smoother", [(0, 1, 0), (1, 1, 0), (2, 1, 0), (3, 1, 0),
+                                                    (0, 3, 0), (3, 3, 1), (0, 1, 1)])
+def test_two_grid_spectrum_equals_lfa_sixth_order(coarse, prolong, smoother):
+    """Sixth-order fine operator (section 3.3) with the transfers of eq. transfer_2d or cubic
+    interpolation, the four coarse operators, both smoothers: exact finite-grid spectra."""
+    n = 17
+    mg = oracle.Multigrid(2, n, order=6, coarse=coarse, prolong=prolong, nu1=1, nu2=1,
+                          n_coarsest=9, smoother=smoother)
+    assert mg.levels == 2
+    ev = np.linalg.eigvals(_cycle_matrix(mg, n, 2))
+    sch = lfa.Scheme(2, order=6, coarse=coarse, prolong=prolong, nu1=1, nu2=1, smoother=smoother,
+                     omega=mg.cfg.omega)
+    ref = lfa.finite_two_grid_spectrum(sch, n)
+    key = lambda z: (round(z.real, 9), round(z.imag, 9))
+    a = np.array(sorted(ev, key=key))
+    b = np.array(sorted(ref.astype(complex), key=key))
+    np.testing.assert_allclose(a, b, atol=1e-9)
+
+
+def test_sixth_order_galerkin_equals_brute_force_rap():
+    """R L_h P of the sixth-order operator by the oracle's definition-based construction
+    against explicit matrices; the coarse stencil keeps radius 3."""
+    n = 17
+    sf = oracle.fine_stencil(2, 6, 1.0 / (n - 1))
+    sc = oracle.galerkin_stencil(sf, oracle.RESTRICT_FW, oracle.PROLONG_CUBIC)
+    assert sc.shape == (7, 7)
+    A = explicit.operator(sf, n)
+    Rm = explicit.restriction(2, n, 1)
+    Pm = explicit.prolongation(2, n, 3)
+    Ac = explicit.galerkin(Rm, A, Pm).toarray()
+    nc = (n - 1) // 2 + 1
+    # interior rows far from the boundary equal the stencil
+    Ae = explicit.operator(sc, nc).toarray()
+    q = nc - 2
+    for J in range(3, q - 3):
+        for I in range(3, q - 3):
+            row = J * q + I
+            np.testing.assert_allclose(Ac[row], Ae[row], atol=1e-9 * np.abs(Ae).max())
+
+
 # ------------------------------------------------------------ red-black smoothing --
 
 def test_rb_symbol_matches_printed_five_point():
@@ -341,14 +401,14 @@ def test_rb_partial_steps_equal_gauss_seidel_five_point():
     np.testing.assert_array_equal(oracle.jacobi_colour(s, 0.9, 0, f, u), oracle.jacobi(s, 0.9, f, u))
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_rbj_default_omega_is_lfa_optimum(dim):
+@pytest.mark.parametrize("dim,order", [(2, 4), (3, 4), (2, 6), (3, 6)])
+def test_rbj_default_omega_is_lfa_optimum(dim, order):
     """The default red-black omega minimises the LFA two-grid factor of V(2,1) (the
     reading that omega is chosen for rho rather than mu, section 2.2 after eq. mu)."""
-    w, rho = lfa.rbj_optimum(dim, 4)
-    assert abs(w - oracle.rbj_omega(dim, 4)) < 0.01
-    assert abs(lfa.RBJ_OMEGA[(dim, 4)] - oracle.rbj_omega(dim, 4)) == 0
-    jac = lfa.two_grid_rho(lfa.Scheme(dim), m=12 if dim == 3 else 24)
+    w, rho = lfa.rbj_optimum(dim, order)
+    assert abs(w - oracle.rbj_omega(dim, order)) < 0.01
+    assert abs(lfa.RBJ_OMEGA[(dim, order)] - oracle.rbj_omega(dim, order)) == 0
+    jac = lfa.two_grid_rho(lfa.Scheme(dim, order=order), m=12 if dim == 3 else 24)
     assert rho < 0.2 * jac  # red-black Jacobi beats omega-Jacobi per sweep by far here
 
 
@@ -432,6 +492,23 @@ def test_manufactured_solution_converges_at_fourth_order():
         errs.append(np.abs(u - ustar).max())
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders[1:] > 3.8) and np.all(orders[1:] < 4.2), orders
+
+
+def test_manufactured_solution_converges_at_sixth_order():
+    """Sixth-order operator (section 3.3): the error falls by ~64 per refinement, and the
+    oracle's stencil applied to the DST solution gives back f."""
+    errs = []
+    for n in [33, 65, 129, 257]:
+        ustar, f, c = inputs.manufactured_2d(n)
+        u = dst.discrete_solution_of_sine_series(n, c, order=6)
+        errs.append(np.abs(u - ustar).max())
+        if n == 65:
+            # the sine transform with the sixth-order eigenvalues inverts the oracle's
+            # stencil with its odd-reflection closure (radius 3 reaches two points out)
+            g = oracle.apply(oracle.fine_stencil(2, 6, 1.0 / (n - 1)), np.ascontiguousarray(u))
+            np.testing.assert_allclose(dst.solve(g, order=6), u, atol=1e-11 * np.abs(u).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 5.7) and np.all(orders < 6.3), orders
 
 
 def test_multigrid_converges_to_exact_discrete_solution():
