@@ -66,6 +66,7 @@ def parse():
     p.add_argument("--gamma", type=int, default=None)
     p.add_argument("--smoother", type=int, default=None,
                    help="0 omega-Jacobi (default), 1 red-black Jacobi")
+    p.add_argument("--order", type=int, default=None, help="fine operator order: 4 (default), 2 or 6")
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
     p.add_argument("--inner", type=int, default=None, help="FP32 cycles per refinement step")
@@ -110,8 +111,8 @@ def describe(w):
     prec = "FP64" if w["precision"] == 0 else "FP32 cycles in FP64 refinement"
     d = w["dim"]
     sm = "red-black Jacobi" if w.get("smoother", 0) else "omega-Jacobi"
-    return "%dD 4th-order Poisson %s, %s, %s %s, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
-        d, "x".join([str(w["n"])] * d), rhs, cyc, sm, kind, d, prec)
+    return "%dD %dth-order Poisson %s, %s, %s %s, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
+        d, w.get("order", 4), "x".join([str(w["n"])] * d), rhs, cyc, sm, kind, d, prec)
 
 
 class Run:
@@ -124,7 +125,8 @@ class Run:
         self.cfg = mg.make_config(dim=w["dim"], n=w["n"], coarse=w["coarse"], gamma=w["gamma"],
                                   nu1=w["nu1"], nu2=w["nu2"], precision=precision, rtol=1e-10,
                                   max_cycles=60 if precision == 0 else 30,
-                                  inner_cycles=w["inner"], smoother=w.get("smoother", 0))
+                                  inner_cycles=w["inner"], smoother=w.get("smoother", 0),
+                                  order=w.get("order", 4))
         self.h = mg.mg_setup(self.cfg, stream.cuda_stream)
         self.fd = fd
         self.ud = torch.zeros_like(fd)
@@ -304,7 +306,7 @@ def cpu_baseline(w, cycles_needed, budget_s=20.0):
     ws = dict(w, n=n)
     f, _ = make_rhs(ws)
     m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
-                         smoother=w.get("smoother", 0))
+                         smoother=w.get("smoother", 0), order=w.get("order", 4))
     u = np.zeros_like(f)
     t0 = time.perf_counter()
     m.cycle(u, f)
@@ -340,7 +342,7 @@ def error_vs_129(ud_host, w, coeffs):
     stride = (n - 1) // (nco - 1)
     f129 = inputs.smooth_sine_3d(nco)
     m = oracle.Multigrid(3, nco, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
-                         smoother=w.get("smoother", 0))
+                         smoother=w.get("smoother", 0), order=w.get("order", 4))
     u129 = np.zeros_like(f129)
     cycles, hist = m.solve(u129, f129, rtol=1e-10, max_cycles=60)
     m.close()
@@ -475,7 +477,7 @@ def main():
     import torch
 
     w = dict(WORKLOADS[args.workload])
-    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother"):
+    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order"):
         if getattr(args, k) is not None:
             w[k] = getattr(args, k)
     torch.cuda.set_device(0)
@@ -502,15 +504,21 @@ def main():
     if args.workload == "poisson2d-4097" and not args.no_variants:
         variants = {}
         kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
-        for coarse, gamma, sm in ((0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 0), (2, 1, 0), (3, 1, 0),
-                                  (0, 1, 1), (1, 1, 1), (3, 1, 1), (0, 2, 1)):
+        for coarse, gamma, sm, order in (
+                (0, 1, 0, 4), (1, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4), (2, 1, 0, 4), (3, 1, 0, 4),
+                (0, 1, 1, 4), (1, 1, 1, 4), (3, 1, 1, 4), (0, 2, 1, 4),
+                (0, 1, 0, 6), (3, 1, 0, 6), (3, 1, 1, 6)):
             name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
             if sm:
                 name = "redblack-" + name
-            if coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0):
+            if order != 4:
+                name = "order%d-%s" % (order, name)
+            if (coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0)
+                    and order == w.get("order", 4)):
                 vs, vres = sec, res
             else:
-                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm), w["precision"], fd, stream)
+                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm, order=order), w["precision"],
+                         fd, stream)
                 vs, (vst, vres) = vr.timed(2, 1)
                 vr.close()
             variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
@@ -551,7 +559,8 @@ def main():
     dom = dom[0]
     cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
     src = "fused2d.hip" if d == 2 else "kernels3d.hip"
-    key = "%s/%s/%s/%d%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "")
+    key = "%s/%s/%s/%d%s%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "",
+                               "/o%d" % w.get("order", 4) if w.get("order", 4) != 4 else "")
     tr = MEASURED_TRAFFIC.get(key)
     traffic = tr["bytes"] if tr and tr["source"] == source_hash(src) else None
 
@@ -575,6 +584,7 @@ def main():
                                      "galerkin-order2"][w["coarse"]],
             "precision": "fp64" if w["precision"] == 0 else "mixed",
             "smoother": "red-black-jacobi" if w.get("smoother", 0) else "jacobi",
+            "order": w.get("order", 4),
             "cycles": res.cycles, "outer_steps": res.outer_steps,
             "final_rel_residual": res.rel_residual, "floor_hit": bool(res.floor_hit),
             "status": status,

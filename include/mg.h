@@ -75,13 +75,15 @@ typedef enum {
 typedef struct {
   int dim;             /* 2 or 3 */
   int n;               /* points per axis incl. boundary, 2^k + 1, reaching n_coarsest */
-  int order;           /* 4 (fourth order, width-5 stencil) or 2 (5-/7-point) */
+  int order;           /* 4 (fourth order, width-5 stencil), 2 (5-/7-point) or 6 (sixth order,
+                          width-7 stencil, section 3.3 eq. LhOrder6) */
   int coarse;          /* mg_coarse */
   int smoother;        /* mg_smoother */
   double omega;        /* Jacobi relaxation; <= 0 selects the Fourier-analysis optimum:
                           omega-Jacobi 10/13 in 2D, 9/11 in 3D for order 4 (4/5, 6/7 for
-                          order 2); red-black Jacobi 1.13 in 2D, 1.17 in 3D for order 4 (1.0,
-                          1.13 for order 2), the minimisers of the two-grid factor of V(2,1) */
+                          order 2; 490/653, 147/185 for order 6); red-black Jacobi 1.13 in
+                          2D, 1.17 in 3D for order 4 (1.0, 1.13 for order 2; 1.13, 1.15 for
+                          order 6), the minimisers of the two-grid factor of V(2,1) */
   int nu1, nu2;        /* pre- and post-smoothing sweeps per cycle (nu1 + nu2 >= 1) */
   int gamma;           /* 1 = V cycle, 2 = W cycle */
   int prolong;         /* 3 = cubic interpolation, 1 = (bi/tri)linear */

@@ -97,7 +97,11 @@ void galerkin_1d(const double c[7], int prolong, double out[7]) {
 LevelOp rediscretized(int order, int dim, double h) {
   LevelOp op{};
   const double s = 1.0 / (h * h);
-  if (order == 4) {
+  if (order == 6) {
+    // section 3.3 eq. LhOrder6: radius 3, applied by the separable (Galerkin-level) kernels
+    const double c[7] = {-2.0 / 180, 27.0 / 180, -270.0 / 180, 490.0 / 180, -270.0 / 180, 27.0 / 180, -2.0 / 180};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  } else if (order == 4) {
     const double c[7] = {0.0, 1.0 / 12, -16.0 / 12, 30.0 / 12, -16.0 / 12, 1.0 / 12, 0.0};
     for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
   } else {
@@ -105,7 +109,7 @@ LevelOp rediscretized(int order, int dim, double h) {
     for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
   }
   op.b[3] = 1.0;
-  op.cross = true;
+  op.cross = order != 6;
   op.diag = dim * op.a[3];
   return op;
 }
@@ -258,7 +262,7 @@ size_t points(int dim, int n) { return dim == 2 ? (size_t)n * n : (size_t)n * n 
 mg_status validate(const mg_config *c, int *levels) {
   if (!c) return fail(MG_EINVAL, "null config");
   if (c->dim != 2 && c->dim != 3) return fail(MG_EINVAL, "dim must be 2 or 3");
-  if (c->order != 2 && c->order != 4) return fail(MG_EINVAL, "order must be 2 or 4");
+  if (c->order != 2 && c->order != 4 && c->order != 6) return fail(MG_EINVAL, "order must be 2, 4 or 6");
   if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN && c->coarse != MG_COARSE_NG2 &&
       c->coarse != MG_COARSE_G2)
     return fail(MG_EINVAL, "unknown coarse operator");
@@ -290,10 +294,12 @@ double default_omega(int dim, int order, int smoother) {
   // Red-black Jacobi: the minimiser of the Fourier-analysis two-grid factor of the V(2,1)
   // cycle (cubic interpolation, rediscretized operator), to two decimals.
   if (smoother == MG_SMOOTH_RBJ) {
+    if (order == 6) return dim == 2 ? 1.13 : 1.15;
     if (order == 4) return dim == 2 ? 1.13 : 1.17;
     return dim == 2 ? 1.0 : 1.13;
   }
   // omega-Jacobi: equioscillation of the symbol over the high frequencies.
+  if (order == 6) return dim == 2 ? 490.0 / 653.0 : 147.0 / 185.0;
   if (order == 4) return dim == 2 ? 10.0 / 13.0 : 9.0 / 11.0;
   return dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0;
 }

@@ -52,7 +52,7 @@ class Handle:
         elif smoother == oracle.SMOOTH_RBJ:
             self.omega = oracle.rbj_omega(dim, order)
         else:
-            self.omega = oracle.jacobi_omega_star(dim) if order == 4 else {2: 4 / 5, 3: 6 / 7}[dim]
+            self.omega = oracle.jacobi_omega(dim, order)
         self.oracle = oracle.Multigrid(dim, n, order=order, coarse=coarse, prolong=prolong,
                                        nu1=nu1, nu2=nu2, gamma=gamma, n_coarsest=n_coarsest,
                                        omega=self.omega, smoother=smoother)

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("kwargs", [
-    dict(dim=4), dict(order=6), dict(n=100), dict(n=129, n_coarsest=7), dict(gamma=3),
+    dict(dim=4), dict(order=8), dict(order=3), dict(n=100), dict(smoother=2), dict(n=129, n_coarsest=7), dict(gamma=3),
     dict(prolong=2), dict(restrict_op=3), dict(nu1=0, nu2=0), dict(omega=2.5),
     dict(max_cycles=0), dict(precision=1, inner_cycles=0), dict(coarse=5),
 ])

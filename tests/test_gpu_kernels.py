@@ -332,6 +332,58 @@ def test_red_black_fused_passes(dim, n, coarse, prolong, level, nu1, nu2, fp32):
         H.close()
 
 
+# Sixth-order fine operator (section 3.3): radius-3 separable kernels on level 0.
+SIXTH_CASES = [
+    # dim, n, coarse, prolong, level
+    (2, 65, 0, 1, 0), (2, 257, 0, 3, 0), (2, 1025, 0, 1, 0), (2, 1025, 3, 3, 1), (2, 257, 1, 1, 1),
+    (3, 33, 0, 3, 0), (3, 65, 0, 1, 0), (3, 129, 0, 3, 0), (3, 65, 1, 3, 1),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,prolong,level", SIXTH_CASES)
+def test_sixth_order_steps(dim, n, coarse, prolong, level, fp32):
+    """Sweep, colour step, defect, defect + full weighting and (2D) the fused passes with
+    the sixth-order operator, against the oracle's same steps."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, order=6, nu1=1, nu2=1)
+    try:
+        n_l, s = H.level(level)
+        d = s[(s.shape[0] // 2,) * dim]
+        u = rand_grid(n_l, dim, 61)
+        f = rand_grid(n_l, dim, 62) * d
+        nc = (n_l - 1) // 2 + 1
+        v = rand_grid(nc, dim, 63)
+        if fp32:
+            u, f, v = (a.astype(np.float32).astype(np.float64) for a in (u, f, v))
+        ud, fd, vd = dev(u, fp32), dev(f, fp32), dev(v, fp32)
+        tol = TOL32 if fp32 else TOL64
+        su = _scale_u(u, f, s)
+        out = dev(np.full_like(u, np.nan), fp32)
+        mg.mg_kernel_smooth(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        assert_close(host(out), oracle.jacobi(s, H.omega, f, u), tol * su * 4, "sweep")
+        mg.mg_kernel_smooth_colour(H.h, level, fp32, 1, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        assert_close(host(out), oracle.jacobi_colour(s, H.omega, 1, f, u), tol * su * 4, "red step")
+        mg.mg_kernel_residual(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        scale = np.abs(f).max() + d * np.abs(u).max()
+        assert_close(host(out), oracle.residual(s, f, u), tol * scale * 8, "defect")
+        fc = dev(np.full((nc,) * dim, np.nan), fp32)
+        mg.mg_kernel_residual_restrict(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
+        assert_close(host(fc), oracle.restrict(oracle.residual(s, f, u)), tol * scale * 8, "defect+FW")
+        if dim == 2:
+            mg.mg_kernel_presmooth_restrict(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(),
+                                            out.data_ptr(), fc.data_ptr())
+            ref = oracle.jacobi(s, H.omega, f, u)
+            assert_close(host(out), ref, tol * su * 8, "pre u")
+            assert_close(host(fc), oracle.restrict(oracle.residual(s, f, ref)), tol * scale * 16, "pre fc")
+            mg.mg_kernel_prolong_postsmooth(H.h, level, fp32, vd.data_ptr(), ud.data_ptr(),
+                                            fd.data_ptr(), out.data_ptr())
+            ref = oracle.jacobi(s, H.omega, f, oracle.prolong_add(v, u.copy(), prolong))
+            sc = (np.abs(u).max() + 2 * np.abs(v).max() + np.abs(f).max() / d) * 2
+            assert_close(host(out), ref, tol * sc * 4, "post")
+    finally:
+        H.close()
+
+
 CASES_3D = [
     # dim, finest n, coarse, prolong, level
     (3, 9, 0, 3, 0), (3, 17, 0, 3, 0), (3, 33, 0, 3, 0), (3, 65, 0, 3, 0), (3, 65, 0, 3, 1),

@@ -99,6 +99,53 @@ def test_red_black_fused_cycles(fused, nu1, nu2, gamma, monkeypatch):
         H.close()
 
 
+SIXTH_CYCLES = [
+    # dim, n, coarse, prolong, nu1, nu2, gamma, smoother: sixth-order fine operator (section 3.3)
+    (2, 129, 0, 1, 2, 1, 1, 0), (2, 129, 1, 1, 2, 1, 1, 0), (2, 129, 2, 1, 2, 1, 1, 0),
+    (2, 129, 3, 1, 2, 1, 1, 0), (2, 1025, 3, 3, 2, 1, 1, 0), (2, 257, 0, 3, 1, 1, 2, 0),
+    (2, 1025, 3, 1, 2, 1, 1, 1), (2, 257, 1, 3, 1, 1, 2, 1),
+    (3, 33, 0, 3, 2, 1, 1, 0), (3, 65, 3, 1, 2, 1, 1, 0), (3, 65, 1, 3, 2, 2, 2, 0),
+    (3, 65, 2, 1, 2, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dim,n,coarse,prolong,nu1,nu2,gamma,smoother", SIXTH_CYCLES)
+def test_sixth_order_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma, smoother):
+    """Cycles with the sixth-order fine operator and each coarse operator (section 3.3:
+    second-order rediscretized or Galerkin coarse operators against sixth-order ones)."""
+    H = Handle(dim, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, gamma=gamma, order=6,
+               smoother=smoother)
+    try:
+        f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 4)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+def test_sixth_order_solve_converges_to_discrete_solution():
+    """A 2D sixth-order solve to 1e-10 lands on the exact discrete solution (sine
+    transform with the sixth-order eigenvalues) within the bound its residual implies."""
+    n = 513
+    H = Handle(2, n, coarse=3, prolong=1, order=6, rtol=1e-10)
+    try:
+        ustar, f, c = inputs.manufactured_2d(n)
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_OK and res.rel_residual <= 1e-10
+        exact = dst.solve(f, order=6)
+        lam_min = dst.eigenvalues(n, 2, order=6).min()
+        bound = res.rel_residual * np.linalg.norm(f[1:-1, 1:-1]) / lam_min
+        assert np.linalg.norm(host(ud) - exact) <= 1.01 * bound + 1e-12 * np.linalg.norm(exact)
+        # the sixth-order discrete solution is far closer to u* than the fourth-order one
+        assert np.abs(exact - ustar).max() < 1e-9 * np.abs(ustar).max()
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17")])
 def test_red_black_tail_variants_agree(dim, n, tail, monkeypatch):
     """Red-black smoothing inside and outside the LDS-resident tail: same cycles."""
