@@ -216,7 +216,8 @@ __global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const 
     if (inside) acc += (double)r * (double)r;
     if (own) {
       const size_t id = ((size_t)z * n + y) * n + x;
-      if (MODE == kSweep) out[id] = (TO)(inside ? uc + colour_om(op, x + y + z) * r : T(0));
+      if (MODE == kSweep || MODE == kSweepRB)
+        out[id] = (TO)(inside ? uc + (MODE == kSweepRB ? colour_om(op, x + y + z) : op.om_d) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     }
     head = (head + 1) % W;
@@ -387,7 +388,8 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
       // value there, 0; a step past this block's planes stores the value the owning
       // block stores too (same inputs, same arithmetic).
       const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep) out[id] = (TO)(inside ? uc + colour_om(kop, x + y + z) * r : T(0));
+      if (MODE == kSweep || MODE == kSweepRB)
+        out[id] = (TO)(inside ? uc + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     };
     for (int z = z0; z < z1; z += kZR)
@@ -567,7 +569,8 @@ __global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
       if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
       // every lane stores (clamped address; see the cross sweep)
       const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep) out[id] = (TO)(inside ? uz + colour_om(kop, x + y + z) * r : T(0));
+      if (MODE == kSweep || MODE == kSweepRB)
+        out[id] = (TO)(inside ? uz + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     };
     for (int z = z0; z < z1; z += 8)
@@ -1175,6 +1178,7 @@ bool wide_tiles(int n, const char *var) {
 template <typename T, typename TO, int XW>
 const void *xsweep3d_fn(int mode, bool has_u) {
   if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW>;
+  if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW>;
   if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW>;
   return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW>;
 }
@@ -1182,6 +1186,7 @@ const void *xsweep3d_fn(int mode, bool has_u) {
 template <typename T, typename TO>
 const void *gsweep3d_fn(int mode) {
   if (mode == kSweep) return (const void *)k_gsweep3d<T, TO, kSweep, 64>;
+  if (mode == kSweepRB) return (const void *)k_gsweep3d<T, TO, kSweepRB, 64>;
   if (mode == kResidual) return (const void *)k_gsweep3d<T, TO, kResidual, 64>;
   return (const void *)k_gsweep3d<T, TO, kNormOnly, 64>;
 }
@@ -1198,6 +1203,7 @@ const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw) {
   if (cross) return xw == 64 ? xsweep3d_fn<T, TO, 64>(mode, has_u) : xsweep3d_fn<T, TO, 32>(mode, has_u);
   if (gsweep_rings()) return gsweep3d_fn<T, TO>(mode);
   if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
+  if (mode == kSweepRB) return (const void *)k_sweep3d<T, TO, kSweepRB, 3>;
   if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
   return (const void *)k_sweep3d<T, TO, kNormOnly, 3>;
 }
@@ -1227,6 +1233,10 @@ template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s, int colour) {
+  if (colour != 0) {  // one colour of a red-black sweep: the kSweepRB instances
+    if (mode != kSweep || !std::is_same<T, TO>::value) return hipErrorInvalidValue;
+    mode = kSweepRB;
+  }
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
   // operator (it uses om_d only)
   const bool xpath = op.cross || u == nullptr, gpath = !xpath && gsweep_rings();
@@ -1242,6 +1252,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   if (gpath) {
 #define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
     if (mode == kSweep) MG_G3(kSweep);
+    else if (mode == kSweepRB) MG_G3(kSweepRB);
     else if (mode == kResidual) MG_G3(kResidual);
     else MG_G3(kNormOnly);
 #undef MG_G3
@@ -1255,10 +1266,12 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
     if (xw == 64) {
       if (mode == kSweep) { MG_X3(kSweep, 64) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64) }
       else if (mode == kResidual) { MG_X3(kResidual, 64) }
       else { MG_X3(kNormOnly, 64) }
     } else {
       if (mode == kSweep) { MG_X3(kSweep, 32) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 32) }
       else if (mode == kResidual) { MG_X3(kResidual, 32) }
       else { MG_X3(kNormOnly, 32) }
     }
@@ -1268,6 +1281,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 #define MG_S3(MODE) \
   hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, 3>), grid, dim3(256), (sweep_smem<T, 3>()), s, f, u, out, n, zc, k, partials, done)
   if (mode == kSweep) MG_S3(kSweep);
+  else if (mode == kSweepRB) MG_S3(kSweepRB);
   else if (mode == kResidual) MG_S3(kResidual);
   else MG_S3(kNormOnly);
 #undef MG_S3
@@ -1357,9 +1371,11 @@ hipError_t prepare_3d() {
 #define MG_P(K, B)                                                                         \
   if (e == hipSuccess) e = hipFuncSetAttribute((const void *)K, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B));
   MG_P((k_sweep3d<double, double, kSweep, 3>), (sweep_smem<double, 3>()));
+  MG_P((k_sweep3d<double, double, kSweepRB, 3>), (sweep_smem<double, 3>()));
   MG_P((k_sweep3d<double, double, kResidual, 3>), (sweep_smem<double, 3>()));
   MG_P((k_sweep3d<double, double, kNormOnly, 3>), (sweep_smem<double, 3>()));
   MG_P((k_sweep3d<float, float, kSweep, 3>), (sweep_smem<float, 3>()));
+  MG_P((k_sweep3d<float, float, kSweepRB, 3>), (sweep_smem<float, 3>()));
   MG_P((k_sweep3d<float, float, kResidual, 3>), (sweep_smem<float, 3>()));
   MG_P((k_sweep3d<float, float, kNormOnly, 3>), (sweep_smem<float, 3>()));
   MG_P((k_resid_restrict3d<double, 3>), (rr_smem<double, 3>()));

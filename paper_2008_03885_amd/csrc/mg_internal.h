@@ -66,7 +66,8 @@ struct DevState {
   double hist[kMaxHistory];
 };
 
-enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2 };
+// kSweepRB: a sweep relaxing one colour (KOp::colour), the 3D kernels' red-black step.
+enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2, kSweepRB = 3 };
 
 // Workgroups are dealt to the XCDs (8 on MI355X, each with its own L2) round-robin in
 // linear dispatch order.  xcd_logical maps a linear id to a logical block id such that
