@@ -73,12 +73,20 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // L u at the centre of window w (rows c-R..c+R of this lane's column); x neighbours
 // through the wave's LDS rows (ra, rb point at this lane's slot).  Cross operator
-// (R = 2): difference form with weights w1, w2.  Separable operator (R = 3):
-// L = a_x b_y + b_x a_y with the a factors in difference form.
-template <typename T, int R>
+// (R = 2, or R = 3 with XC): difference form with weights w1, w2 (, w3).  Separable
+// operator (R = 3): L = a_x b_y + b_x a_y with the a factors in difference form.
+template <typename T, int R, bool XC = false>
 __device__ __forceinline__ T apply_op(const T (&w)[2 * R + 1], const KOp<T> &op, T *ra, T *rb) {
   const T c = w[R];
-  if constexpr (R == 2) {
+  if constexpr (XC) {
+    ra[0] = c;
+    wave_sync();
+    const T xm1 = ra[-1], xp1 = ra[1], xm2 = ra[-2], xp2 = ra[2], xm3 = ra[-3], xp3 = ra[3];
+    wave_sync();
+    return op.w1 * (((c - xm1) + (c - xp1)) + ((c - w[R - 1]) + (c - w[R + 1]))) +
+           op.w2 * (((c - xm2) + (c - xp2)) + ((c - w[R - 2]) + (c - w[R + 2]))) +
+           op.w3 * (((c - xm3) + (c - xp3)) + ((c - w[R - 3]) + (c - w[R + 3])));
+  } else if constexpr (R == 2) {
     ra[0] = c;
     wave_sync();
     const T xm1 = ra[-1], xp1 = ra[1], xm2 = ra[-2], xp2 = ra[2];
@@ -186,7 +194,8 @@ struct PreArgs {
 // x neighbours go through LDS in one batched exchange and their arithmetic overlaps.
 // The full weighting of the defect lags one more row for the same reason.
 // RBS: the stages are red-black partial steps (stage_om), else omega-Jacobi sweeps.
-template <typename T, int R, int NU, int MODE, bool HAS_U, bool RBS = false>
+// XC: the R = 3 operator is a cross (sixth order), exchanged and applied as one.
+template <typename T, int R, int NU, int MODE, bool HAS_U, bool RBS = false, bool XC = false>
 __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   constexpr bool RESTRICT = (MODE & kRestrict) != 0;
   constexpr bool WRITE_R = (MODE & kWriteR) != 0;
@@ -198,7 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
   constexpr int W = 2 * R + 1;
   constexpr int LAG = R + 1;                       // rows between consecutive stages
   constexpr int FQ = (K - 1) * LAG + 1;            // f rows kept (stage s reads row t-(s-1)LAG)
-  constexpr int XV = R == 2 ? 1 : 2;               // values one stage exchanges across lanes
+  constexpr bool CROSS = R == 2 || XC;
+  constexpr int XV = CROSS ? 1 : 2;                // values one stage exchanges across lanes
   constexpr int NX = K * XV + (RESTRICT ? 1 : 0);  // LDS rows per wave
   constexpr int LR = FQ <= 8 ? 8 : 16;            // ring length = row steps per loop turn
   static_assert(K >= 1, "the pre kernel runs at least one stencil stage");
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
       T ya_[K], yb_[K];
 #pragma unroll
       for (int s = 0; s < K; ++s) {
-        if constexpr (R == 2) {
+        if constexpr (CROSS) {
           ya_[s] = w[s][ring<LR>(P - s * LAG)];
           lds0[s * kRowLen] = ya_[s];
         } else {
@@ -346,6 +356,17 @@ __global__ __launch_bounds__(kBlock) void k_pre2d(PreArgs<T> a) {
           const T xm1 = row[-1], xp1 = row[1], xm2 = row[-2], xp2 = row[2];
           lu[s] = op.w1 * (((c - xm1) + (c - xp1)) + ((c - ym1) + (c - yp1))) +
                   op.w2 * (((c - xm2) + (c - xp2)) + ((c - ym2) + (c - yp2)));
+        } else if constexpr (XC) {
+          const T *row = lds0 + s * kRowLen;
+          const T c = ya_[s];
+          T v = T(0);
+#pragma unroll
+          for (int k = 1; k <= 3; ++k) {
+            const T ym = w[s][ring<LR>(P - s * LAG - k)], yp = w[s][ring<LR>(P - s * LAG + k)];
+            const T wk = k == 1 ? op.w1 : k == 2 ? op.w2 : op.w3;
+            v += wk * (((c - row[-k]) + (c - row[k])) + ((c - ym) + (c - yp)));
+          }
+          lu[s] = v;
         } else {
           const T *ra = lds0 + (2 * s) * kRowLen;
           const T *rb = lds0 + (2 * s + 1) * kRowLen;
@@ -436,7 +457,7 @@ struct PostArgs {
   const int *done;
 };
 
-template <typename T, int R, int NU2, int P, bool RBS = false>
+template <typename T, int R, int NU2, int P, bool RBS = false, bool XC = false>
 __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
   constexpr int H = NU2 * R;
   constexpr int S = kWave - 2 * H;
@@ -541,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_post2d(PostArgs<T> a) {
         for (int s = 1; s <= NU2; ++s) {
           // stage s: sweep at row t - s R, the centre of w[s-1]
           const T fv = fw[FQ - 1 - (s - 1) * R];
-          const T r = fv - apply_op<T, R>(w[s - 1], op, ra, rb);
+          const T r = fv - apply_op<T, R, XC>(w[s - 1], op, ra, rb);
           push(w[s], w[s - 1][R] + (RBS ? stage_om(op, s, x + t - s * R) : op.om_d) * r);
         }
         out = w[NU2][W - 1];
@@ -570,6 +591,7 @@ KOp<T> to_kop(const LevelOp &op, double omega) {
   }
   k.w1 = (T)(-op.a[2]);
   k.w2 = (T)(-op.a[1]);
+  k.w3 = (T)(-op.a[0]);
   k.om_d = (T)(omega / op.diag);
   k.colour = 0;
   return k;
@@ -588,53 +610,78 @@ int pre_bands(const void *fn, int n, bool restrict_mode, dim3 *grid) {
   return c;
 }
 
-template <typename T, int R, int NU, int MODE, bool RBS = false>
+template <typename T, int R, int NU, int MODE, bool RBS = false, bool XC = false>
 hipError_t pre_dispatch(PreArgs<T> args, dim3 grid, bool restrict_mode, int *nparts, hipStream_t s) {
-  const void *fn = args.u != nullptr ? (const void *)k_pre2d<T, R, NU, MODE, true, RBS>
-                                     : (const void *)k_pre2d<T, R, NU, MODE, false, RBS>;
+  const void *fn = args.u != nullptr ? (const void *)k_pre2d<T, R, NU, MODE, true, RBS, XC>
+                                     : (const void *)k_pre2d<T, R, NU, MODE, false, RBS, XC>;
   args.chunk = pre_bands(fn, args.n, restrict_mode, &grid);
   if (nparts) *nparts = grid.x * grid.y;
   if (args.u != nullptr)
-    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true, RBS>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, true, RBS, XC>), grid, dim3(kBlock), 0, s, args);
   else
-    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, false, RBS>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_pre2d<T, R, NU, MODE, false, RBS, XC>), grid, dim3(kBlock), 0, s, args);
   return hipGetLastError();
 }
 
-template <typename T, int R, int MODE>
+template <typename T, int R, int MODE, bool XC>
 hipError_t pre_nu(int nu, const PreArgs<T> &args, dim3 grid, int *nparts, hipStream_t s) {
   constexpr bool RM = (MODE & kRestrict) != 0;
   constexpr bool RES = (MODE & (kRestrict | kWriteR)) != 0;
   switch (nu) {
     case 0:
-      if constexpr (RES) return pre_dispatch<T, R, 0, MODE>(args, grid, RM, nparts, s);
+      if constexpr (RES) return pre_dispatch<T, R, 0, MODE, false, XC>(args, grid, RM, nparts, s);
       return hipErrorInvalidValue;  // nothing to compute
-    case 1: return pre_dispatch<T, R, 1, MODE>(args, grid, RM, nparts, s);
-    case 2: return pre_dispatch<T, R, 2, MODE>(args, grid, RM, nparts, s);
-    case 3: return pre_dispatch<T, R, 3, MODE>(args, grid, RM, nparts, s);
+    case 1: return pre_dispatch<T, R, 1, MODE, false, XC>(args, grid, RM, nparts, s);
+    case 2: return pre_dispatch<T, R, 2, MODE, false, XC>(args, grid, RM, nparts, s);
+    case 3: return pre_dispatch<T, R, 3, MODE, false, XC>(args, grid, RM, nparts, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, int R, int NU2, bool RBS = false>
+// The pre passes of one operator shape: R = 2 cross, R = 3 separable or (XC) cross.
+template <typename T, int R, bool XC>
+hipError_t pre_shape(int nu, int mode, bool rb, PreArgs<T> &args, dim3 grid, int *nparts, hipStream_t s) {
+  constexpr int WR = kWriteU | kRestrict;
+  if (rb) {
+    // red-black passes: two stages (one sweep), or none before the defect
+    args.op.colour = kColourRB;
+    if (mode == WR && nu == 0) return pre_dispatch<T, R, 0, WR, false, XC>(args, grid, true, nparts, s);
+    if (mode == WR && nu == 2) return pre_dispatch<T, R, 2, WR, true, XC>(args, grid, true, nparts, s);
+    if (mode == kWriteU && nu == 2) return pre_dispatch<T, R, 2, kWriteU, true, XC>(args, grid, false, nparts, s);
+    return hipErrorInvalidValue;
+  }
+  if (mode == WR) return pre_nu<T, R, WR, XC>(nu, args, grid, nparts, s);
+  if (mode == kWriteU && nu == 1) return pre_dispatch<T, R, 1, kWriteU, false, XC>(args, grid, false, nparts, s);
+  if (mode == kWriteR && nu == 0) return pre_dispatch<T, R, 0, kWriteR, false, XC>(args, grid, false, nparts, s);
+  if (mode == kRestrict && nu == 0) return pre_dispatch<T, R, 0, kRestrict, false, XC>(args, grid, true, nparts, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int R, int NU2, bool RBS = false, bool XC = false>
 hipError_t post_dispatch(int prolong, PostArgs<T> args, dim3 grid, hipStream_t s) {
-  const void *fn = prolong == 3 ? (const void *)k_post2d<T, R, NU2, 3, RBS>
-                                : (const void *)k_post2d<T, R, NU2, 1, RBS>;
+  const void *fn = prolong == 3 ? (const void *)k_post2d<T, R, NU2, 3, RBS, XC>
+                                : (const void *)k_post2d<T, R, NU2, 1, RBS, XC>;
   args.chunk = band_rows(args.n, grid.x, resident_blocks(fn, kBlock, 0), kMinFineRows);
   grid.y = cdiv(args.n, args.chunk);
   if (prolong == 3)
-    hipLaunchKernelGGL((k_post2d<T, R, NU2, 3, RBS>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 3, RBS, XC>), grid, dim3(kBlock), 0, s, args);
   else
-    hipLaunchKernelGGL((k_post2d<T, R, NU2, 1, RBS>), grid, dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL((k_post2d<T, R, NU2, 1, RBS, XC>), grid, dim3(kBlock), 0, s, args);
   return hipGetLastError();
 }
 
-template <typename T, int R>
-hipError_t post_nu(int nu2, int prolong, const PostArgs<T> &args, dim3 grid, hipStream_t s) {
+template <typename T, int R, bool XC>
+hipError_t post_shape(int nu2, int prolong, bool rb, PostArgs<T> &args, dim3 grid, hipStream_t s) {
+  if (rb) {
+    args.op.colour = kColourRB;
+    if (nu2 == 0) return post_dispatch<T, R, 0, false, XC>(prolong, args, grid, s);
+    if (nu2 == 2) return post_dispatch<T, R, 2, true, XC>(prolong, args, grid, s);
+    return hipErrorInvalidValue;
+  }
   switch (nu2) {
-    case 0: return post_dispatch<T, R, 0>(prolong, args, grid, s);
-    case 1: return post_dispatch<T, R, 1>(prolong, args, grid, s);
-    case 2: return post_dispatch<T, R, 2>(prolong, args, grid, s);
+    case 0: return post_dispatch<T, R, 0, false, XC>(prolong, args, grid, s);
+    case 1: return post_dispatch<T, R, 1, false, XC>(prolong, args, grid, s);
+    case 2: return post_dispatch<T, R, 2, false, XC>(prolong, args, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -674,29 +721,9 @@ hipError_t launch_pre2d(const LevelOp &op, double omega, int nu, int mode, const
   if (S <= 0 || nu < 0 || nu > 3) return hipErrorInvalidValue;
   PreArgs<T> args{f, u, uout, rout, fc, n, 0, to_kop<T>(op, omega), partials, done};
   const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
-  if (rb) {
-    // red-black passes: two stages (one sweep), or none before the defect
-    constexpr int WR = kWriteU | kRestrict;
-    args.op.colour = kColourRB;
-    if (R == 2) {
-      if (mode == WR && nu == 0) return pre_dispatch<T, 2, 0, WR>(args, grid, true, nparts, s);
-      if (mode == WR && nu == 2) return pre_dispatch<T, 2, 2, WR, true>(args, grid, true, nparts, s);
-      if (mode == kWriteU && nu == 2) return pre_dispatch<T, 2, 2, kWriteU, true>(args, grid, false, nparts, s);
-    } else {
-      if (mode == WR && nu == 0) return pre_dispatch<T, 3, 0, WR>(args, grid, true, nparts, s);
-      if (mode == WR && nu == 2) return pre_dispatch<T, 3, 2, WR, true>(args, grid, true, nparts, s);
-      if (mode == kWriteU && nu == 2) return pre_dispatch<T, 3, 2, kWriteU, true>(args, grid, false, nparts, s);
-    }
-    return hipErrorInvalidValue;
-  }
-#define MG_PRE(RR)                                                                         \
-  if (mode == (kWriteU | kRestrict)) return pre_nu<T, RR, kWriteU | kRestrict>(nu, args, grid, nparts, s); \
-  if (mode == kWriteU && nu == 1) return pre_dispatch<T, RR, 1, kWriteU>(args, grid, false, nparts, s); \
-  if (mode == kWriteR && nu == 0) return pre_dispatch<T, RR, 0, kWriteR>(args, grid, false, nparts, s); \
-  if (mode == kRestrict && nu == 0) return pre_dispatch<T, RR, 0, kRestrict>(args, grid, true, nparts, s); \
-  return hipErrorInvalidValue;
-  if (R == 2) { MG_PRE(2) } else { MG_PRE(3) }
-#undef MG_PRE
+  if (R == 2) return pre_shape<T, 2, false>(nu, mode, rb, args, grid, nparts, s);
+  if (op.cross3) return pre_shape<T, 3, true>(nu, mode, rb, args, grid, nparts, s);
+  return pre_shape<T, 3, false>(nu, mode, rb, args, grid, nparts, s);
 }
 
 template <typename T>
@@ -711,14 +738,9 @@ hipError_t launch_post2d(const LevelOp &op, double omega, int nu2, int prolong, 
   const int S = kWave - 2 * H;
   PostArgs<T> args{v, uin, f, uout, n, 0, to_kop<T>(op, omega), done};
   const dim3 grid(cdiv(cdiv(n, S), kWavesPerBlock), 1, slots);
-  if (rb) {
-    args.op.colour = kColourRB;
-    if (nu2 == 0) return R == 2 ? post_dispatch<T, 2, 0>(prolong, args, grid, s) : post_dispatch<T, 3, 0>(prolong, args, grid, s);
-    if (nu2 == 2) return R == 2 ? post_dispatch<T, 2, 2, true>(prolong, args, grid, s) : post_dispatch<T, 3, 2, true>(prolong, args, grid, s);
-    return hipErrorInvalidValue;
-  }
-  if (R == 2) return post_nu<T, 2>(nu2, prolong, args, grid, s);
-  return post_nu<T, 3>(nu2, prolong, args, grid, s);
+  if (R == 2) return post_shape<T, 2, false>(nu2, prolong, rb, args, grid, s);
+  if (op.cross3) return post_shape<T, 3, true>(nu2, prolong, rb, args, grid, s);
+  return post_shape<T, 3, false>(nu2, prolong, rb, args, grid, s);
 }
 
 template hipError_t launch_pre2d<double>(const LevelOp &, double, int, int, const double *,

@@ -1154,6 +1154,7 @@ KOp<T> to_kop3(const LevelOp &op, double omega) {
   }
   k.w1 = (T)(-op.a[2]);
   k.w2 = (T)(-op.a[1]);
+  k.w3 = (T)(-op.a[0]);
   k.om_d = (T)(omega / op.diag);
   k.colour = 0;
   return k;

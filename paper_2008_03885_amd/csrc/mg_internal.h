@@ -22,7 +22,9 @@ struct LevelOp {
   double a[7];
   double b[7];
   bool cross;
-  double diag;  // centre coefficient of L
+  double diag;          // centre coefficient of L
+  bool cross3 = false;  // b is the unit stencil and a has radius 3 (sixth order): the fused
+                        // 2D kernels apply it as a radius-3 cross, the others as separable
 };
 
 // Coefficients as seen by a kernel, in its arithmetic type.
@@ -31,6 +33,7 @@ struct KOp {
   T a[7];
   T b[7];
   T w1, w2;   // cross: weights of (u_0 - u_{+-1}) and (u_0 - u_{+-2})
+  T w3;       // radius-3 cross: weight of (u_0 - u_{+-3})
   T om_d;     // omega / diag
   int colour; // sweeps: 0 relax every interior point; 1 only odd x+y(+z), 2 only even
 };

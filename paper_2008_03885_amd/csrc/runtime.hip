@@ -110,6 +110,7 @@ LevelOp rediscretized(int order, int dim, double h) {
   }
   op.b[3] = 1.0;
   op.cross = order != 6;
+  op.cross3 = order == 6;
   op.diag = dim * op.a[3];
   return op;
 }
