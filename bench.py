@@ -46,11 +46,14 @@ WORKLOADS = {
 # dispatch, scaled by the counters of a plain copy of known size), valid only for the
 # kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    # 4097^2 level 0, two sweeps + defect + full weighting: 172,207.5 KiB fetched x 2.0000
-    # + 168,960.5 KiB written x 1.0000 (a 2 GiB copy reads 1,048,595 KiB / writes 2,097,152)
-    "k_pre2d/f64/fused2d.hip/4097": {"bytes": 525690258, "source": "847dc90aeecebc30"},
-    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,525.8 KiB x 1.9999 + 590,408.4 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2069936876, "source": "e6f4e72e0b656061"},
+    # 4097^2 level 0, two sweeps + defect + full weighting: 172,251.9 KiB fetched x 2.0000
+    # + 169,196.7 KiB written x 1.0000 (a 2 GiB copy reads 1,048,595 KiB / writes 2,097,152)
+    "k_pre2d/f64/fused2d.hip/4097": {"bytes": 526022929, "source": "80797142e6561bc3"},
+    # the same pass with red-black smoothing (one red-black sweep + defect + full weighting):
+    # 156,850.3 KiB x 2.0000 + 168,329.4 KiB x 1.0000
+    "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
+    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 716,032.9 KiB x 2.0000 + 591,665.1 KiB x 1.0000
+    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2072270851, "source": "0090bcc0369d0cb8"},
 }
 
 
