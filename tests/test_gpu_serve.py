@@ -101,6 +101,27 @@ def test_results_identical_alone_and_in_the_mix():
     assert np.array_equal(a, b) and np.array_equal(a, d)
 
 
+@pytest.mark.parametrize("precision", [mg.MG_PREC_FP64, mg.MG_PREC_MIXED])
+def test_red_black_requests_equal_standalone_solves(precision):
+    """Red-black smoothing in batched slots (fused passes with the third sweep target,
+    the LDS tail) gives each request its standalone result bit for bit."""
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(10):
+        n = int(rng.choice([65, 129, 257, 1025]))
+        reqs.append((i, n, _rhs(n, inputs.SEED_BASE + 1200 + i)))
+    over = dict(smoother=mg.MG_SMOOTH_RBJ, precision=precision, max_cycles=30)
+    out, stats = _serve(reqs, **over)
+    assert stats["completed"] == len(reqs)
+    for tag, n, f in reqs:
+        ref, st, hist = _solo(n, f, **over)
+        u, c = out[tag]
+        assert c.status == mg.MG_OK and st == mg.MG_OK, tag
+        assert np.array_equal(u, ref), tag
+        assert c.result.hist() == hist, tag
+        assert c.result.rel_residual <= 1e-10
+
+
 def test_admission_by_footprint():
     """A budget that holds one slot of 513^2: three such requests run one after another,
     and a later 257^2 request gets memory by releasing the idle 513 batch."""
