@@ -162,7 +162,8 @@ mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, cons
 /* One partial step of red-black smoothing (section 3.1 eq. S_rb): the points of one colour
  * take the omega-Jacobi step of mg_kernel_smooth, every other point copies u_in.
  * colour 1 = red (odd index sum i+j(+k)), 2 = black (even), 0 = every point.  A red-black
- * sweep is colour 1 into a second array, then colour 2 back.  u_in == NULL means
+ * sweep is colour 1 into a second array, then colour 2 back; colour 3 runs the whole
+ * red-black sweep in one fused pass (2D only, else MG_EINVAL).  u_in == NULL means
  * u_in = 0.  u_out != u_in. */
 mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, const void *f,
                                   const void *u_in, void *u_out);

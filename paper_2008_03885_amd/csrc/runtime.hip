@@ -1142,7 +1142,21 @@ mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, 
   mg_status st = fp32 ? check_level<float>(h, level, false) : check_level<double>(h, level, false);
   if (st != MG_OK) return st;
   if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
-  if (colour < 0 || colour > 2) return fail(MG_EINVAL, "colour must be 0, 1 or 2");
+  if (colour < 0 || colour > 3) return fail(MG_EINVAL, "colour must be 0, 1, 2 or 3");
+  if (colour == 3) {  // a whole red-black sweep in one fused pass (the cycle's sweep-only pass)
+    if (h->dim != 2) return fail(MG_EINVAL, "one-pass red-black sweeps are 2D only");
+    const LevelOp &op = h->ops[level];
+    const int n = h->ns[level];
+    if (fp32)
+      MG_HIP(mgk::launch_pre2d<float>(op, h->omega, 2, mgk::kPreWriteU, (const float *)f, (const float *)u_in,
+                                      (float *)u_out, nullptr, nullptr, n, nullptr, nullptr, nullptr,
+                                      h->stream, 1, true));
+    else
+      MG_HIP(mgk::launch_pre2d<double>(op, h->omega, 2, mgk::kPreWriteU, (const double *)f,
+                                       (const double *)u_in, (double *)u_out, nullptr, nullptr, n, nullptr,
+                                       nullptr, nullptr, h->stream, 1, true));
+    return MG_OK;
+  }
   if (fp32)
     MG_HIP((mgk::launch_sweep<float, float>(h->dim, mgk::kSweep, h->ops[level], h->omega,
                                             (const float *)f, (const float *)u_in, (float *)u_out,

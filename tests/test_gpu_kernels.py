@@ -447,9 +447,10 @@ def test_3d_galerkin_sweep_kernels(n, level, old, fp32, monkeypatch):
 # Galerkin kernels).  Level sides cover single blocks, ragged blocks and 3D plane bands.
 CASES_RB = [
     (2, 17, 0, 0, "0"), (2, 257, 0, 0, "0"), (2, 1025, 0, 1, "0"), (2, 257, 1, 1, "0"),
-    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"),
+    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"), (2, 1025, 0, 0, "0"),
     (3, 17, 0, 0, "0"), (3, 65, 0, 0, "0"), (3, 129, 0, 0, "0"), (3, 65, 1, 1, "0"),
     (3, 129, 1, 1, "0"), (3, 65, 1, 1, "1"), (3, 65, 3, 2, "0"), (3, 33, 2, 1, "0"),
+    (3, 9, 0, 0, "0"), (3, 257, 2, 1, "0"),
 ]
 
 
@@ -483,8 +484,22 @@ def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
             mg.mg_kernel_smooth_colour(H.h, level, fp32, colour, fd.data_ptr(), None, out0.data_ptr())
             ref0 = oracle.jacobi_colour(s, H.omega, colour, f, np.zeros_like(u))
             assert_close(host(out0), ref0, tol, "colour %d, zero guess" % colour)
+        # a whole red-black sweep in one fused pass (2D only)
+        ref = oracle.jacobi_colour(s, H.omega, 2, f, oracle.jacobi_colour(s, H.omega, 1, f, u))
+        out = dev(np.full_like(u, np.nan), fp32)
+        if dim == 3:
+            with pytest.raises(mg.MGError):
+                mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), ud.data_ptr(),
+                                           out.data_ptr())
+        else:
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+            assert_close(host(out), ref, 2 * tol, "red-black sweep")
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), None, out.data_ptr())
+            ref0 = oracle.jacobi_colour(s, H.omega, 2, f,
+                                        oracle.jacobi_colour(s, H.omega, 1, f, np.zeros_like(u)))
+            assert_close(host(out), ref0, 2 * tol, "red-black sweep, zero guess")
         with pytest.raises(mg.MGError):
-            mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), ud.data_ptr(),
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, 4, fd.data_ptr(), ud.data_ptr(),
                                        out.data_ptr())
     finally:
         H.close()

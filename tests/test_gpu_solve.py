@@ -58,6 +58,7 @@ RB_CASES = [
     (2, 129, 0, 3, 2, 1, 1), (2, 129, 1, 3, 1, 1, 2), (2, 257, 3, 3, 2, 1, 1), (2, 65, 0, 1, 0, 2, 1),
     (2, 1025, 0, 3, 2, 1, 1), (2, 257, 2, 3, 1, 0, 2),
     (3, 33, 0, 3, 2, 1, 1), (3, 65, 1, 3, 2, 2, 2), (3, 65, 0, 3, 1, 1, 1), (3, 65, 3, 1, 2, 1, 1),
+    (3, 129, 0, 3, 2, 1, 1), (3, 65, 0, 1, 0, 2, 2),
 ]
 
 
