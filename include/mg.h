@@ -163,8 +163,8 @@ mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, cons
  * take the omega-Jacobi step of mg_kernel_smooth, every other point copies u_in.
  * colour 1 = red (odd index sum i+j(+k)), 2 = black (even), 0 = every point.  A red-black
  * sweep is colour 1 into a second array, then colour 2 back; colour 3 runs the whole
- * red-black sweep in one fused pass (2D only, else MG_EINVAL).  u_in == NULL means
- * u_in = 0.  u_out != u_in. */
+ * red-black sweep in one pass (2D: every level; 3D: levels with the cross operator, else
+ * MG_EINVAL).  u_in == NULL means u_in = 0.  u_out != u_in. */
 mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, const void *f,
                                   const void *u_in, void *u_out);
 

@@ -406,6 +406,145 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   }
 }
 
+// --------------------------------------- red-black sweep of the cross, one pass ----
+// One red-black sweep of the radius-2 cross (section 3.1 eq. S_rb) in one pass: the red
+// partial step (odd x+y+z) on plane z, the black one two planes behind.  The black step
+// of an XW x YW tile needs red results two columns around it, so the block has one thread
+// per column of the tile plus a two-column frame, (XW+4) x (YW+4) threads (60 x 8: twelve
+// whole wavefronts); all of them take
+// the red step, the tile's threads the black step.  Per plane, u of the frame region and
+// a further two-column halo goes through LDS (double-buffered) for the red step; the red
+// results go through an LDS ring of four planes for the black step's in-plane
+// neighbours; z neighbours of u, f and the red results stay in register rings (same
+// register-ring rules as the cross sweep).  One barrier per plane.  Every value is the
+// odd extension across the Dirichlet boundary (reflection keeps a point's colour), so
+// frame columns outside the grid hold the odd extension of the red results.
+template <typename T, bool HAS_U, int XW, int YW>
+__global__ __launch_bounds__((XW + 4) * (YW + 4)) void k_rbxsweep3d(const T *__restrict__ f, const T *__restrict__ u,
+                                                                     T *__restrict__ out, int n, int zchunk,
+                                                                     KOp<T> op, double *__restrict__ partials,
+                                                                     const int *__restrict__ done) {
+  constexpr int R = 2, EX = XW + 2 * R, EY = YW + 2 * R, NT = EX * EY;
+  constexpr int PX = EX + 2 * R, PY = EY + 2 * R, PS = PX * PY;
+  constexpr int NH = PS - NT;  // halo cells of a plane
+  static_assert(NH <= NT, "one halo cell per thread");
+  static_assert(NT % 64 == 0, "whole wavefronts (block_sum)");
+  __shared__ T plane[2][PS];
+  __shared__ T red[4][NT];
+  if (stopped(done)) return;
+  const Block3 blk = block3();
+  const int x0 = blk.x * XW, y0 = blk.y * YW;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
+  const int tid = threadIdx.x;
+  const int ex = tid % EX, ey = tid / EX;
+  const int x = x0 - R + ex, y = y0 - R + ey;
+  // the tile's columns (black step and output); clamped neighbour slots for the others
+  const bool tile = ex >= R && ex < XW + R && ey >= R && ey < YW + R;
+  const bool own = tile && x <= n - 1 && y <= n - 1;
+  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
+  const int qm1 = max(tid - 1, 0), qp1 = min(tid + 1, NT - 1), qm2 = max(tid - 2, 0), qp2 = min(tid + 2, NT - 1);
+  const int qmy = max(tid - EX, 0), qpy = min(tid + EX, NT - 1), qmy2 = max(tid - 2 * EX, 0), qpy2 = min(tid + 2 * EX, NT - 1);
+  Col3<T> cu, ch;
+  cu.init(x, y, n);
+  int hx = 0, hy = 0;
+  const bool has_halo = tid < NH;
+  {
+    const int h = tid;
+    if (h < 2 * PX) {
+      hy = h / PX;
+      hx = h % PX;
+    } else if (h < 4 * PX) {
+      hy = PY - R + (h - 2 * PX) / PX;
+      hx = (h - 2 * PX) % PX;
+    } else {
+      const int hh = h - 4 * PX;
+      hy = R + hh / (2 * R);
+      const int c = hh % (2 * R);
+      hx = c < R ? c : PX - 2 * R + c;
+    }
+  }
+  if (has_halo)
+    ch.init(x - ex - R + hx, y - ey - R + hy, n);
+  else
+    ch = cu;
+  const int pown = (ey + R) * PX + ex + R, phal = hy * PX + hx;
+  const T *up = HAS_U ? u : f;
+  // red steps on planes z0-2 .. z1+1, black steps two planes behind
+  const int zs = z0 - 2, zlast = zs + round_up8(z1 - z0 + 4) - 1;
+  const bool fast = zs - R > 0 && zlast + 6 < n - 1;
+  double acc = 0.0;
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
+    T ur[kZR], fr[kZR], hr[4], vr[kZR];  // u and f of this column at z-2+k; halo at z+k; red results
+#pragma unroll
+    for (int k = 0; k < kZR; ++k) {
+      ur[k] = HAS_U ? up[base(zs - 2 + k) + cu.off] : T(0);
+      fr[k] = f[base(zs - 2 + k) + cu.off];
+      vr[k] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hr[k] = HAS_U ? up[base(zs + k) + ch.off] : T(0);
+    hold_regs(ur);
+    hold_regs(fr);
+    hold_regs(hr);
+    const KOp<T> kop = op;
+    auto step = [&](const int z, auto pc) {  // red step on plane z, black step on plane z-2
+      constexpr int P = decltype(pc)::value;
+      const T m = cu.mul;
+      T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
+      T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
+      T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
+      T fb = fr[P % kZR] * (m * zm(z - 2)), fz = fr[(P + 2) % kZR] * (m * zm(z));
+      T hz = hr[P % 4] * (ch.mul * zm(z));
+      asm volatile("" : "+v"(um2), "+v"(fb), "+v"(hz));
+      __builtin_amdgcn_sched_barrier(0);
+      if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];  // the slot of plane z-2
+      fr[P % kZR] = f[base(z + 6) + cu.off];
+      if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
+      T *pl = plane[P & 1];
+      pl[pown] = uc;
+      if (has_halo) pl[phal] = hz;
+      __syncthreads();
+      // red step on plane z (every frame column), odd extension included
+      const T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
+                                     ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
+                               kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
+                                         ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
+                                         ((uc - um2) + (uc - up2)))
+                         : T(0);
+      const T r = fz - lu;
+      if (partials != nullptr && own && xin && z >= z0 && z < z1 && z > 0 && z < n - 1)
+        acc += (double)r * (double)r;
+      const T v = uc + (((x + y + z) & 1) != 0 ? kop.om_d : T(0)) * r;
+      vr[(P + 4) % kZR] = v;
+      red[(z % 4 + 4) % 4][tid] = v;
+      // black step on plane z-2 from the red results (in-plane: written two planes ago)
+      const int zb = z - 2;
+      const T *rp = red[(zb % 4 + 4) % 4];
+      const T vc = vr[(P + 2) % kZR];
+      const T lb = kop.w1 * (((vc - rp[qm1]) + (vc - rp[qp1])) + ((vc - rp[qmy]) + (vc - rp[qpy])) +
+                             ((vc - vr[(P + 1) % kZR]) + (vc - vr[(P + 3) % kZR]))) +
+                   kop.w2 * (((vc - rp[qm2]) + (vc - rp[qp2])) + ((vc - rp[qmy2]) + (vc - rp[qpy2])) +
+                             ((vc - vr[P % kZR]) + (vc - vr[(P + 4) % kZR])));
+      const bool inside = xin && zb > 0 && zb < n - 1;
+      const T w = inside ? vc + (((x + y + zb) & 1) == 0 ? kop.om_d : T(0)) * (fb - lb) : T(0);
+      if (own && zb >= z0 && zb < z1) out[((size_t)zb * n + y) * n + x] = w;
+    };
+    for (int z = zs; z <= zlast; z += kZR)
+      static_for<kZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+  if (partials != nullptr) {
+    const double tot = block_sum<NT>(acc);
+    if (tid == 0) partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
 // ------------------------------------------- separable (Galerkin) sweep, z rings ----
 // Coarse Galerkin operators are sums of three tensor products of 1D stencils of radius 3,
 // L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as
@@ -1290,6 +1429,29 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 }
 
 template <typename T>
+hipError_t launch_rbsweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
+                             double *partials, int *nparts, const int *done, hipStream_t s) {
+  if (!op.cross) return hipErrorInvalidValue;
+  // 60 x 8 tiles, 768 threads (measured at 513^3 against 28 x 16 tiles, 640 threads:
+  // 56.4 against 57.8 ms per FP64 red-black solve)
+  constexpr int xw = 60, yw = 8, nt = (xw + 4) * (yw + 4);
+  const void *fn = u != nullptr ? (const void *)k_rbxsweep3d<T, true, xw, yw> : (const void *)k_rbxsweep3d<T, false, xw, yw>;
+  const int tiles = cdiv(n, xw) * cdiv(n, yw);
+  // bands of at least 32 planes: every band takes four extra red planes
+  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, nt, 0), 32));
+  const dim3 grid(cdiv(n, xw), cdiv(n, yw), cdiv(n, zc));
+  if (nparts) *nparts = grid.x * grid.y * grid.z;
+  const KOp<T> k = to_kop3<T>(op, omega);
+#define MG_RB3(HU, W, H) hipLaunchKernelGGL((k_rbxsweep3d<T, HU, W, H>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+  if (u != nullptr)
+    MG_RB3(true, xw, yw);
+  else
+    MG_RB3(false, xw, yw);
+#undef MG_RB3
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s) {
   const int nc = (n - 1) / 2 + 1;
@@ -1394,6 +1556,10 @@ template hipError_t launch_sweep_3d<float, float>(int, const LevelOp &, double, 
 template hipError_t launch_sweep_3d<double, float>(int, const LevelOp &, double, const double *,
                                                    const double *, float *, int, double *, int *,
                                                    const int *, hipStream_t, int);
+template hipError_t launch_rbsweep_3d<double>(const LevelOp &, double, const double *, const double *,
+                                              double *, int, double *, int *, const int *, hipStream_t);
+template hipError_t launch_rbsweep_3d<float>(const LevelOp &, double, const float *, const float *,
+                                             float *, int, double *, int *, const int *, hipStream_t);
 template hipError_t launch_resid_restrict_3d<double>(const LevelOp &, const double *,
                                                      const double *, double *, int, const int *,
                                                      hipStream_t);

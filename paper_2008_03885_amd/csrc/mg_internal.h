@@ -170,6 +170,11 @@ template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
                            hipStream_t s, int colour = 0);
+// One red-black sweep (red, then black partial step) of a cross level in one pass;
+// out != u.  hipErrorInvalidValue for a non-cross operator.
+template <typename T>
+hipError_t launch_rbsweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
+                             double *partials, int *nparts, const int *done, hipStream_t s);
 template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s);

@@ -377,6 +377,17 @@ size_t entries_bytes(const mg_config *cfg, int L) {
 // also interpolates and corrects).  Passes alternate between u and t and must end in u;
 // with an odd number of passes the first one writes a third array t2.
 int rb_passes(const mg_config *cfg) { return std::max(1, cfg->nu1) + std::max(1, cfg->nu2); }
+// 3D red-black sweeps of FP64 cross levels in one pass (k_rbxsweep3d); MG_RB3_FUSED=0
+// runs the two partial steps as separate launches.  Measured at 513^3: FP64 solves 56.4
+// against 60.9 ms; FP32 cycles are faster as two launches (mixed 44.0 against 39.8 ms).
+bool rb3_fused() {
+  static const bool on = [] {
+    const char *e = std::getenv("MG_RB3_FUSED");
+    return e == nullptr || std::atoi(e) != 0;
+  }();
+  return on;
+}
+
 bool needs_t2(const mg_config *cfg) {
   return cfg->dim == 2 && cfg->smoother == MG_SMOOTH_RBJ && rb_passes(cfg) % 2 == 1;
 }
@@ -600,15 +611,21 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     if (e != hipSuccess) return e;
     zero = false;
   }
-  // a red-black sweep is two steps: the red points (colour 1), then the black ones (2)
+  // a red-black sweep is two steps: the red points (colour 1), then the black ones (2);
+  // on 3D cross levels one launch does both
   const bool rb = c->cfg.smoother == MG_SMOOTH_RBJ;
-  const int steps = rb ? 2 : 1;
+  const bool rb3 = rb && dim == 3 && op.cross && sizeof(T) == 8 && rb3_fused();
+  const int steps = rb && !rb3 ? 2 : 1;
   for (int k = 0; k < c->cfg.nu1 * steps; ++k) {
     const bool first_check = check && k == 0;
     int np = 0;
-    e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
-                                first_check ? c->partials : nullptr, &np, done, s, c->slots,
-                                rb ? 1 + k % 2 : 0);
+    if (rb3)
+      e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, zero ? nullptr : cur, other, n,
+                                    first_check ? c->partials : nullptr, &np, done, s);
+    else
+      e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
+                                  first_check ? c->partials : nullptr, &np, done, s, c->slots,
+                                  rb ? 1 + k % 2 : 0);
     if (e != hipSuccess) return e;
     if (first_check) {
       e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
@@ -640,8 +657,11 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   cur = dst;
   other = (dst == u) ? t : u;
   for (int k = 0; k < c->cfg.nu2 * steps; ++k) {
-    e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
-                                done, s, c->slots, rb ? 1 + k % 2 : 0);
+    if (rb3)
+      e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
+    else
+      e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
+                                  done, s, c->slots, rb ? 1 + k % 2 : 0);
     if (e != hipSuccess) return e;
     std::swap(cur, other);
   }
@@ -1143,10 +1163,19 @@ mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, 
   if (st != MG_OK) return st;
   if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
   if (colour < 0 || colour > 3) return fail(MG_EINVAL, "colour must be 0, 1, 2 or 3");
-  if (colour == 3) {  // a whole red-black sweep in one fused pass (the cycle's sweep-only pass)
-    if (h->dim != 2) return fail(MG_EINVAL, "one-pass red-black sweeps are 2D only");
+  if (colour == 3) {  // a whole red-black sweep in one pass
     const LevelOp &op = h->ops[level];
     const int n = h->ns[level];
+    if (h->dim == 3) {
+      if (!op.cross) return fail(MG_EINVAL, "one-pass 3D red-black sweeps need the cross operator");
+      if (fp32)
+        MG_HIP(mgk::launch_rbsweep_3d<float>(op, h->omega, (const float *)f, (const float *)u_in,
+                                             (float *)u_out, n, nullptr, nullptr, nullptr, h->stream));
+      else
+        MG_HIP(mgk::launch_rbsweep_3d<double>(op, h->omega, (const double *)f, (const double *)u_in,
+                                              (double *)u_out, n, nullptr, nullptr, nullptr, h->stream));
+      return MG_OK;
+    }
     if (fp32)
       MG_HIP(mgk::launch_pre2d<float>(op, h->omega, 2, mgk::kPreWriteU, (const float *)f, (const float *)u_in,
                                       (float *)u_out, nullptr, nullptr, n, nullptr, nullptr, nullptr,

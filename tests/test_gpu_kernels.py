@@ -455,6 +455,27 @@ CASES_RB = [
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("n", [9, 17, 65, 129, 257])
+def test_red_black_sweep_3d_one_pass(n, fp32):
+    """The one-pass 3D red-black sweep (60 x 8 tiles with a two-column frame) on grids
+    from one tile to ragged multi-tile, multi-band ones."""
+    H = Handle(3, n, smoother=1)
+    try:
+        _, s = H.level(0)
+        u = rand_grid(n, 3, 71)
+        f = rand_grid(n, 3, 72) * s[2, 2, 2]
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        out = dev(np.full_like(u, np.nan), fp32)
+        mg.mg_kernel_smooth_colour(H.h, 0, fp32, 3, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        ref = oracle.jacobi_colour(s, H.omega, 2, f, oracle.jacobi_colour(s, H.omega, 1, f, u))
+        assert_close(host(out), ref, 2 * (TOL32 if fp32 else TOL64) * _scale_u(u, f, s), "red-black sweep")
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("dim,n,coarse,level,old", CASES_RB)
 def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
     """One partial step per colour against the oracle's; the other colour is copied
@@ -484,10 +505,10 @@ def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
             mg.mg_kernel_smooth_colour(H.h, level, fp32, colour, fd.data_ptr(), None, out0.data_ptr())
             ref0 = oracle.jacobi_colour(s, H.omega, colour, f, np.zeros_like(u))
             assert_close(host(out0), ref0, tol, "colour %d, zero guess" % colour)
-        # a whole red-black sweep in one fused pass (2D only)
+        # a whole red-black sweep in one pass (3D: cross levels only)
         ref = oracle.jacobi_colour(s, H.omega, 2, f, oracle.jacobi_colour(s, H.omega, 1, f, u))
         out = dev(np.full_like(u, np.nan), fp32)
-        if dim == 3:
+        if dim == 3 and coarse in (1, 3) and level > 0:
             with pytest.raises(mg.MGError):
                 mg.mg_kernel_smooth_colour(H.h, level, fp32, 3, fd.data_ptr(), ud.data_ptr(),
                                            out.data_ptr())

@@ -62,6 +62,23 @@ RB_CASES = [
 ]
 
 
+@pytest.mark.parametrize("fused", ["0", "1"])
+@pytest.mark.parametrize("n,nu1,nu2,gamma", [(65, 2, 1, 1), (65, 1, 2, 2), (129, 2, 1, 1)])
+def test_red_black_3d_one_pass_and_two_launch_agree(fused, n, nu1, nu2, gamma, monkeypatch):
+    """3D red-black sweeps in one pass or as two partial-step launches: both equal the
+    oracle's cycles."""
+    monkeypatch.setenv("MG_RB3_FUSED", fused)
+    H = Handle(3, n, nu1=nu1, nu2=nu2, gamma=gamma, smoother=1)
+    try:
+        f = inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 3)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("dim,n,coarse,prolong,nu1,nu2,gamma", RB_CASES)
 def test_red_black_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma):
     """Cycles with red-black Jacobi smoothing (section 3.1 eq. S_rb) on every level,
