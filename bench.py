@@ -527,6 +527,18 @@ def main():
             variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
                               "rel_residual": vres.rel_residual}
 
+    # 3D 513^3: red-black Jacobi smoothing (omega 1.17), FP64 and mixed with 4 FP32 cycles
+    # per refinement step
+    if args.workload == "poisson3d-513" and not args.no_variants and not w.get("smoother", 0):
+        variants = {}
+        for prec in (0, 1):
+            vr = Run(dict(w, smoother=1, inner=4), prec, fd, stream)
+            vs, (vst, vres) = vr.timed(2, 1)
+            vr.close()
+            variants["redblack-V(%d,%d)-%s" % (w["nu1"], w["nu2"], "fp64" if prec == 0 else "mixed-inner4")] = {
+                "ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
+                "outer_steps": vres.outer_steps, "rel_residual": vres.rel_residual}
+
     compare = None
     fp64_cycles = res.cycles if w["precision"] == 0 else None
     if w["compare"]:

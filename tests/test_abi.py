@@ -107,3 +107,35 @@ def test_server_rejects_bad_configs(change):
     assert serve.lib().mg_server_submit(None, 0, 65, None, None) == mg.MG_EINVAL
     assert serve.lib().mg_server_poll(None, None, 0, 0.0) == -1
     assert serve.lib().mg_server_destroy(None) == mg.MG_OK
+
+
+def test_enum_values_match_the_binding():
+    """Every `MG_NAME = value` the header declares has the same value in mg.py."""
+    with open(os.path.join(ROOT, "include", "mg.h")) as fh:
+        text = fh.read()
+    found = dict((k, int(v)) for k, v in re.findall(r"\b(MG_[A-Z0-9_]+)\s*=\s*(\d+)", text))
+    for name in ("MG_COARSE_NG", "MG_COARSE_GALERKIN", "MG_COARSE_NG2", "MG_COARSE_G2",
+                 "MG_SMOOTH_JACOBI", "MG_SMOOTH_RBJ", "MG_PREC_FP64", "MG_PREC_MIXED", "MG_OK",
+                 "MG_EINVAL", "MG_EBUSY"):
+        assert found[name] == getattr(mg, name), name
+
+
+@pytest.mark.parametrize("nu1,nu2,extra", [(2, 1, True), (1, 1, False), (2, 2, False), (3, 0, False),
+                                          (1, 2, True), (0, 1, False)])
+def test_red_black_footprint_counts_the_third_sweep_target(nu1, nu2, extra):
+    """Fused 2D red-black cycles run max(1, nu1) + max(1, nu2) passes per level; with an odd
+    count they need a third sweep array on every level above the coarsest, and the
+    footprint says so (host arithmetic)."""
+    n, nc = 1025, 9
+    base = mg.mg_footprint_bytes(mg.make_config(dim=2, n=n, nu1=nu1, nu2=nu2, n_coarsest=nc))
+    rb = mg.mg_footprint_bytes(mg.make_config(dim=2, n=n, nu1=nu1, nu2=nu2, n_coarsest=nc,
+                                              smoother=mg.MG_SMOOTH_RBJ))
+    sides = []
+    m = n
+    while m > nc:
+        sides.append(m)
+        m = (m - 1) // 2 + 1
+    t2 = sum(s * s * 8 for s in sides)
+    passes = max(1, nu1) + max(1, nu2)
+    assert rb - base == (t2 if passes % 2 == 1 else 0)
+    assert (rb > base) == extra
