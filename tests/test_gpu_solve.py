@@ -164,6 +164,22 @@ def test_sixth_order_solve_converges_to_discrete_solution():
         H.close()
 
 
+@pytest.mark.parametrize("dim,n,nc,order,omega", [(2, 257, 5, 2, 1.0), (2, 129, 17, 2, 0.0), (3, 65, 5, 2, 0.0),
+                                                (2, 257, 33, 4, 0.0), (3, 33, 5, 4, 1.0)])
+def test_red_black_other_orders_and_coarsest_sides(dim, n, nc, order, omega):
+    """Red-black cycles with the second-order operator (red-black Gauss-Seidel for the
+    five-point stencil at omega = 1), other coarsest sides and explicit omega."""
+    H = Handle(dim, n, n_coarsest=nc, order=order, omega=omega, smoother=1)
+    try:
+        f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 4)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17")])
 def test_red_black_tail_variants_agree(dim, n, tail, monkeypatch):
     """Red-black smoothing inside and outside the LDS-resident tail: same cycles."""
