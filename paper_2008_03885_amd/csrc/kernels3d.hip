@@ -291,12 +291,15 @@ __device__ __forceinline__ T plane_mul(int z, int n) {
   return (zf > 0 && zf < n - 1) ? T(s) : T(0);
 }
 
-template <typename T, typename TO, int MODE, bool HAS_U, int XW>
+// RR = 3: the radius-3 cross of the sixth-order operator (weights w1, w2, w3), with a u
+// ring of 16 planes.
+template <typename T, typename TO, int MODE, bool HAS_U, int XW, int RR = 2>
 __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, const T *__restrict__ u,
                                                   TO *__restrict__ out, int n, int zchunk, KOp<T> op,
                                                   double *__restrict__ partials,
                                                   const int *__restrict__ done) {
-  constexpr int NT = XW * TY, R = 2, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int NT = XW * TY, R = RR, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int ZR = RR == 2 ? kZR : 16;  // u ring length = planes per loop turn
   constexpr int NH = PS - NT;  // halo cells of a plane
   static_assert(NH <= NT, "one halo cell per thread");
   __shared__ T plane[2][PS];
@@ -310,20 +313,20 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
   Col3<T> cu, ch;
   cu.init(x, y, n);
-  // this thread's halo cell (threads 0 .. NH-1): two rows above, two below, two columns
-  // on each side of the middle rows
+  // this thread's halo cell (threads 0 .. NH-1): R rows above, R below, R columns on
+  // each side of the middle rows
   int hx = 0, hy = 0;
   const bool has_halo = threadIdx.x < NH;
   {
     const int h = threadIdx.x;
-    if (h < 2 * PX) {
+    if (h < R * PX) {
       hy = h / PX;
       hx = h % PX;
-    } else if (h < 4 * PX) {
-      hy = PY - R + (h - 2 * PX) / PX;
-      hx = (h - 2 * PX) % PX;
+    } else if (h < 2 * R * PX) {
+      hy = PY - R + (h - R * PX) / PX;
+      hx = (h - R * PX) % PX;
     } else {
-      const int hh = h - 4 * PX;
+      const int hh = h - 2 * R * PX;
       hy = R + hh / (2 * R);
       const int c = hh % (2 * R);
       hx = c < R ? c : PX - 2 * R + c;
@@ -337,17 +340,17 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   const int pown = (ty + R) * PX + tx + R, phal = hy * PX + hx;
   const size_t fcol = (size_t)(xin ? y : 1) * n + (xin ? x : 1);
   const T *up = HAS_U ? u : f;  // a valid address when there is no u
-  const int zlast = z0 + round_up8(z1 - z0) - 1;
-  const bool fast = z0 - R > 0 && zlast + 6 < n - 1;
+  const int zlast = z0 + (z1 - z0 + ZR - 1) / ZR * ZR - 1;
+  const bool fast = z0 - R > 0 && zlast + ZR - R < n - 1;
 
   double acc = 0.0;
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
     auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
     auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
-    T ur[kZR], fr[4], hr[4];  // raw loads: u of this column at z-2+k, f and the halo at z+k
+    T ur[ZR], fr[4], hr[4];  // raw loads: u of this column at z-R+k, f and the halo at z+k
 #pragma unroll
-    for (int k = 0; k < kZR; ++k) ur[k] = HAS_U ? up[base(z0 - 2 + k) + cu.off] : T(0);
+    for (int k = 0; k < ZR; ++k) ur[k] = HAS_U ? up[base(z0 - R + k) + cu.off] : T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       fr[k] = f[(FAST ? (size_t)(z0 + k) * n * n : base(z0 + k)) + fcol];
@@ -361,25 +364,35 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
     auto step = [&](const int z, auto pc) {
       constexpr int P = decltype(pc)::value;
       const T m = cu.mul;
-      T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
-      T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
-      T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
+      // plane z+d sits in slot (P + R + d) mod ZR
+      T um3 = RR == 3 ? ur[P % ZR] * (m * zm(z - 3)) : T(0);
+      T um2 = ur[(P + R - 2) % ZR] * (m * zm(z - 2)), um1 = ur[(P + R - 1) % ZR] * (m * zm(z - 1));
+      T uc = ur[(P + R) % ZR] * (m * zm(z)), up1 = ur[(P + R + 1) % ZR] * (m * zm(z + 1));
+      T up2 = ur[(P + R + 2) % ZR] * (m * zm(z + 2));
+      T up3 = RR == 3 ? ur[(P + R + 3) % ZR] * (m * zm(z + 3)) : T(0);
       T fz = fr[P % 4] * fmask, hz = hr[P % 4] * (ch.mul * zm(z));
-      asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
+      if constexpr (RR == 3)
+        asm volatile("" : "+v"(um3), "+v"(fz), "+v"(hz));
+      else
+        asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
-      if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];  // the slot of plane z-2
+      if (HAS_U) ur[P % ZR] = up[base(z - R + ZR) + cu.off];  // the slot of plane z-R
       fr[P % 4] = f[base(z + 4) + fcol];
       if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
       T *pl = plane[P & 1];
       pl[pown] = uc;
       if (has_halo) pl[phal] = hz;
       __syncthreads();
-      const T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
-                                     ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
-                               kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
-                                         ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
-                                         ((uc - um2) + (uc - up2)))
-                         : T(0);
+      T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
+                               ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
+                         kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
+                                   ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
+                                   ((uc - um2) + (uc - up2)))
+                   : T(0);
+      if constexpr (RR == 3)
+        if (HAS_U)
+          lu += kop.w3 * (((uc - pl[pown - 3]) + (uc - pl[pown + 3])) +
+                          ((uc - pl[pown - 3 * PX]) + (uc - pl[pown + 3 * PX])) + ((uc - um3) + (uc - up3)));
       const bool inside = own && xin && z > 0 && z < n - 1;
       const T r = inside ? fz - lu : T(0);
       if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
@@ -392,8 +405,8 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
         out[id] = (TO)(inside ? uc + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * r : T(0));
       if (MODE == kResidual) out[id] = (TO)r;
     };
-    for (int z = z0; z < z1; z += kZR)
-      static_for<kZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+    for (int z = z0; z < z1; z += ZR)
+      static_for<ZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
   };
   if (fast)
     run(std::true_type{});
@@ -1315,12 +1328,12 @@ bool wide_tiles(int n, const char *var) {
   return (size_t)n * n * n * sizeof(T) >= ((size_t)96 << 20);
 }
 
-template <typename T, typename TO, int XW>
+template <typename T, typename TO, int XW, int RR = 2>
 const void *xsweep3d_fn(int mode, bool has_u) {
-  if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW>;
-  if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW>;
-  if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW>;
-  return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW>;
+  if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW, RR>;
+  if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW, RR>;
+  if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW, RR>;
+  return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW, RR>;
 }
 
 template <typename T, typename TO>
@@ -1379,12 +1392,22 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   }
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
   // operator (it uses om_d only)
-  const bool xpath = op.cross || u == nullptr, gpath = !xpath && gsweep_rings();
-  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath ? 64 : TX, nt = xpath || gpath ? xw * TY : 256;
+  const bool xpath = op.cross || u == nullptr;
+  // the sixth-order radius-3 cross: the cross sweep with R = 3 (MG_X3_R3=0: separable path)
+  static const bool r3 = [] {
+    const char *e = getenv("MG_X3_R3");
+    return e == nullptr || atoi(e) != 0;
+  }();
+  const bool x3path = !xpath && op.cross3 && r3;
+  const bool gpath = !xpath && !x3path && gsweep_rings();
+  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath || x3path ? 64 : TX;
+  const int nt = xpath || gpath || x3path ? xw * TY : 256;
   const int tiles = cdiv(n, xw) * cdiv(n, TY);
-  const size_t smem = xpath || gpath ? 0 : sweep_smem<T, 3>();
-  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw), nt, smem),
-                                                 kMinPlanes)) + kZR - 1) / kZR * kZR;
+  const size_t smem = xpath || gpath || x3path ? 0 : sweep_smem<T, 3>();
+  const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw);
+  const int zr = x3path ? 16 : kZR;  // planes per loop turn of the kernel
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(occ_fn, nt, smem),
+                                                 kMinPlanes)) + zr - 1) / zr * zr;
   const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   KOp<T> k = to_kop3<T>(op, omega);
@@ -1396,6 +1419,15 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     else if (mode == kResidual) MG_G3(kResidual);
     else MG_G3(kNormOnly);
 #undef MG_G3
+    return hipGetLastError();
+  }
+  if (x3path) {
+#define MG_X33(MODE) hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, 64, 3>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+    if (mode == kSweep) MG_X33(kSweep);
+    else if (mode == kSweepRB) MG_X33(kSweepRB);
+    else if (mode == kResidual) MG_X33(kResidual);
+    else MG_X33(kNormOnly);
+#undef MG_X33
     return hipGetLastError();
   }
   if (xpath) {

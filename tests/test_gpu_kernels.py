@@ -336,7 +336,8 @@ def test_red_black_fused_passes(dim, n, coarse, prolong, level, nu1, nu2, fp32):
 SIXTH_CASES = [
     # dim, n, coarse, prolong, level
     (2, 65, 0, 1, 0), (2, 257, 0, 3, 0), (2, 1025, 0, 1, 0), (2, 1025, 3, 3, 1), (2, 257, 1, 1, 1),
-    (3, 33, 0, 3, 0), (3, 65, 0, 1, 0), (3, 129, 0, 3, 0), (3, 65, 1, 3, 1),
+    (3, 33, 0, 3, 0), (3, 65, 0, 1, 0), (3, 129, 0, 3, 0), (3, 65, 1, 3, 1), (3, 257, 0, 3, 0),
+    (3, 17, 0, 3, 0),
 ]
 
 

@@ -144,6 +144,23 @@ def test_sixth_order_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamm
         H.close()
 
 
+@pytest.mark.parametrize("r3", ["0", "1"])
+@pytest.mark.parametrize("n,coarse,smoother", [(65, 0, 0), (129, 3, 0), (65, 2, 1)])
+def test_sixth_order_3d_cross_and_separable_agree(r3, n, coarse, smoother, monkeypatch):
+    """3D sixth-order level 0 through the radius-3 cross sweep or the separable sweep:
+    both equal the oracle's cycles."""
+    monkeypatch.setenv("MG_X3_R3", r3)
+    H = Handle(3, n, coarse=coarse, order=6, smoother=smoother)
+    try:
+        f = inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 3)
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
 def test_sixth_order_solve_converges_to_discrete_solution():
     """A 2D sixth-order solve to 1e-10 lands on the exact discrete solution (sine
     transform with the sixth-order eigenvalues) within the bound its residual implies."""
