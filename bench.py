@@ -378,7 +378,7 @@ def pmc_probe(w, run, stream):
 SERVE_BUDGET = 32 << 30
 
 
-def serve_bench(count, loads=(0.5, 0.8)):
+def serve_bench(count, loads=(0.5, 0.8), smoother=0, inner=4):
     """Continuous-batching server on a Poisson stream of 2D solves, n = 2^k + 1 with k
     uniform on 6..11, Fourier right-hand sides (k <= min(64, (n-1)/4)), mixed precision
     V(2,1) to 1e-10.  First all requests at once (saturated throughput), then open-loop
@@ -388,7 +388,7 @@ def serve_bench(count, loads=(0.5, 0.8)):
 
     from paper_2008_03885_amd import inputs, mg, serve
     base = dict(dim=2, coarse=0, gamma=1, nu1=2, nu2=1, precision=mg.MG_PREC_MIXED, rtol=1e-10,
-                max_cycles=30, inner_cycles=4)
+                max_cycles=30, inner_cycles=inner, smoother=smoother)
     stream = inputs.request_stream(count, 1.0)
     fs = {}
     reqs = []
@@ -486,7 +486,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.serve_only:
-        print(json.dumps({"serving": serve_bench(max(args.serve_requests, 1))}), flush=True)
+        print(json.dumps({"serving": serve_bench(max(args.serve_requests, 1), smoother=w.get("smoother", 0),
+                                                 inner=args.inner or 4)}), flush=True)
         return
     f, coeffs = make_rhs(w)
     fd = torch.from_numpy(f).cuda()
@@ -632,6 +633,8 @@ def main():
     if args.serve_requests > 0 and args.workload == "poisson2d-4097":
         del fd
         out["serving"] = serve_bench(args.serve_requests)
+        # the same stream with red-black Jacobi smoothing (2 FP32 cycles per refinement step)
+        out["serving_redblack"] = serve_bench(args.serve_requests, smoother=1, inner=2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, max(fp64_cycles or res.cycles, 1))
     print(json.dumps(out), flush=True)
