@@ -848,12 +848,14 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ 
 // registers and its last four defects in another, while plane z of the support plus a
 // two-point halo goes through LDS.  After every odd fine plane 2K+1 the z-weighted
 // defects of planes 2K-1 .. 2K+1 are weighted in x and y through LDS.
-template <typename T, bool HAS_U, int CX, int CY, int NT>
+// RR = 3: the radius-3 cross of the sixth-order operator, with a u ring of 16 planes.
+template <typename T, bool HAS_U, int CX, int CY, int NT, int RR = 2>
 __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *__restrict__ u,
                                               T *__restrict__ fc, int n, int kchunk, KOp<T> op,
                                               const int *__restrict__ done) {
   constexpr int kRDX = 2 * CX + 1, kRDY = 2 * CY + 1;
-  constexpr int R = 2, PX = kRDX + 2 * R, PY = kRDY + 2 * R, PS = PX * PY;
+  constexpr int R = RR, PX = kRDX + 2 * R, PY = kRDY + 2 * R, PS = PX * PY;
+  constexpr int ZR = RR == 2 ? kZR : 16;  // u ring length = planes per loop turn (even)
   constexpr int ND = kRDX * kRDY, NH = PS - ND;  // defect columns, halo cells
   static_assert(ND <= NT && NH <= NT, "one column and one halo cell per thread");
   __shared__ T plane[2][PS];
@@ -871,14 +873,14 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
   cu.init(X0 + dx, Y0 + dy, n);
   int hx = 0, hy = 0;
   const bool has_halo = t < NH;
-  if (t < 2 * PX) {
+  if (t < R * PX) {
     hy = t / PX;
     hx = t % PX;
-  } else if (t < 4 * PX) {
-    hy = PY - R + (t - 2 * PX) / PX;
-    hx = (t - 2 * PX) % PX;
+  } else if (t < 2 * R * PX) {
+    hy = PY - R + (t - R * PX) / PX;
+    hx = (t - R * PX) % PX;
   } else {
-    const int hh = t - 4 * PX;
+    const int hh = t - 2 * R * PX;
     hy = R + hh / (2 * R);
     const int c = hh % (2 * R);
     hx = c < R ? c : PX - 2 * R + c;
@@ -902,18 +904,18 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
   }
   const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
   if (Klo >= Khi) return;
-  const int zs = 2 * Klo - 1;                                // odd
-  const int ze = zs + round_up8(2 * (Khi - Klo) + 1) - 1;    // whole turns of the ring
+  const int zs = 2 * Klo - 1;                                        // odd
+  const int ze = zs + (2 * (Khi - Klo) + ZR) / ZR * ZR - 1;          // whole turns of the ring
   const T *up = HAS_U ? u : f;
-  const bool fast = zs - R > 0 && ze + 6 < n - 1;
+  const bool fast = zs - R > 0 && ze + ZR - R < n - 1;
 
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
     auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
     auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
-    T ur[kZR], fr[4], hr[4], dr[4];
+    T ur[ZR], fr[4], hr[4], dr[4];
 #pragma unroll
-    for (int k = 0; k < kZR; ++k) ur[k] = HAS_U ? up[base(zs - 2 + k) + cu.off] : T(0);
+    for (int k = 0; k < ZR; ++k) ur[k] = HAS_U ? up[base(zs - R + k) + cu.off] : T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       fr[k] = f[base(zs + k) + fcol];
@@ -926,27 +928,37 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
     const KOp<T> kop = op;
     const T fmask = fin ? T(1) : T(0);
     auto step = [&](const int z, auto pc) {
-      constexpr int P = decltype(pc)::value;  // z - zs mod 8; z odd exactly when P is even
+      constexpr int P = decltype(pc)::value;  // z - zs mod ZR; z odd exactly when P is even
       const T m = cu.mul;
-      T um2 = ur[P % kZR] * (m * zm(z - 2)), um1 = ur[(P + 1) % kZR] * (m * zm(z - 1));
-      T uc = ur[(P + 2) % kZR] * (m * zm(z)), up1 = ur[(P + 3) % kZR] * (m * zm(z + 1));
-      T up2 = ur[(P + 4) % kZR] * (m * zm(z + 2));
+      // plane z+d sits in slot (P + R + d) mod ZR
+      T um3 = RR == 3 ? ur[P % ZR] * (m * zm(z - 3)) : T(0);
+      T um2 = ur[(P + R - 2) % ZR] * (m * zm(z - 2)), um1 = ur[(P + R - 1) % ZR] * (m * zm(z - 1));
+      T uc = ur[(P + R) % ZR] * (m * zm(z)), up1 = ur[(P + R + 1) % ZR] * (m * zm(z + 1));
+      T up2 = ur[(P + R + 2) % ZR] * (m * zm(z + 2));
+      T up3 = RR == 3 ? ur[(P + R + 3) % ZR] * (m * zm(z + 3)) : T(0);
       T fz = fr[P % 4] * fmask, hz = hr[P % 4] * (ch.mul * zm(z));
-      asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
+      if constexpr (RR == 3)
+        asm volatile("" : "+v"(um3), "+v"(fz), "+v"(hz));
+      else
+        asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
-      if (HAS_U) ur[P % kZR] = up[base(z + 6) + cu.off];
+      if (HAS_U) ur[P % ZR] = up[base(z - R + ZR) + cu.off];
       fr[P % 4] = f[base(z + 4) + fcol];
       if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
       T *pl = plane[P & 1];
       if (has_col) pl[pown] = uc;
       if (has_halo) pl[phal] = hz;
       __syncthreads();
-      const T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
-                                     ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
-                               kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
-                                         ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
-                                         ((uc - um2) + (uc - up2)))
-                         : T(0);
+      T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
+                               ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
+                         kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
+                                   ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
+                                   ((uc - um2) + (uc - up2)))
+                   : T(0);
+      if constexpr (RR == 3)
+        if (HAS_U)
+          lu += kop.w3 * (((uc - pl[pown - 3]) + (uc - pl[pown + 3])) +
+                          ((uc - pl[pown - 3 * PX]) + (uc - pl[pown + 3 * PX])) + ((uc - um3) + (uc - up3)));
       dr[P % 4] = fz - lu;  // defect of plane z at this column (used on interior supports only)
       if constexpr ((P & 1) == 0) {
         if (z >= zs + 2) {  // z = 2K+1 completes coarse plane K
@@ -970,8 +982,8 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
         }
       }
     };
-    for (int z = zs; z <= ze; z += kZR)
-      static_for<kZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+    for (int z = zs; z <= ze; z += ZR)
+      static_for<ZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
   };
   if (fast)
     run(std::true_type{});
@@ -1382,6 +1394,16 @@ int sweep_partials_3d(int n) {
   return (int)(tiles * cdiv(n, kMinPlanes));
 }
 
+// The sixth-order radius-3 cross runs the cross kernels with R = 3 (MG_X3_R3=0: the
+// separable kernels of the Galerkin levels instead).
+bool x3_r3() {
+  static const bool on = [] {
+    const char *e = getenv("MG_X3_R3");
+    return e == nullptr || atoi(e) != 0;
+  }();
+  return on;
+}
+
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,
                            TO *out, int n, double *partials, int *nparts, const int *done,
@@ -1393,12 +1415,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
   // operator (it uses om_d only)
   const bool xpath = op.cross || u == nullptr;
-  // the sixth-order radius-3 cross: the cross sweep with R = 3 (MG_X3_R3=0: separable path)
-  static const bool r3 = [] {
-    const char *e = getenv("MG_X3_R3");
-    return e == nullptr || atoi(e) != 0;
-  }();
-  const bool x3path = !xpath && op.cross3 && r3;
+  const bool x3path = !xpath && op.cross3 && x3_r3();
   const bool gpath = !xpath && !x3path && gsweep_rings();
   const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath || x3path ? 64 : TX;
   const int nt = xpath || gpath || x3path ? xw * TY : 256;
@@ -1517,6 +1534,17 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
       MG_XRR(16, 3, 256)
     }
 #undef MG_XRR
+    return hipGetLastError();
+  }
+  if (op.cross3 && x3_r3()) {
+    // the radius-3 cross: 16 x 7 coarse columns per 512 threads; coarse planes per band
+    // 8m-1, so that the 16m-1 fine planes of a band fill m turns of the 16-plane ring
+    const int ctiles = cdiv(nc, 16) * cdiv(nc, 7);
+    const void *fx = (const void *)k_xrr3d<T, true, 16, 7, 512, 3>;
+    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 512, 0), kMinPlanes / 2));
+    const int kc = std::max(7, (kb + 1) / 8 * 8 - 1);
+    const dim3 grid(cdiv(nc, 16), cdiv(nc, 7), cdiv(nc, kc));
+    hipLaunchKernelGGL((k_xrr3d<T, true, 16, 7, 512, 3>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
     return hipGetLastError();
   }
   if (gsweep_rings()) {
