@@ -52,8 +52,8 @@ MEASURED_TRAFFIC = {
     # the same pass with red-black smoothing (one red-black sweep + defect + full weighting):
     # 156,850.3 KiB x 2.0000 + 168,329.4 KiB x 1.0000
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
-    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,542.4 KiB x 1.9999 + 590,490.5 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2070055653, "source": "e9d446011f49459f"},
+    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
+    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
 }
 
 
