@@ -161,6 +161,23 @@ def test_sixth_order_3d_cross_and_separable_agree(r3, n, coarse, smoother, monke
         H.close()
 
 
+@pytest.mark.parametrize("dim,n,smoother", [(2, 513, 0), (3, 65, 0), (3, 65, 1)])
+def test_sixth_order_mixed_precision_matches_fp64(dim, n, smoother):
+    """Sixth-order solves in mixed precision reach 1e-10 and agree with the FP64 solve."""
+    f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+    out = []
+    for precision in (0, 1):
+        H = Handle(dim, n, coarse=3, order=6, smoother=smoother, precision=precision, inner_cycles=3)
+        try:
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+            assert st == mg.MG_OK and res.rel_residual <= 1e-10, (precision, res.rel_residual)
+            out.append(host(ud))
+        finally:
+            H.close()
+    assert np.linalg.norm(out[1] - out[0]) <= 1e-8 * np.linalg.norm(out[0])
+
+
 def test_sixth_order_solve_converges_to_discrete_solution():
     """A 2D sixth-order solve to 1e-10 lands on the exact discrete solution (sine
     transform with the sixth-order eigenvalues) within the bound its residual implies."""
