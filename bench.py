@@ -70,6 +70,7 @@ def parse():
     p.add_argument("--smoother", type=int, default=None,
                    help="0 omega-Jacobi (default), 1 red-black Jacobi")
     p.add_argument("--order", type=int, default=None, help="fine operator order: 4 (default), 2 or 6")
+    p.add_argument("--omega", type=float, default=None, help="relaxation (default: the LFA optimum)")
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
     p.add_argument("--inner", type=int, default=None, help="FP32 cycles per refinement step")
@@ -129,7 +130,7 @@ class Run:
                                   nu1=w["nu1"], nu2=w["nu2"], precision=precision, rtol=1e-10,
                                   max_cycles=60 if precision == 0 else 30,
                                   inner_cycles=w["inner"], smoother=w.get("smoother", 0),
-                                  order=w.get("order", 4))
+                                  order=w.get("order", 4), omega=w.get("omega", 0.0))
         self.h = mg.mg_setup(self.cfg, stream.cuda_stream)
         self.fd = fd
         self.ud = torch.zeros_like(fd)
@@ -309,7 +310,8 @@ def cpu_baseline(w, cycles_needed, budget_s=20.0):
     ws = dict(w, n=n)
     f, _ = make_rhs(ws)
     m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
-                         smoother=w.get("smoother", 0), order=w.get("order", 4))
+                         smoother=w.get("smoother", 0), order=w.get("order", 4),
+                         omega=w.get("omega") or None)
     u = np.zeros_like(f)
     t0 = time.perf_counter()
     m.cycle(u, f)
@@ -480,7 +482,7 @@ def main():
     import torch
 
     w = dict(WORKLOADS[args.workload])
-    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order"):
+    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order", "omega"):
         if getattr(args, k) is not None:
             w[k] = getattr(args, k)
     torch.cuda.set_device(0)
@@ -508,21 +510,25 @@ def main():
     if args.workload == "poisson2d-4097" and not args.no_variants:
         variants = {}
         kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
-        for coarse, gamma, sm, order in (
-                (0, 1, 0, 4), (1, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4), (2, 1, 0, 4), (3, 1, 0, 4),
-                (0, 1, 1, 4), (1, 1, 1, 4), (3, 1, 1, 4), (0, 2, 1, 4),
-                (0, 1, 0, 6), (3, 1, 0, 6), (3, 1, 1, 6)):
+        for coarse, gamma, sm, order, om in (
+                (0, 1, 0, 4, 0.0), (1, 1, 0, 4, 0.0), (0, 2, 0, 4, 0.0), (1, 2, 0, 4, 0.0),
+                (2, 1, 0, 4, 0.0), (3, 1, 0, 4, 0.0),
+                (0, 1, 1, 4, 0.0), (1, 1, 1, 4, 0.0), (3, 1, 1, 4, 0.0), (0, 2, 1, 4, 0.0),
+                (0, 1, 1, 4, 1.17),  # the measured multilevel optimum, above the two-grid one
+                (0, 1, 0, 6, 0.0), (3, 1, 0, 6, 0.0), (3, 1, 1, 6, 0.0)):
             name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
             if sm:
                 name = "redblack-" + name
             if order != 4:
                 name = "order%d-%s" % (order, name)
+            if om:
+                name += "-omega%g" % om
             if (coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0)
-                    and order == w.get("order", 4)):
+                    and order == w.get("order", 4) and not om and not w.get("omega")):
                 vs, vres = sec, res
             else:
-                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm, order=order), w["precision"],
-                         fd, stream)
+                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm, order=order, omega=om),
+                         w["precision"], fd, stream)
                 vs, (vst, vres) = vr.timed(2, 1)
                 vr.close()
             variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
@@ -532,11 +538,12 @@ def main():
     # per refinement step
     if args.workload == "poisson3d-513" and not args.no_variants and not w.get("smoother", 0):
         variants = {}
-        for prec in (0, 1):
-            vr = Run(dict(w, smoother=1, inner=4), prec, fd, stream)
+        for prec, om in ((0, 0.0), (1, 0.0), (0, 1.25)):
+            vr = Run(dict(w, smoother=1, inner=4, omega=om), prec, fd, stream)
             vs, (vst, vres) = vr.timed(2, 1)
             vr.close()
-            variants["redblack-V(%d,%d)-%s" % (w["nu1"], w["nu2"], "fp64" if prec == 0 else "mixed-inner4")] = {
+            name = "redblack-V(%d,%d)-%s" % (w["nu1"], w["nu2"], "fp64" if prec == 0 else "mixed-inner4")
+            variants[name + ("-omega%g" % om if om else "")] = {
                 "ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
                 "outer_steps": vres.outer_steps, "rel_residual": vres.rel_residual}
 
