@@ -23,6 +23,9 @@ Everything here is built from the Fourier symbols the paper prints, not from ste
   second-order symbol at H (eq. L_H_2d), or the Galerkin symbol of the second-order
   fine symbol (eq. L_H_2G_2d);
 * smoothing factor: sup over high frequencies (section 2.2 eq. mu; section 5.3).
+* three-level gamma-cycle (section 2.2 eqs. K_l, M; the appendix's eqs. L_H_approx and
+  M_3level): the level-1 solve replaced by gamma level-1 two-grid cycles, on the 4^d
+  fine modes theta + (pi/2) k that standard coarsening couples over two levels.
 
 Convention: an interpolated coarse mode phi_H(2 theta) is sum_alpha p(theta_alpha) phi_h(theta_alpha)
 and restriction maps phi_h(theta_alpha) to r(theta_alpha) phi_H(2 theta).
@@ -119,29 +122,68 @@ class Scheme:
     def smoother_symbol(self, theta, level=0, h0=1.0):
         return 1.0 - self.omega * self.level_symbol(level, theta, h0) / self.level_diagonal(level, h0)
 
-    def smoother_matrix(self, theta, h0=1.0):
-        """2^d x 2^d symbol of one smoothing sweep on the aliases of theta."""
-        th = aliases(theta)
-        D = np.diag(-self.omega * self.level_symbol(0, th, h0) / self.level_diagonal(0, h0))
+    def smoother_on(self, modes, partner, level=0, h0=1.0):
+        """Symbol of one smoothing sweep at level l on a set of modes closed under
+        theta -> theta + (pi,..,pi); partner[i] is the index of that shift of modes[i]."""
+        D = np.diag(-self.omega * self.level_symbol(level, modes, h0) / self.level_diagonal(level, h0))
         eye = np.eye(len(D))
         if self.smoother == JACOBI:
             return eye + D
-        P = eye[::-1]  # alias index alpha (binary, axis 0 first) -> its complement
+        P = eye[:, partner]  # the colour flip (-1)^(index sum) as a permutation of the modes
         red = eye + 0.5 * (eye - P) @ D
         black = eye + 0.5 * (eye + P) @ D
         return black @ red
 
-    def two_grid_matrix(self, theta, h0=1.0):
-        """2^d x 2^d symbol of S^nu2 K S^nu1 at one low frequency theta."""
+    def smoother_matrix(self, theta, h0=1.0, level=0):
+        """2^d x 2^d symbol of one smoothing sweep on the aliases of theta."""
         th = aliases(theta)
-        L = self.level_symbol(0, th, h0)
-        S = self.smoother_matrix(theta, h0)
+        # alias index alpha (binary, axis 0 first) -> its complement
+        return self.smoother_on(th, np.arange(len(th))[::-1], level, h0)
+
+    def two_grid_matrix(self, theta, h0=1.0, level=0):
+        """2^d x 2^d symbol of S^nu2 K S^nu1 at one low frequency theta of level l, with the
+        level l+1 equation solved exactly."""
+        th = aliases(theta)
+        L = self.level_symbol(level, th, h0)
+        S = self.smoother_matrix(theta, h0, level)
         r = symbol_transfer(th, self.restrict_op)
         p = symbol_transfer(th, self.prolong)
-        LH = self.level_symbol(1, 2.0 * np.asarray(theta, dtype=float), h0)
+        LH = self.level_symbol(level + 1, 2.0 * np.asarray(theta, dtype=float), h0)
         K = np.eye(len(L)) - np.outer(p, r * L) / LH
         return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
 
+    def three_grid_matrix(self, theta, h0=1.0, gamma=1):
+        """4^d x 4^d symbol of the three-level gamma-cycle at theta in [-pi/4, pi/4)^d.
+
+        Section 2.2 eqs. K_l and M define the multi-level operator by recursion; the
+        appendix on red-black coarsening writes its three-level form (eqs. L_H_approx,
+        M_3level): the level-1 solve is replaced by gamma level-1 two-grid cycles from a
+        zero guess, L1~^{-1} = (I - M_1^gamma) L_1^{-1}.  Standard coarsening couples the
+        4^d fine modes theta + (pi/2) k, k in {0..3}^d: fine mode k restricts to the level-1
+        alias 2 theta + pi (k mod 2), and those 2^d level-1 modes are the aliases on which
+        M_1 acts.  gamma=None solves level 1 exactly."""
+        theta = np.asarray(theta, dtype=float)
+        ks = np.array(list(itertools.product(range(4), repeat=self.dim)))
+        modes = theta + (np.pi / 2) * ks
+        index = {tuple(k): i for i, k in enumerate(ks)}
+        partner = [index[tuple((k + 2) % 4)] for k in ks]
+        coarse = [int(np.dot(k % 2, 2 ** np.arange(self.dim)[::-1])) for k in ks]  # alias order
+        L0 = self.level_symbol(0, modes, h0)
+        theta1 = 2.0 * theta
+        L1 = self.level_symbol(1, aliases(theta1), h0)
+        m1 = len(L1)
+        if gamma is None:
+            solve1 = np.diag(1.0 / L1)
+        else:
+            M1 = self.two_grid_matrix(theta1, h0, level=1)
+            solve1 = (np.eye(m1) - np.linalg.matrix_power(M1, gamma)) @ np.diag(1.0 / L1)
+        R = np.zeros((m1, len(ks)))
+        P = np.zeros((len(ks), m1))
+        R[coarse, np.arange(len(ks))] = symbol_transfer(modes, self.restrict_op)
+        P[np.arange(len(ks)), coarse] = symbol_transfer(modes, self.prolong)
+        K = np.eye(len(ks)) - P @ solve1 @ R @ np.diag(L0)
+        S = self.smoother_on(modes, partner, 0, h0)
+        return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
 
 # Default omega of the red-black Jacobi smoother: the value minimising the two-grid factor
 # of the V(2,1) cycle with cubic interpolation and the rediscretized operator, rounded to two
@@ -214,6 +256,19 @@ def two_grid_rho(scheme, m=32):
         best = max(best, float(np.max(np.abs(np.linalg.eigvals(scheme.two_grid_matrix(theta))))))
     return best
 
+
+def three_grid_rho(scheme, m=16, gamma=1):
+    """sup over a uniform grid of theta in [-pi/4, pi/4]^d (theta = 0 excluded) of the
+    spectral radius of the three-level gamma-cycle."""
+    grid = -np.pi / 4 + (np.pi / 2) * np.arange(m + 1) / m
+    best = 0.0
+    for theta in itertools.product(grid, repeat=scheme.dim):
+        theta = np.array(theta)
+        if np.allclose(theta, 0.0):
+            continue
+        M = scheme.three_grid_matrix(theta, gamma=gamma)
+        best = max(best, float(np.max(np.abs(np.linalg.eigvals(M)))))
+    return best
 
 def finite_two_grid_spectrum(scheme, n):
     """Exact eigenvalues of the two-grid operator on the Dirichlet grid of n points/axis

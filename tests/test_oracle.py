@@ -572,6 +572,50 @@ def test_multilevel_rate_is_near_two_grid_rate(gamma, coarse, smoother):
     assert rho2 - 0.01 <= cr <= rho2 + 0.05
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("coarse,smoother", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_three_grid_with_exact_level1_solve_splits_into_two_grid_blocks(dim, coarse, smoother):
+    """With the level-1 equation solved exactly the 4^d modes theta + (pi/2) k decouple
+    into the 2^d alias sets of theta + (pi/2) b, b in {0,1}^d, so the three-level symbol's
+    eigenvalues are those of the two-grid symbols at those frequencies (the mode
+    bookkeeping of the three-level analysis, eq. M_3level, checked against eq. M_2level)."""
+    sch = lfa.Scheme(dim, coarse=coarse, smoother=smoother)
+    rng = np.random.default_rng(11)
+    for theta in rng.uniform(-np.pi / 4, np.pi / 4, size=(3, dim)):
+        e3 = np.linalg.eigvals(sch.three_grid_matrix(theta, gamma=None))
+        e2 = np.concatenate([np.linalg.eigvals(sch.two_grid_matrix(theta + (np.pi / 2) * np.array(b)))
+                             for b in itertools.product((0, 1), repeat=dim)])
+        assert len(e3) == len(e2) == 4 ** dim
+        assert max(np.min(np.abs(e2 - z)) for z in e3) < 1e-12
+        assert max(np.min(np.abs(e3 - z)) for z in e2) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,nc,m", [(2, 129, 33, 16), (3, 33, 9, 6)])
+@pytest.mark.parametrize("gamma,coarse,smoother", [(1, 0, 0), (2, 0, 0), (1, 1, 0), (1, 3, 0),
+                                                (1, 0, 1), (2, 1, 1)])
+def test_measured_three_level_rate_matches_three_grid_lfa(dim, n, nc, m, gamma, coarse, smoother):
+    """A three-level cycle's measured asymptotic rate (section 2.2 eq. CR) against the
+    three-level Fourier analysis (eqs. K_l and M; the approximate level-1 solve of eq.
+    L_H_approx).  For the red-black V-cycle the level-1 V-cycle's own error is visible:
+    the rate is well above the two-grid factor and the three-level analysis predicts it."""
+    mg = oracle.Multigrid(dim, n, n_coarsest=nc, gamma=gamma, coarse=coarse, smoother=smoother)
+    assert mg.levels == 3
+    s = mg.level_stencil(0)[1]
+    rng = np.random.default_rng(5)
+    f = np.zeros((n,) * dim)
+    u = np.zeros((n,) * dim)
+    u[(slice(1, -1),) * dim] = rng.standard_normal((n - 2,) * dim)
+    r = [oracle.norm(oracle.residual(s, f, u))]
+    for _ in range(40 if smoother == oracle.SMOOTH_JACOBI else 20):
+        mg.cycle(u, f)
+        r.append(oracle.norm(oracle.residual(s, f, u)))
+    cr = r[-1] / r[-2]
+    sch = lfa.Scheme(dim, coarse=coarse, smoother=smoother)
+    rho3 = lfa.three_grid_rho(sch, m, gamma)
+    assert 0.93 * rho3 <= cr <= 1.02 * rho3
+    if gamma == 1 and smoother == oracle.SMOOTH_RBJ:
+        assert cr > 1.2 * lfa.two_grid_rho(sch, m=2 * m)
+
 def test_residual_norm_long_double_agrees():
     n = 65
     _, f, _ = inputs.manufactured_2d(n)
