@@ -1,0 +1,532 @@
+// rbc.hip -- red-black coarsening multigrid in two dimensions (section 4.3 Theorem 3,
+// section 4.4), FP64.
+//
+// Level l lives on the standard grid of spacing 2^(l/2) h that holds it (side m); an odd
+// level is rotated and uses only the interior points with an even index sum.  Every
+// level's operator is a symmetric stencil of at most four coefficients on that storage
+// grid: centre, axis neighbours at distance 1, diagonal neighbours, axis neighbours at
+// distance 2.  All steps are one thread per storage point: the defect, the transfers and
+// the omega-Jacobi partial steps read the few neighbours they need straight from HBM
+// through the caches, and the coarsest level is assembled and factorised inside one
+// workgroup's LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "batch.h"
+#include "mg_rbc.h"
+
+namespace {
+
+struct Op {
+  double c0, a1, d1, a2;  // centre, axis +-1, diagonal, axis +-2
+};
+
+constexpr int kBX = 64, kBY = 4;          // one wavefront per storage row segment
+constexpr int kMaxCoarseSide = 17;        // storage side of the largest coarsest level
+constexpr int kNormBlocks = 1024;
+
+__device__ __forceinline__ bool interior(int m, int i, int j) {
+  return i > 0 && j > 0 && i < m - 1 && j < m - 1;
+}
+__device__ __forceinline__ bool unknown(bool odd, int m, int i, int j) {
+  return interior(m, i, j) && (!odd || ((i + j) & 1) == 0);
+}
+// C points stay on the next level: even index sum on an even level, both even on an odd one.
+__device__ __forceinline__ bool cpoint(bool odd, int i, int j) {
+  return odd ? (((i | j) & 1) == 0) : (((i + j) & 1) == 0);
+}
+
+// u(i, j) with the odd reflection about the boundary lines; at most one index is outside
+// [0, m) and by at most one point (the distance-2 taps of an interior point).
+__device__ __forceinline__ double tap(const double *u, int m, int i, int j) {
+  if (i < 0) return 2.0 * u[j] - u[(size_t)(-i) * m + j];
+  if (i >= m) return 2.0 * u[(size_t)(m - 1) * m + j] - u[(size_t)(2 * (m - 1) - i) * m + j];
+  if (j < 0) return 2.0 * u[(size_t)i * m] - u[(size_t)i * m - j];
+  if (j >= m) return 2.0 * u[(size_t)i * m + m - 1] - u[(size_t)i * m + 2 * (m - 1) - j];
+  return u[(size_t)i * m + j];
+}
+
+// L u at an interior point.
+__device__ __forceinline__ double apply_op(const double *u, int m, int i, int j, const Op &op) {
+  const size_t p = (size_t)i * m + j;
+  double v = op.c0 * u[p];
+  if (op.a1 != 0.0) v += op.a1 * ((u[p - m] + u[p + m]) + (u[p - 1] + u[p + 1]));
+  if (op.d1 != 0.0)
+    v += op.d1 * ((u[p - m - 1] + u[p - m + 1]) + (u[p + m - 1] + u[p + m + 1]));
+  if (op.a2 != 0.0)
+    v += op.a2 * ((tap(u, m, i - 2, j) + tap(u, m, i + 2, j)) +
+                  (tap(u, m, i, j - 2) + tap(u, m, i, j + 2)));
+  return v;
+}
+
+// One omega-Jacobi partial step on the F points (colour 1) or the C points (colour 2).
+__global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restrict__ f,
+                                                         const double *__restrict__ uin,
+                                                         double *__restrict__ uout, int m,
+                                                         int odd, Op op, int colour,
+                                                         double omega) {
+  const int j = blockIdx.x * kBX + threadIdx.x;
+  const int i = blockIdx.y * kBY + threadIdx.y;
+  if (i >= m || j >= m) return;
+  const size_t p = (size_t)i * m + j;
+  double v = uin[p];
+  if (unknown(odd, m, i, j) && cpoint(odd, i, j) == (colour == 2))
+    v += omega * (f[p] - apply_op(uin, m, i, j, op)) / op.c0;
+  uout[p] = v;
+}
+
+// Defect at the C point and its four F neighbours, restricted with eq. transfer_r2 onto
+// the next level's storage grid (side mc); zero off the next level's unknowns.  uc (may
+// be null) is zeroed: the next level starts from a zero correction.
+__global__ __launch_bounds__(kBX *kBY) void k_rbc_restrict(const double *__restrict__ f,
+                                                           const double *__restrict__ u,
+                                                           double *__restrict__ fc,
+                                                           double *__restrict__ uc, int m,
+                                                           int odd, Op op, int mc) {
+  const int J = blockIdx.x * kBX + threadIdx.x;
+  const int I = blockIdx.y * kBY + threadIdx.y;
+  if (I >= mc || J >= mc) return;
+  const size_t q = (size_t)I * mc + J;
+  double v = 0.0;
+  if (unknown(!odd, mc, I, J)) {
+    const int i = odd ? 2 * I : I, j = odd ? 2 * J : J;
+    auto r = [&](int a, int b) {
+      return unknown(odd, m, a, b) ? f[(size_t)a * m + b] - apply_op(u, m, a, b, op) : 0.0;
+    };
+    const double s = odd ? (r(i - 1, j - 1) + r(i - 1, j + 1)) + (r(i + 1, j - 1) + r(i + 1, j + 1))
+                         : (r(i - 1, j) + r(i + 1, j)) + (r(i, j - 1) + r(i, j + 1));
+    v = (4.0 * r(i, j) + s) * 0.125;
+  }
+  fc[q] = v;
+  if (uc) uc[q] = 0.0;
+}
+
+// u_out = u_in + interpolated correction: C points take the coarse value, F points the
+// mean of their four C neighbours (eq. transfer_r2).
+__global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restrict__ ec,
+                                                          const double *uin, double *uout,
+                                                          int m, int odd, int mc) {
+  const int j = blockIdx.x * kBX + threadIdx.x;
+  const int i = blockIdx.y * kBY + threadIdx.y;
+  if (i >= m || j >= m) return;
+  const size_t p = (size_t)i * m + j;
+  double v = uin[p];
+  if (unknown(odd, m, i, j)) {
+    auto e = [&](int a, int b) {
+      return odd ? ec[(size_t)(a >> 1) * mc + (b >> 1)] : ec[(size_t)a * mc + b];
+    };
+    if (cpoint(odd, i, j))
+      v += e(i, j);
+    else if (odd)
+      v += 0.25 * ((e(i - 1, j - 1) + e(i - 1, j + 1)) + (e(i + 1, j - 1) + e(i + 1, j + 1)));
+    else
+      v += 0.25 * ((e(i - 1, j) + e(i + 1, j)) + (e(i, j - 1) + e(i, j + 1)));
+  }
+  uout[p] = v;
+}
+
+// Exact solve of the coarsest level (zero boundary values): the operator's matrix over
+// the unknowns (row-major storage order) assembled in LDS, Gaussian elimination without
+// pivoting (the matrix is symmetric positive definite), back substitution.
+__global__ __launch_bounds__(256) void k_rbc_coarsest(const double *__restrict__ f,
+                                                      double *__restrict__ u, int m, int odd,
+                                                      Op op) {
+  constexpr int K_MAX = MG_RBC_MAX_COARSEST;
+  __shared__ double A[K_MAX][K_MAX + 1];
+  __shared__ double b[K_MAX], fac[K_MAX];
+  __shared__ int idx[kMaxCoarseSide * kMaxCoarseSide];
+  __shared__ int nk;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int k = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) idx[i * m + j] = unknown(odd, m, i, j) && k < K_MAX ? k++ : -1;
+    nk = k;
+  }
+  for (int q = t; q < K_MAX * (K_MAX + 1); q += blockDim.x) A[q / (K_MAX + 1)][q % (K_MAX + 1)] = 0.0;
+  __syncthreads();
+  const int K = nk;
+  for (int p = t; p < m * m; p += blockDim.x) {
+    const int row = idx[p];
+    if (row < 0) continue;
+    const int i = p / m, j = p % m;
+    auto add = [&](int a, int c, double w) {
+      // a tap beyond the boundary line is minus its mirror image (zero boundary values)
+      if (a < 0 || a >= m || c < 0 || c >= m) {
+        w = -w;
+        a = a < 0 ? -a : (a >= m ? 2 * (m - 1) - a : a);
+        c = c < 0 ? -c : (c >= m ? 2 * (m - 1) - c : c);
+      }
+      const int col = idx[a * m + c];
+      if (col >= 0) A[row][col] += w;
+    };
+    add(i, j, op.c0);
+    if (op.a1 != 0.0) {
+      add(i - 1, j, op.a1); add(i + 1, j, op.a1); add(i, j - 1, op.a1); add(i, j + 1, op.a1);
+    }
+    if (op.d1 != 0.0) {
+      add(i - 1, j - 1, op.d1); add(i - 1, j + 1, op.d1);
+      add(i + 1, j - 1, op.d1); add(i + 1, j + 1, op.d1);
+    }
+    if (op.a2 != 0.0) {
+      add(i - 2, j, op.a2); add(i + 2, j, op.a2); add(i, j - 2, op.a2); add(i, j + 2, op.a2);
+    }
+    b[row] = f[p];
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    if (t < K) fac[t] = t > k ? A[t][k] / A[k][k] : 0.0;
+    __syncthreads();
+    for (int q = t; q < K * K; q += blockDim.x) {
+      const int i = q / K, j = q % K;
+      if (i > k && j >= k) A[i][j] -= fac[i] * A[k][j];
+    }
+    if (t > k && t < K) b[t] -= fac[t] * b[k];
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int i = K - 1; i >= 0; --i) {
+      double s = b[i];
+      for (int j = i + 1; j < K; ++j) s -= A[i][j] * b[j];
+      b[i] = s / A[i][i];
+    }
+  }
+  __syncthreads();
+  for (int p = t; p < m * m; p += blockDim.x) u[p] = idx[p] >= 0 ? b[idx[p]] : 0.0;
+}
+
+// Per-block sums of the squared level-0 defect over the interior.
+__global__ __launch_bounds__(256) void k_rbc_resnorm(const double *__restrict__ f,
+                                                     const double *__restrict__ u, int m, Op op,
+                                                     double *__restrict__ partial) {
+  __shared__ double red[256];
+  const size_t ni = (size_t)(m - 2) * (m - 2);
+  double s = 0.0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < ni;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int i = 1 + (int)(q / (m - 2)), j = 1 + (int)(q % (m - 2));
+    const double r = f[(size_t)i * m + j] - apply_op(u, m, i, j, op);
+    s += r * r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_rbc_sum(const double *__restrict__ partial, int count,
+                                                 double scale, double *__restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < count; q += blockDim.x) s += partial[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0] * scale);
+}
+
+struct Level {
+  int m;
+  bool odd;
+  Op op;
+  int unknowns;
+};
+
+mg_status fail(mg_status st, const std::string &msg) {
+  mgb::set_error(msg);
+  return st;
+}
+
+#define RBC_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+int storage_side(int n, int l) { return (n - 1) / (1 << (l / 2)) + 1; }
+
+int count_unknowns(int m, bool odd) {
+  int k = 0;
+  for (int i = 1; i < m - 1; ++i)
+    for (int j = 1; j < m - 1; ++j) k += !odd || ((i + j) % 2 == 0);
+  return k;
+}
+
+// Level l's stencil on its storage grid of spacing s: the five-point operator on the
+// level's own axes, or eq. L_G1 for the Galerkin choices; an odd level's axes are the
+// storage diagonals and its H^2 = 2 s^2.
+Op level_op(const mg_rbc_config &c, int l) {
+  const double s = std::ldexp(1.0 / (c.n - 1), l / 2), s2 = s * s;
+  const bool g1 = l > 0 && (c.coarse == MG_RBC_G1 || (c.coarse == MG_RBC_GN && l == 1));
+  if (l % 2 == 0) {
+    if (!g1) return Op{4.0 / s2, -1.0 / s2, 0.0, 0.0};
+    return Op{3.0 / s2, -0.5 / s2, -0.25 / s2, 0.0};
+  }
+  const double H2 = 2.0 * s2;
+  if (!g1) return Op{4.0 / H2, 0.0, -1.0 / H2, 0.0};
+  return Op{3.0 / H2, 0.0, -0.5 / H2, -0.25 / H2};
+}
+
+dim3 grid_for(int m) { return dim3((m + kBX - 1) / kBX, (m + kBY - 1) / kBY); }
+
+}  // namespace
+
+struct mg_rbc_ctx {
+  mg_rbc_config cfg;
+  hipStream_t stream = nullptr;
+  std::vector<Level> lv;
+  std::vector<double *> u, f, t;  // per level; u[0], f[0] are the caller's
+  double *partial = nullptr, *norm_dev = nullptr, *norm_host = nullptr;
+};
+
+namespace {
+
+std::string validate(const mg_rbc_config &c) {
+  const int N = c.n - 1;
+  if (c.n < 3 || c.n > 32769 || (N & (N - 1)) != 0) return "n - 1 must be a power of two, 3 <= n <= 32769";
+  if (c.coarse < MG_RBC_NG || c.coarse > MG_RBC_GN) return "coarse must be MG_RBC_NG, MG_RBC_G1 or MG_RBC_GN";
+  if (c.gamma < 1 || c.gamma > 2) return "gamma must be 1 or 2";
+  if (c.nu1 < 0 || c.nu2 < 0 || c.nu1 > 8 || c.nu2 > 8 || c.nu1 + c.nu2 < 1)
+    return "nu1, nu2 must be in 0..8 with at least one sweep";
+  if (!(c.omega == 0.0 || (c.omega > 0.0 && c.omega < 2.0))) return "omega must be 0 (default) or in (0, 2)";
+  if (!(c.rtol >= 0.0)) return "rtol must be >= 0";
+  if (c.max_cycles < 1 || c.max_cycles > MG_MAX_HISTORY) return "max_cycles must be in 1..MG_MAX_HISTORY";
+  if (c.levels < 2) return "levels must be >= 2";
+  for (int l = 1; l < c.levels; ++l) {
+    if (storage_side(c.n, l) < 3 || (N % (1 << (l / 2))) != 0) return "too many levels for n";
+  }
+  const int last = c.levels - 1;
+  const int mc = storage_side(c.n, last);
+  const int k = count_unknowns(mc, last % 2 == 1);
+  if (mc > kMaxCoarseSide || k < 1 || k > MG_RBC_MAX_COARSEST)
+    return "the coarsest level has " + std::to_string(k) + " unknowns (1..MG_RBC_MAX_COARSEST allowed); add levels";
+  return "";
+}
+
+mg_status launch_smooth(mg_rbc_ctx *h, int l, int colour, const double *f, const double *uin,
+                        double *uout) {
+  const Level &L = h->lv[l];
+  const double omega = h->cfg.omega == 0.0 ? 1.0 : h->cfg.omega;
+  hipLaunchKernelGGL(k_rbc_smooth, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, f, uin, uout,
+                     L.m, (int)L.odd, L.op, colour, omega);
+  RBC_HIP(hipGetLastError());
+  return MG_OK;
+}
+
+mg_status launch_restrict(mg_rbc_ctx *h, int l, const double *f, const double *u, double *fc,
+                          double *uc) {
+  const Level &L = h->lv[l];
+  const int mc = h->lv[l + 1].m;
+  hipLaunchKernelGGL(k_rbc_restrict, grid_for(mc), dim3(kBX, kBY), 0, h->stream, f, u, fc, uc,
+                     L.m, (int)L.odd, L.op, mc);
+  RBC_HIP(hipGetLastError());
+  return MG_OK;
+}
+
+mg_status launch_prolong(mg_rbc_ctx *h, int l, const double *ec, const double *uin, double *uout) {
+  const Level &L = h->lv[l];
+  hipLaunchKernelGGL(k_rbc_prolong, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, ec, uin, uout,
+                     L.m, (int)L.odd, h->lv[l + 1].m);
+  RBC_HIP(hipGetLastError());
+  return MG_OK;
+}
+
+mg_status launch_coarsest(mg_rbc_ctx *h, const double *f, double *u) {
+  const Level &L = h->lv.back();
+  hipLaunchKernelGGL(k_rbc_coarsest, dim3(1), dim3(256), 0, h->stream, f, u, L.m, (int)L.odd, L.op);
+  RBC_HIP(hipGetLastError());
+  return MG_OK;
+}
+
+#define RBC_TRY(x)                  \
+  do {                              \
+    mg_status s_ = (x);             \
+    if (s_ != MG_OK) return s_;     \
+  } while (0)
+
+mg_status sweep(mg_rbc_ctx *h, int l, const double *f, double *u) {
+  RBC_TRY(launch_smooth(h, l, 1, f, u, h->t[l]));
+  return launch_smooth(h, l, 2, f, h->t[l], u);
+}
+
+mg_status cycle(mg_rbc_ctx *h, int l, const double *f, double *u) {
+  const int last = (int)h->lv.size() - 1;
+  if (l == last) return launch_coarsest(h, f, u);
+  for (int k = 0; k < h->cfg.nu1; ++k) RBC_TRY(sweep(h, l, f, u));
+  RBC_TRY(launch_restrict(h, l, f, u, h->f[l + 1], h->u[l + 1]));
+  const int reps = l + 1 < last ? h->cfg.gamma : 1;
+  for (int k = 0; k < reps; ++k) RBC_TRY(cycle(h, l + 1, h->f[l + 1], h->u[l + 1]));
+  RBC_TRY(launch_prolong(h, l, h->u[l + 1], u, u));
+  for (int k = 0; k < h->cfg.nu2; ++k) RBC_TRY(sweep(h, l, f, u));
+  return MG_OK;
+}
+
+mg_status norm(mg_rbc_ctx *h, const double *f, const double *u, double *out) {
+  const Level &L = h->lv[0];
+  const size_t ni = (size_t)(L.m - 2) * (L.m - 2);
+  int blocks = (int)std::min<size_t>(kNormBlocks, (ni + 255) / 256);
+  hipLaunchKernelGGL(k_rbc_resnorm, dim3(blocks), dim3(256), 0, h->stream, f, u, L.m, L.op, h->partial);
+  RBC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_rbc_sum, dim3(1), dim3(256), 0, h->stream, h->partial, blocks, 1.0 / (double)ni,
+                     h->norm_dev);
+  RBC_HIP(hipGetLastError());
+  RBC_HIP(hipMemcpyAsync(h->norm_host, h->norm_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  RBC_HIP(hipStreamSynchronize(h->stream));
+  *out = *h->norm_host;
+  return MG_OK;
+}
+
+mg_status check_level(const mg_rbc_ctx *h, int level, bool need_next) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  if (level < 0 || level >= (int)h->lv.size() || (need_next && level + 1 >= (int)h->lv.size()))
+    return fail(MG_EINVAL, "level out of range");
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out) {
+  if (!cfg || !out) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  const std::string why = validate(*cfg);
+  if (!why.empty()) return fail(MG_EINVAL, why);
+  mg_rbc_ctx *h = new mg_rbc_ctx();
+  h->cfg = *cfg;
+  h->stream = (hipStream_t)stream;
+  for (int l = 0; l < cfg->levels; ++l) {
+    Level L;
+    L.m = storage_side(cfg->n, l);
+    L.odd = l % 2 == 1;
+    L.op = level_op(*cfg, l);
+    L.unknowns = count_unknowns(L.m, L.odd);
+    h->lv.push_back(L);
+  }
+  auto alloc = [&](double **p, size_t count) {
+    return hipMalloc((void **)p, count * sizeof(double)) == hipSuccess;
+  };
+  bool ok = true;
+  h->u.assign(cfg->levels, nullptr);
+  h->f.assign(cfg->levels, nullptr);
+  h->t.assign(cfg->levels, nullptr);
+  for (int l = 0; l < cfg->levels && ok; ++l) {
+    const size_t cnt = (size_t)h->lv[l].m * h->lv[l].m;
+    if (l > 0) ok = ok && alloc(&h->u[l], cnt) && alloc(&h->f[l], cnt);
+    ok = ok && alloc(&h->t[l], cnt);
+  }
+  ok = ok && alloc(&h->partial, kNormBlocks) && alloc(&h->norm_dev, 1);
+  ok = ok && hipHostMalloc((void **)&h->norm_host, sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    mg_rbc_destroy(h);
+    return fail(MG_ENOMEM, "device allocation failed");
+  }
+  // every level array starts at zero: their boundaries and off-grid entries stay zero
+  for (int l = 1; l < cfg->levels; ++l) {
+    const size_t bytes = (size_t)h->lv[l].m * h->lv[l].m * sizeof(double);
+    hipError_t e = hipMemsetAsync(h->u[l], 0, bytes, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->f[l], 0, bytes, h->stream);
+    if (e != hipSuccess) {
+      mg_rbc_destroy(h);
+      return fail(MG_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    }
+  }
+  *out = h;
+  return MG_OK;
+}
+
+void mg_rbc_destroy(mg_rbc_ctx *h) {
+  if (!h) return;
+  // teardown: errors here have no caller to go to
+  (void)(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
+  auto release = [](double *p) {
+    if (p) (void)hipFree(p);
+  };
+  for (double *p : h->u) release(p);
+  for (double *p : h->f) release(p);
+  for (double *p : h->t) release(p);
+  release(h->partial);
+  release(h->norm_dev);
+  if (h->norm_host) (void)hipHostFree(h->norm_host);
+  delete h;
+}
+
+int mg_rbc_level_size(const mg_rbc_ctx *h, int level) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return -1;
+  return h->lv[level].m;
+}
+
+mg_status mg_rbc_cycles(mg_rbc_ctx *h, const double *f, double *u, int ncycles) {
+  if (!h || !f || !u || ncycles < 0) return fail(MG_EINVAL, "bad argument");
+  for (int k = 0; k < ncycles; ++k) RBC_TRY(cycle(h, 0, f, u));
+  return MG_OK;
+}
+
+mg_status mg_rbc_residual_norm(mg_rbc_ctx *h, const double *f, const double *u, double *out) {
+  if (!h || !f || !u || !out) return fail(MG_EINVAL, "bad argument");
+  return norm(h, f, u, out);
+}
+
+mg_status mg_rbc_solve(mg_rbc_ctx *h, const double *f, double *u, int *cycles, double *hist) {
+  if (!h || !f || !u) return fail(MG_EINVAL, "bad argument");
+  double r0 = 0.0, r = 0.0;
+  RBC_TRY(norm(h, f, u, &r0));
+  if (hist) hist[0] = r0;
+  int k = 0;
+  r = r0;
+  mg_status st = MG_OK;
+  while (r > h->cfg.rtol * r0 && k < h->cfg.max_cycles) {
+    RBC_TRY(cycle(h, 0, f, u));
+    RBC_TRY(norm(h, f, u, &r));
+    ++k;
+    if (hist) hist[k] = r;
+    if (!std::isfinite(r)) {
+      st = fail(MG_ENUMERIC, "residual norm is not finite");
+      break;
+    }
+  }
+  if (cycles) *cycles = k;
+  if (st == MG_OK && r > h->cfg.rtol * r0) st = fail(MG_ENOCONV, "solve did not reach rtol");
+  return st;
+}
+
+mg_status mg_rbc_kernel_smooth(mg_rbc_ctx *h, int level, int colour, const double *f,
+                               const double *u_in, double *u_out) {
+  RBC_TRY(check_level(h, level, false));
+  if (colour != 1 && colour != 2) return fail(MG_EINVAL, "colour must be 1 (F) or 2 (C)");
+  if (!f || !u_in || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad array arguments");
+  return launch_smooth(h, level, colour, f, u_in, u_out);
+}
+
+mg_status mg_rbc_kernel_restrict(mg_rbc_ctx *h, int level, const double *f, const double *u,
+                                 double *f_coarse) {
+  RBC_TRY(check_level(h, level, true));
+  if (!f || !u || !f_coarse) return fail(MG_EINVAL, "bad array arguments");
+  return launch_restrict(h, level, f, u, f_coarse, nullptr);
+}
+
+mg_status mg_rbc_kernel_prolong(mg_rbc_ctx *h, int level, const double *e_coarse,
+                                const double *u_in, double *u_out) {
+  RBC_TRY(check_level(h, level, true));
+  if (!e_coarse || !u_in || !u_out) return fail(MG_EINVAL, "bad array arguments");
+  return launch_prolong(h, level, e_coarse, u_in, u_out);
+}
+
+mg_status mg_rbc_kernel_coarsest(mg_rbc_ctx *h, const double *f, double *u) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  if (!f || !u) return fail(MG_EINVAL, "bad array arguments");
+  return launch_coarsest(h, f, u);
+}
+
+}  // extern "C"

@@ -7,7 +7,7 @@ import re
 import pytest
 
 from conftest import ROOT
-from paper_2008_03885_amd import mg, serve
+from paper_2008_03885_amd import mg, rbc, serve
 
 
 def _declared_functions():
@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in _declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     # the bindings cover the same names
-    assert set(_declared_functions()) <= set(mg._SIGS) | set(serve._SIGS)
+    assert set(_declared_functions()) <= set(mg._SIGS) | set(serve._SIGS) | set(rbc._SIGS)
 
 
 @pytest.mark.parametrize("kwargs", [
@@ -139,3 +139,28 @@ def test_red_black_footprint_counts_the_third_sweep_target(nu1, nu2, extra):
     passes = max(1, nu1) + max(1, nu2)
     assert rb - base == (t2 if passes % 2 == 1 else 0)
     assert (rb > base) == extra
+
+
+@pytest.mark.parametrize("kwargs", [
+    dict(n=100), dict(n=2), dict(levels=1), dict(n=17, levels=9), dict(n=129, levels=2),
+    dict(coarse=3), dict(gamma=3), dict(nu1=0, nu2=0), dict(nu1=9), dict(omega=2.0),
+    dict(omega=-1.0), dict(max_cycles=0), dict(rtol=-1.0),
+])
+def test_red_black_coarsening_invalid_configs_rejected(kwargs):
+    """mg_rbc_setup validates before touching the device: too many levels for n, a
+    coarsest level above MG_RBC_MAX_COARSEST unknowns (129 with two levels), bad enums."""
+    cfg = rbc.make_config(**{**dict(n=17, levels=4), **kwargs})
+    h = ctypes.c_void_p()
+    st = rbc.lib().mg_rbc_setup(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == mg.MG_EINVAL
+    assert h.value is None
+    assert mg.last_error() != ""
+
+
+def test_red_black_coarsening_enums_match_the_header():
+    with open(os.path.join(ROOT, "include", "mg_rbc.h")) as fh:
+        text = fh.read()
+    m = re.search(r"enum \{ MG_RBC_NG = (\d), MG_RBC_G1 = (\d), MG_RBC_GN = (\d) \}", text)
+    assert tuple(int(v) for v in m.groups()) == (rbc.MG_RBC_NG, rbc.MG_RBC_G1, rbc.MG_RBC_GN)
+    assert "#define MG_RBC_MAX_COARSEST %d" % rbc.MG_RBC_MAX_COARSEST in text
+    assert rbc.lib().mg_rbc_level_size(None, 0) == -1
