@@ -84,6 +84,7 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=120,
                    help="requests per serving run (0: skip the serving measurement)")
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement")
+    p.add_argument("--rbc-only", action="store_true", help="only the red-black coarsening runs")
     return p.parse_args()
 
 
@@ -472,6 +473,85 @@ def serve_bench(count, loads=(0.5, 0.8), smoother=0, inner=4):
         S.close()
 
 
+RBC_VARIANTS = (  # coarse, nu1, nu2, omega: section 4.4's G1 and Gn and the rediscretized operator
+    ("G1", 1, 1, 1.0), ("G1", 2, 1, 1.0), ("G1", 2, 1, 1.2), ("GN", 1, 1, 1.0), ("NG", 1, 1, 1.0))
+
+
+def rbc_bench(fd, stream, n, reps, cpu=True):
+    """Red-black coarsening (section 4.3, 4.4) on the second-order five-point problem with
+    the same right-hand side: V-cycles down to a rotated 9x9 storage level (25 unknowns,
+    20 levels at n = 4097), solved from zero to 1e-10.  Also the level-0 partial step's
+    HBM rate (20 algorithmic bytes a point: u read and written, f read at half the points)
+    and the CPU oracle on a bounded sample."""
+    import numpy as np
+    import torch
+    from paper_2008_03885_amd import rbc
+    levels = 1
+    while True:
+        side = (n - 1) // 2 ** (levels // 2) + 1
+        if side < 9:
+            break
+        levels += 1
+    unknowns = (n - 2) ** 2
+    out = {"levels": levels, "problem": "second-order five-point operator, same right-hand side",
+           "variants": {}}
+    s = stream.cuda_stream
+    ud = torch.zeros_like(fd)
+    for coarse, nu1, nu2, om in RBC_VARIANTS:
+        cfg = rbc.make_config(n=n, levels=levels, coarse=getattr(rbc, "MG_RBC_" + coarse), gamma=1,
+                              nu1=nu1, nu2=nu2, omega=om, rtol=1e-10, max_cycles=60)
+        h = rbc.setup(cfg, s)
+        times, cyc, hist = [], 0, []
+        for k in range(reps + 1):
+            ud.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, hist = rbc.solve(h, fd.data_ptr(), ud.data_ptr(), 60)
+            torch.cuda.synchronize()
+            if k:
+                times.append(time.perf_counter() - t0)
+        sec = min(times)
+        name = "%s-V(%d,%d)-omega%g" % (coarse, nu1, nu2, om)
+        out["variants"][name] = {"ms": 1e3 * sec, "unknowns_per_s": unknowns / sec, "cycles": cyc,
+                                 "rel_residual": hist[-1] / hist[0], "status": st}
+        if (coarse, nu1, nu2, om) == RBC_VARIANTS[0]:
+            # cycles alone, HIP events on the handle's stream (the solve adds one norm a cycle)
+            t = event_time(stream, lambda: rbc.cycles(h, fd.data_ptr(), ud.data_ptr(), 1), 10)
+            out["cycle_ms"] = 1e3 * t
+            tmp = torch.empty_like(fd)
+            ps = event_time(stream, lambda: rbc.kernel_smooth(h, 0, 1, fd.data_ptr(), ud.data_ptr(),
+                                                              tmp.data_ptr()), 50)
+            byts = 20.0 * n * n
+            out["roofline"] = {"bound": "hbm", "kernel": "k_rbc_smooth level 0 (one partial step, FP64)",
+                               "achieved": byts / ps / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": byts / ps / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "avg_launch_us": ps * 1e6, "algorithmic_bytes_per_launch": byts}
+            del tmp
+        rbc.destroy(h)
+    if cpu:
+        from oracle import rbc as orbc
+        nc = 1025
+        lv = 1
+        while (nc - 1) // 2 ** (lv // 2) + 1 >= 9:
+            lv += 1
+        o = orbc.RBC(nc, lv, coarse=orbc.G1, nu1=1, nu2=1, omega=1.0)
+        fs = np.zeros((nc, nc))
+        fs[1:-1, 1:-1] = np.random.default_rng(1).standard_normal((nc - 2, nc - 2))
+        u = np.zeros((nc, nc))
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10.0 or k < 1:
+            u = o.cycle(fs, u)
+            k += 1
+        per_cycle = (time.perf_counter() - t0) / k
+        cyc = out["variants"]["G1-V(1,1)-omega1"]["cycles"]
+        out["cpu_baseline"] = {"value": (nc - 2) ** 2 / (per_cycle * cyc), "unit": "unknowns/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "%d G1 V(1,1) cycles of the numpy oracle at 1025^2 (%d levels), "
+                                         "scaled to the %d cycles of the GPU solve" % (k, lv, cyc)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -494,6 +574,10 @@ def main():
     f, coeffs = make_rhs(w)
     fd = torch.from_numpy(f).cuda()
     del f
+    if args.rbc_only:
+        print(json.dumps({"red_black_coarsening": rbc_bench(fd, stream, w["n"], args.steps,
+                                                            cpu=not args.no_cpu)}), flush=True)
+        return
     d, n = w["dim"], w["n"]
     unknowns = (n - 2) ** d
 
@@ -637,6 +721,8 @@ def main():
         out["levels"] = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
                          for r in rows]
     main_run.close()
+    if args.workload == "poisson2d-4097" and not args.no_variants:
+        out["red_black_coarsening"] = rbc_bench(fd, stream, n, 3, cpu=not args.no_cpu)
     if args.serve_requests > 0 and args.workload == "poisson2d-4097":
         del fd
         out["serving"] = serve_bench(args.serve_requests)

@@ -79,30 +79,82 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restric
   uout[p] = v;
 }
 
-// Defect at the C point and its four F neighbours, restricted with eq. transfer_r2 onto
-// the next level's storage grid (side mc); zero off the next level's unknowns.  uc (may
-// be null) is zeroed: the next level starts from a zero correction.
-__global__ __launch_bounds__(kBX *kBY) void k_rbc_restrict(const double *__restrict__ f,
-                                                           const double *__restrict__ u,
-                                                           double *__restrict__ fc,
-                                                           double *__restrict__ uc, int m,
-                                                           int odd, Op op, int mc) {
-  const int J = blockIdx.x * kBX + threadIdx.x;
-  const int I = blockIdx.y * kBY + threadIdx.y;
-  if (I >= mc || J >= mc) return;
-  const size_t q = (size_t)I * mc + J;
-  double v = 0.0;
-  if (unknown(!odd, mc, I, J)) {
-    const int i = odd ? 2 * I : I, j = odd ? 2 * J : J;
-    auto r = [&](int a, int b) {
-      return unknown(odd, m, a, b) ? f[(size_t)a * m + b] - apply_op(u, m, a, b, op) : 0.0;
-    };
-    const double s = odd ? (r(i - 1, j - 1) + r(i - 1, j + 1)) + (r(i + 1, j - 1) + r(i + 1, j + 1))
-                         : (r(i - 1, j) + r(i + 1, j)) + (r(i, j - 1) + r(i, j + 1));
-    v = (4.0 * r(i, j) + s) * 0.125;
+// Defect restricted with eq. transfer_r2 onto the next level's storage grid (side mc),
+// zero off the next level's unknowns; uc (may be null) is zeroed, the next level starting
+// from a zero correction.  A block takes a kRTY x kRTX tile of level l's storage grid:
+// u with a 3-point halo (the defect one point outside the tile reaches two further) goes
+// to LDS, with the odd reflection written into the halo beyond the boundary lines; the
+// defect over the tile and a 1-point ring is formed once in LDS; each C point of the tile
+// then gathers itself and its four F neighbours.
+constexpr int kRTX = 64, kRTY = 16;
+
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__ f,
+                                                      const double *__restrict__ u,
+                                                      double *__restrict__ fc,
+                                                      double *__restrict__ uc, int m, Op op,
+                                                      int mc) {
+  constexpr int UX = kRTX + 6, UY = kRTY + 6, RX = kRTX + 2, RY = kRTY + 2;
+  __shared__ double su[UY][UX];
+  __shared__ double sr[RY][RX];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.y * kRTY, j0 = blockIdx.x * kRTX;
+  for (int q = t; q < UY * UX; q += 256) {
+    const int a = i0 - 3 + q / UX, b = j0 - 3 + q % UX;
+    const bool ain = a >= 0 && a < m, bin = b >= 0 && b < m;
+    double v = 0.0;  // never read unless one index is at most one point outside
+    if (ain && bin)
+      v = u[(size_t)a * m + b];
+    else if ((ain && (b == -1 || b == m)) || (bin && (a == -1 || a == m)))
+      v = tap(u, m, a, b);
+    su[q / UX][q % UX] = v;
   }
-  fc[q] = v;
-  if (uc) uc[q] = 0.0;
+  __syncthreads();
+  for (int q = t; q < RY * RX; q += 256) {
+    const int x = q / RX, y = q % RX;  // sr[x][y] is the point (i0 - 1 + x, j0 - 1 + y)
+    const int a = i0 - 1 + x, b = j0 - 1 + y;
+    double r = 0.0;
+    if (unknown(ODD, m, a, b)) {
+      const int X = x + 2, Y = y + 2;  // the same point in su
+      double v = op.c0 * su[X][Y];
+      if (op.a1 != 0.0) v += op.a1 * ((su[X - 1][Y] + su[X + 1][Y]) + (su[X][Y - 1] + su[X][Y + 1]));
+      if (op.d1 != 0.0)
+        v += op.d1 * ((su[X - 1][Y - 1] + su[X - 1][Y + 1]) + (su[X + 1][Y - 1] + su[X + 1][Y + 1]));
+      if (op.a2 != 0.0)
+        v += op.a2 * ((su[X - 2][Y] + su[X + 2][Y]) + (su[X][Y - 2] + su[X][Y + 2]));
+      r = f[(size_t)a * m + b] - v;
+    }
+    sr[x][y] = r;
+  }
+  __syncthreads();
+  if (ODD) {
+    // coarse point (I, J) sits at fine (2I, 2J); its F neighbours are the diagonals
+    for (int q = t; q < (kRTY / 2) * (kRTX / 2); q += 256) {
+      const int I = i0 / 2 + q / (kRTX / 2), J = j0 / 2 + q % (kRTX / 2);
+      if (I >= mc || J >= mc) continue;
+      double v = 0.0;
+      if (unknown(false, mc, I, J)) {
+        const int x = 2 * I - i0 + 1, y = 2 * J - j0 + 1;
+        v = (4.0 * sr[x][y] + ((sr[x - 1][y - 1] + sr[x - 1][y + 1]) + (sr[x + 1][y - 1] + sr[x + 1][y + 1]))) *
+            0.125;
+      }
+      fc[(size_t)I * mc + J] = v;
+      if (uc) uc[(size_t)I * mc + J] = 0.0;
+    }
+  } else {
+    // the next (rotated) level shares this storage grid; F neighbours are the axis ones
+    for (int q = t; q < kRTY * kRTX; q += 256) {
+      const int a = i0 + q / kRTX, b = j0 + q % kRTX;
+      if (a >= m || b >= m) continue;
+      double v = 0.0;
+      if (unknown(true, m, a, b)) {
+        const int x = a - i0 + 1, y = b - j0 + 1;
+        v = (4.0 * sr[x][y] + ((sr[x - 1][y] + sr[x + 1][y]) + (sr[x][y - 1] + sr[x][y + 1]))) * 0.125;
+      }
+      fc[(size_t)a * m + b] = v;
+      if (uc) uc[(size_t)a * m + b] = 0.0;
+    }
+  }
 }
 
 // u_out = u_in + interpolated correction: C points take the coarse value, F points the
@@ -328,8 +380,11 @@ mg_status launch_restrict(mg_rbc_ctx *h, int l, const double *f, const double *u
                           double *uc) {
   const Level &L = h->lv[l];
   const int mc = h->lv[l + 1].m;
-  hipLaunchKernelGGL(k_rbc_restrict, grid_for(mc), dim3(kBX, kBY), 0, h->stream, f, u, fc, uc,
-                     L.m, (int)L.odd, L.op, mc);
+  const dim3 grid((L.m + kRTX - 1) / kRTX, (L.m + kRTY - 1) / kRTY);
+  if (L.odd)
+    hipLaunchKernelGGL(k_rbc_restrict<true>, grid, dim3(256), 0, h->stream, f, u, fc, uc, L.m, L.op, mc);
+  else
+    hipLaunchKernelGGL(k_rbc_restrict<false>, grid, dim3(256), 0, h->stream, f, u, fc, uc, L.m, L.op, mc);
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }

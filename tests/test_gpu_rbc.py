@@ -107,6 +107,7 @@ CYCLE_CASES = [
     (9, 2, "G1", 1, 1, 1, 1.0, 2), (65, 8, "G1", 1, 1, 1, 1.0, 3), (65, 8, "GN", 2, 1, 1, 1.0, 3),
     (129, 10, "NG", 1, 2, 1, 1.1, 3), (129, 9, "G1", 2, 1, 1, 1.0, 2), (257, 12, "G1", 1, 0, 2, 1.2, 3),
     (1025, 16, "GN", 1, 1, 1, 1.0, 2), (17, 3, "NG", 2, 2, 2, 0.9, 3),
+    (1025, 16, "G1", 1, 2, 2, 1.1, 2), (1025, 15, "NG", 1, 1, 0, 1.0, 2), (513, 14, "G1", 1, 0, 3, 1.0, 2),
 ]
 
 
@@ -181,6 +182,8 @@ def test_errors_are_reported():
         with pytest.raises(mg.MGError):
             rbc.kernel_smooth(P.h, 0, 3, 1, 2, 3)
         with pytest.raises(mg.MGError):
-            rbc.kernel_restrict(P.h, 3, 1, 2, 3)  # the last level has no next level
+            rbc.kernel_restrict(P.h, 3, 1, 2, 3)
+        with pytest.raises(mg.MGError):
+            rbc.kernel_smooth(P.h, 0, 1, 1, 2, 2)  # in place is not allowed  # the last level has no next level
     finally:
         P.close()
