@@ -15,8 +15,10 @@
  * level 1 is the rotated grid of spacing sqrt(2) h (the level-0 points with an even index
  * sum), level 2 the standard grid of spacing 2h, and so on.  Level l is stored on the
  * standard grid of spacing 2^(l/2) h that holds it: mg_rbc_level_size(l) = (n - 1)/2^(l/2)
- * + 1 points a side; on an odd level only the interior points with an even index sum
- * are unknowns and every other entry of its arrays is zero.  Within a level the C points
+ * + 1 points a side.  An odd (rotated) level's points are those with an even index sum,
+ * and its arrays keep only them: m rows of pitch mg_rbc_level_pitch(l) = (m + 1)/2, point
+ * (i, j) at i*pitch + j/2 (the last entry of an odd row is padding, kept zero).  An even
+ * level's arrays are m x m (pitch m).  Within a level the C points
  * (black) are those kept on the next level (even index sum on an even level, both indices
  * even on an odd one) and the F points (red) the others.
  *
@@ -70,8 +72,10 @@ typedef struct mg_rbc_ctx mg_rbc_ctx;
 mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out);
 void mg_rbc_destroy(mg_rbc_ctx *h);
 
-/* Side of level l's storage grid, or -1 if l is out of range. */
+/* Side m of level l's storage grid, or -1 if l is out of range. */
 int mg_rbc_level_size(const mg_rbc_ctx *h, int level);
+/* Row pitch of level l's arrays (m, or (m + 1)/2 on a rotated level), or -1. */
+int mg_rbc_level_pitch(const mg_rbc_ctx *h, int level);
 
 /* `ncycles` cycles on u (device, n*n, updated in place) for right-hand side f. */
 mg_status mg_rbc_cycles(mg_rbc_ctx *h, const double *f, double *u, int ncycles);
@@ -85,7 +89,7 @@ mg_status mg_rbc_solve(mg_rbc_ctx *h, const double *f, double *u, int *cycles, d
 /* sqrt(mean over the interior of (f - L_0 u)^2) into *out (host); blocks. */
 mg_status mg_rbc_residual_norm(mg_rbc_ctx *h, const double *f, const double *u, double *out);
 
-/* Single steps on the arrays of one level (device, level-size squared), for testing.
+/* Single steps on the arrays of one level (device, m x pitch doubles), for testing.
  * smooth: one omega-Jacobi partial step on the F points (colour 1) or the C points
  *   (colour 2) from u_in into u_out (every other entry copied); u_in != u_out.
  * restrict: the defect f - L_l u restricted onto level l + 1's grid into f_coarse (zero

@@ -1,8 +1,10 @@
 // rbc.hip -- red-black coarsening multigrid in two dimensions (section 4.3 Theorem 3,
 // section 4.4), FP64.
 //
-// Level l lives on the standard grid of spacing 2^(l/2) h that holds it (side m); an odd
-// level is rotated and uses only the interior points with an even index sum.  Every
+// Level l lives on the standard grid of spacing 2^(l/2) h that holds it (side m).  An odd
+// level is rotated: its points are those with an even index sum, and its arrays keep only
+// them, row i holding (i, j) at column j/2 (row pitch (m + 1)/2; the odd rows' last entry
+// is padding and stays zero).  Every
 // level's operator is a symmetric stencil of at most four coefficients on that storage
 // grid: centre, axis neighbours at distance 1, diagonal neighbours, axis neighbours at
 // distance 2.  All steps are one thread per storage point: the defect, the transfers and
@@ -63,19 +65,62 @@ __device__ __forceinline__ double apply_op(const double *u, int m, int i, int j,
   return v;
 }
 
-// One omega-Jacobi partial step on the F points (colour 1) or the C points (colour 2).
+__host__ __device__ __forceinline__ int rot_pitch(int m) { return (m + 1) / 2; }
+
+// A point of a rotated level's packed array beyond the boundary lines by at most one
+// point: minus its mirror image (rotated levels are coarse, with zero boundary values).
+__device__ __forceinline__ double rot_tap(const double *u, int m, int w, int a, int b) {
+  if (a < 0) return -u[(size_t)(-a) * w + (b >> 1)];
+  if (a >= m) return -u[(size_t)(2 * (m - 1) - a) * w + (b >> 1)];
+  if (b < 0) return -u[(size_t)a * w + ((-b) >> 1)];
+  if (b >= m) return -u[(size_t)a * w + ((2 * (m - 1) - b) >> 1)];
+  return u[(size_t)a * w + (b >> 1)];
+}
+
+// L u at an interior point of a rotated level (packed, pitch w): the diagonal taps and
+// the axis taps at distance 2 (the axis-1 coefficient of a rotated level is zero).
+__device__ __forceinline__ double apply_rot(const double *u, int m, int w, int i, int j,
+                                            const Op &op) {
+  const int jl = (j - 1) >> 1, jr = (j + 1) >> 1;
+  const size_t up = (size_t)(i - 1) * w, dn = (size_t)(i + 1) * w;
+  double v = op.c0 * u[(size_t)i * w + (j >> 1)];
+  v += op.d1 * ((u[up + jl] + u[up + jr]) + (u[dn + jl] + u[dn + jr]));
+  if (op.a2 != 0.0)
+    v += op.a2 * ((rot_tap(u, m, w, i - 2, j) + rot_tap(u, m, w, i + 2, j)) +
+                  (rot_tap(u, m, w, i, j - 2) + rot_tap(u, m, w, i, j + 2)));
+  return v;
+}
+
+// One omega-Jacobi partial step on the F points (colour 1) or the C points (colour 2) of
+// a standard level.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restrict__ f,
                                                          const double *__restrict__ uin,
                                                          double *__restrict__ uout, int m,
-                                                         int odd, Op op, int colour,
-                                                         double omega) {
+                                                         Op op, int colour, double omega) {
   const int j = blockIdx.x * kBX + threadIdx.x;
   const int i = blockIdx.y * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
   const size_t p = (size_t)i * m + j;
   double v = uin[p];
-  if (unknown(odd, m, i, j) && cpoint(odd, i, j) == (colour == 2))
+  if (unknown(false, m, i, j) && cpoint(false, i, j) == (colour == 2))
     v += omega * (f[p] - apply_op(uin, m, i, j, op)) / op.c0;
+  uout[p] = v;
+}
+
+// The same on a rotated level, one thread per packed entry.
+__global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth_rot(const double *__restrict__ f,
+                                                             const double *__restrict__ uin,
+                                                             double *__restrict__ uout, int m,
+                                                             Op op, int colour, double omega) {
+  const int w = rot_pitch(m);
+  const int k = blockIdx.x * kBX + threadIdx.x;
+  const int i = blockIdx.y * kBY + threadIdx.y;
+  if (i >= m || k >= w) return;
+  const int j = 2 * k + (i & 1);
+  const size_t p = (size_t)i * w + k;
+  double v = uin[p];
+  if (j < m && unknown(true, m, i, j) && cpoint(true, i, j) == (colour == 2))
+    v += omega * (f[p] - apply_rot(uin, m, w, i, j, op)) / op.c0;
   uout[p] = v;
 }
 
@@ -99,14 +144,19 @@ __global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__
   __shared__ double sr[RY][RX];
   const int t = threadIdx.x;
   const int i0 = blockIdx.y * kRTY, j0 = blockIdx.x * kRTX;
+  const int w = ODD ? rot_pitch(m) : m;  // pitch of this level's arrays
   for (int q = t; q < UY * UX; q += 256) {
     const int a = i0 - 3 + q / UX, b = j0 - 3 + q % UX;
     const bool ain = a >= 0 && a < m, bin = b >= 0 && b < m;
+    const bool near = (ain && (b == -1 || b == m)) || (bin && (a == -1 || a == m));
     double v = 0.0;  // never read unless one index is at most one point outside
-    if (ain && bin)
+    if (ODD) {
+      if (((a + b) & 1) == 0 && ((ain && bin) || near)) v = rot_tap(u, m, w, a, b);
+    } else if (ain && bin) {
       v = u[(size_t)a * m + b];
-    else if ((ain && (b == -1 || b == m)) || (bin && (a == -1 || a == m)))
+    } else if (near) {
       v = tap(u, m, a, b);
+    }
     su[q / UX][q % UX] = v;
   }
   __syncthreads();
@@ -122,7 +172,7 @@ __global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__
         v += op.d1 * ((su[X - 1][Y - 1] + su[X - 1][Y + 1]) + (su[X + 1][Y - 1] + su[X + 1][Y + 1]));
       if (op.a2 != 0.0)
         v += op.a2 * ((su[X - 2][Y] + su[X + 2][Y]) + (su[X][Y - 2] + su[X][Y + 2]));
-      r = f[(size_t)a * m + b] - v;
+      r = f[(size_t)a * w + (ODD ? b >> 1 : b)] - v;
     }
     sr[x][y] = r;
   }
@@ -142,41 +192,63 @@ __global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__
       if (uc) uc[(size_t)I * mc + J] = 0.0;
     }
   } else {
-    // the next (rotated) level shares this storage grid; F neighbours are the axis ones
+    // the next (rotated) level's points are this grid's even-index-sum points, packed;
+    // F neighbours are the axis ones
+    const int wc = rot_pitch(m);
     for (int q = t; q < kRTY * kRTX; q += 256) {
       const int a = i0 + q / kRTX, b = j0 + q % kRTX;
-      if (a >= m || b >= m) continue;
+      if (a >= m || b >= m || ((a + b) & 1)) continue;
       double v = 0.0;
       if (unknown(true, m, a, b)) {
         const int x = a - i0 + 1, y = b - j0 + 1;
         v = (4.0 * sr[x][y] + ((sr[x - 1][y] + sr[x + 1][y]) + (sr[x][y - 1] + sr[x][y + 1]))) * 0.125;
       }
-      fc[(size_t)a * m + b] = v;
-      if (uc) uc[(size_t)a * m + b] = 0.0;
+      fc[(size_t)a * wc + (b >> 1)] = v;
+      if (uc) uc[(size_t)a * wc + (b >> 1)] = 0.0;
     }
   }
 }
 
 // u_out = u_in + interpolated correction: C points take the coarse value, F points the
-// mean of their four C neighbours (eq. transfer_r2).
+// mean of their four C neighbours (eq. transfer_r2).  Standard level: the correction
+// comes from the rotated level below, packed with pitch (m + 1)/2.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restrict__ ec,
                                                           const double *uin, double *uout,
-                                                          int m, int odd, int mc) {
+                                                          int m) {
   const int j = blockIdx.x * kBX + threadIdx.x;
   const int i = blockIdx.y * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
+  const int wc = rot_pitch(m);
   const size_t p = (size_t)i * m + j;
   double v = uin[p];
-  if (unknown(odd, m, i, j)) {
-    auto e = [&](int a, int b) {
-      return odd ? ec[(size_t)(a >> 1) * mc + (b >> 1)] : ec[(size_t)a * mc + b];
-    };
-    if (cpoint(odd, i, j))
+  if (unknown(false, m, i, j)) {
+    auto e = [&](int a, int b) { return ec[(size_t)a * wc + (b >> 1)]; };  // a + b even
+    if (cpoint(false, i, j))
       v += e(i, j);
-    else if (odd)
-      v += 0.25 * ((e(i - 1, j - 1) + e(i - 1, j + 1)) + (e(i + 1, j - 1) + e(i + 1, j + 1)));
     else
       v += 0.25 * ((e(i - 1, j) + e(i + 1, j)) + (e(i, j - 1) + e(i, j + 1)));
+  }
+  uout[p] = v;
+}
+
+// The same on a rotated level (packed), the correction from the standard level below
+// (side mc): C points (both indices even) copy, F points (both odd) average the diagonals.
+__global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__restrict__ ec,
+                                                              const double *uin, double *uout,
+                                                              int m, int mc) {
+  const int w = rot_pitch(m);
+  const int k = blockIdx.x * kBX + threadIdx.x;
+  const int i = blockIdx.y * kBY + threadIdx.y;
+  if (i >= m || k >= w) return;
+  const int j = 2 * k + (i & 1);
+  const size_t p = (size_t)i * w + k;
+  double v = uin[p];
+  if (j < m && unknown(true, m, i, j)) {
+    auto e = [&](int a, int b) { return ec[(size_t)(a >> 1) * mc + (b >> 1)]; };
+    if (cpoint(true, i, j))
+      v += e(i, j);
+    else
+      v += 0.25 * ((e(i - 1, j - 1) + e(i - 1, j + 1)) + (e(i + 1, j - 1) + e(i + 1, j + 1)));
   }
   uout[p] = v;
 }
@@ -227,7 +299,7 @@ __global__ __launch_bounds__(256) void k_rbc_coarsest(const double *__restrict__
     if (op.a2 != 0.0) {
       add(i - 2, j, op.a2); add(i + 2, j, op.a2); add(i, j - 2, op.a2); add(i, j + 2, op.a2);
     }
-    b[row] = f[p];
+    b[row] = f[odd ? (size_t)i * rot_pitch(m) + (j >> 1) : (size_t)p];
   }
   __syncthreads();
   for (int k = 0; k < K; ++k) {
@@ -248,7 +320,11 @@ __global__ __launch_bounds__(256) void k_rbc_coarsest(const double *__restrict__
     }
   }
   __syncthreads();
-  for (int p = t; p < m * m; p += blockDim.x) u[p] = idx[p] >= 0 ? b[idx[p]] : 0.0;
+  const int w = odd ? rot_pitch(m) : m;
+  for (int p = t; p < m * w; p += blockDim.x) {
+    const int i = p / w, j = odd ? 2 * (p % w) + (i & 1) : p % w;
+    u[p] = j < m && idx[i * m + j] >= 0 ? b[idx[i * m + j]] : 0.0;
+  }
 }
 
 // Per-block sums of the squared level-0 defect over the interior.
@@ -330,6 +406,9 @@ Op level_op(const mg_rbc_config &c, int l) {
   return Op{3.0 / H2, 0.0, -0.5 / H2, -0.25 / H2};
 }
 
+// Entries of a level's arrays: m^2, or m rows of (m + 1)/2 on a rotated level.
+size_t level_entries(const Level &L) { return (size_t)L.m * (L.odd ? rot_pitch(L.m) : L.m); }
+
 dim3 grid_for(int m) { return dim3((m + kBX - 1) / kBX, (m + kBY - 1) / kBY); }
 
 }  // namespace
@@ -370,8 +449,12 @@ mg_status launch_smooth(mg_rbc_ctx *h, int l, int colour, const double *f, const
                         double *uout) {
   const Level &L = h->lv[l];
   const double omega = h->cfg.omega == 0.0 ? 1.0 : h->cfg.omega;
-  hipLaunchKernelGGL(k_rbc_smooth, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, f, uin, uout,
-                     L.m, (int)L.odd, L.op, colour, omega);
+  if (L.odd)
+    hipLaunchKernelGGL(k_rbc_smooth_rot, dim3((rot_pitch(L.m) + kBX - 1) / kBX, (L.m + kBY - 1) / kBY),
+                       dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m, L.op, colour, omega);
+  else
+    hipLaunchKernelGGL(k_rbc_smooth, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m,
+                       L.op, colour, omega);
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }
@@ -391,8 +474,11 @@ mg_status launch_restrict(mg_rbc_ctx *h, int l, const double *f, const double *u
 
 mg_status launch_prolong(mg_rbc_ctx *h, int l, const double *ec, const double *uin, double *uout) {
   const Level &L = h->lv[l];
-  hipLaunchKernelGGL(k_rbc_prolong, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, ec, uin, uout,
-                     L.m, (int)L.odd, h->lv[l + 1].m);
+  if (L.odd)
+    hipLaunchKernelGGL(k_rbc_prolong_rot, dim3((rot_pitch(L.m) + kBX - 1) / kBX, (L.m + kBY - 1) / kBY),
+                       dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m, h->lv[l + 1].m);
+  else
+    hipLaunchKernelGGL(k_rbc_prolong, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m);
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }
@@ -477,7 +563,7 @@ mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out)
   h->f.assign(cfg->levels, nullptr);
   h->t.assign(cfg->levels, nullptr);
   for (int l = 0; l < cfg->levels && ok; ++l) {
-    const size_t cnt = (size_t)h->lv[l].m * h->lv[l].m;
+    const size_t cnt = level_entries(h->lv[l]);
     if (l > 0) ok = ok && alloc(&h->u[l], cnt) && alloc(&h->f[l], cnt);
     ok = ok && alloc(&h->t[l], cnt);
   }
@@ -489,9 +575,10 @@ mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out)
   }
   // every level array starts at zero: their boundaries and off-grid entries stay zero
   for (int l = 1; l < cfg->levels; ++l) {
-    const size_t bytes = (size_t)h->lv[l].m * h->lv[l].m * sizeof(double);
+    const size_t bytes = level_entries(h->lv[l]) * sizeof(double);
     hipError_t e = hipMemsetAsync(h->u[l], 0, bytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->f[l], 0, bytes, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->t[l], 0, bytes, h->stream);
     if (e != hipSuccess) {
       mg_rbc_destroy(h);
       return fail(MG_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
@@ -520,6 +607,11 @@ void mg_rbc_destroy(mg_rbc_ctx *h) {
 int mg_rbc_level_size(const mg_rbc_ctx *h, int level) {
   if (!h || level < 0 || level >= (int)h->lv.size()) return -1;
   return h->lv[level].m;
+}
+
+int mg_rbc_level_pitch(const mg_rbc_ctx *h, int level) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return -1;
+  return h->lv[level].odd ? rot_pitch(h->lv[level].m) : h->lv[level].m;
 }
 
 mg_status mg_rbc_cycles(mg_rbc_ctx *h, const double *f, double *u, int ncycles) {

@@ -25,6 +25,7 @@ _SIGS = {
     "mg_rbc_setup": (_I, [ctypes.POINTER(mg_rbc_config), _V, ctypes.POINTER(_V)]),
     "mg_rbc_destroy": (None, [_V]),
     "mg_rbc_level_size": (_I, [_V, _I]),
+    "mg_rbc_level_pitch": (_I, [_V, _I]),
     "mg_rbc_cycles": (_I, [_V, _V, _V, _I]),
     "mg_rbc_solve": (_I, [_V, _V, _V, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
     "mg_rbc_residual_norm": (_I, [_V, _V, _V, ctypes.POINTER(ctypes.c_double)]),
@@ -72,6 +73,10 @@ def destroy(h):
 
 def level_size(h, level):
     return lib().mg_rbc_level_size(_V(h), int(level))
+
+
+def level_pitch(h, level):
+    return lib().mg_rbc_level_pitch(_V(h), int(level))
 
 
 def cycles(h, f_ptr, u_ptr, count):

@@ -27,6 +27,7 @@ class Pair:
         self.o = orbc.RBC(n, levels, coarse=CFG[coarse], gamma=gamma, nu1=nu1, nu2=nu2, omega=omega)
         for l in range(levels):
             assert rbc.level_size(self.h, l) == self.o.size(l)
+            assert rbc.level_pitch(self.h, l) == (self.o.size(l) + 1) // 2 if l % 2 else self.o.size(l)
 
     def close(self):
         rbc.destroy(self.h)
@@ -36,6 +37,29 @@ def _grid(m, seed, mask=None):
     a = np.zeros((m, m))
     a[1:-1, 1:-1] = np.random.default_rng(seed).standard_normal((m - 2, m - 2))
     return a if mask is None else np.where(mask, a, 0.0)
+
+
+def pack(a, l):
+    """A level's full storage array in the library's layout: rotated (odd) levels keep
+    row i's points (i, j), i + j even, at column j // 2."""
+    if l % 2 == 0:
+        return a
+    m = a.shape[0]
+    out = np.zeros((m, (m + 1) // 2))
+    out[0::2, :] = a[0::2, 0::2]
+    out[1::2, :(m - 1) // 2] = a[1::2, 1::2]
+    return out
+
+
+def unpack(p, l):
+    if l % 2 == 0:
+        return p
+    m = p.shape[0]
+    out = np.zeros((m, m))
+    out[0::2, 0::2] = p[0::2, :]
+    out[1::2, 1::2] = p[1::2, :(m - 1) // 2]
+    assert not p[1::2, -1].any(), "padding of an odd row must stay zero"
+    return out
 
 
 def _close(got, ref, what):
@@ -56,26 +80,29 @@ def test_every_step_on_every_level(n, levels, coarse):
             m = P.o.size(l)
             act, _, _ = P.o.masks(l)
             scale = 1.0 / P.o.spacing(l) ** 2
-            f = _grid(m, 10 * l + 1) * scale
-            u = _grid(m, 10 * l + 2)
-            fd, ud, out = dev(f), dev(u), dev(np.zeros((m, m)))
+            mask = act if l % 2 else None  # a rotated level holds only its own points
+            f = _grid(m, 10 * l + 1, mask) * scale
+            u = _grid(m, 10 * l + 2, mask)
+            fd, ud = dev(pack(f, l)), dev(pack(u, l))
+            out = torch().zeros_like(ud)
             for colour in (1, 2):
                 rbc.kernel_smooth(P.h, l, colour, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
-                _close(host(out), P.o.smooth_colour(l, f, u, colour), "smooth l=%d c=%d" % (l, colour))
+                _close(unpack(host(out), l), P.o.smooth_colour(l, f, u, colour),
+                       "smooth l=%d c=%d" % (l, colour))
             if l == levels - 1:
                 rbc.kernel_coarsest(P.h, fd.data_ptr(), out.data_ptr())
-                _close(host(out), P.o.coarsest_solve(np.where(act, f, 0.0)), "coarsest l=%d" % l)
+                _close(unpack(host(out), l), P.o.coarsest_solve(f), "coarsest l=%d" % l)
                 continue
             mc = P.o.size(l + 1)
-            fc = dev(np.full((mc, mc), 7.0))
+            fc = dev(pack(np.zeros((mc, mc)), l + 1))
             rbc.kernel_restrict(P.h, l, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
-            _close(host(fc), P.o.restrict(l, P.o.residual(l, f, u)), "restrict l=%d" % l)
+            _close(unpack(host(fc), l + 1), P.o.restrict(l, P.o.residual(l, f, u)), "restrict l=%d" % l)
             ec = _grid(mc, 10 * l + 3, P.o.masks(l + 1)[0])
-            ecd = dev(ec)
+            ecd = dev(pack(ec, l + 1))
             rbc.kernel_prolong(P.h, l, ecd.data_ptr(), ud.data_ptr(), out.data_ptr())
-            _close(host(out), u + P.o.prolong(l, ec), "prolong l=%d" % l)
+            _close(unpack(host(out), l), u + P.o.prolong(l, ec), "prolong l=%d" % l)
             rbc.kernel_prolong(P.h, l, ecd.data_ptr(), ud.data_ptr(), ud.data_ptr())  # in place
-            _close(host(ud), u + P.o.prolong(l, ec), "prolong in place l=%d" % l)
+            _close(unpack(host(ud), l), u + P.o.prolong(l, ec), "prolong in place l=%d" % l)
     finally:
         P.close()
 
@@ -92,11 +119,11 @@ def test_full_size_level0_steps():
         for colour in (1, 2):
             rbc.kernel_smooth(P.h, 0, colour, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
             _close(host(out), P.o.smooth_colour(0, f, u, colour), "smooth c=%d" % colour)
-        fc = dev(np.zeros((n, n)))
+        fc = dev(pack(np.zeros((n, n)), 1))
         rbc.kernel_restrict(P.h, 0, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
-        _close(host(fc), P.o.restrict(0, P.o.residual(0, f, u)), "restrict")
+        _close(unpack(host(fc), 1), P.o.restrict(0, P.o.residual(0, f, u)), "restrict")
         ec = _grid(n, 33, P.o.masks(1)[0])
-        rbc.kernel_prolong(P.h, 0, dev(ec).data_ptr(), ud.data_ptr(), out.data_ptr())
+        rbc.kernel_prolong(P.h, 0, dev(pack(ec, 1)).data_ptr(), ud.data_ptr(), out.data_ptr())
         _close(host(out), u + P.o.prolong(0, ec), "prolong")
     finally:
         P.close()
