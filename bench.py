@@ -54,6 +54,9 @@ MEASURED_TRAFFIC = {
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
     # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
     "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
+    # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
+    # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
+    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403290579, "source": "8c568bc4981c79a3"},
 }
 
 
@@ -378,6 +381,29 @@ def pmc_probe(w, run, stream):
                       "kernels": rows}), flush=True)
 
 
+
+def rbc_pmc_probe(fd, stream, n):
+    """A plain copy of known size, then five level-0 red-black coarsening partial steps
+    (k_rbc_smooth), for hardware counters."""
+    import torch
+    from paper_2008_03885_amd import rbc
+    a = torch.ones(256 * 1024 * 1024, device="cuda", dtype=torch.float64)  # 2 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    h = rbc.setup(rbc.make_config(n=n, levels=20), stream.cuda_stream)
+    u = torch.rand_like(fd)
+    out = torch.empty_like(fd)
+    for _ in range(5):
+        rbc.kernel_smooth(h, 0, 1, fd.data_ptr(), u.data_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    rbc.destroy(h)
+    print(json.dumps({"copy_bytes_read": 2 << 30, "copy_bytes_written": 2 << 30,
+                      "kernel": "k_rbc_smooth", "launches": 5, "algorithmic_bytes": 20 * n * n}), flush=True)
+
+
 SERVE_BUDGET = 32 << 30
 
 
@@ -522,9 +548,11 @@ def rbc_bench(fd, stream, n, reps, cpu=True):
             ps = event_time(stream, lambda: rbc.kernel_smooth(h, 0, 1, fd.data_ptr(), ud.data_ptr(),
                                                               tmp.data_ptr()), 50)
             byts = 20.0 * n * n
+            tr = MEASURED_TRAFFIC.get("k_rbc_smooth/f64/rbc.hip/%d" % n)
+            traffic = tr["bytes"] if tr and tr["source"] == source_hash("rbc.hip") else None
             out["roofline"] = {"bound": "hbm", "kernel": "k_rbc_smooth level 0 (one partial step, FP64)",
                                "achieved": byts / ps / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": byts / ps / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "frac": byts / ps / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                                "avg_launch_us": ps * 1e6, "algorithmic_bytes_per_launch": byts}
             del tmp
         rbc.destroy(h)
@@ -574,6 +602,9 @@ def main():
     f, coeffs = make_rhs(w)
     fd = torch.from_numpy(f).cuda()
     del f
+    if args.rbc_only and args.pmc_probe:
+        rbc_pmc_probe(fd, stream, w["n"])
+        return
     if args.rbc_only:
         print(json.dumps({"red_black_coarsening": rbc_bench(fd, stream, w["n"], args.steps,
                                                             cpu=not args.no_cpu)}), flush=True)

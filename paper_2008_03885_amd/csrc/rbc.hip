@@ -67,6 +67,18 @@ __device__ __forceinline__ double apply_op(const double *u, int m, int i, int j,
 
 __host__ __device__ __forceinline__ int rot_pitch(int m) { return (m + 1) / 2; }
 
+// The point-wise kernels run on a 1D grid of gx-wide rows of kBX x kBY tiles.  Blocks are
+// dealt round-robin to the eight XCDs, each with its own L2; the remap gives every XCD a
+// contiguous run of tiles in raster order, so tile rows that share halo rows meet in the
+// same L2.  The first 8 * (total / 8) blocks are remapped, the rest keep their place.
+__device__ __forceinline__ void xcd_tile(int gx, int total, int &tx, int &ty) {
+  int b = blockIdx.x;
+  const int q = total / 8;
+  if (b < 8 * q) b = (b % 8) * q + b / 8;
+  tx = b % gx;
+  ty = b / gx;
+}
+
 // A point of a rotated level's packed array beyond the boundary lines by at most one
 // point: minus its mirror image (rotated levels are coarse, with zero boundary values).
 __device__ __forceinline__ double rot_tap(const double *u, int m, int w, int a, int b) {
@@ -96,9 +108,12 @@ __device__ __forceinline__ double apply_rot(const double *u, int m, int w, int i
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restrict__ f,
                                                          const double *__restrict__ uin,
                                                          double *__restrict__ uout, int m,
-                                                         Op op, int colour, double omega) {
-  const int j = blockIdx.x * kBX + threadIdx.x;
-  const int i = blockIdx.y * kBY + threadIdx.y;
+                                                         Op op, int colour, double omega,
+                                                         int gx, int total) {
+  int tx, ty;
+  xcd_tile(gx, total, tx, ty);
+  const int j = tx * kBX + threadIdx.x;
+  const int i = ty * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
   const size_t p = (size_t)i * m + j;
   double v = uin[p];
@@ -111,10 +126,13 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restric
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth_rot(const double *__restrict__ f,
                                                              const double *__restrict__ uin,
                                                              double *__restrict__ uout, int m,
-                                                             Op op, int colour, double omega) {
+                                                             Op op, int colour, double omega,
+                                                             int gx, int total) {
   const int w = rot_pitch(m);
-  const int k = blockIdx.x * kBX + threadIdx.x;
-  const int i = blockIdx.y * kBY + threadIdx.y;
+  int tx, ty;
+  xcd_tile(gx, total, tx, ty);
+  const int k = tx * kBX + threadIdx.x;
+  const int i = ty * kBY + threadIdx.y;
   if (i >= m || k >= w) return;
   const int j = 2 * k + (i & 1);
   const size_t p = (size_t)i * w + k;
@@ -214,9 +232,11 @@ __global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__
 // comes from the rotated level below, packed with pitch (m + 1)/2.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restrict__ ec,
                                                           const double *uin, double *uout,
-                                                          int m) {
-  const int j = blockIdx.x * kBX + threadIdx.x;
-  const int i = blockIdx.y * kBY + threadIdx.y;
+                                                          int m, int gx, int total) {
+  int tx, ty;
+  xcd_tile(gx, total, tx, ty);
+  const int j = tx * kBX + threadIdx.x;
+  const int i = ty * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
   const int wc = rot_pitch(m);
   const size_t p = (size_t)i * m + j;
@@ -235,10 +255,12 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restri
 // (side mc): C points (both indices even) copy, F points (both odd) average the diagonals.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__restrict__ ec,
                                                               const double *uin, double *uout,
-                                                              int m, int mc) {
+                                                              int m, int mc, int gx, int total) {
   const int w = rot_pitch(m);
-  const int k = blockIdx.x * kBX + threadIdx.x;
-  const int i = blockIdx.y * kBY + threadIdx.y;
+  int tx, ty;
+  xcd_tile(gx, total, tx, ty);
+  const int k = tx * kBX + threadIdx.x;
+  const int i = ty * kBY + threadIdx.y;
   if (i >= m || k >= w) return;
   const int j = 2 * k + (i & 1);
   const size_t p = (size_t)i * w + k;
@@ -409,7 +431,6 @@ Op level_op(const mg_rbc_config &c, int l) {
 // Entries of a level's arrays: m^2, or m rows of (m + 1)/2 on a rotated level.
 size_t level_entries(const Level &L) { return (size_t)L.m * (L.odd ? rot_pitch(L.m) : L.m); }
 
-dim3 grid_for(int m) { return dim3((m + kBX - 1) / kBX, (m + kBY - 1) / kBY); }
 
 }  // namespace
 
@@ -449,12 +470,13 @@ mg_status launch_smooth(mg_rbc_ctx *h, int l, int colour, const double *f, const
                         double *uout) {
   const Level &L = h->lv[l];
   const double omega = h->cfg.omega == 0.0 ? 1.0 : h->cfg.omega;
+  const int gx = ((L.odd ? rot_pitch(L.m) : L.m) + kBX - 1) / kBX, total = gx * ((L.m + kBY - 1) / kBY);
   if (L.odd)
-    hipLaunchKernelGGL(k_rbc_smooth_rot, dim3((rot_pitch(L.m) + kBX - 1) / kBX, (L.m + kBY - 1) / kBY),
-                       dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m, L.op, colour, omega);
+    hipLaunchKernelGGL(k_rbc_smooth_rot, dim3(total), dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m,
+                       L.op, colour, omega, gx, total);
   else
-    hipLaunchKernelGGL(k_rbc_smooth, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m,
-                       L.op, colour, omega);
+    hipLaunchKernelGGL(k_rbc_smooth, dim3(total), dim3(kBX, kBY), 0, h->stream, f, uin, uout, L.m, L.op,
+                       colour, omega, gx, total);
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }
@@ -474,11 +496,13 @@ mg_status launch_restrict(mg_rbc_ctx *h, int l, const double *f, const double *u
 
 mg_status launch_prolong(mg_rbc_ctx *h, int l, const double *ec, const double *uin, double *uout) {
   const Level &L = h->lv[l];
+  const int gx = ((L.odd ? rot_pitch(L.m) : L.m) + kBX - 1) / kBX, total = gx * ((L.m + kBY - 1) / kBY);
   if (L.odd)
-    hipLaunchKernelGGL(k_rbc_prolong_rot, dim3((rot_pitch(L.m) + kBX - 1) / kBX, (L.m + kBY - 1) / kBY),
-                       dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m, h->lv[l + 1].m);
+    hipLaunchKernelGGL(k_rbc_prolong_rot, dim3(total), dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m,
+                       h->lv[l + 1].m, gx, total);
   else
-    hipLaunchKernelGGL(k_rbc_prolong, grid_for(L.m), dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m);
+    hipLaunchKernelGGL(k_rbc_prolong, dim3(total), dim3(kBX, kBY), 0, h->stream, ec, uin, uout, L.m, gx,
+                       total);
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }
