@@ -164,3 +164,4 @@ def test_red_black_coarsening_enums_match_the_header():
     assert tuple(int(v) for v in m.groups()) == (rbc.MG_RBC_NG, rbc.MG_RBC_G1, rbc.MG_RBC_GN)
     assert "#define MG_RBC_MAX_COARSEST %d" % rbc.MG_RBC_MAX_COARSEST in text
     assert rbc.lib().mg_rbc_level_size(None, 0) == -1
+    assert rbc.lib().mg_rbc_level_pitch(None, 0) == -1
