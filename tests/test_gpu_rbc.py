@@ -157,6 +157,22 @@ def test_cycles_match_oracle(n, levels, coarse, gamma, nu1, nu2, omega, cycles):
         P.close()
 
 
+def test_full_size_cycle_matches_oracle():
+    """One G1 V(1,1) cycle at 4097^2 with the 20 levels the benchmark times, from the
+    benchmark's right-hand side, against the oracle's cycle."""
+    from paper_2008_03885_amd import inputs
+    n = 4097
+    print("rbc full-size cycle", n, flush=True)
+    P = Pair(n, 20, "G1", 1, 1, 1, 1.0)
+    try:
+        f = inputs.fourier_rhs(n)
+        fd, ud = dev(f), dev(np.zeros((n, n)))
+        rbc.cycles(P.h, fd.data_ptr(), ud.data_ptr(), 1)
+        _close(host(ud), P.o.cycle(f, np.zeros((n, n))), "u after one 4097^2 cycle")
+    finally:
+        P.close()
+
+
 @pytest.mark.parametrize("n", [3, 5, 9])
 @pytest.mark.parametrize("nu1", [0, 1])
 def test_two_level_cycle_is_a_direct_solver(n, nu1):
