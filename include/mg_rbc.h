@@ -93,7 +93,8 @@ mg_status mg_rbc_residual_norm(mg_rbc_ctx *h, const double *f, const double *u, 
  * smooth: one omega-Jacobi partial step on the F points (colour 1) or the C points
  *   (colour 2) from u_in into u_out (every other entry copied); u_in != u_out.
  * restrict: the defect f - L_l u restricted onto level l + 1's grid into f_coarse (zero
- *   off its unknowns); l < levels - 1.
+ *   off its unknowns; the padding of a packed f_coarse is left as it is, zero in the
+ *   handle's own arrays); l < levels - 1.
  * prolong: u_out = u_in + the interpolated level l + 1 correction e_coarse; in place
  *   allowed; l < levels - 1.
  * coarsest: the exact solve of the last level's equation into u (zero off the unknowns). */
