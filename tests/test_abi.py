@@ -165,3 +165,18 @@ def test_red_black_coarsening_enums_match_the_header():
     assert "#define MG_RBC_MAX_COARSEST %d" % rbc.MG_RBC_MAX_COARSEST in text
     assert rbc.lib().mg_rbc_level_size(None, 0) == -1
     assert rbc.lib().mg_rbc_level_pitch(None, 0) == -1
+
+
+def test_red_black_coarsening_null_arguments_rejected():
+    """Every mg_rbc entry point checks its handle and pointers on the host first."""
+    lib = rbc.lib()
+    assert lib.mg_rbc_setup(None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_cycles(None, None, None, 1) == mg.MG_EINVAL
+    assert lib.mg_rbc_solve(None, None, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_residual_norm(None, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_kernel_smooth(None, 0, 1, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_kernel_restrict(None, 0, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_kernel_prolong(None, 0, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_rbc_kernel_coarsest(None, None, None) == mg.MG_EINVAL
+    lib.mg_rbc_destroy(None)
+    assert mg.last_error() != ""
