@@ -56,7 +56,7 @@ MEASURED_TRAFFIC = {
     "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
-    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403290579, "source": "8c568bc4981c79a3"},
+    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403290610, "source": "fad2c5f458b53c3d"},
 }
 
 
@@ -505,18 +505,20 @@ RBC_VARIANTS = (  # coarse, nu1, nu2, omega: section 4.4's G1 and Gn and the red
 
 def rbc_bench(fd, stream, n, reps, cpu=True):
     """Red-black coarsening (section 4.3, 4.4) on the second-order five-point problem with
-    the same right-hand side: V-cycles down to a rotated 9x9 storage level (25 unknowns,
-    20 levels at n = 4097), solved from zero to 1e-10.  Also the level-0 partial step's
+    the same right-hand side: V-cycles down to the first level of at most
+    MG_RBC_MAX_COARSEST unknowns (17 levels at n = 4097, the last a 17x17 grid with 225
+    unknowns), solved from zero to 1e-10.  Also the level-0 partial step's
     HBM rate (20 algorithmic bytes a point: u read and written, f read at half the points)
     and the CPU oracle on a bounded sample."""
     import numpy as np
     import torch
     from paper_2008_03885_amd import rbc
-    levels = 1
-    while True:
-        side = (n - 1) // 2 ** (levels // 2) + 1
-        if side < 9:
-            break
+    def unknowns_of(l):  # of level l: interior points, only the even-index-sum ones if rotated
+        side = (n - 1) // 2 ** (l // 2) + 1
+        inner = (side - 2) ** 2
+        return inner if l % 2 == 0 else (inner + 1) // 2
+    levels = 2  # the fewest levels whose last one the coarsest solve takes
+    while unknowns_of(levels - 1) > rbc.MG_RBC_MAX_COARSEST:
         levels += 1
     unknowns = (n - 2) ** 2
     out = {"levels": levels, "problem": "second-order five-point operator, same right-hand side",

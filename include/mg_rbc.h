@@ -33,8 +33,8 @@
  *
  * Cycle (levels >= 2): nu1 red-black sweeps (omega-Jacobi on the F points, then on the C
  * points), the defect restricted with (1/8)[. 1 .; 1 4 1; . 1 .] onto the C points,
- * gamma cycles on the next level from a zero guess (one exact dense solve on the last
- * level), the correction interpolated with (1/4)]. 1 .; 1 4 1; . 1 .[ (C points copy, F
+ * gamma cycles on the next level from a zero guess (on the last level one exact solve by
+ * the inverse formed at set-up), the correction interpolated with (1/4)]. 1 .; 1 4 1; . 1 .[ (C points copy, F
  * points take the mean of their four C neighbours) and added, nu2 sweeps.
  *
  * Status codes and mg_last_error() are those of mg.h.  Every call is asynchronous on the
@@ -51,8 +51,9 @@ extern "C" {
 
 enum { MG_RBC_NG = 0, MG_RBC_G1 = 1, MG_RBC_GN = 2 };
 
-/* Unknowns of the coarsest level solved in one workgroup. */
-#define MG_RBC_MAX_COARSEST 64
+/* Most unknowns of the coarsest level, whose inverse is formed at set-up and applied in
+ * one workgroup. */
+#define MG_RBC_MAX_COARSEST 256
 
 typedef struct mg_rbc_config {
   int n;           /* points a side, n - 1 a power of two, n >= 3 */

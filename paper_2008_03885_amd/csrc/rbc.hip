@@ -7,10 +7,10 @@
 // is padding and stays zero).  Every
 // level's operator is a symmetric stencil of at most four coefficients on that storage
 // grid: centre, axis neighbours at distance 1, diagonal neighbours, axis neighbours at
-// distance 2.  All steps are one thread per storage point: the defect, the transfers and
-// the omega-Jacobi partial steps read the few neighbours they need straight from HBM
-// through the caches, and the coarsest level is assembled and factorised inside one
-// workgroup's LDS.
+// distance 2.  The omega-Jacobi partial steps and the interpolation are one thread per
+// array entry, reading the few neighbours they need through the caches; the restriction
+// forms the defect once per point in an LDS tile; the coarsest level is solved by its
+// inverse, formed on the host at set-up and applied in one workgroup.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -275,78 +275,37 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__re
   uout[p] = v;
 }
 
-// Exact solve of the coarsest level (zero boundary values): the operator's matrix over
-// the unknowns (row-major storage order) assembled in LDS, Gaussian elimination without
-// pivoting (the matrix is symmetric positive definite), back substitution.
-__global__ __launch_bounds__(256) void k_rbc_coarsest(const double *__restrict__ f,
-                                                      double *__restrict__ u, int m, int odd,
-                                                      Op op) {
+// Exact solve of the coarsest level: u = A^{-1} f over its K unknowns, with the inverse
+// formed once at set-up (transposed, so that for each column the threads of a row range
+// read consecutive entries) and pos[] giving each unknown's array index.  Every other
+// entry of u (boundary, padding) is set to zero first.  One 1024-thread workgroup: four
+// threads share a row, each summing every fourth column, then the four sums are added.
+__global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *__restrict__ f,
+                                                       double *__restrict__ u,
+                                                       const double *__restrict__ ainv_t,
+                                                       const int *__restrict__ pos, int K,
+                                                       int entries) {
   constexpr int K_MAX = MG_RBC_MAX_COARSEST;
-  __shared__ double A[K_MAX][K_MAX + 1];
-  __shared__ double b[K_MAX], fac[K_MAX];
-  __shared__ int idx[kMaxCoarseSide * kMaxCoarseSide];
-  __shared__ int nk;
+  __shared__ double fs[K_MAX];
+  __shared__ double part[4][K_MAX];
   const int t = threadIdx.x;
-  if (t == 0) {
-    int k = 0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) idx[i * m + j] = unknown(odd, m, i, j) && k < K_MAX ? k++ : -1;
-    nk = k;
-  }
-  for (int q = t; q < K_MAX * (K_MAX + 1); q += blockDim.x) A[q / (K_MAX + 1)][q % (K_MAX + 1)] = 0.0;
+  for (int p = t; p < entries; p += 1024) u[p] = 0.0;
+  for (int c = t; c < K; c += 1024) fs[c] = f[pos[c]];
   __syncthreads();
-  const int K = nk;
-  for (int p = t; p < m * m; p += blockDim.x) {
-    const int row = idx[p];
-    if (row < 0) continue;
-    const int i = p / m, j = p % m;
-    auto add = [&](int a, int c, double w) {
-      // a tap beyond the boundary line is minus its mirror image (zero boundary values)
-      if (a < 0 || a >= m || c < 0 || c >= m) {
-        w = -w;
-        a = a < 0 ? -a : (a >= m ? 2 * (m - 1) - a : a);
-        c = c < 0 ? -c : (c >= m ? 2 * (m - 1) - c : c);
-      }
-      const int col = idx[a * m + c];
-      if (col >= 0) A[row][col] += w;
-    };
-    add(i, j, op.c0);
-    if (op.a1 != 0.0) {
-      add(i - 1, j, op.a1); add(i + 1, j, op.a1); add(i, j - 1, op.a1); add(i, j + 1, op.a1);
+  const int r = t % K_MAX, q = t / K_MAX;
+  if (r < K) {
+    // eight independent partial sums keep eight loads in flight
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int c = q;
+    for (; c + 28 < K; c += 32) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a[v] += ainv_t[(size_t)(c + 4 * v) * K + r] * fs[c + 4 * v];
     }
-    if (op.d1 != 0.0) {
-      add(i - 1, j - 1, op.d1); add(i - 1, j + 1, op.d1);
-      add(i + 1, j - 1, op.d1); add(i + 1, j + 1, op.d1);
-    }
-    if (op.a2 != 0.0) {
-      add(i - 2, j, op.a2); add(i + 2, j, op.a2); add(i, j - 2, op.a2); add(i, j + 2, op.a2);
-    }
-    b[row] = f[odd ? (size_t)i * rot_pitch(m) + (j >> 1) : (size_t)p];
+    for (; c < K; c += 4) a[0] += ainv_t[(size_t)c * K + r] * fs[c];
+    part[q][r] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    if (t < K) fac[t] = t > k ? A[t][k] / A[k][k] : 0.0;
-    __syncthreads();
-    for (int q = t; q < K * K; q += blockDim.x) {
-      const int i = q / K, j = q % K;
-      if (i > k && j >= k) A[i][j] -= fac[i] * A[k][j];
-    }
-    if (t > k && t < K) b[t] -= fac[t] * b[k];
-    __syncthreads();
-  }
-  if (t == 0) {
-    for (int i = K - 1; i >= 0; --i) {
-      double s = b[i];
-      for (int j = i + 1; j < K; ++j) s -= A[i][j] * b[j];
-      b[i] = s / A[i][i];
-    }
-  }
-  __syncthreads();
-  const int w = odd ? rot_pitch(m) : m;
-  for (int p = t; p < m * w; p += blockDim.x) {
-    const int i = p / w, j = odd ? 2 * (p % w) + (i & 1) : p % w;
-    u[p] = j < m && idx[i * m + j] >= 0 ? b[idx[i * m + j]] : 0.0;
-  }
+  if (t < K) u[pos[t]] = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
 }
 
 // Per-block sums of the squared level-0 defect over the interior.
@@ -431,6 +390,81 @@ Op level_op(const mg_rbc_config &c, int l) {
 // Entries of a level's arrays: m^2, or m rows of (m + 1)/2 on a rotated level.
 size_t level_entries(const Level &L) { return (size_t)L.m * (L.odd ? rot_pitch(L.m) : L.m); }
 
+// The coarsest level's operator as a dense K x K matrix over its unknowns (row-major
+// storage order), each stencil tap beyond the boundary line folded onto its mirror image
+// with the opposite sign (zero boundary values), and its inverse by Gauss-Jordan
+// elimination with partial pivoting; inv_t is the inverse transposed.  Returns false if
+// the matrix is singular.  pos gets each unknown's index in the level's arrays.
+bool coarsest_inverse(const Level &L, std::vector<double> &inv_t, std::vector<int> &pos) {
+  const int m = L.m, w = L.odd ? rot_pitch(m) : m;
+  std::vector<int> idx((size_t)m * m, -1);
+  pos.clear();
+  for (int i = 1; i < m - 1; ++i)
+    for (int j = 1; j < m - 1; ++j)
+      if (!L.odd || (i + j) % 2 == 0) {
+        idx[(size_t)i * m + j] = (int)pos.size();
+        pos.push_back(i * w + (L.odd ? j / 2 : j));
+      }
+  const int K = (int)pos.size();
+  std::vector<double> A((size_t)K * K, 0.0), X((size_t)K * K, 0.0);
+  const Op &op = L.op;
+  for (int i = 1; i < m - 1; ++i)
+    for (int j = 1; j < m - 1; ++j) {
+      const int row = idx[(size_t)i * m + j];
+      if (row < 0) continue;
+      auto add = [&](int a, int c, double wgt) {
+        if (a < 0 || a >= m || c < 0 || c >= m) {
+          wgt = -wgt;
+          a = a < 0 ? -a : (a >= m ? 2 * (m - 1) - a : a);
+          c = c < 0 ? -c : (c >= m ? 2 * (m - 1) - c : c);
+        }
+        const int col = idx[(size_t)a * m + c];
+        if (col >= 0) A[(size_t)row * K + col] += wgt;
+      };
+      add(i, j, op.c0);
+      if (op.a1 != 0.0) {
+        add(i - 1, j, op.a1); add(i + 1, j, op.a1); add(i, j - 1, op.a1); add(i, j + 1, op.a1);
+      }
+      if (op.d1 != 0.0) {
+        add(i - 1, j - 1, op.d1); add(i - 1, j + 1, op.d1);
+        add(i + 1, j - 1, op.d1); add(i + 1, j + 1, op.d1);
+      }
+      if (op.a2 != 0.0) {
+        add(i - 2, j, op.a2); add(i + 2, j, op.a2); add(i, j - 2, op.a2); add(i, j + 2, op.a2);
+      }
+    }
+  for (int r = 0; r < K; ++r) X[(size_t)r * K + r] = 1.0;
+  for (int k = 0; k < K; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < K; ++r)
+      if (std::fabs(A[(size_t)r * K + k]) > std::fabs(A[(size_t)piv * K + k])) piv = r;
+    if (A[(size_t)piv * K + k] == 0.0) return false;
+    if (piv != k)
+      for (int c = 0; c < K; ++c) {
+        std::swap(A[(size_t)k * K + c], A[(size_t)piv * K + c]);
+        std::swap(X[(size_t)k * K + c], X[(size_t)piv * K + c]);
+      }
+    const double d = 1.0 / A[(size_t)k * K + k];
+    for (int c = 0; c < K; ++c) {
+      A[(size_t)k * K + c] *= d;
+      X[(size_t)k * K + c] *= d;
+    }
+    for (int r = 0; r < K; ++r) {
+      const double g = A[(size_t)r * K + k];
+      if (r == k || g == 0.0) continue;
+      for (int c = 0; c < K; ++c) {
+        A[(size_t)r * K + c] -= g * A[(size_t)k * K + c];
+        X[(size_t)r * K + c] -= g * X[(size_t)k * K + c];
+      }
+    }
+  }
+  inv_t.assign((size_t)K * K, 0.0);
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) inv_t[(size_t)c * K + r] = X[(size_t)r * K + c];
+  return true;
+}
+
+
 
 }  // namespace
 
@@ -440,6 +474,9 @@ struct mg_rbc_ctx {
   std::vector<Level> lv;
   std::vector<double *> u, f, t;  // per level; u[0], f[0] are the caller's
   double *partial = nullptr, *norm_dev = nullptr, *norm_host = nullptr;
+  double *ainv_t = nullptr;  // the coarsest operator's inverse, transposed (K x K)
+  int *pos = nullptr;        // array index of each coarsest unknown
+  int coarse_k = 0;
 };
 
 namespace {
@@ -508,8 +545,8 @@ mg_status launch_prolong(mg_rbc_ctx *h, int l, const double *ec, const double *u
 }
 
 mg_status launch_coarsest(mg_rbc_ctx *h, const double *f, double *u) {
-  const Level &L = h->lv.back();
-  hipLaunchKernelGGL(k_rbc_coarsest, dim3(1), dim3(256), 0, h->stream, f, u, L.m, (int)L.odd, L.op);
+  hipLaunchKernelGGL(k_rbc_coarsest, dim3(1), dim3(1024), 0, h->stream, f, u, h->ainv_t, h->pos,
+                     h->coarse_k, (int)level_entries(h->lv.back()));
   RBC_HIP(hipGetLastError());
   return MG_OK;
 }
@@ -592,10 +629,25 @@ mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out)
     ok = ok && alloc(&h->t[l], cnt);
   }
   ok = ok && alloc(&h->partial, kNormBlocks) && alloc(&h->norm_dev, 1);
+  std::vector<double> inv_t;
+  std::vector<int> pos;
+  if (ok && !coarsest_inverse(h->lv.back(), inv_t, pos)) {
+    mg_rbc_destroy(h);
+    return fail(MG_EINVAL, "the coarsest level's operator is singular");
+  }
+  h->coarse_k = (int)pos.size();
+  ok = ok && alloc(&h->ainv_t, inv_t.size()) &&
+       hipMalloc((void **)&h->pos, pos.size() * sizeof(int)) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&h->norm_host, sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     mg_rbc_destroy(h);
     return fail(MG_ENOMEM, "device allocation failed");
+  }
+  // the set-up copies are synchronous: inv_t and pos are freed on return
+  if (hipMemcpy(h->ainv_t, inv_t.data(), inv_t.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    mg_rbc_destroy(h);
+    return fail(MG_EDEVICE, "copying the coarsest inverse failed");
   }
   // every level array starts at zero: their boundaries and off-grid entries stay zero
   for (int l = 1; l < cfg->levels; ++l) {
@@ -624,6 +676,8 @@ void mg_rbc_destroy(mg_rbc_ctx *h) {
   for (double *p : h->t) release(p);
   release(h->partial);
   release(h->norm_dev);
+  release(h->ainv_t);
+  if (h->pos) (void)hipFree(h->pos);
   if (h->norm_host) (void)hipHostFree(h->norm_host);
   delete h;
 }

@@ -9,7 +9,7 @@ import ctypes
 from paper_2008_03885_amd import mg
 
 MG_RBC_NG, MG_RBC_G1, MG_RBC_GN = 0, 1, 2
-MG_RBC_MAX_COARSEST = 64
+MG_RBC_MAX_COARSEST = 256
 
 _V = ctypes.c_void_p
 _I = ctypes.c_int
