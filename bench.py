@@ -56,7 +56,7 @@ MEASURED_TRAFFIC = {
     "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
-    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403290610, "source": "fad2c5f458b53c3d"},
+    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403290610, "source": "2822764b51ee7b69"},
 }
 
 

@@ -313,14 +313,13 @@ __global__ __launch_bounds__(256) void k_rbc_resnorm(const double *__restrict__ 
                                                      const double *__restrict__ u, int m, Op op,
                                                      double *__restrict__ partial) {
   __shared__ double red[256];
-  const size_t ni = (size_t)(m - 2) * (m - 2);
   double s = 0.0;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < ni;
-       q += (size_t)gridDim.x * blockDim.x) {
-    const int i = 1 + (int)(q / (m - 2)), j = 1 + (int)(q % (m - 2));
-    const double r = f[(size_t)i * m + j] - apply_op(u, m, i, j, op);
-    s += r * r;
-  }
+  // block b takes interior rows b + 1, b + 1 + gridDim.x, ...; its threads stride the row
+  for (int i = 1 + blockIdx.x; i < m - 1; i += gridDim.x)
+    for (int j = 1 + threadIdx.x; j < m - 1; j += blockDim.x) {
+      const double r = f[(size_t)i * m + j] - apply_op(u, m, i, j, op);
+      s += r * r;
+    }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -577,7 +576,7 @@ mg_status cycle(mg_rbc_ctx *h, int l, const double *f, double *u) {
 mg_status norm(mg_rbc_ctx *h, const double *f, const double *u, double *out) {
   const Level &L = h->lv[0];
   const size_t ni = (size_t)(L.m - 2) * (L.m - 2);
-  int blocks = (int)std::min<size_t>(kNormBlocks, (ni + 255) / 256);
+  const int blocks = std::min(kNormBlocks, L.m - 2);  // a block takes whole interior rows
   hipLaunchKernelGGL(k_rbc_resnorm, dim3(blocks), dim3(256), 0, h->stream, f, u, L.m, L.op, h->partial);
   RBC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rbc_sum, dim3(1), dim3(256), 0, h->stream, h->partial, blocks, 1.0 / (double)ni,
