@@ -1,25 +1,28 @@
 """Benchmark: fourth-order Poisson multigrid solves on one MI355X.
 
-One step is one whole solve from a zero initial guess to a 1e-10 relative residual (or
-the FP64 rounding floor), with f and u resident in HBM.  Workloads (--workload):
+One step is one whole solve from a zero initial guess to a 1e-10 relative residual, with
+f and u resident in HBM.  The default workload is the largest configuration:
 
-  poisson2d-4097 (default)  2D, n = 4097 (16,769,025 unknowns), right-hand side
-      sum_{kx,ky<=64} g_k/|k| sin(kx pi x) sin(ky pi y), g_k ~ N(0,1) (seeded), V(2,1)
-      omega-Jacobi (omega = 10/13), full weighting, cubic interpolation, rediscretized
-      coarse operators to 9x9 with an exact coarsest solve, FP64.  The JSON line also
-      carries the Galerkin and W(2,1) combinations of the same problem, and V(2,1) with
-      the second-order coarse operators of section 3.1 (`config_variants`;
-      --no-variants skips them).
-  poisson3d-513             3D, n = 513, uniform[-1,1] noise smoothed by three
-      neighbour-average passes, V(2,1) (omega = 9/11), mixed precision (eight FP32
-      cycles per FP64 refinement step) against FP64.
-  poisson3d-1025-galerkin-w22  3D, n = 1025, smooth sine series (k <= 8), Galerkin
-      coarse operators, W(2,2), mixed against FP64, plus the error of the solution
-      against the oracle's 129^3 solve of the same continuous problem.
+  poisson3d-1025-galerkin-w22 (default)  3D, n = 1025 (1,070,599,167 unknowns), smooth
+      sine-series right-hand side (k <= 8, N(0,1) amplitudes, seeded), fourth-order
+      13-point cross on the finest level, Galerkin coarse operators R L P down to 9^3
+      with an exact coarsest solve, W(2,2) omega-Jacobi (omega = 9/11), full weighting,
+      cubic interpolation.  Timed in mixed precision (FP32 cycles inside FP64 iterative
+      refinement: `value`) and in plain FP64 (`precision_compare`), plus the error of the
+      1025^3 solution against the oracle's 129^3 solve of the same continuous problem.
 
-Prints one JSON line: throughput in unknowns/s, the roofline of the dominant kernel
-(HIP-event timed on the handle's stream), per-level kernel rates, and the CPU oracle
-timed on a bounded sample.  --gpus N with N > 1 exits: this library runs on one GPU.
+The same JSON line carries, as extra keys, the other configurations:
+  `poisson3d_513`   3D, n = 513, uniform[-1,1] noise smoothed by three neighbour-average
+                    passes, V(2,1), mixed (eight FP32 cycles per step) against FP64;
+  `poisson2d_4097`  2D, n = 4097, Fourier right-hand side k <= 64 with N(0,1)/|k|
+                    amplitudes, V(2,1), FP64, with the level-0 fused-kernel roofline and the
+                    Galerkin, W-cycle, second-order, red-black and sixth-order variants;
+  `serving`         the continuous-batching server on a Poisson stream of 2D solves
+                    (n = 2^k + 1, k uniform on 6..11) at 0.5, 0.8 and 0.95 of saturation;
+  `red_black_coarsening`  section 4's rotated-grid cycles on the 4097^2 second-order
+                    problem.
+Other workloads can be run alone with --workload.  --gpus N with N > 1 exits: the
+library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -32,14 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "poisson3d-1025-galerkin-w22"
 
 WORKLOADS = {
     "poisson2d-4097": dict(dim=2, n=4097, rhs="fourier", coarse=0, gamma=1, nu1=2, nu2=1,
                            precision=0, compare=False, inner=4),
     "poisson3d-513": dict(dim=3, n=513, rhs="noise", coarse=0, gamma=1, nu1=2, nu2=1,
                           precision=1, compare=True, inner=8),
+    # inner = 1: measured fastest of 1, 2, 3 FP32 W-cycles per refinement step (651, 696, 723 ms)
     "poisson3d-1025-galerkin-w22": dict(dim=3, n=1025, rhs="sine", coarse=1, gamma=2, nu1=2,
-                                        nu2=2, precision=1, compare=True, inner=3, check129=True),
+                                        nu2=2, precision=1, compare=True, inner=1, check129=True),
 }
 
 # HBM traffic of the dominant kernels from rocprofv3 --pmc (FETCH_SIZE and WRITE_SIZE per
@@ -63,9 +68,11 @@ MEASURED_TRAFFIC = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="poisson2d-4097", choices=sorted(WORKLOADS))
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    p.add_argument("--no-extras", action="store_true",
+                   help="only the chosen workload (no 513^3, 4097^2, serving, red-black coarsening keys)")
     p.add_argument("--n", type=int, default=None)
     p.add_argument("--coarse", type=int, default=None,
                    help="0 rediscretized, 1 Galerkin, 2 second-order rediscretized, 3 second-order Galerkin")
@@ -84,7 +91,7 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=30)
     p.add_argument("--pmc-probe", action="store_true",
                    help="run a plain copy of known size, then the dominant kernel (for counters)")
-    p.add_argument("--serve-requests", type=int, default=120,
+    p.add_argument("--serve-requests", type=int, default=1000,
                    help="requests per serving run (0: skip the serving measurement)")
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     p.add_argument("--rbc-only", action="store_true", help="only the red-black coarsening runs")
@@ -300,70 +307,76 @@ def level_kernels(run, w, stream, reps, only_level0=False):
     return rows
 
 
-def cpu_baseline(w, cycles_needed, budget_s=20.0):
-    """The oracle (plain C, FP64, OpenMP over the outer loop) on a bounded sample: whole
-    cycles of the same configuration, timed, scaled to the cycles the GPU solve needed.
-    3D problems above 513^3 (257^3 with Galerkin operators) are sampled at that size and
-    scaled per unknown."""
+def cpu_baseline(w, gpu_cycles, sample_n=None):
+    """The oracle (plain C, FP64; OpenMP splits the outermost loop of 3D grids, 2D loops run
+    on one thread) timed on the host on a bounded sample of the same configuration.
+    3D: one whole solve to 1e-10 of the same problem at side sample_n on all host cores,
+    and one cycle on one thread scaled to that solve's cycle count.  2D: one cycle of the
+    full-size problem on one thread, scaled to the cycles the GPU solve needed.
+    Returns (baseline dict, oracle solution or None, oracle cycles, oracle final residual)."""
     import numpy as np
 
     import oracle
     d = w["dim"]
-    cap = 257 if w["coarse"] else 513
-    n = w["n"] if (d == 2 or w["n"] <= cap) else cap
-    ws = dict(w, n=n)
-    f, _ = make_rhs(ws)
-    m = oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
-                         smoother=w.get("smoother", 0), order=w.get("order", 4),
-                         omega=w.get("omega") or None)
-    u = np.zeros_like(f)
-    t0 = time.perf_counter()
-    m.cycle(u, f)
-    t_cycle = time.perf_counter() - t0
-    done = 1
-    while (done + 1) * t_cycle < budget_s and done < 4:
-        t0 = time.perf_counter()
-        m.cycle(u, f)
-        t_cycle = min(t_cycle, time.perf_counter() - t0)
-        done += 1
-    m.close()
+    n = sample_n or w["n"]
+    f, _ = make_rhs(dict(w, n=n))
+    all_cores = oracle.num_threads()
+
+    def make():
+        return oracle.Multigrid(d, n, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
+                                smoother=w.get("smoother", 0), order=w.get("order", 4),
+                                omega=w.get("omega") or None)
     unknowns = (n - 2) ** d
     cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
-    return {
-        "value": unknowns / (t_cycle * cycles_needed),
-        "unit": "unknowns/s",
-        "cores": oracle.num_threads(),
-        "kind": "oracle",
-        "sample": "%d FP64 %s cycles of the %s problem (best cycle %.2f s), scaled to the %d "
-                  "cycles the GPU FP64 solve needs" % (done, cyc, "x".join([str(n)] * d), t_cycle,
-                                                      cycles_needed),
-    }
+    grid = "x".join([str(n)] * d)
+    u_all, cycles, final = None, gpu_cycles, None
+    out = {"unit": "unknowns/s", "kind": "oracle"}
+    if d == 3:
+        m = make()
+        u_all = np.zeros_like(f)
+        t0 = time.perf_counter()
+        cycles, hist = m.solve(u_all, f, rtol=1e-10, max_cycles=60)
+        t_all = time.perf_counter() - t0
+        m.close()
+        final = float(hist[-1])
+        out.update(value=unknowns / t_all, cores=all_cores,
+                   sample="one whole FP64 %s solve of the same problem at %s to %.1e on %d threads "
+                          "(%d cycles, %.2f s)" % (cyc, grid, final, all_cores, cycles, t_all))
+    oracle.set_num_threads(1)
+    try:
+        m = make()
+        u1 = np.zeros_like(f)
+        t0 = time.perf_counter()
+        m.cycle(u1, f)
+        t1 = time.perf_counter() - t0
+        m.close()
+    finally:
+        oracle.set_num_threads(all_cores)
+    one = {"value": unknowns / (t1 * cycles), "cores": 1,
+           "sample": "one FP64 %s cycle at %s on one thread (%.2f s), scaled to the %d cycles of %s"
+                     % (cyc, grid, t1, cycles, "that solve" if d == 3 else "the GPU FP64 solve")}
+    if d == 3:
+        out["single_thread"] = one
+    else:
+        out.update(one)
+    return out, u_all, cycles, final
 
 
-def error_vs_129(ud_host, w, coeffs):
-    """The 1025^3 solution injected onto the 129^3 grid against the oracle's 129^3 solve of
-    the same continuous right-hand side, and both against the continuous solution."""
+def error_vs_129(u_inj, coeffs, u129, cycles, final):
+    """The 1025^3 GPU solution injected onto the 129^3 grid against the oracle's 129^3 solve
+    of the same continuous right-hand side, and both against the continuous solution."""
     import numpy as np
 
-    import oracle
     from paper_2008_03885_amd import inputs
-    n, nco = w["n"], 129
-    stride = (n - 1) // (nco - 1)
-    f129 = inputs.smooth_sine_3d(nco)
-    m = oracle.Multigrid(3, nco, coarse=w["coarse"], gamma=w["gamma"], nu1=w["nu1"], nu2=w["nu2"],
-                         smoother=w.get("smoother", 0), order=w.get("order", 4))
-    u129 = np.zeros_like(f129)
-    cycles, hist = m.solve(u129, f129, rtol=1e-10, max_cycles=60)
-    m.close()
+    nco = u129.shape[0]
     k2 = inputs.wavenumber_sq(coeffs.shape[0], 3)
     exact = inputs.sine_series(nco, coeffs / (np.pi ** 2 * k2))
-    inj = ud_host[::stride, ::stride, ::stride]
     nrm = np.linalg.norm(u129)
     return {
-        "oracle_129_cycles": int(cycles), "oracle_129_rel_residual": float(hist[-1]),
-        "rel_diff_gpu1025_vs_oracle129": float(np.linalg.norm(inj - u129) / nrm),
+        "oracle_129_cycles": int(cycles), "oracle_129_rel_residual": final,
+        "rel_diff_gpu1025_vs_oracle129": float(np.linalg.norm(u_inj - u129) / nrm),
         "rel_err_oracle129_vs_continuous": float(np.linalg.norm(u129 - exact) / nrm),
-        "rel_err_gpu1025_vs_continuous": float(np.linalg.norm(inj - exact) / nrm),
+        "rel_err_gpu1025_vs_continuous": float(np.linalg.norm(u_inj - exact) / nrm),
     }
 
 
@@ -407,7 +420,7 @@ def rbc_pmc_probe(fd, stream, n):
 SERVE_BUDGET = 32 << 30
 
 
-def serve_bench(count, loads=(0.5, 0.8), smoother=0, inner=4):
+def serve_bench(count, loads=(0.5, 0.8, 0.95), smoother=0, inner=4):
     """Continuous-batching server on a Poisson stream of 2D solves, n = 2^k + 1 with k
     uniform on 6..11, Fourier right-hand sides (k <= min(64, (n-1)/4)), mixed precision
     V(2,1) to 1e-10.  First all requests at once (saturated throughput), then open-loop
@@ -582,19 +595,128 @@ def rbc_bench(fd, stream, n, reps, cpu=True):
     return out
 
 
+def time_workload(w, args, stream, fd, label, variants_2d=False):
+    """Solves of workload w from zero (its precision, and the other one when w["compare"]),
+    the roofline of its dominant level-0 kernel, per-level kernel rates and, in 2D, the
+    other coarse-operator / cycle / smoother / order combinations.  Returns (dict, main
+    Run still open, its last result)."""
+    import torch
+    d, n = w["dim"], w["n"]
+    unknowns = (n - 2) ** d
+    main_run = Run(w, w["precision"], fd, stream)
+    steps = args.steps if label == "primary" else max(2, args.steps // 3)
+    sec, (status, res) = main_run.timed(steps, args.warmup if label == "primary" else 1)
+    out = {"workload": describe(w), "ms_per_solve": 1e3 * sec, "unknowns_per_s": unknowns / sec,
+           "steps": steps, "cycles": res.cycles, "outer_steps": res.outer_steps,
+           "final_rel_residual": res.rel_residual, "reached_rtol": bool(res.rel_residual <= 1e-10),
+           "floor_hit": bool(res.floor_hit), "status": status}
+    if w["compare"]:
+        other = Run(w, 1 - w["precision"], fd, stream)
+        osec, (ostatus, ores) = other.timed(max(1, steps // 2), 1)
+        u64, umx = (main_run.ud, other.ud) if w["precision"] == 0 else (other.ud, main_run.ud)
+        rel = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+        r64, rmx = (res, ores) if w["precision"] == 0 else (ores, res)
+        s64, smx = (sec, osec) if w["precision"] == 0 else (osec, sec)
+        out["precision_compare"] = {
+            "fp64": {"ms": s64 * 1e3, "unknowns_per_s": unknowns / s64, "cycles": r64.cycles,
+                     "rel_residual": r64.rel_residual, "reached_rtol": bool(r64.rel_residual <= 1e-10),
+                     "floor_hit": bool(r64.floor_hit)},
+            "mixed": {"ms": smx * 1e3, "unknowns_per_s": unknowns / smx, "outer_steps": rmx.outer_steps,
+                      "fp32_cycles": rmx.cycles, "inner_cycles": w["inner"],
+                      "rel_residual": rmx.rel_residual, "reached_rtol": bool(rmx.rel_residual <= 1e-10),
+                      "floor_hit": bool(rmx.floor_hit)},
+            "mixed_speedup": s64 / smx,
+            "rel_diff_mixed_vs_fp64": rel,
+        }
+        other.close()
+        del other
+    if variants_2d:
+        out["config_variants"] = config_variants_2d(w, fd, stream, sec, res)
+    rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
+    rb = bool(w.get("smoother", 0))
+    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
+    dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
+    if not dom:
+        dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
+               if r["kernel"] == dom_name]
+    dom = dom[0]
+    cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
+    src = "fused2d.hip" if d == 2 else "kernels3d.hip"
+    key = "%s/%s/%s/%d%s%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "",
+                               "/o%d" % w.get("order", 4) if w.get("order", 4) != 4 else "")
+    tr = MEASURED_TRAFFIC.get(key)
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": "%s level 0 (%s, %s)" % (dom_name, dom["op"], "FP32" if w["precision"] else "FP64"),
+        "achieved": dom["GB/s"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": dom["GB/s"] / HBM_PEAK_GBS,
+        "traffic": tr["bytes"] if tr and tr["source"] == source_hash(src) else None,
+        "avg_launch_us": dom["us"],
+        "timing": "HIP events around back-to-back launches on the handle's stream",
+        "algorithmic_bytes_per_launch": dom["bytes"],
+        "in_cycle_us": cyc_s * 1e6,
+        "in_cycle_GBs": dom["bytes"] / cyc_s / 1e9,
+    }
+    if rows:
+        out["levels"] = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
+                         for r in rows]
+    return out, main_run, res
+
+
+VARIANTS_2D = (  # coarse, gamma, smoother, order, omega
+    (0, 1, 0, 4, 0.0), (1, 1, 0, 4, 0.0), (0, 2, 0, 4, 0.0), (1, 2, 0, 4, 0.0),
+    (2, 1, 0, 4, 0.0), (3, 1, 0, 4, 0.0),
+    (0, 1, 1, 4, 0.0), (1, 1, 1, 4, 0.0), (3, 1, 1, 4, 0.0), (0, 2, 1, 4, 0.0),
+    (0, 1, 1, 4, 1.17),  # the measured multilevel optimum, above the two-grid one
+    (0, 1, 0, 6, 0.0), (3, 1, 0, 6, 0.0), (3, 1, 1, 6, 0.0))
+
+
+def config_variants_2d(w, fd, stream, sec, res):
+    """The other coarse-operator / cycle / smoother / order combinations of the 2D problem."""
+    unknowns = (w["n"] - 2) ** 2
+    kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
+    variants = {}
+    for coarse, gamma, sm, order, om in VARIANTS_2D:
+        name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
+        if sm:
+            name = "redblack-" + name
+        if order != 4:
+            name = "order%d-%s" % (order, name)
+        if om:
+            name += "-omega%g" % om
+        if (coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0)
+                and order == w.get("order", 4) and not om and not w.get("omega")):
+            vs, vres = sec, res
+        else:
+            vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm, order=order, omega=om),
+                     w["precision"], fd, stream)
+            vs, (vst, vres) = vr.timed(2, 1)
+            vr.close()
+        variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
+                          "rel_residual": vres.rel_residual}
+    return variants
+
+
+def setup_workload(args, name):
+    w = dict(WORKLOADS[name])
+    if name == args.workload:
+        for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order", "omega"):
+            if getattr(args, k) is not None:
+                w[k] = getattr(args, k)
+    return w
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    w = dict(WORKLOADS[args.workload])
-    for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order", "omega"):
-        if getattr(args, k) is not None:
-            w[k] = getattr(args, k)
+    w = setup_workload(args, args.workload)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.serve_only:
@@ -611,158 +733,98 @@ def main():
         print(json.dumps({"red_black_coarsening": rbc_bench(fd, stream, w["n"], args.steps,
                                                             cpu=not args.no_cpu)}), flush=True)
         return
+    if args.pmc_probe:
+        run = Run(w, w["precision"], fd, stream)
+        pmc_probe(w, run, stream)
+        run.close()
+        return
     d, n = w["dim"], w["n"]
     unknowns = (n - 2) ** d
-
-    main_run = Run(w, w["precision"], fd, stream)
-    if args.pmc_probe:
-        pmc_probe(w, main_run, stream)
-        main_run.close()
-        return
-    sec, (status, res) = main_run.timed(args.steps, args.warmup)
-    ms = 1e3 * sec
-
-    # the other coarse-operator / cycle combinations of the 2D 4097^2 configuration
-    variants = None
-    if args.workload == "poisson2d-4097" and not args.no_variants:
-        variants = {}
-        kinds = {0: "rediscretized", 1: "galerkin", 2: "rediscretized-order2", 3: "galerkin-order2"}
-        for coarse, gamma, sm, order, om in (
-                (0, 1, 0, 4, 0.0), (1, 1, 0, 4, 0.0), (0, 2, 0, 4, 0.0), (1, 2, 0, 4, 0.0),
-                (2, 1, 0, 4, 0.0), (3, 1, 0, 4, 0.0),
-                (0, 1, 1, 4, 0.0), (1, 1, 1, 4, 0.0), (3, 1, 1, 4, 0.0), (0, 2, 1, 4, 0.0),
-                (0, 1, 1, 4, 1.17),  # the measured multilevel optimum, above the two-grid one
-                (0, 1, 0, 6, 0.0), (3, 1, 0, 6, 0.0), (3, 1, 1, 6, 0.0)):
-            name = "%s-%s(%d,%d)" % (kinds[coarse], "W" if gamma == 2 else "V", w["nu1"], w["nu2"])
-            if sm:
-                name = "redblack-" + name
-            if order != 4:
-                name = "order%d-%s" % (order, name)
-            if om:
-                name += "-omega%g" % om
-            if (coarse == w["coarse"] and gamma == w["gamma"] and sm == w.get("smoother", 0)
-                    and order == w.get("order", 4) and not om and not w.get("omega")):
-                vs, vres = sec, res
-            else:
-                vr = Run(dict(w, coarse=coarse, gamma=gamma, smoother=sm, order=order, omega=om),
-                         w["precision"], fd, stream)
-                vs, (vst, vres) = vr.timed(2, 1)
-                vr.close()
-            variants[name] = {"ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
-                              "rel_residual": vres.rel_residual}
-
-    # 3D 513^3: red-black Jacobi smoothing (omega 1.17), FP64 and mixed with 4 FP32 cycles
-    # per refinement step
-    if args.workload == "poisson3d-513" and not args.no_variants and not w.get("smoother", 0):
-        variants = {}
-        for prec, om in ((0, 0.0), (1, 0.0), (0, 1.25)):
-            vr = Run(dict(w, smoother=1, inner=4, omega=om), prec, fd, stream)
-            vs, (vst, vres) = vr.timed(2, 1)
-            vr.close()
-            name = "redblack-V(%d,%d)-%s" % (w["nu1"], w["nu2"], "fp64" if prec == 0 else "mixed-inner4")
-            variants[name + ("-omega%g" % om if om else "")] = {
-                "ms": 1e3 * vs, "unknowns_per_s": unknowns / vs, "cycles": vres.cycles,
-                "outer_steps": vres.outer_steps, "rel_residual": vres.rel_residual}
-
-    compare = None
-    fp64_cycles = res.cycles if w["precision"] == 0 else None
-    if w["compare"]:
-        other = Run(w, 1 - w["precision"], fd, stream)
-        osec, (ostatus, ores) = other.timed(max(1, args.steps // 2), 1)
-        u64, umx = (main_run.ud, other.ud) if w["precision"] == 0 else (other.ud, main_run.ud)
-        rel = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
-        r64, rmx = (res, ores) if w["precision"] == 0 else (ores, res)
-        s64, smx = (sec, osec) if w["precision"] == 0 else (osec, sec)
-        fp64_cycles = r64.cycles
-        compare = {
-            "fp64": {"ms": s64 * 1e3, "unknowns_per_s": unknowns / s64, "cycles": r64.cycles,
-                     "rel_residual": r64.rel_residual, "floor_hit": bool(r64.floor_hit)},
-            "mixed": {"ms": smx * 1e3, "unknowns_per_s": unknowns / smx, "outer_steps": rmx.outer_steps,
-                      "fp32_cycles": rmx.cycles, "inner_cycles": w["inner"],
-                      "rel_residual": rmx.rel_residual, "floor_hit": bool(rmx.floor_hit)},
-            "mixed_speedup": s64 / smx,
-            "rel_diff_mixed_vs_fp64": rel,
-        }
-        other.close()
-
-    extra = None
+    print("bench: %s" % describe(w), file=sys.stderr, flush=True)
+    prim, main_run, res = time_workload(w, args, stream, fd, "primary",
+                                        variants_2d=(d == 2 and not args.no_variants))
+    inj = None
     if w.get("check129"):
-        extra = error_vs_129(main_run.ud.cpu().numpy(), w, coeffs)
-
-    rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
-    rb = bool(w.get("smoother", 0))
-    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
-    dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
-    if not dom:
-        dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
-               if r["kernel"] == dom_name]
-    dom = dom[0]
-    cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
-    src = "fused2d.hip" if d == 2 else "kernels3d.hip"
-    key = "%s/%s/%s/%d%s%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "",
-                               "/o%d" % w.get("order", 4) if w.get("order", 4) != 4 else "")
-    tr = MEASURED_TRAFFIC.get(key)
-    traffic = tr["bytes"] if tr and tr["source"] == source_hash(src) else None
+        stride = (n - 1) // 128
+        inj = main_run.ud[::stride, ::stride, ::stride].cpu().numpy()
+    main_run.close()
+    del main_run, fd
+    torch.cuda.empty_cache()
 
     cyc = "%s(%d,%d)" % ("W" if w["gamma"] == 2 else "V", w["nu1"], w["nu2"])
+    cfg = {
+        "workload": prim["workload"], "name": args.workload, "dim": d, "n": n, "unknowns": unknowns,
+        "cycle": cyc, "coarse": ["rediscretized", "galerkin", "rediscretized-order2",
+                                 "galerkin-order2"][w["coarse"]],
+        "precision": "fp64" if w["precision"] == 0 else "mixed",
+        "inner_cycles": w["inner"] if w["precision"] else None,
+        "smoother": "red-black-jacobi" if w.get("smoother", 0) else "jacobi",
+        "order": w.get("order", 4),
+        "cycles": prim["cycles"], "outer_steps": prim["outer_steps"],
+        "final_rel_residual": prim["final_rel_residual"], "reached_rtol": prim["reached_rtol"],
+        "floor_hit": prim["floor_hit"], "status": prim["status"],
+    }
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual (mixed vs FP64) + smoother HBM GB/s; p99 lat",
-        "value": unknowns / sec,
+        "value": prim["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": prim["steps"],
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": prim["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if w["precision"] == 0 else "f32-in-f64",
         "data": "synthetic",
-        "config": {
-            "workload": describe(w), "name": args.workload, "dim": d, "n": n, "unknowns": unknowns,
-            "cycle": cyc, "coarse": ["rediscretized", "galerkin", "rediscretized-order2",
-                                     "galerkin-order2"][w["coarse"]],
-            "precision": "fp64" if w["precision"] == 0 else "mixed",
-            "smoother": "red-black-jacobi" if w.get("smoother", 0) else "jacobi",
-            "order": w.get("order", 4),
-            "cycles": res.cycles, "outer_steps": res.outer_steps,
-            "final_rel_residual": res.rel_residual, "floor_hit": bool(res.floor_hit),
-            "status": status,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "%s level 0 (%s, %s)" % (dom_name, dom["op"], "FP32" if w["precision"] else "FP64"),
-            "achieved": dom["GB/s"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": dom["GB/s"] / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "avg_launch_us": dom["us"],
-            "timing": "HIP events around back-to-back launches on the handle's stream",
-            "algorithmic_bytes_per_launch": dom["bytes"],
-            "in_cycle_us": cyc_s * 1e6,
-            "in_cycle_GBs": dom["bytes"] / cyc_s / 1e9,
-        },
+        "config": cfg,
+        "roofline": prim["roofline"],
     }
-    if compare:
-        out["precision_compare"] = compare
-    if variants:
-        out["config_variants"] = variants
-    if extra:
-        out["error_vs_oracle_129"] = extra
-    if rows:
-        out["levels"] = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
-                         for r in rows]
-    main_run.close()
-    if args.workload == "poisson2d-4097" and not args.no_variants:
-        out["red_black_coarsening"] = rbc_bench(fd, stream, n, 3, cpu=not args.no_cpu)
-    if args.serve_requests > 0 and args.workload == "poisson2d-4097":
-        del fd
-        out["serving"] = serve_bench(args.serve_requests)
-        # the same stream with red-black Jacobi smoothing (2 FP32 cycles per refinement step)
-        out["serving_redblack"] = serve_bench(args.serve_requests, smoother=1, inner=2)
+    for k in ("precision_compare", "config_variants", "levels"):
+        if k in prim:
+            out[k] = prim[k]
+    fp64_cycles = (prim["precision_compare"]["fp64"]["cycles"] if "precision_compare" in prim
+                   else prim["cycles"])
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, max(fp64_cycles or res.cycles, 1))
+        sample = 129 if (d == 3 and n > 129) else None
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        base, u129, ocyc, ofinal = cpu_baseline(w, max(fp64_cycles, 1), sample)
+        out["cpu_baseline"] = base
+        if inj is not None and u129 is not None:
+            out["error_vs_oracle_129"] = error_vs_129(inj, coeffs, u129, ocyc, ofinal)
+
+    if not args.no_extras and args.workload == DEFAULT_WORKLOAD:
+        # the 3D 513^3 configuration: mixed (eight FP32 cycles per step) against FP64
+        print("bench: extra poisson3d-513", file=sys.stderr, flush=True)
+        w3 = setup_workload(args, "poisson3d-513")
+        f3, _ = make_rhs(w3)
+        fd3 = torch.from_numpy(f3).cuda()
+        del f3
+        e3, r3, _ = time_workload(w3, args, stream, fd3, "extra")
+        r3.close()
+        e3.pop("levels", None)
+        out["poisson3d_513"] = e3
+        del fd3, r3
+        torch.cuda.empty_cache()
+        # the 2D 4097^2 configuration (FP64) and its variants
+        print("bench: extra poisson2d-4097", file=sys.stderr, flush=True)
+        w2 = setup_workload(args, "poisson2d-4097")
+        f2, _ = make_rhs(w2)
+        fd2 = torch.from_numpy(f2).cuda()
+        del f2
+        e2, r2, _ = time_workload(w2, args, stream, fd2, "extra", variants_2d=not args.no_variants)
+        r2.close()
+        out["poisson2d_4097"] = e2
+        if not args.no_variants:
+            print("bench: red-black coarsening", file=sys.stderr, flush=True)
+            out["red_black_coarsening"] = rbc_bench(fd2, stream, w2["n"], 3, cpu=not args.no_cpu)
+        del fd2, r2
+        torch.cuda.empty_cache()
+        if args.serve_requests > 0:
+            print("bench: serving", file=sys.stderr, flush=True)
+            out["serving"] = serve_bench(args.serve_requests)
+            # the same stream with red-black Jacobi smoothing (2 FP32 cycles per refinement step)
+            out["serving_redblack"] = serve_bench(args.serve_requests, smoother=1, inner=2)
     print(json.dumps(out), flush=True)
 
 

@@ -44,7 +44,8 @@ typedef enum {
   MG_EINVAL = 1,    /* bad configuration or argument */
   MG_ENOMEM = 2,    /* device allocation failed or the footprint exceeds the budget */
   MG_EDEVICE = 3,   /* a HIP runtime call failed */
-  MG_ENOCONV = 4,   /* max_cycles reached, or the residual grew: result still filled */
+  MG_ENOCONV = 4,   /* rtol not reached: max_cycles reached, the residual grew, or it stopped
+                       decreasing at the rounding floor (floor_hit); result still filled */
   MG_ENUMERIC = 5,  /* the residual norm is NaN or Inf */
   MG_EBUSY = 6      /* an asynchronous solve on the handle has not finished */
 } mg_status;
@@ -109,28 +110,44 @@ typedef struct {
                                      refinement step (MIXED), and after the last */
 } mg_result;
 
-/* Validates cfg, builds the level hierarchy (coarse operators, the coarsest-level
- * inverse) and allocates every device buffer.  hip_stream: a hipStream_t (NULL = the
- * default stream).  On failure *out is NULL and nothing is leaked. */
+/* Set-up of the multigrid hierarchy (section 2.2, the levels l = 0..lmax of standard
+ * coarsening, eq. G_H_d): validates cfg, forms every level's operator (rediscretized,
+ * eq. L_H_4n_2d / L_H_2d, or the Galerkin product R L_l P of eqs. L_H_G, L_H_4G,
+ * L_H_2G_2d, kept as 1D factors), the relaxation weight (the Fourier-analysis optimum
+ * of section 5.3 unless cfg->omega > 0), the exact coarsest-level solve, and allocates
+ * every device buffer on the current device.  hip_stream: a hipStream_t (NULL = the
+ * default stream); all later work of the handle is ordered on it.  On failure *out is
+ * NULL and nothing is leaked (MG_EINVAL for a bad cfg, MG_ENOMEM, MG_EDEVICE). */
 mg_status mg_setup(const mg_config *cfg, void *hip_stream, mg_handle *out);
 
-/* Device bytes a handle for cfg allocates (0 for an invalid cfg). */
+/* Device bytes a handle for cfg allocates: the per-level arrays of the section 2.2
+ * hierarchy (u, f and a sweep target per level; level 0 FP64 u and f are the caller's),
+ * the coarsest-level solve tables and the reduction partials.  Exact, so a caller can
+ * admit work by HBM footprint.  0 for an invalid cfg. */
 size_t mg_footprint_bytes(const mg_config *cfg);
 
-/* Solves L u = f.  f, u: device FP64 arrays of n^dim values; u holds the initial
- * guess on entry and the solution on exit; f is read only.  Stops at rtol, at the
- * rounding floor (floor_hit), or at max_cycles.  res may be NULL.  Returns after the
- * solve finished.  MG_ENOCONV if rtol was not reached (res still filled). */
+/* Solves L u = f by repeated gamma-cycles (section 2.2, the multigrid algorithm; its
+ * loop read as "while ||f - L u||_h / ||f||_h > rtol and fewer than max_cycles"), or,
+ * for MIXED precision, by FP64 refinement steps around FP32 cycles.  f, u: device FP64
+ * arrays of n^dim values (caller-owned); u holds the initial guess on entry and the
+ * solution on exit; f is read only.  The relative residual is checked on the device
+ * before every cycle (step).  Stops at rtol (MG_OK), at max_cycles, on growth, or at the
+ * FP64 rounding floor above rtol (two checks in a row above 0.9 x the best so far:
+ * res->floor_hit = 1); all three return MG_ENOCONV with res filled.  A NaN or Inf
+ * residual returns MG_ENUMERIC.  res may be NULL.  Returns after the solve finished. */
 mg_status mg_solve(mg_handle h, const double *f, double *u, mg_result *res);
 
-/* Runs exactly ncycles cycles (MIXED: ncycles refinement steps) with no stopping
- * test, recording the residual before each and after the last.  For measurement and
- * parity checks at a fixed cycle count. */
+/* Runs exactly ncycles gamma-cycles of section 2.2 (MIXED: ncycles refinement steps)
+ * with no stopping test, recording the residual before each and after the last.  For
+ * measurement and parity checks at a fixed cycle count.  MG_OK unless an argument is
+ * bad (MG_EINVAL), a HIP call fails, or the residual is not finite (MG_ENUMERIC). */
 mg_status mg_run_cycles(mg_handle h, const double *f, double *u, int ncycles, mg_result *res);
 
-/* Stream-ordered solve: enqueues the whole solve (device-side stopping test, the
- * cycle cap as the launch bound) and returns without waiting.  f and u must stay
- * valid until mg_query reports completion. */
+/* Stream-ordered form of mg_solve (the same section 2.2 iteration and stopping rule):
+ * enqueues max_cycles + 1 steps on the handle's stream, each returning at once on the
+ * device after the stopping test has fired, and returns without waiting.  f and u must
+ * stay valid until mg_query reports completion.  MG_EBUSY if a previous asynchronous
+ * solve on the handle has not been collected by mg_query. */
 mg_status mg_solve_async(mg_handle h, const double *f, double *u);
 
 /* After mg_solve_async: MG_EBUSY while running, else the solve's status and res. */

@@ -98,7 +98,8 @@ mg_status mg_rbc_residual_norm(mg_rbc_ctx *h, const double *f, const double *u, 
  *   handle's own arrays); l < levels - 1.
  * prolong: u_out = u_in + the interpolated level l + 1 correction e_coarse; in place
  *   allowed; l < levels - 1.
- * coarsest: the exact solve of the last level's equation into u (zero off the unknowns). */
+ * coarsest: the exact solve of the last level's equation into u (zero off the unknowns);
+ *   f may be the same array as u. */
 mg_status mg_rbc_kernel_smooth(mg_rbc_ctx *h, int level, int colour, const double *f,
                                const double *u_in, double *u_out);
 mg_status mg_rbc_kernel_restrict(mg_rbc_ctx *h, int level, const double *f, const double *u,

@@ -89,6 +89,7 @@ def _load():
             "or_mg_coarsest_solve": (None, [ctypes.c_void_p, _D, _D]),
             "or_mg_solve": (_I, [ctypes.c_void_p, _D, _D, ctypes.c_double, _I, _D]),
             "or_num_threads": (_I, []),
+            "or_set_num_threads": (None, [_I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -115,6 +116,11 @@ def _stencil_radius(s):
 
 def num_threads():
     return _load().or_num_threads()
+
+
+def set_num_threads(threads):
+    """OpenMP threads of the oracle's outer loops (3D grids; 2D loops run on one thread)."""
+    _load().or_set_num_threads(int(threads))
 
 
 def num_levels(n, n_coarsest=9):

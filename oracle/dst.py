@@ -7,8 +7,12 @@ lambda_k = (4/h^2) sum_a (s_a + s_a^2/3), s_a = sin^2(theta_a/2).  A type-I disc
 sine transform therefore solves L_h u = f exactly (up to rounding), independently of
 any multigrid component.
 """
+import os
+
 import numpy as np
 import scipy.fft
+
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 def _per_axis(s, h, order):
@@ -37,14 +41,20 @@ def eigenvalues(n, dim, order=4):
     return lam
 
 
+def min_eigenvalue(n, dim, order=4):
+    """The smallest eigenvalue, mode k = (1, ..., 1): dim times the 1D symbol at theta = pi h."""
+    h = 1.0 / (n - 1)
+    return dim * float(_per_axis(np.sin(np.pi * h / 2.0) ** 2, h, order))
+
+
 def solve(f, order=4, dtype=np.float64):
     """Exact solution of L_h u = f (interior values of f used; zero boundary)."""
     dim, n = f.ndim, f.shape[0]
     inner = tuple(slice(1, n - 1) for _ in range(dim))
-    fh = scipy.fft.dstn(np.asarray(f[inner], dtype=dtype), type=1, norm="ortho")
-    uh = fh / eigenvalues(n, dim, order).astype(dtype)
+    fh = scipy.fft.dstn(np.asarray(f[inner], dtype=dtype), type=1, norm="ortho", workers=_WORKERS)
+    fh /= eigenvalues(n, dim, order).astype(dtype)
     u = np.zeros(f.shape, dtype=dtype)
-    u[inner] = scipy.fft.idstn(uh, type=1, norm="ortho")
+    u[inner] = scipy.fft.idstn(fh, type=1, norm="ortho", workers=_WORKERS)
     return u
 
 

@@ -27,6 +27,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int threads) {
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+}
+
 /* ------------------------------------------------------------------ grids -- */
 
 static long npts(int dim, int n) { return dim == 2 ? (long)n * n : (long)n * n * n; }

@@ -122,6 +122,8 @@ int or_mg_solve(or_mg *m, double *u, const double *f, double rtol, int max_cycle
 
 /* Number of OpenMP threads the loops above use. */
 int or_num_threads(void);
+/* Threads of the OpenMP loops from now on (3D grids split their outermost loop). */
+void or_set_num_threads(int threads);
 
 #ifdef __cplusplus
 }

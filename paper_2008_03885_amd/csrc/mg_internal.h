@@ -118,6 +118,10 @@ __device__ __forceinline__ P *slot_ptr(P *p, size_t per_slot) {
   return p == nullptr ? p : p + (size_t)blockIdx.z * per_slot;
 }
 
+// The rediscretized operator of a level of spacing h (order 2, 4 or 6), as 1D factors
+// (runtime.hip).
+LevelOp rediscretized_op(int order, int dim, double h);
+
 // ---- launchers (kernels.hip) ----------------------------------------------------
 // All take the level side n, dense arrays, and an optional `done` flag.
 

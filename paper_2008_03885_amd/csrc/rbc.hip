@@ -278,20 +278,22 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__re
 // Exact solve of the coarsest level: u = A^{-1} f over its K unknowns, with the inverse
 // formed once at set-up (transposed, so that for each column the threads of a row range
 // read consecutive entries) and pos[] giving each unknown's array index.  Every other
-// entry of u (boundary, padding) is set to zero first.  One 1024-thread workgroup: four
-// threads share a row, each summing every fourth column, then the four sums are added.
-__global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *__restrict__ f,
-                                                       double *__restrict__ u,
+// entry of u (boundary, padding) is set to zero.  f is read whole into LDS before any
+// entry of u is written, so f may be the same array as u.  One 1024-thread workgroup:
+// four threads share a row, each summing every fourth column, then the four sums are
+// added.
+__global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *f, double *u,
                                                        const double *__restrict__ ainv_t,
                                                        const int *__restrict__ pos, int K,
                                                        int entries) {
   constexpr int K_MAX = MG_RBC_MAX_COARSEST;
+  static_assert(4 * K_MAX == 1024, "four threads per row of the inverse fill the workgroup");
   __shared__ double fs[K_MAX];
   __shared__ double part[4][K_MAX];
   const int t = threadIdx.x;
-  for (int p = t; p < entries; p += 1024) u[p] = 0.0;
   for (int c = t; c < K; c += 1024) fs[c] = f[pos[c]];
   __syncthreads();
+  for (int p = t; p < entries; p += 1024) u[p] = 0.0;
   const int r = t % K_MAX, q = t / K_MAX;
   if (r < K) {
     // eight independent partial sums keep eight loads in flight

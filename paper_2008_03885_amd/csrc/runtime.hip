@@ -29,6 +29,36 @@
 using mgk::DevState;
 using mgk::LevelOp;
 
+namespace mgk {
+
+// The rediscretized operator of a level of spacing h as 1D factors: a = the 1D second
+// difference of the given order, b = unit (eqs. L_h_2d_4o, L_H_4n_2d, L_H_2d; section 3.3
+// eq. LhOrder6).
+LevelOp rediscretized_op(int order, int dim, double h) {
+  LevelOp op{};
+  const double s = 1.0 / (h * h);
+  if (order == 6) {
+    // section 3.3 eq. LhOrder6: radius 3, applied by the separable (Galerkin-level) kernels
+    const double c[7] = {-2.0 / 180, 27.0 / 180, -270.0 / 180, 490.0 / 180, -270.0 / 180, 27.0 / 180, -2.0 / 180};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  } else if (order == 4) {
+    const double c[7] = {0.0, 1.0 / 12, -16.0 / 12, 30.0 / 12, -16.0 / 12, 1.0 / 12, 0.0};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  } else {
+    const double c[7] = {0.0, 0.0, -1.0, 2.0, -1.0, 0.0, 0.0};
+    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
+  }
+  op.b[3] = 1.0;
+  op.cross = order != 6;
+  op.cross3 = order == 6;
+  op.diag = dim * op.a[3];
+  return op;
+}
+
+}  // namespace mgk
+
+using mgk::rediscretized_op;
+
 namespace {
 
 thread_local std::string g_error;
@@ -92,27 +122,6 @@ void galerkin_1d(const double c[7], int prolong, double out[7]) {
       for (int k = -3; k <= 3; ++k) s += fw1(o) * c[k + 3] * p1(prolong, o + k - 2 * J);
     out[J + 3] = s;
   }
-}
-
-LevelOp rediscretized(int order, int dim, double h) {
-  LevelOp op{};
-  const double s = 1.0 / (h * h);
-  if (order == 6) {
-    // section 3.3 eq. LhOrder6: radius 3, applied by the separable (Galerkin-level) kernels
-    const double c[7] = {-2.0 / 180, 27.0 / 180, -270.0 / 180, 490.0 / 180, -270.0 / 180, 27.0 / 180, -2.0 / 180};
-    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
-  } else if (order == 4) {
-    const double c[7] = {0.0, 1.0 / 12, -16.0 / 12, 30.0 / 12, -16.0 / 12, 1.0 / 12, 0.0};
-    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
-  } else {
-    const double c[7] = {0.0, 0.0, -1.0, 2.0, -1.0, 0.0, 0.0};
-    for (int i = 0; i < 7; ++i) op.a[i] = c[i] * s;
-  }
-  op.b[3] = 1.0;
-  op.cross = order != 6;
-  op.cross3 = order == 6;
-  op.diag = dim * op.a[3];
-  return op;
 }
 
 LevelOp galerkin(const LevelOp &fine, int dim, int prolong) {
@@ -762,8 +771,9 @@ void result_from_state(const mg_ctx *c, const DevState &hs, mg_result *res, mg_s
   }
   switch (hs.status) {
     case 1: *outcome = MG_OK; break;
-    case 3: *outcome = MG_OK; break;  // rounding floor: the best FP64 can certify
     case 4: *outcome = MG_ENUMERIC; break;
+    // 2 cycle cap, 3 rounding floor above rtol (floor_hit), 5 growth: rtol not reached
+
     default: *outcome = MG_ENOCONV; break;
   }
 }
@@ -832,7 +842,9 @@ mg_status run(mg_ctx *c, const double *f, double *u, double rtol, int max_steps,
   st = fill_result(c, res, &outcome);
   if (st != MG_OK) return st;
   if (outcome == MG_ENOCONV && rtol < 0.0) outcome = MG_OK;  // fixed cycle count requested
-  if (outcome != MG_OK) g_error = "solve did not reach rtol";
+  if (outcome != MG_OK)
+    g_error = res && res->floor_hit ? "solve stopped at the rounding floor above rtol"
+                                    : "solve did not reach rtol";
   return outcome;
 }
 
@@ -906,11 +918,11 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
     c->ns.push_back(n);
     const double h = 1.0 / (n - 1);
     if (l == 0 || cfg->coarse == MG_COARSE_NG)
-      c->ops.push_back(rediscretized(cfg->order, cfg->dim, h));
+      c->ops.push_back(rediscretized_op(cfg->order, cfg->dim, h));
     else if (cfg->coarse == MG_COARSE_NG2)
-      c->ops.push_back(rediscretized(2, cfg->dim, h));
+      c->ops.push_back(rediscretized_op(2, cfg->dim, h));
     else if (cfg->coarse == MG_COARSE_G2 && l == 1)  // R L_h^(2) P, second order at the finest spacing
-      c->ops.push_back(galerkin(rediscretized(2, cfg->dim, 1.0 / (cfg->n - 1)), cfg->dim, cfg->prolong));
+      c->ops.push_back(galerkin(rediscretized_op(2, cfg->dim, 1.0 / (cfg->n - 1)), cfg->dim, cfg->prolong));
     else
       c->ops.push_back(galerkin(c->ops[l - 1], cfg->dim, cfg->prolong));
     n = (n - 1) / 2 + 1;

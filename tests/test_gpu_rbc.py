@@ -27,7 +27,8 @@ class Pair:
         self.o = orbc.RBC(n, levels, coarse=CFG[coarse], gamma=gamma, nu1=nu1, nu2=nu2, omega=omega)
         for l in range(levels):
             assert rbc.level_size(self.h, l) == self.o.size(l)
-            assert rbc.level_pitch(self.h, l) == (self.o.size(l) + 1) // 2 if l % 2 else self.o.size(l)
+            pitch = (self.o.size(l) + 1) // 2 if l % 2 else self.o.size(l)
+            assert rbc.level_pitch(self.h, l) == pitch
 
     def close(self):
         rbc.destroy(self.h)
@@ -94,6 +95,9 @@ def test_every_step_on_every_level(n, levels, coarse):
             if l == levels - 1:
                 rbc.kernel_coarsest(P.h, fd.data_ptr(), out.data_ptr())
                 _close(unpack(host(out), l), P.o.coarsest_solve(f), "coarsest l=%d" % l)
+                inplace = fd.clone()  # f and u the same array
+                rbc.kernel_coarsest(P.h, inplace.data_ptr(), inplace.data_ptr())
+                _close(unpack(host(inplace), l), P.o.coarsest_solve(f), "coarsest in place l=%d" % l)
                 continue
             mc = P.o.size(l + 1)
             fc = dev(pack(np.zeros((mc, mc)), l + 1))

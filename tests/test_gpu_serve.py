@@ -2,12 +2,18 @@
 
 Each request must come out exactly as a standalone handle solves it (same kernels, same
 per-slot reduction order), whatever else shares its batch or the device, and must
-reach the 1e-10 relative residual in FP64.
+reach the 1e-10 relative residual in FP64.  Every served result is also checked against
+the exact discrete solution L_h^{-1} f from the sine transform (no multigrid code): the
+oracle's long-double residual of the served u is at most 1e-10 relative, and the error
+is within the bound ||L_h^{-1}|| ||f - L_h u||_h = ||f - L_h u||_h / lambda_min that this
+residual implies.
 """
 import numpy as np
 import pytest
 
+import oracle
 from gpu_util import dev, host, torch
+from oracle import dst
 from paper_2008_03885_amd import inputs, mg, serve
 
 pytestmark = pytest.mark.gpu
@@ -18,6 +24,19 @@ BASE = dict(dim=2, coarse=0, gamma=1, nu1=2, nu2=1, precision=mg.MG_PREC_MIXED, 
 
 def _rhs(n, seed):
     return inputs.fourier_rhs(n, 2, min(64, (n - 1) // 4), seed=seed)
+
+
+def _check_exact(u, f, what=""):
+    """u against the exact discrete solution, within the bound its residual implies."""
+    n = f.shape[0]
+    st = oracle.fine_stencil(2, 4, 1.0 / (n - 1))
+    fn = oracle.norm(f)
+    rel = oracle.residual_norm_ld(st, f, u) / fn
+    assert rel <= 1.01e-10, "%s: residual %.3e" % (what, rel)
+    exact = dst.solve(f)
+    bound = rel * fn / dst.eigenvalues(n, 2).min()
+    err = oracle.norm(u - exact)
+    assert err <= 1.01 * bound + 1e-14 * oracle.norm(exact), "%s: %.3e > %.3e" % (what, err, bound)
 
 
 def _solo(n, f, **over):
@@ -65,6 +84,7 @@ def test_single_request_equals_standalone_solve(precision):
     assert c.result.hist() == hist
     assert c.result.rel_residual <= 1e-10
     assert stats["completed"] == 1 and stats["batches_created"] == 1
+    _check_exact(u, f, "single")
 
 
 def test_results_identical_alone_and_in_the_mix():
@@ -97,6 +117,7 @@ def test_results_identical_alone_and_in_the_mix():
         assert c.result.hist() == hist, tag
         assert c.result.rel_residual <= 1e-10
         assert c.t_submit <= c.t_admit <= c.t_done
+        _check_exact(u, f, "mix %d" % tag)
     a, b, d = out[0][0], out[9][0], out[20][0]
     assert np.array_equal(a, b) and np.array_equal(a, d)
 
@@ -120,6 +141,7 @@ def test_red_black_requests_equal_standalone_solves(precision):
         assert np.array_equal(u, ref), tag
         assert c.result.hist() == hist, tag
         assert c.result.rel_residual <= 1e-10
+        _check_exact(u, f, "red-black %d" % tag)
 
 
 def test_admission_by_footprint():
@@ -137,12 +159,14 @@ def test_admission_by_footprint():
     for tag, n, f in reqs:
         ref, _, _ = _solo(n, f)
         assert np.array_equal(out[tag][0], ref)
+        _check_exact(out[tag][0], f, "admission %d" % tag)
     # second server: a 513 request, then a 257 request that needs the 513 batch released
     reqs2 = [(0, 513, reqs[0][2]), (1, 257, _rhs(257, inputs.SEED_BASE + 1300))]
     out2, stats2 = _serve(reqs2, budget=budget, stagger=[0.05, 0.0])
     assert stats2["completed"] == 2
     assert stats2["batches_created"] == 2 and stats2["batches_released"] >= 1
     assert np.array_equal(out2[0][0], out[0][0])
+    _check_exact(out2[1][0], reqs2[1][2], "admission 257")
 
 
 def test_many_small_requests_fill_the_slots():
@@ -153,6 +177,8 @@ def test_many_small_requests_fill_the_slots():
         ref, _, hist = _solo(n, f)
         assert np.array_equal(out[tag][0], ref)
         assert out[tag][1].result.hist() == hist
+    for tag, n, f in reqs:
+        _check_exact(out[tag][0], f, "small %d" % tag)
 
 
 def test_oversized_request_is_rejected():

@@ -628,6 +628,59 @@ def test_residual_norm_long_double_agrees():
     assert abs(a - b) <= 1e-13 * b
 
 
+def _sine_mode(n, k):
+    """prod_a sin(k_a pi x_a) on the n-point grid, exactly zero on the boundary; k is
+    (kx, ky[, kz]) and the array is indexed [z][y][x]."""
+    x = np.linspace(0.0, 1.0, n)
+    v = np.ones((n,) * len(k))
+    for a, ka in enumerate(k):
+        shape = [1] * len(k)
+        shape[len(k) - 1 - a] = n
+        line = np.sin(ka * np.pi * x)
+        line[0] = line[-1] = 0.0
+        v = v * line.reshape(shape)
+    return v
+
+
+@pytest.mark.parametrize("dim,n,modes", [
+    (2, 33, [(1, 1), (3, 7), (31, 1), (16, 16), (31, 31)]),
+    (3, 17, [(1, 1, 1), (2, 5, 15), (8, 8, 8), (15, 1, 15)]),
+])
+def test_norm_of_sine_modes_is_closed_form(dim, n, modes):
+    """The grid norm ||v||_h = (h^dim sum over interior points of v^2)^(1/2) of a sine
+    mode is 2^(-dim/2) exactly: along an axis the interior sum of sin^2(k pi i/N) is N/2
+    for 1 <= k <= N-1 (N = n-1), and h^dim (N/2)^dim = 2^-dim.  Boundary values are not
+    part of the norm."""
+    for k in modes:
+        v = _sine_mode(n, k)
+        assert abs(oracle.norm(v) - 2.0 ** (-dim / 2)) <= 1e-14, k
+        assert abs(oracle.norm(-3.5 * v) - 3.5 * 2.0 ** (-dim / 2)) <= 1e-13, k
+        w = v.copy()
+        w[0] = 7.0      # a whole boundary face (z = 0 in 3D, y = 0 in 2D)
+        w[..., -1] = -2.0
+        assert oracle.norm(w) == oracle.norm(v)
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, 33, (1, 1)), (2, 33, (5, 29)), (2, 65, (64 - 1, 2)),
+                                     (3, 17, (1, 2, 3)), (3, 17, (15, 15, 15)), (3, 33, (7, 1, 30))])
+def test_residual_norms_of_a_sine_mode(dim, n, k):
+    """With u a sine mode and f = c u, f - L_h u = (c - lambda_k) u: the odd-reflection
+    closure makes the mode an exact eigenfunction, with lambda_k the fourth-order symbol
+    of appendix A.4, (4/h^2) sum_a (s_a + s_a^2/3), s_a = sin^2(k_a pi h/2).  So both
+    residual norms (FP64 and long double) equal |c - lambda_k| 2^(-dim/2)."""
+    h = 1.0 / (n - 1)
+    s = np.sin(np.array(k) * np.pi * h / 2.0) ** 2
+    lam = 4.0 / h ** 2 * np.sum(s + s * s / 3.0)
+    u = _sine_mode(n, k)
+    st = oracle.fine_stencil(dim, 4, h)
+    for c in (0.0, 0.5 * lam, 2.0 * lam):
+        f = c * u
+        expect = abs(c - lam) * 2.0 ** (-dim / 2)
+        tol = 1e-12 * lam
+        assert abs(oracle.norm(oracle.residual(st, f, u)) - expect) <= tol, c
+        assert abs(oracle.residual_norm_ld(st, f, u) - expect) <= tol, c
+
+
 def test_coarsest_solve_is_exact():
     mg = oracle.Multigrid(3, 17, n_coarsest=9)
     n, s = mg.level_stencil(mg.levels - 1)

@@ -189,3 +189,20 @@ def test_level_counts():
         rbc.RBC(17, 9)
     with pytest.raises(ValueError):
         rbc.RBC(18, 2)
+
+
+@pytest.mark.parametrize("n,k", [(33, (1, 1)), (33, (3, 30)), (65, (32, 32)), (17, (15, 1))])
+def test_norm_of_a_sine_mode_is_closed_form(n, k):
+    """The level-0 norm sqrt(mean of r^2 over the interior) of sin(kx pi x) sin(ky pi y) is
+    N / (2 (N - 1)), N = n - 1: along an axis the interior sum of sin^2(k pi i/N) is N/2 for
+    1 <= k <= N-1, over N - 1 interior points.  Boundary values are not part of it."""
+    N = n - 1
+    x = np.linspace(0.0, 1.0, n)
+    lx, ly = np.sin(k[0] * np.pi * x), np.sin(k[1] * np.pi * x)
+    for line in (lx, ly):
+        line[0] = line[-1] = 0.0
+    r = np.outer(ly, lx)
+    assert abs(rbc.norm(r) - N / (2.0 * (N - 1))) <= 1e-14
+    r[0, :] = 5.0
+    r[:, -1] = -1.0
+    assert abs(rbc.norm(r) - N / (2.0 * (N - 1))) <= 1e-14
