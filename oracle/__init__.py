@@ -34,9 +34,10 @@ COARSE_NG, COARSE_GALERKIN = 0, 1
 # second-order coarse operators for a fourth-order fine operator (section 3.1):
 # rediscretized (eq. L_H_2d) and "Galerkin" from the second-order operator (eq. L_H_2G_2d)
 COARSE_NG2, COARSE_G2 = 2, 3
-# smoothers: omega-Jacobi (section 5.3) and omega red-black Jacobi (section 3.1 eq. S_rb with
-# the Jacobi partial step; red = odd index sum)
-SMOOTH_JACOBI, SMOOTH_RBJ = 0, 1
+# smoothers: omega-Jacobi (section 5.3), omega red-black Jacobi (section 3.1 eq. S_rb with
+# the Jacobi partial step; red = odd index sum) and omega red-black Gauss-Seidel (eqs. S_rb,
+# S_GS: the partial step sweeps its colour in lexicographic order)
+SMOOTH_JACOBI, SMOOTH_RBJ, SMOOTH_RBGS = 0, 1, 2
 MAX_RADIUS = 6
 
 
@@ -77,6 +78,7 @@ def _load():
             "or_residual": (None, [_I, _I, _I, _D, _D, _D, _D]),
             "or_jacobi": (None, [_I, _I, _I, _D, ctypes.c_double, _D, _D, _D]),
             "or_jacobi_colour": (None, [_I, _I, _I, _D, ctypes.c_double, _I, _D, _D, _D]),
+            "or_gs_colour": (None, [_I, _I, _I, _D, ctypes.c_double, _I, _D, _D, _D]),
             "or_restrict": (None, [_I, _I, _I, _D, _D]),
             "or_prolong_add": (None, [_I, _I, _I, _D, _D]),
             "or_norm": (ctypes.c_double, [_I, _I, _D]),
@@ -176,6 +178,17 @@ def jacobi_colour(s, omega, colour, f, u):
     return out
 
 
+def gs_colour(s, omega, colour, f, u):
+    """One Gauss-Seidel partial step (section 3.1 eq. S_GS) on colour 1 (odd index sum),
+    2 (even) or 0 (every point): the colour's points in lexicographic order, in place."""
+    dim, n = _grid_dim(u)
+    out = np.empty_like(u)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    _load().or_gs_colour(dim, n, _stencil_radius(s), _p(s), float(omega), int(colour), _p(f),
+                         _p(u), _p(out))
+    return out
+
+
 def restrict(d, restrict_op=RESTRICT_FW):
     dim, nf = _grid_dim(d)
     nc = (nf - 1) // 2 + 1
@@ -216,6 +229,12 @@ def jacobi_omega(dim, order=4):
             6: {2: 490.0 / 653.0, 3: 147.0 / 185.0}}[order][dim]
 
 
+def rbgs_omega(dim, order=4):
+    """Default omega of red-black Gauss-Seidel (2D): the minimiser of the LFA two-grid factor
+    of the V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
+    return {(2, 4): 1.16, (2, 2): 1.0, (2, 6): 1.18}[(dim, order)]
+
+
 def rbj_omega(dim, order=4):
     """Default omega of red-black Jacobi: the minimiser of the LFA two-grid factor of the
     V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
@@ -230,7 +249,8 @@ class Multigrid:
                  prolong=PROLONG_CUBIC, nu1=2, nu2=1, gamma=1, n_coarsest=9, omega=None,
                  smoother=SMOOTH_JACOBI):
         if omega is None:
-            omega = jacobi_omega(dim, order) if smoother == SMOOTH_JACOBI else rbj_omega(dim, order)
+            omega = {SMOOTH_JACOBI: jacobi_omega, SMOOTH_RBJ: rbj_omega,
+                     SMOOTH_RBGS: rbgs_omega}[smoother](dim, order)
         self.cfg = _Config(dim, n, order, coarse, restrict_op, prolong, nu1, nu2, gamma,
                            n_coarsest, float(omega), smoother)
         self.dim, self.n = dim, n

@@ -16,6 +16,12 @@ Everything here is built from the Fourier symbols the paper prints, not from ste
   step.  Multiplying a grid function by (-1)^(index sum) moves theta to theta + (pi,..,pi),
   so a partial step is I + (1/2)(I -+ P) (S_J - I) on the 2^d aliases, P the alias
   permutation alpha -> 1 - alpha (section 5.3 eq. S_hat_RB_2d is the 2D five-point case);
+* omega red-black Gauss-Seidel (section 3.1 eqs. S_rb, S_GS): the same partial steps with
+  the Jacobi symbol replaced by that of S_GS = -(L+)^{-1} L-, L+ = a_0/omega + the
+  same-colour entries before the point in lexicographic order; on a cross-stencil level
+  these are the entries at -2 e_a, so L+^ = a_0/omega + sum_a c_2 e^{-2 i theta_a} and
+  S_GS^ = 1 - L^/L+^ (appendix A.4 prints it for the fourth-order operator; for the
+  five-point operator it is the Jacobi symbol);
 * two-grid operator on the 2^d aliases of theta in [-pi/2, pi/2)^d:
   M = S^nu2 (I - p L_H^{-1} r^T diag(L)) S^nu1 (section 2.2 eqs. K, M_2level; appendix
   A.2 eqs. K_hat_2, M_2); Galerkin coarse symbol L_H(2 theta) = sum_alpha r_alpha L_alpha p_alpha
@@ -42,7 +48,7 @@ FW, CUBIC = 1, 3
 LINEAR = 1
 NG, GALERKIN = 0, 1
 NG2, G2 = 2, 3  # second-order coarse operators (section 3.1 eqs. L_H_2d, L_H_2G_2d)
-JACOBI, RBJ = 0, 1  # smoothers: omega-Jacobi, omega red-black Jacobi
+JACOBI, RBJ, RBGS = 0, 1, 2  # smoothers: omega-Jacobi, omega red-black Jacobi and Gauss-Seidel
 
 
 def sin2(theta):
@@ -91,7 +97,12 @@ class Scheme:
         self.nu1, self.nu2 = nu1, nu2
         self.smoother = smoother
         if omega is None:
-            omega = jacobi_optimum(dim, order)[0] if smoother == JACOBI else RBJ_OMEGA[(dim, order)]
+            if smoother == JACOBI:
+                omega = jacobi_optimum(dim, order)[0]
+            elif smoother == RBJ:
+                omega = RBJ_OMEGA[(dim, order)]
+            else:
+                omega = RBGS_OMEGA[(dim, order)]
         self.omega = omega
 
     def level_symbol(self, level, theta, h0=1.0):
@@ -122,10 +133,32 @@ class Scheme:
     def smoother_symbol(self, theta, level=0, h0=1.0):
         return 1.0 - self.omega * self.level_symbol(level, theta, h0) / self.level_diagonal(level, h0)
 
+    def cross_c2(self, level, h0=1.0):
+        """Coefficient of the entries at +-2 e_a of a cross-stencil level (the fourth-order
+        operator: 1/(12 h^2); the five-point operator: 0); None for a Galerkin level."""
+        h = h0 * 2 ** level
+        order = self.order if (level == 0 or self.coarse == NG) else (2 if self.coarse == NG2 else None)
+        if order is None:
+            return None
+        return {2: 0.0, 4: 1.0 / (12.0 * h * h), 6: 27.0 / (180.0 * h * h)}[order]
+
+    def gs_symbol(self, modes, level=0, h0=1.0):
+        """Symbol of S_GS = -(L+)^{-1} L- on a cross-stencil level (complex)."""
+        c2 = self.cross_c2(level, h0)
+        if c2 is None:
+            raise ValueError("red-black Gauss-Seidel analysis needs a cross-stencil level")
+        modes = np.asarray(modes, dtype=float)
+        Lh = self.level_symbol(level, modes, h0)
+        lplus = self.level_diagonal(level, h0) / self.omega + c2 * np.sum(np.exp(-2j * modes), axis=-1)
+        return 1.0 - Lh / lplus
+
     def smoother_on(self, modes, partner, level=0, h0=1.0):
         """Symbol of one smoothing sweep at level l on a set of modes closed under
         theta -> theta + (pi,..,pi); partner[i] is the index of that shift of modes[i]."""
-        D = np.diag(-self.omega * self.level_symbol(level, modes, h0) / self.level_diagonal(level, h0))
+        if self.smoother == RBGS:
+            D = np.diag(self.gs_symbol(modes, level, h0) - 1.0)
+        else:
+            D = np.diag(-self.omega * self.level_symbol(level, modes, h0) / self.level_diagonal(level, h0))
         eye = np.eye(len(D))
         if self.smoother == JACOBI:
             return eye + D
@@ -184,6 +217,11 @@ class Scheme:
         K = np.eye(len(ks)) - P @ solve1 @ R @ np.diag(L0)
         S = self.smoother_on(modes, partner, 0, h0)
         return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
+
+# Default omega of the red-black Gauss-Seidel smoother (2D): the minimiser of the two-grid
+# factor of the V(2,1) cycle with cubic interpolation and the rediscretized operator, to two
+# decimals (rbgs_optimum recomputes it).  For the five-point operator it is red-black Jacobi.
+RBGS_OMEGA = {(2, 4): 1.16, (2, 2): 1.0, (2, 6): 1.18}
 
 # Default omega of the red-black Jacobi smoother: the value minimising the two-grid factor
 # of the V(2,1) cycle with cubic interpolation and the rediscretized operator, rounded to two
@@ -299,3 +337,12 @@ def finite_two_grid_spectrum(scheme, n):
             S = fold @ scheme.smoother_matrix(theta, h0)[:, keep]
             eig.extend(np.linalg.eigvals(np.linalg.matrix_power(S, scheme.nu1 + scheme.nu2)))
     return np.array(eig)
+
+
+def rbgs_optimum(order=4, m=24):
+    """omega minimising two_grid_rho for red-black Gauss-Seidel (2D), V(2,1), cubic,
+    rediscretized."""
+    from scipy.optimize import minimize_scalar
+    rho = lambda w: two_grid_rho(Scheme(2, order, nu1=2, nu2=1, omega=w, smoother=RBGS), m)
+    r = minimize_scalar(rho, bounds=(0.8, 1.4), method="bounded", options={"xatol": 1e-4})
+    return float(r.x), float(r.fun)

@@ -310,6 +310,24 @@ void or_jacobi_colour(int dim, int n, int R, const double *s, double omega, int 
   free_entries(&e);
 }
 
+void or_gs_colour(int dim, int n, int R, const double *s, double omega, int colour,
+                  const double *f, const double *u, double *u_out) {
+  entries e = list_entries(dim, R, s);
+  double a0 = s[sidx(dim, R, 0, 0, 0)];
+  memcpy(u_out, u, sizeof(double) * npts(dim, n));
+  /* sequential on purpose: each point sees the new values of the points before it */
+  for (int k = k_first(dim); k < k_end(dim, n); ++k)
+    for (int j = 1; j < n - 1; ++j)
+      for (int i = 1; i < n - 1; ++i) {
+        int odd = (i + j + k) % 2;
+        if (colour == 1 && !odd) continue;
+        if (colour == 2 && odd) continue;
+        long p = at(n, i, j, k);
+        u_out[p] += omega / a0 * (f[p] - apply_at(&e, dim, n, u_out, i, j, k));
+      }
+  free_entries(&e);
+}
+
 void or_jacobi(int dim, int n, int R, const double *s, double omega, const double *f,
                const double *u, double *u_out) {
   or_jacobi_colour(dim, n, R, s, omega, 0, f, u, u_out);
@@ -510,7 +528,9 @@ or_mg *or_mg_create(const or_config *cfg) {
   if (L <= 0 || L > OR_MAX_LEVELS || (cfg->dim != 2 && cfg->dim != 3)) return NULL;
   if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6) return NULL;
   if (cfg->coarse < OR_COARSE_NG || cfg->coarse > OR_COARSE_G2) return NULL;
-  if (cfg->smoother != OR_SMOOTH_JACOBI && cfg->smoother != OR_SMOOTH_RBJ) return NULL;
+  if (cfg->smoother != OR_SMOOTH_JACOBI && cfg->smoother != OR_SMOOTH_RBJ &&
+      cfg->smoother != OR_SMOOTH_RBGS)
+    return NULL;
   or_mg *mg = (or_mg *)calloc(1, sizeof(or_mg));
   int dim = cfg->dim;
   int w = swidth(OR_MAX_RADIUS);
@@ -579,11 +599,15 @@ static void smooth(or_mg *mg, int l, double *u, const double *f, int sweeps) {
   or_level *lv = &mg->lev[l];
   int dim = mg->cfg.dim;
   /* omega-Jacobi: one partial step on every point; red-black: red points, then black
-   * points from the updated red values (S = S^B S^R, section 3.1 eq. S_rb) */
-  const int rb = mg->cfg.smoother == OR_SMOOTH_RBJ;
+   * points from the updated red values (S = S^B S^R, section 3.1 eq. S_rb), each partial
+   * step a Jacobi step (RBJ) or a Gauss-Seidel step (RBGS, eq. S_GS) on its colour */
+  const int rb = mg->cfg.smoother != OR_SMOOTH_JACOBI;
   for (int s = 0; s < sweeps; ++s) {
     for (int c = rb ? 1 : 0; c <= (rb ? 2 : 0); ++c) {
-      or_jacobi_colour(dim, lv->n, lv->R, lv->s, mg->cfg.omega, c, f, u, lv->t);
+      if (mg->cfg.smoother == OR_SMOOTH_RBGS)
+        or_gs_colour(dim, lv->n, lv->R, lv->s, mg->cfg.omega, c, f, u, lv->t);
+      else
+        or_jacobi_colour(dim, lv->n, lv->R, lv->s, mg->cfg.omega, c, f, u, lv->t);
       memcpy(u, lv->t, sizeof(double) * npts(dim, lv->n));
     }
   }

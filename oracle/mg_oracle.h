@@ -47,6 +47,11 @@ extern "C" {
 #define OR_SMOOTH_RBJ 1    /* omega red-black Jacobi: section 3.1 eq. S_rb, S = S^B S^R, with the
                             * Jacobi partial step on each colour (the smoother appendix A.4.1
                             * uses); red = odd index sum i+j(+k), black = even */
+#define OR_SMOOTH_RBGS 2   /* omega red-black Gauss-Seidel: section 3.1 eqs. S_rb and S_GS, the
+                            * partial step on a colour -(L+)^{-1} L- with L+ the centre over
+                            * omega plus the same-colour entries that precede the point in
+                            * lexicographic order (x fastest): an in-place sweep of the colour's
+                            * points in that order */
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -59,7 +64,8 @@ typedef struct {
   int gamma;        /* 1 = V cycle, 2 = W cycle */
   int n_coarsest;   /* points per axis of the coarsest level, e.g. 9 */
   double omega;     /* omega-Jacobi relaxation parameter, same on every level */
-  int smoother;     /* OR_SMOOTH_JACOBI or OR_SMOOTH_RBJ; a sweep of either counts once in nu */
+  int smoother;     /* OR_SMOOTH_JACOBI, OR_SMOOTH_RBJ or OR_SMOOTH_RBGS; a sweep (both colours
+                     * of a red-black one) counts once in nu */
 } or_config;
 
 /* Number of levels n, (n-1)/2+1, ... down to n_coarsest; 0 if n does not reach it. */
@@ -93,6 +99,13 @@ void or_jacobi(int dim, int n, int R, const double *s, double omega, const doubl
  * every other point keeps u.  Colour 0 updates every interior point (or_jacobi). */
 void or_jacobi_colour(int dim, int n, int R, const double *s, double omega, int colour,
                       const double *f, const double *u, double *u_out);
+/* One omega Gauss-Seidel partial step on one colour (section 3.1 eq. S_GS): u_out = u, then
+ * the interior points of the colour, in lexicographic order (x fastest, then y, then z),
+ * are replaced in u_out one at a time by u_out + omega/a_0 (f - L u_out), L evaluated on
+ * the current u_out (values beyond the boundary are odd reflections of current values).
+ * Points of the other colour are not changed.  Colour 0: every interior point. */
+void or_gs_colour(int dim, int n, int R, const double *s, double omega, int colour,
+                  const double *f, const double *u, double *u_out);
 /* fc = I_h^H d on the coarse grid of nc = (nf-1)/2+1 points (standard coarsening). */
 void or_restrict(int dim, int nf, int restrict_op, const double *d, double *fc);
 /* u += I_H^h v, v on the coarse grid of nc = (nf-1)/2+1 points. */
