@@ -78,8 +78,10 @@ def parse():
                    help="0 rediscretized, 1 Galerkin, 2 second-order rediscretized, 3 second-order Galerkin")
     p.add_argument("--gamma", type=int, default=None)
     p.add_argument("--smoother", type=int, default=None,
-                   help="0 omega-Jacobi (default), 1 red-black Jacobi")
+                   help="0 omega-Jacobi (default), 1 red-black Jacobi, 2 red-black Gauss-Seidel (2D)")
     p.add_argument("--order", type=int, default=None, help="fine operator order: 4 (default), 2 or 6")
+    p.add_argument("--restrict", type=int, default=None,
+                   help="restriction: 1 full weighting (default), 3 cubic adjoint (rediscretized coarse operators)")
     p.add_argument("--omega", type=float, default=None, help="relaxation (default: the LFA optimum)")
     p.add_argument("--precision", type=int, default=None)
     p.add_argument("--compare", type=int, default=None, help="also run the other precision")
@@ -94,6 +96,8 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=1000,
                    help="requests per serving run (0: skip the serving measurement)")
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement")
+    p.add_argument("--stream-groups", type=int, default=3,
+                   help="serving: streams shared by size groups (0: one stream per batch)")
     p.add_argument("--rbc-only", action="store_true", help="only the red-black coarsening runs")
     return p.parse_args()
 
@@ -125,9 +129,10 @@ def describe(w):
            "sine": "smooth sine-series RHS k<=8"}[w["rhs"]]
     prec = "FP64" if w["precision"] == 0 else "FP32 cycles in FP64 refinement"
     d = w["dim"]
-    sm = "red-black Jacobi" if w.get("smoother", 0) else "omega-Jacobi"
-    return "%dD %dth-order Poisson %s, %s, %s %s, FW + cubic, %s coarse ops to 9^%d, %s, to 1e-10" % (
-        d, w.get("order", 4), "x".join([str(w["n"])] * d), rhs, cyc, sm, kind, d, prec)
+    sm = {0: "omega-Jacobi", 1: "red-black Jacobi", 2: "red-black Gauss-Seidel"}[w.get("smoother", 0)]
+    tr = "cubic-adjoint restriction + cubic" if w.get("restrict", 1) == 3 else "FW + cubic"
+    return "%dD %dth-order Poisson %s, %s, %s %s, %s, %s coarse ops to 9^%d, %s, to 1e-10" % (
+        d, w.get("order", 4), "x".join([str(w["n"])] * d), rhs, cyc, sm, tr, kind, d, prec)
 
 
 class Run:
@@ -141,7 +146,8 @@ class Run:
                                   nu1=w["nu1"], nu2=w["nu2"], precision=precision, rtol=1e-10,
                                   max_cycles=60 if precision == 0 else 30,
                                   inner_cycles=w["inner"], smoother=w.get("smoother", 0),
-                                  order=w.get("order", 4), omega=w.get("omega", 0.0))
+                                  order=w.get("order", 4), omega=w.get("omega", 0.0),
+                                  restrict_op=w.get("restrict", 1))
         self.h = mg.mg_setup(self.cfg, stream.cuda_stream)
         self.fd = fd
         self.ud = torch.zeros_like(fd)
@@ -197,7 +203,14 @@ def in_cycle_time(run, w, stream, reps):
     t = torch.empty_like(u)
     fc = torch.empty((nc,) * d, device="cuda", dtype=dt)
     v = torch.randn((nc,) * d, generator=gen, device="cuda", dtype=torch.float64).to(dt)
-    if w.get("smoother", 0) and d == 3:
+    if w.get("restrict", 1) == 3 and d == 2 and w.get("smoother", 0) != 2:
+        bufs = [u, t]
+        def one():
+            e0.record(stream)
+            mg.mg_kernel_smooth(run.h, 0, fp32, f.data_ptr(), bufs[0].data_ptr(), bufs[1].data_ptr())
+            e1.record(stream)
+            bufs.reverse()
+    elif w.get("smoother", 0) == 2 or (w.get("smoother", 0) and d == 3):
         # red then black partial steps in a ping-pong, as the cycle runs them
         bufs = [u, t]
         col = [1]
@@ -263,7 +276,33 @@ def level_kernels(run, w, stream, reps, only_level0=False):
         v = torch.randn(cshp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
         P, Pc = n ** d, nc ** d
         rb = w.get("smoother", 0)
-        if rb and d == 3:
+        if d == 2 and (rb == 2 or w.get("restrict", 1) == 3):
+            # 2D separate kernels (red-black Gauss-Seidel, or the cubic-adjoint restriction):
+            # a smoothing launch (a Gauss-Seidel partial step or an omega-Jacobi sweep), the
+            # defect + restriction and the interpolation + correction
+            if rb == 2:
+                sk = ("k_gs2d", "Gauss-Seidel partial step",
+                      lambda: mg.mg_kernel_smooth_colour(run.h, l, fp32, 1, f.data_ptr(), u.data_ptr(),
+                                                         t.data_ptr()))
+            else:
+                sk = ("k_pre2d", "omega-Jacobi sweep",
+                      lambda: mg.mg_kernel_smooth(run.h, l, fp32, f.data_ptr(), u.data_ptr(), t.data_ptr()))
+            cubic = w.get("restrict", 1) == 3
+            ks = [
+                (sk[0], sk[1], 3 * P * b, sk[2]),
+                ("k_restrict_cubic" if cubic else "k_pre2d",
+                 "defect, then cubic-adjoint restriction" if cubic else "defect+FW",
+                 ((2 * P + P) + (P + Pc)) * b if cubic else (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
+                                                        fc.data_ptr())),
+                ("k_pre2d", "defect+FW", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
+                                                        fc.data_ptr())),
+                ("k_post2d", "interp+correct", (2 * P + Pc) * b,
+                 lambda: mg.mg_kernel_prolong_correct(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
+                                                      t.data_ptr())),
+            ]
+        elif rb and d == 3:
             # 3D red-black smoothing: two partial-step launches per sweep
             ks = [
                 ("k_sweep%dd" % d, "red-black partial step", 3 * P * b,
@@ -420,7 +459,7 @@ def rbc_pmc_probe(fd, stream, n):
 SERVE_BUDGET = 32 << 30
 
 
-def serve_bench(count, loads=(0.5, 0.8, 0.95), smoother=0, inner=4):
+def serve_bench(count, loads=(0.5, 0.8, 0.95), smoother=0, inner=4, stream_groups=3):
     """Continuous-batching server on a Poisson stream of 2D solves, n = 2^k + 1 with k
     uniform on 6..11, Fourier right-hand sides (k <= min(64, (n-1)/4)), mixed precision
     V(2,1) to 1e-10.  First all requests at once (saturated throughput), then open-loop
@@ -440,7 +479,7 @@ def serve_bench(count, loads=(0.5, 0.8, 0.95), smoother=0, inner=4):
         fs.setdefault(n, f)
     torch.cuda.synchronize()
     unknowns = sum((n - 2) ** 2 for _, n, _, _, _ in reqs)
-    S = serve.Server(SERVE_BUDGET, 16, 2, n=65, **base)
+    S = serve.Server(SERVE_BUDGET, 16, 2, stream_groups, n=65, **base)
     try:
         # warm-up: one request per size creates every batch and captures its graph
         warm = [(10 ** 6 + n, f, torch.empty_like(f)) for n, f in sorted(fs.items())]
@@ -486,6 +525,7 @@ def serve_bench(count, loads=(0.5, 0.8, 0.95), smoother=0, inner=4):
         rate_sat = len(reqs) / span
         out = {
             "requests": len(reqs), "sizes": "2^k+1, k~U{6..11}", "precision": "mixed",
+            "stream_groups": stream_groups,
             "saturated": {"requests_per_s": rate_sat, "unknowns_per_s": unknowns / span,
                           "makespan_s": span, "p50_ms": float(np.percentile(lat_sat, 50) * 1e3),
                           "p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
@@ -634,12 +674,12 @@ def time_workload(w, args, stream, fd, label, variants_2d=False):
         out["config_variants"] = config_variants_2d(w, fd, stream, sec, res)
     rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
     rb = bool(w.get("smoother", 0))
-    dom_name = "k_pre2d" if d == 2 else "k_sweep3d"
+    dom_name = ("k_gs2d" if w.get("smoother", 0) == 2 else "k_pre2d") if d == 2 else "k_sweep3d"
     dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
     if not dom:
         dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
                if r["kernel"] == dom_name]
-    dom = dom[0]
+    dom = dom[0]  # with separate 2D kernels the first listed (smoothing) launch
     cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
     src = "fused2d.hip" if d == 2 else "kernels3d.hip"
     key = "%s/%s/%s/%d%s%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "",
@@ -702,7 +742,8 @@ def config_variants_2d(w, fd, stream, sec, res):
 def setup_workload(args, name):
     w = dict(WORKLOADS[name])
     if name == args.workload:
-        for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order", "omega"):
+        for k in ("n", "coarse", "gamma", "precision", "compare", "inner", "smoother", "order", "omega",
+                  "restrict"):
             if getattr(args, k) is not None:
                 w[k] = getattr(args, k)
     return w
@@ -721,7 +762,8 @@ def main():
     stream = torch.cuda.current_stream()
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(max(args.serve_requests, 1), smoother=w.get("smoother", 0),
-                                                 inner=args.inner or 4)}), flush=True)
+                                                 inner=args.inner or 4, stream_groups=args.stream_groups)}),
+              flush=True)
         return
     f, coeffs = make_rhs(w)
     fd = torch.from_numpy(f).cuda()
@@ -758,7 +800,7 @@ def main():
                                  "galerkin-order2"][w["coarse"]],
         "precision": "fp64" if w["precision"] == 0 else "mixed",
         "inner_cycles": w["inner"] if w["precision"] else None,
-        "smoother": "red-black-jacobi" if w.get("smoother", 0) else "jacobi",
+        "smoother": {0: "jacobi", 1: "red-black-jacobi", 2: "red-black-gauss-seidel"}[w.get("smoother", 0)],
         "order": w.get("order", 4),
         "cycles": prim["cycles"], "outer_steps": prim["outer_steps"],
         "final_rel_residual": prim["final_rel_residual"], "reached_rtol": prim["reached_rtol"],
@@ -822,9 +864,10 @@ def main():
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
             print("bench: serving", file=sys.stderr, flush=True)
-            out["serving"] = serve_bench(args.serve_requests)
+            out["serving"] = serve_bench(args.serve_requests, stream_groups=args.stream_groups)
             # the same stream with red-black Jacobi smoothing (2 FP32 cycles per refinement step)
-            out["serving_redblack"] = serve_bench(args.serve_requests, smoother=1, inner=2)
+            out["serving_redblack"] = serve_bench(args.serve_requests, smoother=1, inner=2,
+                                                  stream_groups=args.stream_groups)
     print(json.dumps(out), flush=True)
 
 

@@ -61,10 +61,16 @@ typedef enum {
 
 typedef enum {
   MG_SMOOTH_JACOBI = 0,  /* omega-Jacobi: every interior point relaxed at once (section 5.3) */
-  MG_SMOOTH_RBJ = 1      /* omega red-black Jacobi (section 3.1 eq. S_rb with the Jacobi partial
+  MG_SMOOTH_RBJ = 1,     /* omega red-black Jacobi (section 3.1 eq. S_rb with the Jacobi partial
                           * step; the smoother of appendix A.4.1): the red points (odd index sum
                           * i+j(+k)) take an omega-Jacobi step, then the black points from the
                           * updated red values; one such pair counts once in nu1, nu2 */
+  MG_SMOOTH_RBGS = 2     /* omega red-black Gauss-Seidel (section 3.1 eqs. S_rb, S_GS): each
+                          * partial step sweeps its colour in lexicographic order (x fastest),
+                          * a point reading the new values of the same-colour points before it
+                          * (L+ = a_0/omega plus the entries at -2 e_x, -2 e_y); 2D only, with
+                          * rediscretized coarse operators (MG_COARSE_NG or MG_COARSE_NG2, cross
+                          * stencils on every level), else MG_EINVAL */
 } mg_smoother;
 
 typedef enum {
@@ -80,15 +86,22 @@ typedef struct {
                           width-7 stencil, section 3.3 eq. LhOrder6) */
   int coarse;          /* mg_coarse */
   int smoother;        /* mg_smoother */
-  double omega;        /* Jacobi relaxation; <= 0 selects the Fourier-analysis optimum:
-                          omega-Jacobi 10/13 in 2D, 9/11 in 3D for order 4 (4/5, 6/7 for
-                          order 2; 490/653, 147/185 for order 6); red-black Jacobi 1.13 in
-                          2D, 1.17 in 3D for order 4 (1.0, 1.13 for order 2; 1.13, 1.15 for
-                          order 6), the minimisers of the two-grid factor of V(2,1) */
+  double omega;        /* relaxation; <= 0 selects the Fourier-analysis optimum:
+                          omega-Jacobi (any coarse operator) 10/13 in 2D, 9/11 in 3D for order
+                          4 (4/5, 6/7 for order 2; 490/653, 147/185 for order 6), by
+                          equioscillation; the red-black smoothers the minimiser of the
+                          two-grid factor of V(2,1) with cubic interpolation, per coarse
+                          operator (NG, GALERKIN, NG2, G2): red-black Jacobi, order 4:
+                          2D 1.13, 1.00, 0.98, 0.97; 3D 1.17, 1.09, 1.09, 1.08 (order 6: 2D
+                          1.13, 1.02, 0.99, 0.99; 3D 1.15, 1.10, 1.09, 1.08; order 2: 2D 1.00,
+                          0.98; 3D 1.13, 1.09); red-black Gauss-Seidel (2D): NG 1.16, NG2 0.98
+                          for order 4 (1.18, 1.00 for order 6; 1.00 for order 2) */
   int nu1, nu2;        /* pre- and post-smoothing sweeps per cycle (nu1 + nu2 >= 1) */
   int gamma;           /* 1 = V cycle, 2 = W cycle */
   int prolong;         /* 3 = cubic interpolation, 1 = (bi/tri)linear */
-  int restrict_op;     /* 1 = full weighting */
+  int restrict_op;     /* 1 = full weighting (section 3.1 eq. transfer_2d); 3 = the cubic
+                          interpolation's adjoint (appendix A.4, the 1/1024 operator), with
+                          rediscretized coarse operators only (MG_COARSE_NG, MG_COARSE_NG2) */
   int n_coarsest;      /* side of the coarsest level (exact dense solve), e.g. 9 */
   int precision;       /* mg_precision */
   double rtol;         /* stop when ||f - L u||_h <= rtol ||f||_h */
@@ -177,7 +190,9 @@ mg_status mg_kernel_smooth(mg_handle h, int level, int fp32, const void *f, cons
                            void *u_out);
 
 /* One partial step of red-black smoothing (section 3.1 eq. S_rb): the points of one colour
- * take the omega-Jacobi step of mg_kernel_smooth, every other point copies u_in.
+ * take the omega-Jacobi step of mg_kernel_smooth, every other point copies u_in.  On a
+ * MG_SMOOTH_RBGS handle's radius-2/3 cross levels the step is the Gauss-Seidel one of eq.
+ * S_GS instead (colour 1 or 2 only, u_in not NULL).
  * colour 1 = red (odd index sum i+j(+k)), 2 = black (even), 0 = every point.  A red-black
  * sweep is colour 1 into a second array, then colour 2 back; colour 3 runs the whole
  * red-black sweep in one pass (2D: every level; 3D: levels with the cross operator, else
@@ -189,7 +204,9 @@ mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, 
 mg_status mg_kernel_residual(mg_handle h, int level, int fp32, const void *f, const void *u,
                              void *r);
 
-/* fc = I_h^H (f - L_l u) on level l+1 (defect and full weighting in one pass). */
+/* fc = I_h^H (f - L_l u) on level l+1: defect and full weighting in one pass; with the
+ * cubic-adjoint restriction (restrict_op = 3) the defect first goes to the handle's level-l
+ * sweep target (a mixed-precision handle then takes fp32 = 1 only). */
 mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const void *f,
                                       const void *u, void *fc);
 

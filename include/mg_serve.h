@@ -12,8 +12,8 @@
  * that size, every level array laid out [slot][n_l * n_l], one stopping state per slot,
  * and the solve step (a gamma-cycle in FP64, or one refinement step in mixed precision)
  * captured once into a HIP graph whose kernels take the slot from the grid's third
- * dimension.  Each batch runs on its own stream, so batches of different sizes overlap
- * on the device.  A worker thread owned by the server replays each busy batch in
+ * dimension.  Batches run on their own streams (or on streams shared by a group of
+ * sizes, stream_groups), so batches of different sizes overlap on the device.  A worker thread owned by the server replays each busy batch in
  * chunks, reads every slot's stopping flag after a chunk, copies finished solutions out
  * and admits waiting requests into the freed slots between two replays: a request that
  * arrives while others run joins the next replay of its size's batch.
@@ -50,6 +50,10 @@ typedef struct {
   size_t hbm_budget;  /* device bytes the server may hold in batches */
   int max_slots;      /* most problems per batch (1..1024) */
   int chunk_steps;    /* solve steps per launch between two reads of the flags (1..64) */
+  int stream_groups;  /* 0: each batch on a stream of its own; 1..3: batches share that many
+                         streams by side (3: n <= 257, n <= 1025, larger; 2: n <= 1025,
+                         larger; 1: one stream), so that the replays of small problems never
+                         wait in a hardware queue behind those of large ones */
 } mg_server_config;
 
 typedef struct {

@@ -229,17 +229,25 @@ def jacobi_omega(dim, order=4):
             6: {2: 490.0 / 653.0, 3: 147.0 / 185.0}}[order][dim]
 
 
-def rbgs_omega(dim, order=4):
+def rbgs_omega(dim, order=4, coarse=COARSE_NG):
     """Default omega of red-black Gauss-Seidel (2D): the minimiser of the LFA two-grid factor
-    of the V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
-    return {(2, 4): 1.16, (2, 2): 1.0, (2, 6): 1.18}[(dim, order)]
+    of the V(2,1) cycle with cubic interpolation, to two decimals, per fine order and coarse
+    operator (rediscretized, or the second-order rediscretized one)."""
+    table = {(4, COARSE_NG): 1.16, (4, COARSE_NG2): 0.98, (6, COARSE_NG): 1.18, (6, COARSE_NG2): 1.0,
+             (2, COARSE_NG): 1.0, (2, COARSE_NG2): 1.0}
+    assert dim == 2
+    return table[(order, coarse)]
 
 
-def rbj_omega(dim, order=4):
+def rbj_omega(dim, order=4, coarse=COARSE_NG):
     """Default omega of red-black Jacobi: the minimiser of the LFA two-grid factor of the
-    V(2,1) cycle (cubic interpolation, rediscretized operator), to two decimals."""
-    return {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13, (2, 6): 1.13,
-            (3, 6): 1.15}[(dim, order)]
+    V(2,1) cycle with cubic interpolation, to two decimals, per (dim, fine order, coarse
+    operator)."""
+    table = {
+        (2, 4): (1.13, 1.0, 0.98, 0.97), (2, 6): (1.13, 1.02, 0.99, 0.99), (2, 2): (1.0, 0.98, 1.0, 0.98),
+        (3, 4): (1.17, 1.09, 1.09, 1.08), (3, 6): (1.15, 1.1, 1.09, 1.08), (3, 2): (1.13, 1.09, 1.13, 1.09),
+    }
+    return table[(dim, order)][coarse]
 
 
 class Multigrid:
@@ -249,8 +257,8 @@ class Multigrid:
                  prolong=PROLONG_CUBIC, nu1=2, nu2=1, gamma=1, n_coarsest=9, omega=None,
                  smoother=SMOOTH_JACOBI):
         if omega is None:
-            omega = {SMOOTH_JACOBI: jacobi_omega, SMOOTH_RBJ: rbj_omega,
-                     SMOOTH_RBGS: rbgs_omega}[smoother](dim, order)
+            omega = (jacobi_omega(dim, order) if smoother == SMOOTH_JACOBI else
+                     {SMOOTH_RBJ: rbj_omega, SMOOTH_RBGS: rbgs_omega}[smoother](dim, order, coarse))
         self.cfg = _Config(dim, n, order, coarse, restrict_op, prolong, nu1, nu2, gamma,
                            n_coarsest, float(omega), smoother)
         self.dim, self.n = dim, n

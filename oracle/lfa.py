@@ -100,9 +100,9 @@ class Scheme:
             if smoother == JACOBI:
                 omega = jacobi_optimum(dim, order)[0]
             elif smoother == RBJ:
-                omega = RBJ_OMEGA[(dim, order)]
+                omega = RBJ_OMEGA[(dim, order, coarse)]
             else:
-                omega = RBGS_OMEGA[(dim, order)]
+                omega = RBGS_OMEGA[(dim, order, coarse)]
         self.omega = omega
 
     def level_symbol(self, level, theta, h0=1.0):
@@ -218,23 +218,33 @@ class Scheme:
         S = self.smoother_on(modes, partner, 0, h0)
         return np.linalg.matrix_power(S, self.nu2) @ K @ np.linalg.matrix_power(S, self.nu1)
 
-# Default omega of the red-black Gauss-Seidel smoother (2D): the minimiser of the two-grid
-# factor of the V(2,1) cycle with cubic interpolation and the rediscretized operator, to two
-# decimals (rbgs_optimum recomputes it).  For the five-point operator it is red-black Jacobi.
-RBGS_OMEGA = {(2, 4): 1.16, (2, 2): 1.0, (2, 6): 1.18}
+# Default omega of the red-black Gauss-Seidel smoother (2D), per fine order and coarse
+# operator (rediscretized, or the second-order one of section 3.1): the minimiser of the
+# two-grid factor of the V(2,1) cycle with cubic interpolation, to two decimals
+# (rbgs_optimum recomputes it).  For the five-point operator it is red-black Jacobi.
+RBGS_OMEGA = {(2, 4, NG): 1.16, (2, 4, NG2): 0.98, (2, 6, NG): 1.18, (2, 6, NG2): 1.0,
+              (2, 2, NG): 1.0, (2, 2, NG2): 1.0}
 
-# Default omega of the red-black Jacobi smoother: the value minimising the two-grid factor
-# of the V(2,1) cycle with cubic interpolation and the rediscretized operator, rounded to two
-# decimals (rbj_optimum recomputes it).
-RBJ_OMEGA = {(2, 4): 1.13, (3, 4): 1.17, (2, 2): 1.0, (3, 2): 1.13, (2, 6): 1.13, (3, 6): 1.15}
+# Default omega of the red-black Jacobi smoother per (dim, fine order, coarse operator): the
+# value minimising the two-grid factor of the V(2,1) cycle with cubic interpolation, rounded
+# to two decimals (rbj_optimum recomputes it).  For the second-order fine operator the
+# second-order coarse operators are the rediscretized and Galerkin ones.
+RBJ_OMEGA = {
+    (2, 4, NG): 1.13, (2, 4, GALERKIN): 1.0, (2, 4, NG2): 0.98, (2, 4, G2): 0.97,
+    (2, 6, NG): 1.13, (2, 6, GALERKIN): 1.02, (2, 6, NG2): 0.99, (2, 6, G2): 0.99,
+    (2, 2, NG): 1.0, (2, 2, GALERKIN): 0.98, (2, 2, NG2): 1.0, (2, 2, G2): 0.98,
+    (3, 4, NG): 1.17, (3, 4, GALERKIN): 1.09, (3, 4, NG2): 1.09, (3, 4, G2): 1.08,
+    (3, 6, NG): 1.15, (3, 6, GALERKIN): 1.1, (3, 6, NG2): 1.09, (3, 6, G2): 1.08,
+    (3, 2, NG): 1.13, (3, 2, GALERKIN): 1.09, (3, 2, NG2): 1.13, (3, 2, G2): 1.09,
+}
 
 
-def rbj_optimum(dim, order=4, m=None):
-    """omega minimising two_grid_rho for red-black Jacobi, V(2,1), cubic, rediscretized."""
+def rbj_optimum(dim, order=4, m=None, coarse=NG):
+    """omega minimising two_grid_rho for red-black Jacobi, V(2,1), cubic interpolation."""
     from scipy.optimize import minimize_scalar
     m = m or (24 if dim == 2 else 10)
-    rho = lambda w: two_grid_rho(Scheme(dim, order, nu1=2, nu2=1, omega=w, smoother=RBJ), m)
-    r = minimize_scalar(rho, bounds=(0.9, 1.3), method="bounded", options={"xatol": 1e-4})
+    rho = lambda w: two_grid_rho(Scheme(dim, order, coarse=coarse, nu1=2, nu2=1, omega=w, smoother=RBJ), m)
+    r = minimize_scalar(rho, bounds=(0.8, 1.4), method="bounded", options={"xatol": 1e-4})
     return float(r.x), float(r.fun)
 
 
@@ -339,10 +349,10 @@ def finite_two_grid_spectrum(scheme, n):
     return np.array(eig)
 
 
-def rbgs_optimum(order=4, m=24):
-    """omega minimising two_grid_rho for red-black Gauss-Seidel (2D), V(2,1), cubic,
-    rediscretized."""
+def rbgs_optimum(order=4, m=24, coarse=NG):
+    """omega minimising two_grid_rho for red-black Gauss-Seidel (2D), V(2,1), cubic
+    interpolation."""
     from scipy.optimize import minimize_scalar
-    rho = lambda w: two_grid_rho(Scheme(2, order, nu1=2, nu2=1, omega=w, smoother=RBGS), m)
+    rho = lambda w: two_grid_rho(Scheme(2, order, coarse=coarse, nu1=2, nu2=1, omega=w, smoother=RBGS), m)
     r = minimize_scalar(rho, bounds=(0.8, 1.4), method="bounded", options={"xatol": 1e-4})
     return float(r.x), float(r.fun)

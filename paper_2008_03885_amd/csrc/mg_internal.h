@@ -186,6 +186,22 @@ template <typename T>
 hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
                                      const int *done, hipStream_t s);
 
+// ---- cubic-adjoint restriction (restrict.hip) --------------------------------------
+// fc = I_h^H r (appendix A.4, the 1/1024 operator) on the level (n-1)/2+1, r a fine defect
+// with zero boundary; every coarse point written (boundary zeros).  dim 2 or 3.
+template <typename T>
+hipError_t launch_restrict_cubic(int dim, const T *r, T *fc, int n, const int *done, hipStream_t s,
+                                 int slots = 1);
+
+// ---- red-black Gauss-Seidel partial step, 2D (gs2d.hip) --------------------------
+// The colour's points (1 red, 2 black) in lexicographic order from the current values
+// (section 3.1 eq. S_GS), every other point copied; cross operators of radius 2 or 3 only
+// (hipErrorInvalidValue otherwise).  uout != uin, both full n x n arrays (boundary zeros
+// written).
+template <typename T>
+hipError_t launch_gs2d(const LevelOp &op, double omega, int colour, const T *f, const T *uin, T *uout,
+                       int n, const int *done, hipStream_t s, int slots = 1);
+
 // ---- fused 2D cycle kernels (fused2d.hip) ----------------------------------------
 // Pre kernel modes (bit set): 1 write the smoothed iterate, 2 full-weight the defect,
 // 4 write the defect.  Supported: WriteU|Restrict with nu <= 3 (the pre half of a cycle),

@@ -276,13 +276,20 @@ mg_status validate(const mg_config *c, int *levels) {
   if (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_GALERKIN && c->coarse != MG_COARSE_NG2 &&
       c->coarse != MG_COARSE_G2)
     return fail(MG_EINVAL, "unknown coarse operator");
-  if (c->smoother != MG_SMOOTH_JACOBI && c->smoother != MG_SMOOTH_RBJ)
+  if (c->smoother != MG_SMOOTH_JACOBI && c->smoother != MG_SMOOTH_RBJ && c->smoother != MG_SMOOTH_RBGS)
     return fail(MG_EINVAL, "unknown smoother");
+  if (c->smoother == MG_SMOOTH_RBGS &&
+      (c->dim != 2 || (c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_NG2)))
+    return fail(MG_EINVAL, "red-black Gauss-Seidel needs dim 2 and rediscretized (cross-stencil) coarse operators");
   if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
     return fail(MG_EINVAL, "need 0 <= nu1, nu2 <= 16 and nu1 + nu2 >= 1");
   if (c->gamma != 1 && c->gamma != 2) return fail(MG_EINVAL, "gamma must be 1 (V) or 2 (W)");
   if (c->prolong != 1 && c->prolong != 3) return fail(MG_EINVAL, "prolong must be 1 or 3");
-  if (c->restrict_op != 1) return fail(MG_EINVAL, "restrict_op must be 1 (full weighting)");
+  if (c->restrict_op != 1 && c->restrict_op != 3)
+    return fail(MG_EINVAL, "restrict_op must be 1 (full weighting) or 3 (cubic adjoint)");
+  if (c->restrict_op == 3 && c->coarse != MG_COARSE_NG && c->coarse != MG_COARSE_NG2)
+    return fail(MG_EINVAL, "the cubic-adjoint restriction needs rediscretized coarse operators (its Galerkin "
+                           "products would have stencils wider than radius 3)");
   if (c->precision != MG_PREC_FP64 && c->precision != MG_PREC_MIXED)
     return fail(MG_EINVAL, "unknown precision");
   if (c->omega > 0.0 && c->omega >= 2.0) return fail(MG_EINVAL, "omega must be in (0, 2)");
@@ -300,15 +307,23 @@ mg_status validate(const mg_config *c, int *levels) {
   return MG_OK;
 }
 
-double default_omega(int dim, int order, int smoother) {
-  // Red-black Jacobi: the minimiser of the Fourier-analysis two-grid factor of the V(2,1)
-  // cycle (cubic interpolation, rediscretized operator), to two decimals.
-  if (smoother == MG_SMOOTH_RBJ) {
-    if (order == 6) return dim == 2 ? 1.13 : 1.15;
-    if (order == 4) return dim == 2 ? 1.13 : 1.17;
-    return dim == 2 ? 1.0 : 1.13;
+double default_omega(int dim, int order, int smoother, int coarse) {
+  // Red-black smoothers: the minimiser of the Fourier-analysis two-grid factor of the V(2,1)
+  // cycle with cubic interpolation, to two decimals, per fine order and coarse operator
+  // (section 3.1 tunes omega per coarse operator).  Coarse index: NG, GALERKIN, NG2, G2.
+  if (smoother == MG_SMOOTH_RBGS) {  // 2D, NG or NG2
+    if (order == 2) return 1.0;
+    const bool ng2 = coarse == MG_COARSE_NG2;
+    return order == 6 ? (ng2 ? 1.0 : 1.18) : (ng2 ? 0.98 : 1.16);
   }
-  // omega-Jacobi: equioscillation of the symbol over the high frequencies.
+  if (smoother == MG_SMOOTH_RBJ) {
+    static const double t2[3][4] = {{1.0, 0.98, 1.0, 0.98}, {1.13, 1.0, 0.98, 0.97}, {1.13, 1.02, 0.99, 0.99}};
+    static const double t3[3][4] = {{1.13, 1.09, 1.13, 1.09}, {1.17, 1.09, 1.09, 1.08}, {1.15, 1.1, 1.09, 1.08}};
+    const int oi = order == 2 ? 0 : (order == 4 ? 1 : 2);
+    return dim == 2 ? t2[oi][coarse] : t3[oi][coarse];
+  }
+  // omega-Jacobi: equioscillation of the symbol over the high frequencies (the two-grid
+  // factor is smoothing-limited and the same for every coarse operator).
   if (order == 6) return dim == 2 ? 490.0 / 653.0 : 147.0 / 185.0;
   if (order == 4) return dim == 2 ? 10.0 / 13.0 : 9.0 / 11.0;
   return dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0;
@@ -482,6 +497,38 @@ template <typename T>
 hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
                  bool check, hipStream_t s);
 
+// fc = I_h^H (f - L_l u) on level l+1.  Full weighting: one fused pass.  Cubic adjoint
+// (appendix A.4): the defect into scratch (a free level-l array), then the restriction.
+template <typename T>
+hipError_t resid_restrict(mg_ctx *c, int l, const T *f, const T *u, T *scratch, T *fc, const int *done,
+                          hipStream_t s) {
+  if (c->cfg.restrict_op != 3)
+    return mgk::launch_resid_restrict<T>(c->dim, c->ops[l], f, u, fc, c->ns[l], done, s, c->slots);
+  hipError_t e = mgk::launch_sweep<T, T>(c->dim, mgk::kResidual, c->ops[l], c->omega, f, u, scratch, c->ns[l],
+                                         nullptr, nullptr, done, s, c->slots);
+  if (e != hipSuccess) return e;
+  return mgk::launch_restrict_cubic<T>(c->dim, scratch, fc, c->ns[l], done, s, c->slots);
+}
+
+// Cross levels of radius 2 or 3 (where Gauss-Seidel partial steps differ from Jacobi ones).
+bool gs_level(const LevelOp &op) { return op.cross3 || (op.cross && op.a[1] != 0.0); }
+
+// One partial step of the red-black smoother on level l, colour 1 (red) or 2 (black):
+// Gauss-Seidel (section 3.1 eq. S_GS) on radius-2/3 cross levels with MG_SMOOTH_RBGS, else
+// the Jacobi partial step (for the five-point operator the two coincide).  partials: the
+// defect norm partials of u_in (Jacobi steps only), or null.
+template <typename T>
+hipError_t partial_step(mg_ctx *c, int l, int colour, const T *f, const T *uin, T *uout, double *partials,
+                        int *np, hipStream_t s) {
+  const LevelOp &op = c->ops[l];
+  if (c->cfg.smoother == MG_SMOOTH_RBGS && gs_level(op)) {
+    if (uin == nullptr || partials != nullptr) return hipErrorInvalidValue;
+    return mgk::launch_gs2d<T>(op, c->omega, colour, f, uin, uout, c->ns[l], &c->st->done, s, c->slots);
+  }
+  return mgk::launch_sweep<T, T>(c->dim, mgk::kSweep, op, c->omega, f, uin, uout, c->ns[l], partials, np,
+                                 &c->st->done, s, c->slots, colour);
+}
+
 // The fused 2D cycle on level l with red-black smoothing (rb_passes): every pass is one
 // pre or post kernel whose stages alternate red and black partial steps.
 template <typename T>
@@ -622,19 +669,37 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   }
   // a red-black sweep is two steps: the red points (colour 1), then the black ones (2);
   // on 3D cross levels one launch does both
-  const bool rb = c->cfg.smoother == MG_SMOOTH_RBJ;
-  const bool rb3 = rb && dim == 3 && op.cross && sizeof(T) == 8 && rb3_fused();
+  const bool rb = c->cfg.smoother == MG_SMOOTH_RBJ || c->cfg.smoother == MG_SMOOTH_RBGS;
+  const bool rb3 = c->cfg.smoother == MG_SMOOTH_RBJ && dim == 3 && op.cross && sizeof(T) == 8 && rb3_fused();
   const int steps = rb && !rb3 ? 2 : 1;
+  // Gauss-Seidel steps do not form the defect norm: the stopping check gets its own pass
+  const bool gs_check = check && c->cfg.smoother == MG_SMOOTH_RBGS && gs_level(op) && c->cfg.nu1 > 0;
+  if (gs_check) {
+    int np = 0;
+    e = mgk::launch_sweep<T, T>(dim, mgk::kNormOnly, op, c->omega, f, zero ? nullptr : u, (T *)nullptr, n,
+                                c->partials, &np, done, s, c->slots);
+    if (e != hipSuccess) return e;
+    e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
+    if (e != hipSuccess) return e;
+  }
+  if (zero && c->cfg.smoother == MG_SMOOTH_RBGS && gs_level(op) && c->cfg.nu1 > 0) {
+    // a Gauss-Seidel step reads the new values it has just written: start from stored zeros
+    e = mgk::launch_fill<T>(cur, points(dim, n), T(0), done, s, c->slots);
+    if (e != hipSuccess) return e;
+    zero = false;
+  }
   for (int k = 0; k < c->cfg.nu1 * steps; ++k) {
-    const bool first_check = check && k == 0;
+    const bool first_check = check && k == 0 && !gs_check;
     int np = 0;
     if (rb3)
       e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, zero ? nullptr : cur, other, n,
                                     first_check ? c->partials : nullptr, &np, done, s);
+    else if (rb)
+      e = partial_step<T>(c, l, 1 + k % 2, f, zero ? nullptr : cur, other, first_check ? c->partials : nullptr,
+                          &np, s);
     else
       e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, zero ? nullptr : cur, other, n,
-                                  first_check ? c->partials : nullptr, &np, done, s, c->slots,
-                                  rb ? 1 + k % 2 : 0);
+                                  first_check ? c->partials : nullptr, &np, done, s, c->slots, 0);
     if (e != hipSuccess) return e;
     if (first_check) {
       e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
@@ -645,7 +710,7 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   }
   T *uc = (T *)B[l + 1].u;
   T *fc = (T *)B[l + 1].f;
-  e = mgk::launch_resid_restrict<T>(dim, op, f, cur, fc, n, done, s, c->slots);
+  e = resid_restrict<T>(c, l, f, cur, other, fc, done, s);
   if (e != hipSuccess) return e;
   if (l + 1 == c->L - 1 && l + 1 < c->tail_top) {
     e = mgk::launch_coarsest<T>(dim, c->ainv_t, fc, uc, c->ns[l + 1], done, s, c->slots);
@@ -668,9 +733,11 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
   for (int k = 0; k < c->cfg.nu2 * steps; ++k) {
     if (rb3)
       e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
+    else if (rb)
+      e = partial_step<T>(c, l, 1 + k % 2, f, cur, other, nullptr, nullptr, s);
     else
       e = mgk::launch_sweep<T, T>(dim, mgk::kSweep, op, c->omega, f, cur, other, n, nullptr, nullptr,
-                                  done, s, c->slots, rb ? 1 + k % 2 : 0);
+                                  done, s, c->slots, 0);
     if (e != hipSuccess) return e;
     std::swap(cur, other);
   }
@@ -900,12 +967,15 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
   c->own_top = own_top;
   c->dim = cfg->dim;
   c->L = L;
-  c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order, cfg->smoother);
+  c->omega = cfg->omega > 0.0 ? cfg->omega : default_omega(cfg->dim, cfg->order, cfg->smoother, cfg->coarse);
   c->stream = (hipStream_t)hip_stream;
   if (const char *g = std::getenv("MG_GRAPH")) c->use_graph = std::atoi(g) != 0;
   if (const char *k = std::getenv("MG_CHUNK")) c->chunk = std::max(1, std::atoi(k));
   if (const char *fz = std::getenv("MG_FUSED")) c->fused = std::atoi(fz) != 0;
   if (cfg->smoother == MG_SMOOTH_JACOBI && (cfg->nu1 > 3 || cfg->nu2 > 2)) c->fused = false;
+  // Gauss-Seidel partial steps and the cubic-adjoint restriction run as their own kernels on
+  // every level (no fused passes, no LDS-resident tail)
+  if (cfg->smoother == MG_SMOOTH_RBGS || cfg->restrict_op == 3) c->fused = false;
   auto bail = [&](mg_status s) {
     std::string msg = g_error;
     mg_destroy(c);
@@ -1001,6 +1071,7 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
     // solve runs there; in 2D the tail takes the levels up to 33^2.
     int cap = c->dim == 2 ? 33 : 9;
     if (const char *tn = std::getenv("MG_TAIL_N")) cap = std::atoi(tn);
+    if (cfg->smoother == MG_SMOOTH_RBGS || cfg->restrict_op == 3) cap = 0;
     const size_t es = mixed ? sizeof(float) : sizeof(double);
     c->tail_top = L;
     for (int l = L - 1; l >= 0 && L - l <= mgk::kMaxTailLevels; --l) {
@@ -1175,6 +1246,17 @@ mg_status mg_kernel_smooth_colour(mg_handle h, int level, int fp32, int colour, 
   if (st != MG_OK) return st;
   if (!f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
   if (colour < 0 || colour > 3) return fail(MG_EINVAL, "colour must be 0, 1, 2 or 3");
+  if (h->cfg.smoother == MG_SMOOTH_RBGS && gs_level(h->ops[level])) {  // section 3.1 eq. S_GS
+    if (colour != 1 && colour != 2) return fail(MG_EINVAL, "Gauss-Seidel partial steps take colour 1 or 2");
+    if (!u_in) return fail(MG_EINVAL, "Gauss-Seidel partial steps need u_in");
+    if (fp32)
+      MG_HIP(mgk::launch_gs2d<float>(h->ops[level], h->omega, colour, (const float *)f, (const float *)u_in,
+                                     (float *)u_out, h->ns[level], nullptr, h->stream));
+    else
+      MG_HIP(mgk::launch_gs2d<double>(h->ops[level], h->omega, colour, (const double *)f, (const double *)u_in,
+                                      (double *)u_out, h->ns[level], nullptr, h->stream));
+    return MG_OK;
+  }
   if (colour == 3) {  // a whole red-black sweep in one pass
     const LevelOp &op = h->ops[level];
     const int n = h->ns[level];
@@ -1243,6 +1325,19 @@ mg_status mg_kernel_residual_restrict(mg_handle h, int level, int fp32, const vo
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
   if (!f || !fc) return fail(MG_EINVAL, "bad buffers");
+  if (h->cfg.restrict_op == 3) {  // the defect goes through the level's sweep target
+    if (!u) return fail(MG_EINVAL, "the cubic-adjoint restriction needs u");
+    const bool mixed = h->cfg.precision == MG_PREC_MIXED;
+    if (mixed && !fp32) return fail(MG_EINVAL, "a mixed-precision handle holds FP32 level arrays only");
+    void *scratch = mixed ? h->b32[level].t : h->b64[level].t;
+    if (fp32)
+      MG_HIP(resid_restrict<float>(h, level, (const float *)f, (const float *)u, (float *)scratch, (float *)fc,
+                                   nullptr, h->stream));
+    else
+      MG_HIP(resid_restrict<double>(h, level, (const double *)f, (const double *)u, (double *)scratch,
+                                    (double *)fc, nullptr, h->stream));
+    return MG_OK;
+  }
   if (h->dim == 2) {
     if (fp32)
       MG_HIP(mgk::launch_pre2d<float>(h->ops[level], h->omega, 0, mgk::kPreRestrict, (const float *)f,
@@ -1298,6 +1393,8 @@ mg_status mg_kernel_presmooth_restrict(mg_handle h, int level, int fp32, const v
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
   const bool rb = h->cfg.smoother == MG_SMOOTH_RBJ;
+  if (h->cfg.smoother == MG_SMOOTH_RBGS) return fail(MG_EINVAL, "no fused pass for Gauss-Seidel smoothing");
+  if (h->cfg.restrict_op == 3) return fail(MG_EINVAL, "no fused pass for the cubic-adjoint restriction");
   if (h->dim != 2 || (!rb && h->cfg.nu1 > 3))
     return fail(MG_EINVAL, "fused pre-smoothing needs dim 2, nu1 <= 3");
   if (!f || !u_out || !fc || u_in == u_out) return fail(MG_EINVAL, "bad buffers");
@@ -1319,6 +1416,7 @@ mg_status mg_kernel_prolong_postsmooth(mg_handle h, int level, int fp32, const v
   mg_status st = check_level<double>(h, level, true);
   if (st != MG_OK) return st;
   const bool rb = h->cfg.smoother == MG_SMOOTH_RBJ;
+  if (h->cfg.smoother == MG_SMOOTH_RBGS) return fail(MG_EINVAL, "no fused pass for Gauss-Seidel smoothing");
   if (h->dim != 2 || (!rb && h->cfg.nu2 > 2))
     return fail(MG_EINVAL, "fused post-smoothing needs dim 2, nu2 <= 2");
   if (!v || !u_in || !f || !u_out || u_in == u_out) return fail(MG_EINVAL, "bad buffers");

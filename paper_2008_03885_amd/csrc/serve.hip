@@ -47,6 +47,7 @@ struct Batch {
   int n = 0, slots = 0;
   mg_ctx *ctx = nullptr;
   hipStream_t stream = nullptr;
+  bool own_stream = true;             // false: a group stream of the server
   size_t bytes = 0;
   std::vector<int> state;             // SlotState per slot
   std::vector<Req> req;               // occupant per slot
@@ -94,6 +95,7 @@ struct mg_server_s {
   // worker-owned
   std::deque<Req> pending;
   std::map<int, std::unique_ptr<Batch>> batches;
+  hipStream_t group_stream[3] = {nullptr, nullptr, nullptr};  // stream_groups > 0
 };
 
 namespace {
@@ -113,7 +115,7 @@ void free_batch(Batch *b) {
   for (auto &p : b->flags)
     if (p) (void)hipHostFree(p);
   if (b->states) (void)hipHostFree(b->states);
-  if (b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->stream && b->own_stream) (void)hipStreamDestroy(b->stream);
   b->ctx = nullptr;
 }
 
@@ -187,7 +189,17 @@ Batch *Worker::create_batch(int n, bool *ok) {
   b->n = n;
   b->slots = slots;
   b->bytes = mgb::footprint(&cfg, slots);
-  if (!hip_ok(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate")) {
+  const int groups = s_->cfg.stream_groups;
+  if (groups > 0) {  // a stream shared by the sizes of one group, created on first use
+    const int g = groups == 1 ? 0 : (groups == 2 ? (n <= 1025 ? 0 : 1) : (n <= 257 ? 0 : (n <= 1025 ? 1 : 2)));
+    if (!s_->group_stream[g] &&
+        !hip_ok(hipStreamCreateWithFlags(&s_->group_stream[g], hipStreamNonBlocking), "hipStreamCreate")) {
+      *ok = false;
+      return nullptr;
+    }
+    b->stream = s_->group_stream[g];
+    b->own_stream = false;
+  } else if (!hip_ok(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate")) {
     *ok = false;
     return nullptr;
   }
@@ -375,7 +387,8 @@ mg_status mg_server_create(const mg_server_config *cfg, mg_server *out) {
   if (!out) return MG_EINVAL;
   *out = nullptr;
   if (!cfg || cfg->base.dim != 2 || cfg->max_slots < 1 || cfg->max_slots > 1024 ||
-      cfg->chunk_steps < 1 || cfg->chunk_steps > 64 || cfg->hbm_budget == 0)
+      cfg->chunk_steps < 1 || cfg->chunk_steps > 64 || cfg->hbm_budget == 0 || cfg->stream_groups < 0 ||
+      cfg->stream_groups > 3)
     return MG_EINVAL;
   // the base configuration must be valid at its own size
   if (mgb::footprint(&cfg->base, 1) == 0) return MG_EINVAL;
@@ -448,6 +461,8 @@ mg_status mg_server_destroy(mg_server s) {
   (void)hipSetDevice(s->device);
   for (auto &kv : s->batches) free_batch(kv.second.get());
   s->batches.clear();
+  for (auto &st : s->group_stream)
+    if (st) (void)hipStreamDestroy(st);
   delete s;
   return MG_OK;
 }

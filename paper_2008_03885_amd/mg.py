@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libmgmi.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOCONV, MG_ENUMERIC, MG_EBUSY = range(7)
 MG_COARSE_NG, MG_COARSE_GALERKIN, MG_COARSE_NG2, MG_COARSE_G2 = 0, 1, 2, 3
-MG_SMOOTH_JACOBI, MG_SMOOTH_RBJ = 0, 1
+MG_SMOOTH_JACOBI, MG_SMOOTH_RBJ, MG_SMOOTH_RBGS = 0, 1, 2
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_MAX_HISTORY = 512
 STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EDEVICE", 4: "MG_ENOCONV",

@@ -12,7 +12,8 @@ _LL, _I, _D, _V, _SZ = ctypes.c_longlong, ctypes.c_int, ctypes.c_double, ctypes.
 
 
 class mg_server_config(ctypes.Structure):
-    _fields_ = [("base", mg.mg_config), ("hbm_budget", _SZ), ("max_slots", _I), ("chunk_steps", _I)]
+    _fields_ = [("base", mg.mg_config), ("hbm_budget", _SZ), ("max_slots", _I), ("chunk_steps", _I),
+                ("stream_groups", _I)]
 
 
 class mg_completion(ctypes.Structure):
@@ -62,11 +63,11 @@ def mg_server_clock():
     return lib().mg_server_clock()
 
 
-def make_server_config(hbm_budget, max_slots=16, chunk_steps=2, **base_kwargs):
+def make_server_config(hbm_budget, max_slots=16, chunk_steps=2, stream_groups=0, **base_kwargs):
     base_kwargs.setdefault("dim", 2)
     base_kwargs.setdefault("n", 65)
     return mg_server_config(base=mg.make_config(**base_kwargs), hbm_budget=int(hbm_budget),
-                            max_slots=max_slots, chunk_steps=chunk_steps)
+                            max_slots=max_slots, chunk_steps=chunk_steps, stream_groups=stream_groups)
 
 
 def mg_server_create(cfg):
@@ -103,10 +104,10 @@ class Server:
     """A server on the current device.  submit(tag, f, u) takes float64 CUDA tensors of
     shape (n, n) and holds them until the request completes; poll() returns completions."""
 
-    def __init__(self, hbm_budget, max_slots=16, chunk_steps=2, **base_kwargs):
+    def __init__(self, hbm_budget, max_slots=16, chunk_steps=2, stream_groups=0, **base_kwargs):
         import torch
         torch.cuda.init()  # torch owns the device set-up; the server runs on its current device
-        self.cfg = make_server_config(hbm_budget, max_slots, chunk_steps, **base_kwargs)
+        self.cfg = make_server_config(hbm_budget, max_slots, chunk_steps, stream_groups, **base_kwargs)
         self.h = mg_server_create(self.cfg)
         self._live = {}
 

@@ -39,23 +39,25 @@ class Handle:
 
     def __init__(self, dim, n, coarse=0, prolong=3, n_coarsest=9, nu1=2, nu2=1, gamma=1,
                  precision=0, rtol=1e-10, max_cycles=100, inner_cycles=4, order=4, omega=0.0,
-                 smoother=0):
+                 smoother=0, restrict_op=1):
         self.cfg = mg.make_config(dim=dim, n=n, coarse=coarse, prolong=prolong,
                                   n_coarsest=n_coarsest, nu1=nu1, nu2=nu2, gamma=gamma,
                                   precision=precision, rtol=rtol, max_cycles=max_cycles,
                                   inner_cycles=inner_cycles, order=order, omega=omega,
-                                  smoother=smoother)
+                                  smoother=smoother, restrict_op=restrict_op)
         self.h = mg.mg_setup(self.cfg, stream())
         self.dim, self.n = dim, n
         if omega > 0:
             self.omega = omega
         elif smoother == oracle.SMOOTH_RBJ:
-            self.omega = oracle.rbj_omega(dim, order)
+            self.omega = oracle.rbj_omega(dim, order, coarse)
+        elif smoother == oracle.SMOOTH_RBGS:
+            self.omega = oracle.rbgs_omega(dim, order, coarse)
         else:
             self.omega = oracle.jacobi_omega(dim, order)
         self.oracle = oracle.Multigrid(dim, n, order=order, coarse=coarse, prolong=prolong,
                                        nu1=nu1, nu2=nu2, gamma=gamma, n_coarsest=n_coarsest,
-                                       omega=self.omega, smoother=smoother)
+                                       omega=self.omega, smoother=smoother, restrict_op=restrict_op)
 
     def level(self, l):
         n_l, s = self.oracle.level_stencil(l)

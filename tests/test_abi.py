@@ -39,8 +39,12 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("kwargs", [
-    dict(dim=4), dict(order=8), dict(order=3), dict(n=100), dict(smoother=2), dict(n=129, n_coarsest=7), dict(gamma=3),
-    dict(prolong=2), dict(restrict_op=3), dict(nu1=0, nu2=0), dict(omega=2.5),
+    dict(dim=4), dict(order=8), dict(order=3), dict(n=100), dict(smoother=3), dict(n=129, n_coarsest=7), dict(gamma=3),
+    # red-black Gauss-Seidel: 2D with cross-stencil (rediscretized) coarse operators only
+    dict(smoother=2, dim=3), dict(smoother=2, coarse=1), dict(smoother=2, coarse=3),
+    dict(prolong=2), dict(restrict_op=2), dict(nu1=0, nu2=0), dict(omega=2.5),
+    # the cubic-adjoint restriction: rediscretized coarse operators only
+    dict(restrict_op=3, coarse=1), dict(restrict_op=3, coarse=3),
     dict(max_cycles=0), dict(precision=1, inner_cycles=0), dict(coarse=5),
 ])
 def test_invalid_configs_rejected(kwargs):

@@ -448,7 +448,7 @@ def test_3d_galerkin_sweep_kernels(n, level, old, fp32, monkeypatch):
 # Galerkin kernels).  Level sides cover single blocks, ragged blocks and 3D plane bands.
 CASES_RB = [
     (2, 17, 0, 0, "0"), (2, 257, 0, 0, "0"), (2, 1025, 0, 1, "0"), (2, 257, 1, 1, "0"),
-    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"), (2, 1025, 0, 0, "0"),
+    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"), (2, 1025, 0, 0, "0"), (2, 257, 2, 1, "0"),
     (3, 17, 0, 0, "0"), (3, 65, 0, 0, "0"), (3, 129, 0, 0, "0"), (3, 65, 1, 1, "0"),
     (3, 129, 1, 1, "0"), (3, 65, 1, 1, "1"), (3, 65, 3, 2, "0"), (3, 33, 2, 1, "0"),
     (3, 9, 0, 0, "0"), (3, 257, 2, 1, "0"),
@@ -551,5 +551,95 @@ def test_full_size_sweep_513_3d():
         mg.mg_kernel_residual_restrict(H.h, 0, 0, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
         ref = oracle.restrict(oracle.residual(s, f, u))
         assert_close(host(fc), ref, TOL64 * 4 * (np.abs(f).max() + s[2, 2, 2] * np.abs(u).max()), "rr")
+    finally:
+        H.close()
+
+
+GS_CASES = [
+    # finest n, order, coarse, level: fourth- and sixth-order cross levels, one strip, several
+    # strips and bands, a ragged last strip, and a five-point level (Jacobi partial step)
+    (9, 4, 0, 0), (33, 4, 0, 0), (257, 4, 0, 0), (1025, 4, 0, 0), (1025, 4, 0, 1), (4097, 4, 0, 0),
+    (129, 6, 0, 0), (2049, 6, 0, 0), (257, 4, 2, 1),
+]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("n,order,coarse,level", GS_CASES)
+def test_gauss_seidel_partial_steps(n, order, coarse, level, fp32):
+    """Red-black Gauss-Seidel partial steps (section 3.1 eq. S_GS) against the oracle's
+    lexicographic sweep of the colour; the other colour and the boundary are copied bit
+    for bit."""
+    print("gs partial step n=%d order=%d coarse=%d level=%d fp32=%d" % (n, order, coarse, level, fp32),
+          flush=True)
+    H = Handle(2, n, coarse=coarse, order=order, smoother=mg.MG_SMOOTH_RBGS)
+    try:
+        n_l, s = H.level(level)
+        u = rand_grid(n_l, 2, 61)
+        f = rand_grid(n_l, 2, 62) * s[(s.shape[0] // 2,) * 2]
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        idx = np.indices(u.shape).sum(axis=0)
+        tol = (TOL32 if fp32 else TOL64) * _scale_u(u, f, s) * 2
+        red = None
+        for colour in (1, 2):
+            src = ud if colour == 1 else dev(red, fp32)
+            base = u if colour == 1 else red
+            out = dev(np.full_like(u, np.nan), fp32)
+            mg.mg_kernel_smooth_colour(H.h, level, fp32, colour, fd.data_ptr(), src.data_ptr(), out.data_ptr())
+            got = host(out)
+            ref = oracle.gs_colour(s, H.omega, colour, f, base)
+            if not np.abs(got - ref).max() <= tol:  # name the omega and colour the result matches
+                for w in (H.omega, 0.98, 1.0, 1.16, 10.0 / 13.0):
+                    for c in (1, 2):
+                        print("diag omega %.4f colour %d: gs %.3e jacobi %.3e" % (
+                            w, c, np.abs(got - oracle.gs_colour(s, w, c, f, base)).max(),
+                            np.abs(got - oracle.jacobi_colour(s, w, c, f, base)).max()), flush=True)
+                bad = np.argwhere(np.abs(got - ref) > tol)
+                print("diag first bad points", bad[:8].tolist(), len(bad), flush=True)
+            assert_close(got, ref, tol, "colour %d" % colour)
+            keep = (idx % 2) != (colour % 2)
+            assert np.array_equal(got[keep], base[keep])
+            red = got
+    finally:
+        H.close()
+
+
+def test_gauss_seidel_entry_rejects_other_colours():
+    H = Handle(2, 65, smoother=mg.MG_SMOOTH_RBGS)
+    try:
+        a = dev(np.zeros((65, 65)))
+        b = dev(np.zeros((65, 65)))
+        for colour in (0, 3):
+            with pytest.raises(mg.MGError):
+                mg.mg_kernel_smooth_colour(H.h, 0, 0, colour, a.data_ptr(), a.data_ptr(), b.data_ptr())
+        with pytest.raises(mg.MGError):
+            mg.mg_kernel_presmooth_restrict(H.h, 0, 0, a.data_ptr(), a.data_ptr(), b.data_ptr(), b.data_ptr())
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dim,n,coarse,level", [(2, 17, 0, 0), (2, 65, 0, 0), (2, 1025, 0, 1), (2, 257, 2, 1),
+                                                (3, 17, 0, 0), (3, 65, 0, 0), (3, 129, 2, 1)])
+def test_cubic_restriction(dim, n, coarse, level, fp32):
+    """Defect + cubic-adjoint restriction (appendix A.4, the 1/1024 operator) against the
+    oracle's defect and restriction."""
+    print("cubic restriction dim=%d n=%d level=%d fp32=%d" % (dim, n, level, fp32), flush=True)
+    H = Handle(dim, n, coarse=coarse, restrict_op=3, precision=fp32)
+    try:
+        n_l, s = H.level(level)
+        nc = (n_l - 1) // 2 + 1
+        d = s[(s.shape[0] // 2,) * dim]
+        u = rand_grid(n_l, dim, 71)
+        f = rand_grid(n_l, dim, 72) * d
+        if fp32:
+            u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, fp32), dev(f, fp32)
+        fc = dev(np.full((nc,) * dim, np.nan), fp32)
+        mg.mg_kernel_residual_restrict(H.h, level, fp32, fd.data_ptr(), ud.data_ptr(), fc.data_ptr())
+        ref = oracle.restrict(oracle.residual(s, f, u), oracle.RESTRICT_CUBIC)
+        scale = np.abs(f).max() + d * np.abs(u).max()
+        assert_close(host(fc), ref, (TOL32 if fp32 else TOL64) * scale * 16, "defect + cubic restriction")
     finally:
         H.close()

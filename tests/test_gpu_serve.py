@@ -51,11 +51,11 @@ def _solo(n, f, **over):
         mg.mg_destroy(h)
 
 
-def _serve(reqs, budget=8 << 30, max_slots=8, chunk_steps=2, stagger=None, **over):
+def _serve(reqs, budget=8 << 30, max_slots=8, chunk_steps=2, stagger=None, stream_groups=0, **over):
     """Runs (tag, n, f) requests through one server; returns {tag: (u, completion)}."""
     import time
     cfg = dict(BASE, **over)
-    S = serve.Server(budget, max_slots, chunk_steps, n=65, **cfg)
+    S = serve.Server(budget, max_slots, chunk_steps, stream_groups, n=65, **cfg)
     try:
         bufs = {tag: (dev(f), dev(np.full_like(f, np.nan))) for tag, n, f in reqs}
         torch().cuda.synchronize()  # the server reads f on its own streams
@@ -87,10 +87,12 @@ def test_single_request_equals_standalone_solve(precision):
     _check_exact(u, f, "single")
 
 
-def test_results_identical_alone_and_in_the_mix():
+@pytest.mark.parametrize("stream_groups", [0, 3])
+def test_results_identical_alone_and_in_the_mix(stream_groups):
     """A stream of mixed sizes arriving while others run; the probe request (same n and
     f) appears three times at different points of the stream.  Every request equals its
-    standalone solve bit for bit and reaches 1e-10."""
+    standalone solve bit for bit and reaches 1e-10, with batches on streams of their own
+    or sharing streams by size group."""
     rng = np.random.default_rng(5)
     sizes = [65, 129, 257, 513, 1025]
     probe_n, probe_f = 257, _rhs(257, inputs.SEED_BASE + 1001)
@@ -102,7 +104,7 @@ def test_results_identical_alone_and_in_the_mix():
             n = int(rng.choice(sizes))
             reqs.append((i, n, _rhs(n, inputs.SEED_BASE + 1100 + i)))
     stagger = list(rng.exponential(0.002, len(reqs)))
-    out, stats = _serve(reqs, stagger=stagger)
+    out, stats = _serve(reqs, stagger=stagger, stream_groups=stream_groups)
     assert stats["completed"] == len(reqs)
     assert stats["peak_active"] > 1          # requests overlapped on the device
     solo = {}

@@ -96,6 +96,76 @@ def test_red_black_cycles_match_oracle(dim, n, coarse, prolong, nu1, nu2, gamma)
         H.close()
 
 
+CUBIC_R_CYCLES = [
+    # dim, n, coarse, nu1, nu2, gamma, smoother: the cubic-adjoint restriction (appendix A.4)
+    (2, 129, 0, 2, 1, 1, 0), (2, 257, 2, 2, 1, 2, 0), (2, 1025, 0, 2, 1, 1, 1), (2, 257, 0, 2, 1, 1, 2),
+    (3, 33, 0, 2, 1, 1, 0), (3, 65, 0, 2, 2, 2, 0), (3, 65, 2, 2, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dim,n,coarse,nu1,nu2,gamma,smoother", CUBIC_R_CYCLES)
+def test_cubic_restriction_cycles_match_oracle(dim, n, coarse, nu1, nu2, gamma, smoother):
+    """Cycles with cubic interpolation and its adjoint restriction against the oracle's."""
+    print("cubic restriction cycles dim=%d n=%d" % (dim, n), flush=True)
+    H = Handle(dim, n, coarse=coarse, nu1=nu1, nu2=nu2, gamma=gamma, smoother=smoother, restrict_op=3)
+    try:
+        f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
+        u, res, u_ref, hist = _fixed_cycles(H, f, 5)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+GS_CYCLES = [
+    # n, order, coarse, prolong, nu1, nu2, gamma: red-black Gauss-Seidel (section 3.1 eq. S_GS)
+    (129, 4, 0, 3, 2, 1, 1), (257, 4, 0, 3, 1, 1, 2), (257, 4, 2, 3, 2, 1, 1), (65, 4, 0, 1, 0, 2, 1),
+    (1025, 4, 0, 3, 2, 1, 1), (257, 6, 0, 3, 2, 1, 1), (129, 6, 2, 1, 2, 2, 2), (4097, 4, 0, 3, 2, 1, 1),
+]
+
+
+@pytest.mark.parametrize("n,order,coarse,prolong,nu1,nu2,gamma", GS_CYCLES)
+def test_gauss_seidel_cycles_match_oracle(n, order, coarse, prolong, nu1, nu2, gamma):
+    """Cycles with red-black Gauss-Seidel smoothing on every level against the oracle's."""
+    print("gs cycles n=%d order=%d coarse=%d" % (n, order, coarse), flush=True)
+    H = Handle(2, n, coarse=coarse, prolong=prolong, nu1=nu1, nu2=nu2, gamma=gamma, order=order,
+               smoother=mg.MG_SMOOTH_RBGS)
+    try:
+        f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2) if n == 4097 else inputs.manufactured_2d(n)[1]
+        cycles = 2 if n == 4097 else 5
+        u, res, u_ref, hist = _fixed_cycles(H, f, cycles)
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-12, err
+        gh = np.array(res.hist())
+        assert np.all(np.abs(gh - hist) <= 1e-9 * hist + 5e-14)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gauss_seidel_solve_to_tolerance(precision):
+    """A 1025^2 solve with red-black Gauss-Seidel (FP64, and FP32 cycles in FP64 refinement)
+    reaches 1e-10 and lies within the bound 1e-10 ||f||_h / lambda_min of the exact discrete
+    solution; the rate per cycle is near the LFA two-grid factor (0.017 at omega 1.16)."""
+    n = 1025
+    f = inputs.fourier_rhs(n, 2, 64, seed=inputs.SEED_BASE + 2)
+    H = Handle(2, n, smoother=mg.MG_SMOOTH_RBGS, precision=precision, rtol=1e-10, max_cycles=30,
+               inner_cycles=3)
+    try:
+        fd, ud = dev(f), dev(np.zeros_like(f))
+        st, res = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+        assert st == mg.MG_OK and res.rel_residual <= 1e-10
+        if precision == 0:
+            assert res.cycles <= 8
+        exact = dst.solve(f)
+        bound = 1e-10 * oracle.norm(f) / dst.min_eigenvalue(n, 2)
+        assert oracle.norm(host(ud) - exact) <= 1.01 * bound
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("fused", ["0", "1"])
 @pytest.mark.parametrize("nu1,nu2,gamma", [(2, 1, 1), (2, 1, 2), (1, 1, 1), (3, 2, 1), (0, 1, 1),
                                            (1, 0, 2), (2, 2, 2)])

@@ -401,14 +401,16 @@ def test_rb_partial_steps_equal_gauss_seidel_five_point():
     np.testing.assert_array_equal(oracle.jacobi_colour(s, 0.9, 0, f, u), oracle.jacobi(s, 0.9, f, u))
 
 
-@pytest.mark.parametrize("dim,order", [(2, 4), (3, 4), (2, 6), (3, 6)])
-def test_rbj_default_omega_is_lfa_optimum(dim, order):
-    """The default red-black omega minimises the LFA two-grid factor of V(2,1) (the
-    reading that omega is chosen for rho rather than mu, section 2.2 after eq. mu)."""
-    w, rho = lfa.rbj_optimum(dim, order)
-    assert abs(w - oracle.rbj_omega(dim, order)) < 0.01
-    assert abs(lfa.RBJ_OMEGA[(dim, order)] - oracle.rbj_omega(dim, order)) == 0
-    jac = lfa.two_grid_rho(lfa.Scheme(dim, order=order), m=12 if dim == 3 else 24)
+@pytest.mark.parametrize("dim,order,coarse", [(d, o, c) for d in (2, 3) for o in (4, 6) for c in range(4)]
+                         + [(2, 2, 0), (2, 2, 1), (3, 2, 0), (3, 2, 1)])
+def test_rbj_default_omega_is_lfa_optimum(dim, order, coarse):
+    """The default red-black omega minimises the LFA two-grid factor of V(2,1) for each coarse
+    operator (the reading that omega is chosen for rho rather than mu, section 2.2 after
+    eq. mu; section 3.1 re-tunes omega per coarse operator)."""
+    w, rho = lfa.rbj_optimum(dim, order, coarse=coarse)
+    assert abs(w - oracle.rbj_omega(dim, order, coarse)) < 0.01
+    assert lfa.RBJ_OMEGA[(dim, order, coarse)] == oracle.rbj_omega(dim, order, coarse)
+    jac = lfa.two_grid_rho(lfa.Scheme(dim, order=order, coarse=coarse), m=12 if dim == 3 else 24)
     assert rho < 0.2 * jac  # red-black Jacobi beats omega-Jacobi per sweep by far here
 
 
@@ -516,12 +518,12 @@ def test_rbgs_two_level_rate_near_lfa(n, nc, w):
     assert 0.85 * rho <= cr <= 1.15 * rho, (cr, rho)
 
 
-@pytest.mark.parametrize("order", [4, 6])
-def test_rbgs_default_omega_is_lfa_optimum(order):
-    w, rho = lfa.rbgs_optimum(order)
-    assert abs(w - oracle.rbgs_omega(2, order)) < 0.01
-    assert lfa.RBGS_OMEGA[(2, order)] == oracle.rbgs_omega(2, order)
-    assert rho < 0.2 * lfa.two_grid_rho(lfa.Scheme(2, order=order), m=24)
+@pytest.mark.parametrize("order,coarse", [(4, 0), (4, 2), (6, 0), (6, 2)])
+def test_rbgs_default_omega_is_lfa_optimum(order, coarse):
+    w, rho = lfa.rbgs_optimum(order, coarse=coarse)
+    assert abs(w - oracle.rbgs_omega(2, order, coarse)) < 0.01
+    assert lfa.RBGS_OMEGA[(2, order, coarse)] == oracle.rbgs_omega(2, order, coarse)
+    assert rho < 0.2 * lfa.two_grid_rho(lfa.Scheme(2, order=order, coarse=coarse), m=24)
 
 
 # ----------------------------------------------------------------- brute-force RAP --
