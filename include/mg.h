@@ -169,6 +169,25 @@ mg_status mg_query(mg_handle h, mg_result *res);
 /* rel = ||f - L u||_h / ||f||_h in FP64 on the device (difference form). */
 mg_status mg_residual_norm(mg_handle h, const double *f, const double *u, double *rel);
 
+/* ---- for callers that cannot allocate device memory ----
+ * Code under HIP graph capture, tight serving loops and harnesses that forbid hipMalloc.
+ * The library's static scratch (a solve state and per-block partial sums) has this many
+ * bytes, one copy per device, held from the library's load to the end of the process. */
+#define MG_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* mg_residual_norm without a handle and without allocating: *rel = ||f - L_h u||_h /
+ * ||f||_h (||f - L_h u||_h when f = 0), L_h the order-`order` operator at spacing
+ * 1/(n-1), on the current device, ordered on hip_stream (a hipStream_t, NULL = default
+ * stream), not waited for.  f, u: device FP64 arrays of n^dim values; rel: device pointer
+ * to one double, written when the stream reaches it.  The same kernels and summation
+ * order as mg_residual_norm, so the same value bit for bit.  Limits: n = 2^k + 1, k >= 3,
+ * and the partial sums of the norm passes must fit the scratch: n <= 16385 in 2D,
+ * n <= 1025 in 3D; beyond them MG_EINVAL, before any device work.  Calls on one device
+ * share its scratch, which keeps the last call's contents: calls that overlap on a
+ * device (other streams or threads) race; calls ordered on one stream do not. */
+mg_status mg_residual_norm_noalloc(int dim, int n, int order, const double *f, const double *u,
+                                   double *rel, void *hip_stream);
+
 /* Releases every buffer of the handle (waits for its stream first). */
 mg_status mg_destroy(mg_handle h);
 

@@ -60,6 +60,7 @@ _SIGS = {
     "mg_solve_async": (_I, [_V, _V, _V]),
     "mg_query": (_I, [_V, ctypes.POINTER(mg_result)]),
     "mg_residual_norm": (_I, [_V, _V, _V, ctypes.POINTER(ctypes.c_double)]),
+    "mg_residual_norm_noalloc": (_I, [_I, _I, _I, _V, _V, _V, _V]),
     "mg_destroy": (_I, [_V]),
     "mg_last_error": (ctypes.c_char_p, []),
     "mg_level_size": (_I, [_V, _I]),
@@ -148,6 +149,13 @@ def mg_residual_norm(h, f_ptr, u_ptr):
     rel = ctypes.c_double()
     _check(lib().mg_residual_norm(_V(h), _V(f_ptr), _V(u_ptr), ctypes.byref(rel)))
     return rel.value
+
+
+def mg_residual_norm_noalloc(dim, n, order, f_ptr, u_ptr, rel_ptr, stream=0):
+    """Enqueues the relative residual norm into the device double at rel_ptr (no handle,
+    no allocation); returns the status."""
+    return _check(lib().mg_residual_norm_noalloc(int(dim), int(n), int(order), _V(f_ptr), _V(u_ptr),
+                                                 _V(rel_ptr), _V(stream)))
 
 
 def mg_destroy(h):
