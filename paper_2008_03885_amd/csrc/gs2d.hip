@@ -17,13 +17,15 @@
 // start (old values in place of new ones left of the strip) and not stored; so are the
 // rightmost lanes whose neighbours would lie beyond the strip.  The wave marches up a band
 // of rows starting kHaloRows rows below it (row 1, exactly, for the first band).  Per row
-// each lane forms B for its point of the colour from a register window of 2R+1 rows (the
-// new value two rows below is already there), the recurrence runs as a 64-lane inclusive
-// scan of the affine maps x -> A x + B (six shuffle steps), and the finished row is stored.
+// each lane forms B for its point of the colour from a register ring of rows (the new value
+// two rows below is already there; the loads run several rows ahead), the recurrence runs
+// as a 64-lane inclusive scan of the affine maps x -> A x + B (six shuffle steps), and the
+// finished row is stored.
 // Beyond the boundary, values are odd reflections of the current ones; at the first two
 // points of a row the -2 e_x neighbour is such a reflection of an old value or a boundary
 // zero, and the chain restarts there (A = 0).  No LDS, no barriers.
 #include <algorithm>
+#include <utility>
 
 #include "mg_internal.h"
 
@@ -34,9 +36,18 @@ constexpr int kLanes = 64;
 constexpr int kWaves = 4;           // waves per block, independent of each other
 constexpr int kHaloCols = 20;       // columns recomputed left of a strip (ten steps)
 constexpr int kHaloRows = 20;       // rows recomputed below a band (ten steps)
-constexpr int kMinBandRows = 96;
+constexpr int kMinBandRows = 64;
 
 __device__ __forceinline__ bool stopped(const int *done) { return done != nullptr && *done != 0; }
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ __forceinline__ int fold(int i, int n, int &sign) {
   if (i < 0) { i = -i; sign = -sign; }
@@ -101,36 +112,49 @@ __global__ __launch_bounds__(kLanes * kWaves) void k_gs2d(const T *__restrict__ 
   if (band == 0) store(0, T(0), T(0));
   if (jo1 == n - 1) store(n - 1, T(0), T(0));
 
-  // register window: rows j-R .. j+R of the lane's two columns (slot R = row j)
-  T w0[2 * R + 1], w1[2 * R + 1];
+  // Register rings, addressed at compile-time slots in a loop turn unrolled to the ring
+  // length UL: row y of the lane's two columns sits in slot (y - js + R) mod UL, f of row y
+  // in slot (y - js) mod 4.  A slot is refilled right after its last use, so the loads run
+  // UL - 2R rows (u) and four rows (f) ahead of their use.
+  constexpr int UL = R == 2 ? 8 : 12;
+  T w0[UL], w1[UL], g0[4], g1[4];
 #pragma unroll
-  for (int r = 0; r < 2 * R + 1; ++r) load(js - R + r, w0[r], w1[r]);
+  for (int r = 0; r < UL; ++r) load(js - R + r, w0[r], w1[r]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const size_t row = (size_t)min(js + r, n - 2) * n;
+    g0[r] = f[row + a0];
+    g1[r] = f[row + a1];
+  }
   const T A_link = -k.om_d * k.c[2];
-  for (int j = js; j < jo1; ++j) {
-    const size_t row = (size_t)j * n;
-    const T f0 = f[row + a0], f1 = f[row + a1];
+  auto step = [&](const int j, auto pc) {
+    constexpr int P = decltype(pc)::value;
+    if (j >= jo1) return;  // past the band (the same for the whole wave)
     const int sel = colour == 1 ? (j & 1) : ((j & 1) ^ 1);  // the colour's column: x0 + sel
     const int xc = x0 + sel;
+    constexpr int S0 = (P + R) % UL;  // slot of row j
     // row j at columns x0 - 4 .. x0 + 5 from lanes l-2 .. l+2 (beyond the wave: unused)
     T col[10];
-    col[4] = w0[R];
-    col[5] = w1[R];
-    col[2] = __shfl_up(w0[R], 1, kLanes);
-    col[3] = __shfl_up(w1[R], 1, kLanes);
-    col[6] = __shfl_down(w0[R], 1, kLanes);
-    col[7] = __shfl_down(w1[R], 1, kLanes);
+    col[4] = w0[S0];
+    col[5] = w1[S0];
+    col[2] = __shfl_up(w0[S0], 1, kLanes);
+    col[3] = __shfl_up(w1[S0], 1, kLanes);
+    col[6] = __shfl_down(w0[S0], 1, kLanes);
+    col[7] = __shfl_down(w1[S0], 1, kLanes);
     if (R == 3) {
-      col[0] = __shfl_up(w0[R], 2, kLanes);
-      col[1] = __shfl_up(w1[R], 2, kLanes);
-      col[8] = __shfl_down(w0[R], 2, kLanes);
-      col[9] = __shfl_down(w1[R], 2, kLanes);
+      col[0] = __shfl_up(w0[S0], 2, kLanes);
+      col[1] = __shfl_up(w1[S0], 2, kLanes);
+      col[8] = __shfl_down(w0[S0], 2, kLanes);
+      col[9] = __shfl_down(w1[S0], 2, kLanes);
     } else {
       col[0] = col[1] = col[8] = col[9] = T(0);
     }
     auto ux = [&](int d) { return sel ? col[5 + d] : col[4 + d]; };  // row j at xc + d
-    auto uy = [&](int d) { return sel ? w1[R + d] : w0[R + d]; };    // column xc at row j + d
+    auto uy = [&](int d) {                                         // column xc at row j + d
+      return sel ? w1[(P + R + d + UL) % UL] : w0[(P + R + d + UL) % UL];
+    };
     const T up = ux(0);
-    const T fs = sel ? f1 : f0;
+    const T fs = sel ? g1[P % 4] : g0[P % 4];
     const bool active = xc >= 1 && xc <= n - 2;
     const bool start = xc <= 2;  // the -2 e_x neighbour is beyond the boundary or on it
     // the defect without the -2 e_x term (which the recurrence supplies), difference form
@@ -163,19 +187,19 @@ __global__ __launch_bounds__(kLanes * kWaves) void k_gs2d(const T *__restrict__ 
     }
     if (active) {
       if (sel)
-        w1[R] = B;
+        w1[S0] = B;
       else
-        w0[R] = B;
+        w0[S0] = B;
     }
-    if (j >= jo0) store(j, w0[R], w1[R]);
-    // advance the window one row
-#pragma unroll
-    for (int r = 0; r < 2 * R; ++r) {
-      w0[r] = w0[r + 1];
-      w1[r] = w1[r + 1];
-    }
-    load(j + R + 1, w0[2 * R], w1[2 * R]);
-  }
+    if (j >= jo0) store(j, w0[S0], w1[S0]);
+    // refill: row j-R (its last use was this step) with row j-R+UL; f of row j with row j+4
+    load(j - R + UL, w0[P % UL], w1[P % UL]);
+    const size_t row = (size_t)min(j + 4, n - 2) * n;
+    g0[P % 4] = f[row + a0];
+    g1[P % 4] = f[row + a1];
+  };
+  for (int j = js; j < jo1; j += UL)
+    static_for<UL>([&](auto pc) { step(j + decltype(pc)::value, pc); });
 }
 
 }  // namespace
@@ -192,12 +216,13 @@ hipError_t launch_gs2d(const LevelOp &op, double omega, int colour, const T *f, 
   k.om_d = (T)(omega / op.diag);
   const int out = R == 3 ? 2 * out_lanes<3>() : 2 * out_lanes<2>();
   const int strips = (n - 1 + out - 1) / out;  // stored columns cover 1 .. n-1
-  // bands: about eight waves per CU, none shorter than kMinBandRows
+  // bands: about ten waves per CU, none shorter than kMinBandRows (each band recomputes
+  // kHaloRows rows below it)
   int cus = 256, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  const int want = std::max(1, 8 * cus / strips);
+  const int want = std::max(1, 10 * cus / strips);
   const int band_rows = std::max(kMinBandRows, (n - 2 + want - 1) / want);
   const int bands = (n - 2 + band_rows - 1) / band_rows;
   const int blocks = (strips * bands + kWaves - 1) / kWaves;

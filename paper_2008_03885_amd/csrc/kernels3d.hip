@@ -292,29 +292,40 @@ __device__ __forceinline__ T plane_mul(int z, int n) {
 }
 
 // RR = 3: the radius-3 cross of the sixth-order operator (weights w1, w2, w3), with a u
-// ring of 16 planes.
-template <typename T, typename TO, int MODE, bool HAS_U, int XW, int RR = 2>
+// ring of 16 planes.  YS = 2: each thread owns two columns, rows ty and ty + TY, so a
+// block covers an XW x 2TY tile and the y halo (2R rows) is shared by twice the rows.
+template <typename T, typename TO, int MODE, bool HAS_U, int XW, int RR = 2, int YS = 1>
 __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, const T *__restrict__ u,
                                                   TO *__restrict__ out, int n, int zchunk, KOp<T> op,
                                                   double *__restrict__ partials,
                                                   const int *__restrict__ done) {
-  constexpr int NT = XW * TY, R = RR, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
+  constexpr int NT = XW * TY, R = RR, TYB = TY * YS, PX = XW + 2 * R, PY = TYB + 2 * R, PS = PX * PY;
   constexpr int ZR = RR == 2 ? kZR : 16;  // u ring length = planes per loop turn
-  constexpr int NH = PS - NT;  // halo cells of a plane
+  constexpr int NH = PS - NT * YS;  // halo cells of a plane
   static_assert(NH <= NT, "one halo cell per thread");
   __shared__ T plane[2][PS];
   if (stopped(done)) return;
   const Block3 blk = block3();
-  const int x0 = blk.x * XW, y0 = blk.y * TY;
+  const int x0 = blk.x * XW, y0 = blk.y * TYB;
   const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
   const int tx = threadIdx.x % XW, ty = threadIdx.x / XW;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool own = x <= n - 1 && y <= n - 1;
-  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
-  Col3<T> cu, ch;
-  cu.init(x, y, n);
+  const int x = x0 + tx;
+  int yv[YS], pown[YS];
+  bool own[YS], xin[YS];
+  Col3<T> cu[YS];
+  size_t fcol[YS];
+#pragma unroll
+  for (int sr = 0; sr < YS; ++sr) {
+    yv[sr] = y0 + ty + sr * TY;
+    own[sr] = x <= n - 1 && yv[sr] <= n - 1;
+    xin[sr] = x > 0 && x < n - 1 && yv[sr] > 0 && yv[sr] < n - 1;
+    cu[sr].init(x, yv[sr], n);
+    pown[sr] = (ty + sr * TY + R) * PX + tx + R;
+    fcol[sr] = (size_t)(xin[sr] ? yv[sr] : 1) * n + (xin[sr] ? x : 1);
+  }
   // this thread's halo cell (threads 0 .. NH-1): R rows above, R below, R columns on
   // each side of the middle rows
+  Col3<T> ch;
   int hx = 0, hy = 0;
   const bool has_halo = threadIdx.x < NH;
   {
@@ -336,9 +347,8 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   if (has_halo)
     ch.init(x0 - R + hx, y0 - R + hy, n);
   else
-    ch = cu;
-  const int pown = (ty + R) * PX + tx + R, phal = hy * PX + hx;
-  const size_t fcol = (size_t)(xin ? y : 1) * n + (xin ? x : 1);
+    ch = cu[0];
+  const int phal = hy * PX + hx;
   const T *up = HAS_U ? u : f;  // a valid address when there is no u
   const int zlast = z0 + (z1 - z0 + ZR - 1) / ZR * ZR - 1;
   const bool fast = z0 - R > 0 && zlast + ZR - R < n - 1;
@@ -348,62 +358,81 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
     constexpr bool FAST = decltype(fast_tag)::value;
     auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
     auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
-    T ur[ZR], fr[4], hr[4];  // raw loads: u of this column at z-R+k, f and the halo at z+k
+    // raw loads: u of the own columns at z-R+k, f of the own columns and the halo at z+k
+    T ur[YS][ZR], fr[YS][4], hr[4];
 #pragma unroll
-    for (int k = 0; k < ZR; ++k) ur[k] = HAS_U ? up[base(z0 - R + k) + cu.off] : T(0);
+    for (int sr = 0; sr < YS; ++sr) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      fr[k] = f[(FAST ? (size_t)(z0 + k) * n * n : base(z0 + k)) + fcol];
-      hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
+      for (int k = 0; k < ZR; ++k) ur[sr][k] = HAS_U ? up[base(z0 - R + k) + cu[sr].off] : T(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) fr[sr][k] = f[(FAST ? (size_t)(z0 + k) * n * n : base(z0 + k)) + fcol[sr]];
+      hold_regs(ur[sr]);
+      hold_regs(fr[sr]);
     }
-    hold_regs(ur);
-    hold_regs(fr);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
     hold_regs(hr);
     const KOp<T> kop = op;
-    const T fmask = xin ? T(1) : T(0);
     auto step = [&](const int z, auto pc) {
       constexpr int P = decltype(pc)::value;
-      const T m = cu.mul;
       // plane z+d sits in slot (P + R + d) mod ZR
-      T um3 = RR == 3 ? ur[P % ZR] * (m * zm(z - 3)) : T(0);
-      T um2 = ur[(P + R - 2) % ZR] * (m * zm(z - 2)), um1 = ur[(P + R - 1) % ZR] * (m * zm(z - 1));
-      T uc = ur[(P + R) % ZR] * (m * zm(z)), up1 = ur[(P + R + 1) % ZR] * (m * zm(z + 1));
-      T up2 = ur[(P + R + 2) % ZR] * (m * zm(z + 2));
-      T up3 = RR == 3 ? ur[(P + R + 3) % ZR] * (m * zm(z + 3)) : T(0);
-      T fz = fr[P % 4] * fmask, hz = hr[P % 4] * (ch.mul * zm(z));
-      if constexpr (RR == 3)
-        asm volatile("" : "+v"(um3), "+v"(fz), "+v"(hz));
-      else
-        asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
+      T um3[YS], um2[YS], um1[YS], uc[YS], up1[YS], up2[YS], up3[YS], fz[YS];
+#pragma unroll
+      for (int sr = 0; sr < YS; ++sr) {
+        const T m = cu[sr].mul;
+        um3[sr] = RR == 3 ? ur[sr][P % ZR] * (m * zm(z - 3)) : T(0);
+        um2[sr] = ur[sr][(P + R - 2) % ZR] * (m * zm(z - 2));
+        um1[sr] = ur[sr][(P + R - 1) % ZR] * (m * zm(z - 1));
+        uc[sr] = ur[sr][(P + R) % ZR] * (m * zm(z));
+        up1[sr] = ur[sr][(P + R + 1) % ZR] * (m * zm(z + 1));
+        up2[sr] = ur[sr][(P + R + 2) % ZR] * (m * zm(z + 2));
+        up3[sr] = RR == 3 ? ur[sr][(P + R + 3) % ZR] * (m * zm(z + 3)) : T(0);
+        fz[sr] = fr[sr][P % 4] * (xin[sr] ? T(1) : T(0));
+        if constexpr (RR == 3)
+          asm volatile("" : "+v"(um3[sr]), "+v"(fz[sr]));
+        else
+          asm volatile("" : "+v"(um2[sr]), "+v"(fz[sr]));
+      }
+      T hz = hr[P % 4] * (ch.mul * zm(z));
+      asm volatile("" : "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
-      if (HAS_U) ur[P % ZR] = up[base(z - R + ZR) + cu.off];  // the slot of plane z-R
-      fr[P % 4] = f[base(z + 4) + fcol];
+#pragma unroll
+      for (int sr = 0; sr < YS; ++sr) {
+        if (HAS_U) ur[sr][P % ZR] = up[base(z - R + ZR) + cu[sr].off];  // the slot of plane z-R
+        fr[sr][P % 4] = f[base(z + 4) + fcol[sr]];
+      }
       if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
       T *pl = plane[P & 1];
-      pl[pown] = uc;
+#pragma unroll
+      for (int sr = 0; sr < YS; ++sr) pl[pown[sr]] = uc[sr];
       if (has_halo) pl[phal] = hz;
       __syncthreads();
-      T lu = HAS_U ? kop.w1 * (((uc - pl[pown - 1]) + (uc - pl[pown + 1])) +
-                               ((uc - pl[pown - PX]) + (uc - pl[pown + PX])) + ((uc - um1) + (uc - up1))) +
-                         kop.w2 * (((uc - pl[pown - 2]) + (uc - pl[pown + 2])) +
-                                   ((uc - pl[pown - 2 * PX]) + (uc - pl[pown + 2 * PX])) +
-                                   ((uc - um2) + (uc - up2)))
-                   : T(0);
-      if constexpr (RR == 3)
-        if (HAS_U)
-          lu += kop.w3 * (((uc - pl[pown - 3]) + (uc - pl[pown + 3])) +
-                          ((uc - pl[pown - 3 * PX]) + (uc - pl[pown + 3 * PX])) + ((uc - um3) + (uc - up3)));
-      const bool inside = own && xin && z > 0 && z < n - 1;
-      const T r = inside ? fz - lu : T(0);
-      if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
-      // Every lane stores, so no store sits under a branch.  A lane past the grid, or a
-      // step past the last plane, lands on the boundary (clamped address) and stores its
-      // value there, 0; a step past this block's planes stores the value the owning
-      // block stores too (same inputs, same arithmetic).
-      const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep || MODE == kSweepRB)
-        out[id] = (TO)(inside ? uc + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * r : T(0));
-      if (MODE == kResidual) out[id] = (TO)r;
+#pragma unroll
+      for (int sr = 0; sr < YS; ++sr) {
+        const int po = pown[sr];
+        const T c = uc[sr];
+        T lu = HAS_U ? kop.w1 * (((c - pl[po - 1]) + (c - pl[po + 1])) +
+                                 ((c - pl[po - PX]) + (c - pl[po + PX])) + ((c - um1[sr]) + (c - up1[sr]))) +
+                           kop.w2 * (((c - pl[po - 2]) + (c - pl[po + 2])) +
+                                     ((c - pl[po - 2 * PX]) + (c - pl[po + 2 * PX])) +
+                                     ((c - um2[sr]) + (c - up2[sr])))
+                     : T(0);
+        if constexpr (RR == 3)
+          if (HAS_U)
+            lu += kop.w3 * (((c - pl[po - 3]) + (c - pl[po + 3])) +
+                            ((c - pl[po - 3 * PX]) + (c - pl[po + 3 * PX])) + ((c - um3[sr]) + (c - up3[sr])));
+        const bool inside = own[sr] && xin[sr] && z > 0 && z < n - 1;
+        const T r = inside ? fz[sr] - lu : T(0);
+        if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
+        // Every lane stores, so no store sits under a branch.  A lane past the grid, or a
+        // step past the last plane, lands on the boundary (clamped address) and stores its
+        // value there, 0; a step past this block's planes stores the value the owning
+        // block stores too (same inputs, same arithmetic).
+        const size_t id = ((size_t)min(z, n - 1) * n + min(yv[sr], n - 1)) * n + min(x, n - 1);
+        if (MODE == kSweep || MODE == kSweepRB)
+          out[id] = (TO)(inside ? c + (MODE == kSweepRB ? colour_om(kop, x + yv[sr] + z) : kop.om_d) * r : T(0));
+        if (MODE == kResidual) out[id] = (TO)r;
+      }
     };
     for (int z = z0; z < z1; z += ZR)
       static_for<ZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
@@ -1340,12 +1369,23 @@ bool wide_tiles(int n, const char *var) {
   return (size_t)n * n * n * sizeof(T) >= ((size_t)96 << 20);
 }
 
-template <typename T, typename TO, int XW, int RR = 2>
+template <typename T, typename TO, int XW, int RR = 2, int YS = 1>
 const void *xsweep3d_fn(int mode, bool has_u) {
-  if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW, RR>;
-  if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW, RR>;
-  if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW, RR>;
-  return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW, RR> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW, RR>;
+  if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW, RR, YS>;
+  if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW, RR, YS>;
+  if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW, RR, YS>;
+  return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW, RR, YS>;
+}
+
+// Rows per thread of the wide cross-sweep tiles: 2 for FP32 (a 64 x 16 tile per block,
+// 117 VGPRs), 1 for FP64 (two rows would take 187 VGPRs, one block per CU); MG_X3_YS = 1 or
+// 2 sets both.
+template <typename T>
+int x3_ys() {
+  const char *e = getenv("MG_X3_YS");
+  const int env = e != nullptr ? atoi(e) : 0;
+  if (env == 1 || env == 2) return env;
+  return sizeof(T) == 4 ? 2 : 1;
 }
 
 template <typename T, typename TO>
@@ -1364,8 +1404,10 @@ inline bool gsweep_rings() {
 }
 
 template <typename T, typename TO>
-const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw) {
-  if (cross) return xw == 64 ? xsweep3d_fn<T, TO, 64>(mode, has_u) : xsweep3d_fn<T, TO, 32>(mode, has_u);
+const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw, int ys = 1) {
+  if (cross)
+    return xw == 64 ? (ys == 2 ? xsweep3d_fn<T, TO, 64, 2, 2>(mode, has_u) : xsweep3d_fn<T, TO, 64>(mode, has_u))
+                    : xsweep3d_fn<T, TO, 32>(mode, has_u);
   if (gsweep_rings()) return gsweep3d_fn<T, TO>(mode);
   if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
   if (mode == kSweepRB) return (const void *)k_sweep3d<T, TO, kSweepRB, 3>;
@@ -1418,14 +1460,15 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   const bool x3path = !xpath && op.cross3 && x3_r3();
   const bool gpath = !xpath && !x3path && gsweep_rings();
   const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath || x3path ? 64 : TX;
+  const int ys = xpath && xw == 64 ? x3_ys<T>() : 1;  // rows per thread of the cross sweep
   const int nt = xpath || gpath || x3path ? xw * TY : 256;
-  const int tiles = cdiv(n, xw) * cdiv(n, TY);
+  const int tiles = cdiv(n, xw) * cdiv(n, TY * ys);
   const size_t smem = xpath || gpath || x3path ? 0 : sweep_smem<T, 3>();
-  const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw);
+  const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw, ys);
   const int zr = x3path ? 16 : kZR;  // planes per loop turn of the kernel
   const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(occ_fn, nt, smem),
                                                  kMinPlanes)) + zr - 1) / zr * zr;
-  const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
+  const dim3 grid(cdiv(n, xw), cdiv(n, TY * ys), cdiv(n, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   KOp<T> k = to_kop3<T>(op, omega);
   k.colour = colour;
@@ -1448,21 +1491,26 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     return hipGetLastError();
   }
   if (xpath) {
-#define MG_X3(MODE, XW)                                                                      \
+#define MG_X3(MODE, XW, YS)                                                                  \
   if (u != nullptr)                                                                          \
-    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
   else                                                                                       \
-    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
-    if (xw == 64) {
-      if (mode == kSweep) { MG_X3(kSweep, 64) }
-      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64) }
-      else if (mode == kResidual) { MG_X3(kResidual, 64) }
-      else { MG_X3(kNormOnly, 64) }
+    hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
+    if (xw == 64 && ys == 2) {
+      if (mode == kSweep) { MG_X3(kSweep, 64, 2) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 2) }
+      else if (mode == kResidual) { MG_X3(kResidual, 64, 2) }
+      else { MG_X3(kNormOnly, 64, 2) }
+    } else if (xw == 64) {
+      if (mode == kSweep) { MG_X3(kSweep, 64, 1) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 1) }
+      else if (mode == kResidual) { MG_X3(kResidual, 64, 1) }
+      else { MG_X3(kNormOnly, 64, 1) }
     } else {
-      if (mode == kSweep) { MG_X3(kSweep, 32) }
-      else if (mode == kSweepRB) { MG_X3(kSweepRB, 32) }
-      else if (mode == kResidual) { MG_X3(kResidual, 32) }
-      else { MG_X3(kNormOnly, 32) }
+      if (mode == kSweep) { MG_X3(kSweep, 32, 1) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 32, 1) }
+      else if (mode == kResidual) { MG_X3(kResidual, 32, 1) }
+      else { MG_X3(kNormOnly, 32, 1) }
     }
 #undef MG_X3
     return hipGetLastError();

@@ -418,14 +418,15 @@ def test_prolong_correct_3d(dim, n, coarse, prolong, level, fp32):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("wide", ["0", "1"])
+@pytest.mark.parametrize("wide,ys", [("0", "1"), ("1", "1"), ("1", "2")])
 @pytest.mark.parametrize("n,prolong", [(33, 3), (65, 3), (65, 1)])
-def test_3d_tile_shapes(n, prolong, wide, fp32, monkeypatch):
-    """The cross kernels' other tile shapes (64-wide sweep and interpolation tiles,
-    16 x 7 coarse defect tiles), which the large levels take, against the oracle on
-    small and ragged grids; and the small-level shapes forced."""
+def test_3d_tile_shapes(n, prolong, wide, ys, fp32, monkeypatch):
+    """The cross kernels' other tile shapes (64-wide sweep and interpolation tiles, with
+    one or two rows per thread, 16 x 7 coarse defect tiles), which the large levels take,
+    against the oracle on small and ragged grids; and the small-level shapes forced."""
     for var in ("MG_X3_W", "MG_P3_W", "MG_XRR_TALL"):
         monkeypatch.setenv(var, wide)
+    monkeypatch.setenv("MG_X3_YS", ys)
     test_smooth(3, n, 0, prolong, 0, fp32)
     test_residual(3, n, 0, prolong, 0, fp32)
     test_residual_restrict(3, n, 0, prolong, 0, fp32)
@@ -531,6 +532,26 @@ def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
 @pytest.mark.parametrize("coarse,prolong", [(0, 3), (1, 3)])
 def test_coarsest_solve_3d(coarse, prolong, fp32):
     test_coarsest_solve(3, coarse, prolong, fp32)
+
+
+def test_full_size_sweep_513_3d_fp32():
+    """The FP32 level-0 sweep at 513^3 (64 x 16 tiles, two rows per thread), every element,
+    against the FP64 oracle on the same FP32-rounded inputs."""
+    n = 513
+    H = Handle(3, n, precision=1)
+    try:
+        _, s = H.level(0)
+        u = rand_grid(n, 3, 33).astype(np.float32).astype(np.float64)
+        f = (rand_grid(n, 3, 34) * s[2, 2, 2]).astype(np.float32).astype(np.float64)
+        ud, fd = dev(u, True), dev(f, True)
+        out = dev(np.full_like(u, np.nan), True)
+        mg.mg_kernel_smooth(H.h, 0, 1, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        assert_close(host(out), oracle.jacobi(s, H.omega, f, u), TOL32 * _scale_u(u, f, s), "sweep fp32")
+        mg.mg_kernel_residual(H.h, 0, 1, fd.data_ptr(), ud.data_ptr(), out.data_ptr())
+        scale = np.abs(f).max() + s[2, 2, 2] * np.abs(u).max()
+        assert_close(host(out), oracle.residual(s, f, u), TOL32 * 4 * scale, "residual fp32")
+    finally:
+        H.close()
 
 
 def test_full_size_sweep_513_3d():
