@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmgmi.so")
 SOURCES = ["kernels2d.hip", "fused2d.hip", "tile2d.hip", "tail.hip", "kernels3d.hip", "runtime.hip",
-           "serve.hip", "rbc.hip", "noalloc.hip", "gs2d.hip", "restrict.hip"]
+           "serve.hip", "rbc.hip", "noalloc.hip", "gs2d.hip", "restrict.hip", "tail3d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -268,4 +268,23 @@ template <typename T>
 hipError_t launch_tail(int dim, int G, const TailArgs &args, size_t lds_bytes, hipStream_t s,
                        int slots = 1);
 
+// The 3D tail of line passes (tail3d.hip): a 17^3 level whose operator is given by its 1D
+// factors, and the 9^3 coarsest level solved by sine transforms.
+constexpr int kTail3Side = 17, kTail3Coarse = 9;
+struct Tail3Args {
+  int nu1, nu2, prolong, zero_init, repeats;
+  int rb;                // 1: red-black Jacobi sweeps, 0: omega-Jacobi
+  double om_d;           // omega / diagonal of the 17^3 operator
+  double a[7], b[7];     // its 1D factors
+  const double *dst;     // 9^3 sine table (7 x 7), then the 343 per-mode factors
+  const void *f_top;
+  void *u_top;
+  const int *done;
+};
+size_t tail3_lds_bytes(size_t es);
+template <typename T>
+hipError_t tail3_prepare();
+template <typename T>
+hipError_t launch_tail3(const Tail3Args &args, hipStream_t s, int slots = 1);
+
 }  // namespace mgk

@@ -116,11 +116,15 @@ double p1(int prolong, int o) {
 
 // c' = R c P in 1D (coarse offsets -3..3): c'_J = sum_o r(o) sum_k c_k p(o + k - 2J).
 void galerkin_1d(const double c[7], int prolong, double out[7]) {
-  for (int J = -3; J <= 3; ++J) {
+  // c, the weighting and the interpolation are all symmetric, so the product is: the
+  // entries at -J are those at +J (taken from one sum, so that the factor is symmetric to
+  // the last bit and the sine transforms diagonalize the assembled coarsest matrix)
+  for (int J = 0; J <= 3; ++J) {
     double s = 0.0;
     for (int o = -1; o <= 1; ++o)
       for (int k = -3; k <= 3; ++k) s += fw1(o) * c[k + 3] * p1(prolong, o + k - 2 * J);
-    out[J + 3] = s;
+    out[3 + J] = s;
+    out[3 - J] = s;
   }
 }
 
@@ -357,6 +361,7 @@ struct mg_ctx {
   bool fused = true;       // temporally blocked 2D kernels
   int tail_top = 0;        // first level handled by the LDS-resident tail (L: none)
   size_t tail_lds = 0;     // dynamic LDS bytes of the tail
+  bool tail3 = false;      // 3D: the tail is 17^3 + 9^3 in the line-pass kernel
   int *eoff = nullptr;     // stencil entry lists of every level (tail kernel)
   double *ecoef = nullptr;
   std::vector<int> ent_begin, ent_count;
@@ -457,8 +462,29 @@ size_t tail_bytes(const mg_ctx *c, int l, size_t es) {
 template <typename T>
 hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const int *done,
                           hipStream_t s, int repeats = 1) {
+  if (c->tail3 && l == c->L - 2) {
+    mgk::Tail3Args a{};
+    a.nu1 = c->cfg.nu1;
+    a.nu2 = c->cfg.nu2;
+    a.prolong = c->cfg.prolong;
+    a.zero_init = zero_u ? 1 : 0;
+    a.repeats = repeats;
+    a.rb = c->cfg.smoother == MG_SMOOTH_RBJ ? 1 : 0;
+    a.om_d = c->omega / c->ops[l].diag;
+    for (int k = 0; k < 7; ++k) {
+      a.a[k] = c->ops[l].a[k];
+      a.b[k] = c->ops[l].b[k];
+    }
+    a.dst = c->dst;
+    a.f_top = f;
+    a.u_top = u;
+    a.done = done;
+    return mgk::launch_tail3<T>(a, s, c->slots);
+  }
   mgk::TailArgs a{};
-  a.repeats = repeats;
+  // a tail holding only the coarsest level solves it exactly: a repeated visit with the
+  // same right-hand side gives the same values, so it runs once
+  a.repeats = l == c->L - 1 ? 1 : repeats;
   a.levels = c->L - l;
   a.gamma = c->cfg.gamma;
   a.nu1 = c->cfg.nu1;
@@ -1111,6 +1137,25 @@ mg_status setup_ctx(const mg_config *cfg, void *hip_stream, int slots, bool own_
       if (hipMemcpy(table, tab.data(), tab_len * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(MG_EDEVICE, "upload of the coarsest sine table failed"));
       c->dst = table;
+    }
+  }
+  {
+    // 3D: the levels 17^3 and 9^3 in one workgroup of line passes (tail3d.hip) when the
+    // coarsest solve has its sine table and the LDS holds both levels; MG_TAIL3=0, or an
+    // explicit MG_TAIL_N, keeps the general tail
+    const char *e3 = std::getenv("MG_TAIL3");
+    const bool want = !(e3 != nullptr && std::atoi(e3) == 0) && std::getenv("MG_TAIL_N") == nullptr;
+    int lds_limit = 0;
+    if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+      lds_limit = 65536;
+    const size_t need = mgk::tail3_lds_bytes(mixed ? sizeof(float) : sizeof(double));
+    if (want && c->dim == 3 && L >= 2 && c->ns[L - 2] == mgk::kTail3Side && c->ns[L - 1] == mgk::kTail3Coarse &&
+        c->dst != nullptr && cfg->smoother != MG_SMOOTH_RBGS && cfg->restrict_op == 1 &&
+        need <= (size_t)lds_limit) {
+      hipError_t e = mixed ? mgk::tail3_prepare<float>() : mgk::tail3_prepare<double>();
+      if (e != hipSuccess) return bail(fail(MG_EDEVICE, std::string("tail setup: ") + hipGetErrorString(e)));
+      c->tail3 = true;
+      c->tail_top = L - 2;
     }
   }
   {

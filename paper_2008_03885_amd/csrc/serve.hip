@@ -407,7 +407,10 @@ mg_status mg_server_submit(mg_server s, long long tag, int n, const double *f, d
   const size_t one = mgb::footprint(&c, 1);
   if (one == 0) return MG_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
-  if (s->failed) return MG_EDEVICE;
+  if (s->failed) {
+    mgb::set_error(s->error);
+    return MG_EDEVICE;
+  }
   if (one > s->cfg.hbm_budget) {
     s->stats.rejected++;
     return MG_ENOMEM;

@@ -60,7 +60,8 @@ def _serve(reqs, budget=8 << 30, max_slots=8, chunk_steps=2, stagger=None, strea
         bufs = {tag: (dev(f), dev(np.full_like(f, np.nan))) for tag, n, f in reqs}
         torch().cuda.synchronize()  # the server reads f on its own streams
         for i, (tag, n, f) in enumerate(reqs):
-            assert S.submit(tag, *bufs[tag]) == mg.MG_OK
+            st = S.submit(tag, *bufs[tag])
+            assert st == mg.MG_OK, (st, mg.last_error())
             if stagger:
                 time.sleep(stagger[i])
         done = S.wait_all(len(reqs), 300.0)

@@ -284,10 +284,15 @@ def test_red_black_other_orders_and_coarsest_sides(dim, n, nc, order, omega):
         H.close()
 
 
-@pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17")])
+@pytest.mark.parametrize("dim,n,tail", [(2, 257, "0"), (2, 257, "33"), (3, 33, "0"), (3, 33, "17"),
+                                         (3, 33, None)])
 def test_red_black_tail_variants_agree(dim, n, tail, monkeypatch):
-    """Red-black smoothing inside and outside the LDS-resident tail: same cycles."""
-    monkeypatch.setenv("MG_TAIL_N", tail)
+    """Red-black smoothing inside and outside the LDS-resident tail (in 3D also the
+    line-pass tail of the 17^3 and 9^3 levels, tail=None): same cycles."""
+    if tail is None:
+        monkeypatch.delenv("MG_TAIL_N", raising=False)
+    else:
+        monkeypatch.setenv("MG_TAIL_N", tail)
     H = Handle(dim, n, gamma=2, smoother=1)
     try:
         f = inputs.manufactured_2d(n)[1] if dim == 2 else inputs.smooth_sine_3d(n)
@@ -546,18 +551,38 @@ def test_fixed_cycles_match_oracle_3d(n, coarse, prolong, nu1, nu2, gamma):
         H.close()
 
 
-@pytest.mark.parametrize("tail,dst,coarse", [(None, "1", 0), (None, "0", 0), ("0", "1", 0),
-                                              (None, "1", 1), ("17", "1", 0), ("17", "0", 1),
-                                              ("33", "1", 1)])
-def test_3d_tail_variants_agree(tail, dst, coarse, monkeypatch):
-    """With or without the LDS-resident tail, its coarsest solve by sine transforms or by
-    the dense inverse: same cycles as the oracle."""
+@pytest.mark.parametrize("tail,dst,coarse,tail3", [(None, "1", 0, "1"), (None, "0", 0, "1"), ("0", "1", 0, "1"),
+                                                    (None, "1", 1, "1"), ("17", "1", 0, "1"), ("17", "0", 1, "1"),
+                                                    ("33", "1", 1, "1"), (None, "1", 1, "0"), (None, "1", 2, "1"),
+                                                    (None, "1", 3, "1")])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_3d_tail_variants_agree(tail, dst, coarse, tail3, precision, monkeypatch):
+    """With or without the LDS-resident tail, the line-pass tail of the 17^3 and 9^3
+    levels (the default when the sine table exists; MG_TAIL3=0 or an explicit MG_TAIL_N
+    turns it off), the coarsest solve by sine transforms or by the dense inverse: same
+    cycles as the oracle (mixed precision: FP32 cycles inside FP64 steps, against FP64
+    cycles, to the FP32 level)."""
     if tail is None:
         monkeypatch.delenv("MG_TAIL_N", raising=False)
     else:
         monkeypatch.setenv("MG_TAIL_N", tail)
     monkeypatch.setenv("MG_COARSE_DST", dst)
+    monkeypatch.setenv("MG_TAIL3", tail3)
     n = 33
+    if precision:
+        f = inputs.smooth_sine_3d(n)
+        fd = dev(f)
+        out = []
+        for p in (0, 1):
+            H = Handle(3, n, gamma=2, coarse=coarse, precision=p, inner_cycles=1)
+            try:
+                ud = dev(np.zeros_like(f))
+                mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), 3)
+                out.append(host(ud))
+            finally:
+                H.close()
+        assert np.linalg.norm(out[1] - out[0]) <= 1e-5 * np.linalg.norm(out[0])
+        return
     H = Handle(3, n, gamma=2, coarse=coarse)
     try:
         f = inputs.smooth_sine_3d(n)
