@@ -768,6 +768,199 @@ __global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
   }
 }
 
+// Values of the neighbouring lanes across the whole wavefront (DPP wavefront shifts):
+// lane_prev gives lane L the value of lane L-1, lane_next that of lane L+1; the lane with
+// no neighbour gets 0.
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_prev((int)(b & 0xffffffffLL)), hi = dpp_prev((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_next((int)(b & 0xffffffffLL)), hi = dpp_next((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ------------------------------- separable (Galerkin) sweep, wavefront pencils ----
+// The operator of the Galerkin levels (as above, L u(z) = sum_k b_k P1(z+k) + sum_{k != 0}
+// a_k (P2(z+k) - P2(z)) with the in-plane P1 = a_x (b_y u) + b_x (a_y u), P2 = b_x (b_y u))
+// without LDS and without barriers: every wavefront works alone on a pencil of YR rows
+// and 64 columns, of which the middle 58 are its outputs (three columns of x halo on
+// each side).  Per plane a lane loads its column at the YR rows and three rows of y halo
+// on each side, applies b_y and a_y in registers, and takes the x neighbours of b_y u and
+// a_y u from the lanes beside it (cross-lane shuffles); P1 and P2 enter register rings of
+// eight planes, the z pass runs over the rings.  Symmetric factors: with
+// t_j = (v_{+j} - v_0) + (v_{-j} - v_0), a v = sum_j a_j t_j (difference form) and
+// b v = (sum_i b_i) v_0 + sum_j b_j t_j.  Four wavefronts per block take neighbouring row
+// groups of the same columns and planes.  Register rings as in the cross sweep: the u
+// window of a plane is loaded two planes ahead, f four planes ahead.
+template <typename T, typename TO, int MODE, int YR>
+__global__ __launch_bounds__(256) void k_gpen3d(const T *__restrict__ f, const T *__restrict__ u,
+                                                TO *__restrict__ out, int n, int zchunk, KOp<T> op,
+                                                double *__restrict__ partials, const int *__restrict__ done) {
+  constexpr int R = 3, OUT = 64 - 2 * R, WIN = YR + 2 * R;
+  if (stopped(done)) return;
+  const Block3 blk = block3();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = blk.x * OUT + lane - R;  // this lane's column (beyond the grid: folded)
+  const int y0 = (blk.y * 4 + wave) * YR;
+  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
+  // column: folded offset and the factor of the odd extension (0 on the boundary)
+  int sx = 1;
+  const int xf = fold(x, n, sx);
+  const bool xok = xf > 0 && xf < n - 1;
+  const int xoff = xok ? xf : 1;
+  const T xmul = xok ? T(sx) : T(0);
+  // rows of the window (uniform over the wavefront): offsets y*n and factors
+  int yoff[WIN];
+  T ymul[WIN];
+#pragma unroll
+  for (int i = 0; i < WIN; ++i) {
+    int sy = 1;
+    const int yf = fold(y0 - R + i, n, sy);
+    const bool ok = yf > 0 && yf < n - 1;
+    yoff[i] = (ok ? yf : 1) * n;
+    ymul[i] = ok ? T(sy) : T(0);
+  }
+  const bool lane_out = lane >= R && lane < 64 - R;
+  const bool xin = lane_out && x > 0 && x < n - 1;
+  const KOp<T> kop = op;
+  T bsum = kop.b[3];
+#pragma unroll
+  for (int j = 1; j <= 3; ++j) bsum += T(2) * kop.b[3 + j];
+  auto pbase = [&](int z) -> size_t {
+    int sz = 1;
+    int zf = fold(z, n, sz);
+    zf = (zf > 0 && zf < n - 1) ? zf : 1;
+    return (size_t)zf * n * n;
+  };
+  auto pmul = [&](int z) -> T {
+    int sz = 1;
+    const int zf = fold(z, n, sz);
+    return (zf > 0 && zf < n - 1) ? T(sz) : T(0);
+  };
+  double acc = 0.0;
+  // rings: u windows by (plane - (z0-3)) mod 2, P and the window centres by the same
+  // mod 8 / 4, f by (plane - z0) mod 4
+  T win[2][WIN], p1r[YR][8], p2r[YR][8], ucr[YR][4], fr[YR][4];
+  // loads from a plane base that is uniform over the wavefront plus a 32-bit offset
+  auto load_win = [&](int slot, int q) {
+    const T *pl = u + pbase(q);
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) win[slot][i] = pl[(unsigned)(xoff + yoff[i])];
+  };
+  load_win(0, z0 - R);
+  load_win(1, z0 - R + 1);
+  unsigned foff[YR];  // f of the own rows within a plane
+#pragma unroll
+  for (int r = 0; r < YR; ++r) foff[r] = (unsigned)(min(max(y0 + r, 0), n - 1) * n + (xin ? x : 1));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T *pl = f + pbase(min(z0 + k, n - 1));
+#pragma unroll
+    for (int r = 0; r < YR; ++r) fr[r][k] = pl[foff[r]];
+  }
+  hold_regs(win[0]);
+  hold_regs(win[1]);
+  // P1, P2 of plane q from its window (slot ws), into ring slot ps; the window centres
+  // into the centre ring slot cs
+  auto inplane = [&](int q, int ws, int ps, int cs) {
+    __builtin_amdgcn_sched_barrier(0);  // one plane at a time (register pressure)
+    const T m = xmul * pmul(q);
+    T v[WIN];
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) v[i] = win[ws][i] * (m * ymul[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    load_win(ws, q + 2);
+#pragma unroll
+    for (int r = 0; r < YR; ++r) {
+      const T c = v[r + R];
+      ucr[r][cs] = c;
+      T ay = T(0), by = bsum * c;
+#pragma unroll
+      for (int j = 1; j <= 3; ++j) {
+        const T t = (v[r + R + j] - c) + (v[r + R - j] - c);
+        ay += kop.a[3 + j] * t;
+        by += kop.b[3 + j] * t;
+      }
+      // x pass: neighbours from the lanes beside, shifted in j steps of one lane (the
+      // lanes at the strip edges take values of no use: they produce no output)
+      T p1 = kop.b[3] * ay, p2 = bsum * by;
+      T bl = by, br = by, al = ay, ar = ay;
+#pragma unroll
+      for (int j = 1; j <= 3; ++j) {
+        bl = lane_prev(bl);  // by of column x - j
+        br = lane_next(br);  // by of column x + j
+        al = lane_prev(al);
+        ar = lane_next(ar);
+        const T tb = (br - by) + (bl - by);
+        p1 += kop.a[3 + j] * tb + kop.b[3 + j] * (ar + al);
+        p2 += kop.b[3 + j] * tb;
+      }
+      p1r[r][ps] = p1;
+      p2r[r][ps] = p2;
+    }
+  };
+  // Step s (s = 0, 1, ...; P = s mod 8) computes P1, P2 of plane z0-3+s into ring slot P
+  // and, from s = 6 on, the output plane z = z0-6+s from the slots P+2 .. P+8 (mod 8).
+  // The first six steps only fill the rings (a uniform branch skips the z pass).
+  auto step = [&](const int z, auto pc) {
+    constexpr int P = decltype(pc)::value;  // (z - (z0-6)) mod 8
+    inplane(z + R, P % 2, P, P % 4);
+    if (z < z0) return;
+    T fz[YR];
+#pragma unroll
+    for (int r = 0; r < YR; ++r) fz[r] = fr[r][(P + 2) % 4] * (xin ? T(1) : T(0));
+    asm volatile("" : "+v"(fz[0]));
+    {
+      const T *pl = f + pbase(min(z + 4, n - 1));
+#pragma unroll
+      for (int r = 0; r < YR; ++r) fr[r][(P + 2) % 4] = pl[foff[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < YR; ++r) {
+      // z pass: planes z-3 .. z+3 sit in slots P+2 .. P+8
+      const T c2 = p2r[r][(P + 5) % 8];
+      T lu = kop.b[3] * p1r[r][(P + 5) % 8];
+#pragma unroll
+      for (int j = 1; j <= 3; ++j)
+        lu += kop.b[3 + j] * (p1r[r][(P + 5 + j) % 8] + p1r[r][(P + 5 - j) % 8]) +
+              kop.a[3 + j] * ((p2r[r][(P + 5 + j) % 8] - c2) + (p2r[r][(P + 5 - j) % 8] - c2));
+      const int y = y0 + r;
+      const bool inside = xin && y > 0 && y < n - 1 && z > 0 && z < n - 1;
+      const T rr = inside ? fz[r] - lu : T(0);
+      if (partials != nullptr && inside && z < z1) acc += (double)rr * (double)rr;
+      // every lane stores: the x-halo lanes store the value of the nearest output lane
+      // at its address (same value), lanes past the grid the boundary's 0 (clamped)
+      const T uc = ucr[r][(P + 1) % 4];
+      T v = T(0);
+      if (MODE == kSweep || MODE == kSweepRB)
+        v = inside ? uc + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * rr : T(0);
+      if (MODE == kResidual) v = rr;
+      if (MODE != kNormOnly) {
+        const int src = lane < R ? R : (lane >= 64 - R ? 63 - R : lane);
+        const T vs = __shfl(v, src, 64);
+        const int xs = min(max(blk.x * OUT + src - R, 0), n - 1);
+        const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + xs;
+        out[id] = (TO)vs;
+      }
+    }
+  };
+  for (int z = z0 - 6; z < z1; z += 8)
+    static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
+  if (partials != nullptr) {
+    const double tot = block_sum<256>(acc);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
 // ------------------------ plane-ring defect + full weighting (Galerkin levels) ----
 // The second implementation (MG_G3_OLD=1).  Block: coarse tile (TX/2) x (TY/2) at coarse
 // planes [K0, K1).  The defect is computed on the fine tile extended by one point (the
@@ -1396,6 +1589,30 @@ const void *gsweep3d_fn(int mode) {
   return (const void *)k_gsweep3d<T, TO, kNormOnly, 64>;
 }
 
+// Rows per wavefront of the pencil sweep: 2 (FP32 126 VGPRs, four wavefronts per SIMD;
+// FP64 209); MG_GPEN_ROWS = 2 doubles them.  Measured at 513^3: FP32 two rows 571 us,
+// four 540 us, but four rows lose more on the smaller levels (257^3: 81 against 94 us);
+// FP64 one row (147 VGPRs) was slower than two in the whole solve (316 against 308 ms).
+template <typename T>
+constexpr int gpen_rows() { return 2; }
+inline int gpen_rows_scale() {
+  const char *e = getenv("MG_GPEN_ROWS");
+  return e != nullptr && atoi(e) == 2 ? 2 : 1;
+}
+template <typename T, typename TO, int YR>
+const void *gpen3d_fn_rows(int mode) {
+  if (mode == kSweep) return (const void *)k_gpen3d<T, TO, kSweep, YR>;
+  if (mode == kSweepRB) return (const void *)k_gpen3d<T, TO, kSweepRB, YR>;
+  if (mode == kResidual) return (const void *)k_gpen3d<T, TO, kResidual, YR>;
+  return (const void *)k_gpen3d<T, TO, kNormOnly, YR>;
+}
+// The pencil kernel serves the separable sweeps unless MG_GPEN = 0 (then the LDS-tile
+// kernel k_gsweep3d).
+inline bool gsweep_pencils() {
+  const char *e = getenv("MG_GPEN");
+  return !(e != nullptr && atoi(e) == 0);
+}
+
 // The separable kernel serves the radius-3 operators unless MG_G3_OLD = 1 (the LDS-ring
 // kernel that applies them plane by plane, kept as a second implementation).
 inline bool gsweep_rings() {
@@ -1433,7 +1650,9 @@ size_t rr_smem() {
 
 int sweep_partials_3d(int n) {
   const long tiles = (long)cdiv(n, TX) * cdiv(n, TY);
-  return (int)(tiles * cdiv(n, kMinPlanes));
+  // the pencil sweep: 58 columns x 4 wavefronts of gpen_rows rows per block
+  const long pencils = (long)cdiv(n, 58) * cdiv(n, 4 * std::min(gpen_rows<float>(), gpen_rows<double>()));
+  return (int)(std::max(tiles, pencils) * cdiv(n, kMinPlanes));
 }
 
 // The sixth-order radius-3 cross runs the cross kernels with R = 3 (MG_X3_R3=0: the
@@ -1472,6 +1691,29 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   KOp<T> k = to_kop3<T>(op, omega);
   k.colour = colour;
+  if (gpath && gsweep_pencils()) {
+    constexpr int Y1 = gpen_rows<T>(), Y2 = 2 * gpen_rows<T>();
+    const int yr = Y1 * gpen_rows_scale();
+    const void *fn = yr == Y1 ? gpen3d_fn_rows<T, TO, Y1>(mode) : gpen3d_fn_rows<T, TO, Y2>(mode);
+    const int ptiles = cdiv(n, 58) * cdiv(n, 4 * yr);
+    const int pzc = (std::min(kMaxPlanes, band_rows(n, ptiles, kRounds3d * resident_blocks(fn, 256, 0), kMinPlanes)) + 7) / 8 * 8;
+    const dim3 pgrid(cdiv(n, 58), cdiv(n, 4 * yr), cdiv(n, pzc));
+    if (nparts) *nparts = pgrid.x * pgrid.y * pgrid.z;
+#define MG_GP(MODE, YR) hipLaunchKernelGGL((k_gpen3d<T, TO, MODE, YR>), pgrid, dim3(256), 0, s, f, u, out, n, pzc, k, partials, done)
+#define MG_GPM(YR)                          \
+    if (mode == kSweep) MG_GP(kSweep, YR);          \
+    else if (mode == kSweepRB) MG_GP(kSweepRB, YR); \
+    else if (mode == kResidual) MG_GP(kResidual, YR); \
+    else MG_GP(kNormOnly, YR);
+    if (yr == Y1) {
+      MG_GPM(Y1)
+    } else {
+      MG_GPM(Y2)
+    }
+#undef MG_GPM
+#undef MG_GP
+    return hipGetLastError();
+  }
   if (gpath) {
 #define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
     if (mode == kSweep) MG_G3(kSweep);

@@ -434,12 +434,16 @@ def test_3d_tile_shapes(n, prolong, wide, ys, fp32, monkeypatch):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("old", ["0", "1"])
-@pytest.mark.parametrize("n,level", [(33, 1), (65, 1), (65, 2), (129, 1)])
-def test_3d_galerkin_sweep_kernels(n, level, old, fp32, monkeypatch):
-    """Galerkin levels: the separable register-ring kernels (default) and the plane-ring
-    LDS kernels (MG_G3_OLD=1) against the oracle's assembled Galerkin stencils."""
+@pytest.mark.parametrize("old,pencil,rows", [("0", "1", "1"), ("0", "1", "2"), ("0", "0", "1"), ("1", "1", "1")])
+@pytest.mark.parametrize("n,level", [(33, 1), (65, 1), (65, 2), (129, 1), (257, 1)])
+def test_3d_galerkin_sweep_kernels(n, level, old, pencil, rows, fp32, monkeypatch):
+    """Galerkin levels: the wavefront-pencil sweep (default; MG_GPEN_ROWS=2: twice the
+    rows per wavefront), the LDS-tile sweep (MG_GPEN=0) and the plane-ring LDS kernels
+    (MG_G3_OLD=1) against the oracle's assembled Galerkin stencils, on one strip of 58
+    columns up to ragged multi-strip, multi-band levels."""
     monkeypatch.setenv("MG_G3_OLD", old)
+    monkeypatch.setenv("MG_GPEN", pencil)
+    monkeypatch.setenv("MG_GPEN_ROWS", rows)
     test_smooth(3, n, 1, 3, level, fp32)
     test_residual(3, n, 1, 3, level, fp32)
     test_residual_restrict(3, n, 1, 3, level, fp32)
