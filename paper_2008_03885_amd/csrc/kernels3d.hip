@@ -349,7 +349,8 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   else
     ch = cu[0];
   const int phal = hy * PX + hx;
-  const T *up = HAS_U ? u : f;  // a valid address when there is no u
+  // u is read from f (scaled by omega / a0 when consumed) for two sweeps from zero
+  const T *up = (HAS_U && MODE != kSweepZ2) ? u : f;  // a valid address when there is no u
   const int zlast = z0 + (z1 - z0 + ZR - 1) / ZR * ZR - 1;
   const bool fast = z0 - R > 0 && zlast + ZR - R < n - 1;
 
@@ -373,13 +374,14 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
     for (int k = 0; k < 4; ++k) hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
     hold_regs(hr);
     const KOp<T> kop = op;
+    const T uscale = MODE == kSweepZ2 ? kop.om_d : T(1);
     auto step = [&](const int z, auto pc) {
       constexpr int P = decltype(pc)::value;
       // plane z+d sits in slot (P + R + d) mod ZR
       T um3[YS], um2[YS], um1[YS], uc[YS], up1[YS], up2[YS], up3[YS], fz[YS];
 #pragma unroll
       for (int sr = 0; sr < YS; ++sr) {
-        const T m = cu[sr].mul;
+        const T m = cu[sr].mul * uscale;
         um3[sr] = RR == 3 ? ur[sr][P % ZR] * (m * zm(z - 3)) : T(0);
         um2[sr] = ur[sr][(P + R - 2) % ZR] * (m * zm(z - 2));
         um1[sr] = ur[sr][(P + R - 1) % ZR] * (m * zm(z - 1));
@@ -392,8 +394,11 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
           asm volatile("" : "+v"(um3[sr]), "+v"(fz[sr]));
         else
           asm volatile("" : "+v"(um2[sr]), "+v"(fz[sr]));
+        if constexpr (MODE == kSweepZ2)  // the products omega / a0 * f rounded as stored
+          asm volatile("" : "+v"(um2[sr]), "+v"(um1[sr]), "+v"(uc[sr]), "+v"(up1[sr]), "+v"(up2[sr]),
+                       "+v"(um3[sr]), "+v"(up3[sr]));
       }
-      T hz = hr[P % 4] * (ch.mul * zm(z));
+      T hz = hr[P % 4] * ((ch.mul * uscale) * zm(z));
       asm volatile("" : "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
         // value there, 0; a step past this block's planes stores the value the owning
         // block stores too (same inputs, same arithmetic).
         const size_t id = ((size_t)min(z, n - 1) * n + min(yv[sr], n - 1)) * n + min(x, n - 1);
-        if (MODE == kSweep || MODE == kSweepRB)
+        if (MODE == kSweep || MODE == kSweepRB || MODE == kSweepZ2)
           out[id] = (TO)(inside ? c + (MODE == kSweepRB ? colour_om(kop, x + yv[sr] + z) : kop.om_d) * r : T(0));
         if (MODE == kResidual) out[id] = (TO)r;
       }
@@ -850,8 +855,9 @@ __global__ __launch_bounds__(256) void k_gpen3d(const T *__restrict__ f, const T
   // mod 8 / 4, f by (plane - z0) mod 4
   T win[2][WIN], p1r[YR][8], p2r[YR][8], ucr[YR][4], fr[YR][4];
   // loads from a plane base that is uniform over the wavefront plus a 32-bit offset
+  const T *ub = MODE == kSweepZ2 ? f : u;  // two sweeps from zero: u = omega / a0 * f
   auto load_win = [&](int slot, int q) {
-    const T *pl = u + pbase(q);
+    const T *pl = ub + pbase(q);
 #pragma unroll
     for (int i = 0; i < WIN; ++i) win[slot][i] = pl[(unsigned)(xoff + yoff[i])];
   };
@@ -872,10 +878,13 @@ __global__ __launch_bounds__(256) void k_gpen3d(const T *__restrict__ f, const T
   // into the centre ring slot cs
   auto inplane = [&](int q, int ws, int ps, int cs) {
     __builtin_amdgcn_sched_barrier(0);  // one plane at a time (register pressure)
-    const T m = xmul * pmul(q);
+    const T m = (MODE == kSweepZ2 ? xmul * kop.om_d : xmul) * pmul(q);
     T v[WIN];
 #pragma unroll
-    for (int i = 0; i < WIN; ++i) v[i] = win[ws][i] * (m * ymul[i]);
+    for (int i = 0; i < WIN; ++i) {
+      v[i] = win[ws][i] * (m * ymul[i]);
+      if constexpr (MODE == kSweepZ2) asm volatile("" : "+v"(v[i]));  // rounded as stored
+    }
     __builtin_amdgcn_sched_barrier(0);
     load_win(ws, q + 2);
 #pragma unroll
@@ -940,7 +949,7 @@ __global__ __launch_bounds__(256) void k_gpen3d(const T *__restrict__ f, const T
       // at its address (same value), lanes past the grid the boundary's 0 (clamped)
       const T uc = ucr[r][(P + 1) % 4];
       T v = T(0);
-      if (MODE == kSweep || MODE == kSweepRB)
+      if (MODE == kSweep || MODE == kSweepRB || MODE == kSweepZ2)
         v = inside ? uc + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * rr : T(0);
       if (MODE == kResidual) v = rr;
       if (MODE != kNormOnly) {
@@ -1564,21 +1573,23 @@ bool wide_tiles(int n, const char *var) {
 
 template <typename T, typename TO, int XW, int RR = 2, int YS = 1>
 const void *xsweep3d_fn(int mode, bool has_u) {
+  if (mode == kSweepZ2) return (const void *)k_xsweep3d<T, TO, kSweepZ2, true, XW, RR, YS>;
   if (mode == kSweep) return has_u ? (const void *)k_xsweep3d<T, TO, kSweep, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kSweep, false, XW, RR, YS>;
   if (mode == kSweepRB) return has_u ? (const void *)k_xsweep3d<T, TO, kSweepRB, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kSweepRB, false, XW, RR, YS>;
   if (mode == kResidual) return has_u ? (const void *)k_xsweep3d<T, TO, kResidual, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kResidual, false, XW, RR, YS>;
   return has_u ? (const void *)k_xsweep3d<T, TO, kNormOnly, true, XW, RR, YS> : (const void *)k_xsweep3d<T, TO, kNormOnly, false, XW, RR, YS>;
 }
 
-// Rows per thread of the wide cross-sweep tiles: 2 for FP32 (a 64 x 16 tile per block,
-// 117 VGPRs), 1 for FP64 (two rows would take 187 VGPRs, one block per CU); MG_X3_YS = 1 or
-// 2 sets both.
+// Rows per thread of the wide cross-sweep tiles: 2 (a 64 x 16 tile per block; FP32 117
+// VGPRs, FP64 187: 1025^3 FP64 sweep 6632 -> 6269 us, FP64 residual cast to FP32 5543 ->
+// 5328 us against one row), except the FP64 norm-only pass, which spills with two rows;
+// MG_X3_YS = 1 or 2 sets every case.
 template <typename T>
-int x3_ys() {
+int x3_ys(int mode) {
   const char *e = getenv("MG_X3_YS");
   const int env = e != nullptr ? atoi(e) : 0;
   if (env == 1 || env == 2) return env;
-  return sizeof(T) == 4 ? 2 : 1;
+  return sizeof(T) == 8 && mode == kNormOnly ? 1 : 2;
 }
 
 template <typename T, typename TO>
@@ -1601,6 +1612,7 @@ inline int gpen_rows_scale() {
 }
 template <typename T, typename TO, int YR>
 const void *gpen3d_fn_rows(int mode) {
+  if (mode == kSweepZ2) return (const void *)k_gpen3d<T, TO, kSweepZ2, YR>;
   if (mode == kSweep) return (const void *)k_gpen3d<T, TO, kSweep, YR>;
   if (mode == kSweepRB) return (const void *)k_gpen3d<T, TO, kSweepRB, YR>;
   if (mode == kResidual) return (const void *)k_gpen3d<T, TO, kResidual, YR>;
@@ -1619,6 +1631,21 @@ inline bool gsweep_rings() {
   const char *e = getenv("MG_G3_OLD");
   return !(e != nullptr && atoi(e) == 1);
 }
+
+}  // namespace
+
+bool x3_r3();
+
+// Whether two sweeps from zero run in one pass on a level of this operator: the cross
+// kernels (radius 2 and 3) and the pencil kernel have the mode, the LDS-tile and plane-ring
+// kernels do not.
+bool sweep3d_z2_ok(const LevelOp &op) {
+  if (op.cross) return true;
+  if (op.cross3 && x3_r3()) return true;
+  return gsweep_rings() && gsweep_pencils();
+}
+
+namespace {
 
 template <typename T, typename TO>
 const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw, int ys = 1) {
@@ -1673,13 +1700,17 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     if (mode != kSweep || !std::is_same<T, TO>::value) return hipErrorInvalidValue;
     mode = kSweepRB;
   }
+  if (mode == kSweepZ2) {  // two sweeps from zero: the kernels read u from f
+    if (!std::is_same<T, TO>::value || !sweep3d_z2_ok(op)) return hipErrorInvalidValue;
+    u = f;
+  }
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
   // operator (it uses om_d only)
   const bool xpath = op.cross || u == nullptr;
   const bool x3path = !xpath && op.cross3 && x3_r3();
   const bool gpath = !xpath && !x3path && gsweep_rings();
   const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath || x3path ? 64 : TX;
-  const int ys = xpath && xw == 64 ? x3_ys<T>() : 1;  // rows per thread of the cross sweep
+  const int ys = xpath && xw == 64 ? x3_ys<T>(mode) : 1;  // rows per thread of the cross sweep
   const int nt = xpath || gpath || x3path ? xw * TY : 256;
   const int tiles = cdiv(n, xw) * cdiv(n, TY * ys);
   const size_t smem = xpath || gpath || x3path ? 0 : sweep_smem<T, 3>();
@@ -1701,7 +1732,8 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     if (nparts) *nparts = pgrid.x * pgrid.y * pgrid.z;
 #define MG_GP(MODE, YR) hipLaunchKernelGGL((k_gpen3d<T, TO, MODE, YR>), pgrid, dim3(256), 0, s, f, u, out, n, pzc, k, partials, done)
 #define MG_GPM(YR)                          \
-    if (mode == kSweep) MG_GP(kSweep, YR);          \
+    if (mode == kSweepZ2) MG_GP(kSweepZ2, YR);      \
+    else if (mode == kSweep) MG_GP(kSweep, YR);     \
     else if (mode == kSweepRB) MG_GP(kSweepRB, YR); \
     else if (mode == kResidual) MG_GP(kResidual, YR); \
     else MG_GP(kNormOnly, YR);
@@ -1715,6 +1747,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     return hipGetLastError();
   }
   if (gpath) {
+    if (mode == kSweepZ2) return hipErrorInvalidValue;  // (sweep3d_z2_ok excludes this path)
 #define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
     if (mode == kSweep) MG_G3(kSweep);
     else if (mode == kSweepRB) MG_G3(kSweepRB);
@@ -1725,7 +1758,8 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   }
   if (x3path) {
 #define MG_X33(MODE) hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, 64, 3>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
-    if (mode == kSweep) MG_X33(kSweep);
+    if (mode == kSweepZ2) MG_X33(kSweepZ2);
+    else if (mode == kSweep) MG_X33(kSweep);
     else if (mode == kSweepRB) MG_X33(kSweepRB);
     else if (mode == kResidual) MG_X33(kResidual);
     else MG_X33(kNormOnly);
@@ -1738,6 +1772,14 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
   else                                                                                       \
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
+    if (mode == kSweepZ2) {
+#define MG_XZ(XW, YS) hipLaunchKernelGGL((k_xsweep3d<T, TO, kSweepZ2, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+      if (xw == 64 && ys == 2) MG_XZ(64, 2);
+      else if (xw == 64) MG_XZ(64, 1);
+      else MG_XZ(32, 1);
+#undef MG_XZ
+      return hipGetLastError();
+    }
     if (xw == 64 && ys == 2) {
       if (mode == kSweep) { MG_X3(kSweep, 64, 2) }
       else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 2) }
@@ -1757,6 +1799,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 #undef MG_X3
     return hipGetLastError();
   }
+  if (mode == kSweepZ2) return hipErrorInvalidValue;  // (sweep3d_z2_ok excludes this path)
 #define MG_S3(MODE) \
   hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, 3>), grid, dim3(256), (sweep_smem<T, 3>()), s, f, u, out, n, zc, k, partials, done)
   if (mode == kSweep) MG_S3(kSweep);

@@ -70,7 +70,9 @@ struct DevState {
 };
 
 // kSweepRB: a sweep relaxing one colour (KOp::colour), the 3D kernels' red-black step.
-enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2, kSweepRB = 3 };
+// kSweepZ2: two omega-Jacobi sweeps from a zero iterate in one pass (3D): the first
+// sweep's result, omega / a0 * f, is formed on the fly wherever the second reads u.
+enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2, kSweepRB = 3, kSweepZ2 = 4 };
 
 // Workgroups are dealt to the XCDs (8 on MI355X, each with its own L2) round-robin in
 // linear dispatch order.  xcd_logical maps a linear id to a logical block id such that
@@ -169,6 +171,7 @@ int band_rows(int total, int across, int capacity, int cmin);
 
 // 3D variants (kernels3d.hip), called by the launchers above for dim == 3.
 int sweep_partials_3d(int n);
+bool sweep3d_z2_ok(const LevelOp &op);
 hipError_t prepare_3d();  // enables the large dynamic LDS of the separable 3D kernels
 template <typename T, typename TO>
 hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f, const T *u,

@@ -536,6 +536,12 @@ hipError_t resid_restrict(mg_ctx *c, int l, const T *f, const T *u, T *scratch, 
   return mgk::launch_restrict_cubic<T>(c->dim, scratch, fc, c->ns[l], done, s, c->slots);
 }
 
+// Two omega-Jacobi sweeps from a zero iterate in one 3D pass unless MG_Z2=0.
+bool z2_enabled() {
+  const char *e = std::getenv("MG_Z2");
+  return !(e != nullptr && std::atoi(e) == 0);
+}
+
 // Cross levels of radius 2 or 3 (where Gauss-Seidel partial steps differ from Jacobi ones).
 bool gs_level(const LevelOp &op) { return op.cross3 || (op.cross && op.a[1] != 0.0); }
 
@@ -714,7 +720,17 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     if (e != hipSuccess) return e;
     zero = false;
   }
-  for (int k = 0; k < c->cfg.nu1 * steps; ++k) {
+  int k0 = 0;
+  if (zero && !rb && !rb3 && !check && dim == 3 && c->cfg.nu1 >= 2 && z2_enabled() && mgk::sweep3d_z2_ok(op)) {
+    // the first two sweeps from the zero iterate in one pass, into the array the second
+    // sweep would have written (the ping-pong order of the sweeps that follow is kept)
+    e = mgk::launch_sweep<T, T>(dim, mgk::kSweepZ2, op, c->omega, f, (const T *)nullptr, cur, n, nullptr,
+                                nullptr, done, s, c->slots, 0);
+    if (e != hipSuccess) return e;
+    zero = false;
+    k0 = 2;
+  }
+  for (int k = k0; k < c->cfg.nu1 * steps; ++k) {
     const bool first_check = check && k == 0 && !gs_check;
     int np = 0;
     if (rb3)

@@ -721,3 +721,28 @@ def test_c5_1025_galerkin_w22_match_exact():
     t = torch()
     rel = (t.linalg.vector_norm(out[1] - out[0]) / t.linalg.vector_norm(out[0])).item()
     assert rel <= 1e-9, rel
+
+
+@pytest.mark.parametrize("n,coarse,order,nu1,precision", [(65, 0, 4, 2, 0), (65, 1, 4, 2, 0), (129, 1, 4, 2, 1),
+                                                          (65, 0, 6, 2, 0), (65, 3, 6, 3, 1), (33, 1, 4, 3, 0)])
+def test_two_sweeps_from_zero_in_one_pass(n, coarse, order, nu1, precision, monkeypatch):
+    """3D levels entered with a zero iterate take their first two omega-Jacobi sweeps in
+    one pass (the first sweep's omega / a0 * f formed on the fly): the same cycles, bit
+    for bit, as two passes (MG_Z2=0), and the oracle's to 1e-12 in FP64."""
+    f = inputs.smoothed_noise_3d(n)
+    out = {}
+    for z2 in ("0", "1"):
+        monkeypatch.setenv("MG_Z2", z2)
+        H = Handle(3, n, coarse=coarse, order=order, nu1=nu1, nu2=2, gamma=2, precision=precision,
+                   inner_cycles=1)
+        try:
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            st, res = mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), 3)
+            out[z2] = host(ud)
+            if z2 == "1" and precision == 0:
+                u_ref = np.zeros_like(f)
+                H.oracle.solve(u_ref, f, rtol=0.0, max_cycles=3)
+                assert np.linalg.norm(out[z2] - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        finally:
+            H.close()
+    assert np.array_equal(out["0"], out["1"])
