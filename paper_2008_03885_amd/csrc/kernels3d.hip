@@ -466,7 +466,9 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
 // register-ring rules as the cross sweep).  One barrier per plane.  Every value is the
 // odd extension across the Dirichlet boundary (reflection keeps a point's colour), so
 // frame columns outside the grid hold the odd extension of the red results.
-template <typename T, bool HAS_U, int XW, int YW>
+// J2: the same pass with both steps over every point, i.e. two omega-Jacobi sweeps (the
+// first on plane z and the frame, the second two planes behind on the tile).
+template <typename T, bool HAS_U, int XW, int YW, bool J2 = false>
 __global__ __launch_bounds__((XW + 4) * (YW + 4)) void k_rbxsweep3d(const T *__restrict__ f, const T *__restrict__ u,
                                                                      T *__restrict__ out, int n, int zchunk,
                                                                      KOp<T> op, double *__restrict__ partials,
@@ -564,7 +566,7 @@ __global__ __launch_bounds__((XW + 4) * (YW + 4)) void k_rbxsweep3d(const T *__r
       const T r = fz - lu;
       if (partials != nullptr && own && xin && z >= z0 && z < z1 && z > 0 && z < n - 1)
         acc += (double)r * (double)r;
-      const T v = uc + (((x + y + z) & 1) != 0 ? kop.om_d : T(0)) * r;
+      const T v = uc + ((J2 || ((x + y + z) & 1) != 0) ? kop.om_d : T(0)) * r;
       vr[(P + 4) % kZR] = v;
       red[(z % 4 + 4) % 4][tid] = v;
       // black step on plane z-2 from the red results (in-plane: written two planes ago)
@@ -576,7 +578,7 @@ __global__ __launch_bounds__((XW + 4) * (YW + 4)) void k_rbxsweep3d(const T *__r
                    kop.w2 * (((vc - rp[qm2]) + (vc - rp[qp2])) + ((vc - rp[qmy2]) + (vc - rp[qpy2])) +
                              ((vc - vr[P % kZR]) + (vc - vr[(P + 4) % kZR])));
       const bool inside = xin && zb > 0 && zb < n - 1;
-      const T w = inside ? vc + (((x + y + zb) & 1) == 0 ? kop.om_d : T(0)) * (fb - lb) : T(0);
+      const T w = inside ? vc + ((J2 || ((x + y + zb) & 1) == 0) ? kop.om_d : T(0)) * (fb - lb) : T(0);
       if (own && zb >= z0 && zb < z1) out[((size_t)zb * n + y) * n + x] = w;
     };
     for (int z = zs; z <= zlast; z += kZR)
@@ -1833,6 +1835,30 @@ hipError_t launch_rbsweep_3d(const LevelOp &op, double omega, const T *f, const 
   return hipGetLastError();
 }
 
+// Two omega-Jacobi sweeps of the cross in one pass (the red-black pass with both steps over
+// every point).
+template <typename T>
+hipError_t launch_x2sweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
+                             double *partials, int *nparts, const int *done, hipStream_t s) {
+  if (!op.cross) return hipErrorInvalidValue;
+  // the red-black pass's 60 x 8 tiles, 768 threads
+  constexpr int xw = 60, yw = 8, nt = (xw + 4) * (yw + 4);
+  const void *fn = u != nullptr ? (const void *)k_rbxsweep3d<T, true, xw, yw, true> : (const void *)k_rbxsweep3d<T, false, xw, yw, true>;
+  const int tiles = cdiv(n, xw) * cdiv(n, yw);
+  // bands of at least 32 planes: every band takes four extra first-sweep planes
+  const int zc = std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, nt, 0), 32));
+  const dim3 grid(cdiv(n, xw), cdiv(n, yw), cdiv(n, zc));
+  if (nparts) *nparts = grid.x * grid.y * grid.z;
+  const KOp<T> k = to_kop3<T>(op, omega);
+#define MG_RB3(HU, W, H) hipLaunchKernelGGL((k_rbxsweep3d<T, HU, W, H, true>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+  if (u != nullptr)
+    MG_RB3(true, xw, yw);
+  else
+    MG_RB3(false, xw, yw);
+#undef MG_RB3
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s) {
@@ -1952,6 +1978,10 @@ template hipError_t launch_sweep_3d<double, float>(int, const LevelOp &, double,
 template hipError_t launch_rbsweep_3d<double>(const LevelOp &, double, const double *, const double *,
                                               double *, int, double *, int *, const int *, hipStream_t);
 template hipError_t launch_rbsweep_3d<float>(const LevelOp &, double, const float *, const float *,
+                                             float *, int, double *, int *, const int *, hipStream_t);
+template hipError_t launch_x2sweep_3d<double>(const LevelOp &, double, const double *, const double *,
+                                              double *, int, double *, int *, const int *, hipStream_t);
+template hipError_t launch_x2sweep_3d<float>(const LevelOp &, double, const float *, const float *,
                                              float *, int, double *, int *, const int *, hipStream_t);
 template hipError_t launch_resid_restrict_3d<double>(const LevelOp &, const double *,
                                                      const double *, double *, int, const int *,

@@ -182,6 +182,10 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 template <typename T>
 hipError_t launch_rbsweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
                              double *partials, int *nparts, const int *done, hipStream_t s);
+// two omega-Jacobi sweeps of the cross in one pass (out of place)
+template <typename T>
+hipError_t launch_x2sweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
+                             double *partials, int *nparts, const int *done, hipStream_t s);
 template <typename T>
 hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T *fc, int n,
                                     const int *done, hipStream_t s);

@@ -536,6 +536,15 @@ hipError_t resid_restrict(mg_ctx *c, int l, const T *f, const T *u, T *scratch, 
   return mgk::launch_restrict_cubic<T>(c->dim, scratch, fc, c->ns[l], done, s, c->slots);
 }
 
+// Two omega-Jacobi sweeps of a 3D cross level in one pass: FP64 by default; MG_X2=0 or 1
+// sets both precisions.
+template <typename T>
+bool x2_enabled() {
+  const char *e = std::getenv("MG_X2");
+  if (e != nullptr && *e != 0) return std::atoi(e) != 0;
+  return sizeof(T) == 8;
+}
+
 // Two omega-Jacobi sweeps from a zero iterate in one 3D pass unless MG_Z2=0.
 bool z2_enabled() {
   const char *e = std::getenv("MG_Z2");
@@ -730,10 +739,17 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     zero = false;
     k0 = 2;
   }
+  // two omega-Jacobi sweeps of a 3D cross level in one pass where two remain (FP64: 1025^3
+  // 10.8 ms against two sweeps of 6.27; in FP32 the pass takes 7.74 ms against 2 x 3.58)
+  const bool x2 = !rb && !rb3 && dim == 3 && op.cross && x2_enabled<T>();
   for (int k = k0; k < c->cfg.nu1 * steps; ++k) {
     const bool first_check = check && k == 0 && !gs_check;
     int np = 0;
-    if (rb3)
+    if (x2 && c->cfg.nu1 * steps - k >= 2) {
+      e = mgk::launch_x2sweep_3d<T>(op, c->omega, f, zero ? nullptr : cur, other, n,
+                                    first_check ? c->partials : nullptr, &np, done, s);
+      ++k;  // the pass took two sweeps
+    } else if (rb3)
       e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, zero ? nullptr : cur, other, n,
                                     first_check ? c->partials : nullptr, &np, done, s);
     else if (rb)
@@ -767,13 +783,18 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
       if (e != hipSuccess) return e;
     }
   }
-  T *dst = ((c->cfg.nu2 * steps) % 2 == 0) ? u : t;
+  // the passes of the post-smoothing alternate between t and u and end in u
+  const int npost = c->cfg.nu2 * steps, passes = x2 ? npost / 2 + npost % 2 : npost;
+  T *dst = (passes % 2 == 0) ? u : t;
   e = mgk::launch_prolong_correct<T>(dim, c->cfg.prolong, uc, cur, dst, n, done, s, c->slots);
   if (e != hipSuccess) return e;
   cur = dst;
   other = (dst == u) ? t : u;
-  for (int k = 0; k < c->cfg.nu2 * steps; ++k) {
-    if (rb3)
+  for (int k = 0; k < npost; ++k) {
+    if (x2 && npost - k >= 2) {
+      e = mgk::launch_x2sweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
+      ++k;
+    } else if (rb3)
       e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
     else if (rb)
       e = partial_step<T>(c, l, 1 + k % 2, f, cur, other, nullptr, nullptr, s);

@@ -746,3 +746,29 @@ def test_two_sweeps_from_zero_in_one_pass(n, coarse, order, nu1, precision, monk
         finally:
             H.close()
     assert np.array_equal(out["0"], out["1"])
+
+
+@pytest.mark.parametrize("n,coarse,nu1,nu2,gamma,precision", [(65, 0, 2, 2, 2, 0), (65, 1, 2, 1, 1, 0),
+                                                             (129, 1, 2, 2, 2, 1), (65, 0, 3, 3, 1, 0),
+                                                             (33, 0, 4, 2, 2, 0)])
+def test_two_jacobi_sweeps_in_one_pass(n, coarse, nu1, nu2, gamma, precision, monkeypatch):
+    """Pairs of omega-Jacobi sweeps on 3D cross levels run as one pass (the first sweep
+    on a plane and its frame, the second two planes behind; MG_X2=1 turns it on for FP32
+    too): the cycles of one sweep per pass (MG_X2=0) and the oracle's, to rounding."""
+    f = inputs.smoothed_noise_3d(n)
+    out = {}
+    for x2 in ("0", "1"):
+        monkeypatch.setenv("MG_X2", x2)
+        H = Handle(3, n, coarse=coarse, nu1=nu1, nu2=nu2, gamma=gamma, precision=precision, inner_cycles=1)
+        try:
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), 3)
+            out[x2] = host(ud)
+            if x2 == "1" and precision == 0:
+                u_ref = np.zeros_like(f)
+                H.oracle.solve(u_ref, f, rtol=0.0, max_cycles=3)
+                assert np.linalg.norm(out[x2] - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        finally:
+            H.close()
+    tol = 1e-13 if precision == 0 else 1e-6
+    assert np.linalg.norm(out["1"] - out["0"]) <= tol * np.linalg.norm(out["0"])
