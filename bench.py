@@ -59,9 +59,9 @@ MEASURED_TRAFFIC = {
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
     # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
     "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
-    # 1025^3 level 0 FP32 sweep (64 x 16 tiles, two rows per thread): 6,373,646.8 KiB
-    # x 2.0000 + 4,728,717.2 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/1025": {"bytes": 17895242109, "source": "98ce2c42848a5ab2"},
+    # 1025^3 level 0 FP32 sweep (64 x 16 tiles, two rows per thread): 6,375,405.5 KiB
+    # x 2.0000 + 4,728,004.8 KiB x 1.0000
+    "k_sweep3d/f32/kernels3d.hip/1025": {"bytes": 17898113131, "source": "8f3bee0671863744"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
     "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "11dcfa18322facea"},
