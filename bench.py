@@ -58,10 +58,10 @@ MEASURED_TRAFFIC = {
     # 156,850.3 KiB x 2.0000 + 168,329.4 KiB x 1.0000
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
     # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
+    "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
     # 1025^3 level 0 FP32 sweep (64 x 16 tiles, two rows per thread): 6,375,405.5 KiB
     # x 2.0000 + 4,728,004.8 KiB x 1.0000
-    "k_sweep3d/f32/kernels3d.hip/1025": {"bytes": 17898113131, "source": "8f3bee0671863744"},
+    "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 17898113131, "source": "8f3bee0671863744"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
     "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "11dcfa18322facea"},
@@ -304,11 +304,12 @@ def level_kernels(run, w, stream, reps, only_level0=False):
             ]
         elif rb and d == 3:
             # 3D red-black smoothing: two partial-step launches per sweep
+            sep = l > 0 and w["coarse"] in (1, 3)
             ks = [
-                ("k_sweep%dd" % d, "red-black partial step", 3 * P * b,
+                ("k_gpen3d" if sep else "k_xsweep3d", "red-black partial step", 3 * P * b,
                  lambda: mg.mg_kernel_smooth_colour(run.h, l, fp32, 1, f.data_ptr(), u.data_ptr(),
                                                     t.data_ptr())),
-                ("k_resid_restrict%dd" % d, "defect+FW", (2 * P + Pc) * b,
+                ("k_grr3d" if sep else "k_xrr3d", "defect+FW", (2 * P + Pc) * b,
                  lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
                                                         fc.data_ptr())),
                 ("k_prolong%dd" % d, "interp+correct", (2 * P + Pc) * b,
@@ -328,10 +329,13 @@ def level_kernels(run, w, stream, reps, only_level0=False):
                                                          f.data_ptr(), t.data_ptr())),
             ]
         else:
+            # level 0 and rediscretized levels: the cross kernels; Galerkin levels: the
+            # pencil sweep and the separable defect kernel
+            sep = l > 0 and w["coarse"] in (1, 3)
             ks = [
-                ("k_sweep3d", "omega-Jacobi sweep", 3 * P * b,
+                ("k_gpen3d" if sep else "k_xsweep3d", "omega-Jacobi sweep", 3 * P * b,
                  lambda: mg.mg_kernel_smooth(run.h, l, fp32, f.data_ptr(), u.data_ptr(), t.data_ptr())),
-                ("k_resid_restrict3d", "defect+FW", (2 * P + Pc) * b,
+                ("k_grr3d" if sep else "k_xrr3d", "defect+FW", (2 * P + Pc) * b,
                  lambda: mg.mg_kernel_residual_restrict(run.h, l, fp32, f.data_ptr(), u.data_ptr(),
                                                         fc.data_ptr())),
                 ("k_prolong3d", "interp+correct", (2 * P + Pc) * b,
@@ -674,7 +678,7 @@ def time_workload(w, args, stream, fd, label, variants_2d=False):
         out["config_variants"] = config_variants_2d(w, fd, stream, sec, res)
     rows = [] if args.no_levels else level_kernels(main_run, w, stream, args.kernel_reps)
     rb = bool(w.get("smoother", 0))
-    dom_name = ("k_gs2d" if w.get("smoother", 0) == 2 else "k_pre2d") if d == 2 else "k_sweep3d"
+    dom_name = ("k_gs2d" if w.get("smoother", 0) == 2 else "k_pre2d") if d == 2 else "k_xsweep3d"
     dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
     if not dom:
         dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)

@@ -51,185 +51,6 @@ __device__ double block_sum(double v) {
 }
 __device__ double block_sum256(double v) { return block_sum<256>(v); }
 
-// Cooperative loader of one z-plane of a PX x PY region with origin (gx0, gy0): each
-// thread owns up to Q positions; their (x, y) reflection is fixed, the z part is
-// applied per plane.
-template <typename T, int PX, int PY>
-struct PlaneLoader {
-  static constexpr int NP = PX * PY;
-  static constexpr int Q = (NP + 255) / 256;
-  int off[Q];   // y*n + x of the folded position (valid address)
-  T mul[Q];     // sign of the xy reflection, 0 for boundary / far positions
-  int n;
-  __device__ void init(int gx0, int gy0, int n_) {
-    n = n_;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int px = e % PX, py = e / PX;
-      int s = 1;
-      const int xf = fold(gx0 + px, n, s), yf = fold(gy0 + py, n, s);
-      const bool ok = e < NP && xf > 0 && xf < n - 1 && yf > 0 && yf < n - 1;
-      off[q] = ok ? yf * n + xf : n + 1;
-      mul[q] = ok ? T(s) : T(0);
-    }
-  }
-  // raw loads of plane z (valid addresses always)
-  __device__ void load(const T *p, int z, T (&raw)[Q]) const {
-    int s = 1;
-    int zf = fold(z, n, s);
-    zf = (zf > 0 && zf < n - 1) ? zf : 1;
-    const T *base = p + (size_t)zf * n * n;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) raw[q] = base[off[q]];
-  }
-  // store the odd-extended values of plane z into dst (PX*PY, row-major)
-  __device__ void store(T *dst, int z, const T (&raw)[Q]) const {
-    int s = 1;
-    const int zf = fold(z, n, s);
-    const T zm = (zf > 0 && zf < n - 1) ? T(s) : T(0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      if (e < NP) dst[e] = (mul[q] * zm != T(0)) ? raw[q] * (mul[q] * zm) : T(0);
-    }
-  }
-};
-
-// Separable operator on the region's inner part: given the ring of 7 planes, compute
-// L u for every (px, py) with E <= px < PX-E, E <= py < PY-E (E = 3) into out (same
-// pitch).  Uses scratch arrays zb, za (PX*PY) and yb, ys (PX*PY).  Barriers inside.
-template <typename T, int PX, int PY>
-__device__ void sep_lu_plane(const T *ring, int plane_sz, const int (&slot)[7], const KOp<T> &op,
-                             T *zb, T *za, T *t1, T *t2, T *out) {
-  constexpr int NP = PX * PY;
-  // z pass over the whole region
-  for (int e = threadIdx.x; e < NP; e += 256) {
-    const T c = ring[slot[3] * plane_sz + e];
-    T A = T(0), B = T(0);
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      const T v = ring[slot[k] * plane_sz + e];
-      if (k != 3) A += op.a[k] * (v - c);
-      B += op.b[k] * v;
-    }
-    zb[e] = B;
-    za[e] = A;
-  }
-  __syncthreads();
-  // y pass over rows 3..PY-4 (all columns)
-  for (int e = threadIdx.x; e < NP; e += 256) {
-    const int py = e / PX;
-    if (py < 3 || py >= PY - 3) continue;
-    const T bc = zb[e];
-    T s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      const T bz = zb[e + (j - 3) * PX];
-      s1 += op.b[j] * bz;                               // b_y b_z u
-      if (j != 3) s2 += op.a[j] * (bz - bc);             // a_y b_z u
-      s3 += op.b[j] * za[e + (j - 3) * PX];              // b_y a_z u
-    }
-    t1[e] = s1;
-    t2[e] = s2 + s3;
-  }
-  __syncthreads();
-  // x pass for the inner points
-  for (int e = threadIdx.x; e < NP; e += 256) {
-    const int px = e % PX, py = e / PX;
-    if (py < 3 || py >= PY - 3 || px < 3 || px >= PX - 3) continue;
-    const T c1 = t1[e];
-    T lu = T(0);
-#pragma unroll
-    for (int i = 0; i < 7; ++i) {
-      if (i != 3) lu += op.a[i] * (t1[e + i - 3] - c1);
-      lu += op.b[i] * t2[e + i - 3];
-    }
-    out[e] = lu;
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------- plane-ring sweep (Galerkin levels) ----
-// The second implementation of the radius-3 separable operator (MG_G3_OLD=1): an LDS
-// ring of 2R+1 haloed planes, the operator applied plane by plane with sep_lu_plane.
-template <typename T, typename TO, int MODE, int R>
-__global__ __launch_bounds__(256) void k_sweep3d(const T *__restrict__ f, const T *__restrict__ u,
-                                                 TO *__restrict__ out, int n, int zchunk, KOp<T> op,
-                                                 double *__restrict__ partials,
-                                                 const int *__restrict__ done) {
-  static_assert(R == 3, "separable radius-3 operators only");
-  constexpr int W = 2 * R + 1;
-  constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
-  extern __shared__ __align__(16) unsigned char smem3[];
-  T *ring = reinterpret_cast<T *>(smem3);
-  T *zb = ring + W * PS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
-  if (stopped(done)) return;
-  const Block3 blk = block3();
-  const int x0 = blk.x * TX, y0 = blk.y * TY;
-  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool own = x <= n - 1 && y <= n - 1;
-  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
-  const bool zero_u = u == nullptr;
-  PlaneLoader<T, PX, PY> ld;
-  ld.init(x0 - R, y0 - R, n);
-  using Raw = T[PlaneLoader<T, PX, PY>::Q];
-  Raw nxt;
-  const T *up = zero_u ? f : u;
-  // fill the ring with planes z0-R .. z0+R-1 (zeros for a zero initial guess)
-  if (zero_u) {
-    for (int e = threadIdx.x; e < W * PS; e += 256) ring[e] = T(0);
-  } else {
-    for (int k = 0; k < 2 * R; ++k) {
-      Raw r;
-      ld.load(up, z0 - R + k, r);
-      ld.store(ring + k * PS, z0 - R + k, r);
-    }
-  }
-  ld.load(up, z0 + R, nxt);
-  // f at this thread's column, address always valid
-  const size_t fcol = (size_t)(own && xin ? y : 1) * n + (own && xin ? x : 1);
-  double acc = 0.0;
-  int head = 0;  // ring slot of plane z - R
-  for (int z = z0; z < z1; ++z) {
-    // plane z + R into the slot after the newest
-    const int ns = (head + 2 * R) % W;
-    if (!zero_u) ld.store(ring + ns * PS, z + R, nxt);
-    if (!zero_u) ld.load(up, z + R + 1, nxt);
-    const T fraw = f[(size_t)(z > 0 && z < n - 1 ? z : 1) * n * n + fcol];
-    __syncthreads();
-    const T fv = (own && xin && z > 0 && z < n - 1) ? fraw : T(0);
-    T lu;
-    const int p = (ty + R) * PX + (tx + R);
-    {
-      int slot[7];
-#pragma unroll
-      for (int k = 0; k < 7; ++k) slot[k] = (head + k) % W;
-      sep_lu_plane<T, PX, PY>(ring, PS, slot, op, zb, za, t1, t2, lo);
-      lu = zero_u ? T(0) : lo[p];
-    }
-    const T uc = ring[((head + R) % W) * PS + p];
-    const bool inside = own && xin && z > 0 && z < n - 1;
-    const T r = inside ? fv - lu : T(0);
-    if (inside) acc += (double)r * (double)r;
-    if (own) {
-      const size_t id = ((size_t)z * n + y) * n + x;
-      if (MODE == kSweep || MODE == kSweepRB)
-        out[id] = (TO)(inside ? uc + (MODE == kSweepRB ? colour_om(op, x + y + z) : op.om_d) * r : T(0));
-      if (MODE == kResidual) out[id] = (TO)r;
-    }
-    head = (head + 1) % W;
-    __syncthreads();
-  }
-  if (partials != nullptr) {
-    const double tot = block_sum256(acc);
-    if (threadIdx.x == 0)
-      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
-  }
-}
-
 // ----------------------------------------------- cross sweep, z windows in registers ----
 // The radius-2 cross operator (rediscretized levels).  Each thread keeps the u values of
 // its own column at planes z-2 .. z+5 in a ring of registers; only plane z of the tile and
@@ -594,187 +415,6 @@ __global__ __launch_bounds__((XW + 4) * (YW + 4)) void k_rbxsweep3d(const T *__r
   }
 }
 
-// ------------------------------------------- separable (Galerkin) sweep, z rings ----
-// Coarse Galerkin operators are sums of three tensor products of 1D stencils of radius 3,
-// L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as
-//   L u(z) = sum_k b_k P1(z+k) + sum_{k != 0} a_k (P2(z+k) - P2(z)),
-//   P1 = a_x (b_y u) + b_x (a_y u),  P2 = b_x (b_y u)   (in-plane, per plane),
-// each a-stencil in difference form (its coefficients sum to zero).  A block owns an
-// XW x TY tile of columns, one per thread.  Plane q = z+3 of the tile plus a three-point
-// halo goes through LDS; the y pass (b_y u and a_y u over the tile rows and all halo
-// columns) and the x pass give P1(q) and P2(q) at this thread's column, which enter
-// register rings of eight planes; the z pass over the rings completes L u(z).  The u of
-// the own column, the halo cell and f are loaded ahead into register rings as in the
-// cross sweep (same register-ring rules).
-template <typename T, typename TO, int MODE, int XW>
-__global__ __launch_bounds__(XW * TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_gsweep3d(const T *__restrict__ f, const T *__restrict__ u,
-                                                     TO *__restrict__ out, int n, int zchunk, KOp<T> op,
-                                                     double *__restrict__ partials,
-                                                     const int *__restrict__ done) {
-  constexpr int NT = XW * TY, R = 3, PX = XW + 2 * R, PY = TY + 2 * R, PS = PX * PY;
-  constexpr int NH = PS - NT;   // halo cells of a plane
-  constexpr int NYO = PX * TY;  // y-pass outputs: all region columns, the tile's rows
-  static_assert(NH <= NT && NYO <= 2 * NT, "one halo cell and at most two y outputs per thread");
-  __shared__ T upl[PS];
-  __shared__ T yb[NYO], ya[NYO];
-  if (stopped(done)) return;
-  const Block3 blk = block3();
-  const int x0 = blk.x * XW, y0 = blk.y * TY;
-  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
-  const int t = threadIdx.x;
-  const int tx = t % XW, ty = t / XW;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool own = x <= n - 1 && y <= n - 1;
-  const bool xin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
-  Col3<T> cu, ch;
-  cu.init(x, y, n);
-  int hx = 0, hy = 0;
-  const bool has_halo = t < NH;
-  if (t < R * PX) {
-    hy = t / PX;
-    hx = t % PX;
-  } else if (t < 2 * R * PX) {
-    hy = PY - R + (t - R * PX) / PX;
-    hx = (t - R * PX) % PX;
-  } else {
-    const int hh = t - 2 * R * PX;
-    hy = R + hh / (2 * R);
-    const int c = hh % (2 * R);
-    hx = c < R ? c : PX - 2 * R + c;
-  }
-  if (has_halo)
-    ch.init(x0 - R + hx, y0 - R + hy, n);
-  else
-    ch = cu;
-  const int pown = (ty + R) * PX + tx + R, phal = hy * PX + hx;
-  const size_t fcol = (size_t)(xin ? y : 1) * n + (xin ? x : 1);
-  // y-pass items of this thread: e = t and t + NT (region column e % PX, tile row e / PX)
-  const bool y2 = t + NT < NYO;
-  const int ye0 = (t / PX + R) * PX + t % PX, ye1 = y2 ? ((t + NT) / PX + R) * PX + (t + NT) % PX : ye0;
-  const int xo = ty * PX + tx + R;  // this column in the y-pass outputs
-  const int zlast = z0 + round_up8(z1 - z0) - 1;
-  const bool fast = z0 - R > 0 && zlast + 8 < n - 1;
-
-  double acc = 0.0;
-  auto run = [&](auto fast_tag) {
-    constexpr bool FAST = decltype(fast_tag)::value;
-    auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
-    auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
-    const KOp<T> kop = op;
-    // ring slots: u and P rings by (plane - (z0-3)) mod 8, halo by the same mod 4, f by
-    // (plane - z0) mod 4
-    T ur[8], hr[4], fr[4], p1r[8], p2r[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ur[k] = u[base(z0 - R + k) + cu.off];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      hr[k] = u[base(z0 - R + k) + ch.off];
-      fr[k] = f[base(z0 + k) + fcol];
-    }
-    hold_regs(ur);
-    hold_regs(hr);
-    hold_regs(fr);
-    // P1(q), P2(q) at this column from plane q (own value uq, halo value hq)
-    auto inplane = [&](T uq, T hq, T &p1, T &p2) {
-      upl[pown] = uq;
-      if (has_halo) upl[phal] = hq;
-      __syncthreads();
-      {
-        const T c = upl[ye0];
-        T sb = T(0), sa = T(0);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-          const T v = upl[ye0 + (j - 3) * PX];
-          sb += kop.b[j] * v;
-          if (j != 3) sa += kop.a[j] * (v - c);
-        }
-        yb[t] = sb;
-        ya[t] = sa;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if (y2) {
-        const T c = upl[ye1];
-        T sb = T(0), sa = T(0);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-          const T v = upl[ye1 + (j - 3) * PX];
-          sb += kop.b[j] * v;
-          if (j != 3) sa += kop.a[j] * (v - c);
-        }
-        yb[t + NT] = sb;
-        ya[t + NT] = sa;
-      }
-      __syncthreads();
-      const T c1 = yb[xo];
-      T s1 = T(0), s2 = T(0);
-#pragma unroll
-      for (int i = 0; i < 7; ++i) {
-        const T vb = yb[xo + i - 3];
-        if (i != 3) s1 += kop.a[i] * (vb - c1);
-        s1 += kop.b[i] * ya[xo + i - 3];
-        s2 += kop.b[i] * vb;
-      }
-      p1 = s1;
-      p2 = s2;
-    };
-    // prologue: P of planes z0-3 .. z0+2 (slots 0..5); the u slots of planes z0-3 .. z0-1
-    // are refilled with planes z0+5 .. z0+7, the halo ring runs ahead by four planes
-    static_for<6>([&](auto kc) {
-      constexpr int K = decltype(kc)::value;
-      const int q = z0 - R + K;
-      T uq = ur[K] * (cu.mul * zm(q)), hq = hr[K % 4] * (ch.mul * zm(q));
-      asm volatile("" : "+v"(uq), "+v"(hq));
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (K < 3) ur[K] = u[base(q + 8) + cu.off];
-      hr[K % 4] = u[base(q + 4) + ch.off];
-      inplane(uq, hq, p1r[K], p2r[K]);
-    });
-    hold_regs(ur);
-    hold_regs(hr);
-    const T fmask = xin ? T(1) : T(0);
-    auto step = [&](const int z, auto pc) {
-      constexpr int P = decltype(pc)::value;  // z - z0 mod 8
-      constexpr int SQ = (P + 6) % 8, SZ = (P + 3) % 8, SH = (P + 2) % 4, SF = P % 4;
-      const T m = cu.mul;
-      T uq = ur[SQ] * (m * zm(z + R)), hq = hr[SH] * (ch.mul * zm(z + R));
-      T uz = ur[SZ] * (m * zm(z)), fz = fr[SF] * fmask;
-      asm volatile("" : "+v"(uq), "+v"(hq), "+v"(uz), "+v"(fz));
-      __builtin_amdgcn_sched_barrier(0);
-      ur[SZ] = u[base(z + 8) + cu.off];
-      hr[SH] = u[base(z + R + 4) + ch.off];
-      fr[SF] = f[base(z + 4) + fcol];
-      inplane(uq, hq, p1r[SQ], p2r[SQ]);
-      // z pass: planes z-3 .. z+3 sit in slots P .. P+6
-      const T c2 = p2r[SZ];
-      T lu = T(0);
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        lu += kop.b[k] * p1r[(P + k) % 8];
-        if (k != 3) lu += kop.a[k] * (p2r[(P + k) % 8] - c2);
-      }
-      const bool inside = own && xin && z > 0 && z < n - 1;
-      const T r = inside ? fz - lu : T(0);
-      if (partials != nullptr && inside && z < z1) acc += (double)r * (double)r;
-      // every lane stores (clamped address; see the cross sweep)
-      const size_t id = ((size_t)min(z, n - 1) * n + min(y, n - 1)) * n + min(x, n - 1);
-      if (MODE == kSweep || MODE == kSweepRB)
-        out[id] = (TO)(inside ? uz + (MODE == kSweepRB ? colour_om(kop, x + y + z) : kop.om_d) * r : T(0));
-      if (MODE == kResidual) out[id] = (TO)r;
-    };
-    for (int z = z0; z < z1; z += 8)
-      static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
-  };
-  if (fast)
-    run(std::true_type{});
-  else
-    run(std::false_type{});
-  if (partials != nullptr) {
-    const double tot = block_sum<NT>(acc);
-    if (threadIdx.x == 0)
-      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
-  }
-}
-
 // Values of the neighbouring lanes across the whole wavefront (DPP wavefront shifts):
 // lane_prev gives lane L the value of lane L-1, lane_next that of lane L+1; the lane with
 // no neighbour gets 0.
@@ -794,9 +434,12 @@ __device__ __forceinline__ double lane_next(double v) {
 }
 
 // ------------------------------- separable (Galerkin) sweep, wavefront pencils ----
-// The operator of the Galerkin levels (as above, L u(z) = sum_k b_k P1(z+k) + sum_{k != 0}
-// a_k (P2(z+k) - P2(z)) with the in-plane P1 = a_x (b_y u) + b_x (a_y u), P2 = b_x (b_y u))
-// without LDS and without barriers: every wavefront works alone on a pencil of YR rows
+// Coarse Galerkin operators are sums of three tensor products of 1D stencils of radius 3,
+// L = a_x b_y b_z + b_x a_y b_z + b_x b_y a_z, applied as
+//   L u(z) = sum_k b_k P1(z+k) + sum_{k != 0} a_k (P2(z+k) - P2(z)),
+//   P1 = a_x (b_y u) + b_x (a_y u),  P2 = b_x (b_y u)   (in-plane, per plane),
+// each a-stencil in difference form (its coefficients sum to zero).  This kernel applies
+// it without LDS and without barriers: every wavefront works alone on a pencil of YR rows
 // and 64 columns, of which the middle 58 are its outputs (three columns of x halo on
 // each side).  Per plane a lane loads its column at the YR rows and three rows of y halo
 // on each side, applies b_y and a_y in registers, and takes the x neighbours of b_y u and
@@ -972,108 +615,6 @@ __global__ __launch_bounds__(256) void k_gpen3d(const T *__restrict__ f, const T
   }
 }
 
-// ------------------------ plane-ring defect + full weighting (Galerkin levels) ----
-// The second implementation (MG_G3_OLD=1).  Block: coarse tile (TX/2) x (TY/2) at coarse
-// planes [K0, K1).  The defect is computed on the fine tile extended by one point (the
-// full-weighting support), kept for three fine planes in LDS, and restricted in z, y and x.
-template <typename T, int R>
-__global__ __launch_bounds__(256) void k_resid_restrict3d(const T *__restrict__ f,
-                                                          const T *__restrict__ u,
-                                                          T *__restrict__ fc, int n, int kchunk,
-                                                          KOp<T> op, const int *__restrict__ done) {
-  static_assert(R == 3, "separable radius-3 operators only");
-  constexpr int W = 2 * R + 1;
-  constexpr int E = R + 1;  // halo of the u region: stencil plus the restriction support
-  constexpr int PX = TX + 2 * E, PY = TY + 2 * E, PS = PX * PY;
-  constexpr int RX = TX + 2, RY = TY + 2, RS = RX * RY;  // defect region
-  extern __shared__ __align__(16) unsigned char smem3[];
-  T *ring = reinterpret_cast<T *>(smem3);
-  T *rr = ring + W * PS;  // three defect planes
-  T *zb = rr + 3 * RS, *za = zb + PS, *t1 = za + PS, *t2 = t1 + PS, *lo = t2 + PS;
-  if (stopped(done)) return;
-  const int nc = (n - 1) / 2 + 1;
-  const Block3 blk = block3();
-  const int x0 = blk.x * TX, y0 = blk.y * TY;  // fine origin (even)
-  const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
-  const bool zero_u = u == nullptr;
-  PlaneLoader<T, PX, PY> ld;
-  ld.init(x0 - E, y0 - E, n);
-  using Raw = T[PlaneLoader<T, PX, PY>::Q];
-  Raw nxt;
-  const T *up = zero_u ? f : u;
-  // coarse points of this thread: (I, J) = (x0/2 + ci, y0/2 + cj), ci < TX/2, cj < TY/2
-  const int ci = threadIdx.x % (TX / 2), cj = threadIdx.x / (TX / 2);
-  const int I = x0 / 2 + ci, J = y0 / 2 + cj;
-  const bool cown = threadIdx.x < (TX / 2) * (TY / 2) && I <= nc - 1 && J <= nc - 1;
-  const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
-  // boundary coarse planes
-  if (cown) {
-    if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
-    if (K1 == nc) fc[((size_t)(nc - 1) * nc + J) * nc + I] = T(0);
-  }
-  const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
-  if (Klo >= Khi) return;
-  const int zs = 2 * Klo - 1, ze = 2 * (Khi - 1) + 1;
-  if (zero_u) {
-    for (int e = threadIdx.x; e < W * PS; e += 256) ring[e] = T(0);
-  } else {
-    for (int k = 0; k < 2 * R; ++k) {
-      Raw r;
-      ld.load(up, zs - R + k, r);
-      ld.store(ring + k * PS, zs - R + k, r);
-    }
-  }
-  ld.load(up, zs + R, nxt);
-  int head = 0;
-  int rhead = 0;  // slot of the oldest defect plane
-  for (int z = zs; z <= ze; ++z) {
-    const int ns = (head + 2 * R) % W;
-    if (!zero_u) ld.store(ring + ns * PS, z + R, nxt);
-    if (!zero_u) ld.load(up, z + R + 1, nxt);
-    __syncthreads();
-    // defect on the RX x RY region (fine x0-1 .. x0+TX, y0-1 .. y0+TY) into the newest slot
-    T *rnew = rr + ((rhead + 2) % 3) * RS;
-    int slot7[7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) slot7[k] = (head + k) % W;
-    sep_lu_plane<T, PX, PY>(ring, PS, slot7, op, zb, za, t1, t2, lo);
-    for (int e = threadIdx.x; e < RS; e += 256) {
-      const int rx = e % RX, ry = e / RX;
-      const int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
-      const bool inside = gx > 0 && gx < n - 1 && gy > 0 && gy < n - 1 && z > 0 && z < n - 1;
-      T v = T(0);
-      if (inside) {
-        const int px = rx + (E - 1), py = ry + (E - 1);
-        const T lu = zero_u ? T(0) : lo[py * PX + px];
-        v = f[((size_t)z * n + gy) * n + gx] - lu;
-      }
-      rnew[e] = v;
-    }
-    __syncthreads();
-    // z = 2K+1 completes coarse plane K = (z-1)/2 (planes 2K-1, 2K, 2K+1 in the ring)
-    if (((z - zs) & 1) == 0 && z > zs) {
-      const int K = (z - 1) / 2;
-      if (cown) {
-        T s = T(0);
-        if (cin) {
-          const T *p0 = rr + (rhead % 3) * RS, *p1 = rr + ((rhead + 1) % 3) * RS,
-                  *p2 = rr + ((rhead + 2) % 3) * RS;
-          for (int oy = -1; oy <= 1; ++oy)
-            for (int ox = -1; ox <= 1; ++ox) {
-              const int e = (2 * cj + 1 + oy) * RX + (2 * ci + 1 + ox);
-              const T wxy = (ox == 0 ? T(0.5) : T(0.25)) * (oy == 0 ? T(0.5) : T(0.25));
-              s += wxy * (T(0.25) * p0[e] + T(0.5) * p1[e] + T(0.25) * p2[e]);
-            }
-        }
-        fc[((size_t)K * nc + J) * nc + I] = s;
-      }
-    }
-    head = (head + 1) % W;
-    rhead = (rhead + 1) % 3;
-    __syncthreads();
-  }
-}
-
 // ------------------------------------- cross defect + full weighting, z rings ----
 // The radius-2 cross operator.  A block owns a CX x CY tile of coarse columns and coarse
 // planes [K0, K1).  The full-weighting support of the tile is (2CX+1) x (2CY+1) fine
@@ -1225,10 +766,11 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
 }
 
 // ----------------------- separable (Galerkin) defect + full weighting, z rings ----
-// The defect of the separable operator (applied as in the separable sweep) on the
-// full-weighting support of a CX x CY coarse tile, restricted as in the cross kernel:
-// support columns one per thread, P1/P2 and defect rings in registers, z weighting per
-// column, x and y weighting through LDS after every odd fine plane.
+// The defect of the separable operator (the P1/P2 form of the pencil sweep, in-plane
+// passes through LDS) on the full-weighting support of a CX x CY coarse tile, restricted
+// as in the cross kernel: support columns one per thread, P1/P2 and defect rings in
+// registers, z weighting per column, x and y weighting through LDS after every odd fine
+// plane.
 template <typename T, int CX, int CY, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 void k_grr3d(const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc, int n,
@@ -1594,14 +1136,6 @@ int x3_ys(int mode) {
   return sizeof(T) == 8 && mode == kNormOnly ? 1 : 2;
 }
 
-template <typename T, typename TO>
-const void *gsweep3d_fn(int mode) {
-  if (mode == kSweep) return (const void *)k_gsweep3d<T, TO, kSweep, 64>;
-  if (mode == kSweepRB) return (const void *)k_gsweep3d<T, TO, kSweepRB, 64>;
-  if (mode == kResidual) return (const void *)k_gsweep3d<T, TO, kResidual, 64>;
-  return (const void *)k_gsweep3d<T, TO, kNormOnly, 64>;
-}
-
 // Rows per wavefront of the pencil sweep: 2 (FP32 126 VGPRs, four wavefronts per SIMD;
 // FP64 209); MG_GPEN_ROWS = 2 doubles them.  Measured at 513^3: FP32 two rows 571 us,
 // four 540 us, but four rows lose more on the smaller levels (257^3: 81 against 94 us);
@@ -1620,59 +1154,23 @@ const void *gpen3d_fn_rows(int mode) {
   if (mode == kResidual) return (const void *)k_gpen3d<T, TO, kResidual, YR>;
   return (const void *)k_gpen3d<T, TO, kNormOnly, YR>;
 }
-// The pencil kernel serves the separable sweeps unless MG_GPEN = 0 (then the LDS-tile
-// kernel k_gsweep3d).
-inline bool gsweep_pencils() {
-  const char *e = getenv("MG_GPEN");
-  return !(e != nullptr && atoi(e) == 0);
-}
-
-// The separable kernel serves the radius-3 operators unless MG_G3_OLD = 1 (the LDS-ring
-// kernel that applies them plane by plane, kept as a second implementation).
-inline bool gsweep_rings() {
-  const char *e = getenv("MG_G3_OLD");
-  return !(e != nullptr && atoi(e) == 1);
-}
-
 }  // namespace
 
 bool x3_r3();
 
 // Whether two sweeps from zero run in one pass on a level of this operator: the cross
-// kernels (radius 2 and 3) and the pencil kernel have the mode, the LDS-tile and plane-ring
-// kernels do not.
+// kernels (radius 2 and 3) and the pencil kernel all have the mode.
 bool sweep3d_z2_ok(const LevelOp &op) {
-  if (op.cross) return true;
-  if (op.cross3 && x3_r3()) return true;
-  return gsweep_rings() && gsweep_pencils();
+  (void)op;
+  return true;
 }
 
 namespace {
 
 template <typename T, typename TO>
-const void *sweep3d_fn(int mode, bool cross, bool has_u, int xw, int ys = 1) {
-  if (cross)
-    return xw == 64 ? (ys == 2 ? xsweep3d_fn<T, TO, 64, 2, 2>(mode, has_u) : xsweep3d_fn<T, TO, 64>(mode, has_u))
-                    : xsweep3d_fn<T, TO, 32>(mode, has_u);
-  if (gsweep_rings()) return gsweep3d_fn<T, TO>(mode);
-  if (mode == kSweep) return (const void *)k_sweep3d<T, TO, kSweep, 3>;
-  if (mode == kSweepRB) return (const void *)k_sweep3d<T, TO, kSweepRB, 3>;
-  if (mode == kResidual) return (const void *)k_sweep3d<T, TO, kResidual, 3>;
-  return (const void *)k_sweep3d<T, TO, kNormOnly, 3>;
-}
-
-template <typename T, int R>
-size_t sweep_smem() {
-  constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PS = PX * PY;
-  return sizeof(T) * (size_t)((2 * R + 1) * PS + (R == 3 ? 5 * PS : 0));
-}
-
-template <typename T, int R>
-size_t rr_smem() {
-  constexpr int E = R + 1;
-  constexpr int PX = TX + 2 * E, PY = TY + 2 * E, PS = PX * PY;
-  constexpr int RS = (TX + 2) * (TY + 2);
-  return sizeof(T) * (size_t)((2 * R + 1) * PS + 3 * RS + (R == 3 ? 5 * PS : 0));
+const void *sweep3d_fn(int mode, bool has_u, int xw, int ys = 1) {
+  return xw == 64 ? (ys == 2 ? xsweep3d_fn<T, TO, 64, 2, 2>(mode, has_u) : xsweep3d_fn<T, TO, 64>(mode, has_u))
+                  : xsweep3d_fn<T, TO, 32>(mode, has_u);
 }
 
 }  // namespace
@@ -1707,24 +1205,13 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     u = f;
   }
   // a zero initial guess needs no operator: the cross kernel's u-free path serves every
-  // operator (it uses om_d only)
+  // operator (it uses om_d only); radius-3 crosses (sixth order) take the cross kernel
+  // with R = 3 unless MG_X3_R3 = 0; every other operator the separable pencil kernel
   const bool xpath = op.cross || u == nullptr;
   const bool x3path = !xpath && op.cross3 && x3_r3();
-  const bool gpath = !xpath && !x3path && gsweep_rings();
-  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || gpath || x3path ? 64 : TX;
-  const int ys = xpath && xw == 64 ? x3_ys<T>(mode) : 1;  // rows per thread of the cross sweep
-  const int nt = xpath || gpath || x3path ? xw * TY : 256;
-  const int tiles = cdiv(n, xw) * cdiv(n, TY * ys);
-  const size_t smem = xpath || gpath || x3path ? 0 : sweep_smem<T, 3>();
-  const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, xpath, u != nullptr, xw, ys);
-  const int zr = x3path ? 16 : kZR;  // planes per loop turn of the kernel
-  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(occ_fn, nt, smem),
-                                                 kMinPlanes)) + zr - 1) / zr * zr;
-  const dim3 grid(cdiv(n, xw), cdiv(n, TY * ys), cdiv(n, zc));
-  if (nparts) *nparts = grid.x * grid.y * grid.z;
   KOp<T> k = to_kop3<T>(op, omega);
   k.colour = colour;
-  if (gpath && gsweep_pencils()) {
+  if (!xpath && !x3path) {
     constexpr int Y1 = gpen_rows<T>(), Y2 = 2 * gpen_rows<T>();
     const int yr = Y1 * gpen_rows_scale();
     const void *fn = yr == Y1 ? gpen3d_fn_rows<T, TO, Y1>(mode) : gpen3d_fn_rows<T, TO, Y2>(mode);
@@ -1748,16 +1235,16 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 #undef MG_GP
     return hipGetLastError();
   }
-  if (gpath) {
-    if (mode == kSweepZ2) return hipErrorInvalidValue;  // (sweep3d_z2_ok excludes this path)
-#define MG_G3(MODE) hipLaunchKernelGGL((k_gsweep3d<T, TO, MODE, 64>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
-    if (mode == kSweep) MG_G3(kSweep);
-    else if (mode == kSweepRB) MG_G3(kSweepRB);
-    else if (mode == kResidual) MG_G3(kResidual);
-    else MG_G3(kNormOnly);
-#undef MG_G3
-    return hipGetLastError();
-  }
+  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || x3path ? 64 : TX;
+  const int ys = xpath && xw == 64 ? x3_ys<T>(mode) : 1;  // rows per thread of the cross sweep
+  const int nt = xw * TY;
+  const int tiles = cdiv(n, xw) * cdiv(n, TY * ys);
+  const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, u != nullptr, xw, ys);
+  const int zr = x3path ? 16 : kZR;  // planes per loop turn of the kernel
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(occ_fn, nt, 0),
+                                                 kMinPlanes)) + zr - 1) / zr * zr;
+  const dim3 grid(cdiv(n, xw), cdiv(n, TY * ys), cdiv(n, zc));
+  if (nparts) *nparts = grid.x * grid.y * grid.z;
   if (x3path) {
 #define MG_X33(MODE) hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, 64, 3>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
     if (mode == kSweepZ2) MG_X33(kSweepZ2);
@@ -1768,47 +1255,36 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 #undef MG_X33
     return hipGetLastError();
   }
-  if (xpath) {
 #define MG_X3(MODE, XW, YS)                                                                  \
   if (u != nullptr)                                                                          \
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done); \
   else                                                                                       \
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
-    if (mode == kSweepZ2) {
+  if (mode == kSweepZ2) {
 #define MG_XZ(XW, YS) hipLaunchKernelGGL((k_xsweep3d<T, TO, kSweepZ2, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
-      if (xw == 64 && ys == 2) MG_XZ(64, 2);
-      else if (xw == 64) MG_XZ(64, 1);
-      else MG_XZ(32, 1);
+    if (xw == 64 && ys == 2) MG_XZ(64, 2);
+    else if (xw == 64) MG_XZ(64, 1);
+    else MG_XZ(32, 1);
 #undef MG_XZ
-      return hipGetLastError();
-    }
-    if (xw == 64 && ys == 2) {
-      if (mode == kSweep) { MG_X3(kSweep, 64, 2) }
-      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 2) }
-      else if (mode == kResidual) { MG_X3(kResidual, 64, 2) }
-      else { MG_X3(kNormOnly, 64, 2) }
-    } else if (xw == 64) {
-      if (mode == kSweep) { MG_X3(kSweep, 64, 1) }
-      else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 1) }
-      else if (mode == kResidual) { MG_X3(kResidual, 64, 1) }
-      else { MG_X3(kNormOnly, 64, 1) }
-    } else {
-      if (mode == kSweep) { MG_X3(kSweep, 32, 1) }
-      else if (mode == kSweepRB) { MG_X3(kSweepRB, 32, 1) }
-      else if (mode == kResidual) { MG_X3(kResidual, 32, 1) }
-      else { MG_X3(kNormOnly, 32, 1) }
-    }
-#undef MG_X3
     return hipGetLastError();
   }
-  if (mode == kSweepZ2) return hipErrorInvalidValue;  // (sweep3d_z2_ok excludes this path)
-#define MG_S3(MODE) \
-  hipLaunchKernelGGL((k_sweep3d<T, TO, MODE, 3>), grid, dim3(256), (sweep_smem<T, 3>()), s, f, u, out, n, zc, k, partials, done)
-  if (mode == kSweep) MG_S3(kSweep);
-  else if (mode == kSweepRB) MG_S3(kSweepRB);
-  else if (mode == kResidual) MG_S3(kResidual);
-  else MG_S3(kNormOnly);
-#undef MG_S3
+  if (xw == 64 && ys == 2) {
+    if (mode == kSweep) { MG_X3(kSweep, 64, 2) }
+    else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 2) }
+    else if (mode == kResidual) { MG_X3(kResidual, 64, 2) }
+    else { MG_X3(kNormOnly, 64, 2) }
+  } else if (xw == 64) {
+    if (mode == kSweep) { MG_X3(kSweep, 64, 1) }
+    else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 1) }
+    else if (mode == kResidual) { MG_X3(kResidual, 64, 1) }
+    else { MG_X3(kNormOnly, 64, 1) }
+  } else {
+    if (mode == kSweep) { MG_X3(kSweep, 32, 1) }
+    else if (mode == kSweepRB) { MG_X3(kSweepRB, 32, 1) }
+    else if (mode == kResidual) { MG_X3(kResidual, 32, 1) }
+    else { MG_X3(kNormOnly, 32, 1) }
+  }
+#undef MG_X3
   return hipGetLastError();
 }
 
@@ -1906,22 +1382,13 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
     hipLaunchKernelGGL((k_xrr3d<T, true, 16, 7, 512, 3>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
     return hipGetLastError();
   }
-  if (gsweep_rings()) {
-    const int ctiles = cdiv(nc, 16) * cdiv(nc, 7);
-    const void *fx = (const void *)k_grr3d<T, 16, 7, 512>;
-    const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 512, 0), kMinPlanes / 2));
-    const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
-    const dim3 grid(cdiv(nc, 16), cdiv(nc, 7), cdiv(nc, kc));
-    hipLaunchKernelGGL((k_grr3d<T, 16, 7, 512>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
-    return hipGetLastError();
-  }
-  const int tiles = cdiv(n, TX) * cdiv(n, TY);
-  const void *fn = (const void *)k_resid_restrict3d<T, 3>;
-  const size_t smem = rr_smem<T, 3>();
-  const int kc = std::min(kMaxPlanes / 2, band_rows(nc, tiles, kRounds3d * resident_blocks(fn, 256, smem), kMinPlanes / 2));
-  const dim3 grid(cdiv(n, TX), cdiv(n, TY), cdiv(nc, kc));
-  const KOp<T> k = to_kop3<T>(op, 1.0);
-  hipLaunchKernelGGL((k_resid_restrict3d<T, 3>), grid, dim3(256), (rr_smem<T, 3>()), s, f, u, fc, n, kc, k, done);
+  // every other operator: the separable defect kernel
+  const int ctiles = cdiv(nc, 16) * cdiv(nc, 7);
+  const void *fx = (const void *)k_grr3d<T, 16, 7, 512>;
+  const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 512, 0), kMinPlanes / 2));
+  const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
+  const dim3 grid(cdiv(nc, 16), cdiv(nc, 7), cdiv(nc, kc));
+  hipLaunchKernelGGL((k_grr3d<T, 16, 7, 512>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
   return hipGetLastError();
 }
 
@@ -1947,24 +1414,8 @@ hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *u
   return hipGetLastError();
 }
 
-// Dynamic LDS above 64 KB must be enabled per kernel before the first launch.
-hipError_t prepare_3d() {
-  hipError_t e = hipSuccess;
-#define MG_P(K, B)                                                                         \
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void *)K, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B));
-  MG_P((k_sweep3d<double, double, kSweep, 3>), (sweep_smem<double, 3>()));
-  MG_P((k_sweep3d<double, double, kSweepRB, 3>), (sweep_smem<double, 3>()));
-  MG_P((k_sweep3d<double, double, kResidual, 3>), (sweep_smem<double, 3>()));
-  MG_P((k_sweep3d<double, double, kNormOnly, 3>), (sweep_smem<double, 3>()));
-  MG_P((k_sweep3d<float, float, kSweep, 3>), (sweep_smem<float, 3>()));
-  MG_P((k_sweep3d<float, float, kSweepRB, 3>), (sweep_smem<float, 3>()));
-  MG_P((k_sweep3d<float, float, kResidual, 3>), (sweep_smem<float, 3>()));
-  MG_P((k_sweep3d<float, float, kNormOnly, 3>), (sweep_smem<float, 3>()));
-  MG_P((k_resid_restrict3d<double, 3>), (rr_smem<double, 3>()));
-  MG_P((k_resid_restrict3d<float, 3>), (rr_smem<float, 3>()));
-#undef MG_P
-  return e;
-}
+// Set-up of the 3D kernels before their first launch (none of them needs dynamic LDS).
+hipError_t prepare_3d() { return hipSuccess; }
 
 template hipError_t launch_sweep_3d<double, double>(int, const LevelOp &, double, const double *,
                                                     const double *, double *, int, double *, int *,

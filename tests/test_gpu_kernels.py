@@ -434,29 +434,27 @@ def test_3d_tile_shapes(n, prolong, wide, ys, fp32, monkeypatch):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("old,pencil,rows", [("0", "1", "1"), ("0", "1", "2"), ("0", "0", "1"), ("1", "1", "1")])
+@pytest.mark.parametrize("rows", ["1", "2"])
 @pytest.mark.parametrize("n,level", [(33, 1), (65, 1), (65, 2), (129, 1), (257, 1)])
-def test_3d_galerkin_sweep_kernels(n, level, old, pencil, rows, fp32, monkeypatch):
-    """Galerkin levels: the wavefront-pencil sweep (default; MG_GPEN_ROWS=2: twice the
-    rows per wavefront), the LDS-tile sweep (MG_GPEN=0) and the plane-ring LDS kernels
-    (MG_G3_OLD=1) against the oracle's assembled Galerkin stencils, on one strip of 58
-    columns up to ragged multi-strip, multi-band levels."""
-    monkeypatch.setenv("MG_G3_OLD", old)
-    monkeypatch.setenv("MG_GPEN", pencil)
+def test_3d_galerkin_sweep_kernels(n, level, rows, fp32, monkeypatch):
+    """Galerkin levels: the wavefront-pencil sweep (MG_GPEN_ROWS=2: twice the rows per
+    wavefront) and the separable defect + full weighting against the oracle's assembled
+    Galerkin stencils, on one strip of 58 columns up to ragged multi-strip, multi-band
+    levels."""
     monkeypatch.setenv("MG_GPEN_ROWS", rows)
     test_smooth(3, n, 1, 3, level, fp32)
     test_residual(3, n, 1, 3, level, fp32)
     test_residual_restrict(3, n, 1, 3, level, fp32)
 
 
-# Red-black partial steps (section 3.1 eq. S_rb): (dim, finest n, coarse, level, old 3D
-# Galerkin kernels).  Level sides cover single blocks, ragged blocks and 3D plane bands.
+# Red-black partial steps (section 3.1 eq. S_rb): (dim, finest n, coarse, level).  Level
+# sides cover single blocks, ragged blocks and 3D plane bands.
 CASES_RB = [
-    (2, 17, 0, 0, "0"), (2, 257, 0, 0, "0"), (2, 1025, 0, 1, "0"), (2, 257, 1, 1, "0"),
-    (2, 513, 3, 1, "0"), (2, 257, 1, 2, "0"), (2, 1025, 0, 0, "0"), (2, 257, 2, 1, "0"),
-    (3, 17, 0, 0, "0"), (3, 65, 0, 0, "0"), (3, 129, 0, 0, "0"), (3, 65, 1, 1, "0"),
-    (3, 129, 1, 1, "0"), (3, 65, 1, 1, "1"), (3, 65, 3, 2, "0"), (3, 33, 2, 1, "0"),
-    (3, 9, 0, 0, "0"), (3, 257, 2, 1, "0"),
+    (2, 17, 0, 0), (2, 257, 0, 0), (2, 1025, 0, 1), (2, 257, 1, 1),
+    (2, 513, 3, 1), (2, 257, 1, 2), (2, 1025, 0, 0), (2, 257, 2, 1),
+    (3, 17, 0, 0), (3, 65, 0, 0), (3, 129, 0, 0), (3, 65, 1, 1),
+    (3, 129, 1, 1), (3, 65, 3, 2), (3, 33, 2, 1),
+    (3, 9, 0, 0), (3, 257, 2, 1),
 ]
 
 
@@ -482,11 +480,10 @@ def test_red_black_sweep_3d_one_pass(n, fp32):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("dim,n,coarse,level,old", CASES_RB)
-def test_smooth_colour(dim, n, coarse, level, old, fp32, monkeypatch):
+@pytest.mark.parametrize("dim,n,coarse,level", CASES_RB)
+def test_smooth_colour(dim, n, coarse, level, fp32):
     """One partial step per colour against the oracle's; the other colour is copied
     bit for bit."""
-    monkeypatch.setenv("MG_G3_OLD", old)
     H = Handle(dim, n, coarse=coarse, smoother=1)
     try:
         n_l, s = H.level(level)
