@@ -127,8 +127,12 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   __shared__ T plane[2][PS];
   if (stopped(done)) return;
   const Block3 blk = block3();
-  const int x0 = blk.x * XW, y0 = blk.y * TYB;
-  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);
+  // tiles and plane chunks start at row, column and plane 1: for n = 2^k + 1 the points
+  // 1 .. n-1 fill whole tiles and chunks, and no block is left with the boundary column,
+  // row or plane n-1 alone.  Column 0 and row 0 are stored by the halo lanes of the
+  // first tiles, plane 0 by the first chunks.
+  const int x0 = 1 + blk.x * XW, y0 = 1 + blk.y * TYB;
+  const int z0 = 1 + blk.z * zchunk, z1 = min(z0 + zchunk, n);
   const int tx = threadIdx.x % XW, ty = threadIdx.x / XW;
   const int x = x0 + tx;
   int yv[YS], pown[YS];
@@ -170,6 +174,18 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   else
     ch = cu[0];
   const int phal = hy * PX + hx;
+  // halo lanes on column 0 beside the tile's rows, on row 0 above its columns, and the
+  // corner (0, 0) store those boundary points (0)
+  const int xe = x0 - R + hx, ye = y0 - R + hy;
+  const bool edge = has_halo && ((xe == 0 && ye >= y0 && ye < y0 + TYB) || (ye == 0 && xe >= x0 && xe < x0 + XW) ||
+                                 (xe == 0 && ye == 0));
+  const size_t ide = (size_t)min(max(ye, 0), n - 1) * n + min(max(xe, 0), n - 1);
+  constexpr bool STORES = MODE == kSweep || MODE == kSweepRB || MODE == kSweepZ2 || MODE == kResidual;
+  if (STORES && blk.z == 0) {  // plane 0
+#pragma unroll
+    for (int sr = 0; sr < YS; ++sr) out[(size_t)min(yv[sr], n - 1) * n + min(x, n - 1)] = (TO)0;
+    if (edge) out[ide] = (TO)0;
+  }
   // u is read from f (scaled by omega / a0 when consumed) for two sweeps from zero
   const T *up = (HAS_U && MODE != kSweepZ2) ? u : f;  // a valid address when there is no u
   const int zlast = z0 + (z1 - z0 + ZR - 1) / ZR * ZR - 1;
@@ -179,6 +195,9 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
     auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    // ring refills past the planes this chunk consumes re-read the last one it needs (an
+    // L2 hit) instead of fetching planes it never uses: 1025^3 FP32 sweep 3582 -> 3478 us
+    auto basec = [&](int z, int cap) -> size_t { return FAST ? (size_t)min(z, cap) * n * n : plane_base(z, n); };
     auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
     // raw loads: u of the own columns at z-R+k, f of the own columns and the halo at z+k
     T ur[YS][ZR], fr[YS][4], hr[4];
@@ -224,10 +243,10 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int sr = 0; sr < YS; ++sr) {
-        if (HAS_U) ur[sr][P % ZR] = up[base(z - R + ZR) + cu[sr].off];  // the slot of plane z-R
-        fr[sr][P % 4] = f[base(z + 4) + fcol[sr]];
+        if (HAS_U) ur[sr][P % ZR] = up[basec(z - R + ZR, z1 - 1 + R) + cu[sr].off];  // the slot of plane z-R
+        fr[sr][P % 4] = f[basec(z + 4, z1 - 1) + fcol[sr]];
       }
-      if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
+      if (HAS_U) hr[P % 4] = up[basec(z + 4, z1 - 1) + ch.off];
       T *pl = plane[P & 1];
 #pragma unroll
       for (int sr = 0; sr < YS; ++sr) pl[pown[sr]] = uc[sr];
@@ -259,6 +278,7 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
           out[id] = (TO)(inside ? c + (MODE == kSweepRB ? colour_om(kop, x + yv[sr] + z) : kop.om_d) * r : T(0));
         if (MODE == kResidual) out[id] = (TO)r;
       }
+      if (STORES && edge) out[(size_t)min(z, n - 1) * n * n + ide] = (TO)0;
     };
     for (int z = z0; z < z1; z += ZR)
       static_for<ZR>([&](auto pc) { step(z + decltype(pc)::value, pc); });
@@ -686,6 +706,9 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
     auto base = [&](int z) -> size_t { return FAST ? (size_t)z * n * n : plane_base(z, n); };
+    // refills past the last fine plane of the chunk re-read that plane (see the sweep)
+    auto basec = [&](int z, int cap) -> size_t { return FAST ? (size_t)min(z, cap) * n * n : plane_base(z, n); };
+    const int zl = 2 * Khi - 1;  // last fine plane of the chunk's supports
     auto zm = [&](int z) -> T { return FAST ? T(1) : plane_mul<T>(z, n); };
     T ur[ZR], fr[4], hr[4], dr[4];
 #pragma unroll
@@ -716,9 +739,9 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
       else
         asm volatile("" : "+v"(um2), "+v"(fz), "+v"(hz));
       __builtin_amdgcn_sched_barrier(0);
-      if (HAS_U) ur[P % ZR] = up[base(z - R + ZR) + cu.off];
-      fr[P % 4] = f[base(z + 4) + fcol];
-      if (HAS_U) hr[P % 4] = up[base(z + 4) + ch.off];
+      if (HAS_U) ur[P % ZR] = up[basec(z - R + ZR, zl + R) + cu.off];
+      fr[P % 4] = f[basec(z + 4, zl) + fcol];
+      if (HAS_U) hr[P % 4] = up[basec(z + 4, zl) + ch.off];
       T *pl = plane[P & 1];
       if (has_col) pl[pown] = uc;
       if (has_halo) pl[phal] = hz;
@@ -1136,6 +1159,12 @@ int x3_ys(int mode) {
   return sizeof(T) == 8 && mode == kNormOnly ? 1 : 2;
 }
 
+// FP32 wide cross-sweep tiles of 128 columns (MG_X3_W128 = 0: 64 columns).
+inline bool wide128() {
+  const char *e = getenv("MG_X3_W128");
+  return e == nullptr || atoi(e) != 0;
+}
+
 // Rows per wavefront of the pencil sweep: 2 (FP32 126 VGPRs, four wavefronts per SIMD;
 // FP64 209); MG_GPEN_ROWS = 2 doubles them.  Measured at 513^3: FP32 two rows 571 us,
 // four 540 us, but four rows lose more on the smaller levels (257^3: 81 against 94 us);
@@ -1169,6 +1198,8 @@ namespace {
 
 template <typename T, typename TO>
 const void *sweep3d_fn(int mode, bool has_u, int xw, int ys = 1) {
+  if constexpr (sizeof(T) == 4)
+    if (xw == 128) return xsweep3d_fn<T, TO, 128, 2, 2>(mode, has_u);
   return xw == 64 ? (ys == 2 ? xsweep3d_fn<T, TO, 64, 2, 2>(mode, has_u) : xsweep3d_fn<T, TO, 64>(mode, has_u))
                   : xsweep3d_fn<T, TO, 32>(mode, has_u);
 }
@@ -1235,15 +1266,19 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 #undef MG_GP
     return hipGetLastError();
   }
-  const int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || x3path ? 64 : TX;
+  int xw = (xpath && wide_tiles<T>(n, "MG_X3_W")) || x3path ? 64 : TX;
   const int ys = xpath && xw == 64 ? x3_ys<T>(mode) : 1;  // rows per thread of the cross sweep
+  // FP32 wide tiles: 128 x 16 points, 1024 threads (121 VGPRs; FP64 would spill).  Half
+  // the x halo and row-alignment bytes of 64-column tiles: 1025^3 sweep 3472 -> 3198 us
+  if (xpath && xw == 64 && ys == 2 && sizeof(T) == 4 && wide128()) xw = 128;
   const int nt = xw * TY;
-  const int tiles = cdiv(n, xw) * cdiv(n, TY * ys);
+  // tiles and chunks cover points 1 .. n-1 (the kernel stores row, column and plane 0)
+  const int tiles = cdiv(n - 1, xw) * cdiv(n - 1, TY * ys);
   const void *occ_fn = x3path ? xsweep3d_fn<T, TO, 64, 3>(mode, true) : sweep3d_fn<T, TO>(mode, u != nullptr, xw, ys);
   const int zr = x3path ? 16 : kZR;  // planes per loop turn of the kernel
   const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(occ_fn, nt, 0),
                                                  kMinPlanes)) + zr - 1) / zr * zr;
-  const dim3 grid(cdiv(n, xw), cdiv(n, TY * ys), cdiv(n, zc));
+  const dim3 grid(cdiv(n - 1, xw), cdiv(n - 1, TY * ys), cdiv(n - 1, zc));
   if (nparts) *nparts = grid.x * grid.y * grid.z;
   if (x3path) {
 #define MG_X33(MODE) hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, true, 64, 3>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
@@ -1262,12 +1297,25 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
     hipLaunchKernelGGL((k_xsweep3d<T, TO, MODE, false, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done);
   if (mode == kSweepZ2) {
 #define MG_XZ(XW, YS) hipLaunchKernelGGL((k_xsweep3d<T, TO, kSweepZ2, true, XW, 2, YS>), grid, dim3(nt), 0, s, f, u, out, n, zc, k, partials, done)
+    if constexpr (sizeof(T) == 4)
+      if (xw == 128) {
+        MG_XZ(128, 2);
+        return hipGetLastError();
+      }
     if (xw == 64 && ys == 2) MG_XZ(64, 2);
     else if (xw == 64) MG_XZ(64, 1);
     else MG_XZ(32, 1);
 #undef MG_XZ
     return hipGetLastError();
   }
+  if constexpr (sizeof(T) == 4)
+    if (xw == 128) {
+      if (mode == kSweep) { MG_X3(kSweep, 128, 2) }
+      else if (mode == kSweepRB) { MG_X3(kSweepRB, 128, 2) }
+      else if (mode == kResidual) { MG_X3(kResidual, 128, 2) }
+      else { MG_X3(kNormOnly, 128, 2) }
+      return hipGetLastError();
+    }
   if (xw == 64 && ys == 2) {
     if (mode == kSweep) { MG_X3(kSweep, 64, 2) }
     else if (mode == kSweepRB) { MG_X3(kSweepRB, 64, 2) }
