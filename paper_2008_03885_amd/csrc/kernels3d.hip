@@ -997,14 +997,35 @@ template <typename T, int P, int XW>
 __global__ __launch_bounds__(XW * TY) void k_prolong3d(const T *__restrict__ v, const T *uin, T *uout,
                                                       int n, int zchunk, const int *__restrict__ done) {
   constexpr int NT = XW * TY, CX = XW / 2 + 4, CY = TY / 2 + 4, CS = CX * CY;
-  static_assert(CS <= NT, "one coarse point per thread");
+  static_assert(CS + TY + XW + 1 <= NT, "one coarse point or edge point per thread");
   __shared__ T cpl[2][CS + 1];  // the last slot takes the stores of threads past CS
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
   const Block3 blk = block3();
-  const int x0 = blk.x * XW, y0 = blk.y * TY;
-  const int z0 = blk.z * zchunk, z1 = min(z0 + zchunk, n);  // z0 even (zchunk is)
+  // tiles start at row and column 1 (for n = 2^k + 1 the n - 1 points 1 .. n-1 fill whole
+  // tiles); the last band also takes the planes past the last whole band
+  const int x0 = 1 + blk.x * XW, y0 = 1 + blk.y * TY;
+  const int z0 = blk.z * zchunk;  // even (zchunk is)
+  const int z1 = blk.z == gridDim.z - 1 ? n : min(z0 + zchunk, n);
   const int tx = threadIdx.x % XW, ty = threadIdx.x / XW;
+  // edge lanes (threads past the coarse points): column 0 beside the tile's rows, row 0
+  // above its columns and the corner (0, 0) store those boundary points (0)
+  int xe = -1, ye = -1;
+  {
+    const int e = (int)threadIdx.x - CS;
+    if (blk.x == 0 && e >= 0 && e < TY) {
+      xe = 0;
+      ye = y0 + e;
+    } else if (blk.y == 0 && e >= TY && e < TY + XW) {
+      ye = 0;
+      xe = x0 + e - TY;
+    } else if (blk.x == 0 && blk.y == 0 && e == TY + XW) {
+      xe = 0;
+      ye = 0;
+    }
+  }
+  const bool edge = xe >= 0;
+  const size_t ide = (size_t)min(max(ye, 0), n - 1) * n + min(max(xe, 0), n - 1);
   const int x = x0 + tx, y = y0 + ty;
   const int Ib = x0 / 2 - 1, Jb = y0 / 2 - 1;  // coarse region origin
   const bool xyin = x > 0 && x < n - 1 && y > 0 && y < n - 1;
@@ -1100,6 +1121,7 @@ __global__ __launch_bounds__(XW * TY) void k_prolong3d(const T *__restrict__ v, 
     __builtin_amdgcn_sched_barrier(0);
     ur[Q] = uin[(size_t)min(z + 8, n - 1) * n * n + col];
     uout[(size_t)min(z, n - 1) * n * n + col] = res;
+    if (edge) uout[(size_t)min(z, n - 1) * n * n + ide] = T(0);
   };
   for (int z = z0; z <= zlast; z += 8)
     static_for<8>([&](auto pc) { step(z + decltype(pc)::value, pc); });
@@ -1444,12 +1466,14 @@ template <typename T>
 hipError_t launch_prolong_correct_3d(int prolong, const T *v, const T *uin, T *uout, int n,
                                      const int *done, hipStream_t s) {
   const int xw = wide_tiles<T>(n, "MG_P3_W") ? 64 : TX, nt = xw * TY;
-  const int tiles = cdiv(n, xw) * cdiv(n, TY);
+  // tiles cover points 1 .. n-1 (the kernel stores row and column 0)
+  const int tiles = cdiv(n - 1, xw) * cdiv(n - 1, TY);
   const void *fn = xw == 64 ? (prolong == 3 ? (const void *)k_prolong3d<T, 3, 64> : (const void *)k_prolong3d<T, 1, 64>)
                             : (prolong == 3 ? (const void *)k_prolong3d<T, 3, TX> : (const void *)k_prolong3d<T, 1, TX>);
-  // bands of whole turns (8 planes): no block stores outside its planes
+  // bands of whole turns (8 planes): no block stores outside its planes; the last band
+  // takes the remainder (for n = 2^k + 1 the boundary plane)
   const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, nt, 0), kMinPlanes)) + 7) / 8 * 8;
-  const dim3 grid(cdiv(n, xw), cdiv(n, TY), cdiv(n, zc));
+  const dim3 grid(cdiv(n - 1, xw), cdiv(n - 1, TY), std::max(1, (n - 1) / zc));
 #define MG_P3(PP, XW) hipLaunchKernelGGL((k_prolong3d<T, PP, XW>), grid, dim3(nt), 0, s, v, uin, uout, n, zc, done)
   if (xw == 64) {
     if (prolong == 3) MG_P3(3, 64);
