@@ -657,7 +657,9 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
   if (stopped(done)) return;
   const int nc = (n - 1) / 2 + 1;
   const Block3 blk = block3();
-  const int I0 = blk.x * CX, J0 = blk.y * CY;
+  // coarse tiles start at column 1 (for n = 2^k + 1 the nc - 1 columns 1 .. nc-1 fill
+  // whole tiles); column 0 is stored by edge lanes of the first tiles
+  const int I0 = 1 + blk.x * CX, J0 = blk.y * CY;
   const int X0 = 2 * I0 - 1, Y0 = 2 * J0 - 1;  // defect support origin
   const int K0 = blk.z * kchunk, K1 = min(K0 + kchunk, nc);
   const int t = threadIdx.x;
@@ -692,10 +694,17 @@ __global__ __launch_bounds__(NT) void k_xrr3d(const T *__restrict__ f, const T *
   const int I = I0 + ci, J = J0 + cj;
   const bool cown = t < CX * CY && I <= nc - 1 && J <= nc - 1;
   const bool cin = cown && I > 0 && I < nc - 1 && J > 0 && J < nc - 1;
+  // edge lanes: coarse column 0 beside the tile's rows
+  static_assert(CX * CY + CY <= NT, "edge lanes");
+  const int je = J0 + t - CX * CY;
+  const bool edge = blk.x == 0 && t >= CX * CY && t < CX * CY + CY && je <= nc - 1;
+  const size_t ide = (size_t)min(je, nc - 1) * nc;
   if (cown) {
     if (K0 == 0) fc[(size_t)J * nc + I] = T(0);
     if (K1 == nc) fc[((size_t)(nc - 1) * nc + J) * nc + I] = T(0);
   }
+  if (edge)
+    for (int K = K0; K < K1; ++K) fc[(size_t)K * nc * nc + ide] = T(0);
   const int Klo = max(K0, 1), Khi = min(K1, nc - 1);
   if (Klo >= Khi) return;
   const int zs = 2 * Klo - 1;                                        // odd
@@ -1419,14 +1428,15 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
       if (*e != 0) tall = atoi(e) != 0;
     }
     const int cx = 16, cy = tall ? 7 : 3, nt = tall ? 512 : 256;
-    const int ctiles = cdiv(nc, cx) * cdiv(nc, cy);
+    // coarse tiles cover columns 1 .. nc-1 (the kernel stores column 0)
+    const int ctiles = cdiv(nc - 1, cx) * cdiv(nc, cy);
     const void *fx = tall ? (u != nullptr ? (const void *)k_xrr3d<T, true, 16, 7, 512> : (const void *)k_xrr3d<T, false, 16, 7, 512>)
                           : (u != nullptr ? (const void *)k_xrr3d<T, true, 16, 3, 256> : (const void *)k_xrr3d<T, false, 16, 3, 256>);
     // coarse planes per band: 4m-1, so that the 8m-1 fine planes of a band fill m turns
     // of the plane ring but one plane
     const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, nt, 0), kMinPlanes / 2));
     const int kc = std::max(3, (kb + 1) / 4 * 4 - 1);
-    const dim3 grid(cdiv(nc, cx), cdiv(nc, cy), cdiv(nc, kc));
+    const dim3 grid(cdiv(nc - 1, cx), cdiv(nc, cy), cdiv(nc, kc));
     const KOp<T> k = to_kop3<T>(op, 1.0);
 #define MG_XRR(CX, CY, NT)                                                                  \
   if (u != nullptr)                                                                         \
@@ -1444,11 +1454,11 @@ hipError_t launch_resid_restrict_3d(const LevelOp &op, const T *f, const T *u, T
   if (op.cross3 && x3_r3()) {
     // the radius-3 cross: 16 x 7 coarse columns per 512 threads; coarse planes per band
     // 8m-1, so that the 16m-1 fine planes of a band fill m turns of the 16-plane ring
-    const int ctiles = cdiv(nc, 16) * cdiv(nc, 7);
+    const int ctiles = cdiv(nc - 1, 16) * cdiv(nc, 7);
     const void *fx = (const void *)k_xrr3d<T, true, 16, 7, 512, 3>;
     const int kb = std::min(kMaxPlanes / 2, band_rows(nc, ctiles, kRounds3d * resident_blocks(fx, 512, 0), kMinPlanes / 2));
     const int kc = std::max(7, (kb + 1) / 8 * 8 - 1);
-    const dim3 grid(cdiv(nc, 16), cdiv(nc, 7), cdiv(nc, kc));
+    const dim3 grid(cdiv(nc - 1, 16), cdiv(nc, 7), cdiv(nc, kc));
     hipLaunchKernelGGL((k_xrr3d<T, true, 16, 7, 512, 3>), grid, dim3(512), 0, s, f, u, fc, n, kc, to_kop3<T>(op, 1.0), done);
     return hipGetLastError();
   }
