@@ -59,9 +59,9 @@ MEASURED_TRAFFIC = {
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
     # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
     "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
-    # 1025^3 level 0 FP32 sweep (64 x 16 tiles, two rows per thread): 6,375,405.5 KiB
-    # x 2.0000 + 4,728,004.8 KiB x 1.0000
-    "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 17898113131, "source": "8f3bee0671863744"},
+    # 1025^3 level 0 FP32 sweep (128 x 16 tiles from point 1, two rows per thread):
+    # 4,689,041.2 KiB x 2.0000 + 4,432,600.7 KiB x 1.0000
+    "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 14141996627, "source": "3fd73c1038877ac5"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
     "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "11dcfa18322facea"},
