@@ -9,8 +9,9 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import Handle, assert_close, dev, host, rand_grid
-from paper_2008_03885_amd import mg
+import blocks
+from gpu_util import Handle, assert_close, dev, host, rand_grid, stream, torch
+from paper_2008_03885_amd import inputs, mg
 
 pytestmark = pytest.mark.gpu
 
@@ -418,15 +419,17 @@ def test_prolong_correct_3d(dim, n, coarse, prolong, level, fp32):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("wide,ys", [("0", "1"), ("1", "1"), ("1", "2")])
-@pytest.mark.parametrize("n,prolong", [(33, 3), (65, 3), (65, 1)])
-def test_3d_tile_shapes(n, prolong, wide, ys, fp32, monkeypatch):
-    """The cross kernels' other tile shapes (64-wide sweep and interpolation tiles, with
-    one or two rows per thread, 16 x 7 coarse defect tiles), which the large levels take,
-    against the oracle on small and ragged grids; and the small-level shapes forced."""
+@pytest.mark.parametrize("wide,ys,w128", [("0", "1", "1"), ("1", "1", "1"), ("1", "2", "1"), ("1", "2", "0")])
+@pytest.mark.parametrize("n,prolong", [(33, 3), (65, 3), (65, 1), (129, 3)])
+def test_3d_tile_shapes(n, prolong, wide, ys, w128, fp32, monkeypatch):
+    """The cross kernels' other tile shapes (wide sweep and interpolation tiles with one or
+    two rows per thread: FP32 sweeps with two rows take 128-column tiles unless
+    MG_X3_W128=0; 16 x 7 coarse defect tiles), which the large levels take, against the
+    oracle on small and ragged grids; and the small-level shapes forced."""
     for var in ("MG_X3_W", "MG_P3_W", "MG_XRR_TALL"):
         monkeypatch.setenv(var, wide)
     monkeypatch.setenv("MG_X3_YS", ys)
+    monkeypatch.setenv("MG_X3_W128", w128)
     test_smooth(3, n, 0, prolong, 0, fp32)
     test_residual(3, n, 0, prolong, 0, fp32)
     test_residual_restrict(3, n, 0, prolong, 0, fp32)
@@ -536,8 +539,8 @@ def test_coarsest_solve_3d(coarse, prolong, fp32):
 
 
 def test_full_size_sweep_513_3d_fp32():
-    """The FP32 level-0 sweep at 513^3 (64 x 16 tiles, two rows per thread), every element,
-    against the FP64 oracle on the same FP32-rounded inputs."""
+    """The FP32 level-0 sweep at 513^3 (128 x 16 tiles from point 1, two rows per thread),
+    every element, against the FP64 oracle on the same FP32-rounded inputs."""
     n = 513
     H = Handle(3, n, precision=1)
     try:
@@ -553,6 +556,76 @@ def test_full_size_sweep_513_3d_fp32():
         assert_close(host(out), oracle.residual(s, f, u), TOL32 * 4 * scale, "residual fp32")
     finally:
         H.close()
+
+
+def test_full_size_1025_3d_fp32_sampled():
+    """The 1025^3 level-0 FP32 kernels in the launch shapes that the 1025^3 benchmark
+    times (sweep tiles of 128 x 16 points and 64-plane chunks from point 1, coarse defect
+    tiles from column 1, interpolation tiles from point 1 with the last plane band taking
+    the boundary plane): every point of blocks placed across tile, chunk and grid edges,
+    against the oracle applied to the same blocks of the FP32 inputs (tests/blocks.py)."""
+    t = torch()
+    n = 1025
+    nc = (n - 1) // 2 + 1
+    print("1025^3 FP32 level-0 kernels, sampled blocks", flush=True)
+    h = mg.mg_setup(mg.make_config(dim=3, n=n, coarse=1, gamma=2, nu1=2, nu2=2, precision=1,
+                                   inner_cycles=1), stream())
+    try:
+        s = oracle.fine_stencil(3, 4, 1.0 / (n - 1))
+        om = oracle.jacobi_omega(3)
+        gen = t.Generator(device="cuda")
+        gen.manual_seed(inputs.SEED_BASE + 1025)
+
+        def field(m, scale):
+            a = (t.rand((m, m, m), generator=gen, device="cuda", dtype=t.float32) * 2 - 1) * scale
+            for ax in range(3):
+                a.narrow(ax, 0, 1).zero_()
+                a.narrow(ax, m - 1, 1).zero_()
+            return a
+
+        u, f = field(n, 1.0), field(n, float(s[2, 2, 2]))
+        out = t.full_like(u, float("nan"))
+        # centres on the sweep's tile edges (x 1 + 128k, y 1 + 16k, z 1 + 64k) and the grid's
+        per = [blocks.starts(n, blocks.SWEEP_B, c) for c in
+               ([0, 64, 65, 512, 961, n - 1], [0, 16, 17, 513, 1009, n - 1], [0, 128, 129, 513, 897, n - 1])]
+        sts = [(a, b, c) for a in per[0] for b in per[1] for c in per[2]]
+        B = blocks.SWEEP_B
+        mg.mg_kernel_smooth(h, 0, 1, f.data_ptr(), u.data_ptr(), out.data_ptr())
+        for st in sts:
+            c = blocks.core(st, B, n, blocks.SWEEP_M)
+            ref = oracle.jacobi(s, om, blocks.cut(f, st, B), blocks.cut(u, st, B))
+            assert_close(blocks.cut(out, st, B)[c], ref[c], TOL32 * 2, "sweep %s" % (st,))
+        mg.mg_kernel_residual(h, 0, 1, f.data_ptr(), u.data_ptr(), out.data_ptr())
+        for st in sts:
+            c = blocks.core(st, B, n, blocks.SWEEP_M)
+            ref = oracle.residual(s, blocks.cut(f, st, B), blocks.cut(u, st, B))
+            assert_close(blocks.cut(out, st, B)[c], ref[c], TOL32 * 8 * s[2, 2, 2], "residual %s" % (st,))
+        del out
+        # defect + full weighting: coarse tile edges (x 1 + 16k, y 7k, z 31k coarse)
+        B, CB = blocks.RR_B, blocks.RR_CB
+        fc = t.full((nc,) * 3, float("nan"), device="cuda", dtype=t.float32)
+        mg.mg_kernel_residual_restrict(h, 0, 1, f.data_ptr(), u.data_ptr(), fc.data_ptr())
+        per = [blocks.starts(n, B, c, even=True) for c in
+               ([0, 62, 64, 496, 992, n - 1], [0, 14, 16, 504, 1010, n - 1], [0, 32, 34, 514, 994, n - 1])]
+        for st in [(a, b, c) for a in per[0] for b in per[1] for c in per[2]]:
+            c = blocks.core(blocks.coarse(st), CB, nc, blocks.RR_M)
+            ref = oracle.restrict(oracle.residual(s, blocks.cut(f, st, B), blocks.cut(u, st, B)))
+            got = blocks.cut(fc, blocks.coarse(st), CB)
+            assert_close(got[c], ref[c], TOL32 * 8 * s[2, 2, 2], "defect + FW %s" % (st,))
+        del fc
+        # interpolation + correction: tiles x 1 + 64k, y 1 + 8k, bands of 64 planes from 0
+        B, CB = blocks.PRO_B, blocks.PRO_CB
+        v = field(nc, 1.0)
+        out = t.full_like(u, float("nan"))
+        mg.mg_kernel_prolong_correct(h, 0, 1, v.data_ptr(), u.data_ptr(), out.data_ptr())
+        per = [blocks.starts(n, B, c, even=True) for c in
+               ([0, 64, 66, 512, 960, n - 1], [0, 8, 10, 512, 1016, n - 1], [0, 64, 66, 512, 960, n - 1])]
+        for st in [(a, b, c) for a in per[0] for b in per[1] for c in per[2]]:
+            c = blocks.core(st, B, n, blocks.PRO_M)
+            ref = oracle.prolong_add(blocks.cut(v, blocks.coarse(st), CB), blocks.cut(u, st, B))
+            assert_close(blocks.cut(out, st, B)[c], ref[c], TOL32 * 3, "interpolation %s" % (st,))
+    finally:
+        mg.mg_destroy(h)
 
 
 def test_full_size_sweep_513_3d():
