@@ -96,6 +96,7 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=30)
     p.add_argument("--pmc-probe", action="store_true",
                    help="run a plain copy of known size, then the dominant kernel (for counters)")
+    p.add_argument("--pmc-level", type=int, default=0, help="--pmc-probe: the level whose kernels run")
     p.add_argument("--serve-requests", type=int, default=1000,
                    help="requests per serving run (0: skip the serving measurement)")
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement")
@@ -249,7 +250,7 @@ def in_cycle_time(run, w, stream, reps):
     return total / len(events)
 
 
-def level_kernels(run, w, stream, reps, only_level0=False):
+def level_kernels(run, w, stream, reps, only_level=None):
     """Per-level launches of the kernels the cycle runs on that level, each timed with HIP
     events, with their algorithmic bytes.  2D: the fused pre-smoothing + defect + full
     weighting and the fused interpolation + correction + post-smoothing; 3D: the sweep, the
@@ -269,8 +270,10 @@ def level_kernels(run, w, stream, reps, only_level0=False):
     gen.manual_seed(7)
     for l in range(L - 1):
         n, nc = mg.mg_level_size(run.h, l), mg.mg_level_size(run.h, l + 1)
-        if n <= tail_cap or (only_level0 and l > 0):
+        if n <= tail_cap or (only_level is not None and l > only_level):
             break
+        if only_level is not None and l < only_level:
+            continue
         shp, cshp = (n,) * d, (nc,) * d
         f = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
         u = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64).to(dt)
@@ -423,15 +426,16 @@ def error_vs_129(u_inj, coeffs, u129, cycles, final):
     }
 
 
-def pmc_probe(w, run, stream):
-    """A plain copy of known size, then the dominant kernel, for hardware counters."""
+def pmc_probe(w, run, stream, level=0):
+    """A plain copy of known size, then the kernels of one level (level 0: the dominant
+    kernel), five launches each, for hardware counters."""
     import torch
     a = torch.ones(256 * 1024 * 1024, device="cuda", dtype=torch.float64)  # 2 GiB
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    rows = level_kernels(run, w, stream, 5, only_level0=True)
+    rows = level_kernels(run, w, stream, 5, only_level=level)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8,
                       "kernels": rows}), flush=True)
@@ -681,7 +685,7 @@ def time_workload(w, args, stream, fd, label, variants_2d=False):
     dom_name = ("k_gs2d" if w.get("smoother", 0) == 2 else "k_pre2d") if d == 2 else "k_xsweep3d"
     dom = [r for r in rows if r["level"] == 0 and r["kernel"] == dom_name]
     if not dom:
-        dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, True)
+        dom = [r for r in level_kernels(main_run, w, stream, args.kernel_reps, only_level=0)
                if r["kernel"] == dom_name]
     dom = dom[0]  # with separate 2D kernels the first listed (smoothing) launch
     cyc_s = in_cycle_time(main_run, w, stream, args.kernel_reps)
@@ -792,7 +796,7 @@ def main():
         return
     if args.pmc_probe:
         run = Run(w, w["precision"], fd, stream)
-        pmc_probe(w, run, stream)
+        pmc_probe(w, run, stream, args.pmc_level)
         run.close()
         return
     d, n = w["dim"], w["n"]
