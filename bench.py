@@ -57,8 +57,9 @@ MEASURED_TRAFFIC = {
     # the same pass with red-black smoothing (one red-black sweep + defect + full weighting):
     # 156,850.3 KiB x 2.0000 + 168,329.4 KiB x 1.0000
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
-    # 513^3 level 0 FP32 sweep (64 x 8 tiles): 715,493.8 KiB x 1.9999 + 589,509.2 KiB x 1.0000
-    "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 2068949484, "source": "2c471c29e35f5f6d"},
+    # 513^3 level 0 FP32 sweep (128 x 16 tiles from point 1, two rows per thread):
+    # 573,624.3 KiB x 2.0000 + 545,052.6 KiB x 1.0000
+    "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 1732893797, "source": "3fd73c1038877ac5"},
     # 1025^3 level 0 FP32 sweep (128 x 16 tiles from point 1, two rows per thread):
     # 4,689,041.2 KiB x 2.0000 + 4,432,600.7 KiB x 1.0000
     "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 14141996627, "source": "3fd73c1038877ac5"},
