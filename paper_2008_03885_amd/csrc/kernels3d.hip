@@ -49,7 +49,6 @@ __device__ double block_sum(double v) {
     for (int w = 0; w < NT / 64; ++w) t += ws[w];
   return t;
 }
-__device__ double block_sum256(double v) { return block_sum<256>(v); }
 
 // ----------------------------------------------- cross sweep, z windows in registers ----
 // The radius-2 cross operator (rediscretized levels).  Each thread keeps the u values of
@@ -181,6 +180,7 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
                                  (xe == 0 && ye == 0));
   const size_t ide = (size_t)min(max(ye, 0), n - 1) * n + min(max(xe, 0), n - 1);
   constexpr bool STORES = MODE == kSweep || MODE == kSweepRB || MODE == kSweepZ2 || MODE == kResidual;
+  constexpr bool CORR = MODE == kSweepCorr;  // out is the FP64 iterate: out += the sweep's result
   if (STORES && blk.z == 0) {  // plane 0
 #pragma unroll
     for (int sr = 0; sr < YS; ++sr) out[(size_t)min(yv[sr], n - 1) * n + min(x, n - 1)] = (TO)0;
@@ -213,6 +213,14 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
 #pragma unroll
     for (int k = 0; k < 4; ++k) hr[k] = HAS_U ? up[base(z0 + k) + ch.off] : T(0);
     hold_regs(hr);
+    // CORR: the FP64 iterate of the own columns at the current plane, loaded one step
+    // ahead (refilled right after its use)
+    TO gr[YS];
+    if constexpr (CORR) {
+#pragma unroll
+      for (int sr = 0; sr < YS; ++sr)
+        gr[sr] = out[((size_t)min(z0, n - 1) * n + min(yv[sr], n - 1)) * n + min(x, n - 1)];
+    }
     const KOp<T> kop = op;
     const T uscale = MODE == kSweepZ2 ? kop.om_d : T(1);
     auto step = [&](const int z, auto pc) {
@@ -277,6 +285,14 @@ __global__ __launch_bounds__(XW * TY) void k_xsweep3d(const T *__restrict__ f, c
         if (MODE == kSweep || MODE == kSweepRB || MODE == kSweepZ2)
           out[id] = (TO)(inside ? c + (MODE == kSweepRB ? colour_om(kop, x + yv[sr] + z) : kop.om_d) * r : T(0));
         if (MODE == kResidual) out[id] = (TO)r;
+        if constexpr (CORR) {
+          // e' rounded to T as a stored sweep result would be, then added in TO
+          T e1 = c + kop.om_d * r;
+          asm volatile("" : "+v"(e1));
+          const TO unew = gr[sr] + (TO)e1;
+          if (inside) out[id] = unew;
+          gr[sr] = out[((size_t)min(z + 1, n - 1) * n + min(yv[sr], n - 1)) * n + min(x, n - 1)];
+        }
       }
       if (STORES && edge) out[(size_t)min(z, n - 1) * n * n + ide] = (TO)0;
     };
@@ -1411,6 +1427,32 @@ hipError_t launch_x2sweep_3d(const LevelOp &op, double omega, const T *f, const 
   else
     MG_RB3(false, xw, yw);
 #undef MG_RB3
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_corr_3d(const LevelOp &op, double omega, const float *f, const float *e,
+                                double *u64, int n, const int *done, hipStream_t s) {
+  if (!op.cross || op.cross3) return hipErrorInvalidValue;
+  // the FP32 sweep's tiles: 128 x 16 points (two rows per thread) on the large levels
+  const bool wide = wide_tiles<float>(n, "MG_X3_W");
+  const int xw = wide ? (wide128() ? 128 : 64) : TX, ys = wide ? 2 : 1, nt = xw * TY;
+  const void *fn = xw == 128 ? (const void *)k_xsweep3d<float, double, kSweepCorr, true, 128, 2, 2>
+                 : xw == 64  ? (const void *)k_xsweep3d<float, double, kSweepCorr, true, 64, 2, 2>
+                             : (const void *)k_xsweep3d<float, double, kSweepCorr, true, TX, 2, 1>;
+  const int tiles = cdiv(n - 1, xw) * cdiv(n - 1, TY * ys);
+  const int zc = (std::min(kMaxPlanes, band_rows(n, tiles, kRounds3d * resident_blocks(fn, nt, 0), kMinPlanes)) +
+                  kZR - 1) / kZR * kZR;
+  const dim3 grid(cdiv(n - 1, xw), cdiv(n - 1, TY * ys), cdiv(n - 1, zc));
+  const KOp<float> k = to_kop3<float>(op, omega);
+  if (xw == 128)
+    hipLaunchKernelGGL((k_xsweep3d<float, double, kSweepCorr, true, 128, 2, 2>), grid, dim3(nt), 0, s, f, e, u64, n,
+                       zc, k, nullptr, done);
+  else if (xw == 64)
+    hipLaunchKernelGGL((k_xsweep3d<float, double, kSweepCorr, true, 64, 2, 2>), grid, dim3(nt), 0, s, f, e, u64, n,
+                       zc, k, nullptr, done);
+  else
+    hipLaunchKernelGGL((k_xsweep3d<float, double, kSweepCorr, true, TX, 2, 1>), grid, dim3(nt), 0, s, f, e, u64, n,
+                       zc, k, nullptr, done);
   return hipGetLastError();
 }
 

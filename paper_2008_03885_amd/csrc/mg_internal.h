@@ -72,7 +72,7 @@ struct DevState {
 // kSweepRB: a sweep relaxing one colour (KOp::colour), the 3D kernels' red-black step.
 // kSweepZ2: two omega-Jacobi sweeps from a zero iterate in one pass (3D): the first
 // sweep's result, omega / a0 * f, is formed on the fly wherever the second reads u.
-enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2, kSweepRB = 3, kSweepZ2 = 4 };
+enum SweepMode { kSweep = 0, kResidual = 1, kNormOnly = 2, kSweepRB = 3, kSweepZ2 = 4, kSweepCorr = 5 };
 
 // Workgroups are dealt to the XCDs (8 on MI355X, each with its own L2) round-robin in
 // linear dispatch order.  xcd_logical maps a linear id to a logical block id such that
@@ -182,6 +182,12 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
 template <typename T>
 hipError_t launch_rbsweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,
                              double *partials, int *nparts, const int *done, hipStream_t s);
+// The last FP32 sweep of a refinement step fused with the FP64 correction: one
+// omega-Jacobi sweep of the cross on e (FP32), whose result e' (rounded to FP32) is added to
+// u64 at every interior point, u64 += e'; e' itself is not stored.  Interior points only:
+// u64's boundary is left as it is.
+hipError_t launch_sweep_corr_3d(const LevelOp &op, double omega, const float *f, const float *e,
+                                double *u64, int n, const int *done, hipStream_t s);
 // two omega-Jacobi sweeps of the cross in one pass (out of place)
 template <typename T>
 hipError_t launch_x2sweep_3d(const LevelOp &op, double omega, const T *f, const T *u, T *out, int n,

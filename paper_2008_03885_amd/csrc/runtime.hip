@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "batch.h"
@@ -521,7 +522,7 @@ hipError_t launch_tail_at(mg_ctx *c, int l, T *u, const T *f, bool zero_u, const
 
 template <typename T>
 hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
-                 bool check, hipStream_t s);
+                 bool check, hipStream_t s, double *corr = nullptr);
 
 // fc = I_h^H (f - L_l u) on level l+1.  Full weighting: one fused pass.  Cubic adjoint
 // (appendix A.4): the defect into scratch (a free level-l array), then the restriction.
@@ -632,9 +633,21 @@ hipError_t cycle_rb2d(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *
   return in == u ? hipSuccess : hipErrorInvalidValue;
 }
 
+// Whether the last FP32 cycle of a refinement step ends in the fused sweep + correction
+// (3D cross level 0 run by the streaming kernels with omega-Jacobi sweeps, one sweep per
+// pass after the interpolation); MG_FUSE_CORR=0 keeps the separate correction.
+bool fuse_corr(const mg_ctx *c) {
+  const char *e = std::getenv("MG_FUSE_CORR");
+  const bool on = !(e != nullptr && std::atoi(e) == 0);
+  const LevelOp &op = c->ops[0];
+  return on && c->cfg.precision == MG_PREC_MIXED && c->dim == 3 && c->L > 1 && c->tail_top > 0 &&
+         op.cross && !op.cross3 && c->cfg.smoother == MG_SMOOTH_JACOBI && c->cfg.nu2 >= 1 &&
+         !x2_enabled<float>() && c->slots == 1;
+}
+
 template <typename T>
 hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
-                 bool check, hipStream_t s) {
+                 bool check, hipStream_t s, double *corr) {
   const int *done = &c->st->done;
   const int dim = c->dim;
   const int n = c->ns[l];
@@ -794,6 +807,12 @@ hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bo
     if (x2 && npost - k >= 2) {
       e = mgk::launch_x2sweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
       ++k;
+    } else if (corr != nullptr && k == npost - 1) {
+      // the last sweep of the step's last cycle adds its result to the FP64 iterate
+      if constexpr (std::is_same<T, float>::value)
+        e = mgk::launch_sweep_corr_3d(op, c->omega, f, cur, corr, n, done, s);
+      else
+        e = hipErrorInvalidValue;
     } else if (rb3)
       e = mgk::launch_rbsweep_3d<T>(op, c->omega, f, cur, other, n, nullptr, nullptr, done, s);
     else if (rb)
@@ -819,10 +838,13 @@ hipError_t record_step(mg_ctx *c, const double *f, double *u, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = mgk::launch_check(c->st, c->partials, np, 1, s, c->slots);
   if (e != hipSuccess) return e;
+  const bool fuse = fuse_corr(c);
   for (int i = 0; i < c->cfg.inner_cycles; ++i) {
-    e = cycle<float>(c, c->b32, 0, e32, r32, i == 0, false, s);
+    const bool last = i == c->cfg.inner_cycles - 1;
+    e = cycle<float>(c, c->b32, 0, e32, r32, i == 0, false, s, fuse && last ? u : nullptr);
     if (e != hipSuccess) return e;
   }
+  if (fuse) return hipSuccess;  // the last sweep added e to u
   return mgk::launch_ir_correct(c->dim, u, e32, c->ns[0], done, s, c->slots);
 }
 

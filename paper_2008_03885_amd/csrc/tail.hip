@@ -31,17 +31,16 @@ static_assert(65 * 65 <= kSlots * kTailThreads && 17 * 17 * 17 <= kSlots * kTail
 // interpolation one coarse point; G = 1 when every tail level is the radius-2 cross,
 // G = 2 otherwise.
 
-// Thread tiling of a level (NT threads) and the number of points each thread visits at
-// the largest tail side (65 in 2D, 17 in 3D).
+// Thread tiling of a level (NT threads): TX x TY (x TZ) threads stride over the level.
 template <int DIM, int NT>
 struct Tiling;
 template <>
 struct Tiling<2, 1024> {
-  static constexpr int TX = 64, TY = 16, TZ = 1, NI = 2, NJ = 5, NK = 1;
+  static constexpr int TX = 64, TY = 16, TZ = 1;
 };
 template <>
 struct Tiling<3, 1024> {
-  static constexpr int TX = 16, TY = 8, TZ = 8, NI = 2, NJ = 3, NK = 3;
+  static constexpr int TX = 16, TY = 8, TZ = 8;
 };
 
 struct LevelInfo {

@@ -772,3 +772,36 @@ def test_two_jacobi_sweeps_in_one_pass(n, coarse, nu1, nu2, gamma, precision, mo
             H.close()
     tol = 1e-13 if precision == 0 else 1e-6
     assert np.linalg.norm(out["1"] - out["0"]) <= tol * np.linalg.norm(out["0"])
+
+
+@pytest.mark.parametrize("n,coarse,nu1,nu2,gamma,inner", [(65, 1, 2, 2, 2, 1), (65, 0, 2, 1, 1, 2), (129, 1, 2, 2, 2, 1),
+                                                          (33, 0, 1, 2, 1, 3), (257, 0, 2, 1, 1, 1)])
+def test_fused_correction_equals_separate(n, coarse, nu1, nu2, gamma, inner, monkeypatch):
+    """Mixed-precision steps whose last level-0 FP32 sweep adds its result to the FP64
+    iterate (the correction fused into the sweep) give, bit for bit, the steps with the
+    sweep stored and the correction u += e as a pass of its own (MG_FUSE_CORR=0): the same
+    iterate and the same residual history; and both approach the oracle's FP64 solution
+    of the same problem."""
+    f = inputs.smoothed_noise_3d(n)
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MG_FUSE_CORR", fuse)
+        H = Handle(3, n, coarse=coarse, nu1=nu1, nu2=nu2, gamma=gamma, precision=1, inner_cycles=inner,
+                   max_cycles=30)
+        try:
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            st, res = mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), 3)
+            u3 = host(ud)
+            st2, res2 = mg.mg_solve(H.h, fd.data_ptr(), ud.data_ptr())
+            out[fuse] = (u3, res.hist(), host(ud), res2.hist(), st2, res2.rel_residual)
+        finally:
+            H.close()
+    assert np.array_equal(out["0"][0], out["1"][0])
+    assert out["0"][1] == out["1"][1]
+    assert np.array_equal(out["0"][2], out["1"][2])
+    assert out["0"][3] == out["1"][3] and out["0"][4] == out["1"][4] == mg.MG_OK
+    # the solve's residual bounds its error against the exact discrete solution
+    rel = out["1"][5]
+    assert rel <= 1e-10
+    err = oracle.norm(out["1"][2] - dst.solve(f))
+    assert err <= 1.01 * rel * oracle.norm(f) / dst.min_eigenvalue(n, 3) + 1e-14 * oracle.norm(out["1"][2])
