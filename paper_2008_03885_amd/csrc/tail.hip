@@ -94,6 +94,34 @@ struct Tail {
       k = 0;
     }
   }
+  // The points threadIdx.x + r NT (r = 0, 1, ...) of an n^DIM level in x-fastest order,
+  // walked without a division per point: start at the thread's point, then add NT's
+  // coordinates (d) with carries.
+  struct Walk {
+    int i, j, k, di, dj, dk, n;
+    __device__ __forceinline__ void next() {
+      i += di;
+      j += dj;
+      if (i >= n) {
+        i -= n;
+        ++j;
+      }
+      if (DIM == 3) {
+        k += dk;
+        if (j >= n) {
+          j -= n;
+          ++k;
+        }
+      }
+    }
+  };
+  __device__ __forceinline__ Walk walk(int n) const {
+    Walk w;
+    w.n = n;
+    decode((int)threadIdx.x, n, w.i, w.j, w.k);
+    decode(NT, n, w.di, w.dj, w.dk);
+    return w;
+  }
   // Stores the value v of interior point (i, j, k) of level l together with its odd
   // images in the ghost frame (points within G of the boundary have one image per such
   // axis, and the products of those for corners).  Frame cells whose source is a
@@ -163,13 +191,13 @@ struct Tail {
     const int total = DIM == 3 ? n * n * n : n * n;
     const T om_all = T(lv[l].om_d);
     T vals[kSlots];
+    Walk wk = walk(n);
 #pragma unroll
     for (int r = 0; r < kSlots; ++r) {
       const int p = (int)threadIdx.x + r * NT;
       T v = T(0);
       if (p < total) {
-        int i, j, k;
-        decode(p, n, i, j, k);
+        const int i = wk.i, j = wk.j, k = wk.k;
         if (interior(n, i, j, k)) {
           const int q = pidx(l, i, j, k);
           const T u0 = zero ? T(0) : lds[q];
@@ -179,16 +207,15 @@ struct Tail {
         }
       }
       vals[r] = v;
+      wk.next();
     }
     __syncthreads();
+    wk = walk(n);
 #pragma unroll
     for (int r = 0; r < kSlots; ++r) {
       const int p = (int)threadIdx.x + r * NT;
-      if (p < total) {
-        int i, j, k;
-        decode(p, n, i, j, k);
-        if (interior(n, i, j, k)) put(l, i, j, k, vals[r]);
-      }
+      if (p < total && interior(n, wk.i, wk.j, wk.k)) put(l, wk.i, wk.j, wk.k, vals[r]);
+      wk.next();
     }
     __syncthreads();
   }
@@ -237,36 +264,55 @@ struct Tail {
     });
     __syncthreads();
   }
-  // 1D interpolation weight of the coarse point at fine distance o
-  __device__ __forceinline__ T pw1(int o) const {
-    o = o < 0 ? -o : o;
-    if (prolong == 3) return o == 0 ? T(1) : (o == 1 ? T(0.5625) : (o == 3 ? T(-0.0625) : T(0)));
-    return o == 0 ? T(1) : (o == 1 ? T(0.5) : T(0));
+  // Coarse points and weights of the interpolation along one axis at fine index x
+  // (interior): four consecutive points from c0 for cubic interpolation, two for linear;
+  // an even x takes its coarse point alone (weight 1, the others 0).  Every point read
+  // lies inside the ghost-framed coarse array.
+  template <int NP>
+  __device__ __forceinline__ int axis_weights(int x, T (&w)[NP]) const {
+    if (NP == 4) {
+      const bool odd = x & 1;
+      w[0] = odd ? T(-0.0625) : T(0);
+      w[1] = odd ? T(0.5625) : T(1);
+      w[2] = odd ? T(0.5625) : T(0);
+      w[3] = odd ? T(-0.0625) : T(0);
+      return odd ? (x - 3) >> 1 : (x >> 1) - 1;
+    }
+    const bool odd = x & 1;
+    w[0] = odd ? T(0.5) : T(1);
+    w[NP - 1] = odd ? T(0.5) : T(0);
+    return x >> 1;
   }
   // u(l) += I_H^h u(l+1), coarse values read from the ghost-framed array
-  __device__ __forceinline__ void prolong_correct(int l) const {
-    const int n = lv[l].n;
-    const int rP = prolong == 3 ? 3 : 1;
+  template <int NP>
+  __device__ __forceinline__ void prolong_np(int l) const {
+    const int n = lv[l].n, ppc = lv[l + 1].pp;
     each(n, [&](int i, int j, int k) {
       if (!interior(n, i, j, k)) return;
+      T wx[NP], wy[NP], wz[NP];
+      const int i0 = axis_weights<NP>(i, wx), j0 = axis_weights<NP>(j, wy);
+      const int k0 = DIM == 3 ? axis_weights<NP>(k, wz) : 0;
+      const int base = pidx(l + 1, i0, j0, k0);
       T s = T(0);
-      const int klo = DIM == 3 ? ((k - rP + 1) >> 1) : 0, khi = DIM == 3 ? ((k + rP) >> 1) : 0;
-      for (int Kc = klo; Kc <= khi; ++Kc) {
-        const T wz = DIM == 3 ? pw1(k - 2 * Kc) : T(1);
-        if (wz == T(0)) continue;
-        for (int Jc = (j - rP + 1) >> 1; Jc <= (j + rP) >> 1; ++Jc) {
-          const T wy = pw1(j - 2 * Jc);
-          if (wy == T(0)) continue;
-          for (int Ic = (i - rP + 1) >> 1; Ic <= (i + rP) >> 1; ++Ic) {
-            const T wx = pw1(i - 2 * Ic);
-            if (wx == T(0)) continue;
-            s += wx * wy * wz * lds[pidx(l + 1, Ic, Jc, Kc)];
-          }
+#pragma unroll
+      for (int c = 0; c < (DIM == 3 ? NP : 1); ++c) {
+        const T zc = DIM == 3 ? wz[c] : T(1);
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+#pragma unroll
+          for (int a = 0; a < NP; ++a)
+            s += wx[a] * wy[b] * zc * lds[base + (DIM == 3 ? c * ppc * ppc : 0) + b * ppc + a];
         }
       }
       put(l, i, j, k, lds[pidx(l, i, j, k)] + s);
     });
     __syncthreads();
+  }
+  __device__ __forceinline__ void prolong_correct(int l) const {
+    if (prolong == 3)
+      prolong_np<4>(l);
+    else
+      prolong_np<2>(l);
   }
   // v = A^{-1} f on the coarsest level by sine transforms (FP64): the interior right-hand
   // side goes to a double array in the defect scratch, is transformed along each axis
