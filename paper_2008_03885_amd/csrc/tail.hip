@@ -45,7 +45,7 @@ struct Tiling<3, 1024> {
 
 struct LevelInfo {
   int n, pp;       // side and padded pitch (n + 2G)
-  int u, f;        // element offsets in LDS
+  int u, u2, f;    // element offsets in LDS: the two framed iterates, the right-hand side
   int e0, ne;      // entries of this level in the LDS entry table
   double om_d;
   double w1, w2;   // cross weights (rediscretized levels)
@@ -64,11 +64,18 @@ struct Tail {
   int m, levels, gamma, nu1, nu2, prolong, scratch;
   int rb;  // red-black smoothing: a sweep is the red, then the black partial step
   int tx, ty, tz;
+  // Each level keeps two framed iterates: a smoothing step reads one and writes the
+  // other, so it needs one barrier; bit l tells which is current (uniform over threads).
+  unsigned cur = 0u;
 
-  __device__ __forceinline__ int pidx(int l, int i, int j, int k) const {
+  __device__ __forceinline__ int ubase(int l) const { return ((cur >> l) & 1u) ? lv[l].u2 : lv[l].u; }
+  __device__ __forceinline__ int obase(int l) const { return ((cur >> l) & 1u) ? lv[l].u : lv[l].u2; }
+  __device__ __forceinline__ int pidx_in(int base, int l, int i, int j, int k) const {
     const int pp = lv[l].pp;
-    return lv[l].u + (DIM == 3 ? ((k + G) * pp + (j + G)) * pp : (j + G) * pp) + (i + G);
+    return base + (DIM == 3 ? ((k + G) * pp + (j + G)) * pp : (j + G) * pp) + (i + G);
   }
+  // element of the current iterate of level l
+  __device__ __forceinline__ int pidx(int l, int i, int j, int k) const { return pidx_in(ubase(l), l, i, j, k); }
   __device__ __forceinline__ int didx(int l, int i, int j, int k) const {
     const int n = lv[l].n;
     return (DIM == 3 ? (k * n + j) * n : j * n) + i;
@@ -126,7 +133,8 @@ struct Tail {
   // images in the ghost frame (points within G of the boundary have one image per such
   // axis, and the products of those for corners).  Frame cells whose source is a
   // boundary point hold 0 from the start and are never written.
-  __device__ __forceinline__ void put(int l, int i, int j, int k, T v) const {
+  __device__ __forceinline__ void put(int l, int i, int j, int k, T v) const { put_in(ubase(l), l, i, j, k, v); }
+  __device__ __forceinline__ void put_in(int base, int l, int i, int j, int k, T v) const {
     const int n = lv[l].n;
     int xs[2] = {i, i}, ys[2] = {j, j}, zs[2] = {k, k};
     int nx = 1, ny = 1, nz = 1;
@@ -139,7 +147,7 @@ struct Tail {
       for (int b = 0; b < ny; ++b)
         for (int a = 0; a < nx; ++a) {
           const bool odd = (a + b + c) & 1;
-          lds[pidx(l, xs[a], ys[b], zs[c])] = odd ? -v : v;
+          lds[pidx_in(base, l, xs[a], ys[b], zs[c])] = odd ? -v : v;
         }
   }
   __device__ __forceinline__ T lu(int l, int p, T c) const {
@@ -183,19 +191,19 @@ struct Tail {
     __syncthreads();
   }
   // One omega-Jacobi step on level l: every thread computes its points (at most kSlots,
-  // x-fastest order) into registers, then all store them with their ghost images.
-  // colour 0 updates every interior point, 1 those with odd i+j(+k), 2 the even ones; the
-  // others keep their value (relaxation weight 0).
-  __device__ __forceinline__ void step(int l, bool zero, int colour) const {
+  // x-fastest order) from the current iterate and stores them, with their ghost images,
+  // into the other one, which then becomes current.  colour 0 updates every interior
+  // point, 1 those with odd i+j(+k), 2 the even ones; the others keep their value
+  // (relaxation weight 0, stored as well).
+  __device__ __forceinline__ void step(int l, bool zero, int colour) {
     const int n = lv[l].n;
     const int total = DIM == 3 ? n * n * n : n * n;
     const T om_all = T(lv[l].om_d);
-    T vals[kSlots];
+    const int ob = obase(l);
     Walk wk = walk(n);
 #pragma unroll
     for (int r = 0; r < kSlots; ++r) {
       const int p = (int)threadIdx.x + r * NT;
-      T v = T(0);
       if (p < total) {
         const int i = wk.i, j = wk.j, k = wk.k;
         if (interior(n, i, j, k)) {
@@ -203,24 +211,16 @@ struct Tail {
           const T u0 = zero ? T(0) : lds[q];
           const T rr = lds[lv[l].f + p] - (zero ? T(0) : lu(l, q, u0));
           const T om = (colour == 0 || ((i + j + k) & 1) == (colour & 1)) ? om_all : T(0);
-          v = u0 + om * rr;
+          put_in(ob, l, i, j, k, u0 + om * rr);
         }
       }
-      vals[r] = v;
       wk.next();
     }
-    __syncthreads();
-    wk = walk(n);
-#pragma unroll
-    for (int r = 0; r < kSlots; ++r) {
-      const int p = (int)threadIdx.x + r * NT;
-      if (p < total && interior(n, wk.i, wk.j, wk.k)) put(l, wk.i, wk.j, wk.k, vals[r]);
-      wk.next();
-    }
+    cur ^= 1u << l;
     __syncthreads();
   }
   // One smoothing sweep: omega-Jacobi, or red then black (section 3.1 eq. S_rb).
-  __device__ __forceinline__ void smooth(int l, bool zero) const {
+  __device__ __forceinline__ void smooth(int l, bool zero) {
     if (rb) {
       step(l, zero, 1);
       step(l, false, 2);
@@ -322,13 +322,25 @@ struct Tail {
     const int n = lv[l].n, q = n - 2;
     double *w0 = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(lds + scratch) + 7) & ~uintptr_t(7));
     double *w1 = w0 + m, *S = w0 + 2 * m;
-    for (int c = threadIdx.x; c < m; c += NT) {
-      const int ci = 1 + c % q, cj = 1 + (c / q) % q, ck = DIM == 3 ? 1 + c / (q * q) : 0;
-      w0[c] = (double)lds[lv[l].f + didx(l, ci, cj, ck)];
-    }
-    for (int e = threadIdx.x; e < q * q; e += NT) S[e] = dst[e];
-    __syncthreads();
     const double *scale = dst + q * q;
+    // interior point (1 + a, 1 + b, 1 + c) of element e in x-fastest order
+    auto coords = [&](int e, int &ci, int &cj, int &ck) {
+      ci = 1 + e % q;
+      cj = 1 + (e / q) % q;
+      ck = DIM == 3 ? 1 + e / (q * q) : 0;
+    };
+    // the first pass (along x) reads the right-hand side in place, with the table from
+    // global memory, and copies the table to LDS for the other passes
+    for (int e = threadIdx.x; e < q * q; e += NT) S[e] = dst[e];
+    for (int c = threadIdx.x; c < m; c += NT) {
+      const int a = c % q, b0 = c - a;
+      int ci, cj, ck;
+      coords(b0, ci, cj, ck);
+      double acc = 0.0;
+      for (int i = 0; i < q; ++i) acc += dst[a * q + i] * (double)lds[lv[l].f + didx(l, 1 + i, cj, ck)];
+      w1[c] = acc;
+    }
+    __syncthreads();
     auto pass = [&](const double *in, double *out, int stride, bool scaled) {
       for (int c = threadIdx.x; c < m; c += NT) {
         const int a = (c / stride) % q, b0 = c - a * stride;
@@ -338,31 +350,25 @@ struct Tail {
       }
       __syncthreads();
     };
-    // forward along x, y (, z), the last pass scaled; then back.  Each pass reads one
-    // array and writes the other; the result ends in w1.
-    auto flip = [&] {
-      double *t = w0;
-      w0 = w1;
-      w1 = t;
-    };
-    pass(w0, w1, 1, false);
+    // forward along x (above), y (, z), the last forward pass scaled; then back along x,
+    // y (, z), the last backward pass storing the solution into the iterate
     if (DIM == 3) {
       pass(w1, w0, q, false);
       pass(w0, w1, q * q, true);
+      pass(w1, w0, 1, false);
+      pass(w0, w1, q, false);
     } else {
       pass(w1, w0, q, true);
-      flip();
+      pass(w0, w1, 1, false);
     }
-    pass(w1, w0, 1, false);
-    pass(w0, w1, q, false);
-    if (DIM == 3) {
-      pass(w1, w0, q * q, false);
-      flip();
-    }
-    const double *res = w1;
-    for (int r = threadIdx.x; r < m; r += NT) {
-      const int ri = 1 + r % q, rj = 1 + (r / q) % q, rk = DIM == 3 ? 1 + r / (q * q) : 0;
-      put(l, ri, rj, rk, (T)res[r]);
+    const int stride = DIM == 3 ? q * q : q;
+    for (int c = threadIdx.x; c < m; c += NT) {
+      const int a = (c / stride) % q, b0 = c - a * stride;
+      double acc = 0.0;
+      for (int i = 0; i < q; ++i) acc += S[a * q + i] * w1[b0 + i * stride];
+      int ci, cj, ck;
+      coords(c, ci, cj, ck);
+      put(l, ci, cj, ck, (T)acc);
     }
     __syncthreads();
   }
@@ -409,7 +415,7 @@ struct Tail {
 // either repeats level l (gamma > 1, second visit from the same parent, non-zero guess)
 // or returns to the parent.  Bit l of `visited` records a finished visit of level l.
 template <typename T, int DIM, int G, int NT>
-__device__ __forceinline__ void run_cycle(const Tail<T, DIM, G, NT> &c, bool zero0) {
+__device__ __forceinline__ void run_cycle(Tail<T, DIM, G, NT> &c, bool zero0) {
   const int last = c.levels - 1;
   if (last == 0) {
     c.coarsest(0);
@@ -460,6 +466,8 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
       L.pp = L.n + 2 * G;
       L.u = off;
       off += DIM == 3 ? L.pp * L.pp * L.pp : L.pp * L.pp;
+      L.u2 = off;
+      off += DIM == 3 ? L.pp * L.pp * L.pp : L.pp * L.pp;
       L.f = off;
       off += DIM == 3 ? L.n * L.n * L.n : L.n * L.n;
       L.e0 = a.lv[l].ent_begin - a.ent_first;
@@ -506,11 +514,15 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
   const size_t per = DIM == 3 ? (size_t)n * n * n : (size_t)n * n;
   const T *fg = slot_ptr(static_cast<const T *>(a.f_top), per);
   T *ug = slot_ptr(static_cast<T *>(a.u_top), per);
-  // coarser levels' framed u start at zero: boundary points and the frame cells that
-  // mirror them are never written afterwards
-  for (int l = 1; l < a.levels; ++l) {
+  // the framed iterates start at zero (both of every level; level 0's current one is
+  // loaded below): boundary points and the frame cells that mirror them are never
+  // written afterwards
+  for (int l = 0; l < a.levels; ++l) {
     const int pp = lvt[l].pp, tot = DIM == 3 ? pp * pp * pp : pp * pp;
-    for (int e = threadIdx.x; e < tot; e += NT) lds[lvt[l].u + e] = T(0);
+    for (int e = threadIdx.x; e < tot; e += NT) {
+      if (l > 0) lds[lvt[l].u + e] = T(0);
+      lds[lvt[l].u2 + e] = T(0);
+    }
   }
   c.each(n, [&](int i, int j, int k) {
     const int d = c.didx(0, i, j, k);
@@ -528,12 +540,12 @@ __global__ __launch_bounds__(NT) void k_tail(TailArgs a) {
 
 int tail_max_side(int dim) { return dim == 2 ? 65 : 17; }
 
-// Element offset of the defect scratch (after every level's framed u and dense f).
+// Element offset of the defect scratch (after every level's two framed iterates and dense f).
 size_t tail_scratch_offset(int dim, int G, const int *ns, int levels) {
   size_t pts = 0;
   for (int l = 0; l < levels; ++l) {
     const size_t n = ns[l], pp = n + 2 * G;
-    pts += dim == 3 ? pp * pp * pp + n * n * n : pp * pp + n * n;
+    pts += dim == 3 ? 2 * pp * pp * pp + n * n * n : 2 * pp * pp + n * n;
   }
   return pts;
 }
