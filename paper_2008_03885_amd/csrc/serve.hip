@@ -5,7 +5,7 @@
 //   2. completes retirements whose copies have landed (slot freed, completion queued);
 //   3. admits pending requests into free slots of their size's batch, creating a batch
 //      when the HBM budget allows (releasing idle batches, least recently used first);
-//   4. keeps one chunk of replays in flight per busy batch (see max_inflight) and, when
+//   4. keeps one chunk of replays in flight per busy batch (see inflight_from_env) and, when
 //      the oldest chunk's flag copy has landed, retires every slot that finished in it.
 // A slot's flags are trusted only from chunks launched after the slot was admitted,
 // and a slot is reused only after its retirement copy has been observed, so the host
@@ -36,12 +36,10 @@ namespace {
 // keeps that wait short.  Measured at half load (400 requests, sizes 65^2 .. 2049^2,
 // chunks of two steps): p50 / p99 13.4 / 18.1 ms with two in flight, 8.0 / 12.3 ms with
 // one, and the saturated rate rose from 2516 to 2849 requests/s.
-int max_inflight() {
-  static const int v = [] {
-    const char *e = getenv("MG_SERVE_INFLIGHT");
-    return e != nullptr && atoi(e) == 2 ? 2 : 1;
-  }();
-  return v;
+// Read once per server, when it is created.
+int inflight_from_env() {
+  const char *e = getenv("MG_SERVE_INFLIGHT");
+  return e != nullptr && atoi(e) == 2 ? 2 : 1;
 }
 
 double now_s() {
@@ -98,6 +96,7 @@ struct Batch {
 struct mg_server_s {
   mg_server_config cfg{};
   int device = 0;
+  int max_inflight = 1;  // chunks in flight per busy batch, 1 or 2
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req> incoming;
@@ -321,8 +320,8 @@ bool Worker::complete_retirements(bool *progress) {
 }
 
 bool Worker::drive(Batch *b, bool *progress) {
-  // launch while fewer than max_inflight() chunks are in flight and some slot is running
-  while (b->inflight < max_inflight() && b->running() > 0) {
+  // launch while fewer than max_inflight chunks are in flight and some slot is running
+  while (b->inflight < s_->max_inflight && b->running() > 0) {
     const int buf = (b->oldest + b->inflight) & 1;
     if (!mg_ok(mgb::step(b->ctx, s_->cfg.chunk_steps), "replay")) return false;
     if (!mg_ok(mgb::read_flags(b->ctx, b->flags[buf]), "flag copy")) return false;
@@ -409,6 +408,7 @@ mg_status mg_server_create(const mg_server_config *cfg, mg_server *out) {
   if (mgb::footprint(&cfg->base, 1) == 0) return MG_EINVAL;
   auto s = std::make_unique<mg_server_s>();
   s->cfg = *cfg;
+  s->max_inflight = inflight_from_env();
   if (hipGetDevice(&s->device) != hipSuccess) return MG_EDEVICE;
   mg_server_s *raw = s.release();
   raw->worker = std::thread([raw] { Worker(raw).run(); });

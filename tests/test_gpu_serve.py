@@ -88,12 +88,14 @@ def test_single_request_equals_standalone_solve(precision):
     _check_exact(u, f, "single")
 
 
-@pytest.mark.parametrize("stream_groups", [0, 3])
-def test_results_identical_alone_and_in_the_mix(stream_groups):
+@pytest.mark.parametrize("stream_groups,inflight", [(0, "1"), (3, "1"), (3, "2")])
+def test_results_identical_alone_and_in_the_mix(stream_groups, inflight, monkeypatch):
     """A stream of mixed sizes arriving while others run; the probe request (same n and
     f) appears three times at different points of the stream.  Every request equals its
     standalone solve bit for bit and reaches 1e-10, with batches on streams of their own
-    or sharing streams by size group."""
+    or sharing streams by size group, and with one or two replay chunks in flight per
+    batch (MG_SERVE_INFLIGHT, read when the server is created)."""
+    monkeypatch.setenv("MG_SERVE_INFLIGHT", inflight)
     rng = np.random.default_rng(5)
     sizes = [65, 129, 257, 513, 1025]
     probe_n, probe_f = 257, _rhs(257, inputs.SEED_BASE + 1001)
