@@ -190,6 +190,22 @@ def event_time(stream, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def copy_rate(stream, reps=10):
+    """Bytes read + written per second by a plain 2 GiB device copy (torch) on the handle's
+    stream: the rate a streaming kernel reaches on this device, beside the published peak."""
+    import torch
+    a = torch.ones(256 * 1024 * 1024, device="cuda", dtype=torch.float64)
+    b = torch.empty_like(a)
+    def fn():
+        with torch.cuda.stream(stream):
+            b.copy_(a)
+    sec = event_time(stream, fn, reps)
+    nbytes = 2 * a.numel() * 8
+    del a, b
+    torch.cuda.empty_cache()
+    return nbytes / sec / 1e9
+
+
 def in_cycle_time(run, w, stream, reps):
     """Average duration of the dominant level-0 kernel in the order the cycle runs it, each
     launch bracketed by HIP events on the handle's stream: 2D, the fused pre kernel right
@@ -698,6 +714,7 @@ def time_workload(w, args, stream, fd, label, variants_2d=False):
     key = "%s/%s/%s/%d%s%s" % (dom_name, "f32" if w["precision"] else "f64", src, n, "/rb" if rb else "",
                                "/o%d" % w.get("order", 4) if w.get("order", 4) != 4 else "")
     tr = MEASURED_TRAFFIC.get(key)
+    copy_gbs = copy_rate(stream)
     out["roofline"] = {
         "bound": "hbm",
         "kernel": "%s level 0 (%s, %s)" % (dom_name, dom["op"], "FP32" if w["precision"] else "FP64"),
@@ -711,6 +728,8 @@ def time_workload(w, args, stream, fd, label, variants_2d=False):
         "algorithmic_bytes_per_launch": dom["bytes"],
         "in_cycle_us": cyc_s * 1e6,
         "in_cycle_GBs": dom["bytes"] / cyc_s / 1e9,
+        "copy_GBs": copy_gbs,
+        "frac_of_copy": dom["GB/s"] / copy_gbs,
     }
     if rows:
         out["levels"] = [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
