@@ -65,7 +65,7 @@ MEASURED_TRAFFIC = {
     "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 14160174698, "source": "333bedf8cb33f582"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
-    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "11dcfa18322facea"},
+    "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "b03ea673ddfdb24d"},
 }
 
 

@@ -35,7 +35,9 @@
  * points), the defect restricted with (1/8)[. 1 .; 1 4 1; . 1 .] onto the C points,
  * gamma cycles on the next level from a zero guess (on the last level one exact solve by
  * the inverse formed at set-up), the correction interpolated with (1/4)]. 1 .; 1 4 1; . 1 .[ (C points copy, F
- * points take the mean of their four C neighbours) and added, nu2 sweeps.
+ * points take the mean of their four C neighbours) and added, nu2 sweeps.  The levels of
+ * side <= 33 (environment MG_RBC_TAIL: another side, 0 for none) run in one workgroup
+ * launch per visit, with the same arithmetic as the per-level kernels.
  *
  * Status codes and mg_last_error() are those of mg.h.  Every call is asynchronous on the
  * handle's stream unless it returns a host value.  Calls on one handle must not overlap.

@@ -13,7 +13,9 @@
 // inverse, formed on the host at set-up and applied in one workgroup.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -103,8 +105,23 @@ __device__ __forceinline__ double apply_rot(const double *u, int m, int w, int i
   return v;
 }
 
-// One omega-Jacobi partial step on the F points (colour 1) or the C points (colour 2) of
-// a standard level.
+// One omega-Jacobi partial step on the F points (colour 1) or the C points (colour 2) at
+// array entry (i, k) of a level: column k = j of a standard level, or the packed column of
+// a rotated one (point (i, 2k + (i & 1)); padding entries are copied).
+template <bool ODD>
+__device__ __forceinline__ void smooth_entry(const double *__restrict__ f, const double *__restrict__ uin,
+                                             double *__restrict__ uout, int m, const Op &op, int colour,
+                                             double omega, int i, int k) {
+  const int w = ODD ? rot_pitch(m) : m;
+  const int j = ODD ? 2 * k + (i & 1) : k;
+  const size_t p = (size_t)i * w + k;
+  double v = uin[p];
+  if (j < m && unknown(ODD, m, i, j) && cpoint(ODD, i, j) == (colour == 2))
+    v += omega * (f[p] - (ODD ? apply_rot(uin, m, w, i, j, op) : apply_op(uin, m, i, j, op))) / op.c0;
+  uout[p] = v;
+}
+
+// The partial step over a standard level, one thread per entry.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restrict__ f,
                                                          const double *__restrict__ uin,
                                                          double *__restrict__ uout, int m,
@@ -115,11 +132,7 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth(const double *__restric
   const int j = tx * kBX + threadIdx.x;
   const int i = ty * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
-  const size_t p = (size_t)i * m + j;
-  double v = uin[p];
-  if (unknown(false, m, i, j) && cpoint(false, i, j) == (colour == 2))
-    v += omega * (f[p] - apply_op(uin, m, i, j, op)) / op.c0;
-  uout[p] = v;
+  smooth_entry<false>(f, uin, uout, m, op, colour, omega, i, j);
 }
 
 // The same on a rotated level, one thread per packed entry.
@@ -128,18 +141,12 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_smooth_rot(const double *__res
                                                              double *__restrict__ uout, int m,
                                                              Op op, int colour, double omega,
                                                              int gx, int total) {
-  const int w = rot_pitch(m);
   int tx, ty;
   xcd_tile(gx, total, tx, ty);
   const int k = tx * kBX + threadIdx.x;
   const int i = ty * kBY + threadIdx.y;
-  if (i >= m || k >= w) return;
-  const int j = 2 * k + (i & 1);
-  const size_t p = (size_t)i * w + k;
-  double v = uin[p];
-  if (j < m && unknown(true, m, i, j) && cpoint(true, i, j) == (colour == 2))
-    v += omega * (f[p] - apply_rot(uin, m, w, i, j, op)) / op.c0;
-  uout[p] = v;
+  if (i >= m || k >= rot_pitch(m)) return;
+  smooth_entry<true>(f, uin, uout, m, op, colour, omega, i, k);
 }
 
 // Defect restricted with eq. transfer_r2 onto the next level's storage grid (side mc),
@@ -227,9 +234,37 @@ __global__ __launch_bounds__(256) void k_rbc_restrict(const double *__restrict__
   }
 }
 
-// u_out = u_in + interpolated correction: C points take the coarse value, F points the
-// mean of their four C neighbours (eq. transfer_r2).  Standard level: the correction
-// comes from the rotated level below, packed with pitch (m + 1)/2.
+// u_out = u_in + interpolated correction at array entry (i, k): C points take the coarse
+// value, F points the mean of their four C neighbours (eq. transfer_r2).  A standard level
+// (side m) takes the correction from the rotated level below, packed with pitch
+// (m + 1)/2, along the axes; a rotated level (packed) from the standard level below (side
+// mc) along the diagonals, its C points having both indices even.
+template <bool ODD>
+__device__ __forceinline__ void prolong_entry(const double *__restrict__ ec, const double *uin, double *uout,
+                                              int m, int mc, int i, int k) {
+  const int w = ODD ? rot_pitch(m) : m;
+  const int j = ODD ? 2 * k + (i & 1) : k;
+  const size_t p = (size_t)i * w + k;
+  double v = uin[p];
+  if (j < m && unknown(ODD, m, i, j)) {
+    if (ODD) {
+      auto e = [&](int a, int b) { return ec[(size_t)(a >> 1) * mc + (b >> 1)]; };
+      if (cpoint(true, i, j))
+        v += e(i, j);
+      else
+        v += 0.25 * ((e(i - 1, j - 1) + e(i - 1, j + 1)) + (e(i + 1, j - 1) + e(i + 1, j + 1)));
+    } else {
+      const int wc = rot_pitch(m);
+      auto e = [&](int a, int b) { return ec[(size_t)a * wc + (b >> 1)]; };  // a + b even
+      if (cpoint(false, i, j))
+        v += e(i, j);
+      else
+        v += 0.25 * ((e(i - 1, j) + e(i + 1, j)) + (e(i, j - 1) + e(i, j + 1)));
+    }
+  }
+  uout[p] = v;
+}
+
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restrict__ ec,
                                                           const double *uin, double *uout,
                                                           int m, int gx, int total) {
@@ -238,41 +273,18 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong(const double *__restri
   const int j = tx * kBX + threadIdx.x;
   const int i = ty * kBY + threadIdx.y;
   if (i >= m || j >= m) return;
-  const int wc = rot_pitch(m);
-  const size_t p = (size_t)i * m + j;
-  double v = uin[p];
-  if (unknown(false, m, i, j)) {
-    auto e = [&](int a, int b) { return ec[(size_t)a * wc + (b >> 1)]; };  // a + b even
-    if (cpoint(false, i, j))
-      v += e(i, j);
-    else
-      v += 0.25 * ((e(i - 1, j) + e(i + 1, j)) + (e(i, j - 1) + e(i, j + 1)));
-  }
-  uout[p] = v;
+  prolong_entry<false>(ec, uin, uout, m, 0, i, j);
 }
 
-// The same on a rotated level (packed), the correction from the standard level below
-// (side mc): C points (both indices even) copy, F points (both odd) average the diagonals.
 __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__restrict__ ec,
                                                               const double *uin, double *uout,
                                                               int m, int mc, int gx, int total) {
-  const int w = rot_pitch(m);
   int tx, ty;
   xcd_tile(gx, total, tx, ty);
   const int k = tx * kBX + threadIdx.x;
   const int i = ty * kBY + threadIdx.y;
-  if (i >= m || k >= w) return;
-  const int j = 2 * k + (i & 1);
-  const size_t p = (size_t)i * w + k;
-  double v = uin[p];
-  if (j < m && unknown(true, m, i, j)) {
-    auto e = [&](int a, int b) { return ec[(size_t)(a >> 1) * mc + (b >> 1)]; };
-    if (cpoint(true, i, j))
-      v += e(i, j);
-    else
-      v += 0.25 * ((e(i - 1, j - 1) + e(i - 1, j + 1)) + (e(i + 1, j - 1) + e(i + 1, j + 1)));
-  }
-  uout[p] = v;
+  if (i >= m || k >= rot_pitch(m)) return;
+  prolong_entry<true>(ec, uin, uout, m, mc, i, k);
 }
 
 // Exact solve of the coarsest level: u = A^{-1} f over its K unknowns, with the inverse
@@ -282,10 +294,8 @@ __global__ __launch_bounds__(kBX *kBY) void k_rbc_prolong_rot(const double *__re
 // entry of u is written, so f may be the same array as u.  One 1024-thread workgroup:
 // four threads share a row, each summing every fourth column, then the four sums are
 // added.
-__global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *f, double *u,
-                                                       const double *__restrict__ ainv_t,
-                                                       const int *__restrict__ pos, int K,
-                                                       int entries) {
+__device__ __forceinline__ void coarsest_solve(const double *f, double *u, const double *__restrict__ ainv_t,
+                                               const int *__restrict__ pos, int K, int entries) {
   constexpr int K_MAX = MG_RBC_MAX_COARSEST;
   static_assert(4 * K_MAX == 1024, "four threads per row of the inverse fill the workgroup");
   __shared__ double fs[K_MAX];
@@ -308,6 +318,152 @@ __global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *f, double *
   }
   __syncthreads();
   if (t < K) u[pos[t]] = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+}
+
+__global__ __launch_bounds__(1024) void k_rbc_coarsest(const double *f, double *u,
+                                                       const double *__restrict__ ainv_t,
+                                                       const int *__restrict__ pos, int K,
+                                                       int entries) {
+  coarsest_solve(f, u, ainv_t, pos, K, entries);
+}
+
+// ------------------------------------------------------------- small-level tail ----
+// The levels from a side of at most 33 (by default) down to the coarsest run in one
+// 1024-thread workgroup: the same partial steps, interpolation and coarsest solve as the
+// per-level kernels (the same device functions), the restriction gathering each coarse
+// point's defects directly, one phase after another with a workgroup barrier between
+// them.  The small levels' arrays stay in the caches; the tail replaces a launch per
+// phase (five or six per level and visit) by a barrier.  Measured at 4097^2 (17 levels,
+// G1 V(1,1) cycle): 1.476 ms per-level, 1.456 ms from side 33, 1.477 ms from side 65 and
+// 1.662 ms from 129: a phase over a 65^2 level in one workgroup takes as long as a launch.
+constexpr int kTailMaxLevels = 8;
+
+struct TailLevel {
+  double *f, *u, *t;
+  Op op;
+  int m, odd;
+};
+
+struct TailArgs {
+  TailLevel lv[kTailMaxLevels];
+  int nl;               // levels in the tail, the last one the coarsest
+  int gamma, nu1, nu2;  // cycle
+  int visits;           // visits of the tail's top level in a row
+  double omega;
+  const double *ainv_t;
+  const int *pos;
+  int K;
+};
+
+// The defect at point (a, b) of a level, zero off its unknowns.
+template <bool ODD>
+__device__ __forceinline__ double defect_at(const double *f, const double *u, int m, const Op &op, int a,
+                                            int b) {
+  if (!unknown(ODD, m, a, b)) return 0.0;
+  if (ODD) {
+    const int w = rot_pitch(m);
+    return f[(size_t)a * w + (b >> 1)] - apply_rot(u, m, w, a, b, op);
+  }
+  return f[(size_t)a * m + b] - apply_op(u, m, a, b, op);
+}
+
+// Restriction (eq. transfer_r2) from level L onto the next level C, with C's iterate
+// zeroed: the weights and sum order of k_rbc_restrict.
+__device__ void tail_restrict(const TailLevel &L, const TailLevel &C) {
+  const int t = threadIdx.x, m = L.m, mc = C.m;
+  if (L.odd) {
+    for (int q = t; q < mc * mc; q += 1024) {
+      const int I = q / mc, J = q % mc;
+      double v = 0.0;
+      if (unknown(false, mc, I, J)) {
+        const int a = 2 * I, b = 2 * J;
+        auto r = [&](int x, int y) { return defect_at<true>(L.f, L.u, m, L.op, x, y); };
+        v = (4.0 * r(a, b) + ((r(a - 1, b - 1) + r(a - 1, b + 1)) + (r(a + 1, b - 1) + r(a + 1, b + 1)))) * 0.125;
+      }
+      C.f[q] = v;
+      C.u[q] = 0.0;
+    }
+  } else {
+    const int wc = rot_pitch(m);
+    for (int q = t; q < m * wc; q += 1024) {
+      const int a = q / wc, b = 2 * (q % wc) + (a & 1);
+      if (b >= m) continue;  // padding of an odd row
+      double v = 0.0;
+      if (unknown(true, m, a, b)) {
+        auto r = [&](int x, int y) { return defect_at<false>(L.f, L.u, m, L.op, x, y); };
+        v = (4.0 * r(a, b) + ((r(a - 1, b) + r(a + 1, b)) + (r(a, b - 1) + r(a, b + 1)))) * 0.125;
+      }
+      C.f[q] = v;
+      C.u[q] = 0.0;
+    }
+  }
+}
+
+__device__ void tail_smooth(const TailLevel &L, int colour, const double *uin, double *uout, double omega) {
+  const int w = L.odd ? rot_pitch(L.m) : L.m, entries = L.m * w;
+  for (int q = threadIdx.x; q < entries; q += 1024) {
+    if (L.odd)
+      smooth_entry<true>(L.f, uin, uout, L.m, L.op, colour, omega, q / w, q % w);
+    else
+      smooth_entry<false>(L.f, uin, uout, L.m, L.op, colour, omega, q / w, q % w);
+  }
+  __syncthreads();
+}
+
+// A red-black sweep: F points into t, then C points back into u.
+__device__ void tail_sweep(const TailLevel &L, double omega) {
+  tail_smooth(L, 1, L.u, L.t, omega);
+  tail_smooth(L, 2, L.t, L.u, omega);
+}
+
+__device__ void tail_prolong(const TailLevel &L, const TailLevel &C) {
+  const int w = L.odd ? rot_pitch(L.m) : L.m, entries = L.m * w;
+  for (int q = threadIdx.x; q < entries; q += 1024) {
+    if (L.odd)
+      prolong_entry<true>(C.u, L.u, L.u, L.m, C.m, q / w, q % w);
+    else
+      prolong_entry<false>(C.u, L.u, L.u, L.m, C.m, q / w, q % w);
+  }
+  __syncthreads();
+}
+
+// The gamma-cycle over the tail's levels without recursion: descending, each level
+// smooths and restricts; a finished visit of level l + 1 either starts the next one (the
+// second visit of a W-cycle, bit l of `again`) or lets level l interpolate and smooth.
+__global__ __launch_bounds__(1024) void k_rbc_tail(TailArgs a) {
+  const int last = a.nl - 1;
+  for (int v = 0; v < a.visits; ++v) {
+    int l = 0;
+    bool down = true;
+    unsigned again = 0u;
+    while (true) {
+      if (down) {
+        if (l == last) {
+          const TailLevel &C = a.lv[l];
+          coarsest_solve(C.f, C.u, a.ainv_t, a.pos, a.K, C.m * (C.odd ? rot_pitch(C.m) : C.m));
+          __syncthreads();
+          down = false;
+          continue;
+        }
+        for (int k = 0; k < a.nu1; ++k) tail_sweep(a.lv[l], a.omega);
+        tail_restrict(a.lv[l], a.lv[l + 1]);
+        __syncthreads();
+        again &= ~(1u << l);
+        ++l;
+        continue;
+      }
+      if (l == 0) break;  // the top level's visit is complete
+      const int p = l - 1;
+      if (p + 1 < last && a.gamma == 2 && !((again >> p) & 1u)) {
+        again |= 1u << p;
+        down = true;  // a second visit of level p + 1
+        continue;
+      }
+      tail_prolong(a.lv[p], a.lv[p + 1]);
+      for (int k = 0; k < a.nu2; ++k) tail_sweep(a.lv[p], a.omega);
+      l = p;
+    }
+  }
 }
 
 // Per-block sums of the squared level-0 defect over the interior.
@@ -478,6 +634,7 @@ struct mg_rbc_ctx {
   double *ainv_t = nullptr;  // the coarsest operator's inverse, transposed (K x K)
   int *pos = nullptr;        // array index of each coarsest unknown
   int coarse_k = 0;
+  int tail_top = 1 << 30;    // first level of the one-workgroup tail (none: past the last)
 };
 
 namespace {
@@ -545,6 +702,30 @@ mg_status launch_prolong(mg_rbc_ctx *h, int l, const double *ec, const double *u
   return MG_OK;
 }
 
+// Levels tail_top .. last in one launch, the top level's arrays f and u, visited `visits`
+// times in a row.
+mg_status launch_tail(mg_rbc_ctx *h, const double *f, double *u, int visits) {
+  const int top = h->tail_top, last = (int)h->lv.size() - 1;
+  TailArgs a{};
+  a.nl = last - top + 1;
+  for (int i = 0; i < a.nl; ++i) {
+    const Level &L = h->lv[top + i];
+    a.lv[i] = TailLevel{i == 0 ? const_cast<double *>(f) : h->f[top + i], i == 0 ? u : h->u[top + i],
+                        h->t[top + i], L.op, L.m, L.odd ? 1 : 0};
+  }
+  a.gamma = h->cfg.gamma;
+  a.nu1 = h->cfg.nu1;
+  a.nu2 = h->cfg.nu2;
+  a.visits = visits;
+  a.omega = h->cfg.omega == 0.0 ? 1.0 : h->cfg.omega;
+  a.ainv_t = h->ainv_t;
+  a.pos = h->pos;
+  a.K = h->coarse_k;
+  hipLaunchKernelGGL(k_rbc_tail, dim3(1), dim3(1024), 0, h->stream, a);
+  RBC_HIP(hipGetLastError());
+  return MG_OK;
+}
+
 mg_status launch_coarsest(mg_rbc_ctx *h, const double *f, double *u) {
   hipLaunchKernelGGL(k_rbc_coarsest, dim3(1), dim3(1024), 0, h->stream, f, u, h->ainv_t, h->pos,
                      h->coarse_k, (int)level_entries(h->lv.back()));
@@ -565,11 +746,15 @@ mg_status sweep(mg_rbc_ctx *h, int l, const double *f, double *u) {
 
 mg_status cycle(mg_rbc_ctx *h, int l, const double *f, double *u) {
   const int last = (int)h->lv.size() - 1;
+  if (l == h->tail_top) return launch_tail(h, f, u, 1);
   if (l == last) return launch_coarsest(h, f, u);
   for (int k = 0; k < h->cfg.nu1; ++k) RBC_TRY(sweep(h, l, f, u));
   RBC_TRY(launch_restrict(h, l, f, u, h->f[l + 1], h->u[l + 1]));
   const int reps = l + 1 < last ? h->cfg.gamma : 1;
-  for (int k = 0; k < reps; ++k) RBC_TRY(cycle(h, l + 1, h->f[l + 1], h->u[l + 1]));
+  if (l + 1 == h->tail_top)  // the visits of the tail's top level in one launch
+    RBC_TRY(launch_tail(h, h->f[l + 1], h->u[l + 1], reps));
+  else
+    for (int k = 0; k < reps; ++k) RBC_TRY(cycle(h, l + 1, h->f[l + 1], h->u[l + 1]));
   RBC_TRY(launch_prolong(h, l, h->u[l + 1], u, u));
   for (int k = 0; k < h->cfg.nu2; ++k) RBC_TRY(sweep(h, l, f, u));
   return MG_OK;
@@ -649,6 +834,17 @@ mg_status mg_rbc_setup(const mg_rbc_config *cfg, void *stream, mg_rbc_ctx **out)
       hipMemcpy(h->pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     mg_rbc_destroy(h);
     return fail(MG_EDEVICE, "copying the coarsest inverse failed");
+  }
+  // the one-workgroup tail: from the first level of side <= MG_RBC_TAIL (default 33; 0
+  // switches it off) to the coarsest, at least two levels and at most kTailMaxLevels
+  {
+    const char *e = getenv("MG_RBC_TAIL");
+    const int side = e != nullptr && *e != 0 ? atoi(e) : 33;
+    const int last = cfg->levels - 1;
+    int top = 0;
+    while (top <= last && h->lv[top].m > side) ++top;
+    top = std::max(top, last + 1 - kTailMaxLevels);
+    if (side > 0 && top < last) h->tail_top = top;
   }
   // every level array starts at zero: their boundaries and off-grid entries stay zero
   for (int l = 1; l < cfg->levels; ++l) {

@@ -164,6 +164,40 @@ def test_cycles_match_oracle(n, levels, coarse, gamma, nu1, nu2, omega, cycles):
         P.close()
 
 
+TAIL_CASES = [
+    # n, levels, coarse, gamma, nu1, nu2, omega, cycles
+    (65, 8, "G1", 1, 1, 1, 1.0, 2), (65, 8, "GN", 2, 1, 1, 1.0, 2), (129, 10, "NG", 2, 2, 1, 1.1, 2),
+    (257, 12, "G1", 1, 0, 2, 1.2, 2), (1025, 16, "GN", 2, 1, 1, 1.0, 1), (33, 6, "G1", 2, 2, 2, 0.9, 2),
+    (129, 7, "G1", 1, 1, 0, 1.0, 2),
+]
+
+
+@pytest.mark.parametrize("side", ["17", "33", "65", "129"])
+@pytest.mark.parametrize("n,levels,coarse,gamma,nu1,nu2,omega,cycles", TAIL_CASES)
+def test_tail_equals_per_level_kernels(n, levels, coarse, gamma, nu1, nu2, omega, cycles, side,
+                                       monkeypatch):
+    """The one-workgroup tail (the levels of side <= MG_RBC_TAIL down to the coarsest in
+    one launch; a side reaching level 0 runs the whole cycle there) against the cycle of
+    per-level kernels, V- and W-cycles: the partial steps, interpolation and coarsest
+    solve are the same device functions and the restriction sums in the same order, so
+    the two agree to rounding (bit for bit where the compiler fuses the same multiply-adds:
+    on the levels without distance-2 taps)."""
+    print("rbc tail", n, levels, coarse, gamma, nu1, nu2, omega, side, flush=True)
+    f = _grid(n, 700 + n + levels) * (n - 1) ** 2
+    out = []
+    for env in ("0", side):
+        monkeypatch.setenv("MG_RBC_TAIL", env)
+        P = Pair(n, levels, coarse, gamma, nu1, nu2, omega)
+        try:
+            fd, ud = dev(f), dev(np.zeros((n, n)))
+            rbc.cycles(P.h, fd.data_ptr(), ud.data_ptr(), cycles)
+            out.append(host(ud))
+        finally:
+            P.close()
+    _close(out[1], out[0], "tail against per-level kernels")
+    print("  bit-identical:", np.array_equal(out[0], out[1]), flush=True)
+
+
 def test_full_size_cycle_matches_oracle():
     """One G1 V(1,1) cycle at 4097^2 with the 17 levels the benchmark times, from the
     benchmark's right-hand side, against the oracle's cycle."""
