@@ -271,7 +271,8 @@ def level_kernels(run, w, stream, reps, only_level=None):
     """Per-level launches of the kernels the cycle runs on that level, each timed with HIP
     events, with their algorithmic bytes.  2D: the fused pre-smoothing + defect + full
     weighting and the fused interpolation + correction + post-smoothing; 3D: the sweep, the
-    fused defect + full weighting and the interpolation + correction."""
+    fused defect + full weighting (on Galerkin levels also the defect pass followed by full
+    weighting, which the cycle runs) and the interpolation + correction."""
     import torch
     mg = run.mg
     fp32 = 1 if run.precision == 1 else 0
@@ -362,6 +363,13 @@ def level_kernels(run, w, stream, reps, only_level=None):
                  lambda: mg.mg_kernel_prolong_correct(run.h, l, fp32, v.data_ptr(), u.data_ptr(),
                                                       t.data_ptr())),
             ]
+            if sep:
+                # what the cycle runs there: the pencil kernel's defect, then full weighting
+                def two_pass():
+                    mg.mg_kernel_residual(run.h, l, fp32, f.data_ptr(), u.data_ptr(), t.data_ptr())
+                    mg.mg_kernel_residual_restrict(run.h, l, fp32, t.data_ptr(), 0, fc.data_ptr())
+                ks.insert(2, ("k_gpen3d+k_xrr3d", "defect, then FW (the cycle's pass)",
+                              (3 * P + P + Pc) * b, two_pass))
         for name, what, nbytes, fn in ks:
             s = event_time(stream, fn, reps)
             rows.append({"level": l, "n": n, "kernel": name, "op": what, "us": s * 1e6,

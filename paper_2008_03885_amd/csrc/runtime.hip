@@ -524,11 +524,25 @@ template <typename T>
 hipError_t cycle(mg_ctx *c, std::vector<Buffers> &B, int l, T *u, const T *f, bool zero_u,
                  bool check, hipStream_t s, double *corr = nullptr);
 
-// fc = I_h^H (f - L_l u) on level l+1.  Full weighting: one fused pass.  Cubic adjoint
-// (appendix A.4): the defect into scratch (a free level-l array), then the restriction.
+// fc = I_h^H (f - L_l u) on level l+1.  Full weighting: one fused pass, or on 3D separable
+// levels the defect into scratch (a free level-l array) and then its restriction.  Cubic
+// adjoint (appendix A.4): the defect into scratch, then the restriction.
 template <typename T>
 hipError_t resid_restrict(mg_ctx *c, int l, const T *f, const T *u, T *scratch, T *fc, const int *done,
                           hipStream_t s) {
+  // 3D separable (Galerkin) levels: the pencil kernel's defect into scratch, then full
+  // weighting of it by the cross kernel's zero-iterate form (C5 FP64 278.6 -> 272.8 ms,
+  // mixed 431.3 -> 430.2 ms against the fused k_grr3d, which waits at its barriers);
+  // MG_GRR_2PASS=0 keeps the fused kernel.
+  const LevelOp &op = c->ops[l];
+  const char *two = std::getenv("MG_GRR_2PASS");
+  if (c->cfg.restrict_op != 3 && c->dim == 3 && !op.cross && !op.cross3 && u != nullptr &&
+      !(two != nullptr && *two != 0 && std::atoi(two) == 0)) {
+    hipError_t e = mgk::launch_sweep<T, T>(3, mgk::kResidual, op, c->omega, f, u, scratch, c->ns[l], nullptr,
+                                           nullptr, done, s, c->slots);
+    if (e != hipSuccess) return e;
+    return mgk::launch_resid_restrict<T>(3, op, scratch, nullptr, fc, c->ns[l], done, s, c->slots);
+  }
   if (c->cfg.restrict_op != 3)
     return mgk::launch_resid_restrict<T>(c->dim, c->ops[l], f, u, fc, c->ns[l], done, s, c->slots);
   hipError_t e = mgk::launch_sweep<T, T>(c->dim, mgk::kResidual, c->ops[l], c->omega, f, u, scratch, c->ns[l],
