@@ -805,3 +805,28 @@ def test_fused_correction_equals_separate(n, coarse, nu1, nu2, gamma, inner, mon
     assert rel <= 1e-10
     err = oracle.norm(out["1"][2] - dst.solve(f))
     assert err <= 1.01 * rel * oracle.norm(f) / dst.min_eigenvalue(n, 3) + 1e-14 * oracle.norm(out["1"][2])
+
+
+@pytest.mark.parametrize("n,coarse,gamma,precision", [(65, 1, 2, 0), (129, 1, 1, 0), (65, 3, 2, 0), (129, 1, 2, 1),
+                                                      (33, 1, 1, 0)])
+def test_galerkin_two_pass_restriction(n, coarse, gamma, precision, monkeypatch):
+    """3D Galerkin levels: the defect formed by the pencil kernel and then restricted by
+    full weighting (the cycle's default) against the fused separable defect + full
+    weighting (MG_GRR_2PASS=0), to rounding; in FP64 also against the oracle's cycles."""
+    f = inputs.smoothed_noise_3d(n)
+    out = {}
+    for two in ("0", "1"):
+        monkeypatch.setenv("MG_GRR_2PASS", two)
+        H = Handle(3, n, coarse=coarse, nu1=2, nu2=2, gamma=gamma, precision=precision, inner_cycles=1)
+        try:
+            fd, ud = dev(f), dev(np.zeros_like(f))
+            mg.mg_run_cycles(H.h, fd.data_ptr(), ud.data_ptr(), 3)
+            out[two] = host(ud)
+            if two == "1" and precision == 0:
+                u_ref = np.zeros_like(f)
+                H.oracle.solve(u_ref, f, rtol=0.0, max_cycles=3)
+                assert np.linalg.norm(out[two] - u_ref) <= 1e-12 * np.linalg.norm(u_ref)
+        finally:
+            H.close()
+    tol = 1e-13 if precision == 0 else 1e-6
+    assert np.linalg.norm(out["1"] - out["0"]) <= tol * np.linalg.norm(out["0"])
