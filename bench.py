@@ -381,9 +381,10 @@ def level_kernels(run, w, stream, reps, only_level=None):
 def cpu_baseline(w, gpu_cycles, sample_n=None):
     """The oracle (plain C, FP64; OpenMP splits the outermost loop of 3D grids, 2D loops run
     on one thread) timed on the host on a bounded sample of the same configuration.
-    3D: one whole solve to 1e-10 of the same problem at side sample_n on all host cores,
-    and one cycle on one thread scaled to that solve's cycle count.  2D: one cycle of the
-    full-size problem on one thread, scaled to the cycles the GPU solve needed.
+    3D: whole solves to 1e-10 of the same problem at side sample_n on all host cores, and
+    a cycle on one thread scaled to that solve's cycle count.  2D: a cycle of the
+    full-size problem on one thread, scaled to the cycles the GPU solve needed.  Each time
+    is the median of three runs.
     Returns (baseline dict, oracle solution or None, oracle cycles, oracle final residual)."""
     import numpy as np
 
@@ -402,30 +403,37 @@ def cpu_baseline(w, gpu_cycles, sample_n=None):
     grid = "x".join([str(n)] * d)
     u_all, cycles, final = None, gpu_cycles, None
     out = {"unit": "unknowns/s", "kind": "oracle"}
+    reps = 3  # timings: the median of three
     if d == 3:
-        m = make()
-        u_all = np.zeros_like(f)
-        t0 = time.perf_counter()
-        cycles, hist = m.solve(u_all, f, rtol=1e-10, max_cycles=60)
-        t_all = time.perf_counter() - t0
-        m.close()
+        times = []
+        for _ in range(reps):
+            m = make()
+            u_all = np.zeros_like(f)
+            t0 = time.perf_counter()
+            cycles, hist = m.solve(u_all, f, rtol=1e-10, max_cycles=60)
+            times.append(time.perf_counter() - t0)
+            m.close()
+        t_all = float(np.median(times))
         final = float(hist[-1])
         out.update(value=unknowns / t_all, cores=all_cores,
-                   sample="one whole FP64 %s solve of the same problem at %s to %.1e on %d threads "
-                          "(%d cycles, %.2f s)" % (cyc, grid, final, all_cores, cycles, t_all))
+                   sample="whole FP64 %s solves of the same problem at %s to %.1e on %d threads "
+                          "(%d cycles), median of %d: %.2f s" % (cyc, grid, final, all_cores, cycles, reps, t_all))
     oracle.set_num_threads(1)
     try:
-        m = make()
-        u1 = np.zeros_like(f)
-        t0 = time.perf_counter()
-        m.cycle(u1, f)
-        t1 = time.perf_counter() - t0
-        m.close()
+        times = []
+        for _ in range(reps):
+            m = make()
+            u1 = np.zeros_like(f)
+            t0 = time.perf_counter()
+            m.cycle(u1, f)
+            times.append(time.perf_counter() - t0)
+            m.close()
+        t1 = float(np.median(times))
     finally:
         oracle.set_num_threads(all_cores)
     one = {"value": unknowns / (t1 * cycles), "cores": 1,
-           "sample": "one FP64 %s cycle at %s on one thread (%.2f s), scaled to the %d cycles of %s"
-                     % (cyc, grid, t1, cycles, "that solve" if d == 3 else "the GPU FP64 solve")}
+           "sample": "FP64 %s cycles at %s on one thread, median of %d: %.2f s, scaled to the %d cycles of %s"
+                     % (cyc, grid, reps, t1, cycles, "that solve" if d == 3 else "the GPU FP64 solve")}
     if d == 3:
         out["single_thread"] = one
     else:
