@@ -58,11 +58,11 @@ MEASURED_TRAFFIC = {
     # 156,850.3 KiB x 2.0000 + 168,329.4 KiB x 1.0000
     "k_pre2d/f64/fused2d.hip/4097/rb": {"bytes": 493592759, "source": "80797142e6561bc3"},
     # 513^3 level 0 FP32 sweep (128 x 16 tiles from point 1, two rows per thread):
-    # 597,640.8 KiB x 2.0000 + 551,637.8 KiB x 1.0000
-    "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 1788822551, "source": "333bedf8cb33f582"},
+    # 596,214.4 KiB x 2.0000 + 550,147.5 KiB x 1.0000
+    "k_xsweep3d/f32/kernels3d.hip/513": {"bytes": 1784398131, "source": "fbab958a857d17c1"},
     # 1025^3 level 0 FP32 sweep (128 x 16 tiles from point 1, two rows per thread):
-    # 4,699,123.6 KiB x 2.0000 + 4,430,188.0 KiB x 1.0000
-    "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 14160174698, "source": "333bedf8cb33f582"},
+    # 4,696,404.6 KiB x 2.0000 + 4,433,740.2 KiB x 1.0000
+    "k_xsweep3d/f32/kernels3d.hip/1025": {"bytes": 14158386586, "source": "fbab958a857d17c1"},
     # red-black coarsening, 4097^2 level-0 partial step (XCD-remapped 64 x 4 tiles):
     # 131,353.0 KiB x 2.0000 + 131,137.3 KiB x 1.0000 (f is read whole: 24 B a point)
     "k_rbc_smooth/f64/rbc.hip/4097": {"bytes": 403291537, "source": "b03ea673ddfdb24d"},

@@ -1213,14 +1213,17 @@ inline bool wide128() {
 }
 
 // Rows per wavefront of the pencil sweep: 2 (FP32 126 VGPRs, four wavefronts per SIMD;
-// FP64 209); MG_GPEN_ROWS = 2 doubles them.  Measured at 513^3: FP32 two rows 571 us,
-// four 540 us, but four rows lose more on the smaller levels (257^3: 81 against 94 us);
-// FP64 one row (147 VGPRs) was slower than two in the whole solve (316 against 308 ms).
+// FP64 209), doubled for FP32 levels from 513^3 up.  Measured at 513^3: FP32 two rows
+// 571 us, four 540 us, but four rows lose on the smaller levels (257^3: 81 against
+// 94 us); FP64 one row (147 VGPRs) was slower than two in the whole solve (316 against
+// 308 ms).  MG_GPEN_ROWS = 1 or 2 sets the factor on every level.
 template <typename T>
 constexpr int gpen_rows() { return 2; }
-inline int gpen_rows_scale() {
+template <typename T>
+int gpen_rows_scale(int n) {
   const char *e = getenv("MG_GPEN_ROWS");
-  return e != nullptr && atoi(e) == 2 ? 2 : 1;
+  if (e != nullptr && *e != 0) return atoi(e) == 2 ? 2 : 1;
+  return sizeof(T) == 4 && n >= 513 ? 2 : 1;
 }
 template <typename T, typename TO, int YR>
 const void *gpen3d_fn_rows(int mode) {
@@ -1291,7 +1294,7 @@ hipError_t launch_sweep_3d(int mode, const LevelOp &op, double omega, const T *f
   k.colour = colour;
   if (!xpath && !x3path) {
     constexpr int Y1 = gpen_rows<T>(), Y2 = 2 * gpen_rows<T>();
-    const int yr = Y1 * gpen_rows_scale();
+    const int yr = Y1 * gpen_rows_scale<T>(n);
     const void *fn = yr == Y1 ? gpen3d_fn_rows<T, TO, Y1>(mode) : gpen3d_fn_rows<T, TO, Y2>(mode);
     const int ptiles = cdiv(n, 58) * cdiv(n, 4 * yr);
     const int pzc = (std::min(kMaxPlanes, band_rows(n, ptiles, kRounds3d * resident_blocks(fn, 256, 0), kMinPlanes)) + 7) / 8 * 8;
